@@ -1,0 +1,252 @@
+"""One implicit incremental-potential step and its Newton minimiser
+(oracle, FP64, test infrastructure).
+
+Sec. III-B / Alg. 2 line "Physics": the pad advances by minimising, over the
+free degrees of freedom,
+
+    E(x) = 1/2 sum_a m_a |x_a - xhat_a|^2 + h^2 [ sum_e V_e Psi(F_e) + E_b(x) ],
+    xhat = x_t + h v_t + h^2 g,
+
+with the fixed components held at their rest positions.  The h^2 factor on
+the potential is the one Alg. 2 undoes when it turns the contact gradient
+into a force (f = -g / dt^2).  `quasi_static` drops the inertia term.
+
+The minimiser (the paper caps Newton at 1024 iterations per step):
+  1. initial guess x_t; any candidate closer than 0.1 d_hat to an indenter is
+     pushed out along grad(phi) (at most 8 rounds; failure = infeasible);
+  2. Newton direction p from the PSD-projected Hessian (sparse direct solve);
+     converged when ||p||_inf <= tol * (rest bounding-box diagonal), in which
+     case the filtered step is taken without a line search;
+  3. step filter alpha <= 0.9 d_k / |p_k| for every candidate (valid because
+     every distance function here is 1-Lipschitz);
+  4. Armijo backtracking E(x + a p) <= E(x) + 1e-4 a g.p + 1e-12 |E(x)|, at
+     most 40 halvings (the last term admits energy changes below what a
+     float64 sum over the mesh resolves);
+  5. x += a p.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import List
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from . import contact, fem, material, surface
+
+
+ENERGY_NOISE = 1e-12
+
+
+class Infeasible(RuntimeError):
+    pass
+
+
+class LineSearchFailure(RuntimeError):
+    pass
+
+
+class NotConverged(RuntimeError):
+    pass
+
+
+@dataclasses.dataclass
+class OraclePad:
+    X: np.ndarray
+    tets: np.ndarray
+    mu: np.ndarray          # per tet
+    lam: np.ndarray
+    alpha: np.ndarray
+    density: float
+    Dminv: np.ndarray
+    vol: np.ndarray
+    mass: np.ndarray
+    fixed: np.ndarray       # per-vertex xyz bitmask
+    tris: np.ndarray
+    parent: np.ndarray
+    is_top: np.ndarray
+    cand: np.ndarray
+    area: np.ndarray        # rest contact-face areas of the candidates
+    L_diag: float
+    free: np.ndarray        # [V,3] bool
+    x: np.ndarray           # committed state
+    v: np.ndarray
+
+
+def make_pad(X, tets, E, nu, density, fixed=None, literal_alpha=False):
+    """Setup: Eq. 1 Lame parameters, rest data, mass, surface (Alg. 1 1-3)."""
+    X = np.asarray(X, dtype=np.float64)
+    tets = np.asarray(tets, dtype=np.int32)
+    T = tets.shape[0]
+    E = np.broadcast_to(np.asarray(E, dtype=np.float64), (T,)).copy()
+    nu = np.broadcast_to(np.asarray(nu, dtype=np.float64), (T,)).copy()
+    mu, lam = material.lame(E, nu)
+    alpha = np.array([material.rest_shift(m, l, literal_alpha) for m, l in zip(mu, lam)])
+    Dminv, vol = fem.rest_data(X, tets)
+    mass = surface.lumped_mass(X, tets, density)
+    fixed = surface.default_fixed(X) if fixed is None else np.asarray(fixed, np.uint8)
+    tris, parent = surface.surface_triangles(tets)
+    is_top = surface.contact_face_labels(X, tris)
+    cand = surface.candidates(tris, is_top, fixed, X.shape[0])
+    area = surface.vertex_areas(X, tris[is_top.astype(bool)], cand)
+    L = float(np.linalg.norm(X.max(axis=0) - X.min(axis=0)))
+    free = np.stack([(fixed >> b) & 1 == 0 for b in range(3)], axis=1)
+    return OraclePad(X, tets, mu, lam, alpha, density, Dminv, vol, mass, fixed,
+                     tris, parent, is_top, cand, area, L, free, X.copy(), np.zeros_like(X))
+
+
+@dataclasses.dataclass
+class StepParams:
+    dt: float = 1.0 / 60.0
+    dhat: float = 1e-4
+    kappa: float = 1e3
+    newton_tol: float = 1e-6
+    max_newton: int = 1024
+    quasi_static: bool = False
+    gravity: tuple = (0.0, 0.0, 0.0)
+    max_halvings: int = 40
+
+
+@dataclasses.dataclass
+class StepResult:
+    x: np.ndarray
+    v: np.ndarray
+    newton_iters: int
+    energies: List[float]
+
+
+def energy(pad, x, xhat, inds, prm):
+    """E(x) of the incremental potential (inf if a candidate penetrates)."""
+    h2 = prm.dt ** 2
+    Eel = float(np.sum(fem.elastic_energy(x, pad.tets, pad.Dminv, pad.vol,
+                                          pad.mu, pad.lam, pad.alpha)))
+    Eb, _, _ = contact.barrier_terms(inds, x[pad.cand], pad.area, prm.dhat, prm.kappa)
+    Ein = 0.0 if prm.quasi_static else 0.5 * float(np.sum(pad.mass[:, None] * (x - xhat) ** 2))
+    return Ein + h2 * (Eel + Eb)
+
+
+def gradient(pad, x, xhat, inds, prm):
+    """dE/dx as [V,3] (fixed components included, not masked)."""
+    h2 = prm.dt ** 2
+    ge = fem.elastic_gradient(x, pad.tets, pad.Dminv, pad.vol, pad.mu, pad.lam, pad.alpha)
+    g = h2 * fem.scatter_vector(pad.tets, ge, x.shape[0])
+    _, gb, _ = contact.barrier_terms(inds, x[pad.cand], pad.area, prm.dhat, prm.kappa)
+    g[pad.cand] += h2 * gb
+    if not prm.quasi_static:
+        g += pad.mass[:, None] * (x - xhat)
+    return g
+
+
+def hessian(pad, x, inds, prm, project=True):
+    """Assembled (3V x 3V) sparse Hessian of E."""
+    h2 = prm.dt ** 2
+    V = x.shape[0]
+    Ke = fem.elastic_hessian(x, pad.tets, pad.Dminv, pad.vol, pad.mu, pad.lam,
+                             pad.alpha, project=project)
+    dof = (3 * pad.tets[:, :, None] + np.arange(3)[None, None, :]).reshape(-1, 12)
+    rows = np.repeat(dof, 12, axis=1).ravel()
+    cols = np.tile(dof, (1, 12)).ravel()
+    vals = h2 * Ke.ravel()
+    _, _, Hb = contact.barrier_terms(inds, x[pad.cand], pad.area, prm.dhat, prm.kappa)
+    cd = (3 * pad.cand[:, None] + np.arange(3)[None, :])
+    rows = np.concatenate([rows, np.repeat(cd, 3, axis=1).ravel()])
+    cols = np.concatenate([cols, np.tile(cd, (1, 3)).ravel()])
+    vals = np.concatenate([vals, h2 * Hb.ravel()])
+    if not prm.quasi_static:
+        d = np.arange(3 * V)
+        rows = np.concatenate([rows, d])
+        cols = np.concatenate([cols, d])
+        vals = np.concatenate([vals, np.repeat(pad.mass, 3)])
+    return sp.csr_matrix((vals, (rows, cols)), shape=(3 * V, 3 * V))
+
+
+def candidate_distances(pad, x, inds):
+    """min over indenters of phi at every candidate."""
+    d = np.full(pad.cand.shape[0], np.inf)
+    for ind in inds:
+        phi, _, _ = contact.sdf(ind, x[pad.cand])
+        d = np.minimum(d, phi)
+    return d
+
+
+def feasible_start(pad, x, inds, prm):
+    """Initial guess: push candidates closer than 0.1 d_hat out along
+    grad(phi), free components only, at most 8 rounds."""
+    x = x.copy()
+    d_safe = 0.1 * prm.dhat
+    free_c = pad.free[pad.cand]
+    for _ in range(8):
+        moved = False
+        for ind in inds:
+            phi, n, _ = contact.sdf(ind, x[pad.cand])
+            low = phi < d_safe * (1.0 - 1e-9)
+            if low.any():
+                moved = True
+                x[pad.cand[low]] += ((d_safe - phi[low])[:, None] * n[low]) * free_c[low]
+        if not moved:
+            break
+    if np.any(candidate_distances(pad, x, inds) <= 0.0):
+        raise Infeasible("indenter pose leaves no feasible start")
+    return x
+
+
+def step_filter(pad, x, p, inds):
+    """alpha_max = min(1, min_k 0.9 d_k / |p_k|)."""
+    d = candidate_distances(pad, x, inds)
+    pk = np.linalg.norm(p[pad.cand], axis=1)
+    moving = pk > 0
+    if not moving.any():
+        return 1.0
+    return float(min(1.0, np.min(0.9 * d[moving] / pk[moving])))
+
+
+def step(pad, inds, prm, solver="direct", cg_tol=1e-12, verbose=False):
+    """Advance the pad one step under the end-of-step indenter poses `inds`.
+    Returns StepResult; pad.x / pad.v are NOT modified (commit separately)."""
+    h = prm.dt
+    x_t, v_t = pad.x, pad.v
+    xhat = x_t + h * v_t + h * h * np.asarray(prm.gravity)[None]
+    x = feasible_start(pad, x_t, inds, prm)
+    free = pad.free.ravel()
+    tol = prm.newton_tol * pad.L_diag
+    energies = [energy(pad, x, xhat, inds, prm)]
+    for it in range(1, prm.max_newton + 1):
+        g = gradient(pad, x, xhat, inds, prm).ravel()
+        H = hessian(pad, x, inds, prm)
+        Hff = H[free][:, free]
+        if solver == "direct":
+            pf = spla.spsolve(Hff.tocsc(), -g[free])
+        else:
+            dinv = 1.0 / Hff.diagonal()
+            pf, info = spla.cg(Hff, -g[free], rtol=cg_tol, maxiter=100000,
+                               M=sp.diags(dinv))
+        p = np.zeros_like(g)
+        p[free] = pf
+        P3 = p.reshape(-1, 3)
+        a = step_filter(pad, x, P3, inds)
+        pinf = float(np.max(np.abs(p))) if p.size else 0.0
+        if pinf <= tol:
+            x = x + a * P3
+            energies.append(energy(pad, x, xhat, inds, prm))
+            v = (x - x_t) / h
+            return StepResult(x, v, it, energies)
+        E0 = energies[-1]
+        gTp = float(g @ p)
+        for _ in range(prm.max_halvings + 1):
+            E1 = energy(pad, x + a * P3, xhat, inds, prm)
+            if E1 <= E0 + 1e-4 * a * gTp + ENERGY_NOISE * abs(E0):
+                break
+            a *= 0.5
+        else:
+            raise LineSearchFailure(f"no decrease at Newton iteration {it}")
+        x = x + a * P3
+        energies.append(E1)
+        if verbose:
+            print(f"  newton {it}: |p|inf={pinf:.3e} a={a:.3e} E={E1:.6e}")
+    raise NotConverged("Newton did not converge")
+
+
+def commit(pad, res):
+    pad.x = res.x.copy()
+    pad.v = res.v.copy()

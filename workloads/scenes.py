@@ -1,0 +1,310 @@
+"""Seeded synthetic scenes: pads, materials, indenter poses, schedules.
+
+The paper measures on its own sensor meshes (GelSight Mini, DIGIT, 9DTact)
+which are not available; these scenes stand in with the shapes and sizes of
+the five benchmark workloads:
+
+  1. single 18x14x4 mm pad, 12x9x3 cells (1,944 tets), sphere r = 5 mm,
+     0.5 mm over 10 steps, FP64;
+  2. the same pad as a 45x35x13 graded grid (122,850 tets, top layer
+     0.2 mm) with five indenters, 30 steps each;
+  3. 60 uneven pads (flat 18x14x4, dome 19x16x3 + R30 cap, flat 24x24x5),
+     20k-80k tets each, random material and indenter;
+  4. 256 resident pads, 5k-150k tets log-uniform, Poisson step requests;
+  5. one 24x24x5 mm pad, ~1.2M tets, four-level refinement around a
+     seeded patch, sphere r = 3 mm, 1 mm over 60 steps.
+
+Random draws use numpy's PCG64 seeded by SeedSequence.  Nothing here
+evaluates the method: indenter start heights come from vertex heights only
+(no signed distances).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional
+
+import numpy as np
+
+from . import meshes
+
+MM = 1e-3
+
+SPHERE, CYLINDER, BOX, TORUS, TEXTURE = 0, 1, 2, 3, 4
+SHAPE_NAMES = {SPHERE: "sphere", CYLINDER: "cylinder", BOX: "cube_edge",
+               TORUS: "torus", TEXTURE: "texture"}
+
+
+@dataclasses.dataclass
+class Material:
+    E: float = 0.3e6        # Young's modulus [Pa]
+    nu: float = 0.45        # Poisson ratio
+    density: float = 1000.0  # [kg/m^3]
+
+
+@dataclasses.dataclass
+class Params:
+    dt: float = 1.0 / 60.0
+    dhat: float = 0.1 * MM
+    kappa: float = 1e3       # barrier stiffness [Pa]
+    newton_tol: float = 1e-6  # ||p||_inf <= tol * bbox diagonal
+    cg_rel_tol: float = 1e-4
+    max_newton: int = 1024
+    max_cg: int = 4000
+    quasi_static: int = 0
+    gravity: tuple = (0.0, 0.0, 0.0)
+    literal_alpha: int = 0   # 1: rest shift alpha = 1 exactly as printed
+
+
+@dataclasses.dataclass
+class Indenter:
+    shape: int
+    prm: tuple               # shape parameters [m]
+    R: np.ndarray            # 3x3 rotation, local -> world
+    c: np.ndarray            # centre at the start of the episode [m]
+
+    def at_depth(self, depth):
+        """Pose after travelling `depth` metres along world -z."""
+        return Indenter(self.shape, self.prm, self.R.copy(),
+                        self.c - np.array([0.0, 0.0, depth]))
+
+
+@dataclasses.dataclass
+class Pad:
+    name: str
+    X: np.ndarray            # rest positions [V,3] float64
+    tets: np.ndarray         # [T,4] int32
+    material: Material
+    dims: tuple              # (Lx, Ly, H) [m]
+    fixed: Optional[np.ndarray] = None   # per-vertex xyz bitmask (uint8)
+
+
+@dataclasses.dataclass
+class Episode:
+    pad: Pad
+    indenter: Indenter       # start pose (barrier just inactive)
+    depth: float             # total travel [m]
+    n_steps: int             # steps to reach `depth`
+    params: Params
+    schedule: str = "press"  # "press": ramp then hold; "triangle": press/release
+
+    def depth_at(self, step):
+        """Indenter travel after `step` steps (step >= 1)."""
+        n = self.n_steps
+        if self.schedule == "triangle":
+            ph = step % (2 * n)
+            frac = ph / n if ph <= n else (2 * n - ph) / n
+        else:
+            frac = min(step, n) / n
+        return self.depth * frac
+
+    def pose(self, step):
+        return self.indenter.at_depth(self.depth_at(step))
+
+
+# ----------------------------------------------------------------------------
+# pads
+
+def box_pad(Lx, Ly, H, nx, ny, nz, material=None, name="box", zs=None):
+    xs = meshes.uniform_axis(Lx, nx)
+    ys = meshes.uniform_axis(Ly, ny)
+    zs = meshes.uniform_axis(H, nz) if zs is None else zs
+    X, T = meshes.kuhn_grid(xs, ys, zs)
+    return Pad(name, X, T, material or Material(), (Lx, Ly, H))
+
+
+def dome_pad(Lx, Ly, H, nx, ny, nz, cap_radius=30 * MM, material=None):
+    pad = box_pad(Lx, Ly, H, nx, ny, nz, material, name="dome")
+    pad.X = meshes.dome_map(pad.X, H, cap_radius, (0.5 * Lx, 0.5 * Ly))
+    return pad
+
+
+def one_tet_pad():
+    X = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1]], float) * MM
+    return Pad("one_tet", X, np.array([[0, 1, 2, 3]], np.int32), Material(),
+               (1 * MM, 1 * MM, 1 * MM))
+
+
+def one_cube_pad(size=1 * MM):
+    return box_pad(size, size, size, 1, 1, 1, name="one_cube")
+
+
+SHAPES3 = (("flat18", 18 * MM, 14 * MM, 4 * MM, False),
+           ("dome19", 19 * MM, 16 * MM, 3 * MM, True),
+           ("flat24", 24 * MM, 24 * MM, 5 * MM, False))
+
+
+def pad_for_target(shape_idx, target_tets, material):
+    name, Lx, Ly, H, dome = SHAPES3[shape_idx]
+    nx, ny, nz = meshes.cells_for_target(Lx, Ly, H, target_tets)
+    if dome:
+        pad = dome_pad(Lx, Ly, H, nx, ny, nz, material=material)
+    else:
+        pad = box_pad(Lx, Ly, H, nx, ny, nz, material, name=name)
+    return pad
+
+
+# ----------------------------------------------------------------------------
+# indenters
+
+def _rot_x(angle):
+    c, s = math.cos(angle), math.sin(angle)
+    return np.array([[1, 0, 0], [0, c, -s], [0, s, c]], float)
+
+
+def indenter_geometry(shape, rng=None, sphere_radius=None):
+    """(prm, R, footprint radius, lowest-point offset below the centre)."""
+    if shape == SPHERE:
+        r = sphere_radius if sphere_radius is not None else rng.uniform(2, 8) * MM
+        return (r, 0, 0, 0), np.eye(3), r, r
+    if shape == CYLINDER:      # 5 mm diameter, 10 mm long, axis vertical
+        r, a = 2.5 * MM, 5 * MM
+        return (r, a, 0, 0), np.eye(3), r, a
+    if shape == BOX:           # cube of half-size 3 mm, edge pointing down
+        a = 3 * MM
+        return (a, a, a, 0), _rot_x(math.pi / 4), a * math.sqrt(2), a * math.sqrt(2)
+    if shape == TORUS:         # ring lying flat
+        Rt, rt = 4 * MM, 1 * MM
+        return (Rt, rt, 0, 0), np.eye(3), Rt + rt, rt
+    if shape == TEXTURE:       # sinusoidal plate, amplitude 0.2 mm, period 2 mm
+        A, lam = 0.2 * MM, 2 * MM
+        return (A, lam, 0, 0), np.eye(3), np.inf, A
+    raise ValueError(shape)
+
+
+def place_indenter(pad, shape, xy, dhat, rng=None, sphere_radius=None):
+    """Start pose: lowest point d_hat above the highest rest vertex under the
+    indenter footprint (vertex heights only)."""
+    prm, R, foot, low = indenter_geometry(shape, rng, sphere_radius)
+    X = pad.X
+    near = np.hypot(X[:, 0] - xy[0], X[:, 1] - xy[1]) <= foot + 10 * dhat
+    ztop = X[near, 2].max() if near.any() else X[:, 2].max()
+    c = np.array([xy[0], xy[1], ztop + dhat + low], float)
+    return Indenter(shape, prm, R, c)
+
+
+def seeded_xy(rng, pad, margin):
+    Lx, Ly, _ = pad.dims
+    mx = min(margin, 0.45 * Lx)
+    my = min(margin, 0.45 * Ly)
+    return rng.uniform(mx, Lx - mx), rng.uniform(my, Ly - my)
+
+
+# ----------------------------------------------------------------------------
+# the five workloads
+
+def config1():
+    """Single 18x14x4 mm pad, 12x9x3 cells, sphere r = 5 mm at a seeded (x, y)
+    on the top face shrunk by r/2 margins (seed 1), 0.5 mm over 10 steps."""
+    pad = box_pad(18 * MM, 14 * MM, 4 * MM, 12, 9, 3, Material(0.3e6, 0.45, 1000.0),
+                  name="config1")
+    params = Params()
+    rng = np.random.default_rng(1)
+    r = 5 * MM
+    xy = (rng.uniform(r / 2, pad.dims[0] - r / 2), rng.uniform(r / 2, pad.dims[1] - r / 2))
+    ind = place_indenter(pad, SPHERE, xy, params.dhat, sphere_radius=r)
+    return Episode(pad, ind, 0.5 * MM, 10, params)
+
+
+def config2_pad():
+    zs = meshes.graded_axis_top(4 * MM, 13, 0.2 * MM)
+    return box_pad(18 * MM, 14 * MM, 4 * MM, 45, 35, 13, Material(0.3e6, 0.45, 1000.0),
+                   name="config2", zs=zs)
+
+
+def config2(i, pad=None):
+    """Graded 45x35x13 pad; episode i in 0..4 = sphere, cylinder, cube edge,
+    torus, texture; depth ~ U[0.2, 1.0] mm, 30 steps (SeedSequence(2).spawn(5))."""
+    pad = pad or config2_pad()
+    params = Params()
+    rng = np.random.default_rng(np.random.SeedSequence(2).spawn(5)[i])
+    shape = (SPHERE, CYLINDER, BOX, TORUS, TEXTURE)[i]
+    depth = rng.uniform(0.2, 1.0) * MM
+    r = rng.uniform(2, 8) * MM if shape == SPHERE else None
+    _, _, foot, _ = indenter_geometry(shape, rng, r)
+    margin = 0.5 * foot if np.isfinite(foot) else 0.0
+    xy = seeded_xy(rng, pad, margin)
+    ind = place_indenter(pad, shape, xy, params.dhat, sphere_radius=r)
+    return Episode(pad, ind, depth, 30, params)
+
+
+def _random_env(rng, target_lo, target_hi, log_uniform, n_steps, schedule):
+    shape_idx = int(rng.integers(3))
+    if log_uniform:
+        target = math.exp(rng.uniform(math.log(target_lo), math.log(target_hi)))
+    else:
+        target = rng.uniform(target_lo, target_hi)
+    mat = Material(rng.uniform(0.1, 1.0) * 1e6, rng.uniform(0.40, 0.48), 1000.0)
+    pad = pad_for_target(shape_idx, target, mat)
+    params = Params()
+    shape = int(rng.integers(5))
+    r = rng.uniform(2, 8) * MM if shape == SPHERE else None
+    _, _, foot, _ = indenter_geometry(shape, rng, r)
+    margin = 0.5 * foot if np.isfinite(foot) else 0.0
+    xy = seeded_xy(rng, pad, margin)
+    depth = rng.uniform(0.2, 1.0) * MM
+    ind = place_indenter(pad, shape, xy, params.dhat, sphere_radius=r)
+    return Episode(pad, ind, depth, n_steps, params, schedule)
+
+
+def config3(n_envs=60):
+    """60 uneven envs from SeedSequence(3).spawn(60): pad shape uniform over
+    three, tets ~ U[20k, 80k], E ~ U[0.1, 1.0] MPa, nu ~ U[0.40, 0.48], random
+    indenter type/pose, depth ~ U[0.2, 1.0] mm over 30 steps."""
+    seqs = np.random.SeedSequence(3).spawn(60)
+    return [_random_env(np.random.default_rng(s), 20e3, 80e3, False, 30, "press")
+            for s in seqs[:n_envs]]
+
+
+def config4(n_pads=256):
+    """256 resident pads, tets log-uniform in [5k, 150k] (SeedSequence(4));
+    each pad presses and releases its indenter over 2 x 30 steps."""
+    seqs = np.random.SeedSequence(4).spawn(n_pads + 1)
+    return [_random_env(np.random.default_rng(s), 5e3, 150e3, True, 30, "triangle")
+            for s in seqs[:n_pads]]
+
+
+def config4_arrivals(rate_hz, duration_s, n_pads, seed=4):
+    """Poisson arrival times and uniformly chosen pad ids."""
+    rng = np.random.default_rng(np.random.SeedSequence(seed).spawn(n_pads + 1)[-1])
+    n = rng.poisson(rate_hz * duration_s)
+    t = np.sort(rng.uniform(0.0, duration_s, n))
+    env = rng.integers(0, n_pads, n)
+    return t, env
+
+
+def config5_axes(h_f, centre):
+    L, H = 24 * MM, 5 * MM
+    xs = meshes.sizing_profile_axis(L, centre[0], h_f)
+    ys = meshes.sizing_profile_axis(L, centre[1], h_f)
+    zs = meshes.graded_axis_top(H, 12, h_f)
+    return xs, ys, zs
+
+
+def config5(target=1.2e6):
+    """24x24x5 mm pad, x/y spacing from the cosine sizing profile around a
+    seeded patch centre quantised to h_f * {1, 2, 4, 8}, 12 graded layers with
+    top layer h_f; h_f chosen so that tets ~ 1.2M; sphere r = 3 mm pressed
+    1.0 mm over 60 steps at the patch centre."""
+    rng = np.random.default_rng(np.random.SeedSequence(5))
+    L = 24 * MM
+    centre = (rng.uniform(0.35 * L, 0.65 * L), rng.uniform(0.35 * L, 0.65 * L))
+    lo, hi = 0.02 * MM, 0.5 * MM
+    best = None
+    for _ in range(40):
+        h = math.sqrt(lo * hi)
+        xs, ys, zs = config5_axes(h, centre)
+        n = 6 * (len(xs) - 1) * (len(ys) - 1) * (len(zs) - 1)
+        if best is None or abs(n - target) < abs(best[1] - target):
+            best = (h, n)
+        if n > target:
+            lo = h
+        else:
+            hi = h
+    h_f = best[0]
+    xs, ys, zs = config5_axes(h_f, centre)
+    X, T = meshes.kuhn_grid(xs, ys, zs)
+    pad = Pad("config5", X, T, Material(0.3e6, 0.45, 1000.0), (L, L, 5 * MM))
+    params = Params()
+    ind = place_indenter(pad, SPHERE, centre, params.dhat, sphere_radius=3 * MM)
+    return Episode(pad, ind, 1.0 * MM, 60, params)
