@@ -1,0 +1,168 @@
+"""Benchmark: aggregate tactile-FEM sensor steps/s for 60 mixed pads on one
+MI355X, with p50/p99 fused-step latency.
+
+A step is one pass of the whole hot path over every pad of the batch:
+prediction, feasible start, Newton (element Hessians, barrier, assembly,
+block-Jacobi CG, step filter, line search), Cauchy stress, surface traction,
+contact forces and commit, all in one fused set of launches.
+
+    python bench.py [--gpus 1] [--steps 30] [--warmup 3] [--workload batch60]
+
+Prints one JSON line (see README of the metric fields in the design doc).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def build_workload(name):
+    from workloads import scenes
+    if name == "batch60":
+        return scenes.config3(), "60 mixed pads (flat 18x14x4 / dome 19x16x3 R30 / flat 24x24x5 mm), 20k-80k tets each, random indenters, SeedSequence(3)"
+    if name == "single1944":
+        return [scenes.config1()], "single 18x14x4 mm pad, 1,944 tets, sphere r=5 mm"
+    if name == "large1.2m":
+        return [scenes.config5()], "24x24x5 mm pad, ~1.2M tets, 4-level refinement, sphere r=3 mm"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(envs, budget_s=20.0):
+    """The FP64 oracle as it stands on a bounded sample: steps of the
+    smallest pad of the workload, single thread."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle import stepper
+    ep = min(envs, key=lambda e: e.pad.tets.shape[0])
+    op = stepper.make_pad(ep.pad.X, ep.pad.tets, ep.pad.material.E, ep.pad.material.nu,
+                          ep.pad.material.density)
+    prm = stepper.StepParams(dt=ep.params.dt, dhat=ep.params.dhat, kappa=ep.params.kappa,
+                             newton_tol=ep.params.newton_tol)
+    done, t0 = 0, time.perf_counter()
+    with threadpool_limits(limits=1):
+        for s in range(1, 100):
+            res = stepper.step(op, [ep.pose(s)], prm)
+            stepper.commit(op, res)
+            done += 1
+            if time.perf_counter() - t0 > budget_s:
+                break
+    dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} consecutive steps of the smallest pad of the workload "
+                      f"({ep.pad.tets.shape[0]} tets), FP64 oracle, direct sparse solves, 1 thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="batch60")
+    ap.add_argument("--precision", default="mixed")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-timing", action="store_true")
+    ap.add_argument("--graphs", type=int, default=1)
+    ap.add_argument("--cg-block", type=int, default=0)
+    ap.add_argument("--elem-block", type=int, default=0)
+    ap.add_argument("--autotune", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); pads are independent, so N GPUs "
+              "would each run their own batch (see DESIGN.md, sharding)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2606_20426_amd as tc
+
+    envs, desc = build_workload(args.workload)
+    log(f"workload {args.workload}: {len(envs)} pads, {sum(e.pad.tets.shape[0] for e in envs)} tets")
+    ctx = tc.Context(0)
+    t0 = time.perf_counter()
+    pads = []
+    for e in envs:
+        m = e.pad.material
+        pads.append(tc.Pad(ctx, e.pad.X, e.pad.tets, dict(E=m.E, nu=m.nu, density=m.density),
+                           tc.make_params(precision=args.precision, dt=e.params.dt, dhat=e.params.dhat,
+                                          kappa=e.params.kappa, newton_tol=e.params.newton_tol,
+                                          cg_rel_tol=e.params.cg_rel_tol)))
+    log(f"pads created in {time.perf_counter() - t0:.1f} s; HBM used {ctx.memory()[0] / 2**30:.2f} GiB")
+    ctx.set_launch(cg_block=args.cg_block, elem_block=args.elem_block, use_graphs=args.graphs)
+    if args.autotune:
+        chosen = ctx.autotune(pads, [[e.pose(1)] for e in envs])
+        log(f"autotune: cg block {chosen[0]}, element block {chosen[1]}, CG per replay {chosen[2]}")
+
+    def step(s):
+        return tc.step_batch(ctx, pads, [[e.pose(s)] for e in envs])
+
+    for s in range(1, args.warmup + 1):
+        st = step(s)
+        log(f"warmup {s}: newton max {max(x.newton_iters for x in st)} cg sum {sum(x.cg_iters for x in st)} "
+            f"ms {st[0].ms:.1f}")
+    if not args.no_timing:
+        ctx.set_timing(True)
+        ctx.reset_timing()
+    torch.cuda.synchronize()
+    lat = []
+    newton, cg = [], []
+    t_start = time.perf_counter()
+    for s in range(args.warmup + 1, args.warmup + args.steps + 1):
+        a = time.perf_counter()
+        st = step(s)
+        lat.append((time.perf_counter() - a) * 1e3)
+        newton.append(max(x.newton_iters for x in st))
+        cg.append(sum(x.cg_iters for x in st))
+        log(f"step {s}: {lat[-1]:.1f} ms, newton max {newton[-1]}, cg total {cg[-1]}")
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_start
+    n_env = len(envs)
+    value = n_env * args.steps / total
+    timers = ctx.timing() if not args.no_timing else {}
+    roof = None
+    if timers:
+        # dominant kernel by total time
+        k = max(timers, key=lambda n: timers[n][0] * timers[n][1])
+        avg_ms, launches, bpl = timers[k]
+        achieved = bpl / (avg_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "kernel": k, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "avg_launch_ms": avg_ms, "launches": launches, "bytes_per_launch": bpl}
+        log("kernel timers (avg ms, launches, GB/s):")
+        for name, (a, n, b) in sorted(timers.items(), key=lambda kv: -kv[1][0] * kv[1][1]):
+            log(f"  {name:14s} {a:9.4f} {n:7d} {b / max(a, 1e-12) / 1e6:9.1f}")
+    lat_s = sorted(lat)
+    out = {
+        "metric": "aggregate IPC-FEM sensor steps/s (60 mixed envs) + p99 step latency",
+        "value": round(value, 2), "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(total / args.steps * 1e3, 3),
+        "p50_ms": round(float(np.percentile(lat_s, 50)), 3),
+        "p99_ms": round(float(np.percentile(lat_s, 99)), 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if args.precision == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "description": desc, "envs": n_env,
+                   "tets": int(sum(e.pad.tets.shape[0] for e in envs)),
+                   "newton_max_mean": float(np.mean(newton)), "cg_iters_mean": float(np.mean(cg)),
+                   "precision": args.precision, "graphs": bool(args.graphs and args.no_timing)},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        log("timing the oracle on a bounded sample ...")
+        out["cpu_baseline"] = cpu_baseline(envs)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,357 @@
+/*
+ * tacauchy.h - C ABI of the MI355X tactile-FEM hot path.
+ *
+ * One implicit time step of a tetrahedral Stable Neo-Hookean gel pad pressed
+ * by rigid indenters, followed by Cauchy stress and surface traction
+ * extraction (TaCauchy, Sec. III-B/C, Alg. 1 and Alg. 2):
+ *
+ *   physics   minimise the incremental potential
+ *               E(x) = 1/2 |x - xhat|_M^2 + dt^2 [ sum_e V_e Psi(F_e) + E_b(x) ]
+ *             (Psi: energy density whose derivative is the first Piola stress
+ *             of Eq. 2; E_b: IPC log barrier with threshold d_hat, Sec. III-B)
+ *             by Newton with a matrix-free-assembled, block-Jacobi
+ *             preconditioned CG solve and backtracking line search;
+ *   stress    per tet sigma = J^-1 P F^T = (mu/J) F F^T + lambda (J - alpha) I
+ *             (Eq. 3 and Eq. 4);
+ *   traction  per surface triangle t = sigma n, p_n = t . n, t_tau = t - p_n n
+ *             (Alg. 1, Eq. 6-9);
+ *   contact   per contact vertex f = -dE_b/dx, normal/tangential split,
+ *             pressure |f| / A (Alg. 2).
+ *
+ * Conventions
+ *   - Every call returns tc_status: TC_OK (0) or a negative error code.
+ *     tc_last_error() returns a message for the calling thread's last error.
+ *   - No call throws; no torch or HIP type appears in a signature.  Device
+ *     pointers are plain void* into memory of the context's device.
+ *   - Units: metres, seconds, kilograms, pascals, newtons.
+ *   - Arrays are row-major; [N][3] means N consecutive xyz triples.
+ *   - Every input array is copied; the caller keeps ownership of its memory.
+ *   - Entry points marked "host only" touch no GPU and may run on a machine
+ *     without one.  All others need a context on an MI355X (gfx950).
+ *   - Calls on one context are not thread-safe with respect to each other,
+ *     except tc_server_submit / tc_server_poll, which may be called from any
+ *     thread while the server's own thread drives the device.
+ */
+#ifndef TACAUCHY_H
+#define TACAUCHY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status */
+typedef int32_t tc_status;
+#define TC_OK               0
+#define TC_E_INVALID_ARG   -1  /* null pointer, bad size, value out of range */
+#define TC_E_BAD_MESH      -2  /* index out of range, non-positive tet volume */
+#define TC_E_NO_MEMORY     -3  /* HBM budget exceeded or allocation failed */
+#define TC_E_HIP           -4  /* HIP runtime error (message has details) */
+#define TC_E_INFEASIBLE    -5  /* indenter pose leaves no feasible start */
+#define TC_E_NOT_CONVERGED -6  /* Newton hit max_newton iterations */
+#define TC_E_LINESEARCH    -7  /* no energy decrease within max_halvings */
+#define TC_E_NO_DEVICE     -8  /* no usable gfx950 device */
+#define TC_E_BUSY          -9  /* pad has a request in flight on a server */
+
+/* ------------------------------------------------------------- constants */
+#define TC_PREC_FP64  0   /* every kernel in float64 */
+#define TC_PREC_MIXED 1   /* element/assembly/SpMV in float32; positions,
+                             residual, dot products, line-search energy and
+                             barrier in float64 */
+
+#define TC_PRECOND_BLOCK_JACOBI  0  /* inverse of each vertex's 3x3 diagonal block */
+#define TC_PRECOND_JACOBI        1  /* inverse of the scalar diagonal */
+
+/* Indenter shapes (local frame; the solid is where phi < 0):
+ *   SPHERE   prm[0] = radius                               phi = |y| - r
+ *   CYLINDER prm[0] = radius, prm[1] = half height, axis z
+ *   BOX      prm[0..2] = half extents
+ *   TORUS    prm[0] = ring radius, prm[1] = tube radius, axis z
+ *   TEXTURE  prm[0] = amplitude A, prm[1] = period L: plate occupying
+ *            y_z >= A sin(2 pi y_x / L) sin(2 pi y_y / L); phi is the
+ *            1-Lipschitz bound (eta - y_z) / sqrt(1 + (2 pi A / L)^2). */
+#define TC_SPHERE   0
+#define TC_CYLINDER 1
+#define TC_BOX      2
+#define TC_TORUS    3
+#define TC_TEXTURE  4
+
+#define TC_MAX_INDENTERS 5   /* per pad and step */
+#define TC_MAX_MATERIALS 8   /* per pad */
+
+/* Output / state fields for tc_pad_read (and tc_pad_write where noted).
+ * dtype "real" is float64 in TC_PREC_FP64 and float32 in TC_PREC_MIXED;
+ * tc_field_info reports it. */
+#define TC_F_POSITIONS        0  /* f64 [V][3] committed positions (writable) */
+#define TC_F_VELOCITIES       1  /* f64 [V][3] committed velocities (writable) */
+#define TC_F_REST             2  /* f64 [V][3] rest positions */
+#define TC_F_SIGMA            3  /* real [T][6] Cauchy stress (xx,yy,zz,yz,xz,xy) */
+#define TC_F_TRACTION         4  /* real [S][3] t = sigma n per surface triangle */
+#define TC_F_PRESSURE         5  /* real [S] p_n = t . n (> 0 tension) */
+#define TC_F_TANGENTIAL       6  /* real [S][3] t_tau = t - p_n n */
+#define TC_F_TRI_AREA         7  /* real [S] current triangle area */
+#define TC_F_TRI_NORMAL       8  /* real [S][3] current unit normal */
+#define TC_F_CONTACT_FORCE    9  /* f64 [C][3] f_k = -dE_b/dx_k */
+#define TC_F_CONTACT_NORMAL  10  /* f64 [C][3] area-weighted vertex normal */
+#define TC_F_CONTACT_AREA    11  /* f64 [C] 1/3 of incident contact-face area */
+#define TC_F_CONTACT_FN      12  /* f64 [C][3] (f . n) n */
+#define TC_F_CONTACT_FT      13  /* f64 [C][3] f - f_n */
+#define TC_F_CONTACT_PRESSURE 14 /* f64 [C] |f| / A */
+#define TC_F_REACTION        15  /* f64 [3] force on the indenters = -sum f_k */
+#define TC_F_TRACTION_SUM    16  /* f64 [3] sum over contact-face tris of t A */
+#define TC_F_SURFACE_TRIS    17  /* i32 [S][3] outward-wound surface triangles */
+#define TC_F_SURFACE_PARENT  18  /* i32 [S] owning tet of each triangle */
+#define TC_F_SURFACE_IS_TOP  19  /* u8  [S] 1 = contact face */
+#define TC_F_CANDIDATES      20  /* i32 [C] contact vertex ids, ascending */
+#define TC_F_CAND_REST_AREA  21  /* f64 [C] barrier weight A_k (rest) */
+#define TC_F_MASS            22  /* f64 [V] lumped mass */
+#define TC_F_FIXED           23  /* u8  [V] xyz bitmask of fixed components */
+#define TC_F_TETS            24  /* i32 [T][4] */
+#define TC_F_COUNT           25
+
+#define TC_DT_F64 0
+#define TC_DT_F32 1
+#define TC_DT_I32 2
+#define TC_DT_U8  3
+
+/* ---------------------------------------------------------------- types */
+typedef struct tc_context tc_context;
+typedef struct tc_pad tc_pad;
+typedef struct tc_server tc_server;
+
+/* Tet mesh (Alg. 1 / Alg. 2 input (V, T)). */
+typedef struct {
+  int32_t n_verts;
+  int32_t n_tets;
+  const double* rest_xyz;      /* [n_verts][3] host */
+  const int32_t* tets;         /* [n_tets][4] host, det(Dm) > 0 */
+  const uint8_t* fixed;        /* [n_verts] bit c set = component c fixed;
+                                  NULL = the base (minimum along the thinnest
+                                  bounding-box axis) fully fixed */
+  const int32_t* tet_material; /* [n_tets] index into the material table, or
+                                  NULL = material 0 everywhere */
+} tc_mesh;
+
+/* Eq. 1 inputs: Young's modulus [Pa] > 0, Poisson ratio in (-1, 0.5),
+ * density [kg/m^3] > 0. */
+typedef struct {
+  double E;
+  double nu;
+  double density;
+} tc_material;
+
+typedef struct {
+  double dt;            /* time step [s] > 0 */
+  double dhat;          /* barrier threshold d_hat [m] > 0 */
+  double kappa;         /* barrier stiffness [Pa] > 0 */
+  double newton_tol;    /* converged when |p|_inf <= tol * bbox diagonal */
+  double cg_rel_tol;    /* CG stops at sqrt(r.z / r0.z0) <= this */
+  int32_t max_newton;   /* Newton cap (1024 in Sec. III-B) */
+  int32_t max_cg;       /* CG cap per Newton iteration */
+  int32_t quasi_static; /* 1 = drop the inertia term */
+  int32_t precision;    /* TC_PREC_* (fixed at pad creation) */
+  double gravity[3];    /* [m/s^2], enters xhat = x + dt v + dt^2 g */
+  int32_t literal_alpha;/* 1 = rest shift alpha = 1 exactly as Eq. 2 prints */
+  int32_t precond;      /* TC_PRECOND_* */
+  int32_t max_halvings; /* line-search halvings before TC_E_LINESEARCH */
+  int32_t reserved;
+} tc_params;
+
+/* Rigid indenter pose at the end of the step: world x = R y + c. */
+typedef struct {
+  int32_t shape;        /* TC_SPHERE ... TC_TEXTURE */
+  int32_t reserved;
+  double R[9];          /* row-major rotation, orthonormal to 1e-9, det +1 */
+  double c[3];          /* centre [m] */
+  double prm[4];        /* shape parameters [m], see TC_SPHERE ... */
+} tc_indenter;
+
+typedef struct {
+  int32_t status;          /* TC_OK or the step's error */
+  int32_t newton_iters;
+  int32_t cg_iters;        /* summed over Newton iterations */
+  int32_t ls_halvings;     /* summed over Newton iterations */
+  double final_step_inf;   /* |p|_inf of the last Newton direction [m] */
+  double energy;           /* E at the accepted state [J] */
+  double reaction[3];      /* force on the indenters [N] */
+  double ms;               /* wall time of the call [ms] */
+} tc_step_stats;
+
+typedef struct {
+  int32_t n_verts, n_tets, n_surface_tris, n_top_tris, n_candidates;
+  int32_t ell_width;       /* stored blocks per matrix row */
+  int32_t precision;
+  int32_t n_materials;
+  uint64_t resident_bytes; /* HBM held while the pad exists */
+  uint64_t scratch_bytes;  /* HBM needed while a step runs */
+  double bbox_diag;        /* [m] */
+} tc_pad_info;
+
+/* ---------------------------------------------------- host-only helpers */
+const char* tc_version(void);                 /* host only */
+const char* tc_status_string(tc_status s);    /* host only */
+const char* tc_last_error(void);              /* host only, thread-local */
+
+/* Defaults: dt 1/60, d_hat 1e-4, kappa 1e3, newton_tol 1e-6, cg_rel_tol 1e-4,
+ * max_newton 1024, max_cg 4000, dynamic, MIXED, block Jacobi, 40 halvings. */
+tc_status tc_params_default(tc_params* out);  /* host only */
+
+/* Argument checks used by every entry point (host only):
+ * mesh: counts > 0, pointers non-null, indices in range, distinct vertices
+ *       per tet, det(Dm) > 0 (TC_E_BAD_MESH), fixed bits <= 7, material ids
+ *       in [0, n_materials);
+ * material: E > 0, -1 < nu < 0.5, density > 0 (all finite);
+ * params: dt, dhat, kappa, tolerances > 0 and finite, caps >= 1, known enums;
+ * indenters: 0 <= n <= TC_MAX_INDENTERS, known shape, positive parameters,
+ *       R orthonormal with det +1 to 1e-9, finite centre. */
+tc_status tc_validate_mesh(const tc_mesh* mesh, int32_t n_materials);
+tc_status tc_validate_materials(int32_t n, const tc_material* m);
+tc_status tc_validate_params(const tc_params* p);
+tc_status tc_validate_indenters(int32_t n, const tc_indenter* ind);
+
+/* Alg. 1 lines 1-3 on the host: surface triangles (faces owned by exactly
+ * one tet, outward winding, ascending (tet, local face) order), their parent
+ * tets, the contact-face label (rest outward normal >= 0.5 along the thinnest
+ * bounding-box axis, on the side away from the base) and the contact vertices
+ * (vertices of contact-face triangles with a free component, ascending).
+ * Two-call pattern: with tris == NULL only the counts are written.  Capacity
+ * arguments are element counts of the caller's arrays (host only). */
+tc_status tc_mesh_surface(const tc_mesh* mesh,
+                          int32_t* n_tris, int32_t* n_candidates,
+                          int32_t* tris, int32_t* parent, uint8_t* is_top,
+                          int32_t* candidates,
+                          int32_t tris_capacity, int32_t cand_capacity);
+
+/* ---------------------------------------------------------------- context */
+/* device: HIP ordinal; hip_stream: a hipStream_t of that device (e.g. torch's
+ * current stream) or NULL for a stream the context creates; hbm_budget: bytes
+ * the context may hold in total (resident pads + step scratch), 0 = no limit
+ * beyond the device. */
+tc_status tc_context_create(int32_t device, void* hip_stream, uint64_t hbm_budget,
+                            tc_context** out);
+tc_status tc_context_destroy(tc_context* ctx);
+/* Bytes currently held (resident + scratch pool) and the budget. */
+tc_status tc_context_memory(const tc_context* ctx, uint64_t* used, uint64_t* budget);
+
+/* Per-kernel timing with HIP events on the context stream (for roofline
+ * reporting).  names/avg_ms/launches are filled for up to cap kernels. */
+#define TC_TIMER_NAME_LEN 32
+tc_status tc_context_set_timing(tc_context* ctx, int32_t enable);
+tc_status tc_context_timing(tc_context* ctx, int32_t cap, int32_t* n,
+                            char (*names)[TC_TIMER_NAME_LEN], double* avg_ms,
+                            int64_t* launches, double* bytes_per_launch);
+tc_status tc_context_reset_timing(tc_context* ctx);
+
+/* Launch-shape autotuner: times the element, assembly and CG kernels on the
+ * given pads for each candidate block size and CG iterations per graph
+ * replay, and keeps the fastest for the context.  Committed pad state is not
+ * modified.  chosen[0..2] = (CG block, element block, CG iterations per
+ * replay) when chosen != NULL. */
+tc_status tc_autotune(tc_context* ctx, int32_t n, tc_pad* const* pads,
+                      const int32_t* n_ind, const tc_indenter* ind, int32_t* chosen);
+/* Force a launch shape (block sizes 64..1024, multiple of 64; replay >= 2,
+ * even).  0 leaves a value unchanged. */
+tc_status tc_set_launch(tc_context* ctx, int32_t cg_block, int32_t elem_block,
+                        int32_t cg_per_replay, int32_t use_graphs);
+
+/* ------------------------------------------------------------------- pads */
+/* Copies the mesh and materials into HBM and runs the setup kernels: Eq. 1
+ * Lame parameters, Dm^-1 and V_e, lumped mass, rest contact areas; builds the
+ * surface (Alg. 1 lines 1-3) and the sparsity of the assembled Hessian on
+ * the host.  State starts at rest (x = X, v = 0). */
+tc_status tc_pad_create(tc_context* ctx, const tc_mesh* mesh,
+                        int32_t n_materials, const tc_material* materials,
+                        const tc_params* params, tc_pad** out);
+tc_status tc_pad_destroy(tc_pad* pad);
+tc_status tc_pad_get_info(const tc_pad* pad, tc_pad_info* out);
+/* Replace solver parameters (precision cannot change). */
+tc_status tc_pad_set_params(tc_pad* pad, const tc_params* params);
+/* Back to rest: x = X, v = 0. */
+tc_status tc_pad_reset(tc_pad* pad);
+/* Release the pad's step scratch back to the context pool (it is taken again
+ * by the next step). */
+tc_status tc_pad_release_scratch(tc_pad* pad);
+
+/* ------------------------------------------------------------------- step */
+/* Alg. 2 one iteration: physics, stress, traction, contact for one pad under
+ * n_ind end-of-step indenter poses.  Synchronous on the context stream and
+ * transactional: on error the committed state (x, v) is unchanged. */
+tc_status tc_step(tc_pad* pad, int32_t n_ind, const tc_indenter* ind,
+                  tc_step_stats* stats);
+
+/* The same for n pads fused into one set of launches (uneven pads share every
+ * kernel launch).  n_ind[i] poses for pad i are consecutive in ind.  stats[i]
+ * receives pad i's outcome; the return value is TC_OK when every pad
+ * succeeded, else the first failing pad's status.  Each pad is transactional
+ * on its own.  A pad may appear only once. */
+tc_status tc_step_batch(tc_context* ctx, int32_t n, tc_pad* const* pads,
+                        const int32_t* n_ind, const tc_indenter* ind,
+                        tc_step_stats* stats);
+
+/* Extraction only (Alg. 2 stress/traction/contact) on the committed positions
+ * under the given poses: fills SIGMA ... TRACTION_SUM. */
+tc_status tc_extract(tc_pad* pad, int32_t n_ind, const tc_indenter* ind);
+
+/* ------------------------------------------------------------------ fields */
+tc_status tc_field_info(const tc_pad* pad, int32_t field, int32_t* dtype,
+                        int64_t* count, int32_t* components);
+/* Copy a field into dst (bytes must be >= its size, else TC_E_INVALID_ARG).
+ * dst_is_device: 1 = dst is device memory on the context's device. */
+tc_status tc_pad_read(const tc_pad* pad, int32_t field, void* dst, size_t bytes,
+                      int32_t dst_is_device);
+/* Overwrite POSITIONS or VELOCITIES (bytes must equal the field size). */
+tc_status tc_pad_write(tc_pad* pad, int32_t field, const void* src, size_t bytes,
+                       int32_t src_is_device);
+
+/* ------------------------------------------------------ checkpoint/resume */
+/* Serialise x, v and the step counter.  With buf == NULL *bytes receives the
+ * size needed; otherwise *bytes is the capacity on input and the size written
+ * on output.  load restores a buffer written for a pad with the same mesh. */
+tc_status tc_pad_save_state(const tc_pad* pad, void* buf, size_t* bytes);
+tc_status tc_pad_load_state(tc_pad* pad, const void* buf, size_t bytes);
+
+/* --------------------------------------------------------------- serving */
+typedef struct {
+  uint64_t ticket;
+  int32_t status;          /* step status */
+  int32_t pad_index;       /* caller tag given at submit */
+  double t_arrive_ms;      /* submit time, ms on the server clock */
+  double t_admit_ms;       /* admission into the running batch */
+  double t_done_ms;        /* result committed and readable */
+  tc_step_stats stats;
+} tc_result;
+
+typedef struct {
+  int64_t submitted, admitted, completed, rejected;
+  int32_t queued, running;
+  int32_t max_running_seen;
+  int64_t ticks;           /* batched Newton iterations executed */
+  uint64_t scratch_in_use; /* bytes of step scratch held by running requests */
+} tc_server_stats;
+
+/* Continuous-batching request loop on its own host thread.  Pads stay
+ * resident; a request (pad, poses) is admitted when a slot is free and its
+ * step scratch fits the context budget, joins the running batch at the next
+ * Newton-iteration boundary and leaves it when its step completes.
+ * max_slots: requests on the device at once (>= 1). */
+tc_status tc_server_create(tc_context* ctx, int32_t max_slots, tc_server** out);
+/* Queue one step request.  The pad must belong to the server's context;
+ * requests for the same pad run in submission order.  tag is echoed in the
+ * result's pad_index. */
+tc_status tc_server_submit(tc_server* srv, tc_pad* pad, int32_t tag, int32_t n_ind,
+                           const tc_indenter* ind, uint64_t* ticket);
+/* Collect up to cap finished results; waits up to wait_us microseconds for
+ * the first one (0 = do not wait). */
+tc_status tc_server_poll(tc_server* srv, tc_result* out, int32_t cap, int32_t* n,
+                         int32_t wait_us);
+tc_status tc_server_get_stats(tc_server* srv, tc_server_stats* out);
+/* Stops the thread after finishing running requests; queued ones are
+ * dropped with status TC_E_BUSY. */
+tc_status tc_server_destroy(tc_server* srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TACAUCHY_H */

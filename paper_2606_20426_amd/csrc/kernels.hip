@@ -1,0 +1,1517 @@
+// HIP kernels (gfx950, wave64) of one implicit step of a batch of gel pads.
+//
+// Work is cut into tiles of one pad each (Tile{env, tile}); a launch covers
+// the tiles of every pad in the batch, so uneven pads share each launch.
+// Per-pad reductions are deterministic: every tile writes one partial, and
+// the consumer kernel re-reduces the pad's partials in a fixed order (no
+// atomics on floating point anywhere), so a pad's result does not depend on
+// which other pads share the batch.
+//
+// Precision: R = float (mixed mode: element, assembly, SpMV, preconditioner)
+// or double (FP64 mode).  Positions, residual, dot products, line-search
+// energy and barrier terms are always double.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "../../include/tacauchy.h"
+#include "tc_device.h"
+#include "tc_launch.h"
+
+namespace tc {
+
+// ---------------------------------------------------------------- helpers
+
+// Blocks are handed to the 8 XCDs round-robin by block index; give each XCD
+// a contiguous run of tiles so that neighbouring tiles (which gather the same
+// vertices) share that XCD's L2.  gridDim.x is a multiple of 8.
+__device__ __forceinline__ int xcd_tile(int ntiles) {
+  const int G = gridDim.x;
+  const int b = blockIdx.x;
+  const int t = (b & 7) * (G >> 3) + (b >> 3);
+  return t < ntiles ? t : -1;
+}
+
+__device__ __forceinline__ bool running(const EnvState* S) {
+  return S->phase == PH_RUN && S->status == TC_OK;
+}
+
+__device__ __forceinline__ bool initialising(const EnvState* S) {
+  return S->phase == PH_INIT && S->status == TC_OK;
+}
+
+struct OpSum { __device__ double operator()(double a, double b) const { return a + b; } };
+struct OpMax { __device__ double operator()(double a, double b) const { return fmax(a, b); } };
+struct OpMin { __device__ double operator()(double a, double b) const { return fmin(a, b); } };
+
+// Block-wide reduction, identical result in every thread.  Butterfly within
+// each wave (pairs add in both orders -> bitwise equal lanes), then every
+// thread folds the per-wave values in wave order.  Must be reached by all
+// threads of the block.
+template <class Op>
+__device__ double block_reduce(double v, Op op, double* sh) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = op(v, __shfl_xor(v, o, 64));
+  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[w] = v;
+  __syncthreads();
+  double r = sh[0];
+  for (int k = 1; k < nw; ++k) r = op(r, sh[k]);
+  return r;
+}
+
+template <class Op>
+__device__ double reduce_partials(const double* p, int n, Op op, double init, double* sh) {
+  double v = init;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) v = op(v, p[i]);
+  return block_reduce(v, op, sh);
+}
+
+template <typename R> __device__ __forceinline__ R rsq(R x);
+template <> __device__ __forceinline__ float rsq<float>(float x) { return 1.0f / sqrtf(x); }
+template <> __device__ __forceinline__ double rsq<double>(double x) { return 1.0 / sqrt(x); }
+
+// ------------------------------------------------------- 3x3 eigen / SVD
+
+// One cyclic-Jacobi rotation annihilating A[p][q]; Q accumulates the
+// eigenvectors (columns).
+template <int p, int q, typename R>
+__device__ __forceinline__ void jacobi_rot(R A[3][3], R Q[3][3]) {
+  const R apq = A[p][q];
+  if (apq == R(0)) return;
+  const R tau = (A[q][q] - A[p][p]) / (R(2) * apq);
+  const R t = (tau >= R(0) ? R(1) : R(-1)) / (fabs(tau) + sqrt(R(1) + tau * tau));
+  const R c = rsq<R>(R(1) + t * t), s = t * c;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const R akp = A[k][p], akq = A[k][q];
+    A[k][p] = c * akp - s * akq;
+    A[k][q] = s * akp + c * akq;
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const R apk = A[p][k], aqk = A[q][k];
+    A[p][k] = c * apk - s * aqk;
+    A[q][k] = s * apk + c * aqk;
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const R qkp = Q[k][p], qkq = Q[k][q];
+    Q[k][p] = c * qkp - s * qkq;
+    Q[k][q] = s * qkp + c * qkq;
+  }
+}
+
+template <typename R> struct Eps;
+template <> struct Eps<float> { static constexpr float v = 1e-7f; static constexpr int sweeps = 6; };
+template <> struct Eps<double> { static constexpr double v = 1e-15; static constexpr int sweeps = 10; };
+
+// Symmetric eigen-decomposition: A (destroyed) = Q diag(w) Q^T.
+template <typename R>
+__device__ void sym_eig3(R A[3][3], R Q[3][3], R w[3]) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) Q[i][j] = (i == j) ? R(1) : R(0);
+  for (int sweep = 0; sweep < Eps<R>::sweeps; ++sweep) {
+    const R off = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
+    const R dia = A[0][0] * A[0][0] + A[1][1] * A[1][1] + A[2][2] * A[2][2];
+    if (off <= Eps<R>::v * Eps<R>::v * dia) break;
+    jacobi_rot<0, 1>(A, Q);
+    jacobi_rot<0, 2>(A, Q);
+    jacobi_rot<1, 2>(A, Q);
+  }
+  w[0] = A[0][0]; w[1] = A[1][1]; w[2] = A[2][2];
+}
+
+template <typename R>
+__device__ __forceinline__ void swap_cols(R M[3][3], R w[3], int) {}
+
+template <int i, int j, typename R>
+__device__ __forceinline__ void sort_pair(R V[3][3], R w[3]) {
+  if (w[i] < w[j]) {
+    const R t = w[i]; w[i] = w[j]; w[j] = t;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) { const R a = V[k][i]; V[k][i] = V[k][j]; V[k][j] = a; }
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ R det3(const R M[3][3]) {
+  return M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1])
+       - M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0])
+       + M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0]);
+}
+
+// Rotation-variant SVD F = U diag(s) V^T with U, V in SO(3) and s0 >= s1 >=
+// |s2|, s2 < 0 for inverted elements.  V from the eigenvectors of F^T F,
+// U by Gram-Schmidt on the columns of F V.
+template <typename R>
+__device__ void svd3(const R F[3][3], R U[3][3], R s[3], R V[3][3]) {
+  R S[3][3], w[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      S[i][j] = F[0][i] * F[0][j] + F[1][i] * F[1][j] + F[2][i] * F[2][j];
+  sym_eig3(S, V, w);
+  sort_pair<0, 1>(V, w);
+  sort_pair<0, 2>(V, w);
+  sort_pair<1, 2>(V, w);
+  if (det3(V) < R(0)) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) V[k][2] = -V[k][2];
+  }
+  R B[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) B[i][j] = F[i][0] * V[0][j] + F[i][1] * V[1][j] + F[i][2] * V[2][j];
+  R u0[3] = {B[0][0], B[1][0], B[2][0]};
+  R n0 = sqrt(u0[0] * u0[0] + u0[1] * u0[1] + u0[2] * u0[2]);
+  if (n0 > R(1e-30)) { u0[0] /= n0; u0[1] /= n0; u0[2] /= n0; }
+  else { u0[0] = 1; u0[1] = 0; u0[2] = 0; n0 = 0; }
+  R u1[3] = {B[0][1], B[1][1], B[2][1]};
+  const R d01 = u0[0] * u1[0] + u0[1] * u1[1] + u0[2] * u1[2];
+  u1[0] -= d01 * u0[0]; u1[1] -= d01 * u0[1]; u1[2] -= d01 * u0[2];
+  R n1 = sqrt(u1[0] * u1[0] + u1[1] * u1[1] + u1[2] * u1[2]);
+  if (n1 > Eps<R>::v * n0 + R(1e-30)) {
+    u1[0] /= n1; u1[1] /= n1; u1[2] /= n1;
+  } else {  // flattened element: any direction orthogonal to u0
+    const R ex = fabs(u0[0]) < R(0.9) ? R(1) : R(0), ey = R(1) - ex;
+    u1[0] = u0[1] * R(0) - u0[2] * ey;
+    u1[1] = u0[2] * ex - u0[0] * R(0);
+    u1[2] = u0[0] * ey - u0[1] * ex;
+    const R m = rsq<R>(u1[0] * u1[0] + u1[1] * u1[1] + u1[2] * u1[2]);
+    u1[0] *= m; u1[1] *= m; u1[2] *= m;
+    n1 = 0;
+  }
+  const R u2[3] = {u0[1] * u1[2] - u0[2] * u1[1], u0[2] * u1[0] - u0[0] * u1[2],
+                   u0[0] * u1[1] - u0[1] * u1[0]};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) { U[k][0] = u0[k]; U[k][1] = u1[k]; U[k][2] = u2[k]; }
+  s[0] = n0;
+  s[1] = n1;
+  s[2] = u2[0] * B[0][2] + u2[1] * B[1][2] + u2[2] * B[2][2];
+}
+
+// K += lam c c^T over the 10 stored blocks of the symmetric 12x12.
+template <typename R>
+__device__ __forceinline__ void rank1_update(R K[78], const R c[4][3], R lam) {
+  int o = 0;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = a; b < 4; ++b) {
+      if (a == b) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int k = i; k < 3; ++k) K[o++] += lam * c[a][i] * c[a][k];
+      } else {
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+          for (int k = 0; k < 3; ++k) K[o++] += lam * c[a][i] * c[b][k];
+      }
+    }
+}
+
+// ------------------------------------------------ signed distance functions
+
+// Local-frame distance, gradient and (optionally) Hessian of indenter shapes
+// (see TC_SPHERE ... in tacauchy.h).
+__device__ void sdf_local(int shape, const double* prm, const double y[3], double& phi,
+                          double g[3], double H[3][3], bool wantH) {
+  if (wantH)
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) H[i][j] = 0.0;
+  if (shape == TC_SPHERE) {
+    const double L = sqrt(y[0] * y[0] + y[1] * y[1] + y[2] * y[2]);
+    phi = L - prm[0];
+    if (L > 0) {
+      for (int i = 0; i < 3; ++i) g[i] = y[i] / L;
+      if (wantH)
+        for (int i = 0; i < 3; ++i)
+          for (int j = 0; j < 3; ++j) H[i][j] = ((i == j ? 1.0 : 0.0) - g[i] * g[j]) / L;
+    } else {
+      g[0] = 0; g[1] = 0; g[2] = 1;
+    }
+    return;
+  }
+  if (shape == TC_BOX) {
+    double q[3], sg[3];
+    int npos = 0;
+    for (int i = 0; i < 3; ++i) {
+      sg[i] = y[i] >= 0 ? 1.0 : -1.0;
+      q[i] = fabs(y[i]) - prm[i];
+      npos += q[i] > 0;
+    }
+    if (npos >= 2) {
+      double qp[3], L2 = 0;
+      for (int i = 0; i < 3; ++i) { qp[i] = q[i] > 0 ? q[i] : 0.0; L2 += qp[i] * qp[i]; }
+      const double L = sqrt(L2);
+      phi = L;
+      for (int i = 0; i < 3; ++i) g[i] = qp[i] * sg[i] / L;
+      if (wantH)
+        for (int i = 0; i < 3; ++i)
+          for (int j = 0; j < 3; ++j)
+            H[i][j] = ((i == j && q[i] > 0) ? 1.0 : 0.0) / L - g[i] * g[j] / L;
+    } else {
+      int k = 0;
+      if (q[1] > q[k]) k = 1;
+      if (q[2] > q[k]) k = 2;
+      phi = q[k];
+      g[0] = g[1] = g[2] = 0;
+      g[k] = sg[k];
+    }
+    return;
+  }
+  if (shape == TC_TEXTURE) {
+    const double A = prm[0], kk = 2.0 * M_PI / prm[1];
+    const double c = sqrt(1.0 + (kk * A) * (kk * A));
+    const double sx = sin(kk * y[0]), cx = cos(kk * y[0]);
+    const double sy = sin(kk * y[1]), cy = cos(kk * y[1]);
+    const double eta = A * sx * sy;
+    phi = (eta - y[2]) / c;
+    g[0] = A * kk * cx * sy / c;
+    g[1] = A * kk * sx * cy / c;
+    g[2] = -1.0 / c;
+    if (wantH) {
+      H[0][0] = -kk * kk * eta / c;
+      H[1][1] = -kk * kk * eta / c;
+      H[0][1] = H[1][0] = A * kk * kk * cx * cy / c;
+    }
+    return;
+  }
+  // axisymmetric shapes about local z: cylinder and torus
+  const double rho = sqrt(y[0] * y[0] + y[1] * y[1]);
+  double er[3] = {1.0, 0.0, 0.0};
+  const double irho = rho > 0 ? 1.0 / rho : 1.0;
+  if (rho > 0) { er[0] = y[0] * irho; er[1] = y[1] * irho; }
+  // Hessian of rho: (I_xy - er er^T) / rho
+  auto add_Hrho = [&](double w) {
+    for (int i = 0; i < 2; ++i)
+      for (int j = 0; j < 2; ++j) H[i][j] += w * ((i == j ? 1.0 : 0.0) - er[i] * er[j]) * irho;
+  };
+  if (shape == TC_CYLINDER) {
+    const double r = prm[0], a = prm[1];
+    const double sz = y[2] >= 0 ? 1.0 : -1.0;
+    const double qx = rho - r, qy = fabs(y[2]) - a;
+    if (qx > 0 && qy > 0) {
+      const double L = sqrt(qx * qx + qy * qy);
+      phi = L;
+      const double fr = qx / L, fz = qy / L;
+      g[0] = fr * er[0]; g[1] = fr * er[1]; g[2] = fz * sz;
+      if (wantH) {
+        const double L3 = L * L * L;
+        const double prr = qy * qy / L3, pzz = qx * qx / L3, prz = -qx * qy / L3;
+        const double ez[3] = {0, 0, sz};
+        for (int i = 0; i < 3; ++i)
+          for (int j = 0; j < 3; ++j)
+            H[i][j] = prr * er[i] * er[j] + pzz * ez[i] * ez[j] + prz * (er[i] * ez[j] + ez[i] * er[j]);
+        add_Hrho(fr);
+      }
+    } else if (qx > 0 || (qx <= 0 && qy <= 0 && qx >= qy)) {
+      phi = (qx > 0) ? qx : fmax(qx, qy);
+      g[0] = er[0]; g[1] = er[1]; g[2] = 0;
+      if (wantH) add_Hrho(1.0);
+    } else {
+      phi = (qy > 0) ? qy : fmax(qx, qy);
+      g[0] = 0; g[1] = 0; g[2] = sz;
+    }
+    return;
+  }
+  // torus: | (rho - Rt, y_z) | - rt
+  const double w0 = rho - prm[0], w1 = y[2];
+  const double L = sqrt(w0 * w0 + w1 * w1);
+  phi = L - prm[1];
+  const double fr = w0 / L, fz = w1 / L;
+  g[0] = fr * er[0]; g[1] = fr * er[1]; g[2] = fz;
+  if (wantH) {
+    const double L3 = L * L * L;
+    const double prr = w1 * w1 / L3, pzz = w0 * w0 / L3, prz = -w0 * w1 / L3;
+    const double ez[3] = {0, 0, 1};
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        H[i][j] = prr * er[i] * er[j] + pzz * ez[i] * ez[j] + prz * (er[i] * ez[j] + ez[i] * er[j]);
+    add_Hrho(fr);
+  }
+}
+
+// World frame: y = R^T (x - c), grad = R g, hess = R H R^T.
+__device__ void sdf_world(const DevIndenter& ind, const double x[3], double& phi, double g[3],
+                          double H[3][3], bool wantH) {
+  const double dx[3] = {x[0] - ind.c[0], x[1] - ind.c[1], x[2] - ind.c[2]};
+  double y[3];
+  for (int i = 0; i < 3; ++i) y[i] = ind.R[0 * 3 + i] * dx[0] + ind.R[1 * 3 + i] * dx[1] + ind.R[2 * 3 + i] * dx[2];
+  double gl[3], Hl[3][3];
+  sdf_local(ind.shape, ind.prm, y, phi, gl, Hl, wantH);
+  for (int i = 0; i < 3; ++i) g[i] = ind.R[i * 3 + 0] * gl[0] + ind.R[i * 3 + 1] * gl[1] + ind.R[i * 3 + 2] * gl[2];
+  if (wantH) {
+    double T[3][3];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        T[i][j] = ind.R[i * 3 + 0] * Hl[0][j] + ind.R[i * 3 + 1] * Hl[1][j] + ind.R[i * 3 + 2] * Hl[2][j];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        H[i][j] = T[i][0] * ind.R[j * 3 + 0] + T[i][1] * ind.R[j * 3 + 1] + T[i][2] * ind.R[j * 3 + 2];
+  }
+}
+
+__device__ __forceinline__ bool convex_shape(int s) {
+  return s == TC_SPHERE || s == TC_CYLINDER || s == TC_BOX;
+}
+
+// IPC log barrier b(s) = -(s-1)^2 ln s on (0, 1) and its derivatives.
+__device__ __forceinline__ double bar0(double s) {
+  return s >= 1.0 ? 0.0 : (s <= 0.0 ? INFINITY : -(s - 1.0) * (s - 1.0) * log(s));
+}
+__device__ __forceinline__ double bar1(double s) {
+  return (s >= 1.0 || s <= 0.0) ? 0.0 : -2.0 * (s - 1.0) * log(s) - (s - 1.0) * (s - 1.0) / s;
+}
+__device__ __forceinline__ double bar2(double s) {
+  return (s >= 1.0 || s <= 0.0) ? 0.0
+         : -2.0 * log(s) - 4.0 * (s - 1.0) / s + (s - 1.0) * (s - 1.0) / (s * s);
+}
+
+__device__ __forceinline__ void load3(const double* p, int i, double v[3]) {
+  v[0] = p[3 * i]; v[1] = p[3 * i + 1]; v[2] = p[3 * i + 2];
+}
+
+// ------------------------------------------------------------ setup (a1)
+
+// Per tet: Dm^-1 and V_e = det(Dm) / 6 from rest positions (float64 math).
+template <typename R>
+__global__ void k_setup_tets(const Tile* tiles, int ntiles, const EnvDesc* envs) {
+  const int t = xcd_tile(ntiles);
+  if (t < 0) return;
+  const EnvDesc& E = envs[tiles[t].env];
+  const int e = tiles[t].tile * blockDim.x + threadIdx.x;
+  if (e >= E.T) return;
+  const int4 tv = reinterpret_cast<const int4*>(E.tets)[e];
+  double x0[3], x1[3], x2[3], x3[3];
+  load3(E.X, tv.x, x0); load3(E.X, tv.y, x1); load3(E.X, tv.z, x2); load3(E.X, tv.w, x3);
+  double D[3][3];
+  for (int i = 0; i < 3; ++i) { D[i][0] = x1[i] - x0[i]; D[i][1] = x2[i] - x0[i]; D[i][2] = x3[i] - x0[i]; }
+  const double det = det3(D);
+  double inv[3][3];
+  inv[0][0] = (D[1][1] * D[2][2] - D[1][2] * D[2][1]) / det;
+  inv[0][1] = (D[0][2] * D[2][1] - D[0][1] * D[2][2]) / det;
+  inv[0][2] = (D[0][1] * D[1][2] - D[0][2] * D[1][1]) / det;
+  inv[1][0] = (D[1][2] * D[2][0] - D[1][0] * D[2][2]) / det;
+  inv[1][1] = (D[0][0] * D[2][2] - D[0][2] * D[2][0]) / det;
+  inv[1][2] = (D[0][2] * D[1][0] - D[0][0] * D[1][2]) / det;
+  inv[2][0] = (D[1][0] * D[2][1] - D[1][1] * D[2][0]) / det;
+  inv[2][1] = (D[0][1] * D[2][0] - D[0][0] * D[2][1]) / det;
+  inv[2][2] = (D[0][0] * D[1][1] - D[0][1] * D[1][0]) / det;
+  R* Dm = (R*)E.Dminv + 9 * e;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) Dm[3 * i + j] = (R)inv[i][j];
+  ((R*)E.vol)[e] = (R)(det / 6.0);
+}
+
+// Per vertex: lumped mass m_a = sum_e rho_e V_e / 4 gathered over the
+// vertex's incident tets (its diagonal contribution list).
+template <typename R>
+__global__ void k_setup_mass(const Tile* tiles, int ntiles, const EnvDesc* envs, double* mass_out) {
+  const int t = xcd_tile(ntiles);
+  if (t < 0) return;
+  const EnvDesc& E = envs[tiles[t].env];
+  const int i = tiles[t].tile * blockDim.x + threadIdx.x;
+  if (i >= E.V) return;
+  double m = 0.0;
+  for (int c = E.cptr[i]; c < E.cptr[i + 1]; ++c) {
+    const int e = (int)(E.clist[c] >> 4);
+    const int4 tv = reinterpret_cast<const int4*>(E.tets)[e];
+    double x0[3], x1[3], x2[3], x3[3];
+    load3(E.X, tv.x, x0); load3(E.X, tv.y, x1); load3(E.X, tv.z, x2); load3(E.X, tv.w, x3);
+    double D[3][3];
+    for (int k = 0; k < 3; ++k) { D[k][0] = x1[k] - x0[k]; D[k][1] = x2[k] - x0[k]; D[k][2] = x3[k] - x0[k]; }
+    const int mid = E.mat ? E.mat[e] : 0;
+    m += E.rho[mid] * (det3(D) / 6.0) / 4.0;
+  }
+  mass_out[i] = m;
+}
+
+// Per contact vertex: rest barrier weight A_k = 1/3 sum of incident
+// contact-face triangle areas.
+__global__ void k_setup_cand_area(const Tile* tiles, int ntiles, const EnvDesc* envs, double* area_out) {
+  const int t = xcd_tile(ntiles);
+  if (t < 0) return;
+  const EnvDesc& E = envs[tiles[t].env];
+  const int k = tiles[t].tile * blockDim.x + threadIdx.x;
+  if (k >= E.C) return;
+  double A = 0.0;
+  for (int c = E.ctri_ptr[k]; c < E.ctri_ptr[k + 1]; ++c) {
+    const int j = E.ctri_idx[c];
+    double v0[3], v1[3], v2[3];
+    load3(E.X, E.tris[3 * j], v0); load3(E.X, E.tris[3 * j + 1], v1); load3(E.X, E.tris[3 * j + 2], v2);
+    const double e1[3] = {v1[0] - v0[0], v1[1] - v0[1], v1[2] - v0[2]};
+    const double e2[3] = {v2[0] - v0[0], v2[1] - v0[1], v2[2] - v0[2]};
+    const double cx = e1[1] * e2[2] - e1[2] * e2[1], cy = e1[2] * e2[0] - e1[0] * e2[2],
+                 cz = e1[0] * e2[1] - e1[1] * e2[0];
+    A += 0.5 * sqrt(cx * cx + cy * cy + cz * cz) / 3.0;
+  }
+  area_out[k] = A;
+}
+
+// ------------------------------------------------------ predict (a2)
+
+// xhat = x + h v + h^2 g_ext; Newton starts from x.
+__global__ void k_predict(const Tile* tiles, int ntiles, const EnvDesc* envs) {
+  const int t = xcd_tile(ntiles);
+  if (t < 0) return;
+  const EnvDesc& E = envs[tiles[t].env];
+  if (!initialising(E.st)) return;
+  const int i = tiles[t].tile * blockDim.x + threadIdx.x;
+  if (i >= E.V) return;
+  const double h = E.h;
+  for (int c = 0; c < 3; ++c) {
+    const double x = E.x[3 * i + c];
+    E.xhat[3 * i + c] = x + h * E.v[3 * i + c] + h * h * E.gravity[c];
+    E.xn[3 * i + c] = x;
+  }
+}
+
+// Feasible start: contact vertices closer than 0.1 d_hat to an indenter are
+// pushed out along grad(phi) (free components only), at most 8 rounds.
+__global__ void k_project(const Tile* tiles, int ntiles, const EnvDesc* envs) {
+  const int t = xcd_tile(ntiles);
+  if (t < 0) return;
+  const EnvDesc& E = envs[tiles[t].env];
+  EnvState* S = E.st;
+  const EnvPose* P = E.pose;
+  if (!initialising(S)) return;
+  const int k = tiles[t].tile * blockDim.x + threadIdx.x;
+  if (k >= E.C) return;
+  const int vi = E.cand[k];
+  const uint8_t fm = E.fixed[vi];
+  double x[3];
+  load3(E.xn, vi, x);
+  const double dsafe = 0.1 * E.dhat;
+  double H[3][3];
+  for (int round = 0; round < 8; ++round) {
+    bool moved = false;
+    for (int m = 0; m < P->n_ind; ++m) {
+      double phi, g[3];
+      sdf_world(P->ind[m], x, phi, g, H, false);
+      if (phi < dsafe * (1.0 - 1e-9)) {
+        moved = true;
+        for (int c = 0; c < 3; ++c)
+          if (!((fm >> c) & 1)) x[c] += (dsafe - phi) * g[c];
+      }
+    }
+    if (!moved) break;
+  }
+  double dmin = INFINITY;
+  for (int m = 0; m < P->n_ind; ++m) {
+    double phi, g[3];
+    sdf_world(P->ind[m], x, phi, g, H, false);
+    dmin = fmin(dmin, phi);
+  }
+  for (int c = 0; c < 3; ++c) E.xn[3 * vi + c] = x[c];
+  if (!(dmin > 0.0)) atomicOr(&S->infeasible, 1);
+}
+
+// ------------------------------------------------------ element (a3)
+
+// Per tet: F = Ds Dm^-1, P (Eq. 2 with shift alpha), gradient V_e P G_a^T and
+// the PSD-projected element Hessian from the analytic eigensystem of
+// d2Psi/dF2 in the SVD frame of F:
+//   twist/flip pairs (i,j; k the third index): mu +/- lam (J - alpha) s_k,
+//   modes (u_i v_j^T -/+ u_j v_i^T) / sqrt 2;
+//   scaling block: mu I + lam cof(S) cof(S)^T + lam (J - alpha) d2J/ds2,
+//   a 3x3 symmetric eigenproblem, modes U diag(w) V^T.
+// Negative eigenvalues are dropped; K_e = V_e sum lam+ c c^T with
+// c = Q G^T (Q the 3x3 mode, G the shape-function gradients).
+template <typename R>
+__global__ void __launch_bounds__(256) k_element(const Tile* tiles, int ntiles, const EnvDesc* envs) {
+  const int t = xcd_tile(ntiles);
+  if (t < 0) return;
+  const EnvDesc& E = envs[tiles[t].env];
+  if (!running(E.st)) return;
+  const int e = tiles[t].tile * blockDim.x + threadIdx.x;
+  if (e >= E.T) return;
+  const int4 tv = reinterpret_cast<const int4*>(E.tets)[e];
+  double x0[3], x1[3], x2[3], x3[3];
+  load3(E.xn, tv.x, x0); load3(E.xn, tv.y, x1); load3(E.xn, tv.z, x2); load3(E.xn, tv.w, x3);
+  R Ds[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    Ds[i][0] = (R)(x1[i] - x0[i]);
+    Ds[i][1] = (R)(x2[i] - x0[i]);
+    Ds[i][2] = (R)(x3[i] - x0[i]);
+  }
+  const R* Dmp = (const R*)E.Dminv + 9 * e;
+  R Dm[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) Dm[i][j] = Dmp[3 * i + j];
+  R F[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) F[i][j] = Ds[i][0] * Dm[0][j] + Ds[i][1] * Dm[1][j] + Ds[i][2] * Dm[2][j];
+  const int mid = E.mat ? E.mat[e] : 0;
+  const R mu = (R)E.mu[mid], lam = (R)E.lam[mid], alpha = (R)E.alpha[mid];
+  const R vol = ((const R*)E.vol)[e];
+
+  // cofactor (columns f1 x f2, f2 x f0, f0 x f1) and J
+  R cof[3][3];
+  cof[0][0] = F[1][1] * F[2][2] - F[2][1] * F[1][2];
+  cof[1][0] = F[2][1] * F[0][2] - F[0][1] * F[2][2];
+  cof[2][0] = F[0][1] * F[1][2] - F[1][1] * F[0][2];
+  cof[0][1] = F[1][2] * F[2][0] - F[2][2] * F[1][0];
+  cof[1][1] = F[2][2] * F[0][0] - F[0][2] * F[2][0];
+  cof[2][1] = F[0][2] * F[1][0] - F[1][2] * F[0][0];
+  cof[0][2] = F[1][0] * F[2][1] - F[2][0] * F[1][1];
+  cof[1][2] = F[2][0] * F[0][1] - F[0][0] * F[2][1];
+  cof[2][2] = F[0][0] * F[1][1] - F[1][0] * F[0][1];
+  const R J = F[0][0] * cof[0][0] + F[1][0] * cof[1][0] + F[2][0] * cof[2][0];
+  const R sJ = lam * (J - alpha);
+
+  R rec[KE_STRIDE];
+#pragma unroll
+  for (int k = 0; k < KE_STRIDE; ++k) rec[k] = R(0);
+
+  // gradient: vertex a >= 1 gets V P Dm^-T column a-1; vertex 0 minus the sum
+  {
+    R P[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) P[i][j] = mu * F[i][j] + sJ * cof[i][j];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      R s0 = 0;
+#pragma unroll
+      for (int a = 1; a < 4; ++a) {
+        const R ga = vol * (P[i][0] * Dm[a - 1][0] + P[i][1] * Dm[a - 1][1] + P[i][2] * Dm[a - 1][2]);
+        rec[KE_GRAD + 3 * a + i] = ga;
+        s0 += ga;
+      }
+      rec[KE_GRAD + i] = -s0;
+    }
+  }
+
+  R U[3][3], sv[3], V[3][3];
+  svd3(F, U, sv, V);
+  // h[l][a] = v_l . G_a
+  R hh[3][4];
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    R s0 = 0;
+#pragma unroll
+    for (int a = 1; a < 4; ++a) {
+      hh[l][a] = V[0][l] * Dm[a - 1][0] + V[1][l] * Dm[a - 1][1] + V[2][l] * Dm[a - 1][2];
+      s0 += hh[l][a];
+    }
+    hh[l][0] = -s0;
+  }
+  const R isq2 = R(0.70710678118654752440);
+  // twist / flip modes
+#pragma unroll
+  for (int pr = 0; pr < 3; ++pr) {
+    const int i = pr == 2 ? 1 : 0;
+    const int j = pr == 0 ? 1 : 2;
+    const int k = 3 - i - j;
+    const R ltw = mu + sJ * sv[k];
+    const R lfl = mu - sJ * sv[k];
+    R c[4][3];
+    if (ltw > R(0)) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int m = 0; m < 3; ++m) c[a][m] = isq2 * (U[m][i] * hh[j][a] - U[m][j] * hh[i][a]);
+      rank1_update(rec, c, vol * ltw);
+    }
+    if (lfl > R(0)) {
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int m = 0; m < 3; ++m) c[a][m] = isq2 * (U[m][i] * hh[j][a] + U[m][j] * hh[i][a]);
+      rank1_update(rec, c, vol * lfl);
+    }
+  }
+  // scaling block
+  {
+    const R gh[3] = {sv[1] * sv[2], sv[0] * sv[2], sv[0] * sv[1]};
+    R As[3][3];
+#pragma unroll
+    for (int l = 0; l < 3; ++l)
+#pragma unroll
+      for (int m = 0; m < 3; ++m) As[l][m] = lam * gh[l] * gh[m] + (l == m ? mu : R(0));
+    As[0][1] += sJ * sv[2]; As[1][0] += sJ * sv[2];
+    As[0][2] += sJ * sv[1]; As[2][0] += sJ * sv[1];
+    As[1][2] += sJ * sv[0]; As[2][1] += sJ * sv[0];
+    R Qs[3][3], ws[3];
+    sym_eig3(As, Qs, ws);
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      if (ws[m] > R(0)) {
+        R c[4][3];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int r = 0; r < 3; ++r)
+            c[a][r] = Qs[0][m] * hh[0][a] * U[r][0] + Qs[1][m] * hh[1][a] * U[r][1] +
+                      Qs[2][m] * hh[2][a] * U[r][2];
+        rank1_update(rec, c, vol * ws[m]);
+      }
+    }
+  }
+  R* out = (R*)E.Ke + (size_t)KE_STRIDE * e;
+  if constexpr (sizeof(R) == 4) {
+    float4* o4 = reinterpret_cast<float4*>(out);
+#pragma unroll
+    for (int k = 0; k < KE_STRIDE / 4; ++k)
+      o4[k] = make_float4(rec[4 * k], rec[4 * k + 1], rec[4 * k + 2], rec[4 * k + 3]);
+  } else {
+    double2* o2 = reinterpret_cast<double2*>(out);
+#pragma unroll
+    for (int k = 0; k < KE_STRIDE / 2; ++k) o2[k] = make_double2(rec[2 * k], rec[2 * k + 1]);
+  }
+}
+
+// ------------------------------------------------------ barrier (a4)
+
+__device__ void project_psd3(double H[3][3]) {
+  double A[3][3], Q[3][3], w[3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) A[i][j] = 0.5 * (H[i][j] + H[j][i]);
+  sym_eig3(A, Q, w);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s = 0;
+      for (int m = 0; m < 3; ++m) s += Q[i][m] * fmax(w[m], 0.0) * Q[j][m];
+      H[i][j] = s;
+    }
+}
+
+// Per contact vertex: E_b gradient kappa A b'(s) grad(phi) and PSD-projected
+// Hessian kappa A [b''(s)/d_hat grad grad^T + b'(s) hess(phi)], summed over
+// indenters (float64).
+__global__ void k_barrier(const Tile* tiles, int ntiles, const EnvDesc* envs) {
+  const int t = xcd_tile(ntiles);
+  if (t < 0) return;
+  const EnvDesc& E = envs[tiles[t].env];
+  const EnvPose* P = E.pose;
+  if (!running(E.st)) return;
+  const int k = tiles[t].tile * blockDim.x + threadIdx.x;
+  if (k >= E.C) return;
+  const int vi = E.cand[k];
+  double x[3];
+  load3(E.xn, vi, x);
+  const double kA = E.kappa * E.cand_area[k];
+  double g[3] = {0, 0, 0}, H[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  for (int m = 0; m < P->n_ind; ++m) {
+    double phi, n[3], Hp[3][3];
+    sdf_world(P->ind[m], x, phi, n, Hp, true);
+    if (phi < E.dhat) {
+      const double s = phi / E.dhat;
+      const double b1 = bar1(s), b2 = bar2(s);
+      for (int i = 0; i < 3; ++i) {
+        g[i] += kA * b1 * n[i];
+        for (int j = 0; j < 3; ++j) H[i][j] += kA * (b2 / E.dhat * n[i] * n[j] + b1 * Hp[i][j]);
+      }
+    }
+  }
+  project_psd3(H);
+  for (int i = 0; i < 3; ++i) E.gb[3 * k + i] = g[i];
+  double* hb = E.Hb + 6 * k;
+  hb[0] = H[0][0]; hb[1] = H[0][1]; hb[2] = H[0][2]; hb[3] = H[1][1]; hb[4] = H[1][2]; hb[5] = H[2][2];
+}
+
+// ------------------------------------------------------ assembly
+
+template <typename R>
+__device__ __forceinline__ void load_block(const R* rec, int a, int b, R blk[3][3]) {
+  if (a == b) {
+    const R* p = rec + ke_block_offset(a, a);
+    blk[0][0] = p[0]; blk[0][1] = p[1]; blk[0][2] = p[2];
+    blk[1][0] = p[1]; blk[1][1] = p[3]; blk[1][2] = p[4];
+    blk[2][0] = p[2]; blk[2][1] = p[4]; blk[2][2] = p[5];
+  } else if (a < b) {
+    const R* p = rec + ke_block_offset(a, b);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) blk[i][k] = p[3 * i + k];
+  } else {
+    const R* p = rec + ke_block_offset(b, a);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) blk[i][k] = p[3 * k + i];
+  }
+}
+
+// Diagonal block rows (slot 0): sum of element blocks, inertia, barrier,
+// Dirichlet masking, gradient, preconditioner, and CG initialisation
+// (d = 0, r = -g, z = P^-1 r, partial r.z and g.g).
+template <typename R>
+__global__ void k_asm_diag(const Tile* tiles, int ntiles, const EnvDesc* envs) {
+  __shared__ double sh[16];
+  const int t = xcd_tile(ntiles);
+  if (t < 0) return;
+  const Tile tl = tiles[t];
+  const EnvDesc& E = envs[tl.env];
+  if (!running(E.st)) return;
+  const int i = tl.tile * blockDim.x + threadIdx.x;
+  const bool valid = i < E.V;
+  double rz = 0.0, gg = 0.0;
+  if (valid) {
+    double D[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    double gs[3] = {0, 0, 0};
+    const R* Ke = (const R*)E.Ke;
+    for (int c = E.cptr[i]; c < E.cptr[i + 1]; ++c) {
+      const uint32_t code = E.clist[c];
+      const int e = (int)(code >> 4), a = (int)((code >> 2) & 3);
+      const R* rec = Ke + (size_t)KE_STRIDE * e;
+      R blk[3][3];
+      load_block(rec, a, a, blk);
+      for (int r = 0; r < 3; ++r) {
+        for (int q = 0; q < 3; ++q) D[r][q] += (double)blk[r][q];
+        gs[r] += (double)rec[KE_GRAD + 3 * a + r];
+      }
+    }
+    const double h2 = E.h * E.h;
+    double xi[3], xh[3];
+    load3(E.xn, i, xi);
+    load3(E.xhat, i, xh);
+    const double m = E.quasi_static ? 0.0 : E.mass[i];
+    for (int r = 0; r < 3; ++r) {
+      for (int q = 0; q < 3; ++q) D[r][q] *= h2;
+      D[r][r] += m;
+      gs[r] = h2 * gs[r] + m * (xi[r] - xh[r]);
+    }
+    const int k = E.cand_of_vert[i];
+    if (k >= 0) {
+      const double* hb = E.Hb + 6 * k;
+      const double Hk[3][3] = {{hb[0], hb[1], hb[2]}, {hb[1], hb[3], hb[4]}, {hb[2], hb[4], hb[5]}};
+      for (int r = 0; r < 3; ++r) {
+        for (int q = 0; q < 3; ++q) D[r][q] += h2 * Hk[r][q];
+        gs[r] += h2 * E.gb[3 * k + r];
+      }
+    }
+    const uint8_t fm = E.fixed[i];
+    for (int r = 0; r < 3; ++r)
+      if ((fm >> r) & 1) {
+        for (int q = 0; q < 3; ++q) { D[r][q] = 0; D[q][r] = 0; }
+        D[r][r] = 1.0;
+        gs[r] = 0.0;
+      }
+    R* A = (R*)E.A;
+    const int V = E.V;
+    for (int r = 0; r < 3; ++r)
+      for (int q = 0; q < 3; ++q) A[(size_t)(3 * r + q) * V + i] = (R)D[r][q];
+    // preconditioner: inverse of the 3x3 diagonal block, or of its diagonal
+    double P[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    if (E.precond == TC_PRECOND_BLOCK_JACOBI) {
+      const double c00 = D[1][1] * D[2][2] - D[1][2] * D[2][1];
+      const double c01 = D[1][2] * D[2][0] - D[1][0] * D[2][2];
+      const double c02 = D[1][0] * D[2][1] - D[1][1] * D[2][0];
+      const double det = D[0][0] * c00 + D[0][1] * c01 + D[0][2] * c02;
+      const double id = 1.0 / det;
+      P[0][0] = c00 * id;
+      P[0][1] = (D[0][2] * D[2][1] - D[0][1] * D[2][2]) * id;
+      P[0][2] = (D[0][1] * D[1][2] - D[0][2] * D[1][1]) * id;
+      P[1][1] = (D[0][0] * D[2][2] - D[0][2] * D[2][0]) * id;
+      P[1][2] = (D[0][2] * D[1][0] - D[0][0] * D[1][2]) * id;
+      P[2][2] = (D[0][0] * D[1][1] - D[0][1] * D[1][0]) * id;
+      P[1][0] = P[0][1]; P[2][0] = P[0][2]; P[2][1] = P[1][2];
+    } else {
+      for (int r = 0; r < 3; ++r) P[r][r] = 1.0 / D[r][r];
+    }
+    R* Pi = (R*)E.Pinv + 6 * i;
+    Pi[0] = (R)P[0][0]; Pi[1] = (R)P[0][1]; Pi[2] = (R)P[0][2];
+    Pi[3] = (R)P[1][1]; Pi[4] = (R)P[1][2]; Pi[5] = (R)P[2][2];
+    R Pr[3][3] = {{Pi[0], Pi[1], Pi[2]}, {Pi[1], Pi[3], Pi[4]}, {Pi[2], Pi[4], Pi[5]}};
+    R* d = (R*)E.d;
+    R* z = (R*)E.z;
+    R* p1 = (R*)E.p1;
+    double rr[3];
+    for (int r = 0; r < 3; ++r) {
+      E.g[3 * i + r] = gs[r];
+      rr[r] = -gs[r];
+      E.r[3 * i + r] = rr[r];
+      d[3 * i + r] = R(0);
+      p1[3 * i + r] = R(0);
+      gg += gs[r] * gs[r];
+    }
+    for (int r = 0; r < 3; ++r) {
+      const R zr = Pr[r][0] * (R)rr[0] + Pr[r][1] * (R)rr[1] + Pr[r][2] * (R)rr[2];
+      z[3 * i + r] = zr;
+      rz += rr[r] * (double)zr;
+    }
+  }
+  rz = block_reduce(rz, OpSum(), sh);
+  gg = block_reduce(gg, OpSum(), sh);
+  if (threadIdx.x == 0) {
+    E.part_rz[tl.tile] = rz;
+    E.part_g2[tl.tile] = gg;
+  }
+}
+
+// Off-diagonal blocks (slots >= 1): sum of element blocks (a, b) of every tet
+// sharing the edge, times h^2, Dirichlet rows and columns zeroed.
+template <typename R>
+__global__ void k_asm_off(const Tile* tiles, int ntiles, const EnvDesc* envs) {
+  const int t = xcd_tile(ntiles);
+  if (t < 0) return;
+  const EnvDesc& E = envs[tiles[t].env];
+  if (!running(E.st)) return;
+  const int V = E.V;
+  const int item = V + tiles[t].tile * blockDim.x + threadIdx.x;   // skip slot 0
+  if (item >= E.W * V) return;
+  const int s = item / V, i = item - s * V;
+  const int j = E.col[item];
+  R acc[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  if (j >= 0) {
+    const R* Ke = (const R*)E.Ke;
+    for (int c = E.cptr[item]; c < E.cptr[item + 1]; ++c) {
+      const uint32_t code = E.clist[c];
+      const int e = (int)(code >> 4), a = (int)((code >> 2) & 3), b = (int)(code & 3);
+      R blk[3][3];
+      load_block(Ke + (size_t)KE_STRIDE * e, a, b, blk);
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) acc[r][q] += blk[r][q];
+    }
+    const R h2 = (R)(E.h * E.h);
+    const uint8_t fi = E.fixed[i], fj = E.fixed[j];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+        acc[r][q] = (((fi >> r) & 1) || ((fj >> q) & 1)) ? R(0) : acc[r][q] * h2;
+  }
+  R* A = (R*)E.A + (size_t)s * 9 * V;
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int q = 0; q < 3; ++q) A[(size_t)(3 * r + q) * V + i] = acc[r][q];
+}
+
+// ------------------------------------------------------ CG (a5)
+
+// Per Newton iteration reset of the CG / line-search flags (one block/pad).
+__global__ void k_env_newton_begin(const EnvDesc* envs, int n) {
+  if (blockIdx.x >= n || threadIdx.x != 0) return;
+  EnvState* S = envs[blockIdx.x].st;
+  if (!running(S)) return;
+  S->cg_tol2 = envs[blockIdx.x].cg_tol2;
+  S->cg_done = 0;
+  S->cg_iters = 0;
+  S->breakdown = 0;
+  S->it[0] = -1;
+  S->it[1] = -1;
+  S->rzp[0] = S->rzp[1] = 0.0;
+  S->dir_conv = 0;
+  S->apply = 0;
+  S->ls_done = 0;
+  S->ls_halv = 0;
+}
+
+// q = A p_new with p_new = z + beta p_old formed on the fly for every gathered
+// neighbour (the row owner stores it).  beta from this pad's r.z partials;
+// the pad's CG stops here when r.z <= tol^2 r0.z0 or at max_cg.
+template <typename R>
+__global__ void __launch_bounds__(1024) k_cg_spmv(const Tile* tiles, int ntiles, const EnvDesc* envs, int parity) {
+  __shared__ double sh[16];
+  const int t = xcd_tile(ntiles);
+  if (t < 0) return;
+  const Tile tl = tiles[t];
+  const EnvDesc& E = envs[tl.env];
+  EnvState* S = E.st;
+  if (!running(S) || S->cg_done) return;
+  const double rz = reduce_partials(E.part_rz, E.n_vt, OpSum(), 0.0, sh);
+  const int it = S->it[parity ^ 1] + 1;
+  const double rz0 = it == 0 ? rz : S->rz0;
+  const bool done = it >= E.max_cg || !(rz > S->cg_tol2 * rz0) || S->breakdown;
+  if (tl.tile == 0 && threadIdx.x == 0) {
+    if (done) {
+      S->cg_done = 1;
+      S->cg_iters = it;
+    } else {
+      S->it[parity] = it;
+      S->rzp[parity] = rz;
+      if (it == 0) S->rz0 = rz;
+    }
+  }
+  if (done) return;
+  const R beta = it == 0 ? R(0) : (R)(rz / S->rzp[parity ^ 1]);
+  const int V = E.V;
+  const int i = tl.tile * blockDim.x + threadIdx.x;
+  const R* z = (const R*)E.z;
+  const R* pold = (const R*)(parity ? E.p0 : E.p1);
+  R* pnew = (R*)(parity ? E.p1 : E.p0);
+  double pq = 0.0;
+  if (i < V) {
+    const R* A = (const R*)E.A;
+    R y0 = 0, y1 = 0, y2 = 0;
+    R pi0 = 0, pi1 = 0, pi2 = 0;
+    for (int s = 0; s < E.W; ++s) {
+      const int j = E.col[(size_t)s * V + i];
+      if (j < 0) break;
+      const R pj0 = z[3 * j] + beta * pold[3 * j];
+      const R pj1 = z[3 * j + 1] + beta * pold[3 * j + 1];
+      const R pj2 = z[3 * j + 2] + beta * pold[3 * j + 2];
+      if (s == 0) { pi0 = pj0; pi1 = pj1; pi2 = pj2; }
+      const R* As = A + (size_t)s * 9 * V + i;
+      y0 += As[0 * (size_t)V] * pj0 + As[1 * (size_t)V] * pj1 + As[2 * (size_t)V] * pj2;
+      y1 += As[3 * (size_t)V] * pj0 + As[4 * (size_t)V] * pj1 + As[5 * (size_t)V] * pj2;
+      y2 += As[6 * (size_t)V] * pj0 + As[7 * (size_t)V] * pj1 + As[8 * (size_t)V] * pj2;
+    }
+    pnew[3 * i] = pi0; pnew[3 * i + 1] = pi1; pnew[3 * i + 2] = pi2;
+    R* q = (R*)E.q;
+    q[3 * i] = y0; q[3 * i + 1] = y1; q[3 * i + 2] = y2;
+    pq = (double)pi0 * y0 + (double)pi1 * y1 + (double)pi2 * y2;
+  }
+  pq = block_reduce(pq, OpSum(), sh);
+  if (threadIdx.x == 0) E.part_pq[tl.tile] = pq;
+}
+
+// alpha = r.z / p.Ap; d += alpha p; r -= alpha Ap (float64); z = P^-1 r;
+// partial r.z for the next iteration.
+template <typename R>
+__global__ void __launch_bounds__(1024) k_cg_update(const Tile* tiles, int ntiles, const EnvDesc* envs, int parity) {
+  __shared__ double sh[16];
+  const int t = xcd_tile(ntiles);
+  if (t < 0) return;
+  const Tile tl = tiles[t];
+  const EnvDesc& E = envs[tl.env];
+  EnvState* S = E.st;
+  if (!running(S) || S->cg_done) return;
+  const double pq = reduce_partials(E.part_pq, E.n_vt, OpSum(), 0.0, sh);
+  const double rz = S->rzp[parity];
+  double alpha = rz / pq;
+  if (!(pq > 0.0) || !isfinite(alpha)) {
+    alpha = 0.0;
+    if (tl.tile == 0 && threadIdx.x == 0) S->breakdown = 1;
+  }
+  const int i = tl.tile * blockDim.x + threadIdx.x;
+  double rzn = 0.0;
+  if (i < E.V) {
+    const R* p = (const R*)(parity ? E.p1 : E.p0);
+    const R* q = (const R*)E.q;
+    R* d = (R*)E.d;
+    R* z = (R*)E.z;
+    const R* Pi = (const R*)E.Pinv + 6 * i;
+    const R a = (R)alpha;
+    double rr[3];
+    for (int c = 0; c < 3; ++c) {
+      d[3 * i + c] += a * p[3 * i + c];
+      rr[c] = E.r[3 * i + c] - alpha * (double)q[3 * i + c];
+      E.r[3 * i + c] = rr[c];
+    }
+    const R r0 = (R)rr[0], r1 = (R)rr[1], r2 = (R)rr[2];
+    const R z0 = Pi[0] * r0 + Pi[1] * r1 + Pi[2] * r2;
+    const R z1 = Pi[1] * r0 + Pi[3] * r1 + Pi[4] * r2;
+    const R z2 = Pi[2] * r0 + Pi[4] * r1 + Pi[5] * r2;
+    z[3 * i] = z0; z[3 * i + 1] = z1; z[3 * i + 2] = z2;
+    rzn = rr[0] * (double)z0 + rr[1] * (double)z1 + rr[2] * (double)z2;
+  }
+  rzn = block_reduce(rzn, OpSum(), sh);
+  if (threadIdx.x == 0) E.part_rz[tl.tile] = rzn;
+}
+
+// ------------------------------------------------------ Newton direction, filter (a6)
+
+// partials: |d|_inf and g . d
+template <typename R>
+__global__ void k_newton_dir(const Tile* tiles, int ntiles, const EnvDesc* envs) {
+  __shared__ double sh[16];
+  const int t = xcd_tile(ntiles);
+  if (t < 0) return;
+  const Tile tl = tiles[t];
+  const EnvDesc& E = envs[tl.env];
+  if (!running(E.st)) return;
+  const int i = tl.tile * blockDim.x + threadIdx.x;
+  double dm = 0.0, gd = 0.0;
+  if (i < E.V) {
+    const R* d = (const R*)E.d;
+    for (int c = 0; c < 3; ++c) {
+      const double dc = (double)d[3 * i + c];
+      dm = fmax(dm, fabs(dc));
+      gd += E.g[3 * i + c] * dc;
+    }
+  }
+  dm = block_reduce(dm, OpMax(), sh);
+  gd = block_reduce(gd, OpSum(), sh);
+  if (threadIdx.x == 0) {
+    E.part_dir[2 * tl.tile] = dm;
+    E.part_dir[2 * tl.tile + 1] = gd;
+  }
+}
+
+// Largest safe step per contact vertex.  Convex indenters: phi(x + a p) >=
+// phi(x) + a grad(phi).p, so only approach (grad.p < 0) limits the step,
+// a <= 0.9 phi / (-grad.p).  Other shapes use the 1-Lipschitz bound
+// a <= 0.9 phi / |p|.  Either keeps phi > 0.1 phi(x).
+template <typename R>
+__global__ void k_filter(const Tile* tiles, int ntiles, const EnvDesc* envs) {
+  __shared__ double sh[16];
+  const int t = xcd_tile(ntiles);
+  if (t < 0) return;
+  const Tile tl = tiles[t];
+  const EnvDesc& E = envs[tl.env];
+  const EnvPose* P = E.pose;
+  if (!running(E.st)) return;
+  const int k = tl.tile * blockDim.x + threadIdx.x;
+  double amax = INFINITY;
+  if (k < E.C) {
+    const int vi = E.cand[k];
+    double x[3], p[3], H[3][3];
+    load3(E.xn, vi, x);
+    const R* d = (const R*)E.d;
+    for (int c = 0; c < 3; ++c) p[c] = (double)d[3 * vi + c];
+    const double pn = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+    if (pn > 0) {
+      for (int m = 0; m < P->n_ind; ++m) {
+        double phi, g[3];
+        sdf_world(P->ind[m], x, phi, g, H, false);
+        double a = INFINITY;
+        if (convex_shape(P->ind[m].shape)) {
+          const double gp = g[0] * p[0] + g[1] * p[1] + g[2] * p[2];
+          if (gp < 0) a = 0.9 * phi / (-gp);
+        } else {
+          a = 0.9 * phi / pn;
+        }
+        amax = fmin(amax, a);
+      }
+    }
+  }
+  amax = block_reduce(amax, OpMin(), sh);
+  if (threadIdx.x == 0) E.part_filt[tl.tile] = amax;
+}
+
+// One block per pad: reduce |d|_inf, g.d, the step bound; decide
+// convergence (|d|_inf <= tol * bbox diagonal -> take the filtered step and
+// stop) or start the line search at min(1, bound).
+__global__ void k_env_dir(const EnvDesc* envs, int n) {
+  __shared__ double sh[16];
+  if (blockIdx.x >= n) return;
+  const EnvDesc& E = envs[blockIdx.x];
+  EnvState* S = E.st;
+  if (!running(S)) return;
+  double dm = -INFINITY, gd = 0.0, am = INFINITY;
+  for (int k = threadIdx.x; k < E.n_vt; k += blockDim.x) {
+    dm = fmax(dm, E.part_dir[2 * k]);
+    gd += E.part_dir[2 * k + 1];
+  }
+  for (int k = threadIdx.x; k < E.n_ct; k += blockDim.x) am = fmin(am, E.part_filt[k]);
+  dm = block_reduce(dm, OpMax(), sh);
+  gd = block_reduce(gd, OpSum(), sh);
+  am = block_reduce(am, OpMin(), sh);
+  if (threadIdx.x == 0) {
+    S->final_step_inf = dm;
+    S->gTd = gd;
+    S->alpha_max = am;
+    S->ls_alpha = fmin(1.0, am);
+    S->dir_conv = dm <= E.tol_abs;
+    S->ls_done = S->dir_conv;
+    S->apply = S->dir_conv;
+    S->cg_total += S->cg_iters;
+  }
+}
+
+// ------------------------------------------------------ energy / line search (a6)
+
+// Incremental potential at y = x + alpha d (float64 throughout): tet tiles
+// give sum V_e Psi(F_e), vertex tiles the inertia term, candidate tiles the
+// barrier (+inf on contact).  mode 0: alpha = 0 for every running pad;
+// mode 1: trial step of pads still searching.
+template <typename R>
+__global__ void k_energy(const Tile* tiles, int ntiles, const EnvDesc* envs, int mode) {
+  __shared__ double sh[16];
+  const int t = xcd_tile(ntiles);
+  if (t < 0) return;
+  const Tile tl = tiles[t];
+  const EnvDesc& E = envs[tl.env];
+  const EnvState* S = E.st;
+  const EnvPose* P = E.pose;
+  if (mode == 0 ? !initialising(S) : (!running(S) || S->ls_done)) return;
+  const double al = mode == 0 ? 0.0 : S->ls_alpha;
+  const R* d = (const R*)E.d;
+  double acc = 0.0;
+  int tt = tl.tile;
+  if (tt < E.n_te) {
+    const int e = tt * blockDim.x + threadIdx.x;
+    if (e < E.T) {
+      const int4 tv = reinterpret_cast<const int4*>(E.tets)[e];
+      const int vv[4] = {tv.x, tv.y, tv.z, tv.w};
+      double y[4][3];
+      for (int a = 0; a < 4; ++a)
+        for (int c = 0; c < 3; ++c) y[a][c] = E.xn[3 * vv[a] + c] + al * (double)d[3 * vv[a] + c];
+      const R* Dmp = (const R*)E.Dminv + 9 * e;
+      double F[3][3];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j)
+          F[i][j] = (y[1][i] - y[0][i]) * (double)Dmp[j] + (y[2][i] - y[0][i]) * (double)Dmp[3 + j] +
+                    (y[3][i] - y[0][i]) * (double)Dmp[6 + j];
+      const int mid = E.mat ? E.mat[e] : 0;
+      const double J = det3(F);
+      double ff = 0;
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) ff += F[i][j] * F[i][j];
+      const double psi = 0.5 * E.mu[mid] * (ff - 3.0) + 0.5 * E.lam[mid] * (J - E.alpha[mid]) * (J - E.alpha[mid]);
+      acc = (double)((const R*)E.vol)[e] * psi;
+    }
+  } else if ((tt -= E.n_te) < E.n_vt) {
+    const int i = tt * blockDim.x + threadIdx.x;
+    if (i < E.V && !E.quasi_static) {
+      double s = 0;
+      for (int c = 0; c < 3; ++c) {
+        const double dy = E.xn[3 * i + c] + al * (double)d[3 * i + c] - E.xhat[3 * i + c];
+        s += dy * dy;
+      }
+      acc = 0.5 * E.mass[i] * s;
+    }
+  } else {
+    tt -= E.n_vt;
+    const int k = tt * blockDim.x + threadIdx.x;
+    if (k < E.C) {
+      const int vi = E.cand[k];
+      double y[3], g[3], H[3][3];
+      for (int c = 0; c < 3; ++c) y[c] = E.xn[3 * vi + c] + al * (double)d[3 * vi + c];
+      for (int m = 0; m < P->n_ind; ++m) {
+        double phi;
+        sdf_world(P->ind[m], y, phi, g, H, false);
+        if (phi < E.dhat) acc += E.kappa * E.cand_area[k] * E.dhat * bar0(phi / E.dhat);
+      }
+    }
+  }
+  acc = block_reduce(acc, OpSum(), sh);
+  if (threadIdx.x == 0) E.part_e[tl.tile] = acc;
+}
+
+// One block per pad: E = inertia + h^2 (elastic + barrier).  mode 0 stores
+// E(x).  mode 1: Armijo test E(x + a d) <= E(x) + 1e-4 a g.d + noise |E(x)|,
+// accept or halve a.
+__global__ void k_env_ls(const EnvDesc* envs, int n, int mode) {
+  __shared__ double sh[16];
+  if (blockIdx.x >= n) return;
+  const EnvDesc& E = envs[blockIdx.x];
+  EnvState* S = E.st;
+  if (mode == 0 ? !initialising(S) : (!running(S) || S->ls_done)) return;
+  double el = 0, in = 0, ba = 0;
+  for (int k = threadIdx.x; k < E.n_te; k += blockDim.x) el += E.part_e[k];
+  for (int k = threadIdx.x; k < E.n_vt; k += blockDim.x) in += E.part_e[E.n_te + k];
+  for (int k = threadIdx.x; k < E.n_ct; k += blockDim.x) ba += E.part_e[E.n_te + E.n_vt + k];
+  el = block_reduce(el, OpSum(), sh);
+  in = block_reduce(in, OpSum(), sh);
+  ba = block_reduce(ba, OpSum(), sh);
+  if (threadIdx.x != 0) return;
+  const double Etot = in + E.h * E.h * (el + ba);
+  if (mode == 0) {
+    S->E_cur = Etot;
+    if (S->infeasible) {
+      S->status = TC_E_INFEASIBLE;
+      S->phase = PH_FINISH;
+    } else {
+      S->phase = PH_RUN;
+    }
+    return;
+  }
+  const double a = S->ls_alpha;
+  if (Etot <= S->E_cur + 1e-4 * a * S->gTd + E.noise * fabs(S->E_cur)) {
+    S->ls_done = 1;
+    S->apply = 1;
+    S->E_next = Etot;
+  } else {
+    S->ls_alpha = 0.5 * a;
+    S->ls_halv += 1;
+    if (S->ls_halv > E.max_halvings) {
+      S->status = TC_E_LINESEARCH;
+      S->phase = PH_FINISH;
+    }
+  }
+}
+
+// x += alpha d for pads whose step was accepted; tile 0 advances the pad's
+// Newton counters.
+template <typename R>
+__global__ void k_update(const Tile* tiles, int ntiles, const EnvDesc* envs) {
+  const int t = xcd_tile(ntiles);
+  if (t < 0) return;
+  const Tile tl = tiles[t];
+  const EnvDesc& E = envs[tl.env];
+  EnvState* S = E.st;
+  if (!running(S)) return;
+  const int i = tl.tile * blockDim.x + threadIdx.x;
+  if (S->apply && i < E.V) {
+    const R* d = (const R*)E.d;
+    const double a = S->ls_alpha;
+    for (int c = 0; c < 3; ++c) E.xn[3 * i + c] += a * (double)d[3 * i + c];
+  }
+  if (tl.tile == 0 && threadIdx.x == 0) {
+    S->newton_iters += 1;
+    S->ls_total += S->ls_halv;
+    if (!S->dir_conv) S->E_cur = S->E_next;
+    if (S->dir_conv) {
+      S->newton_done = 1;
+      S->phase = PH_FINISH;
+    } else if (S->newton_iters >= E.max_newton) {
+      S->status = TC_E_NOT_CONVERGED;
+      S->phase = PH_FINISH;
+    }
+  }
+}
+
+// ------------------------------------------------------ extraction (a8-a10)
+
+__device__ __forceinline__ bool extract_ok(const EnvState* S) {
+  return S->phase == PH_FINISH && S->status == TC_OK;
+}
+
+// Eq. 4 per tet: sigma = (mu / J) F F^T + lam (J - alpha) I, Voigt order
+// (xx, yy, zz, yz, xz, xy).
+template <typename R>
+__global__ void k_sigma(const Tile* tiles, int ntiles, const EnvDesc* envs) {
+  const int t = xcd_tile(ntiles);
+  if (t < 0) return;
+  const EnvDesc& E = envs[tiles[t].env];
+  const EnvState* S = E.st;
+  if (!extract_ok(S)) return;
+  const int e = tiles[t].tile * blockDim.x + threadIdx.x;
+  if (e >= E.T) return;
+  const double* x = S->mode == 1 ? E.x : E.xn;
+  const int4 tv = reinterpret_cast<const int4*>(E.tets)[e];
+  double x0[3], x1[3], x2[3], x3[3];
+  load3(x, tv.x, x0); load3(x, tv.y, x1); load3(x, tv.z, x2); load3(x, tv.w, x3);
+  const R* Dmp = (const R*)E.Dminv + 9 * e;
+  R F[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const R a = (R)(x1[i] - x0[i]), b = (R)(x2[i] - x0[i]), c = (R)(x3[i] - x0[i]);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) F[i][j] = a * Dmp[j] + b * Dmp[3 + j] + c * Dmp[6 + j];
+  }
+  const int mid = E.mat ? E.mat[e] : 0;
+  const R mu = (R)E.mu[mid], lam = (R)E.lam[mid], alpha = (R)E.alpha[mid];
+  const R J = det3(F);
+  const R muJ = mu / J, vol = lam * (J - alpha);
+  R b[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) b[i][j] = F[i][0] * F[j][0] + F[i][1] * F[j][1] + F[i][2] * F[j][2];
+  R* s = (R*)E.sigma + 6 * e;
+  s[0] = muJ * b[0][0] + vol;
+  s[1] = muJ * b[1][1] + vol;
+  s[2] = muJ * b[2][2] + vol;
+  s[3] = muJ * b[1][2];
+  s[4] = muJ * b[0][2];
+  s[5] = muJ * b[0][1];
+}
+
+// Alg. 1 per surface triangle (current positions): n = e1 x e2 / |e1 x e2|,
+// t = sigma_parent n, p_n = t . n, t_tau = t - p_n n; partial sum of t * area
+// over contact-face triangles.
+template <typename R>
+__global__ void k_traction(const Tile* tiles, int ntiles, const EnvDesc* envs) {
+  __shared__ double sh[16];
+  const int t = xcd_tile(ntiles);
+  if (t < 0) return;
+  const Tile tl = tiles[t];
+  const EnvDesc& E = envs[tl.env];
+  const EnvState* S = E.st;
+  if (!extract_ok(S)) return;
+  const double* x = S->mode == 1 ? E.x : E.xn;
+  const int j = tl.tile * blockDim.x + threadIdx.x;
+  double ts[3] = {0, 0, 0};
+  if (j < E.S) {
+    double v0[3], v1[3], v2[3];
+    load3(x, E.tris[3 * j], v0); load3(x, E.tris[3 * j + 1], v1); load3(x, E.tris[3 * j + 2], v2);
+    const double e1[3] = {v1[0] - v0[0], v1[1] - v0[1], v1[2] - v0[2]};
+    const double e2[3] = {v2[0] - v0[0], v2[1] - v0[1], v2[2] - v0[2]};
+    const double cr[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                          e1[0] * e2[1] - e1[1] * e2[0]};
+    const double L = sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+    for (int c = 0; c < 3; ++c) E.tri_cross[3 * j + c] = cr[c];
+    const R n[3] = {(R)(cr[0] / L), (R)(cr[1] / L), (R)(cr[2] / L)};
+    const R* s6 = (const R*)E.sigma + 6 * E.parent[j];
+    const R sg[3][3] = {{s6[0], s6[5], s6[4]}, {s6[5], s6[1], s6[3]}, {s6[4], s6[3], s6[2]}};
+    R tr[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) tr[r] = sg[r][0] * n[0] + sg[r][1] * n[1] + sg[r][2] * n[2];
+    const R pn = tr[0] * n[0] + tr[1] * n[1] + tr[2] * n[2];
+    R* to = (R*)E.traction + 3 * j;
+    R* tt = (R*)E.tangential + 3 * j;
+    R* no = (R*)E.tri_normal + 3 * j;
+    for (int c = 0; c < 3; ++c) {
+      to[c] = tr[c];
+      tt[c] = tr[c] - pn * n[c];
+      no[c] = n[c];
+    }
+    ((R*)E.pressure)[j] = pn;
+    const R area = (R)(0.5 * L);
+    ((R*)E.tri_area)[j] = area;
+    if (E.is_top[j])
+      for (int c = 0; c < 3; ++c) ts[c] = (double)tr[c] * (double)area;
+  }
+  for (int c = 0; c < 3; ++c) {
+    const double v = block_reduce(ts[c], OpSum(), sh);
+    if (threadIdx.x == 0) E.part_s3[3 * tl.tile + c] = v;
+  }
+}
+
+// Alg. 2 contact path per contact vertex: f = -dE_b/dx (float64), vertex
+// normal = normalised sum of incident contact-face e1 x e2, A = 1/3 incident
+// area, f_n = (f.n) n, f_tau = f - f_n, p = |f| / A; partial sum of f.
+__global__ void k_contact(const Tile* tiles, int ntiles, const EnvDesc* envs) {
+  __shared__ double sh[16];
+  const int t = xcd_tile(ntiles);
+  if (t < 0) return;
+  const Tile tl = tiles[t];
+  const EnvDesc& E = envs[tl.env];
+  const EnvState* S = E.st;
+  const EnvPose* P = E.pose;
+  if (!extract_ok(S)) return;
+  const double* x = S->mode == 1 ? E.x : E.xn;
+  const int k = tl.tile * blockDim.x + threadIdx.x;
+  double fs[3] = {0, 0, 0};
+  if (k < E.C) {
+    const int vi = E.cand[k];
+    double xv[3], H[3][3];
+    load3(x, vi, xv);
+    const double kA = E.kappa * E.cand_area[k];
+    double f[3] = {0, 0, 0};
+    for (int m = 0; m < P->n_ind; ++m) {
+      double phi, g[3];
+      sdf_world(P->ind[m], xv, phi, g, H, false);
+      if (phi < E.dhat) {
+        const double b1 = bar1(phi / E.dhat);
+        for (int c = 0; c < 3; ++c) f[c] -= kA * b1 * g[c];
+      }
+    }
+    double nn[3] = {0, 0, 0}, A = 0;
+    for (int c = E.ctri_ptr[k]; c < E.ctri_ptr[k + 1]; ++c) {
+      const int j = E.ctri_idx[c];
+      const double* cr = E.tri_cross + 3 * j;
+      for (int q = 0; q < 3; ++q) nn[q] += cr[q];
+      A += 0.5 * sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]) / 3.0;
+    }
+    const double L = sqrt(nn[0] * nn[0] + nn[1] * nn[1] + nn[2] * nn[2]);
+    for (int q = 0; q < 3; ++q) nn[q] /= L;
+    const double fn = f[0] * nn[0] + f[1] * nn[1] + f[2] * nn[2];
+    const double fm = sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+    for (int q = 0; q < 3; ++q) {
+      E.c_force[3 * k + q] = f[q];
+      E.c_normal[3 * k + q] = nn[q];
+      E.c_fn[3 * k + q] = fn * nn[q];
+      E.c_ft[3 * k + q] = f[q] - fn * nn[q];
+      fs[q] = f[q];
+    }
+    E.c_area[k] = A;
+    E.c_press[k] = fm / A;
+  }
+  for (int c = 0; c < 3; ++c) {
+    const double v = block_reduce(fs[c], OpSum(), sh);
+    if (threadIdx.x == 0) E.part_c3[3 * tl.tile + c] = v;
+  }
+}
+
+// One block per pad: reaction = -sum f_k, contact-face traction integral.
+__global__ void k_env_extract(const EnvDesc* envs, int n) {
+  __shared__ double sh[16];
+  if (blockIdx.x >= n) return;
+  const EnvDesc& E = envs[blockIdx.x];
+  EnvState* S = E.st;
+  if (S->phase != PH_FINISH) return;
+  if (S->status != TC_OK) {
+    if (threadIdx.x == 0) S->phase = PH_DONE;
+    return;
+  }
+  for (int c = 0; c < 3; ++c) {
+    double f = 0, s = 0;
+    for (int k = threadIdx.x; k < E.n_ct; k += blockDim.x) f += E.part_c3[3 * k + c];
+    for (int k = threadIdx.x; k < E.n_st; k += blockDim.x) s += E.part_s3[3 * k + c];
+    f = block_reduce(f, OpSum(), sh);
+    s = block_reduce(s, OpSum(), sh);
+    if (threadIdx.x == 0) {
+      E.reaction[c] = -f;
+      E.traction_sum[c] = s;
+      S->reaction[c] = -f;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) S->phase = PH_DONE;
+}
+
+// Commit: v = (x_new - x) / h, x = x_new.
+__global__ void k_commit(const Tile* tiles, int ntiles, const EnvDesc* envs) {
+  const int t = xcd_tile(ntiles);
+  if (t < 0) return;
+  const EnvDesc& E = envs[tiles[t].env];
+  const EnvState* S = E.st;
+  if (S->mode != 0 || S->phase != PH_FINISH || S->status != TC_OK) return;
+  const int i = tiles[t].tile * blockDim.x + threadIdx.x;
+  if (i >= E.V) return;
+  for (int c = 0; c < 3; ++c) {
+    const double xn = E.xn[3 * i + c];
+    E.v[3 * i + c] = (xn - E.x[3 * i + c]) / E.h;
+    E.x[3 * i + c] = xn;
+  }
+}
+
+// ------------------------------------------------------------ launchers
+
+static inline unsigned grid8(int ntiles) { return (unsigned)(((ntiles + 7) / 8) * 8); }
+
+#define TC_LAUNCH(kern, ntiles, block, stream, ...)                                   \
+  do {                                                                                \
+    if ((ntiles) > 0)                                                                 \
+      hipLaunchKernelGGL(kern, dim3(grid8(ntiles)), dim3(block), 0, stream, __VA_ARGS__); \
+  } while (0)
+
+template <typename R>
+void launch_typed(KernelId id, const LaunchArgs& a) {
+  switch (id) {
+    case KernelId::setup_tets: TC_LAUNCH(k_setup_tets<R>, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs); break;
+    case KernelId::setup_mass: TC_LAUNCH(k_setup_mass<R>, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs, a.out); break;
+    case KernelId::setup_area: TC_LAUNCH(k_setup_cand_area, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs, a.out); break;
+    case KernelId::predict: TC_LAUNCH(k_predict, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs); break;
+    case KernelId::project: TC_LAUNCH(k_project, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs); break;
+    case KernelId::element: TC_LAUNCH(k_element<R>, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs); break;
+    case KernelId::barrier: TC_LAUNCH(k_barrier, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs); break;
+    case KernelId::asm_diag: TC_LAUNCH(k_asm_diag<R>, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs); break;
+    case KernelId::asm_off: TC_LAUNCH(k_asm_off<R>, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs); break;
+    case KernelId::newton_begin:
+      if (a.n_env > 0) hipLaunchKernelGGL(k_env_newton_begin, dim3(a.n_env), dim3(64), 0, a.stream, a.envs, a.n_env);
+      break;
+    case KernelId::cg_spmv: TC_LAUNCH(k_cg_spmv<R>, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs, a.parity); break;
+    case KernelId::cg_update: TC_LAUNCH(k_cg_update<R>, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs, a.parity); break;
+    case KernelId::newton_dir: TC_LAUNCH(k_newton_dir<R>, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs); break;
+    case KernelId::filter: TC_LAUNCH(k_filter<R>, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs); break;
+    case KernelId::env_dir:
+      if (a.n_env > 0) hipLaunchKernelGGL(k_env_dir, dim3(a.n_env), dim3(256), 0, a.stream, a.envs, a.n_env);
+      break;
+    case KernelId::energy: TC_LAUNCH(k_energy<R>, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs, a.mode); break;
+    case KernelId::env_ls:
+      if (a.n_env > 0) hipLaunchKernelGGL(k_env_ls, dim3(a.n_env), dim3(256), 0, a.stream, a.envs, a.n_env, a.mode);
+      break;
+    case KernelId::update: TC_LAUNCH(k_update<R>, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs); break;
+    case KernelId::sigma: TC_LAUNCH(k_sigma<R>, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs); break;
+    case KernelId::traction: TC_LAUNCH(k_traction<R>, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs); break;
+    case KernelId::contact: TC_LAUNCH(k_contact, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs); break;
+    case KernelId::env_extract:
+      if (a.n_env > 0) hipLaunchKernelGGL(k_env_extract, dim3(a.n_env), dim3(256), 0, a.stream, a.envs, a.n_env);
+      break;
+    case KernelId::commit: TC_LAUNCH(k_commit, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs); break;
+    default: break;
+  }
+}
+
+void launch_kernel(KernelId id, bool fp64, const LaunchArgs& a) {
+  if (fp64) launch_typed<double>(id, a);
+  else launch_typed<float>(id, a);
+}
+
+}  // namespace tc

@@ -1,0 +1,179 @@
+// Internal runtime objects behind the C ABI (context, pads, batch plans).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/tacauchy.h"
+#include "tc_device.h"
+#include "tc_launch.h"
+#include "topology.h"
+
+namespace tc {
+
+tc_status set_error(tc_status s, const std::string& msg);
+tc_status hip_fail(hipError_t e, const char* what);
+
+#define TC_HIP(expr)                                        \
+  do {                                                      \
+    hipError_t e_ = (expr);                                 \
+    if (e_ != hipSuccess) return ::tc::hip_fail(e_, #expr); \
+  } while (0)
+
+// First-fit sub-allocator of step scratch over device chunks of the context.
+class Arena {
+ public:
+  struct Chunk {
+    char* base;
+    size_t size;
+    std::map<size_t, size_t> free_;  // offset -> length
+  };
+  void* take(size_t bytes);          // nullptr if nothing fits
+  void give(void* p, size_t bytes);
+  bool add_chunk(char* base, size_t size);
+  size_t held() const;
+  std::vector<Chunk> chunks;
+};
+
+struct KernelTimer {
+  double ms = 0.0;
+  int64_t launches = 0;
+  double bytes = 0.0;
+};
+
+struct BatchPlan;
+
+// Device array of per-step states and poses with pinned host mirrors; a pad
+// in a batch occupies one slot.
+struct SlotPool {
+  int cap = 0;
+  EnvState* d_state = nullptr;
+  EnvPose* d_pose = nullptr;
+  EnvState* h_state = nullptr;
+  EnvPose* h_pose = nullptr;
+};
+
+}  // namespace tc
+
+struct tc_pad;
+
+struct tc_context {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  uint64_t budget = 0;
+  uint64_t used = 0;                 // resident + scratch chunks + plans
+  tc::Arena arena;
+  // launch shape
+  int cg_block = 256;
+  int el_block = 128;
+  int cg_per_replay = 16;
+  bool use_graphs = true;
+  // timing
+  bool timing = false;
+  struct Pending { tc::KernelId k; hipEvent_t a, b; };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> free_events;
+  tc::KernelTimer timers[(int)tc::KernelId::count];
+  // per-step algorithmic byte counts are added when the step finishes
+  std::unique_ptr<tc::BatchPlan> plan;
+  tc::SlotPool pool;                 // slots of synchronous steps
+  std::recursive_mutex mu;           // serialises device work of API calls and the server
+  int next_pad_id = 1;
+
+  void* dev_alloc(size_t bytes, tc_status* st);
+  void dev_free(void* p, size_t bytes);
+};
+
+struct tc_pad {
+  tc_context* ctx = nullptr;
+  int id = 0;
+  int V = 0, T = 0, C = 0, S = 0, S_top = 0, W = 0;
+  int64_t nnz_blocks = 0;
+  bool fp64 = false;
+  int rsize = 4;
+  tc_params params{};
+  int n_mat = 1;
+  double mu[tc::MAX_MAT], lam[tc::MAX_MAT], alpha[tc::MAX_MAT], rho[tc::MAX_MAT];
+  double bbox_diag = 0.0;
+  int64_t step_count = 0;
+  std::atomic<int> busy{0};
+  // resident device arrays (one allocation each, tracked for free)
+  std::vector<std::pair<void*, size_t>> allocs;
+  uint64_t resident_bytes = 0;
+  tc::EnvDesc desc{};                // resident and output pointers
+  // step scratch (one arena block)
+  void* scratch = nullptr;
+  size_t scratch_bytes = 0;
+  size_t scratch_need = 0;
+};
+
+namespace tc {
+
+// Device-side data of a fixed list of pads with their scratch bound.
+struct BatchPlan {
+  std::vector<tc_pad*> pads;
+  std::vector<int> slots;            // state/pose slot of each pad
+  std::vector<void*> scratch;
+  int BV = 0, BT = 0;
+  bool fp64 = false;
+  EnvDesc* d_desc = nullptr;
+  EnvState* d_state = nullptr;
+  EnvState* h_state = nullptr;      // pinned
+  Tile* d_tiles = nullptr;
+  size_t dev_bytes = 0;
+  enum Cls { VERT, TET, CAND, SURF, ASM, ENERGY, NCLS };
+  int off[NCLS] = {0}, cnt[NCLS] = {0};
+  std::vector<EnvDesc> h_desc;
+  hipGraphExec_t cg_exec = nullptr;
+  hipGraph_t cg_graph = nullptr;
+  int graph_M = 0;
+  ~BatchPlan();
+};
+
+// Runs one step (mode 0) or extraction only (mode 1) for the pads.
+tc_status run_batch(tc_context* ctx, int n, tc_pad* const* pads, const int32_t* n_ind,
+                    const tc_indenter* ind, tc_step_stats* stats, int mode);
+
+tc_status ensure_scratch(tc_pad* pad);
+void release_scratch(tc_pad* pad);
+tc_status pool_reserve(tc_context* ctx, SlotPool& p, int cap);
+void pool_free(SlotPool& p);
+tc_status build_plan(tc_context* ctx, int n, tc_pad* const* pads, const int* slots, const SlotPool& pool,
+                     std::unique_ptr<BatchPlan>& out);
+bool plan_matches(const BatchPlan* P, tc_context* ctx, int n, tc_pad* const* pads, const int* slots,
+                  const SlotPool& pool);
+void account_bytes(tc_context* ctx, const tc_pad* pad, const EnvState& s);
+void init_state(EnvState& S, EnvPose& Q, int mode, int n_ind, const tc_indenter* ind);
+void fill_stats(tc_step_stats& o, const EnvState& S, double ms);
+
+// Sequences the kernels of one Newton iteration over a plan.  Pad i of the
+// plan uses state slot P->slots[i]; readbacks copy slots [0, span).
+struct Runner {
+  tc_context* ctx;
+  BatchPlan* P;
+  int n;
+  SlotPool* pool;
+  int span;
+
+  const EnvState& state(int i) const { return pool->h_state[P->slots[i]]; }
+  void launch(KernelId k, int cls, int parity = 0, int mode = 0);
+  tc_status readback();
+  bool any(bool (*pred)(const EnvState&)) const;
+  tc_status cg_chunk(int M);
+  tc_status tick(bool init);
+
+  static bool is_run(const EnvState& s) { return s.phase == PH_RUN && s.status == TC_OK; }
+  static bool cg_pending(const EnvState& s) { return is_run(s) && !s.cg_done; }
+  static bool ls_pending(const EnvState& s) { return is_run(s) && !s.ls_done; }
+  static bool is_finish(const EnvState& s) { return s.phase == PH_FINISH; }
+  static bool not_done(const EnvState& s) { return s.phase != PH_DONE && s.phase != PH_IDLE; }
+};
+
+}  // namespace tc

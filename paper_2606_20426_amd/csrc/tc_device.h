@@ -1,0 +1,166 @@
+// Device-visible data of the tactile FEM step: per-pad descriptors, per-step
+// state and tile tables shared by the kernels (kernels.hip) and the runtime
+// that launches them (runtime.hip).
+#pragma once
+
+#include <cstdint>
+
+namespace tc {
+
+constexpr int MAX_IND = 5;
+constexpr int MAX_MAT = 8;
+// Per-tet record written by the element kernel: the 78 independent entries
+// of the symmetric 12x12 element Hessian in 10 blocks (a <= b), then the 12
+// gradient entries, padded to 96 values.
+constexpr int KE_STRIDE = 96;
+constexpr int KE_GRAD = 78;
+
+// offset of block (a, b), a <= b, inside the record; diagonal blocks hold
+// (xx, xy, xz, yy, yz, zz), off-diagonal blocks row-major 3x3
+__host__ __device__ constexpr int ke_block_offset(int a, int b) {
+  return a == 0 ? (b == 0 ? 0 : 6 + 9 * (b - 1))
+       : a == 1 ? (b == 1 ? 33 : 39 + 9 * (b - 2))
+       : a == 2 ? (b == 2 ? 57 : 63)
+       : 72;
+}
+
+struct DevIndenter {
+  int32_t shape;
+  int32_t reserved;
+  double R[9];
+  double c[3];
+  double prm[4];
+};
+
+// Indenter poses of one pad for the current step (uploaded at step start).
+struct EnvPose {
+  int32_t n_ind;
+  int32_t reserved;
+  DevIndenter ind[MAX_IND];
+};
+
+// Life cycle of a pad's step inside a batch.
+enum Phase : int32_t {
+  PH_INIT = 0,    // predict + feasible start + E(x0) pending
+  PH_RUN = 1,     // Newton iterations
+  PH_FINISH = 2,  // Newton ended (or extraction only): extraction/commit pending
+  PH_DONE = 3,    // results readable, slot free
+  PH_IDLE = 4     // slot not in use
+};
+
+// Mutable per-pad state of one step, in device memory (one slot of a pool).
+// The runtime initialises it at step start; kernels own it afterwards.
+struct EnvState {
+  int32_t phase;
+  int32_t mode;            // 0 = full step, 1 = extraction only
+  int32_t status;          // TC_OK or TC_E_*
+  int32_t infeasible;
+  int32_t newton_done;
+  int32_t newton_iters;
+  int32_t cg_total;
+  int32_t ls_total;
+  double final_step_inf;
+  double reaction[3];
+  // per Newton iteration
+  int32_t dir_conv;
+  int32_t apply;
+  int32_t ls_done;
+  int32_t ls_halv;
+  double ls_alpha;
+  double alpha_max;
+  double gTd;
+  double E_cur;
+  double E_next;
+  // CG (ping-pong slots indexed by iteration parity)
+  double rzp[2];
+  double rz0;
+  int32_t it[2];
+  int32_t cg_done;
+  int32_t cg_iters;
+  int32_t breakdown;
+  int32_t pad0;
+  double cg_tol2;
+};
+
+// Immutable-per-batch description of one pad: pointers into its resident
+// arrays, step scratch and outputs, sizes, material table and parameters.
+struct EnvDesc {
+  int32_t V, T, C, S, W;
+  int32_t n_vt, n_tt, n_ct, n_st, n_at, n_te;   // tiles per kernel class
+  // resident inputs
+  const double* X;
+  double* x;
+  double* v;
+  const int32_t* tets;       // [T][4]
+  const void* Dminv;         // real [T][9]
+  const void* vol;           // real [T]
+  const int8_t* mat;         // [T] material index or null
+  const double* mass;        // [V]
+  const uint8_t* fixed;      // [V]
+  const int32_t* cand;       // [C]
+  const int32_t* cand_of_vert;  // [V], -1 if not a candidate
+  const double* cand_area;   // [C] rest barrier weight
+  const int32_t* tris;       // [S][3]
+  const int32_t* parent;     // [S]
+  const uint8_t* is_top;     // [S]
+  const int32_t* ctri_ptr;   // [C+1] incident contact-face tris per candidate
+  const int32_t* ctri_idx;
+  const int32_t* col;        // [W][V] block column of each stored block, -1 = empty
+  const int32_t* cptr;       // [W*V+1] contribution ranges per (slot, row)
+  const uint32_t* clist;     // (tet << 4) | (a << 2) | b
+  // outputs
+  void* sigma;               // real [T][6]
+  void* traction;            // real [S][3]
+  void* pressure;            // real [S]
+  void* tangential;          // real [S][3]
+  void* tri_area;            // real [S]
+  void* tri_normal;          // real [S][3]
+  double* tri_cross;         // [S][3] e1 x e2 (current)
+  double* c_force;           // [C][3]
+  double* c_normal;
+  double* c_area;
+  double* c_fn;
+  double* c_ft;
+  double* c_press;
+  double* reaction;          // [3]
+  double* traction_sum;      // [3]
+  // step scratch
+  void* Ke;                  // real [T][KE_STRIDE]
+  void* A;                   // real [W][9][V]
+  double* xn;                // Newton iterate [V][3]
+  double* xhat;
+  double* g;                 // gradient [V][3]
+  void* d;                   // real [V][3] Newton direction (CG solution)
+  double* r;                 // CG residual
+  void* z;                   // real
+  void* p0;                  // real, ping-pong search directions
+  void* p1;
+  void* q;                   // real, A p
+  void* Pinv;                // real [V][6] symmetric preconditioner blocks
+  double* gb;                // [C][3] barrier gradient
+  double* Hb;                // [C][6] projected barrier Hessian
+  double* part_rz;           // [n_vt]
+  double* part_pq;           // [n_vt]
+  double* part_g2;           // [n_vt]
+  double* part_e;            // [n_te + n_vt + n_ct]
+  double* part_dir;          // [2 n_vt]
+  double* part_filt;         // [n_ct]
+  double* part_c3;           // [3 n_ct]
+  double* part_s3;           // [3 n_st]
+  EnvState* st;
+  const EnvPose* pose;
+  // material table (Eq. 1) and parameters
+  double mu[MAX_MAT], lam[MAX_MAT], alpha[MAX_MAT], rho[MAX_MAT];
+  double h, dhat, kappa, tol_abs, noise, cg_tol2;
+  double gravity[3];
+  int32_t quasi_static, max_cg, max_newton, max_halvings, precond, pad1;
+};
+
+// One block of a launch: pad `env`, tile index `tile` within that pad's
+// work of the kernel's class.
+struct Tile {
+  int32_t env;
+  int32_t tile;
+};
+
+}  // namespace tc

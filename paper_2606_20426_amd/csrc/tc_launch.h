@@ -1,0 +1,60 @@
+// Host-side launch interface of the kernels in kernels.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "tc_device.h"
+
+namespace tc {
+
+enum class KernelId : int {
+  setup_tets,
+  setup_mass,
+  setup_area,
+  predict,
+  project,
+  element,
+  barrier,
+  asm_diag,
+  asm_off,
+  newton_begin,
+  cg_spmv,
+  cg_update,
+  newton_dir,
+  filter,
+  env_dir,
+  energy,
+  env_ls,
+  update,
+  sigma,
+  traction,
+  contact,
+  env_extract,
+  commit,
+  count
+};
+
+inline const char* kernel_name(KernelId k) {
+  static const char* names[] = {"setup_tets", "setup_mass", "setup_area", "predict",   "project",
+                                "element",    "barrier",    "asm_diag",   "asm_off",   "newton_begin",
+                                "cg_spmv",    "cg_update",  "newton_dir", "filter",    "env_dir",
+                                "energy",     "env_ls",     "update",     "sigma",     "traction",
+                                "contact",    "env_extract", "commit"};
+  return names[static_cast<int>(k)];
+}
+
+struct LaunchArgs {
+  const Tile* tiles = nullptr;
+  int ntiles = 0;
+  int block = 256;
+  const EnvDesc* envs = nullptr;
+  int n_env = 0;
+  int parity = 0;
+  int mode = 0;
+  double* out = nullptr;
+  hipStream_t stream = nullptr;
+};
+
+void launch_kernel(KernelId id, bool fp64, const LaunchArgs& a);
+
+}  // namespace tc

@@ -1,0 +1,137 @@
+"""Host-only checks of the C-ABI library: it loads, exports every entry point
+declared in include/tacauchy.h, its surface extraction (Alg. 1 lines 1-3)
+matches the oracle bit for bit, and argument validation returns the
+documented error codes.  No GPU is touched."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import surface as osurf
+from workloads import scenes
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tacauchy.h")
+
+
+@pytest.fixture(scope="module")
+def tc():
+    import paper_2606_20426_amd as tc
+    from paper_2606_20426_amd import _abi
+    if not os.path.exists(_abi.LIB_PATH):
+        from paper_2606_20426_amd import build
+        build.build()
+    tc.load()
+    return tc
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tc_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(tc):
+    lib = tc.load()
+    names = header_functions()
+    assert len(names) >= 35
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert lib.tc_version().decode().startswith("tacauchy")
+    assert tc._abi.status_name(-6) == "TC_E_NOT_CONVERGED"
+
+
+def _oracle_surface(X, tets, fixed=None):
+    tris, parent = osurf.surface_triangles(tets)
+    top = osurf.contact_face_labels(X, tris)
+    fixed = osurf.default_fixed(X) if fixed is None else fixed
+    cand = osurf.candidates(tris, top, fixed, X.shape[0])
+    return tris, parent, top, cand
+
+
+@pytest.mark.parametrize("which", ["config1", "dome", "graded", "odd", "one_cube"])
+def test_surface_bit_exact_vs_oracle(tc, which):
+    fixed = None
+    if which == "config1":
+        p = scenes.config1().pad
+    elif which == "dome":
+        p = scenes.dome_pad(0.019, 0.016, 0.003, 9, 7, 4)
+    elif which == "graded":
+        from workloads import meshes
+        p = scenes.box_pad(0.018, 0.014, 0.004, 9, 7, 6, zs=meshes.graded_axis_top(0.004, 6, 0.0002))
+    elif which == "odd":
+        p = scenes.box_pad(0.005, 0.007, 0.003, 5, 7, 3)
+        rng = np.random.default_rng(0)
+        fixed = rng.integers(0, 8, p.X.shape[0]).astype(np.uint8)
+    else:
+        p = scenes.one_cube_pad()
+        fixed = np.where(p.X[:, 2] == 0, 7, 0).astype(np.uint8)
+    got = tc.mesh_surface(p.X, p.tets, fixed)
+    tris, parent, top, cand = _oracle_surface(p.X, p.tets, fixed)
+    assert np.array_equal(got["tris"], tris)
+    assert np.array_equal(got["parent"], parent)
+    assert np.array_equal(got["is_top"], top)
+    assert np.array_equal(got["candidates"], cand)
+
+
+def test_config2_surface_bit_exact(tc):
+    p = scenes.config2_pad()
+    got = tc.mesh_surface(p.X, p.tets)
+    tris, parent, top, cand = _oracle_surface(p.X, p.tets)
+    assert got["tris"].shape[0] == 10460 and int(top.sum()) == 3150
+    assert np.array_equal(got["tris"], tris) and np.array_equal(got["parent"], parent)
+    assert np.array_equal(got["is_top"], top) and np.array_equal(got["candidates"], cand)
+
+
+def _status(fn):
+    from paper_2606_20426_amd import TcError
+    try:
+        fn()
+    except TcError as e:
+        return e.status
+    return 0
+
+
+def test_validation_error_codes(tc):
+    p = scenes.one_cube_pad()
+    X, T = p.X.copy(), p.tets.copy()
+    V = tc.validate
+    assert _status(lambda: V(mesh=(X, T))) == 0
+    bad = T.copy(); bad[0, 1] = 99
+    assert _status(lambda: V(mesh=(X, bad))) == -2               # index out of range
+    inv = T.copy(); inv[0, [2, 3]] = inv[0, [3, 2]]
+    assert _status(lambda: V(mesh=(X, inv))) == -2               # negative volume
+    rep = T.copy(); rep[0, 1] = rep[0, 0]
+    assert _status(lambda: V(mesh=(X, rep))) == -2               # repeated vertex
+    Xn = X.copy(); Xn[3, 1] = np.nan
+    assert _status(lambda: V(mesh=(Xn, T))) == -1
+    assert _status(lambda: V(mesh=(X, T, np.full(8, 9, np.uint8)))) == -1
+    ok = dict(E=3e5, nu=0.45, density=1000.0)
+    assert _status(lambda: V(materials=ok)) == 0
+    for badm in (dict(ok, E=0.0), dict(ok, E=-1.0), dict(ok, nu=0.5), dict(ok, nu=-1.0),
+                 dict(ok, density=0.0), dict(ok, E=float("nan"))):
+        assert _status(lambda: V(materials=badm)) == -1
+    assert _status(lambda: V(params=tc.make_params())) == 0
+    for kw in (dict(dt=0.0), dict(dhat=-1.0), dict(kappa=float("inf")), dict(max_newton=0),
+               dict(precision=7), dict(precond=3), dict(cg_rel_tol=0.0)):
+        assert _status(lambda: V(params=tc.make_params(**kw))) == -1
+    I = np.eye(3)
+    good = dict(shape=0, prm=(1e-3,), R=I, c=(0, 0, 0))
+    assert _status(lambda: V(indenters=[good])) == 0
+    assert _status(lambda: V(indenters=[good] * 6)) == -1
+    assert _status(lambda: V(indenters=[dict(good, shape=9)])) == -1
+    assert _status(lambda: V(indenters=[dict(good, prm=(0.0,))])) == -1
+    assert _status(lambda: V(indenters=[dict(good, R=2 * I)])) == -1
+    assert _status(lambda: V(indenters=[dict(good, R=np.diag([1.0, 1.0, -1.0]))])) == -1
+    assert _status(lambda: V(indenters=[dict(good, shape=2, prm=(1e-3, 1e-3, 0.0))])) == -1
+
+
+def test_context_without_device_fails_loudly(tc):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(tc.TcError) as e:
+        tc.Context(0)
+    assert e.value.status == -8
