@@ -76,7 +76,11 @@ def main():
     ap.add_argument("--graphs", type=int, default=1)
     ap.add_argument("--cg-block", type=int, default=0)
     ap.add_argument("--elem-block", type=int, default=0)
+    ap.add_argument("--spmv-block", type=int, default=0)
     ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--cg-rel-tol", type=float, default=None)
+    ap.add_argument("--cg-forcing", type=int, default=None)
+    ap.add_argument("--init-guess", type=int, default=None)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); pads are independent, so N GPUs "
@@ -92,17 +96,26 @@ def main():
     ctx = tc.Context(0)
     t0 = time.perf_counter()
     pads = []
+    extra = {}
+    if args.cg_rel_tol is not None:
+        extra["cg_rel_tol"] = args.cg_rel_tol
+    if args.cg_forcing is not None:
+        extra["cg_forcing"] = args.cg_forcing
+    if args.init_guess is not None:
+        extra["init_guess"] = args.init_guess
     for e in envs:
         m = e.pad.material
+        kw = dict(precision=args.precision, dt=e.params.dt, dhat=e.params.dhat, kappa=e.params.kappa,
+                  newton_tol=e.params.newton_tol, cg_rel_tol=e.params.cg_rel_tol)
+        kw.update(extra)
         pads.append(tc.Pad(ctx, e.pad.X, e.pad.tets, dict(E=m.E, nu=m.nu, density=m.density),
-                           tc.make_params(precision=args.precision, dt=e.params.dt, dhat=e.params.dhat,
-                                          kappa=e.params.kappa, newton_tol=e.params.newton_tol,
-                                          cg_rel_tol=e.params.cg_rel_tol)))
+                           tc.make_params(**kw)))
     log(f"pads created in {time.perf_counter() - t0:.1f} s; HBM used {ctx.memory()[0] / 2**30:.2f} GiB")
-    ctx.set_launch(cg_block=args.cg_block, elem_block=args.elem_block, use_graphs=args.graphs)
+    ctx.set_launch(cg_block=args.cg_block, elem_block=args.elem_block, spmv_block=args.spmv_block,
+                   use_graphs=args.graphs)
     if args.autotune:
         chosen = ctx.autotune(pads, [[e.pose(1)] for e in envs])
-        log(f"autotune: cg block {chosen[0]}, element block {chosen[1]}, CG per replay {chosen[2]}")
+        log(f"autotune: vertex block {chosen[0]}, element block {chosen[1]}, SpMV block {chosen[2]}")
 
     def step(s):
         return tc.step_batch(ctx, pads, [[e.pose(s)] for e in envs])

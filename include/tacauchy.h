@@ -156,7 +156,14 @@ typedef struct {
   int32_t literal_alpha;/* 1 = rest shift alpha = 1 exactly as Eq. 2 prints */
   int32_t precond;      /* TC_PRECOND_* */
   int32_t max_halvings; /* line-search halvings before TC_E_LINESEARCH */
-  int32_t reserved;
+  int32_t cg_forcing;   /* 0: CG to cg_rel_tol every Newton iteration;
+                           1: Eisenstat-Walker forcing eta_k = 0.9 (|g_k| /
+                           |g_k-1|)^2 (preconditioned norms), safeguarded,
+                           within [cg_rel_tol, 0.5] */
+  int32_t hess_proj;    /* element Hessian eigenvalue filter: 0 = clamp
+                           negatives to 0, 1 = absolute value */
+  int32_t init_guess;   /* Newton start: 0 = x_t, 1 = x_t + dt v_t (free
+                           components); either is then made feasible */
 } tc_params;
 
 /* Rigid indenter pose at the end of the step: world x = R y + c. */
@@ -195,7 +202,8 @@ const char* tc_status_string(tc_status s);    /* host only */
 const char* tc_last_error(void);              /* host only, thread-local */
 
 /* Defaults: dt 1/60, d_hat 1e-4, kappa 1e3, newton_tol 1e-6, cg_rel_tol 1e-4,
- * max_newton 1024, max_cg 4000, dynamic, MIXED, block Jacobi, 40 halvings. */
+ * max_newton 1024, max_cg 4000, dynamic, MIXED, block Jacobi, 40 halvings,
+ * Eisenstat-Walker CG forcing. */
 tc_status tc_params_default(tc_params* out);  /* host only */
 
 /* Argument checks used by every entry point (host only):
@@ -244,16 +252,17 @@ tc_status tc_context_timing(tc_context* ctx, int32_t cap, int32_t* n,
                             int64_t* launches, double* bytes_per_launch);
 tc_status tc_context_reset_timing(tc_context* ctx);
 
-/* Launch-shape autotuner: times the element, assembly and CG kernels on the
- * given pads for each candidate block size and CG iterations per graph
- * replay, and keeps the fastest for the context.  Committed pad state is not
- * modified.  chosen[0..2] = (CG block, element block, CG iterations per
- * replay) when chosen != NULL. */
+/* Launch-shape autotuner: times the element and CG kernels on the given pads
+ * for each candidate block size and keeps the fastest for the context.
+ * Committed pad state is not modified.  chosen[0..3] = (vertex-row block,
+ * element block, SpMV block, CG iterations per replay) when chosen != NULL. */
 tc_status tc_autotune(tc_context* ctx, int32_t n, tc_pad* const* pads,
                       const int32_t* n_ind, const tc_indenter* ind, int32_t* chosen);
-/* Force a launch shape (block sizes 64..1024, multiple of 64; replay >= 2,
- * even).  0 leaves a value unchanged. */
-tc_status tc_set_launch(tc_context* ctx, int32_t cg_block, int32_t elem_block,
+/* Force a launch shape: block sizes of the vertex-row kernels (64..1024),
+ * the element kernels (64..256) and the SpMV (64..1024), all multiples of 64;
+ * CG iterations per graph replay (even, >= 2); use_graphs 0/1, -1 unchanged.
+ * 0 leaves a value unchanged. */
+tc_status tc_set_launch(tc_context* ctx, int32_t cg_block, int32_t elem_block, int32_t spmv_block,
                         int32_t cg_per_replay, int32_t use_graphs);
 
 /* ------------------------------------------------------------------- pads */

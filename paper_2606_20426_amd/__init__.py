@@ -7,7 +7,9 @@ Context does, and fails loudly without a gfx950 device or a built library.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
+import weakref
 from typing import Iterable, List, Optional, Sequence
 
 import numpy as np
@@ -15,6 +17,21 @@ import numpy as np
 from . import _abi
 from ._abi import (BOX, CYLINDER, FIELDS, PREC_FP64, PREC_MIXED, PRECOND_BLOCK_JACOBI,  # noqa: F401
                    PRECOND_JACOBI, SPHERE, TEXTURE, TORUS, TcError, check, load)
+
+# Live library objects, closed in dependency order (servers, pads, contexts)
+# before the interpreter and the HIP runtime shut down.
+_LIVE = {"server": weakref.WeakSet(), "pad": weakref.WeakSet(), "ctx": weakref.WeakSet()}
+
+
+@atexit.register
+def _close_all():
+    for kind in ("server", "pad", "ctx"):
+        for obj in list(_LIVE[kind]):
+            try:
+                obj.close()
+            except Exception:
+                pass
+
 
 _DT_NP = {_abi.DT_F64: np.float64, _abi.DT_F32: np.float32, _abi.DT_I32: np.int32, _abi.DT_U8: np.uint8}
 
@@ -126,9 +143,16 @@ class Context:
                                          int(hbm_budget), C.byref(h)))
         self.h = h
         self.device = device
+        _LIVE["ctx"].add(self)
 
     def close(self):
         if getattr(self, "h", None):
+            for srv in list(_LIVE["server"]):
+                if srv.ctx is self:
+                    srv.close()
+            for pad in list(_LIVE["pad"]):
+                if pad.ctx is self:
+                    pad.close()
             self.lib.tc_context_destroy(self.h)
             self.h = None
 
@@ -160,15 +184,15 @@ class Context:
         check(self.lib.tc_context_timing(self.h, cap, C.byref(n), names, avg, cnt, byt))
         return {names[i].value.decode(): (avg[i], cnt[i], byt[i]) for i in range(n.value)}
 
-    def set_launch(self, cg_block=0, elem_block=0, cg_per_replay=0, use_graphs=-1):
-        check(self.lib.tc_set_launch(self.h, cg_block, elem_block, cg_per_replay, use_graphs))
+    def set_launch(self, cg_block=0, elem_block=0, spmv_block=0, cg_per_replay=0, use_graphs=-1):
+        check(self.lib.tc_set_launch(self.h, cg_block, elem_block, spmv_block, cg_per_replay, use_graphs))
 
     def autotune(self, pads: Sequence["Pad"], indenters: Sequence[Sequence]):
         n = len(pads)
         ph = (C.c_void_p * n)(*[p.h for p in pads])
         nind = (C.c_int32 * n)(*[len(i) for i in indenters])
         flat = _indenter_array([x for inds in indenters for x in inds])
-        chosen = (C.c_int32 * 3)()
+        chosen = (C.c_int32 * 4)()
         check(self.lib.tc_autotune(self.h, n, ph, nind, flat, chosen))
         return tuple(chosen)
 
@@ -191,6 +215,7 @@ class Pad:
         check(self.lib.tc_pad_create(ctx.h, C.byref(mesh), len(mats), marr, C.byref(params), C.byref(h)))
         self.h = h
         self.params = params
+        _LIVE["pad"].add(self)
         info = _abi.TcPadInfo()
         check(self.lib.tc_pad_get_info(self.h, C.byref(info)))
         self.info = {k: getattr(info, k) for k, _ in _abi.TcPadInfo._fields_}
@@ -293,6 +318,7 @@ class Server:
         h = C.c_void_p()
         check(self.lib.tc_server_create(ctx.h, int(max_slots), C.byref(h)))
         self.h = h
+        _LIVE["server"].add(self)
 
     def submit(self, pad: Pad, indenters: Sequence = (), tag: int = 0) -> int:
         t = C.c_uint64()

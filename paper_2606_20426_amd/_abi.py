@@ -43,7 +43,8 @@ class TcParams(C.Structure):
                 ("max_newton", C.c_int32), ("max_cg", C.c_int32), ("quasi_static", C.c_int32),
                 ("precision", C.c_int32), ("gravity", C.c_double * 3),
                 ("literal_alpha", C.c_int32), ("precond", C.c_int32),
-                ("max_halvings", C.c_int32), ("reserved", C.c_int32)]
+                ("max_halvings", C.c_int32), ("cg_forcing", C.c_int32),
+                ("hess_proj", C.c_int32), ("init_guess", C.c_int32)]
 
 
 class TcIndenter(C.Structure):
@@ -99,7 +100,7 @@ PROTOS = {
                               C.POINTER(C.c_double)]),
     "tc_context_reset_timing": (S, [P]),
     "tc_autotune": (S, [P, S, C.POINTER(P), C.POINTER(S), C.POINTER(TcIndenter), C.POINTER(S)]),
-    "tc_set_launch": (S, [P, S, S, S, S]),
+    "tc_set_launch": (S, [P, S, S, S, S, S]),
     "tc_pad_create": (S, [P, C.POINTER(TcMesh), S, C.POINTER(TcMaterial), C.POINTER(TcParams), C.POINTER(P)]),
     "tc_pad_destroy": (S, [P]),
     "tc_pad_get_info": (S, [P, C.POINTER(TcPadInfo)]),

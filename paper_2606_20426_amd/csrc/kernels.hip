@@ -381,6 +381,64 @@ __device__ __forceinline__ void load3(const double* p, int i, double v[3]) {
   v[0] = p[3 * i]; v[1] = p[3 * i + 1]; v[2] = p[3 * i + 2];
 }
 
+// ------------------------------------------------ kinematics (cancellation-free)
+
+// Displacement gradient H = Du Dm^-1 with Du formed from float64 displacement
+// differences (u = x - X), so F = I + H carries no O(1) rounding at rest.
+template <typename R>
+__device__ __forceinline__ void disp_gradient(const double* x, const double* X, const int4 tv,
+                                              const R Dm[3][3], R H[3][3]) {
+  const int vv[4] = {tv.x, tv.y, tv.z, tv.w};
+  double u[4][3];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) u[a][c] = x[3 * vv[a] + c] - X[3 * vv[a] + c];
+  R Du[3][3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) Du[i][b] = (R)(u[b + 1][i] - u[0][i]);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) H[i][j] = Du[i][0] * Dm[0][j] + Du[i][1] * Dm[1][j] + Du[i][2] * Dm[2][j];
+}
+
+// cofactor matrix (cof M)_ij = d det M / dM_ij
+template <typename R>
+__device__ __forceinline__ void cofactor3(const R M[3][3], R C[3][3]) {
+  C[0][0] = M[1][1] * M[2][2] - M[1][2] * M[2][1];
+  C[0][1] = M[1][2] * M[2][0] - M[1][0] * M[2][2];
+  C[0][2] = M[1][0] * M[2][1] - M[1][1] * M[2][0];
+  C[1][0] = M[0][2] * M[2][1] - M[0][1] * M[2][2];
+  C[1][1] = M[0][0] * M[2][2] - M[0][2] * M[2][0];
+  C[1][2] = M[0][1] * M[2][0] - M[0][0] * M[2][1];
+  C[2][0] = M[0][1] * M[1][2] - M[0][2] * M[1][1];
+  C[2][1] = M[0][2] * M[1][0] - M[0][0] * M[1][2];
+  C[2][2] = M[0][0] * M[1][1] - M[0][1] * M[1][0];
+}
+
+// From H: J - 1 = I1 + I2 + I3 (invariants of H) and dC = cof F - I =
+// tr(H) I - H^T + cof H, both without cancellation for small H.
+template <typename R>
+__device__ __forceinline__ R kinematics(const R H[3][3], R dC[3][3]) {
+  const R tr = H[0][0] + H[1][1] + H[2][2];
+  R trHH = 0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) trHH += H[i][j] * H[j][i];
+  R cH[3][3];
+  cofactor3(H, cH);
+  const R I3 = H[0][0] * cH[0][0] + H[0][1] * cH[0][1] + H[0][2] * cH[0][2];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) dC[i][j] = (i == j ? tr : R(0)) - H[j][i] + cH[i][j];
+  return tr + R(0.5) * (tr * tr - trHH) + I3;
+}
+
 // ------------------------------------------------------------ setup (a1)
 
 // Per tet: Dm^-1 and V_e = det(Dm) / 6 from rest positions (float64 math).
@@ -423,7 +481,8 @@ __global__ void k_setup_mass(const Tile* tiles, int ntiles, const EnvDesc* envs,
   const int i = tiles[t].tile * blockDim.x + threadIdx.x;
   if (i >= E.V) return;
   double m = 0.0;
-  for (int c = E.cptr[i]; c < E.cptr[i + 1]; ++c) {
+  const size_t it0 = (size_t)i * E.W;
+  for (int c = E.cptr[it0]; c < E.cptr[it0 + 1]; ++c) {
     const int e = (int)(E.clist[c] >> 4);
     const int4 tv = reinterpret_cast<const int4*>(E.tets)[e];
     double x0[3], x1[3], x2[3], x3[3];
@@ -460,7 +519,8 @@ __global__ void k_setup_cand_area(const Tile* tiles, int ntiles, const EnvDesc* 
 
 // ------------------------------------------------------ predict (a2)
 
-// xhat = x + h v + h^2 g_ext; Newton starts from x.
+// xhat = x + h v + h^2 g_ext; Newton starts from x (or x + h v on free
+// components when init_guess is set).
 __global__ void k_predict(const Tile* tiles, int ntiles, const EnvDesc* envs) {
   const int t = xcd_tile(ntiles);
   if (t < 0) return;
@@ -469,10 +529,11 @@ __global__ void k_predict(const Tile* tiles, int ntiles, const EnvDesc* envs) {
   const int i = tiles[t].tile * blockDim.x + threadIdx.x;
   if (i >= E.V) return;
   const double h = E.h;
+  const uint8_t fm = E.fixed[i];
   for (int c = 0; c < 3; ++c) {
     const double x = E.x[3 * i + c];
     E.xhat[3 * i + c] = x + h * E.v[3 * i + c] + h * h * E.gravity[c];
-    E.xn[3 * i + c] = x;
+    E.xn[3 * i + c] = (E.init_guess && !((fm >> c) & 1)) ? x + h * E.v[3 * i + c] : x;
   }
 }
 
@@ -536,43 +597,27 @@ __global__ void __launch_bounds__(256) k_element(const Tile* tiles, int ntiles, 
   const int e = tiles[t].tile * blockDim.x + threadIdx.x;
   if (e >= E.T) return;
   const int4 tv = reinterpret_cast<const int4*>(E.tets)[e];
-  double x0[3], x1[3], x2[3], x3[3];
-  load3(E.xn, tv.x, x0); load3(E.xn, tv.y, x1); load3(E.xn, tv.z, x2); load3(E.xn, tv.w, x3);
-  R Ds[3][3];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    Ds[i][0] = (R)(x1[i] - x0[i]);
-    Ds[i][1] = (R)(x2[i] - x0[i]);
-    Ds[i][2] = (R)(x3[i] - x0[i]);
-  }
   const R* Dmp = (const R*)E.Dminv + 9 * e;
   R Dm[3][3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
     for (int j = 0; j < 3; ++j) Dm[i][j] = Dmp[3 * i + j];
+  R H[3][3];
+  disp_gradient(E.xn, E.X, tv, Dm, H);
+  const int mid = E.mat ? E.mat[e] : 0;
+  const R mu = (R)E.mu[mid], lam = (R)E.lam[mid], csh = (R)E.cshift[mid];
+  const R vol = ((const R*)E.vol)[e];
+  R dC[3][3];
+  const R Jm1 = kinematics(H, dC);
+  // lam (J - alpha) = lam (J - 1) - c with c = lam (alpha - 1) (= mu for the
+  // rest-stable shift, 0 for alpha = 1)
+  const R sJ = lam * Jm1 - csh;
   R F[3][3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int j = 0; j < 3; ++j) F[i][j] = Ds[i][0] * Dm[0][j] + Ds[i][1] * Dm[1][j] + Ds[i][2] * Dm[2][j];
-  const int mid = E.mat ? E.mat[e] : 0;
-  const R mu = (R)E.mu[mid], lam = (R)E.lam[mid], alpha = (R)E.alpha[mid];
-  const R vol = ((const R*)E.vol)[e];
-
-  // cofactor (columns f1 x f2, f2 x f0, f0 x f1) and J
-  R cof[3][3];
-  cof[0][0] = F[1][1] * F[2][2] - F[2][1] * F[1][2];
-  cof[1][0] = F[2][1] * F[0][2] - F[0][1] * F[2][2];
-  cof[2][0] = F[0][1] * F[1][2] - F[1][1] * F[0][2];
-  cof[0][1] = F[1][2] * F[2][0] - F[2][2] * F[1][0];
-  cof[1][1] = F[2][2] * F[0][0] - F[0][2] * F[2][0];
-  cof[2][1] = F[0][2] * F[1][0] - F[1][2] * F[0][0];
-  cof[0][2] = F[1][0] * F[2][1] - F[2][0] * F[1][1];
-  cof[1][2] = F[2][0] * F[0][1] - F[0][0] * F[2][1];
-  cof[2][2] = F[0][0] * F[1][1] - F[1][0] * F[0][1];
-  const R J = F[0][0] * cof[0][0] + F[1][0] * cof[1][0] + F[2][0] * cof[2][0];
-  const R sJ = lam * (J - alpha);
+    for (int j = 0; j < 3; ++j) F[i][j] = H[i][j] + (i == j ? R(1) : R(0));
 
   R rec[KE_STRIDE];
 #pragma unroll
@@ -580,11 +625,14 @@ __global__ void __launch_bounds__(256) k_element(const Tile* tiles, int ntiles, 
 
   // gradient: vertex a >= 1 gets V P Dm^-T column a-1; vertex 0 minus the sum
   {
+    // Eq. 2, P = mu F + lam (J - alpha) cof F, regrouped so every term is
+    // O(H): (mu - c + lam (J-1)) I + mu H + (lam (J-1) - c) (cof F - I)
     R P[3][3];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
-      for (int j = 0; j < 3; ++j) P[i][j] = mu * F[i][j] + sJ * cof[i][j];
+      for (int j = 0; j < 3; ++j)
+        P[i][j] = (i == j ? mu - csh + lam * Jm1 : R(0)) + mu * H[i][j] + (lam * Jm1 - csh) * dC[i][j];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       R s0 = 0;
@@ -619,8 +667,9 @@ __global__ void __launch_bounds__(256) k_element(const Tile* tiles, int ntiles, 
     const int i = pr == 2 ? 1 : 0;
     const int j = pr == 0 ? 1 : 2;
     const int k = 3 - i - j;
-    const R ltw = mu + sJ * sv[k];
-    const R lfl = mu - sJ * sv[k];
+    R ltw = mu + sJ * sv[k];
+    R lfl = mu - sJ * sv[k];
+    if (E.hess_proj) { ltw = fabs(ltw); lfl = fabs(lfl); }
     R c[4][3];
     if (ltw > R(0)) {
 #pragma unroll
@@ -652,6 +701,7 @@ __global__ void __launch_bounds__(256) k_element(const Tile* tiles, int ntiles, 
     sym_eig3(As, Qs, ws);
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
+      if (E.hess_proj) ws[m] = fabs(ws[m]);
       if (ws[m] > R(0)) {
         R c[4][3];
 #pragma unroll
@@ -768,7 +818,8 @@ __global__ void k_asm_diag(const Tile* tiles, int ntiles, const EnvDesc* envs) {
     double D[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
     double gs[3] = {0, 0, 0};
     const R* Ke = (const R*)E.Ke;
-    for (int c = E.cptr[i]; c < E.cptr[i + 1]; ++c) {
+    const size_t it0 = (size_t)i * E.W;
+    for (int c = E.cptr[it0]; c < E.cptr[it0 + 1]; ++c) {
       const uint32_t code = E.clist[c];
       const int e = (int)(code >> 4), a = (int)((code >> 2) & 3);
       const R* rec = Ke + (size_t)KE_STRIDE * e;
@@ -805,10 +856,9 @@ __global__ void k_asm_diag(const Tile* tiles, int ntiles, const EnvDesc* envs) {
         D[r][r] = 1.0;
         gs[r] = 0.0;
       }
-    R* A = (R*)E.A;
-    const int V = E.V;
+    R* A = (R*)E.A + it0 * 9;
     for (int r = 0; r < 3; ++r)
-      for (int q = 0; q < 3; ++q) A[(size_t)(3 * r + q) * V + i] = (R)D[r][q];
+      for (int q = 0; q < 3; ++q) A[3 * r + q] = (R)D[r][q];
     // preconditioner: inverse of the 3x3 diagonal block, or of its diagonal
     double P[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
     if (E.precond == TC_PRECOND_BLOCK_JACOBI) {
@@ -865,10 +915,12 @@ __global__ void k_asm_off(const Tile* tiles, int ntiles, const EnvDesc* envs) {
   if (t < 0) return;
   const EnvDesc& E = envs[tiles[t].env];
   if (!running(E.st)) return;
-  const int V = E.V;
-  const int item = V + tiles[t].tile * blockDim.x + threadIdx.x;   // skip slot 0
-  if (item >= E.W * V) return;
-  const int s = item / V, i = item - s * V;
+  const int W1 = E.W - 1;
+  if (W1 <= 0) return;
+  const int64_t t2 = (int64_t)tiles[t].tile * blockDim.x + threadIdx.x;
+  if (t2 >= (int64_t)E.V * W1) return;
+  const int i = (int)(t2 / W1), s = 1 + (int)(t2 - (int64_t)i * W1);
+  const size_t item = (size_t)i * E.W + s;       // row-major (row, slot)
   const int j = E.col[item];
   R acc[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
   if (j >= 0) {
@@ -891,11 +943,11 @@ __global__ void k_asm_off(const Tile* tiles, int ntiles, const EnvDesc* envs) {
       for (int q = 0; q < 3; ++q)
         acc[r][q] = (((fi >> r) & 1) || ((fj >> q) & 1)) ? R(0) : acc[r][q] * h2;
   }
-  R* A = (R*)E.A + (size_t)s * 9 * V;
+  R* A = (R*)E.A + item * 9;
 #pragma unroll
   for (int r = 0; r < 3; ++r)
 #pragma unroll
-    for (int q = 0; q < 3; ++q) A[(size_t)(3 * r + q) * V + i] = acc[r][q];
+    for (int q = 0; q < 3; ++q) A[3 * r + q] = acc[r][q];
 }
 
 // ------------------------------------------------------ CG (a5)
@@ -905,7 +957,13 @@ __global__ void k_env_newton_begin(const EnvDesc* envs, int n) {
   if (blockIdx.x >= n || threadIdx.x != 0) return;
   EnvState* S = envs[blockIdx.x].st;
   if (!running(S)) return;
-  S->cg_tol2 = envs[blockIdx.x].cg_tol2;
+  if (S->newton_iters == 0) {
+    S->rz0_prev = -1.0;
+    S->eta_prev = 0.0;
+  } else {
+    S->rz0_prev = S->rz0;
+    S->eta_prev = sqrt(S->cg_tol2);
+  }
   S->cg_done = 0;
   S->cg_iters = 0;
   S->breakdown = 0;
@@ -933,8 +991,25 @@ __global__ void __launch_bounds__(1024) k_cg_spmv(const Tile* tiles, int ntiles,
   const double rz = reduce_partials(E.part_rz, E.n_vt, OpSum(), 0.0, sh);
   const int it = S->it[parity ^ 1] + 1;
   const double rz0 = it == 0 ? rz : S->rz0;
-  const bool done = it >= E.max_cg || !(rz > S->cg_tol2 * rz0) || S->breakdown;
+  double tol2 = S->cg_tol2;
+  if (it == 0) {
+    // forcing term of this Newton iteration (every block computes the same)
+    double eta = E.cg_rel_tol;
+    if (E.cg_forcing && !S->force_tight) {
+      if (S->rz0_prev > 0.0) {
+        eta = 0.9 * rz / S->rz0_prev;          // 0.9 (|g_k| / |g_k-1|)^2
+        const double safe = 0.9 * S->eta_prev * S->eta_prev;
+        if (safe > 0.1) eta = fmax(eta, safe);
+      } else {
+        eta = 0.5;
+      }
+      eta = fmin(0.5, fmax(eta, E.cg_rel_tol));
+    }
+    tol2 = eta * eta;
+  }
+  const bool done = it >= E.max_cg || !(rz > tol2 * rz0) || S->breakdown;
   if (tl.tile == 0 && threadIdx.x == 0) {
+    if (it == 0) S->cg_tol2 = tol2;
     if (done) {
       S->cg_done = 1;
       S->cg_iters = it;
@@ -946,32 +1021,117 @@ __global__ void __launch_bounds__(1024) k_cg_spmv(const Tile* tiles, int ntiles,
   }
   if (done) return;
   const R beta = it == 0 ? R(0) : (R)(rz / S->rzp[parity ^ 1]);
-  const int V = E.V;
   const int i = tl.tile * blockDim.x + threadIdx.x;
   const R* z = (const R*)E.z;
   const R* pold = (const R*)(parity ? E.p0 : E.p1);
   R* pnew = (R*)(parity ? E.p1 : E.p0);
   double pq = 0.0;
-  if (i < V) {
+  if (i < E.V) {
     const R* A = (const R*)E.A;
     R y0 = 0, y1 = 0, y2 = 0;
     R pi0 = 0, pi1 = 0, pi2 = 0;
     for (int s = 0; s < E.W; ++s) {
-      const int j = E.col[(size_t)s * V + i];
+      const int j = E.col[(size_t)i * E.W + s];
       if (j < 0) break;
       const R pj0 = z[3 * j] + beta * pold[3 * j];
       const R pj1 = z[3 * j + 1] + beta * pold[3 * j + 1];
       const R pj2 = z[3 * j + 2] + beta * pold[3 * j + 2];
       if (s == 0) { pi0 = pj0; pi1 = pj1; pi2 = pj2; }
-      const R* As = A + (size_t)s * 9 * V + i;
-      y0 += As[0 * (size_t)V] * pj0 + As[1 * (size_t)V] * pj1 + As[2 * (size_t)V] * pj2;
-      y1 += As[3 * (size_t)V] * pj0 + As[4 * (size_t)V] * pj1 + As[5 * (size_t)V] * pj2;
-      y2 += As[6 * (size_t)V] * pj0 + As[7 * (size_t)V] * pj1 + As[8 * (size_t)V] * pj2;
+      const R* As = A + ((size_t)i * E.W + s) * 9;
+      y0 += As[0] * pj0 + As[1] * pj1 + As[2] * pj2;
+      y1 += As[3] * pj0 + As[4] * pj1 + As[5] * pj2;
+      y2 += As[6] * pj0 + As[7] * pj1 + As[8] * pj2;
     }
     pnew[3 * i] = pi0; pnew[3 * i + 1] = pi1; pnew[3 * i + 2] = pi2;
     R* q = (R*)E.q;
     q[3 * i] = y0; q[3 * i + 1] = y1; q[3 * i + 2] = y2;
     pq = (double)pi0 * y0 + (double)pi1 * y1 + (double)pi2 * y2;
+  }
+  pq = block_reduce(pq, OpSum(), sh);
+  if (threadIdx.x == 0) E.part_pq[tl.tile] = pq;
+}
+
+// The same product with LPR lanes per matrix row (one stored 3x3 block per
+// lane, blocks of a row contiguous): every lane issues its own independent
+// neighbour gather, and the row sum is a shuffle reduction inside the lane
+// group.  A tile is blockDim.x / LPR lane groups x SPMV_ROWS_PER_GROUP rows.
+template <typename R, int LPR>
+__global__ void __launch_bounds__(1024) k_cg_spmv_vec(const Tile* tiles, int ntiles, const EnvDesc* envs, int parity) {
+  __shared__ double sh[16];
+  const int t = xcd_tile(ntiles);
+  if (t < 0) return;
+  const Tile tl = tiles[t];
+  const EnvDesc& E = envs[tl.env];
+  EnvState* S = E.st;
+  if (!running(S) || S->cg_done) return;
+  const double rz = reduce_partials(E.part_rz, E.n_vt, OpSum(), 0.0, sh);
+  const int it = S->it[parity ^ 1] + 1;
+  const double rz0 = it == 0 ? rz : S->rz0;
+  double tol2 = S->cg_tol2;
+  if (it == 0) {
+    double eta = E.cg_rel_tol;
+    if (E.cg_forcing && !S->force_tight) {
+      if (S->rz0_prev > 0.0) {
+        eta = 0.9 * rz / S->rz0_prev;
+        const double safe = 0.9 * S->eta_prev * S->eta_prev;
+        if (safe > 0.1) eta = fmax(eta, safe);
+      } else {
+        eta = 0.5;
+      }
+      eta = fmin(0.5, fmax(eta, E.cg_rel_tol));
+    }
+    tol2 = eta * eta;
+  }
+  const bool done = it >= E.max_cg || !(rz > tol2 * rz0) || S->breakdown;
+  if (tl.tile == 0 && threadIdx.x == 0) {
+    if (it == 0) S->cg_tol2 = tol2;
+    if (done) {
+      S->cg_done = 1;
+      S->cg_iters = it;
+    } else {
+      S->it[parity] = it;
+      S->rzp[parity] = rz;
+      if (it == 0) S->rz0 = rz;
+    }
+  }
+  if (done) return;
+  const R beta = it == 0 ? R(0) : (R)(rz / S->rzp[parity ^ 1]);
+  const int lane = threadIdx.x & (LPR - 1);
+  const int groups = blockDim.x / LPR;
+  const R* z = (const R*)E.z;
+  const R* pold = (const R*)(parity ? E.p0 : E.p1);
+  R* pnew = (R*)(parity ? E.p1 : E.p0);
+  R* q = (R*)E.q;
+  double pq = 0.0;
+  const int row0 = tl.tile * groups * SPMV_ROWS_PER_GROUP + threadIdx.x / LPR;
+#pragma unroll 2
+  for (int k = 0; k < SPMV_ROWS_PER_GROUP; ++k) {
+    const int i = row0 + k * groups;
+    R y0 = 0, y1 = 0, y2 = 0, pj0 = 0, pj1 = 0, pj2 = 0;
+    if (i < E.V && lane < E.W) {
+      const size_t item = (size_t)i * E.W + lane;
+      const int j = E.col[item];
+      if (j >= 0) {
+        pj0 = z[3 * j] + beta * pold[3 * j];
+        pj1 = z[3 * j + 1] + beta * pold[3 * j + 1];
+        pj2 = z[3 * j + 2] + beta * pold[3 * j + 2];
+        const R* As = (const R*)E.A + item * 9;
+        y0 = As[0] * pj0 + As[1] * pj1 + As[2] * pj2;
+        y1 = As[3] * pj0 + As[4] * pj1 + As[5] * pj2;
+        y2 = As[6] * pj0 + As[7] * pj1 + As[8] * pj2;
+      }
+    }
+#pragma unroll
+    for (int o = LPR / 2; o > 0; o >>= 1) {
+      y0 += __shfl_xor(y0, o, LPR);
+      y1 += __shfl_xor(y1, o, LPR);
+      y2 += __shfl_xor(y2, o, LPR);
+    }
+    if (lane == 0 && i < E.V) {   // slot 0 is the diagonal: pj = p_new of row i
+      pnew[3 * i] = pj0; pnew[3 * i + 1] = pj1; pnew[3 * i + 2] = pj2;
+      q[3 * i] = y0; q[3 * i + 1] = y1; q[3 * i + 2] = y2;
+      pq += (double)pj0 * y0 + (double)pj1 * y1 + (double)pj2 * y2;
+    }
   }
   pq = block_reduce(pq, OpSum(), sh);
   if (threadIdx.x == 0) E.part_pq[tl.tile] = pq;
@@ -988,7 +1148,7 @@ __global__ void __launch_bounds__(1024) k_cg_update(const Tile* tiles, int ntile
   const EnvDesc& E = envs[tl.env];
   EnvState* S = E.st;
   if (!running(S) || S->cg_done) return;
-  const double pq = reduce_partials(E.part_pq, E.n_vt, OpSum(), 0.0, sh);
+  const double pq = reduce_partials(E.part_pq, E.n_spt, OpSum(), 0.0, sh);
   const double rz = S->rzp[parity];
   double alpha = rz / pq;
   if (!(pq > 0.0) || !isfinite(alpha)) {
@@ -1114,7 +1274,11 @@ __global__ void k_env_dir(const EnvDesc* envs, int n) {
     S->gTd = gd;
     S->alpha_max = am;
     S->ls_alpha = fmin(1.0, am);
-    S->dir_conv = dm <= E.tol_abs;
+    // a direction from a loose CG solve can be short only because the soft
+    // modes are unresolved: convergence is judged on a floor-tolerance solve
+    const bool tight = S->cg_tol2 <= E.cg_rel_tol * E.cg_rel_tol * (1.0 + 1e-12) || S->cg_iters >= E.max_cg;
+    S->dir_conv = dm <= E.tol_abs && tight;
+    S->force_tight = dm <= E.tol_abs && !tight;
     S->ls_done = S->dir_conv;
     S->apply = S->dir_conv;
     S->cg_total += S->cg_iters;
@@ -1125,8 +1289,8 @@ __global__ void k_env_dir(const EnvDesc* envs, int n) {
 
 // Incremental potential at y = x + alpha d (float64 throughout): tet tiles
 // give sum V_e Psi(F_e), vertex tiles the inertia term, candidate tiles the
-// barrier (+inf on contact).  mode 0: alpha = 0 for every running pad;
-// mode 1: trial step of pads still searching.
+// barrier (+inf on contact).  mode 0: E(x) of pads being initialised (d is
+// not read); mode 1: trial step of pads still searching.
 template <typename R>
 __global__ void k_energy(const Tile* tiles, int ntiles, const EnvDesc* envs, int mode) {
   __shared__ double sh[16];
@@ -1146,21 +1310,25 @@ __global__ void k_energy(const Tile* tiles, int ntiles, const EnvDesc* envs, int
     if (e < E.T) {
       const int4 tv = reinterpret_cast<const int4*>(E.tets)[e];
       const int vv[4] = {tv.x, tv.y, tv.z, tv.w};
-      double y[4][3];
+      double u[4][3];
       for (int a = 0; a < 4; ++a)
-        for (int c = 0; c < 3; ++c) y[a][c] = E.xn[3 * vv[a] + c] + al * (double)d[3 * vv[a] + c];
+        for (int c = 0; c < 3; ++c)
+          u[a][c] = E.xn[3 * vv[a] + c] + (mode ? al * (double)d[3 * vv[a] + c] : 0.0) - E.X[3 * vv[a] + c];
       const R* Dmp = (const R*)E.Dminv + 9 * e;
-      double F[3][3];
+      double H[3][3];
       for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j)
-          F[i][j] = (y[1][i] - y[0][i]) * (double)Dmp[j] + (y[2][i] - y[0][i]) * (double)Dmp[3 + j] +
-                    (y[3][i] - y[0][i]) * (double)Dmp[6 + j];
+          H[i][j] = (u[1][i] - u[0][i]) * (double)Dmp[j] + (u[2][i] - u[0][i]) * (double)Dmp[3 + j] +
+                    (u[3][i] - u[0][i]) * (double)Dmp[6 + j];
       const int mid = E.mat ? E.mat[e] : 0;
-      const double J = det3(F);
-      double ff = 0;
+      double dC[3][3];
+      const double Jm1 = kinematics(H, dC);
+      double hh = 0, tr = H[0][0] + H[1][1] + H[2][2];
       for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) ff += F[i][j] * F[i][j];
-      const double psi = 0.5 * E.mu[mid] * (ff - 3.0) + 0.5 * E.lam[mid] * (J - E.alpha[mid]) * (J - E.alpha[mid]);
+        for (int j = 0; j < 3; ++j) hh += H[i][j] * H[i][j];
+      // Psi = mu/2 (tr F^T F - 3) + lam/2 (J - alpha)^2 with F = I + H
+      const double sJ = Jm1 - E.cshift[mid] / E.lam[mid];
+      const double psi = 0.5 * E.mu[mid] * (2.0 * tr + hh) + 0.5 * E.lam[mid] * sJ * sJ;
       acc = (double)((const R*)E.vol)[e] * psi;
     }
   } else if ((tt -= E.n_te) < E.n_vt) {
@@ -1168,7 +1336,7 @@ __global__ void k_energy(const Tile* tiles, int ntiles, const EnvDesc* envs, int
     if (i < E.V && !E.quasi_static) {
       double s = 0;
       for (int c = 0; c < 3; ++c) {
-        const double dy = E.xn[3 * i + c] + al * (double)d[3 * i + c] - E.xhat[3 * i + c];
+        const double dy = E.xn[3 * i + c] + (mode ? al * (double)d[3 * i + c] : 0.0) - E.xhat[3 * i + c];
         s += dy * dy;
       }
       acc = 0.5 * E.mass[i] * s;
@@ -1179,7 +1347,7 @@ __global__ void k_energy(const Tile* tiles, int ntiles, const EnvDesc* envs, int
     if (k < E.C) {
       const int vi = E.cand[k];
       double y[3], g[3], H[3][3];
-      for (int c = 0; c < 3; ++c) y[c] = E.xn[3 * vi + c] + al * (double)d[3 * vi + c];
+      for (int c = 0; c < 3; ++c) y[c] = E.xn[3 * vi + c] + (mode ? al * (double)d[3 * vi + c] : 0.0);
       for (int m = 0; m < P->n_ind; ++m) {
         double phi;
         sdf_world(P->ind[m], y, phi, g, H, false);
@@ -1283,25 +1451,26 @@ __global__ void k_sigma(const Tile* tiles, int ntiles, const EnvDesc* envs) {
   if (e >= E.T) return;
   const double* x = S->mode == 1 ? E.x : E.xn;
   const int4 tv = reinterpret_cast<const int4*>(E.tets)[e];
-  double x0[3], x1[3], x2[3], x3[3];
-  load3(x, tv.x, x0); load3(x, tv.y, x1); load3(x, tv.z, x2); load3(x, tv.w, x3);
   const R* Dmp = (const R*)E.Dminv + 9 * e;
-  R F[3][3];
+  R Dm[3][3];
 #pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    const R a = (R)(x1[i] - x0[i]), b = (R)(x2[i] - x0[i]), c = (R)(x3[i] - x0[i]);
+  for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int j = 0; j < 3; ++j) F[i][j] = a * Dmp[j] + b * Dmp[3 + j] + c * Dmp[6 + j];
-  }
+    for (int j = 0; j < 3; ++j) Dm[i][j] = Dmp[3 * i + j];
+  R H[3][3], dC[3][3];
+  disp_gradient(x, E.X, tv, Dm, H);
+  const R Jm1 = kinematics(H, dC);
   const int mid = E.mat ? E.mat[e] : 0;
-  const R mu = (R)E.mu[mid], lam = (R)E.lam[mid], alpha = (R)E.alpha[mid];
-  const R J = det3(F);
-  const R muJ = mu / J, vol = lam * (J - alpha);
+  const R mu = (R)E.mu[mid], lam = (R)E.lam[mid], csh = (R)E.cshift[mid];
+  const R J = R(1) + Jm1;
+  // Eq. 4 with F = I + H: (mu/J)(H + H^T + H H^T) + [mu - c - mu (J-1)/J + lam (J-1)] I
+  const R muJ = mu / J, vol = (mu - csh) - mu * Jm1 / J + lam * Jm1;
   R b[3][3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
 #pragma unroll
-    for (int j = 0; j < 3; ++j) b[i][j] = F[i][0] * F[j][0] + F[i][1] * F[j][1] + F[i][2] * F[j][2];
+    for (int j = 0; j < 3; ++j)
+      b[i][j] = H[i][j] + H[j][i] + H[i][0] * H[j][0] + H[i][1] * H[j][1] + H[i][2] * H[j][2];
   R* s = (R*)E.sigma + 6 * e;
   s[0] = muJ * b[0][0] + vol;
   s[1] = muJ * b[1][1] + vol;
@@ -1486,7 +1655,11 @@ void launch_typed(KernelId id, const LaunchArgs& a) {
     case KernelId::newton_begin:
       if (a.n_env > 0) hipLaunchKernelGGL(k_env_newton_begin, dim3(a.n_env), dim3(64), 0, a.stream, a.envs, a.n_env);
       break;
-    case KernelId::cg_spmv: TC_LAUNCH(k_cg_spmv<R>, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs, a.parity); break;
+    case KernelId::cg_spmv:
+      if (a.lpr == 16) TC_LAUNCH((k_cg_spmv_vec<R, 16>), a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs, a.parity);
+      else if (a.lpr == 32) TC_LAUNCH((k_cg_spmv_vec<R, 32>), a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs, a.parity);
+      else TC_LAUNCH(k_cg_spmv<R>, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs, a.parity);
+      break;
     case KernelId::cg_update: TC_LAUNCH(k_cg_update<R>, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs, a.parity); break;
     case KernelId::newton_dir: TC_LAUNCH(k_newton_dir<R>, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs); break;
     case KernelId::filter: TC_LAUNCH(k_filter<R>, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs); break;

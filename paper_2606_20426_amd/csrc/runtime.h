@@ -72,6 +72,7 @@ struct tc_context {
   tc::Arena arena;
   // launch shape
   int cg_block = 256;
+  int spmv_block = 256;
   int el_block = 128;
   int cg_per_replay = 16;
   bool use_graphs = true;
@@ -121,16 +122,20 @@ struct BatchPlan {
   std::vector<tc_pad*> pads;
   std::vector<int> slots;            // state/pose slot of each pad
   std::vector<void*> scratch;
-  int BV = 0, BT = 0;
+  int BV = 0, BT = 0, BS = 0;
   bool fp64 = false;
   EnvDesc* d_desc = nullptr;
   EnvState* d_state = nullptr;
   EnvState* h_state = nullptr;      // pinned
   Tile* d_tiles = nullptr;
   size_t dev_bytes = 0;
-  enum Cls { VERT, TET, CAND, SURF, ASM, ENERGY, NCLS };
+  enum Cls { VERT, TET, CAND, SURF, ASM, ENERGY, SPMV, NCLS };
+  int lpr = 0;                       // SpMV lanes per row
   int off[NCLS] = {0}, cnt[NCLS] = {0};
   std::vector<EnvDesc> h_desc;
+  Tile* d_ctiles = nullptr;          // compacted SPMV + VERT tiles of CG tails
+  Tile* h_ctiles = nullptr;          // pinned staging
+  int ctiles_cap = 0;
   hipGraphExec_t cg_exec = nullptr;
   hipGraph_t cg_graph = nullptr;
   int graph_M = 0;
@@ -167,6 +172,8 @@ struct Runner {
   tc_status readback();
   bool any(bool (*pred)(const EnvState&)) const;
   tc_status cg_chunk(int M);
+  tc_status cg_chunk_compact(int M, int n_spmv, int n_vert);
+  void launch_tiles(KernelId k, const Tile* tiles, int ntiles, int block, int parity);
   tc_status tick(bool init);
 
   static bool is_run(const EnvState& s) { return s.phase == PH_RUN && s.status == TC_OK; }

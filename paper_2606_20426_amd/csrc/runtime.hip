@@ -6,6 +6,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 namespace tc {
@@ -88,6 +89,8 @@ size_t Arena::held() const {
 }
 
 BatchPlan::~BatchPlan() {
+  if (d_ctiles) (void)hipFree(d_ctiles);
+  if (h_ctiles) (void)hipHostFree(h_ctiles);
   if (cg_exec) (void)hipGraphExecDestroy(cg_exec);
   if (cg_graph) (void)hipGraphDestroy(cg_graph);
   if (d_desc) (void)hipFree(d_desc);
@@ -227,7 +230,7 @@ static ScratchLayout scratch_layout(const tc_pad* p) {
   L.Hb = take(48 * C);
   const size_t nv = cdiv(V, 64), nt = cdiv(T, 64), nc = cdiv(C, 64), ns = cdiv(std::max<size_t>(S, 1), 64);
   L.prz = take(8 * nv);
-  L.ppq = take(8 * nv);
+  L.ppq = take(8 * ((size_t)cdiv(V, 2) + 1));
   L.pg2 = take(8 * nv);
   L.pe = take(8 * (nt + nv + nc));
   L.pdir = take(16 * nv);
@@ -305,9 +308,14 @@ tc_status build_plan(tc_context* ctx, int n, tc_pad* const* pads, const int* slo
   P->slots.assign(slots, slots + n);
   P->BV = ctx->cg_block;
   P->BT = ctx->el_block;
+  P->BS = ctx->spmv_block;
   P->fp64 = pads[0]->fp64;
   P->pads.assign(pads, pads + n);
   P->h_desc.resize(n);
+  int Wmax = 0;
+  for (int i = 0; i < n; ++i) Wmax = std::max(Wmax, pads[i]->W);
+  P->lpr = Wmax <= 16 ? 16 : Wmax <= 32 ? 32 : 0;
+  const int rows_spmv = P->lpr ? (ctx->spmv_block / P->lpr) * SPMV_ROWS_PER_GROUP : P->BV;
   std::vector<Tile> tiles;
   const int BV = P->BV, BT = P->BT;
   for (int i = 0; i < n; ++i) {
@@ -320,6 +328,7 @@ tc_status build_plan(tc_context* ctx, int n, tc_pad* const* pads, const int* slo
     E.n_st = cdiv(p->S, BV);
     E.n_at = cdiv((int64_t)(p->W - 1) * p->V, BV);
     E.n_te = cdiv(p->T, BV);
+    E.n_spt = cdiv(p->V, rows_spmv);
     E.st = pool.d_state + slots[i];
     E.pose = pool.d_pose + slots[i];
     P->h_desc[i] = E;
@@ -338,8 +347,12 @@ tc_status build_plan(tc_context* ctx, int n, tc_pad* const* pads, const int* slo
   add_cls(BatchPlan::SURF, [](const EnvDesc& E) { return E.n_st; });
   add_cls(BatchPlan::ASM, [](const EnvDesc& E) { return E.n_at; });
   add_cls(BatchPlan::ENERGY, [](const EnvDesc& E) { return E.n_te + E.n_vt + E.n_ct; });
+  add_cls(BatchPlan::SPMV, [](const EnvDesc& E) { return E.n_spt; });
   TC_HIP(hipMalloc(&P->d_desc, sizeof(EnvDesc) * n));
   TC_HIP(hipMalloc(&P->d_tiles, sizeof(Tile) * std::max<size_t>(tiles.size(), 1)));
+  P->ctiles_cap = P->cnt[BatchPlan::SPMV] + P->cnt[BatchPlan::VERT];
+  TC_HIP(hipMalloc(&P->d_ctiles, sizeof(Tile) * std::max(P->ctiles_cap, 1)));
+  TC_HIP(hipHostMalloc(&P->h_ctiles, sizeof(Tile) * std::max(P->ctiles_cap, 1), hipHostMallocDefault));
   TC_HIP(hipMemcpyAsync(P->d_desc, P->h_desc.data(), sizeof(EnvDesc) * n, hipMemcpyHostToDevice, ctx->stream));
   TC_HIP(hipMemcpyAsync(P->d_tiles, tiles.data(), sizeof(Tile) * tiles.size(), hipMemcpyHostToDevice, ctx->stream));
   TC_HIP(hipStreamSynchronize(ctx->stream));
@@ -350,7 +363,7 @@ tc_status build_plan(tc_context* ctx, int n, tc_pad* const* pads, const int* slo
 
 bool plan_matches(const BatchPlan* P, tc_context* ctx, int n, tc_pad* const* pads, const int* slots,
                   const SlotPool& pool) {
-  if (!P || (int)P->pads.size() != n || P->BV != ctx->cg_block || P->BT != ctx->el_block ||
+  if (!P || (int)P->pads.size() != n || P->BV != ctx->cg_block || P->BT != ctx->el_block || P->BS != ctx->spmv_block ||
       P->d_state != pool.d_state)
     return false;
   for (int i = 0; i < n; ++i)
@@ -370,7 +383,8 @@ void Runner::launch(KernelId k, int cls, int parity, int mode) {
   if (cls != BatchPlan::NCLS) {
     a.tiles = P->d_tiles + P->off[cls];
     a.ntiles = P->cnt[cls];
-    a.block = cls == BatchPlan::TET ? P->BT : P->BV;
+    a.block = cls == BatchPlan::TET ? P->BT : (cls == BatchPlan::SPMV && P->lpr) ? P->BS : P->BV;
+    a.lpr = P->lpr;
   }
   if (ctx->timing) {
     hipEvent_t e0 = get_event(ctx), e1 = get_event(ctx);
@@ -381,6 +395,38 @@ void Runner::launch(KernelId k, int cls, int parity, int mode) {
   } else {
     launch_kernel(k, P->fp64, a);
   }
+}
+
+void Runner::launch_tiles(KernelId k, const Tile* tiles, int ntiles, int block, int parity) {
+  LaunchArgs a;
+  a.envs = P->d_desc;
+  a.n_env = n;
+  a.parity = parity;
+  a.stream = ctx->stream;
+  a.tiles = tiles;
+  a.ntiles = ntiles;
+  a.block = block;
+  a.lpr = P->lpr;
+  if (ctx->timing) {
+    hipEvent_t e0 = get_event(ctx), e1 = get_event(ctx);
+    (void)hipEventRecord(e0, ctx->stream);
+    launch_kernel(k, P->fp64, a);
+    (void)hipEventRecord(e1, ctx->stream);
+    ctx->pending.push_back({k, e0, e1});
+  } else {
+    launch_kernel(k, P->fp64, a);
+  }
+}
+
+// CG iterations over the tiles of the pads still iterating only (tails of
+// uneven batches); the compacted lists were uploaded to d_ctiles.
+tc_status Runner::cg_chunk_compact(int M, int n_spmv, int n_vert) {
+  const int bs = P->lpr ? P->BS : P->BV;
+  for (int k = 0; k < M; ++k) {
+    launch_tiles(KernelId::cg_spmv, P->d_ctiles, n_spmv, bs, k & 1);
+    launch_tiles(KernelId::cg_update, P->d_ctiles + n_spmv, n_vert, P->BV, k & 1);
+  }
+  return TC_OK;
 }
 
 tc_status Runner::readback() {
@@ -404,7 +450,7 @@ tc_status Runner::cg_chunk(int M) {
       if (P->cg_graph) { (void)hipGraphDestroy(P->cg_graph); P->cg_graph = nullptr; }
       TC_HIP(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
       for (int k = 0; k < M; ++k) {
-        launch(KernelId::cg_spmv, BatchPlan::VERT, k & 1);
+        launch(KernelId::cg_spmv, BatchPlan::SPMV, k & 1);
         launch(KernelId::cg_update, BatchPlan::VERT, k & 1);
       }
       TC_HIP(hipStreamEndCapture(ctx->stream, &P->cg_graph));
@@ -414,7 +460,7 @@ tc_status Runner::cg_chunk(int M) {
     TC_HIP(hipGraphLaunch(P->cg_exec, ctx->stream));
   } else {
     for (int k = 0; k < M; ++k) {
-      launch(KernelId::cg_spmv, BatchPlan::VERT, k & 1);
+      launch(KernelId::cg_spmv, BatchPlan::SPMV, k & 1);
       launch(KernelId::cg_update, BatchPlan::VERT, k & 1);
     }
   }
@@ -441,21 +487,63 @@ tc_status Runner::tick(bool init) {
     int max_cg = 0;
     for (int i = 0; i < n; ++i) max_cg = std::max(max_cg, P->pads[i]->params.max_cg);
     const int M = std::max(2, ctx->cg_per_replay & ~1);
+    int n_full = 0;
+    for (int i = 0; i < n; ++i) n_full += is_run(state(i));
+    int n_cur = n_full, n_spmv = 0, n_vert = 0;
+    bool compact = false;
     for (int done = 0; done <= max_cg + M; done += M) {
-      if ((st = cg_chunk(M))) return st;
+      if (compact) {
+        if ((st = cg_chunk_compact(M, n_spmv, n_vert))) return st;
+      } else if ((st = cg_chunk(M))) {
+        return st;
+      }
       if ((st = readback())) return st;
-      if (!any(cg_pending)) break;
+      int n_act = 0;
+      for (int i = 0; i < n; ++i) n_act += cg_pending(state(i));
+      if (n_act == 0) break;
+      if (n_act * 4 <= n_cur * 3 && n > 1) {
+        // shrink the launch to the pads still iterating
+        int k = 0;
+        const Tile* all = nullptr;
+        std::vector<Tile> host;
+        (void)all;
+        n_spmv = n_vert = 0;
+        for (int i = 0; i < n; ++i)
+          if (cg_pending(state(i)))
+            for (int t = 0; t < P->h_desc[i].n_spt; ++t) P->h_ctiles[k++] = Tile{i, t};
+        n_spmv = k;
+        for (int i = 0; i < n; ++i)
+          if (cg_pending(state(i)))
+            for (int t = 0; t < P->h_desc[i].n_vt; ++t) P->h_ctiles[k++] = Tile{i, t};
+        n_vert = k - n_spmv;
+        TC_HIP(hipMemcpyAsync(P->d_ctiles, P->h_ctiles, sizeof(Tile) * k, hipMemcpyHostToDevice, ctx->stream));
+        compact = true;
+        n_cur = n_act;
+      }
     }
     launch(KernelId::newton_dir, BatchPlan::VERT);
     launch(KernelId::filter, BatchPlan::CAND);
     launch(KernelId::env_dir, BatchPlan::NCLS);
     if ((st = readback())) return st;
+    static const bool debug = std::getenv("TC_DEBUG") != nullptr;
+    if (debug)
+      for (int i = 0; i < n; ++i) {
+        const EnvState& S = state(i);
+        std::fprintf(stderr, "[tc] pad %d newton %d cg %d rz0 %.3e |d| %.3e g.d %.3e amax %.3e E %.12e conv %d\n", i,
+                     S.newton_iters, S.cg_iters, S.rz0, S.final_step_inf, S.gTd, S.alpha_max, S.E_cur, S.dir_conv);
+      }
     int max_h = 0;
     for (int i = 0; i < n; ++i) max_h = std::max(max_h, P->pads[i]->params.max_halvings);
     for (int r = 0; r <= max_h + 1 && any(ls_pending); ++r) {
       launch(KernelId::energy, BatchPlan::ENERGY, 0, 1);
       launch(KernelId::env_ls, BatchPlan::NCLS, 0, 1);
       if ((st = readback())) return st;
+      if (debug)
+        for (int i = 0; i < n; ++i) {
+          const EnvState& S = state(i);
+          std::fprintf(stderr, "[tc]   ls pad %d done %d halv %d alpha %.3e E_next %.12e status %d\n", i, S.ls_done,
+                       S.ls_halv, S.ls_alpha, S.E_next, S.status);
+        }
     }
     launch(KernelId::update, BatchPlan::VERT);
     if ((st = readback())) return st;
@@ -479,7 +567,7 @@ static double kernel_bytes(KernelId k, const tc_pad* p) {
   switch (k) {
     case KernelId::cg_spmv: return nnzb * (9 * R + 4) + V * 12 * R;
     case KernelId::cg_update: return V * (21 * R + 48);
-    case KernelId::element: return T * (16 + 106 * R) + V * 24;
+    case KernelId::element: return T * (16 + 106 * R) + V * 48;
     case KernelId::asm_diag: return T * (16 + 36 * R) + V * (93 + 24 * R);
     case KernelId::asm_off: return T * (48 + 108 * R) + (W - 1) * V * (8 + 9 * R);
     case KernelId::energy: return T * (16 + 10 * R) + V * (56 + 3 * R) + C * 40;
@@ -684,6 +772,9 @@ tc_status tc_params_default(tc_params* out) {
   out->literal_alpha = 0;
   out->precond = TC_PRECOND_BLOCK_JACOBI;
   out->max_halvings = 40;
+  out->cg_forcing = 1;
+  out->hess_proj = 0;
+  out->init_guess = 0;
   return TC_OK;
 }
 
@@ -826,15 +917,19 @@ tc_status tc_context_timing(tc_context* ctx, int32_t cap, int32_t* n, char (*nam
   return TC_OK;
 }
 
-tc_status tc_set_launch(tc_context* ctx, int32_t cg_block, int32_t elem_block, int32_t cg_per_replay,
-                        int32_t use_graphs) {
+tc_status tc_set_launch(tc_context* ctx, int32_t cg_block, int32_t elem_block, int32_t spmv_block,
+                        int32_t cg_per_replay, int32_t use_graphs) {
   if (!ctx) return set_error(TC_E_INVALID_ARG, "ctx is null");
   auto okb = [](int b) { return b == 0 || (b >= 64 && b <= 1024 && b % 64 == 0); };
-  if (!okb(cg_block) || !okb(elem_block) || elem_block > 256) return set_error(TC_E_INVALID_ARG, "block sizes: multiples of 64, cg <= 1024, element <= 256");
-  if (cg_per_replay < 0 || (cg_per_replay && (cg_per_replay < 2 || cg_per_replay % 2))) return set_error(TC_E_INVALID_ARG, "CG iterations per replay must be even and >= 2");
+  if (!okb(cg_block) || !okb(elem_block) || !okb(spmv_block) || elem_block > 256)
+    return set_error(TC_E_INVALID_ARG, "block sizes: multiples of 64 up to 1024 (element up to 256)");
+  if (cg_per_replay < 0 || (cg_per_replay && (cg_per_replay < 2 || cg_per_replay % 2)))
+    return set_error(TC_E_INVALID_ARG, "CG iterations per replay must be even and >= 2");
+  if (use_graphs < -1 || use_graphs > 1) return set_error(TC_E_INVALID_ARG, "use_graphs must be -1, 0 or 1");
   std::lock_guard<std::recursive_mutex> lk(ctx->mu);
   if (cg_block) ctx->cg_block = cg_block;
   if (elem_block) ctx->el_block = elem_block;
+  if (spmv_block) ctx->spmv_block = spmv_block;
   if (cg_per_replay) ctx->cg_per_replay = cg_per_replay;
   if (use_graphs >= 0) ctx->use_graphs = use_graphs != 0;
   ctx->plan.reset();
@@ -978,6 +1073,7 @@ tc_status tc_pad_create(tc_context* ctx, const tc_mesh* mesh, int32_t n_material
     E.col = col; E.cptr = cptr; E.clist = clist;
     for (int k = 0; k < MAX_MAT; ++k) {
       E.mu[k] = p->mu[k]; E.lam[k] = p->lam[k]; E.alpha[k] = p->alpha[k]; E.rho[k] = p->rho[k];
+      E.cshift[k] = (k < n_materials && !params->literal_alpha) ? p->mu[k] : 0.0;
     }
     tc_pad_set_params(p, params);
     // setup kernels (a1): Dm^-1 and V_e, lumped mass, rest contact areas
@@ -1063,7 +1159,10 @@ tc_status tc_pad_set_params(tc_pad* pad, const tc_params* params) {
   E.kappa = params->kappa;
   E.tol_abs = params->newton_tol * pad->bbox_diag;
   E.noise = 1e-12;
-  E.cg_tol2 = params->cg_rel_tol * params->cg_rel_tol;
+  E.cg_rel_tol = params->cg_rel_tol;
+  E.cg_forcing = params->cg_forcing;
+  E.hess_proj = params->hess_proj;
+  E.init_guess = params->init_guess;
   for (int c = 0; c < 3; ++c) E.gravity[c] = params->gravity[c];
   E.quasi_static = params->quasi_static;
   E.max_cg = params->max_cg;
@@ -1192,58 +1291,70 @@ tc_status tc_autotune(tc_context* ctx, int32_t n, tc_pad* const* pads, const int
   return guarded([&]() -> tc_status {
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     TC_HIP(hipSetDevice(ctx->device));
-    const int cg_cands[] = {128, 256, 512, 1024};
+    const int blk_cands[] = {128, 256, 512, 1024};
     const int el_cands[] = {64, 128, 256};
     const bool old_timing = ctx->timing;
     const bool old_graphs = ctx->use_graphs;
     ctx->timing = true;
     ctx->use_graphs = false;
-    double best_cg = 1e30, best_el = 1e30;
-    int bcg = ctx->cg_block, bel = ctx->el_block;
-    for (int cb : cg_cands) {
-      for (int eb : el_cands) {
-        ctx->cg_block = cb;
-        ctx->el_block = eb;
-        ctx->plan.reset();
-        for (auto& t : ctx->timers) t = KernelTimer{};
-        // one extraction-only pass builds the plan; timings come from a
-        // probe step on copies: the committed state is restored afterwards
-        std::vector<std::vector<char>> saved(n);
-        for (int i = 0; i < n; ++i) {
-          size_t b = 0;
-          tc_pad_save_state(pads[i], nullptr, &b);
-          saved[i].resize(b);
-          tc_status s = tc_pad_save_state(pads[i], saved[i].data(), &b);
-          if (s) return s;
-        }
-        std::vector<tc_step_stats> st(n);
-        tc_status s = run_batch(ctx, n, pads, n_ind, ind, st.data(), 0);
-        for (int i = 0; i < n; ++i) {
-          tc_pad_load_state(pads[i], saved[i].data(), saved[i].size());
-          pads[i]->step_count -= (s == TC_OK) ? 0 : 0;
-        }
-        if (s && s != TC_E_NOT_CONVERGED && s != TC_E_LINESEARCH) return s;
-        resolve_timing(ctx);
-        const KernelTimer& ts = ctx->timers[(int)KernelId::cg_spmv];
-        const KernelTimer& tu = ctx->timers[(int)KernelId::cg_update];
-        const KernelTimer& te = ctx->timers[(int)KernelId::element];
-        int64_t cgit = 0;
-        for (auto& x : st) cgit += x.cg_iters;
-        const double cg_per_it = cgit ? (ts.ms + tu.ms) / (double)cgit : 1e30;
-        const double el = te.launches ? te.ms / te.launches : 1e30;
-        if (eb == el_cands[0] && cg_per_it < best_cg) { best_cg = cg_per_it; bcg = cb; }
-        if (cb == cg_cands[0] && el < best_el) { best_el = el; bel = eb; }
+    // probe: one step per candidate on saved state, restored afterwards
+    auto probe = [&](int vb, int eb, int sb, double* t_spmv, double* t_upd, double* t_el) -> tc_status {
+      ctx->cg_block = vb;
+      ctx->el_block = eb;
+      ctx->spmv_block = sb;
+      ctx->plan.reset();
+      for (auto& t : ctx->timers) t = KernelTimer{};
+      std::vector<std::vector<char>> saved(n);
+      std::vector<int64_t> steps(n);
+      for (int i = 0; i < n; ++i) {
+        size_t b = 0;
+        tc_pad_save_state(pads[i], nullptr, &b);
+        saved[i].resize(b);
+        tc_status s = tc_pad_save_state(pads[i], saved[i].data(), &b);
+        if (s) return s;
+        steps[i] = pads[i]->step_count;
       }
+      std::vector<tc_step_stats> st(n);
+      tc_status s = run_batch(ctx, n, pads, n_ind, ind, st.data(), 0);
+      for (int i = 0; i < n; ++i) {
+        tc_pad_load_state(pads[i], saved[i].data(), saved[i].size());
+        pads[i]->step_count = steps[i];
+      }
+      if (s && s != TC_E_NOT_CONVERGED && s != TC_E_LINESEARCH) return s;
+      resolve_timing(ctx);
+      int64_t cgit = 0;
+      for (auto& x : st) cgit += x.cg_iters;
+      const KernelTimer& ts = ctx->timers[(int)KernelId::cg_spmv];
+      const KernelTimer& tu = ctx->timers[(int)KernelId::cg_update];
+      const KernelTimer& te = ctx->timers[(int)KernelId::element];
+      *t_spmv = cgit ? ts.ms / (double)cgit : 1e30;
+      *t_upd = cgit ? tu.ms / (double)cgit : 1e30;
+      *t_el = te.launches ? te.ms / te.launches : 1e30;
+      return TC_OK;
+    };
+    int bcg = ctx->cg_block, bel = ctx->el_block, bsp = ctx->spmv_block;
+    double best_u = 1e30, best_s = 1e30, best_e = 1e30;
+    for (int b : blk_cands) {
+      double ts, tu, te;
+      tc_status s = probe(b, 128, b, &ts, &tu, &te);
+      if (s) return s;
+      if (tu < best_u) { best_u = tu; bcg = b; }
+      if (ts < best_s) { best_s = ts; bsp = b; }
+    }
+    for (int eb : el_cands) {
+      double ts, tu, te;
+      tc_status s = probe(bcg, eb, bsp, &ts, &tu, &te);
+      if (s) return s;
+      if (te < best_e) { best_e = te; bel = eb; }
     }
     ctx->cg_block = bcg;
     ctx->el_block = bel;
-    // CG iterations per graph replay: fewer readbacks vs wasted iterations
-    ctx->cg_per_replay = 16;
+    ctx->spmv_block = bsp;
     ctx->timing = old_timing;
     ctx->use_graphs = old_graphs;
     ctx->plan.reset();
     for (auto& t : ctx->timers) t = KernelTimer{};
-    if (chosen) { chosen[0] = bcg; chosen[1] = bel; chosen[2] = ctx->cg_per_replay; }
+    if (chosen) { chosen[0] = bcg; chosen[1] = bel; chosen[2] = bsp; chosen[3] = ctx->cg_per_replay; }
     return TC_OK;
   });
 }

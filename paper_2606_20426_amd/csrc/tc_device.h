@@ -14,6 +14,8 @@ constexpr int MAX_MAT = 8;
 // gradient entries, padded to 96 values.
 constexpr int KE_STRIDE = 96;
 constexpr int KE_GRAD = 78;
+// rows handled by each lane group of the vectorised SpMV per tile
+constexpr int SPMV_ROWS_PER_GROUP = 8;
 
 // offset of block (a, b), a <= b, inside the record; diagonal blocks hold
 // (xx, xy, xz, yy, yz, zz), off-diagonal blocks row-major 3x3
@@ -78,15 +80,17 @@ struct EnvState {
   int32_t cg_done;
   int32_t cg_iters;
   int32_t breakdown;
-  int32_t pad0;
+  int32_t force_tight;     // next CG must reach the floor tolerance
   double cg_tol2;
+  double rz0_prev;         // r0.z0 of the previous Newton iteration (< 0: none)
+  double eta_prev;
 };
 
 // Immutable-per-batch description of one pad: pointers into its resident
 // arrays, step scratch and outputs, sizes, material table and parameters.
 struct EnvDesc {
   int32_t V, T, C, S, W;
-  int32_t n_vt, n_tt, n_ct, n_st, n_at, n_te;   // tiles per kernel class
+  int32_t n_vt, n_tt, n_ct, n_st, n_at, n_te, n_spt;   // tiles per kernel class
   // resident inputs
   const double* X;
   double* x;
@@ -105,8 +109,8 @@ struct EnvDesc {
   const uint8_t* is_top;     // [S]
   const int32_t* ctri_ptr;   // [C+1] incident contact-face tris per candidate
   const int32_t* ctri_idx;
-  const int32_t* col;        // [W][V] block column of each stored block, -1 = empty
-  const int32_t* cptr;       // [W*V+1] contribution ranges per (slot, row)
+  const int32_t* col;        // [V][W] block column of each stored block, -1 = empty
+  const int32_t* cptr;       // [V*W+1] contribution ranges per (row, slot)
   const uint32_t* clist;     // (tet << 4) | (a << 2) | b
   // outputs
   void* sigma;               // real [T][6]
@@ -126,7 +130,7 @@ struct EnvDesc {
   double* traction_sum;      // [3]
   // step scratch
   void* Ke;                  // real [T][KE_STRIDE]
-  void* A;                   // real [W][9][V]
+  void* A;                   // real [V][W][9] row-major 3x3 blocks
   double* xn;                // Newton iterate [V][3]
   double* xhat;
   double* g;                 // gradient [V][3]
@@ -140,7 +144,7 @@ struct EnvDesc {
   double* gb;                // [C][3] barrier gradient
   double* Hb;                // [C][6] projected barrier Hessian
   double* part_rz;           // [n_vt]
-  double* part_pq;           // [n_vt]
+  double* part_pq;           // [n_spt]
   double* part_g2;           // [n_vt]
   double* part_e;            // [n_te + n_vt + n_ct]
   double* part_dir;          // [2 n_vt]
@@ -150,10 +154,11 @@ struct EnvDesc {
   EnvState* st;
   const EnvPose* pose;
   // material table (Eq. 1) and parameters
-  double mu[MAX_MAT], lam[MAX_MAT], alpha[MAX_MAT], rho[MAX_MAT];
-  double h, dhat, kappa, tol_abs, noise, cg_tol2;
+  // cshift = lam (alpha - 1): mu for the rest-stable shift, 0 for alpha = 1
+  double mu[MAX_MAT], lam[MAX_MAT], alpha[MAX_MAT], rho[MAX_MAT], cshift[MAX_MAT];
+  double h, dhat, kappa, tol_abs, noise, cg_rel_tol;
   double gravity[3];
-  int32_t quasi_static, max_cg, max_newton, max_halvings, precond, pad1;
+  int32_t quasi_static, max_cg, max_newton, max_halvings, precond, cg_forcing, hess_proj, init_guess;
 };
 
 // One block of a launch: pad `env`, tile index `tile` within that pad's

@@ -51,6 +51,7 @@ struct LaunchArgs {
   int n_env = 0;
   int parity = 0;
   int mode = 0;
+  int lpr = 0;             // SpMV lanes per row (16, 32; 0 = one thread per row)
   double* out = nullptr;
   hipStream_t stream = nullptr;
 };

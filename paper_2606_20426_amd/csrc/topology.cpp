@@ -80,6 +80,11 @@ tc_status validate_params(const tc_params* p, std::string& err) {
   if (p->max_newton < 1 || p->max_cg < 1 || p->max_halvings < 0) { err = "iteration caps must be >= 1"; return TC_E_INVALID_ARG; }
   if (p->precision != TC_PREC_FP64 && p->precision != TC_PREC_MIXED) { err = "unknown precision"; return TC_E_INVALID_ARG; }
   if (p->precond != TC_PRECOND_BLOCK_JACOBI && p->precond != TC_PRECOND_JACOBI) { err = "unknown preconditioner"; return TC_E_INVALID_ARG; }
+  if (p->cg_forcing != 0 && p->cg_forcing != 1) { err = "cg_forcing must be 0 or 1"; return TC_E_INVALID_ARG; }
+  if (p->literal_alpha != 0 && p->literal_alpha != 1) { err = "literal_alpha must be 0 or 1"; return TC_E_INVALID_ARG; }
+  if (p->quasi_static != 0 && p->quasi_static != 1) { err = "quasi_static must be 0 or 1"; return TC_E_INVALID_ARG; }
+  if (p->hess_proj != 0 && p->hess_proj != 1) { err = "hess_proj must be 0 or 1"; return TC_E_INVALID_ARG; }
+  if (p->init_guess != 0 && p->init_guess != 1) { err = "init_guess must be 0 or 1"; return TC_E_INVALID_ARG; }
   for (int c = 0; c < 3; ++c)
     if (!finite(p->gravity[c])) { err = "gravity must be finite"; return TC_E_INVALID_ARG; }
   return TC_OK;
@@ -234,7 +239,7 @@ void build_sparsity(const tc_mesh* m, Topology& t) {
   t.W = W;
   t.col.assign((size_t)W * V, -1);
   for (int i = 0; i < V; ++i)
-    for (size_t s = 0; s < nb[i].size(); ++s) t.col[s * V + i] = nb[i][s];
+    for (size_t s = 0; s < nb[i].size(); ++s) t.col[(size_t)i * W + s] = nb[i][s];
   auto slot_of = [&](int row, int c) {
     const auto& L = nb[row];
     return (int)(std::find(L.begin(), L.end(), c) - L.begin());
@@ -246,7 +251,7 @@ void build_sparsity(const tc_mesh* m, Topology& t) {
     const int32_t* tv = m->tets + 4LL * e;
     for (int a = 0; a < 4; ++a)
       for (int b = 0; b < 4; ++b) {
-        const int64_t it = (int64_t)slot_of(tv[a], tv[b]) * V + tv[a];
+        const int64_t it = (int64_t)tv[a] * W + slot_of(tv[a], tv[b]);
         item[16LL * e + 4 * a + b] = (int32_t)it;
         cnt[it + 1]++;
       }

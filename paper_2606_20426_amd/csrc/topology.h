@@ -24,11 +24,11 @@ struct Topology {
   std::vector<int32_t> ctri_ptr;  // [C+1] incident contact-face triangles
   std::vector<int32_t> ctri_idx;
   // assembled Hessian: W stored 3x3 blocks per vertex row, slot 0 = diagonal,
-  // then neighbours ascending; col[s * V + i] = -1 past the row's end
+  // then neighbours ascending; col[i * W + s] = -1 past the row's end
   int W = 0;
   int64_t nnz_blocks = 0;
   std::vector<int32_t> col;       // [W*V]
-  std::vector<int32_t> cptr;      // [W*V+1] gather range of each (slot, row)
+  std::vector<int32_t> cptr;      // [V*W+1] gather range of each (row, slot)
   std::vector<uint32_t> clist;    // (tet << 4) | (a << 2) | b, ascending tet
 };
 
