@@ -157,13 +157,23 @@ typedef struct {
   int32_t precond;      /* TC_PRECOND_* */
   int32_t max_halvings; /* line-search halvings before TC_E_LINESEARCH */
   int32_t cg_forcing;   /* 0: CG to cg_rel_tol every Newton iteration;
-                           1: Eisenstat-Walker forcing eta_k = 0.9 (|g_k| /
-                           |g_k-1|)^2 (preconditioned norms), safeguarded,
-                           within [cg_rel_tol, 0.5] */
-  int32_t hess_proj;    /* element Hessian eigenvalue filter: 0 = clamp
-                           negatives to 0, 1 = absolute value */
+                           1: adaptive forcing within [cg_rel_tol,
+                           cg_eta_max]: Eisenstat-Walker eta_k = 0.9 (|g_k| /
+                           |g_k-1|)^2 (preconditioned norms, safeguarded)
+                           while the gradient falls by 2x or more per
+                           iteration, eta_k = eta_k-1 / 4 otherwise */
+  int32_t hess_proj;    /* Hessian filters.  Bits 0-1, element eigenvalues:
+                           0 clamp negatives to 0, 1 absolute value, 2 clamp
+                           until a full Newton step is accepted, then the
+                           unfiltered Hessian (CG stops at negative
+                           curvature; a breakdown reverts to clamping for the
+                           rest of the step).  Bits 2-3, barrier 3x3: 0 clamp,
+                           1 unfiltered, 2 normal term only. */
   int32_t init_guess;   /* Newton start: 0 = x_t, 1 = x_t + dt v_t (free
                            components); either is then made feasible */
+  double cg_conv_tol;   /* CG tolerance of the direction on which Newton
+                           convergence is accepted (0 = cg_rel_tol) */
+  double cg_eta_max;    /* largest forcing term (first Newton iteration) */
 } tc_params;
 
 /* Rigid indenter pose at the end of the step: world x = R y + c. */
@@ -302,6 +312,15 @@ tc_status tc_step_batch(tc_context* ctx, int32_t n, tc_pad* const* pads,
 /* Extraction only (Alg. 2 stress/traction/contact) on the committed positions
  * under the given poses: fills SIGMA ... TRACTION_SUM. */
 tc_status tc_extract(tc_pad* pad, int32_t n_ind, const tc_indenter* ind);
+
+/* Inspection: one Newton direction at the committed positions (taken as the
+ * current iterate as they are: no feasible-start projection) under the given
+ * poses.  Assembles the element and barrier Hessians and gradient and runs
+ * CG to cg_conv_tol (else cg_rel_tol).  dir and grad (host, [V][3] float64,
+ * grad may be NULL) receive p and dE/dx (inertia + dt^2 (elastic + barrier),
+ * fixed components zeroed).  The pad state is not modified. */
+tc_status tc_pad_newton_direction(tc_pad* pad, int32_t n_ind, const tc_indenter* ind, double* dir,
+                                  double* grad);
 
 /* ------------------------------------------------------------------ fields */
 tc_status tc_field_info(const tc_pad* pad, int32_t field, int32_t* dtype,

@@ -252,6 +252,16 @@ class Pad:
     def extract(self, indenters: Sequence = ()):
         check(self.lib.tc_extract(self.h, len(indenters), _indenter_array(indenters)))
 
+    def newton_direction(self, indenters: Sequence = ()):
+        """(p, dE/dx) at the committed positions, both [V,3] float64."""
+        V = self.info["n_verts"]
+        d = np.zeros((V, 3))
+        g = np.zeros((V, 3))
+        check(self.lib.tc_pad_newton_direction(self.h, len(indenters), _indenter_array(indenters),
+                                               d.ctypes.data_as(C.POINTER(C.c_double)),
+                                               g.ctypes.data_as(C.POINTER(C.c_double))))
+        return d, g
+
     def field_info(self, field):
         f = FIELDS[field] if isinstance(field, str) else int(field)
         dt, n, c = C.c_int32(), C.c_int64(), C.c_int32()

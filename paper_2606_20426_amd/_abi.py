@@ -44,7 +44,8 @@ class TcParams(C.Structure):
                 ("precision", C.c_int32), ("gravity", C.c_double * 3),
                 ("literal_alpha", C.c_int32), ("precond", C.c_int32),
                 ("max_halvings", C.c_int32), ("cg_forcing", C.c_int32),
-                ("hess_proj", C.c_int32), ("init_guess", C.c_int32)]
+                ("hess_proj", C.c_int32), ("init_guess", C.c_int32),
+                ("cg_conv_tol", C.c_double), ("cg_eta_max", C.c_double)]
 
 
 class TcIndenter(C.Structure):
@@ -110,6 +111,7 @@ PROTOS = {
     "tc_step": (S, [P, S, C.POINTER(TcIndenter), C.POINTER(TcStepStats)]),
     "tc_step_batch": (S, [P, S, C.POINTER(P), C.POINTER(S), C.POINTER(TcIndenter), C.POINTER(TcStepStats)]),
     "tc_extract": (S, [P, S, C.POINTER(TcIndenter)]),
+    "tc_pad_newton_direction": (S, [P, S, C.POINTER(TcIndenter), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "tc_field_info": (S, [P, S, C.POINTER(S), C.POINTER(C.c_int64), C.POINTER(S)]),
     "tc_pad_read": (S, [P, S, P, C.c_size_t, S]),
     "tc_pad_write": (S, [P, S, P, C.c_size_t, S]),

@@ -646,6 +646,10 @@ __global__ void __launch_bounds__(256) k_element(const Tile* tiles, int ntiles, 
     }
   }
 
+  // element eigenvalue filter: 0 clamp, 1 absolute value, 2 clamp until a
+  // full Newton step is accepted, then unfiltered (true Hessian)
+  const int emode = E.hess_proj & 3;
+  const bool unfiltered = emode == 2 && E.st->true_hess;
   R U[3][3], sv[3], V[3][3];
   svd3(F, U, sv, V);
   // h[l][a] = v_l . G_a
@@ -669,16 +673,16 @@ __global__ void __launch_bounds__(256) k_element(const Tile* tiles, int ntiles, 
     const int k = 3 - i - j;
     R ltw = mu + sJ * sv[k];
     R lfl = mu - sJ * sv[k];
-    if (E.hess_proj) { ltw = fabs(ltw); lfl = fabs(lfl); }
+    if (emode == 1) { ltw = fabs(ltw); lfl = fabs(lfl); }
     R c[4][3];
-    if (ltw > R(0)) {
+    if (ltw > R(0) || (unfiltered && ltw != R(0))) {
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int m = 0; m < 3; ++m) c[a][m] = isq2 * (U[m][i] * hh[j][a] - U[m][j] * hh[i][a]);
       rank1_update(rec, c, vol * ltw);
     }
-    if (lfl > R(0)) {
+    if (lfl > R(0) || (unfiltered && lfl != R(0))) {
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -701,8 +705,8 @@ __global__ void __launch_bounds__(256) k_element(const Tile* tiles, int ntiles, 
     sym_eig3(As, Qs, ws);
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
-      if (E.hess_proj) ws[m] = fabs(ws[m]);
-      if (ws[m] > R(0)) {
+      if (emode == 1) ws[m] = fabs(ws[m]);
+      if (ws[m] > R(0) || (unfiltered && ws[m] != R(0))) {
         R c[4][3];
 #pragma unroll
         for (int a = 0; a < 4; ++a)
@@ -757,7 +761,7 @@ __global__ void k_barrier(const Tile* tiles, int ntiles, const EnvDesc* envs) {
   double x[3];
   load3(E.xn, vi, x);
   const double kA = E.kappa * E.cand_area[k];
-  double g[3] = {0, 0, 0}, H[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  double g[3] = {0, 0, 0}, H[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, Hn[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
   for (int m = 0; m < P->n_ind; ++m) {
     double phi, n[3], Hp[3][3];
     sdf_world(P->ind[m], x, phi, n, Hp, true);
@@ -766,11 +770,20 @@ __global__ void k_barrier(const Tile* tiles, int ntiles, const EnvDesc* envs) {
       const double b1 = bar1(s), b2 = bar2(s);
       for (int i = 0; i < 3; ++i) {
         g[i] += kA * b1 * n[i];
-        for (int j = 0; j < 3; ++j) H[i][j] += kA * (b2 / E.dhat * n[i] * n[j] + b1 * Hp[i][j]);
+        for (int j = 0; j < 3; ++j) {
+          H[i][j] += kA * (b2 / E.dhat * n[i] * n[j] + b1 * Hp[i][j]);
+          Hn[i][j] += kA * b2 / E.dhat * n[i] * n[j];
+        }
       }
     }
   }
-  project_psd3(H);
+  const int bmode = (E.hess_proj >> 2) & 3;   // 0 clamp, 1 as is, 2 normal term only
+  if (bmode == 0) {
+    project_psd3(H);
+  } else if (bmode == 2) {
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) H[i][j] = Hn[i][j];
+  }
   for (int i = 0; i < 3; ++i) E.gb[3 * k + i] = g[i];
   double* hb = E.Hb + 6 * k;
   hb[0] = H[0][0]; hb[1] = H[0][1]; hb[2] = H[0][2]; hb[3] = H[1][1]; hb[4] = H[1][2]; hb[5] = H[2][2];
@@ -861,11 +874,14 @@ __global__ void k_asm_diag(const Tile* tiles, int ntiles, const EnvDesc* envs) {
       for (int q = 0; q < 3; ++q) A[3 * r + q] = (R)D[r][q];
     // preconditioner: inverse of the 3x3 diagonal block, or of its diagonal
     double P[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-    if (E.precond == TC_PRECOND_BLOCK_JACOBI) {
-      const double c00 = D[1][1] * D[2][2] - D[1][2] * D[2][1];
-      const double c01 = D[1][2] * D[2][0] - D[1][0] * D[2][2];
-      const double c02 = D[1][0] * D[2][1] - D[1][1] * D[2][0];
-      const double det = D[0][0] * c00 + D[0][1] * c01 + D[0][2] * c02;
+    const double c00 = D[1][1] * D[2][2] - D[1][2] * D[2][1];
+    const double c01 = D[1][2] * D[2][0] - D[1][0] * D[2][2];
+    const double c02 = D[1][0] * D[2][1] - D[1][1] * D[2][0];
+    const double det = D[0][0] * c00 + D[0][1] * c01 + D[0][2] * c02;
+    // the block must be positive definite (leading minors) to serve as a CG
+    // preconditioner; otherwise fall back to the absolute diagonal
+    const bool spd = D[0][0] > 0 && D[0][0] * D[1][1] - D[0][1] * D[1][0] > 0 && det > 0;
+    if (E.precond == TC_PRECOND_BLOCK_JACOBI && spd) {
       const double id = 1.0 / det;
       P[0][0] = c00 * id;
       P[0][1] = (D[0][2] * D[2][1] - D[0][1] * D[2][2]) * id;
@@ -875,7 +891,7 @@ __global__ void k_asm_diag(const Tile* tiles, int ntiles, const EnvDesc* envs) {
       P[2][2] = (D[0][0] * D[1][1] - D[0][1] * D[1][0]) * id;
       P[1][0] = P[0][1]; P[2][0] = P[0][2]; P[2][1] = P[1][2];
     } else {
-      for (int r = 0; r < 3; ++r) P[r][r] = 1.0 / D[r][r];
+      for (int r = 0; r < 3; ++r) P[r][r] = 1.0 / fmax(fabs(D[r][r]), 1e-300);
     }
     R* Pi = (R*)E.Pinv + 6 * i;
     Pi[0] = (R)P[0][0]; Pi[1] = (R)P[0][1]; Pi[2] = (R)P[0][2];
@@ -967,6 +983,7 @@ __global__ void k_env_newton_begin(const EnvDesc* envs, int n) {
   S->cg_done = 0;
   S->cg_iters = 0;
   S->breakdown = 0;
+  S->true_hess = S->true_hess && !S->no_true_hess;
   S->it[0] = -1;
   S->it[1] = -1;
   S->rzp[0] = S->rzp[1] = 0.0;
@@ -994,16 +1011,21 @@ __global__ void __launch_bounds__(1024) k_cg_spmv(const Tile* tiles, int ntiles,
   double tol2 = S->cg_tol2;
   if (it == 0) {
     // forcing term of this Newton iteration (every block computes the same)
-    double eta = E.cg_rel_tol;
+    double eta = S->force_tight ? fmin(E.cg_conv_tol, E.cg_rel_tol) : E.cg_rel_tol;
     if (E.cg_forcing && !S->force_tight) {
       if (S->rz0_prev > 0.0) {
-        eta = 0.9 * rz / S->rz0_prev;          // 0.9 (|g_k| / |g_k-1|)^2
-        const double safe = 0.9 * S->eta_prev * S->eta_prev;
-        if (safe > 0.1) eta = fmax(eta, safe);
+        const double r2 = rz / S->rz0_prev;      // (|g_k| / |g_k-1|)^2, preconditioned norms
+        if (r2 < 0.25) {
+          eta = 0.9 * r2;                        // fast progress: Eisenstat-Walker choice 2
+          const double safe = 0.9 * S->eta_prev * S->eta_prev;
+          if (safe > 0.1) eta = fmax(eta, safe);
+        } else {
+          eta = 0.25 * S->eta_prev;              // slow progress: solve more accurately
+        }
       } else {
-        eta = 0.5;
+        eta = E.cg_eta_max;
       }
-      eta = fmin(0.5, fmax(eta, E.cg_rel_tol));
+      eta = fmin(E.cg_eta_max, fmax(eta, E.cg_rel_tol));
     }
     tol2 = eta * eta;
   }
@@ -1069,16 +1091,21 @@ __global__ void __launch_bounds__(1024) k_cg_spmv_vec(const Tile* tiles, int nti
   const double rz0 = it == 0 ? rz : S->rz0;
   double tol2 = S->cg_tol2;
   if (it == 0) {
-    double eta = E.cg_rel_tol;
+    double eta = S->force_tight ? fmin(E.cg_conv_tol, E.cg_rel_tol) : E.cg_rel_tol;
     if (E.cg_forcing && !S->force_tight) {
       if (S->rz0_prev > 0.0) {
-        eta = 0.9 * rz / S->rz0_prev;
-        const double safe = 0.9 * S->eta_prev * S->eta_prev;
-        if (safe > 0.1) eta = fmax(eta, safe);
+        const double r2 = rz / S->rz0_prev;      // (|g_k| / |g_k-1|)^2, preconditioned norms
+        if (r2 < 0.25) {
+          eta = 0.9 * r2;                        // fast progress: Eisenstat-Walker choice 2
+          const double safe = 0.9 * S->eta_prev * S->eta_prev;
+          if (safe > 0.1) eta = fmax(eta, safe);
+        } else {
+          eta = 0.25 * S->eta_prev;              // slow progress: solve more accurately
+        }
       } else {
-        eta = 0.5;
+        eta = E.cg_eta_max;
       }
-      eta = fmin(0.5, fmax(eta, E.cg_rel_tol));
+      eta = fmin(E.cg_eta_max, fmax(eta, E.cg_rel_tol));
     }
     tol2 = eta * eta;
   }
@@ -1212,8 +1239,10 @@ __global__ void k_newton_dir(const Tile* tiles, int ntiles, const EnvDesc* envs)
 
 // Largest safe step per contact vertex.  Convex indenters: phi(x + a p) >=
 // phi(x) + a grad(phi).p, so only approach (grad.p < 0) limits the step,
-// a <= 0.9 phi / (-grad.p).  Other shapes use the 1-Lipschitz bound
-// a <= 0.9 phi / |p|.  Either keeps phi > 0.1 phi(x).
+// a <= 0.9 phi / (-grad.p).  The textured plate has a global curvature
+// bound, which gives a quadratic lower model of phi along the step.  The
+// torus advances conservatively with the 1-Lipschitz bound (at most 8
+// moves).  Each keeps phi >= 0.1 phi(x).
 template <typename R>
 __global__ void k_filter(const Tile* tiles, int ntiles, const EnvDesc* envs) {
   __shared__ double sh[16];
@@ -1237,11 +1266,30 @@ __global__ void k_filter(const Tile* tiles, int ntiles, const EnvDesc* envs) {
         double phi, g[3];
         sdf_world(P->ind[m], x, phi, g, H, false);
         double a = INFINITY;
+        const double gp = g[0] * p[0] + g[1] * p[1] + g[2] * p[2];
         if (convex_shape(P->ind[m].shape)) {
-          const double gp = g[0] * p[0] + g[1] * p[1] + g[2] * p[2];
           if (gp < 0) a = 0.9 * phi / (-gp);
+        } else if (P->ind[m].shape == TC_TEXTURE) {
+          // |hess phi| <= K = k^2 A / c everywhere, so phi(x + a p) >= phi +
+          // a g.p - K a^2 |p|^2 / 2; largest a keeping that >= 0.1 phi
+          const double A = P->ind[m].prm[0], kk = 2.0 * M_PI / P->ind[m].prm[1];
+          const double K = kk * kk * A / sqrt(1.0 + (kk * A) * (kk * A));
+          const double qa = K * pn * pn;
+          a = (gp + sqrt(gp * gp + 1.8 * qa * phi)) / qa;
         } else {
-          a = 0.9 * phi / pn;
+          // conservative advancement with the 1-Lipschitz bound: each move
+          // of 0.9 (phi - target) / |p| keeps phi >= target = 0.1 phi(x)
+          const double target = 0.1 * phi;
+          double acc = 0.0, dcur = phi;
+          for (int r = 0; r < 8 && acc < 1.0; ++r) {
+            const double da = 0.9 * (dcur - target) / pn;
+            if (!(da > 0.0)) break;
+            acc = fmin(1.0, acc + da);
+            const double y[3] = {x[0] + acc * p[0], x[1] + acc * p[1], x[2] + acc * p[2]};
+            double gy[3];
+            sdf_world(P->ind[m], y, dcur, gy, H, false);
+          }
+          a = acc;
         }
         amax = fmin(amax, a);
       }
@@ -1276,9 +1324,18 @@ __global__ void k_env_dir(const EnvDesc* envs, int n) {
     S->ls_alpha = fmin(1.0, am);
     // a direction from a loose CG solve can be short only because the soft
     // modes are unresolved: convergence is judged on a floor-tolerance solve
-    const bool tight = S->cg_tol2 <= E.cg_rel_tol * E.cg_rel_tol * (1.0 + 1e-12) || S->cg_iters >= E.max_cg;
-    S->dir_conv = dm <= E.tol_abs && tight;
-    S->force_tight = dm <= E.tol_abs && !tight;
+    const bool tight = S->cg_tol2 <= E.cg_conv_tol * E.cg_conv_tol * (1.0 + 1e-12) || S->cg_iters >= E.max_cg;
+    if (S->breakdown && S->true_hess) {
+      // negative curvature met with the unfiltered Hessian: keep the CG
+      // iterate (a descent direction, possibly zero) but judge nothing on it
+      // and use filtered Hessians for the rest of the step
+      S->no_true_hess = 1;
+      S->true_hess = 0;
+      S->dir_conv = 0;
+    } else {
+      S->dir_conv = dm <= E.tol_abs && tight;
+      S->force_tight = dm <= E.tol_abs && !tight;
+    }
     S->ls_done = S->dir_conv;
     S->apply = S->dir_conv;
     S->cg_total += S->cg_iters;
@@ -1421,6 +1478,7 @@ __global__ void k_update(const Tile* tiles, int ntiles, const EnvDesc* envs) {
   if (tl.tile == 0 && threadIdx.x == 0) {
     S->newton_iters += 1;
     S->ls_total += S->ls_halv;
+    if ((E.hess_proj & 3) == 2 && S->apply && S->ls_alpha == 1.0 && !S->no_true_hess) S->true_hess = 1;
     if (!S->dir_conv) S->E_cur = S->E_next;
     if (S->dir_conv) {
       S->newton_done = 1;

@@ -133,9 +133,10 @@ struct BatchPlan {
   int lpr = 0;                       // SpMV lanes per row
   int off[NCLS] = {0}, cnt[NCLS] = {0};
   std::vector<EnvDesc> h_desc;
-  Tile* d_ctiles = nullptr;          // compacted SPMV + VERT tiles of CG tails
-  Tile* h_ctiles = nullptr;          // pinned staging
+  Tile* d_ctiles = nullptr;          // ring of compacted tile lists
+  Tile* h_ctiles = nullptr;          // pinned staging of the ring
   int ctiles_cap = 0;
+  int ctiles_off = 0;                // reset at every host sync
   hipGraphExec_t cg_exec = nullptr;
   hipGraph_t cg_graph = nullptr;
   int graph_M = 0;
@@ -146,6 +147,7 @@ struct BatchPlan {
 tc_status run_batch(tc_context* ctx, int n, tc_pad* const* pads, const int32_t* n_ind,
                     const tc_indenter* ind, tc_step_stats* stats, int mode);
 
+tc_status newton_direction(tc_pad* pad, int n_ind, const tc_indenter* ind, double* dir, double* grad);
 tc_status ensure_scratch(tc_pad* pad);
 void release_scratch(tc_pad* pad);
 tc_status pool_reserve(tc_context* ctx, SlotPool& p, int cap);
@@ -171,9 +173,17 @@ struct Runner {
   void launch(KernelId k, int cls, int parity = 0, int mode = 0);
   tc_status readback();
   bool any(bool (*pred)(const EnvState&)) const;
-  tc_status cg_chunk(int M);
-  tc_status cg_chunk_compact(int M, int n_spmv, int n_vert);
-  void launch_tiles(KernelId k, const Tile* tiles, int ntiles, int block, int parity);
+  // tile lists of the kernel classes restricted to the pads matching a
+  // predicate (the plan's own lists when every pad matches)
+  struct View {
+    const Tile* t[8];
+    int c[8];
+    bool full;
+  };
+  View view(bool (*pred)(const EnvState&));
+  void launch_v(KernelId k, const View& v, int cls, int parity = 0, int mode = 0);
+  tc_status cg_chunk(int M, const View& v);
+  void launch_tiles(KernelId k, const Tile* tiles, int ntiles, int block, int parity, int mode = 0);
   tc_status tick(bool init);
 
   static bool is_run(const EnvState& s) { return s.phase == PH_RUN && s.status == TC_OK; }
@@ -181,6 +191,8 @@ struct Runner {
   static bool ls_pending(const EnvState& s) { return is_run(s) && !s.ls_done; }
   static bool is_finish(const EnvState& s) { return s.phase == PH_FINISH; }
   static bool not_done(const EnvState& s) { return s.phase != PH_DONE && s.phase != PH_IDLE; }
+  static bool is_init(const EnvState& s) { return s.phase == PH_INIT && s.status == TC_OK; }
+  static bool init_or_run(const EnvState& s) { return is_init(s) || is_run(s); }
 };
 
 }  // namespace tc

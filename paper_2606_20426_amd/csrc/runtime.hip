@@ -350,7 +350,7 @@ tc_status build_plan(tc_context* ctx, int n, tc_pad* const* pads, const int* slo
   add_cls(BatchPlan::SPMV, [](const EnvDesc& E) { return E.n_spt; });
   TC_HIP(hipMalloc(&P->d_desc, sizeof(EnvDesc) * n));
   TC_HIP(hipMalloc(&P->d_tiles, sizeof(Tile) * std::max<size_t>(tiles.size(), 1)));
-  P->ctiles_cap = P->cnt[BatchPlan::SPMV] + P->cnt[BatchPlan::VERT];
+  P->ctiles_cap = 4 * (int)tiles.size() + 64;
   TC_HIP(hipMalloc(&P->d_ctiles, sizeof(Tile) * std::max(P->ctiles_cap, 1)));
   TC_HIP(hipHostMalloc(&P->h_ctiles, sizeof(Tile) * std::max(P->ctiles_cap, 1), hipHostMallocDefault));
   TC_HIP(hipMemcpyAsync(P->d_desc, P->h_desc.data(), sizeof(EnvDesc) * n, hipMemcpyHostToDevice, ctx->stream));
@@ -397,11 +397,12 @@ void Runner::launch(KernelId k, int cls, int parity, int mode) {
   }
 }
 
-void Runner::launch_tiles(KernelId k, const Tile* tiles, int ntiles, int block, int parity) {
+void Runner::launch_tiles(KernelId k, const Tile* tiles, int ntiles, int block, int parity, int mode) {
   LaunchArgs a;
   a.envs = P->d_desc;
   a.n_env = n;
   a.parity = parity;
+  a.mode = mode;
   a.stream = ctx->stream;
   a.tiles = tiles;
   a.ntiles = ntiles;
@@ -418,21 +419,54 @@ void Runner::launch_tiles(KernelId k, const Tile* tiles, int ntiles, int block, 
   }
 }
 
-// CG iterations over the tiles of the pads still iterating only (tails of
-// uneven batches); the compacted lists were uploaded to d_ctiles.
-tc_status Runner::cg_chunk_compact(int M, int n_spmv, int n_vert) {
-  const int bs = P->lpr ? P->BS : P->BV;
-  for (int k = 0; k < M; ++k) {
-    launch_tiles(KernelId::cg_spmv, P->d_ctiles, n_spmv, bs, k & 1);
-    launch_tiles(KernelId::cg_update, P->d_ctiles + n_spmv, n_vert, P->BV, k & 1);
+Runner::View Runner::view(bool (*pred)(const EnvState&)) {
+  View v{};
+  int nm = 0;
+  for (int i = 0; i < n; ++i) nm += pred(state(i));
+  v.full = nm == n;
+  if (v.full) {
+    for (int c = 0; c < BatchPlan::NCLS; ++c) {
+      v.t[c] = P->d_tiles + P->off[c];
+      v.c[c] = P->cnt[c];
+    }
+    return v;
   }
-  return TC_OK;
+  // compacted lists go to the next free part of the ring; the ring is only
+  // rewritten after a host sync, when every earlier copy and launch is done
+  for (int c = 0; c < BatchPlan::NCLS; ++c) {
+    const int start = P->ctiles_off;
+    int k = start;
+    for (int i = 0; i < n; ++i) {
+      if (!pred(state(i))) continue;
+      const EnvDesc& E = P->h_desc[i];
+      const int cnt = c == BatchPlan::VERT ? E.n_vt : c == BatchPlan::TET ? E.n_tt : c == BatchPlan::CAND ? E.n_ct
+                    : c == BatchPlan::SURF ? E.n_st : c == BatchPlan::ASM ? E.n_at
+                    : c == BatchPlan::ENERGY ? E.n_te + E.n_vt + E.n_ct : E.n_spt;
+      if (k + cnt > P->ctiles_cap) break;   // ring full: cannot happen (4x capacity)
+      for (int t = 0; t < cnt; ++t) P->h_ctiles[k++] = Tile{i, t};
+    }
+    v.t[c] = P->d_ctiles + start;
+    v.c[c] = k - start;
+    P->ctiles_off = k;
+  }
+  const int base = (int)(v.t[0] - P->d_ctiles);
+  const int len = P->ctiles_off - base;
+  if (len > 0)
+    (void)hipMemcpyAsync(P->d_ctiles + base, P->h_ctiles + base, sizeof(Tile) * len, hipMemcpyHostToDevice,
+                         ctx->stream);
+  return v;
+}
+
+void Runner::launch_v(KernelId k, const View& v, int cls, int parity, int mode) {
+  const int block = cls == BatchPlan::TET ? P->BT : (cls == BatchPlan::SPMV && P->lpr) ? P->BS : P->BV;
+  launch_tiles(k, v.t[cls], v.c[cls], block, parity, mode);
 }
 
 tc_status Runner::readback() {
   TC_HIP(hipGetLastError());
   TC_HIP(hipMemcpyAsync(pool->h_state, pool->d_state, sizeof(EnvState) * span, hipMemcpyDeviceToHost, ctx->stream));
   TC_HIP(hipStreamSynchronize(ctx->stream));
+  P->ctiles_off = 0;
   if (ctx->timing) resolve_timing(ctx);
   return TC_OK;
 }
@@ -443,15 +477,15 @@ bool Runner::any(bool (*pred)(const EnvState&)) const {
   return false;
 }
 
-tc_status Runner::cg_chunk(int M) {
-  if (ctx->use_graphs && !ctx->timing) {
+tc_status Runner::cg_chunk(int M, const View& v) {
+  if (v.full && ctx->use_graphs && !ctx->timing) {
     if (!P->cg_exec || P->graph_M != M) {
       if (P->cg_exec) { (void)hipGraphExecDestroy(P->cg_exec); P->cg_exec = nullptr; }
       if (P->cg_graph) { (void)hipGraphDestroy(P->cg_graph); P->cg_graph = nullptr; }
       TC_HIP(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
       for (int k = 0; k < M; ++k) {
-        launch(KernelId::cg_spmv, BatchPlan::SPMV, k & 1);
-        launch(KernelId::cg_update, BatchPlan::VERT, k & 1);
+        launch_v(KernelId::cg_spmv, v, BatchPlan::SPMV, k & 1);
+        launch_v(KernelId::cg_update, v, BatchPlan::VERT, k & 1);
       }
       TC_HIP(hipStreamEndCapture(ctx->stream, &P->cg_graph));
       TC_HIP(hipGraphInstantiate(&P->cg_exec, P->cg_graph, nullptr, nullptr, 0));
@@ -460,82 +494,73 @@ tc_status Runner::cg_chunk(int M) {
     TC_HIP(hipGraphLaunch(P->cg_exec, ctx->stream));
   } else {
     for (int k = 0; k < M; ++k) {
-      launch(KernelId::cg_spmv, BatchPlan::SPMV, k & 1);
-      launch(KernelId::cg_update, BatchPlan::VERT, k & 1);
+      launch_v(KernelId::cg_spmv, v, BatchPlan::SPMV, k & 1);
+      launch_v(KernelId::cg_update, v, BatchPlan::VERT, k & 1);
     }
   }
   return TC_OK;
 }
 
-// One Newton iteration for every pad in PH_RUN (init first for PH_INIT pads,
-// extraction for pads that end up in PH_FINISH).
+// One Newton iteration for every pad in PH_RUN (pads in PH_INIT are
+// initialised first and join it; pads that end up in PH_FINISH get their
+// extraction).  Launches cover only the tiles of the pads concerned.
 tc_status Runner::tick(bool init) {
   tc_status st;
+  static const bool debug = std::getenv("TC_DEBUG") != nullptr;
   if (init) {
-    launch(KernelId::predict, BatchPlan::VERT);
-    launch(KernelId::project, BatchPlan::CAND);
-    launch(KernelId::energy, BatchPlan::ENERGY, 0, 0);
+    const View vi = view(is_init);
+    launch_v(KernelId::predict, vi, BatchPlan::VERT);
+    launch_v(KernelId::project, vi, BatchPlan::CAND);
+    launch_v(KernelId::energy, vi, BatchPlan::ENERGY, 0, 0);
     launch(KernelId::env_ls, BatchPlan::NCLS, 0, 0);
-    if ((st = readback())) return st;
   }
-  if (any(is_run)) {
+  if (any(init ? init_or_run : is_run)) {
+    const View v = view(init ? init_or_run : is_run);
     launch(KernelId::newton_begin, BatchPlan::NCLS);
-    launch(KernelId::element, BatchPlan::TET);
-    launch(KernelId::barrier, BatchPlan::CAND);
-    launch(KernelId::asm_diag, BatchPlan::VERT);
-    launch(KernelId::asm_off, BatchPlan::ASM);
+    launch_v(KernelId::element, v, BatchPlan::TET);
+    launch_v(KernelId::barrier, v, BatchPlan::CAND);
+    launch_v(KernelId::asm_diag, v, BatchPlan::VERT);
+    launch_v(KernelId::asm_off, v, BatchPlan::ASM);
     int max_cg = 0;
     for (int i = 0; i < n; ++i) max_cg = std::max(max_cg, P->pads[i]->params.max_cg);
     const int M = std::max(2, ctx->cg_per_replay & ~1);
-    int n_full = 0;
-    for (int i = 0; i < n; ++i) n_full += is_run(state(i));
-    int n_cur = n_full, n_spmv = 0, n_vert = 0;
-    bool compact = false;
+    View vc = v;
+    int n_cur = -1;
     for (int done = 0; done <= max_cg + M; done += M) {
-      if (compact) {
-        if ((st = cg_chunk_compact(M, n_spmv, n_vert))) return st;
-      } else if ((st = cg_chunk(M))) {
-        return st;
-      }
+      if ((st = cg_chunk(M, vc))) return st;
       if ((st = readback())) return st;
       int n_act = 0;
       for (int i = 0; i < n; ++i) n_act += cg_pending(state(i));
       if (n_act == 0) break;
-      if (n_act * 4 <= n_cur * 3 && n > 1) {
-        // shrink the launch to the pads still iterating
-        int k = 0;
-        const Tile* all = nullptr;
-        std::vector<Tile> host;
-        (void)all;
-        n_spmv = n_vert = 0;
-        for (int i = 0; i < n; ++i)
-          if (cg_pending(state(i)))
-            for (int t = 0; t < P->h_desc[i].n_spt; ++t) P->h_ctiles[k++] = Tile{i, t};
-        n_spmv = k;
-        for (int i = 0; i < n; ++i)
-          if (cg_pending(state(i)))
-            for (int t = 0; t < P->h_desc[i].n_vt; ++t) P->h_ctiles[k++] = Tile{i, t};
-        n_vert = k - n_spmv;
-        TC_HIP(hipMemcpyAsync(P->d_ctiles, P->h_ctiles, sizeof(Tile) * k, hipMemcpyHostToDevice, ctx->stream));
-        compact = true;
+      if (n_cur < 0) {
+        n_cur = 0;
+        for (int i = 0; i < n; ++i) n_cur += is_run(state(i));
+      }
+      if (n_act * 4 <= n_cur * 3 || !vc.full) {
+        vc = view(cg_pending);   // shrink the launches to the pads still iterating
         n_cur = n_act;
       }
     }
-    launch(KernelId::newton_dir, BatchPlan::VERT);
-    launch(KernelId::filter, BatchPlan::CAND);
+    // the views are rebuilt after the sync: pads may have failed meanwhile
+    const View vr = view(is_run);
+    launch_v(KernelId::newton_dir, vr, BatchPlan::VERT);
+    launch_v(KernelId::filter, vr, BatchPlan::CAND);
     launch(KernelId::env_dir, BatchPlan::NCLS);
-    if ((st = readback())) return st;
-    static const bool debug = std::getenv("TC_DEBUG") != nullptr;
-    if (debug)
+    if (debug) {
+      if ((st = readback())) return st;
       for (int i = 0; i < n; ++i) {
         const EnvState& S = state(i);
         std::fprintf(stderr, "[tc] pad %d newton %d cg %d rz0 %.3e |d| %.3e g.d %.3e amax %.3e E %.12e conv %d\n", i,
                      S.newton_iters, S.cg_iters, S.rz0, S.final_step_inf, S.gTd, S.alpha_max, S.E_cur, S.dir_conv);
       }
+    }
     int max_h = 0;
     for (int i = 0; i < n; ++i) max_h = std::max(max_h, P->pads[i]->params.max_halvings);
-    for (int r = 0; r <= max_h + 1 && any(ls_pending); ++r) {
-      launch(KernelId::energy, BatchPlan::ENERGY, 0, 1);
+    // first line-search round without waiting for the direction's flags
+    // (pads that converged skip it on the device)
+    View vl = debug ? view(ls_pending) : vr;
+    for (int r = 0; r <= max_h + 1; ++r) {
+      launch_v(KernelId::energy, vl, BatchPlan::ENERGY, 0, 1);
       launch(KernelId::env_ls, BatchPlan::NCLS, 0, 1);
       if ((st = readback())) return st;
       if (debug)
@@ -544,15 +569,21 @@ tc_status Runner::tick(bool init) {
           std::fprintf(stderr, "[tc]   ls pad %d done %d halv %d alpha %.3e E_next %.12e status %d\n", i, S.ls_done,
                        S.ls_halv, S.ls_alpha, S.E_next, S.status);
         }
+      if (!any(ls_pending)) break;
+      vl = view(ls_pending);
     }
-    launch(KernelId::update, BatchPlan::VERT);
+    const View vu = view(is_run);
+    launch_v(KernelId::update, vu, BatchPlan::VERT);
+    if ((st = readback())) return st;
+  } else if (init) {
     if ((st = readback())) return st;
   }
   if (any(is_finish)) {
-    launch(KernelId::sigma, BatchPlan::TET);
-    launch(KernelId::traction, BatchPlan::SURF);
-    launch(KernelId::contact, BatchPlan::CAND);
-    launch(KernelId::commit, BatchPlan::VERT);
+    const View vf = view(is_finish);
+    launch_v(KernelId::sigma, vf, BatchPlan::TET);
+    launch_v(KernelId::traction, vf, BatchPlan::SURF);
+    launch_v(KernelId::contact, vf, BatchPlan::CAND);
+    launch_v(KernelId::commit, vf, BatchPlan::VERT);
     launch(KernelId::env_extract, BatchPlan::NCLS);
     if ((st = readback())) return st;
   }
@@ -667,6 +698,61 @@ tc_status run_batch(tc_context* ctx, int n, tc_pad* const* pads, const int32_t* 
   return first;
 }
 
+// One Newton direction at the committed positions (inspection).
+tc_status newton_direction(tc_pad* pad, int n_ind, const tc_indenter* ind, double* dir, double* grad) {
+  tc_context* ctx = pad->ctx;
+  std::string err;
+  tc_status s = validate_indenters(n_ind, ind, err);
+  if (s) return set_error(s, err);
+  if (!dir) return set_error(TC_E_INVALID_ARG, "dir is null");
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  TC_HIP(hipSetDevice(ctx->device));
+  if ((s = ensure_scratch(pad))) return s;
+  SlotPool& pool = ctx->pool;
+  if ((s = pool_reserve(ctx, pool, 1))) return s;
+  int slot = 0;
+  tc_pad* pads[1] = {pad};
+  if (!plan_matches(ctx->plan.get(), ctx, 1, pads, &slot, pool)) {
+    ctx->plan.reset();
+    if ((s = build_plan(ctx, 1, pads, &slot, pool, ctx->plan))) return s;
+  }
+  BatchPlan* P = ctx->plan.get();
+  init_state(pool.h_state[0], pool.h_pose[0], 0, n_ind, ind);
+  pool.h_state[0].force_tight = 1;   // CG straight to the convergence tolerance
+  TC_HIP(hipMemcpyAsync(pool.d_state, pool.h_state, sizeof(EnvState), hipMemcpyHostToDevice, ctx->stream));
+  TC_HIP(hipMemcpyAsync(pool.d_pose, pool.h_pose, sizeof(EnvPose), hipMemcpyHostToDevice, ctx->stream));
+  Runner run{ctx, P, 1, &pool, 1};
+  const Runner::View v = run.view(Runner::not_done);
+  run.launch_v(KernelId::predict, v, BatchPlan::VERT);
+  run.launch_v(KernelId::energy, v, BatchPlan::ENERGY, 0, 0);
+  run.launch(KernelId::env_ls, BatchPlan::NCLS, 0, 0);
+  run.launch(KernelId::newton_begin, BatchPlan::NCLS);
+  run.launch_v(KernelId::element, v, BatchPlan::TET);
+  run.launch_v(KernelId::barrier, v, BatchPlan::CAND);
+  run.launch_v(KernelId::asm_diag, v, BatchPlan::VERT);
+  run.launch_v(KernelId::asm_off, v, BatchPlan::ASM);
+  const int M = std::max(2, ctx->cg_per_replay & ~1);
+  for (int done = 0; done <= pad->params.max_cg + M; done += M) {
+    for (int k = 0; k < M; ++k) {
+      run.launch_v(KernelId::cg_spmv, v, BatchPlan::SPMV, k & 1);
+      run.launch_v(KernelId::cg_update, v, BatchPlan::VERT, k & 1);
+    }
+    if ((s = run.readback())) return s;
+    if (pool.h_state[0].status != TC_OK) return set_error(pool.h_state[0].status, "probe failed");
+    if (pool.h_state[0].cg_done) break;
+  }
+  const size_t n3 = 3 * (size_t)pad->V;
+  if (pad->fp64) {
+    TC_HIP(hipMemcpy(dir, pad->desc.d, 8 * n3, hipMemcpyDeviceToHost));
+  } else {
+    std::vector<float> tmp(n3);
+    TC_HIP(hipMemcpy(tmp.data(), pad->desc.d, 4 * n3, hipMemcpyDeviceToHost));
+    for (size_t k = 0; k < n3; ++k) dir[k] = tmp[k];
+  }
+  if (grad) TC_HIP(hipMemcpy(grad, pad->desc.g, 8 * n3, hipMemcpyDeviceToHost));
+  return TC_OK;
+}
+
 }  // namespace tc
 
 // =================================================================== C ABI
@@ -775,6 +861,8 @@ tc_status tc_params_default(tc_params* out) {
   out->cg_forcing = 1;
   out->hess_proj = 0;
   out->init_guess = 0;
+  out->cg_conv_tol = 0.0;
+  out->cg_eta_max = 0.5;
   return TC_OK;
 }
 
@@ -1162,6 +1250,8 @@ tc_status tc_pad_set_params(tc_pad* pad, const tc_params* params) {
   E.cg_rel_tol = params->cg_rel_tol;
   E.cg_forcing = params->cg_forcing;
   E.hess_proj = params->hess_proj;
+  E.cg_conv_tol = params->cg_conv_tol > 0 ? params->cg_conv_tol : params->cg_rel_tol;
+  E.cg_eta_max = params->cg_eta_max;
   E.init_guess = params->init_guess;
   for (int c = 0; c < 3; ++c) E.gravity[c] = params->gravity[c];
   E.quasi_static = params->quasi_static;
@@ -1209,6 +1299,12 @@ tc_status tc_step_batch(tc_context* ctx, int32_t n, tc_pad* const* pads, const i
 tc_status tc_extract(tc_pad* pad, int32_t n_ind, const tc_indenter* ind) {
   if (!pad) return set_error(TC_E_INVALID_ARG, "pad is null");
   return guarded([&] { return run_batch(pad->ctx, 1, &pad, &n_ind, ind, nullptr, 1); });
+}
+
+tc_status tc_pad_newton_direction(tc_pad* pad, int32_t n_ind, const tc_indenter* ind, double* dir, double* grad) {
+  if (!pad) return set_error(TC_E_INVALID_ARG, "pad is null");
+  if (pad->busy.load()) return set_error(TC_E_BUSY, "pad has a request in flight on a server");
+  return guarded([&] { return newton_direction(pad, n_ind, ind, dir, grad); });
 }
 
 tc_status tc_field_info(const tc_pad* pad, int32_t field, int32_t* dtype, int64_t* count, int32_t* components) {

@@ -81,6 +81,8 @@ struct EnvState {
   int32_t cg_iters;
   int32_t breakdown;
   int32_t force_tight;     // next CG must reach the floor tolerance
+  int32_t true_hess;       // element Hessians unfiltered in this iteration
+  int32_t no_true_hess;    // a breakdown happened: filtered for the rest of the step
   double cg_tol2;
   double rz0_prev;         // r0.z0 of the previous Newton iteration (< 0: none)
   double eta_prev;
@@ -156,7 +158,7 @@ struct EnvDesc {
   // material table (Eq. 1) and parameters
   // cshift = lam (alpha - 1): mu for the rest-stable shift, 0 for alpha = 1
   double mu[MAX_MAT], lam[MAX_MAT], alpha[MAX_MAT], rho[MAX_MAT], cshift[MAX_MAT];
-  double h, dhat, kappa, tol_abs, noise, cg_rel_tol;
+  double h, dhat, kappa, tol_abs, noise, cg_rel_tol, cg_conv_tol, cg_eta_max;
   double gravity[3];
   int32_t quasi_static, max_cg, max_newton, max_halvings, precond, cg_forcing, hess_proj, init_guess;
 };
