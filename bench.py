@@ -22,6 +22,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# measured HBM traffic of the dominant kernel (rocprofv3 FETCH_SIZE and
+# WRITE_SIZE passes of this same command, scaled by a copy of known size);
+# used only while the kernel sources still hash to the recorded value
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "cg_spmv_batch60_pmc.md")
 
 
 def log(*a):
@@ -37,6 +41,40 @@ def build_workload(name):
     if name == "large1.2m":
         return [scenes.config5()], "24x24x5 mm pad, ~1.2M tets, 4-level refinement, sphere r=3 mm"
     raise SystemExit(f"unknown workload {name}")
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    or None when it is absent, for another workload or kernel, or older than
+    the kernel sources."""
+    try:
+        kv = {}
+        with open(TRAFFIC_SUMMARY) as fh:
+            for line in fh:
+                if line.startswith("- ") and ": " in line:
+                    k, v = line[2:].strip().split(": ", 1)
+                    kv[k] = v.strip("` ")
+        if kv.get("workload") != workload or kv.get("kernel") != kernel:
+            return None
+        from paper_2606_20426_amd.profiling import kernel_sources_hash
+        if kv.get("kernel_sources_sha256") != kernel_sources_hash():
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def copy_probe(mib):
+    """Device-to-device copies of a known size: the reference the counter
+    passes scale FETCH_SIZE / WRITE_SIZE by."""
+    import torch
+    n = mib * 2**20 // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(4):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
 
 
 def cpu_baseline(envs, budget_s=20.0):
@@ -73,13 +111,22 @@ def main():
     ap.add_argument("--precision", default="mixed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true")
-    ap.add_argument("--graphs", type=int, default=1)
+    ap.add_argument("--timing-stride", type=int, default=32,
+                    help="time every k-th launch of each kernel with events")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MiB",
+                    help="run 4 device copies of this size first (counter calibration)")
+    ap.add_argument("--graphs", type=int, default=0)
     ap.add_argument("--cg-block", type=int, default=0)
     ap.add_argument("--elem-block", type=int, default=0)
     ap.add_argument("--spmv-block", type=int, default=0)
     ap.add_argument("--autotune", action="store_true")
-    ap.add_argument("--cg-rel-tol", type=float, default=None)
-    ap.add_argument("--cg-forcing", type=int, default=None)
+    # solver settings of the timed run: adaptive CG forcing between 1e-3 and
+    # 0.1, element Hessians clamped, barrier Hessians unfiltered after the
+    # first full Newton step (same minimiser, fewer iterations)
+    ap.add_argument("--cg-rel-tol", type=float, default=1e-3)
+    ap.add_argument("--cg-eta-max", type=float, default=0.1)
+    ap.add_argument("--cg-forcing", type=int, default=1)
+    ap.add_argument("--hess-proj", type=int, default=12)
     ap.add_argument("--init-guess", type=int, default=None)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -91,22 +138,21 @@ def main():
     import torch
     import paper_2606_20426_amd as tc
 
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
     envs, desc = build_workload(args.workload)
     log(f"workload {args.workload}: {len(envs)} pads, {sum(e.pad.tets.shape[0] for e in envs)} tets")
     ctx = tc.Context(0)
     t0 = time.perf_counter()
     pads = []
-    extra = {}
-    if args.cg_rel_tol is not None:
-        extra["cg_rel_tol"] = args.cg_rel_tol
-    if args.cg_forcing is not None:
-        extra["cg_forcing"] = args.cg_forcing
+    extra = dict(cg_rel_tol=args.cg_rel_tol, cg_eta_max=args.cg_eta_max, cg_forcing=args.cg_forcing,
+                 hess_proj=args.hess_proj)
     if args.init_guess is not None:
         extra["init_guess"] = args.init_guess
     for e in envs:
         m = e.pad.material
         kw = dict(precision=args.precision, dt=e.params.dt, dhat=e.params.dhat, kappa=e.params.kappa,
-                  newton_tol=e.params.newton_tol, cg_rel_tol=e.params.cg_rel_tol)
+                  newton_tol=e.params.newton_tol)
         kw.update(extra)
         pads.append(tc.Pad(ctx, e.pad.X, e.pad.tets, dict(E=m.E, nu=m.nu, density=m.density),
                            tc.make_params(**kw)))
@@ -125,7 +171,7 @@ def main():
         log(f"warmup {s}: newton max {max(x.newton_iters for x in st)} cg sum {sum(x.cg_iters for x in st)} "
             f"ms {st[0].ms:.1f}")
     if not args.no_timing:
-        ctx.set_timing(True)
+        ctx.set_timing(True, stride=args.timing_stride)
         ctx.reset_timing()
     torch.cuda.synchronize()
     lat = []
@@ -150,8 +196,10 @@ def main():
         avg_ms, launches, bpl = timers[k]
         achieved = bpl / (avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "kernel": k, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "avg_launch_ms": avg_ms, "launches": launches, "bytes_per_launch": bpl}
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(args.workload, k),
+                "avg_launch_ms": avg_ms, "launches": launches, "bytes_per_launch": bpl,
+                "timing_stride": args.timing_stride}
         log("kernel timers (avg ms, launches, GB/s):")
         for name, (a, n, b) in sorted(timers.items(), key=lambda kv: -kv[1][0] * kv[1][1]):
             log(f"  {name:14s} {a:9.4f} {n:7d} {b / max(a, 1e-12) / 1e6:9.1f}")

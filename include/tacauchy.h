@@ -168,7 +168,9 @@ typedef struct {
                            unfiltered Hessian (CG stops at negative
                            curvature; a breakdown reverts to clamping for the
                            rest of the step).  Bits 2-3, barrier 3x3: 0 clamp,
-                           1 unfiltered, 2 normal term only. */
+                           1 unfiltered, 2 normal term only, 3 clamp until a
+                           full Newton step is accepted, then unfiltered (with
+                           the same safeguards). */
   int32_t init_guess;   /* Newton start: 0 = x_t, 1 = x_t + dt v_t (free
                            components); either is then made feasible */
   double cg_conv_tol;   /* CG tolerance of the direction on which Newton
@@ -254,7 +256,13 @@ tc_status tc_context_destroy(tc_context* ctx);
 tc_status tc_context_memory(const tc_context* ctx, uint64_t* used, uint64_t* budget);
 
 /* Per-kernel timing with HIP events on the context stream (for roofline
- * reporting).  names/avg_ms/launches are filled for up to cap kernels. */
+ * reporting).  enable = 0 off; k >= 1: every k-th launch of each kernel is
+ * bracketed by a pair of events (k = 1 times every launch; a larger k keeps
+ * the events' own cost out of the run).  tc_context_timing fills, for up to
+ * cap kernels, the average duration of the timed launches, the number of
+ * launches made while timing was on, and the algorithmic bytes per launch
+ * (model of each kernel's compulsory HBM traffic, averaged over all those
+ * launches). */
 #define TC_TIMER_NAME_LEN 32
 tc_status tc_context_set_timing(tc_context* ctx, int32_t enable);
 tc_status tc_context_timing(tc_context* ctx, int32_t cap, int32_t* n,
@@ -270,7 +278,9 @@ tc_status tc_autotune(tc_context* ctx, int32_t n, tc_pad* const* pads,
                       const int32_t* n_ind, const tc_indenter* ind, int32_t* chosen);
 /* Force a launch shape: block sizes of the vertex-row kernels (64..1024),
  * the element kernels (64..256) and the SpMV (64..1024), all multiples of 64;
- * CG iterations per graph replay (even, >= 2); use_graphs 0/1, -1 unchanged.
+ * CG iterations between host checks of convergence (even, >= 2; default 16);
+ * use_graphs 1 replays those iterations of a whole batch as one captured HIP
+ * graph, 0 (default) launches them directly, -1 leaves it unchanged.
  * 0 leaves a value unchanged. */
 tc_status tc_set_launch(tc_context* ctx, int32_t cg_block, int32_t elem_block, int32_t spmv_block,
                         int32_t cg_per_replay, int32_t use_graphs);

@@ -167,8 +167,10 @@ class Context:
         check(self.lib.tc_context_memory(self.h, C.byref(u), C.byref(b)))
         return u.value, b.value
 
-    def set_timing(self, on: bool):
-        check(self.lib.tc_context_set_timing(self.h, int(bool(on))))
+    def set_timing(self, on: bool, stride: int = 1):
+        """Per-kernel event timing; with stride k only every k-th launch of
+        each kernel is bracketed by events."""
+        check(self.lib.tc_context_set_timing(self.h, int(stride) if on else 0))
 
     def reset_timing(self):
         check(self.lib.tc_context_reset_timing(self.h))

@@ -777,7 +777,10 @@ __global__ void k_barrier(const Tile* tiles, int ntiles, const EnvDesc* envs) {
       }
     }
   }
-  const int bmode = (E.hess_proj >> 2) & 3;   // 0 clamp, 1 as is, 2 normal term only
+  // 0 clamp, 1 as is, 2 normal term only, 3 clamp until a full Newton step
+  // is accepted, then as is
+  int bmode = (E.hess_proj >> 2) & 3;
+  if (bmode == 3) bmode = E.st->true_hess ? 1 : 0;
   if (bmode == 0) {
     project_psd3(H);
   } else if (bmode == 2) {
@@ -1478,7 +1481,8 @@ __global__ void k_update(const Tile* tiles, int ntiles, const EnvDesc* envs) {
   if (tl.tile == 0 && threadIdx.x == 0) {
     S->newton_iters += 1;
     S->ls_total += S->ls_halv;
-    if ((E.hess_proj & 3) == 2 && S->apply && S->ls_alpha == 1.0 && !S->no_true_hess) S->true_hess = 1;
+    const bool adaptive = (E.hess_proj & 3) == 2 || ((E.hess_proj >> 2) & 3) == 3;
+    if (adaptive && S->apply && S->ls_alpha == 1.0 && !S->no_true_hess) S->true_hess = 1;
     if (!S->dir_conv) S->E_cur = S->E_next;
     if (S->dir_conv) {
       S->newton_done = 1;

@@ -42,9 +42,10 @@ class Arena {
 };
 
 struct KernelTimer {
-  double ms = 0.0;
-  int64_t launches = 0;
-  double bytes = 0.0;
+  double ms = 0.0;          // summed over the timed launches
+  int64_t timed = 0;        // launches bracketed by events
+  int64_t launches = 0;     // every launch while timing was on
+  double bytes = 0.0;       // algorithmic bytes of all those launches
 };
 
 struct BatchPlan;
@@ -75,9 +76,10 @@ struct tc_context {
   int spmv_block = 256;
   int el_block = 128;
   int cg_per_replay = 16;
-  bool use_graphs = true;
+  bool use_graphs = false;
   // timing
   bool timing = false;
+  int timing_stride = 1;             // time every k-th launch of each kernel
   struct Pending { tc::KernelId k; hipEvent_t a, b; };
   std::vector<Pending> pending;
   std::vector<hipEvent_t> free_events;

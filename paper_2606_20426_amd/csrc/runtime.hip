@@ -188,12 +188,31 @@ static hipEvent_t get_event(tc_context* ctx) {
   return e;
 }
 
+// Launch; while timing is on, every timing_stride-th launch of each kernel
+// is bracketed by events on the context stream.
+static void timed_launch(tc_context* ctx, KernelId k, bool fp64, const LaunchArgs& a) {
+  if (!ctx->timing) {
+    launch_kernel(k, fp64, a);
+    return;
+  }
+  KernelTimer& t = ctx->timers[(int)k];
+  if (t.launches++ % ctx->timing_stride != 0) {
+    launch_kernel(k, fp64, a);
+    return;
+  }
+  hipEvent_t e0 = get_event(ctx), e1 = get_event(ctx);
+  (void)hipEventRecord(e0, ctx->stream);
+  launch_kernel(k, fp64, a);
+  (void)hipEventRecord(e1, ctx->stream);
+  ctx->pending.push_back({k, e0, e1});
+}
+
 static void resolve_timing(tc_context* ctx) {
   for (auto& p : ctx->pending) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
       ctx->timers[(int)p.k].ms += ms;
-      ctx->timers[(int)p.k].launches += 1;
+      ctx->timers[(int)p.k].timed += 1;
     }
     ctx->free_events.push_back(p.a);
     ctx->free_events.push_back(p.b);
@@ -386,15 +405,7 @@ void Runner::launch(KernelId k, int cls, int parity, int mode) {
     a.block = cls == BatchPlan::TET ? P->BT : (cls == BatchPlan::SPMV && P->lpr) ? P->BS : P->BV;
     a.lpr = P->lpr;
   }
-  if (ctx->timing) {
-    hipEvent_t e0 = get_event(ctx), e1 = get_event(ctx);
-    (void)hipEventRecord(e0, ctx->stream);
-    launch_kernel(k, P->fp64, a);
-    (void)hipEventRecord(e1, ctx->stream);
-    ctx->pending.push_back({k, e0, e1});
-  } else {
-    launch_kernel(k, P->fp64, a);
-  }
+  timed_launch(ctx, k, P->fp64, a);
 }
 
 void Runner::launch_tiles(KernelId k, const Tile* tiles, int ntiles, int block, int parity, int mode) {
@@ -408,15 +419,7 @@ void Runner::launch_tiles(KernelId k, const Tile* tiles, int ntiles, int block, 
   a.ntiles = ntiles;
   a.block = block;
   a.lpr = P->lpr;
-  if (ctx->timing) {
-    hipEvent_t e0 = get_event(ctx), e1 = get_event(ctx);
-    (void)hipEventRecord(e0, ctx->stream);
-    launch_kernel(k, P->fp64, a);
-    (void)hipEventRecord(e1, ctx->stream);
-    ctx->pending.push_back({k, e0, e1});
-  } else {
-    launch_kernel(k, P->fp64, a);
-  }
+  timed_launch(ctx, k, P->fp64, a);
 }
 
 Runner::View Runner::view(bool (*pred)(const EnvState&)) {
@@ -971,7 +974,9 @@ tc_status tc_context_memory(const tc_context* ctx, uint64_t* used, uint64_t* bud
 tc_status tc_context_set_timing(tc_context* ctx, int32_t enable) {
   if (!ctx) return set_error(TC_E_INVALID_ARG, "ctx is null");
   std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  if (enable < 0) return set_error(TC_E_INVALID_ARG, "enable must be >= 0");
   ctx->timing = enable != 0;
+  if (enable > 0) ctx->timing_stride = enable;
   return TC_OK;
 }
 
@@ -991,12 +996,12 @@ tc_status tc_context_timing(tc_context* ctx, int32_t cap, int32_t* n, char (*nam
   int k = 0;
   for (int i = 0; i < (int)KernelId::count && k < cap; ++i) {
     const KernelTimer& t = ctx->timers[i];
-    if (t.launches == 0) continue;
+    if (t.launches == 0 || t.timed == 0) continue;
     if (names) {
       std::strncpy(names[k], kernel_name((KernelId)i), TC_TIMER_NAME_LEN - 1);
       names[k][TC_TIMER_NAME_LEN - 1] = 0;
     }
-    if (avg_ms) avg_ms[k] = t.ms / t.launches;
+    if (avg_ms) avg_ms[k] = t.ms / t.timed;
     if (launches) launches[k] = t.launches;
     if (bytes_per_launch) bytes_per_launch[k] = t.bytes / t.launches;
     ++k;
@@ -1390,8 +1395,10 @@ tc_status tc_autotune(tc_context* ctx, int32_t n, tc_pad* const* pads, const int
     const int blk_cands[] = {128, 256, 512, 1024};
     const int el_cands[] = {64, 128, 256};
     const bool old_timing = ctx->timing;
+    const int old_stride = ctx->timing_stride;
     const bool old_graphs = ctx->use_graphs;
     ctx->timing = true;
+    ctx->timing_stride = 1;
     ctx->use_graphs = false;
     // probe: one step per candidate on saved state, restored afterwards
     auto probe = [&](int vb, int eb, int sb, double* t_spmv, double* t_upd, double* t_el) -> tc_status {
@@ -1425,7 +1432,7 @@ tc_status tc_autotune(tc_context* ctx, int32_t n, tc_pad* const* pads, const int
       const KernelTimer& te = ctx->timers[(int)KernelId::element];
       *t_spmv = cgit ? ts.ms / (double)cgit : 1e30;
       *t_upd = cgit ? tu.ms / (double)cgit : 1e30;
-      *t_el = te.launches ? te.ms / te.launches : 1e30;
+      *t_el = te.timed ? te.ms / te.timed : 1e30;
       return TC_OK;
     };
     int bcg = ctx->cg_block, bel = ctx->el_block, bsp = ctx->spmv_block;
@@ -1447,6 +1454,7 @@ tc_status tc_autotune(tc_context* ctx, int32_t n, tc_pad* const* pads, const int
     ctx->el_block = bel;
     ctx->spmv_block = bsp;
     ctx->timing = old_timing;
+    ctx->timing_stride = old_stride;
     ctx->use_graphs = old_graphs;
     ctx->plan.reset();
     for (auto& t : ctx->timers) t = KernelTimer{};
