@@ -11,6 +11,7 @@
 // or double (FP64 mode).  Positions, residual, dot products, line-search
 // energy and barrier terms are always double.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cmath>
 #include <cstdint>
@@ -996,24 +997,28 @@ __global__ void k_env_newton_begin(const EnvDesc* envs, int n) {
   S->ls_halv = 0;
 }
 
-// q = A p_new with p_new = z + beta p_old formed on the fly for every gathered
-// neighbour (the row owner stores it).  beta from this pad's r.z partials;
-// the pad's CG stops here when r.z <= tol^2 r0.z0 or at max_cg.
-template <typename R>
-__global__ void __launch_bounds__(1024) k_cg_spmv(const Tile* tiles, int ntiles, const EnvDesc* envs, int parity) {
-  __shared__ double sh[16];
-  const int t = xcd_tile(ntiles);
-  if (t < 0) return;
-  const Tile tl = tiles[t];
-  const EnvDesc& E = envs[tl.env];
+// Common head of the CG product for one tile: reduce this pad's r.z
+// partials, decide whether its CG stops here (r.z <= tol^2 r0.z0, max_cg or a
+// breakdown) and publish the iteration's scalars (tile 0).  Every block of the
+// pad computes the same decision.  Returns false when the tile has no work;
+// else beta for p_new = z + beta p_old.
+__device__ __forceinline__ bool cg_head(const Tile tl, const EnvDesc& E, int parity, double* sh,
+                                        double* beta) {
   EnvState* S = E.st;
-  if (!running(S) || S->cg_done) return;
+  // tile 0 of the pad may set cg_done while this block reads it: one thread
+  // reads, the block follows, so that all its waves take the same path
+  __shared__ int s_go;
+  if (threadIdx.x == 0) s_go = running(S) && !S->cg_done;
+  __syncthreads();
+  const bool go = s_go != 0;
+  __syncthreads();
+  if (!go) return false;
   const double rz = reduce_partials(E.part_rz, E.n_vt, OpSum(), 0.0, sh);
   const int it = S->it[parity ^ 1] + 1;
   const double rz0 = it == 0 ? rz : S->rz0;
   double tol2 = S->cg_tol2;
   if (it == 0) {
-    // forcing term of this Newton iteration (every block computes the same)
+    // forcing term of this Newton iteration
     double eta = S->force_tight ? fmin(E.cg_conv_tol, E.cg_rel_tol) : E.cg_rel_tol;
     if (E.cg_forcing && !S->force_tight) {
       if (S->rz0_prev > 0.0) {
@@ -1044,8 +1049,19 @@ __global__ void __launch_bounds__(1024) k_cg_spmv(const Tile* tiles, int ntiles,
       if (it == 0) S->rz0 = rz;
     }
   }
-  if (done) return;
-  const R beta = it == 0 ? R(0) : (R)(rz / S->rzp[parity ^ 1]);
+  if (done) return false;
+  *beta = it == 0 ? 0.0 : rz / S->rzp[parity ^ 1];
+  return true;
+}
+
+// q = A p_new, one thread per matrix row (tiles of blockDim.x rows); the row
+// owner stores p_new.
+template <typename R>
+__device__ __forceinline__ void cg_spmv_rows(const Tile tl, const EnvDesc* envs, int parity, double* sh) {
+  const EnvDesc& E = envs[tl.env];
+  double beta_d;
+  if (!cg_head(tl, E, parity, sh, &beta_d)) return;
+  const R beta = (R)beta_d;
   const int i = tl.tile * blockDim.x + threadIdx.x;
   const R* z = (const R*)E.z;
   const R* pold = (const R*)(parity ? E.p0 : E.p1);
@@ -1081,51 +1097,11 @@ __global__ void __launch_bounds__(1024) k_cg_spmv(const Tile* tiles, int ntiles,
 // neighbour gather, and the row sum is a shuffle reduction inside the lane
 // group.  A tile is blockDim.x / LPR lane groups x SPMV_ROWS_PER_GROUP rows.
 template <typename R, int LPR>
-__global__ void __launch_bounds__(1024) k_cg_spmv_vec(const Tile* tiles, int ntiles, const EnvDesc* envs, int parity) {
-  __shared__ double sh[16];
-  const int t = xcd_tile(ntiles);
-  if (t < 0) return;
-  const Tile tl = tiles[t];
+__device__ __forceinline__ void cg_spmv_lanes(const Tile tl, const EnvDesc* envs, int parity, double* sh) {
   const EnvDesc& E = envs[tl.env];
-  EnvState* S = E.st;
-  if (!running(S) || S->cg_done) return;
-  const double rz = reduce_partials(E.part_rz, E.n_vt, OpSum(), 0.0, sh);
-  const int it = S->it[parity ^ 1] + 1;
-  const double rz0 = it == 0 ? rz : S->rz0;
-  double tol2 = S->cg_tol2;
-  if (it == 0) {
-    double eta = S->force_tight ? fmin(E.cg_conv_tol, E.cg_rel_tol) : E.cg_rel_tol;
-    if (E.cg_forcing && !S->force_tight) {
-      if (S->rz0_prev > 0.0) {
-        const double r2 = rz / S->rz0_prev;      // (|g_k| / |g_k-1|)^2, preconditioned norms
-        if (r2 < 0.25) {
-          eta = 0.9 * r2;                        // fast progress: Eisenstat-Walker choice 2
-          const double safe = 0.9 * S->eta_prev * S->eta_prev;
-          if (safe > 0.1) eta = fmax(eta, safe);
-        } else {
-          eta = 0.25 * S->eta_prev;              // slow progress: solve more accurately
-        }
-      } else {
-        eta = E.cg_eta_max;
-      }
-      eta = fmin(E.cg_eta_max, fmax(eta, E.cg_rel_tol));
-    }
-    tol2 = eta * eta;
-  }
-  const bool done = it >= E.max_cg || !(rz > tol2 * rz0) || S->breakdown;
-  if (tl.tile == 0 && threadIdx.x == 0) {
-    if (it == 0) S->cg_tol2 = tol2;
-    if (done) {
-      S->cg_done = 1;
-      S->cg_iters = it;
-    } else {
-      S->it[parity] = it;
-      S->rzp[parity] = rz;
-      if (it == 0) S->rz0 = rz;
-    }
-  }
-  if (done) return;
-  const R beta = it == 0 ? R(0) : (R)(rz / S->rzp[parity ^ 1]);
+  double beta_d;
+  if (!cg_head(tl, E, parity, sh, &beta_d)) return;
+  const R beta = (R)beta_d;
   const int lane = threadIdx.x & (LPR - 1);
   const int groups = blockDim.x / LPR;
   const R* z = (const R*)E.z;
@@ -1167,14 +1143,16 @@ __global__ void __launch_bounds__(1024) k_cg_spmv_vec(const Tile* tiles, int nti
   if (threadIdx.x == 0) E.part_pq[tl.tile] = pq;
 }
 
+template <typename R, int LPR>
+__device__ __forceinline__ void cg_spmv_tile(const Tile tl, const EnvDesc* envs, int parity, double* sh) {
+  if constexpr (LPR == 0) cg_spmv_rows<R>(tl, envs, parity, sh);
+  else cg_spmv_lanes<R, LPR>(tl, envs, parity, sh);
+}
+
 // alpha = r.z / p.Ap; d += alpha p; r -= alpha Ap (float64); z = P^-1 r;
 // partial r.z for the next iteration.
 template <typename R>
-__global__ void __launch_bounds__(1024) k_cg_update(const Tile* tiles, int ntiles, const EnvDesc* envs, int parity) {
-  __shared__ double sh[16];
-  const int t = xcd_tile(ntiles);
-  if (t < 0) return;
-  const Tile tl = tiles[t];
+__device__ __forceinline__ void cg_update_tile(const Tile tl, const EnvDesc* envs, int parity, double* sh) {
   const EnvDesc& E = envs[tl.env];
   EnvState* S = E.st;
   if (!running(S) || S->cg_done) return;
@@ -1209,6 +1187,22 @@ __global__ void __launch_bounds__(1024) k_cg_update(const Tile* tiles, int ntile
   }
   rzn = block_reduce(rzn, OpSum(), sh);
   if (threadIdx.x == 0) E.part_rz[tl.tile] = rzn;
+}
+
+template <typename R, int LPR>
+__global__ void __launch_bounds__(1024) k_cg_spmv(const Tile* tiles, int ntiles, const EnvDesc* envs, int parity) {
+  __shared__ double sh[16];
+  const int t = xcd_tile(ntiles);
+  if (t < 0) return;
+  cg_spmv_tile<R, LPR>(tiles[t], envs, parity, sh);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(1024) k_cg_update(const Tile* tiles, int ntiles, const EnvDesc* envs, int parity) {
+  __shared__ double sh[16];
+  const int t = xcd_tile(ntiles);
+  if (t < 0) return;
+  cg_update_tile<R>(tiles[t], envs, parity, sh);
 }
 
 // ------------------------------------------------------ Newton direction, filter (a6)
@@ -1462,8 +1456,7 @@ __global__ void k_env_ls(const EnvDesc* envs, int n, int mode) {
   }
 }
 
-// x += alpha d for pads whose step was accepted; tile 0 advances the pad's
-// Newton counters.
+// x += alpha d for pads whose step was accepted.
 template <typename R>
 __global__ void k_update(const Tile* tiles, int ntiles, const EnvDesc* envs) {
   const int t = xcd_tile(ntiles);
@@ -1478,19 +1471,26 @@ __global__ void k_update(const Tile* tiles, int ntiles, const EnvDesc* envs) {
     const double a = S->ls_alpha;
     for (int c = 0; c < 3; ++c) E.xn[3 * i + c] += a * (double)d[3 * i + c];
   }
-  if (tl.tile == 0 && threadIdx.x == 0) {
-    S->newton_iters += 1;
-    S->ls_total += S->ls_halv;
-    const bool adaptive = (E.hess_proj & 3) == 2 || ((E.hess_proj >> 2) & 3) == 3;
-    if (adaptive && S->apply && S->ls_alpha == 1.0 && !S->no_true_hess) S->true_hess = 1;
-    if (!S->dir_conv) S->E_cur = S->E_next;
-    if (S->dir_conv) {
-      S->newton_done = 1;
-      S->phase = PH_FINISH;
-    } else if (S->newton_iters >= E.max_newton) {
-      S->status = TC_E_NOT_CONVERGED;
-      S->phase = PH_FINISH;
-    }
+}
+
+// One block per pad, after k_update (which must see the pad still running in
+// every block): Newton counters and the end-of-solve transition.
+__global__ void k_env_update(const EnvDesc* envs, int n) {
+  if (blockIdx.x >= n || threadIdx.x != 0) return;
+  const EnvDesc& E = envs[blockIdx.x];
+  EnvState* S = E.st;
+  if (!running(S)) return;
+  S->newton_iters += 1;
+  S->ls_total += S->ls_halv;
+  const bool adaptive = (E.hess_proj & 3) == 2 || ((E.hess_proj >> 2) & 3) == 3;
+  if (adaptive && S->apply && S->ls_alpha == 1.0 && !S->no_true_hess) S->true_hess = 1;
+  if (!S->dir_conv) S->E_cur = S->E_next;
+  if (S->dir_conv) {
+    S->newton_done = 1;
+    S->phase = PH_FINISH;
+  } else if (S->newton_iters >= E.max_newton) {
+    S->status = TC_E_NOT_CONVERGED;
+    S->phase = PH_FINISH;
   }
 }
 
@@ -1696,14 +1696,24 @@ __global__ void k_commit(const Tile* tiles, int ntiles, const EnvDesc* envs) {
 
 static inline unsigned grid8(int ntiles) { return (unsigned)(((ntiles + 7) / 8) * 8); }
 
-#define TC_LAUNCH(kern, ntiles, block, stream, ...)                                   \
-  do {                                                                                \
-    if ((ntiles) > 0)                                                                 \
-      hipLaunchKernelGGL(kern, dim3(grid8(ntiles)), dim3(block), 0, stream, __VA_ARGS__); \
+// With timing events the dispatch itself carries them (its own start and end
+// timestamps, no separate marker packets around it).
+#define TC_GO(kern, grid, block, stream, ...)                                                       \
+  do {                                                                                              \
+    if (a.ev0)                                                                                      \
+      hipExtLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, stream, a.ev0, a.ev1, 0, __VA_ARGS__); \
+    else                                                                                            \
+      hipLaunchKernelGGL(kern, dim3(grid), dim3(block), 0, stream, __VA_ARGS__);                   \
+  } while (0)
+
+#define TC_LAUNCH(kern, ntiles, block, stream, ...)                   \
+  do {                                                                \
+    if ((ntiles) > 0) TC_GO(kern, grid8(ntiles), block, stream, __VA_ARGS__); \
   } while (0)
 
 template <typename R>
-void launch_typed(KernelId id, const LaunchArgs& a) {
+hipError_t launch_typed(KernelId id, const LaunchArgs& a) {
+  hipError_t err = hipSuccess;
   switch (id) {
     case KernelId::setup_tets: TC_LAUNCH(k_setup_tets<R>, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs); break;
     case KernelId::setup_mass: TC_LAUNCH(k_setup_mass<R>, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs, a.out); break;
@@ -1715,38 +1725,41 @@ void launch_typed(KernelId id, const LaunchArgs& a) {
     case KernelId::asm_diag: TC_LAUNCH(k_asm_diag<R>, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs); break;
     case KernelId::asm_off: TC_LAUNCH(k_asm_off<R>, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs); break;
     case KernelId::newton_begin:
-      if (a.n_env > 0) hipLaunchKernelGGL(k_env_newton_begin, dim3(a.n_env), dim3(64), 0, a.stream, a.envs, a.n_env);
+      if (a.n_env > 0) TC_GO(k_env_newton_begin, a.n_env, 64, a.stream, a.envs, a.n_env);
       break;
     case KernelId::cg_spmv:
-      if (a.lpr == 16) TC_LAUNCH((k_cg_spmv_vec<R, 16>), a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs, a.parity);
-      else if (a.lpr == 32) TC_LAUNCH((k_cg_spmv_vec<R, 32>), a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs, a.parity);
-      else TC_LAUNCH(k_cg_spmv<R>, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs, a.parity);
+      if (a.lpr == 16) TC_LAUNCH((k_cg_spmv<R, 16>), a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs, a.parity);
+      else if (a.lpr == 32) TC_LAUNCH((k_cg_spmv<R, 32>), a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs, a.parity);
+      else TC_LAUNCH((k_cg_spmv<R, 0>), a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs, a.parity);
       break;
     case KernelId::cg_update: TC_LAUNCH(k_cg_update<R>, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs, a.parity); break;
     case KernelId::newton_dir: TC_LAUNCH(k_newton_dir<R>, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs); break;
     case KernelId::filter: TC_LAUNCH(k_filter<R>, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs); break;
     case KernelId::env_dir:
-      if (a.n_env > 0) hipLaunchKernelGGL(k_env_dir, dim3(a.n_env), dim3(256), 0, a.stream, a.envs, a.n_env);
+      if (a.n_env > 0) TC_GO(k_env_dir, a.n_env, 256, a.stream, a.envs, a.n_env);
       break;
     case KernelId::energy: TC_LAUNCH(k_energy<R>, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs, a.mode); break;
     case KernelId::env_ls:
-      if (a.n_env > 0) hipLaunchKernelGGL(k_env_ls, dim3(a.n_env), dim3(256), 0, a.stream, a.envs, a.n_env, a.mode);
+      if (a.n_env > 0) TC_GO(k_env_ls, a.n_env, 256, a.stream, a.envs, a.n_env, a.mode);
       break;
     case KernelId::update: TC_LAUNCH(k_update<R>, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs); break;
+    case KernelId::env_update:
+      if (a.n_env > 0) TC_GO(k_env_update, a.n_env, 64, a.stream, a.envs, a.n_env);
+      break;
     case KernelId::sigma: TC_LAUNCH(k_sigma<R>, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs); break;
     case KernelId::traction: TC_LAUNCH(k_traction<R>, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs); break;
     case KernelId::contact: TC_LAUNCH(k_contact, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs); break;
     case KernelId::env_extract:
-      if (a.n_env > 0) hipLaunchKernelGGL(k_env_extract, dim3(a.n_env), dim3(256), 0, a.stream, a.envs, a.n_env);
+      if (a.n_env > 0) TC_GO(k_env_extract, a.n_env, 256, a.stream, a.envs, a.n_env);
       break;
     case KernelId::commit: TC_LAUNCH(k_commit, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs); break;
     default: break;
   }
+  return err;
 }
 
-void launch_kernel(KernelId id, bool fp64, const LaunchArgs& a) {
-  if (fp64) launch_typed<double>(id, a);
-  else launch_typed<float>(id, a);
+hipError_t launch_kernel(KernelId id, bool fp64, const LaunchArgs& a) {
+  return fp64 ? launch_typed<double>(id, a) : launch_typed<float>(id, a);
 }
 
 }  // namespace tc

@@ -190,21 +190,16 @@ static hipEvent_t get_event(tc_context* ctx) {
 
 // Launch; while timing is on, every timing_stride-th launch of each kernel
 // is bracketed by events on the context stream.
-static void timed_launch(tc_context* ctx, KernelId k, bool fp64, const LaunchArgs& a) {
-  if (!ctx->timing) {
-    launch_kernel(k, fp64, a);
-    return;
-  }
+static hipError_t timed_launch(tc_context* ctx, KernelId k, bool fp64, const LaunchArgs& a) {
+  if (!ctx->timing) return launch_kernel(k, fp64, a);
   KernelTimer& t = ctx->timers[(int)k];
-  if (t.launches++ % ctx->timing_stride != 0) {
-    launch_kernel(k, fp64, a);
-    return;
-  }
-  hipEvent_t e0 = get_event(ctx), e1 = get_event(ctx);
-  (void)hipEventRecord(e0, ctx->stream);
-  launch_kernel(k, fp64, a);
-  (void)hipEventRecord(e1, ctx->stream);
-  ctx->pending.push_back({k, e0, e1});
+  if (t.launches++ % ctx->timing_stride != 0) return launch_kernel(k, fp64, a);
+  LaunchArgs b = a;
+  b.ev0 = get_event(ctx);
+  b.ev1 = get_event(ctx);
+  const hipError_t e = launch_kernel(k, fp64, b);
+  ctx->pending.push_back({k, b.ev0, b.ev1});
+  return e;
 }
 
 static void resolve_timing(tc_context* ctx) {
@@ -405,7 +400,7 @@ void Runner::launch(KernelId k, int cls, int parity, int mode) {
     a.block = cls == BatchPlan::TET ? P->BT : (cls == BatchPlan::SPMV && P->lpr) ? P->BS : P->BV;
     a.lpr = P->lpr;
   }
-  timed_launch(ctx, k, P->fp64, a);
+  (void)timed_launch(ctx, k, P->fp64, a);
 }
 
 void Runner::launch_tiles(KernelId k, const Tile* tiles, int ntiles, int block, int parity, int mode) {
@@ -419,7 +414,7 @@ void Runner::launch_tiles(KernelId k, const Tile* tiles, int ntiles, int block, 
   a.ntiles = ntiles;
   a.block = block;
   a.lpr = P->lpr;
-  timed_launch(ctx, k, P->fp64, a);
+  (void)timed_launch(ctx, k, P->fp64, a);
 }
 
 Runner::View Runner::view(bool (*pred)(const EnvState&)) {
@@ -577,6 +572,7 @@ tc_status Runner::tick(bool init) {
     }
     const View vu = view(is_run);
     launch_v(KernelId::update, vu, BatchPlan::VERT);
+    launch(KernelId::env_update, BatchPlan::NCLS);
     if ((st = readback())) return st;
   } else if (init) {
     if ((st = readback())) return st;

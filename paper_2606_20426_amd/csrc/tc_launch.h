@@ -26,6 +26,7 @@ enum class KernelId : int {
   energy,
   env_ls,
   update,
+  env_update,
   sigma,
   traction,
   contact,
@@ -38,7 +39,7 @@ inline const char* kernel_name(KernelId k) {
   static const char* names[] = {"setup_tets", "setup_mass", "setup_area", "predict",   "project",
                                 "element",    "barrier",    "asm_diag",   "asm_off",   "newton_begin",
                                 "cg_spmv",    "cg_update",  "newton_dir", "filter",    "env_dir",
-                                "energy",     "env_ls",     "update",     "sigma",     "traction",
+                                "energy",     "env_ls",     "update",     "env_update", "sigma",     "traction",
                                 "contact",    "env_extract", "commit"};
   return names[static_cast<int>(k)];
 }
@@ -54,8 +55,11 @@ struct LaunchArgs {
   int lpr = 0;             // SpMV lanes per row (16, 32; 0 = one thread per row)
   double* out = nullptr;
   hipStream_t stream = nullptr;
+  hipEvent_t ev0 = nullptr;    // timing: recorded at the dispatch's start and end
+  hipEvent_t ev1 = nullptr;
 };
 
-void launch_kernel(KernelId id, bool fp64, const LaunchArgs& a);
+// Launch errors surface through hipGetLastError.
+hipError_t launch_kernel(KernelId id, bool fp64, const LaunchArgs& a);
 
 }  // namespace tc

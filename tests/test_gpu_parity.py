@@ -144,6 +144,31 @@ def test_batch_equals_alone_bitwise():
         log(prec, [str(x) for x in sb])
 
 
+def test_rerun_is_bitwise_reproducible():
+    """The same steps from the same state give bitwise equal results: after a
+    reset, and on a fresh context (no scheduling-dependent arithmetic)."""
+    pads = [scenes.box_pad(0.018, 0.014, 0.004, 30, 24, 6), scenes.config1().pad]
+    eps = []
+    for p in pads:
+        ind = scenes.place_indenter(p, scenes.TEXTURE if len(eps) == 0 else scenes.SPHERE,
+                                    (0.5 * p.dims[0], 0.45 * p.dims[1]), 1e-4, sphere_radius=4 * MM)
+        eps.append(scenes.Episode(p, ind, 0.5 * MM, 6, scenes.Params()))
+    runs = []
+    for fresh in (True, False, True):
+        if fresh or not runs:
+            ctx = tc.Context(0)
+            gp = [gpu_pad(ctx, e.pad, "mixed") for e in eps]
+        else:
+            for g in gp:
+                g.reset()
+        for s in range(1, 5):
+            tc.step_batch(ctx, gp, [[e.pose(s)] for e in eps])
+        runs.append([(g.read("positions"), g.read("sigma")) for g in gp])
+    for r in runs[1:]:
+        for (xa, sa), (xb, sb) in zip(runs[0], r):
+            assert np.array_equal(xa, xb) and np.array_equal(sa, sb)
+
+
 def test_failures_are_transactional():
     ep = scenes.config1()
     ctx = context()
