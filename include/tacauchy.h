@@ -295,7 +295,8 @@ tc_status tc_pad_create(tc_context* ctx, const tc_mesh* mesh,
                         const tc_params* params, tc_pad** out);
 tc_status tc_pad_destroy(tc_pad* pad);
 tc_status tc_pad_get_info(const tc_pad* pad, tc_pad_info* out);
-/* Replace solver parameters (precision cannot change). */
+/* Replace solver parameters (precision cannot change; TC_E_INVALID_ARG).
+ * TC_E_BUSY while the pad has a request in flight on a server. */
 tc_status tc_pad_set_params(tc_pad* pad, const tc_params* params);
 /* Back to rest: x = X, v = 0. */
 tc_status tc_pad_reset(tc_pad* pad);

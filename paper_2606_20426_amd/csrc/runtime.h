@@ -106,6 +106,7 @@ struct tc_pad {
   double mu[tc::MAX_MAT], lam[tc::MAX_MAT], alpha[tc::MAX_MAT], rho[tc::MAX_MAT];
   double bbox_diag = 0.0;
   int64_t step_count = 0;
+  uint64_t desc_version = 0;         // bumped whenever the device descriptor changes
   std::atomic<int> busy{0};
   // resident device arrays (one allocation each, tracked for free)
   std::vector<std::pair<void*, size_t>> allocs;
@@ -124,6 +125,7 @@ struct BatchPlan {
   std::vector<tc_pad*> pads;
   std::vector<int> slots;            // state/pose slot of each pad
   std::vector<void*> scratch;
+  std::vector<uint64_t> versions;    // desc_version of each pad at build time
   int BV = 0, BT = 0, BS = 0;
   bool fp64 = false;
   EnvDesc* d_desc = nullptr;

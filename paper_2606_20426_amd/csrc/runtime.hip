@@ -335,6 +335,7 @@ tc_status build_plan(tc_context* ctx, int n, tc_pad* const* pads, const int* slo
   for (int i = 0; i < n; ++i) {
     tc_pad* p = pads[i];
     P->scratch.push_back(p->scratch);
+    P->versions.push_back(p->desc_version);
     EnvDesc E = p->desc;
     E.n_vt = cdiv(p->V, BV);
     E.n_tt = cdiv(p->T, BT);
@@ -381,7 +382,9 @@ bool plan_matches(const BatchPlan* P, tc_context* ctx, int n, tc_pad* const* pad
       P->d_state != pool.d_state)
     return false;
   for (int i = 0; i < n; ++i)
-    if (P->pads[i] != pads[i] || P->scratch[i] != pads[i]->scratch || P->slots[i] != slots[i]) return false;
+    if (P->pads[i] != pads[i] || P->scratch[i] != pads[i]->scratch || P->slots[i] != slots[i] ||
+        P->versions[i] != pads[i]->desc_version)
+      return false;
   return true;
 }
 
@@ -1241,6 +1244,7 @@ tc_status tc_pad_set_params(tc_pad* pad, const tc_params* params) {
   if (s) return set_error(s, err);
   if ((params->precision == TC_PREC_FP64) != pad->fp64) return set_error(TC_E_INVALID_ARG, "precision is fixed at pad creation");
   std::lock_guard<std::recursive_mutex> lk(pad->ctx->mu);
+  if (pad->busy.load()) return set_error(TC_E_BUSY, "pad has a request in flight on a server");
   pad->params = *params;
   EnvDesc& E = pad->desc;
   E.h = params->dt;
@@ -1260,6 +1264,7 @@ tc_status tc_pad_set_params(tc_pad* pad, const tc_params* params) {
   E.max_newton = params->max_newton;
   E.max_halvings = params->max_halvings;
   E.precond = params->precond;
+  pad->desc_version++;
   pad->ctx->plan.reset();
   return TC_OK;
 }

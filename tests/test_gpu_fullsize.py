@@ -1,0 +1,173 @@
+"""GPU checks at the workloads' full sizes, where the oracle cannot replay
+whole episodes: the graded 122,850-tet pad under its five indenters, and the
+60-pad batch in the launch configuration the benchmark times.
+
+After the GPU has run the steps, the oracle (FP64) checks the GPU's final
+state of a step from the outside:
+  * stationarity: the oracle's own Newton direction of the incremental
+    potential at the GPU's positions (x_hat from the GPU's state before the
+    step) is within the convergence tolerance, i.e. the GPU stopped at the
+    minimiser the oracle defines (Sec. III-B, Alg. 2 Physics);
+  * extraction: sigma (Eq. 4), traction, pressure and tangential traction
+    (Alg. 1, Eq. 6-9) and contact forces (Alg. 2 Contact) recomputed by the
+    oracle from the GPU's positions, element by element;
+  * identities: t_tau . n = 0 and reaction = -sum f_k.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from gpu_util import context, gpu_pad, log, oracle_pad, tc, voigt_to_mat
+from oracle import extract, stepper
+from workloads import scenes
+
+pytestmark = pytest.mark.gpu
+
+# mixed precision: FP32 element arithmetic, FP64 positions and reductions
+SIGMA_TOL = 1e-4
+FORCE_TOL = 1e-8
+KKT_FACTOR = 3.0        # oracle direction <= KKT_FACTOR * newton_tol * L
+
+
+def oracle_direction(op, x_prev, v_prev, x, inds, prm):
+    """The oracle's Newton direction at x for the step that started at
+    (x_prev, v_prev): PSD-projected Hessian, Jacobi-preconditioned CG."""
+    xhat = x_prev + prm.dt * v_prev
+    g = stepper.gradient(op, x, xhat, inds, prm).ravel()
+    H = stepper.hessian(op, x, inds, prm)
+    free = op.free.ravel()
+    Hff = H[free][:, free]
+    pf, info = spla.cg(Hff, -g[free], rtol=1e-7, maxiter=200000, M=sp.diags(1.0 / Hff.diagonal()))
+    assert info == 0
+    return float(np.abs(pf).max())
+
+
+FIELDS = ("positions", "sigma", "traction", "pressure", "tangential", "tri_normal", "contact_force",
+          "reaction")
+
+
+def snapshot(gp):
+    return {f: gp.read(f) for f in FIELDS}
+
+
+def check_state(out, op, x_prev, v_prev, inds, prm, label):
+    """out: the GPU's outputs after the step (snapshot)."""
+    x = out["positions"]
+    p_inf = oracle_direction(op, x_prev, v_prev, x, inds, prm)
+    tol = prm.newton_tol * op.L_diag
+    # extraction from the GPU's positions
+    sig_ref = extract.cauchy_per_tet(op, x)
+    sig = voigt_to_mat(out["sigma"])
+    # stresses below 1e-6 mu are roundoff (a pad not yet touched is at rest:
+    # exactly zero on the GPU, ~1e-11 Pa in the oracle's F = Ds Dm^-1)
+    floor = 1e-6 * float(np.max(op.mu))
+    smax = max(np.linalg.norm(sig_ref, axis=(1, 2)).max(), floor)
+    e_sig = np.linalg.norm(sig - sig_ref, axis=(1, 2)).max() / smax
+    t_ref, pn_ref, tt_ref, n_ref, _ = extract.surface_traction(op, x, sig_ref)
+    t = out["traction"].astype(np.float64)
+    pn = out["pressure"].astype(np.float64)
+    tt = out["tangential"].astype(np.float64)
+    e_t = np.abs(t - t_ref).max() / max(np.abs(t_ref).max(), floor)
+    e_pn = np.abs(pn - pn_ref).max() / max(np.abs(pn_ref).max(), floor)
+    cf_ref = extract.contact_forces(op, x, inds, prm)
+    f = out["contact_force"]
+    fscale = max(np.abs(cf_ref["f"]).max(), 1e-300)
+    e_f = np.abs(f - cf_ref["f"]).max() / fscale
+    reaction = out["reaction"]
+    e_r = np.abs(reaction + f.sum(axis=0)).max() / max(np.abs(reaction).max(), 1e-300)
+    n = out["tri_normal"].astype(np.float64)
+    orth = np.abs(np.einsum("si,si->s", tt, n)).max() / max(np.abs(t).max(), floor)
+    log(f"{label}: oracle |p|inf / tol {p_inf / tol:.3f}, sigma {e_sig:.2e}, traction {e_t:.2e}, "
+        f"pressure {e_pn:.2e}, contact force {e_f:.2e}, reaction {e_r:.1e}, t_tau.n {orth:.1e}, "
+        f"|reaction| {np.linalg.norm(reaction):.4e} N")
+    assert p_inf <= KKT_FACTOR * tol, label
+    assert e_sig <= SIGMA_TOL and e_t <= SIGMA_TOL and e_pn <= SIGMA_TOL, label
+    assert e_f <= FORCE_TOL and e_r <= 1e-12 and orth <= 1e-5, label
+
+
+@pytest.mark.parametrize("i", range(5), ids=["sphere", "cylinder", "cube_edge", "torus", "texture"])
+def test_graded_pad_episode(i):
+    pad = _graded_pad()
+    ep = scenes.config2(i, pad)
+    ctx = context()
+    gp = gpu_pad(ctx, pad, "mixed")
+    op = oracle_pad(pad)
+    prm = stepper.StepParams(dt=ep.params.dt, dhat=ep.params.dhat, kappa=ep.params.kappa,
+                             newton_tol=ep.params.newton_tol)
+    t0 = time.perf_counter()
+    newton = []
+    for s in range(1, ep.n_steps + 1):
+        if s in (15, ep.n_steps):
+            x_prev, v_prev = gp.read("positions"), gp.read("velocities")
+        st = gp.step([ep.pose(s)])
+        newton.append(st.newton_iters)
+        if s in (15, ep.n_steps):
+            check_state(snapshot(gp), op, x_prev, v_prev, [ep.pose(s)], prm,
+                        f"graded {ep.indenter.shape} step {s}")
+    log(f"graded pad, indenter {i}: {ep.n_steps} steps in {time.perf_counter() - t0:.2f} s, newton {newton}")
+    gp.close()
+
+
+_PAD = {}
+
+
+def _graded_pad():
+    if "p" not in _PAD:
+        _PAD["p"] = scenes.config2_pad()
+    return _PAD["p"]
+
+
+# (step, pads) checked after the batch run; four groups keep each test short
+BATCH_CHECKS = [(33, (0, 4, 8, 12, 16)), (33, (20, 24, 28, 32, 36)), (33, (40, 44, 48, 52, 56)),
+                (12, (2, 13, 27, 41, 58))]
+
+
+@pytest.fixture(scope="module")
+def batch60_run():
+    """The 60-pad batch with the benchmark's solver settings and launch
+    shape, steps 1-33; keeps the GPU states the checks need."""
+    envs = scenes.config3()
+    ctx = tc.Context(0)
+    kw = dict(precision="mixed", cg_rel_tol=1e-3, cg_eta_max=0.1, cg_forcing=1, hess_proj=12)
+    pads = []
+    for e in envs:
+        m = e.pad.material
+        pads.append(tc.Pad(ctx, e.pad.X, e.pad.tets, dict(E=m.E, nu=m.nu, density=m.density),
+                           tc.make_params(dt=e.params.dt, dhat=e.params.dhat, kappa=e.params.kappa,
+                                          newton_tol=e.params.newton_tol, **kw)))
+    want = {}
+    for s, ks in BATCH_CHECKS:
+        want.setdefault(s, set()).update(ks)
+    saved = {}
+    t0 = time.perf_counter()
+    newton = []
+    for s in range(1, 34):
+        prev = {k: (pads[k].read("positions"), pads[k].read("velocities")) for k in want.get(s, ())}
+        st = tc.step_batch(ctx, pads, [[e.pose(s)] for e in envs])
+        assert all(x.status == 0 for x in st)
+        newton.append(max(x.newton_iters for x in st))
+        for k in want.get(s, ()):
+            saved[(s, k)] = (prev[k][0], prev[k][1], snapshot(pads[k]))
+    log(f"batch60: 33 steps in {time.perf_counter() - t0:.1f} s, newton max per step {newton}")
+    for p in pads:
+        p.close()
+    ctx.close()
+    return envs, saved
+
+
+@pytest.mark.parametrize("step,ks", BATCH_CHECKS, ids=["last_a", "last_b", "last_c", "mid"])
+def test_batch60_bench_configuration(batch60_run, step, ks):
+    envs, saved = batch60_run
+    for k in ks:
+        e = envs[k]
+        x_prev, v_prev, out = saved[(step, k)]
+        prm = stepper.StepParams(dt=e.params.dt, dhat=e.params.dhat, kappa=e.params.kappa,
+                                 newton_tol=e.params.newton_tol)
+        check_state(out, oracle_pad(e.pad), x_prev, v_prev, [e.pose(step)], prm,
+                    f"batch pad {k} ({e.pad.name}, {e.pad.tets.shape[0]} tets, indenter "
+                    f"{e.indenter.shape}) step {step}")

@@ -1,0 +1,110 @@
+"""Continuous-batching server (tc_server_*): requests from pads of different
+sizes arrive while others run, join the running batch at Newton-iteration
+boundaries, and give the same result as the same step run alone (bitwise:
+the per-pad arithmetic does not depend on the batch).  Admission by HBM
+footprint: with a budget that holds only a few pads' step scratch, every
+request still completes, with the same results."""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+import pytest
+
+from gpu_util import gpu_pad, log, tc
+from workloads import scenes
+
+pytestmark = pytest.mark.gpu
+
+MM = scenes.MM
+N_STEPS = 4
+
+
+def _episodes():
+    rng = np.random.default_rng(11)
+    eps = [scenes.config1()]
+    shapes = [scenes.SPHERE, scenes.TEXTURE, scenes.TORUS, scenes.BOX, scenes.CYLINDER, scenes.SPHERE, scenes.TEXTURE]
+    dims = [(7, 5, 3), (12, 10, 4), (16, 12, 4), (9, 8, 3), (20, 16, 5), (10, 10, 3), (14, 11, 3)]
+    for shape, (nx, ny, nz) in zip(shapes, dims):
+        p = scenes.box_pad(0.018, 0.014, 0.004, nx, ny, nz) if nz != 3 else \
+            scenes.dome_pad(0.019, 0.016, 0.003, nx, ny, nz)
+        ind = scenes.place_indenter(p, shape, (0.5 * p.dims[0], 0.45 * p.dims[1]), 1e-4, sphere_radius=3 * MM)
+        eps.append(scenes.Episode(p, ind, float(rng.uniform(0.2, 0.6)) * MM, N_STEPS, scenes.Params()))
+    return eps
+
+
+def _alone(eps):
+    ctx = tc.Context(0)
+    out = []
+    for e in eps:
+        g = gpu_pad(ctx, e.pad, "mixed")
+        st = [g.step([e.pose(s)]) for s in range(1, N_STEPS + 1)]
+        out.append((g.read("positions"), g.read("sigma"), [(x.newton_iters, x.cg_iters) for x in st]))
+        g.close()
+    ctx.close()
+    return out
+
+
+def _served(eps, budget=0, max_slots=4):
+    ctx = tc.Context(0, hbm_budget=budget)
+    pads = [gpu_pad(ctx, e.pad, "mixed") for e in eps]
+    srv = tc.Server(ctx, max_slots)
+    order = [(k, s) for s in range(1, N_STEPS + 1) for k in range(len(eps))]
+    rng = np.random.default_rng(5)
+    results = []
+    i = 0
+    while i < len(order):
+        # bursts of 1-4 requests, each pad's steps in order
+        burst = int(rng.integers(1, 5))
+        for k, s in order[i:i + burst]:
+            srv.submit(pads[k], [eps[k].pose(s)], tag=k * 100 + s)
+        i += burst
+        time.sleep(float(rng.uniform(0.0, 0.004)))
+        results += srv.poll()
+    t0 = time.perf_counter()
+    while len(results) < len(order):
+        results += srv.poll(wait_us=2000)
+        assert time.perf_counter() - t0 < 60, "server did not finish"
+    stats = srv.stats()
+    srv.close()
+    final = [(g.read("positions"), g.read("sigma")) for g in pads]
+    for g in pads:
+        g.close()
+    ctx.close()
+    return results, final, stats
+
+
+def _check(eps, alone, results, final, stats, label):
+    assert all(r["status"] == 0 for r in results), [r for r in results if r["status"]]
+    for r in results:
+        assert r["t_arrive_ms"] <= r["t_admit_ms"] <= r["t_done_ms"]
+        k, s = divmod(r["tag"], 100)
+        assert (r["stats"].newton_iters, r["stats"].cg_iters) == alone[k][2][s - 1], (label, k, s)
+    for k, ((xa, sa, _), (xb, sb)) in enumerate(zip(alone, final)):
+        assert np.array_equal(xa, xb) and np.array_equal(sa, sb), (label, k)
+    lat = np.array([r["t_done_ms"] - r["t_arrive_ms"] for r in results])
+    log(f"{label}: {len(results)} requests, max running {stats['max_running_seen']}, batched iterations "
+        f"{stats['ticks']}, latency p50 {np.percentile(lat, 50):.1f} ms p99 {np.percentile(lat, 99):.1f} ms")
+
+
+def test_server_results_equal_alone_bitwise():
+    eps = _episodes()
+    alone = _alone(eps)
+    results, final, stats = _served(eps)
+    _check(eps, alone, results, final, stats, "server")
+    assert stats["max_running_seen"] > 1      # requests did overlap on the device
+
+
+def test_server_admission_by_memory_budget():
+    eps = _episodes()
+    alone = _alone(eps)
+    # probe the pads' footprints, then allow the resident data plus room for
+    # the step scratch of about two of the largest pads
+    ctx = tc.Context(0)
+    pads = [gpu_pad(ctx, e.pad, "mixed") for e in eps]
+    resident = sum(g.info["resident_bytes"] for g in pads)
+    scratch = max(g.info["scratch_bytes"] for g in pads)
+    ctx.close()
+    budget = resident + int(2.2 * scratch) + (8 << 20)
+    results, final, stats = _served(eps, budget=budget, max_slots=6)
+    _check(eps, alone, results, final, stats, f"server, budget {budget / 2**20:.1f} MiB")
