@@ -6,9 +6,12 @@ prediction, feasible start, Newton (element Hessians, barrier, assembly,
 block-Jacobi CG, step filter, line search), Cauchy stress, surface traction,
 contact forces and commit, all in one fused set of launches.
 
-    python bench.py [--gpus 1] [--steps 30] [--warmup 3] [--workload batch60]
+    python bench.py [--gpus 1] [--steps 30] [--warmup 3]        # 60-pad batch (headline)
+    python bench.py --sequential --precision fp64                 # the same pads one at a time
+    python bench.py --workload serve256 [--rate 2000] [--duration 20]
+    python bench.py --workload large1.2m --ablation               # FP32/FP64 CG ablation + extraction
 
-Prints one JSON line (see README of the metric fields in the design doc).
+Each mode prints one JSON line.
 """
 from __future__ import annotations
 
@@ -16,6 +19,7 @@ import argparse
 import json
 import os
 import sys
+import threading
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -26,6 +30,7 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE passes of this same command, scaled by a copy of known size);
 # used only while the kernel sources still hash to the recorded value
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "cg_spmv_batch60_pmc.md")
+METRIC = "aggregate IPC-FEM sensor steps/s (60 mixed envs) + p99 step latency"
 
 
 def log(*a):
@@ -39,7 +44,9 @@ def build_workload(name):
     if name == "single1944":
         return [scenes.config1()], "single 18x14x4 mm pad, 1,944 tets, sphere r=5 mm"
     if name == "large1.2m":
-        return [scenes.config5()], "24x24x5 mm pad, ~1.2M tets, 4-level refinement, sphere r=3 mm"
+        return [scenes.config5()], "24x24x5 mm pad, ~1.2M tets, 4-level refinement, sphere r=3 mm, 1.0 mm over 60 steps"
+    if name == "serve256":
+        return scenes.config4(), "256 resident pads, 5k-150k tets log-uniform (SeedSequence(4)), press/release episodes"
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -106,6 +113,241 @@ def cpu_baseline(envs, budget_s=20.0):
                       f"{t_small}/{t_mean:.0f} tets to the mean pad of the mix"}
 
 
+def make_pads(tc, ctx, envs, args, precision=None):
+    extra = dict(cg_rel_tol=args.cg_rel_tol, cg_eta_max=args.cg_eta_max, cg_forcing=args.cg_forcing,
+                 hess_proj=args.hess_proj)
+    if args.init_guess is not None:
+        extra["init_guess"] = args.init_guess
+    pads = []
+    for e in envs:
+        m = e.pad.material
+        kw = dict(precision=precision or args.precision, dt=e.params.dt, dhat=e.params.dhat,
+                  kappa=e.params.kappa, newton_tol=e.params.newton_tol)
+        kw.update(extra)
+        pads.append(tc.Pad(ctx, e.pad.X, e.pad.tets, dict(E=m.E, nu=m.nu, density=m.density),
+                           tc.make_params(**kw)))
+    return pads
+
+
+def roofline(ctx, args):
+    timers = ctx.timing()
+    if not timers:
+        return None
+    # dominant kernel by total time (average duration x launches)
+    k = max(timers, key=lambda n: timers[n][0] * timers[n][1])
+    avg_ms, launches, bpl = timers[k]
+    achieved = bpl / (avg_ms * 1e-3) / 1e9
+    log("kernel timers (avg ms, launches, GB/s):")
+    for name, (a, n, b) in sorted(timers.items(), key=lambda kv: -kv[1][0] * kv[1][1]):
+        log(f"  {name:14s} {a:9.4f} {n:7d} {b / max(a, 1e-12) / 1e6:9.1f}")
+    return {"bound": "hbm", "kernel": k, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(args.workload, k) if not args.sequential else None,
+            "avg_launch_ms": avg_ms, "launches": launches, "bytes_per_launch": bpl,
+            "timing_stride": args.timing_stride}
+
+
+def run_steps(args):
+    """Batch (default) or one-pad-at-a-time stepping of a fixed set of pads."""
+    import numpy as np
+    import torch
+    import paper_2606_20426_amd as tc
+
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+    envs, desc = build_workload(args.workload)
+    log(f"workload {args.workload}: {len(envs)} pads, {sum(e.pad.tets.shape[0] for e in envs)} tets")
+    ctx = tc.Context(0)
+    t0 = time.perf_counter()
+    pads = make_pads(tc, ctx, envs, args)
+    log(f"pads created in {time.perf_counter() - t0:.1f} s; HBM used {ctx.memory()[0] / 2**30:.2f} GiB")
+    ctx.set_launch(cg_block=args.cg_block, elem_block=args.elem_block, spmv_block=args.spmv_block,
+                   use_graphs=args.graphs)
+    if args.autotune:
+        chosen = ctx.autotune(pads, [[e.pose(1)] for e in envs])
+        log(f"autotune: vertex block {chosen[0]}, element block {chosen[1]}, SpMV block {chosen[2]}")
+
+    def step(s):
+        if args.sequential:
+            return [p.step([e.pose(s)]) for p, e in zip(pads, envs)]
+        return tc.step_batch(ctx, pads, [[e.pose(s)] for e in envs])
+
+    for s in range(1, args.warmup + 1):
+        st = step(s)
+        log(f"warmup {s}: newton max {max(x.newton_iters for x in st)} cg sum {sum(x.cg_iters for x in st)}")
+    if not args.no_timing:
+        ctx.set_timing(True, stride=args.timing_stride)
+        ctx.reset_timing()
+    torch.cuda.synchronize()
+    lat, newton, cg = [], [], []
+    t_start = time.perf_counter()
+    for s in range(args.warmup + 1, args.warmup + args.steps + 1):
+        a = time.perf_counter()
+        st = step(s)
+        lat.append((time.perf_counter() - a) * 1e3)
+        newton.append(max(x.newton_iters for x in st))
+        cg.append(sum(x.cg_iters for x in st))
+        log(f"step {s}: {lat[-1]:.1f} ms, newton max {newton[-1]}, cg total {cg[-1]}")
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_start
+    n_env = len(envs)
+    value = n_env * args.steps / total
+    roof = roofline(ctx, args) if not args.no_timing else None
+    mode = "sequential" if args.sequential else "batched"
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2), "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(total / args.steps * 1e3, 3),
+        "p50_ms": round(float(np.percentile(lat, 50)), 3),
+        "p99_ms": round(float(np.percentile(lat, 99)), 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if args.precision == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "description": desc, "envs": n_env,
+                   "tets": int(sum(e.pad.tets.shape[0] for e in envs)), "mode": mode,
+                   "newton_max_mean": float(np.mean(newton)), "cg_iters_mean": float(np.mean(cg)),
+                   "precision": args.precision, "graphs": bool(args.graphs and args.no_timing)},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        log("timing the oracle on a bounded sample ...")
+        out["cpu_baseline"] = cpu_baseline(envs)
+    return out
+
+
+def run_serve(args):
+    """Poisson step requests from many resident pads into the continuous-
+    batching server; latency = arrival (submit) to result."""
+    import numpy as np
+    import paper_2606_20426_amd as tc
+    from workloads import scenes
+
+    envs, desc = build_workload(args.workload)
+    n_pads = len(envs)
+    ctx = tc.Context(0, hbm_budget=int(args.hbm_budget_gib * 2**30) if args.hbm_budget_gib else 0)
+    t0 = time.perf_counter()
+    pads = make_pads(tc, ctx, envs, args)
+    resident = sum(p.info["resident_bytes"] for p in pads)
+    log(f"{n_pads} pads created in {time.perf_counter() - t0:.1f} s; resident {resident / 2**30:.2f} GiB")
+    t_arr, which = scenes.config4_arrivals(args.rate, args.duration, n_pads)
+    srv = tc.Server(ctx, args.max_slots)
+    step_of = [0] * n_pads
+    results = []
+    done_evt = threading.Event()
+
+    def collect():
+        while True:
+            results.extend(srv.poll(cap=1024, wait_us=1000))
+            if done_evt.is_set() and len(results) >= len(t_arr):
+                break
+
+    th = threading.Thread(target=collect, daemon=True)
+    th.start()
+    start = time.perf_counter()
+    last_log = start
+    for i, (t, k) in enumerate(zip(t_arr, which)):
+        delay = start + t - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        step_of[k] += 1
+        srv.submit(pads[k], [envs[k].pose(step_of[k])], tag=int(k))
+        if time.perf_counter() - last_log > 5.0:
+            last_log = time.perf_counter()
+            log(f"t={last_log - start:.1f} s: submitted {i + 1}, completed {len(results)}")
+    submit_end = time.perf_counter() - start
+    done_evt.set()
+    while th.is_alive():
+        th.join(timeout=5.0)
+        log(f"draining: completed {len(results)} of {len(t_arr)}")
+        if time.perf_counter() - start > args.duration + 600:
+            raise SystemExit("server did not drain")
+    total = time.perf_counter() - start
+    st = srv.stats()
+    srv.close()
+    ok = [r for r in results if r["status"] == 0]
+    lat = np.array([r["t_done_ms"] - r["t_arrive_ms"] for r in ok])
+    service = np.array([r["t_done_ms"] - r["t_admit_ms"] for r in ok])
+    completion_rate = len(ok) / total
+    saturated = total > args.duration * 1.05 + 0.5
+    return {
+        "metric": "serving: step requests/s completed and p50/p99 latency (arrival to result)",
+        "value": round(completion_rate, 1), "unit": "steps/s", "n_gpus": 1,
+        "p50_ms": round(float(np.percentile(lat, 50)), 2), "p99_ms": round(float(np.percentile(lat, 99)), 2),
+        "service_p50_ms": round(float(np.percentile(service, 50)), 2),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if args.precision == "mixed" else "f64", "data": "synthetic",
+        "config": {"workload": args.workload, "description": desc, "pads": n_pads,
+                   "arrival_rate_hz": args.rate, "duration_s": args.duration, "requests": int(len(t_arr)),
+                   "completed": len(ok), "failed": len(results) - len(ok), "max_slots": args.max_slots,
+                   "hbm_budget_gib": args.hbm_budget_gib, "resident_gib": round(resident / 2**30, 3),
+                   "max_running_seen": st["max_running_seen"], "batched_iterations": st["ticks"],
+                   "submit_span_s": round(submit_end, 2), "wall_s": round(total, 2),
+                   "saturated": bool(saturated)},
+    }
+
+
+def run_ablation(args):
+    """Large pad: the episode in mixed precision (FP32 element/SpMV, FP64
+    reductions) and in FP64, error of the mixed run against the FP64 run,
+    and standalone extraction (sigma, traction, contact) timing."""
+    import numpy as np
+    import torch
+    import paper_2606_20426_amd as tc
+
+    envs, desc = build_workload(args.workload)
+    e = envs[0]
+    ctx = tc.Context(0)
+    res = {}
+    steps = min(args.steps, e.n_steps) if args.steps else e.n_steps
+    for prec in ("mixed", "fp64"):
+        pad = make_pads(tc, ctx, [e], args, precision=prec)[0]
+        newton, t0 = [], time.perf_counter()
+        for s in range(1, steps + 1):
+            st = pad.step([e.pose(s)])
+            newton.append(st.newton_iters)
+            log(f"{prec} step {s}: newton {st.newton_iters}, cg {st.cg_iters}")
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        outp = {f: pad.read(f) for f in ("positions", "sigma", "pressure")}
+        # standalone extraction on the final state
+        ctx.set_timing(True, stride=1)
+        ctx.reset_timing()
+        reps = 20
+        t1 = time.perf_counter()
+        for _ in range(reps):
+            pad.extract([e.pose(steps)])
+        torch.cuda.synchronize()
+        ext_ms = (time.perf_counter() - t1) / reps * 1e3
+        timers = ctx.timing()
+        ctx.set_timing(False)
+        res[prec] = dict(ms_per_step=dt / steps * 1e3, newton=newton, out=outp, extract_ms=ext_ms,
+                         timers={k: v for k, v in timers.items() if k in ("sigma", "traction", "contact")})
+        log(f"{prec}: {steps} steps in {dt:.1f} s ({dt / steps * 1e3:.1f} ms/step), extraction {ext_ms:.3f} ms")
+        pad.close()
+    X = e.pad.X
+    a, b = res["mixed"]["out"], res["fp64"]["out"]
+    e_pos = float(np.abs(a["positions"] - b["positions"]).max() / np.abs(b["positions"] - X).max())
+    e_sig = float(np.abs(a["sigma"].astype(np.float64) - b["sigma"]).max() / np.abs(b["sigma"]).max())
+    e_pn = float(np.abs(a["pressure"].astype(np.float64) - b["pressure"]).max() / np.abs(b["pressure"]).max())
+    ext = {}
+    for prec in ("mixed", "fp64"):
+        tm = res[prec]["timers"]
+        ext[prec] = {"wall_ms": round(res[prec]["extract_ms"], 4),
+                     "kernels": {k: {"avg_ms": round(v[0], 4), "GB/s": round(v[2] / (v[0] * 1e-3) / 1e9, 1)}
+                                 for k, v in tm.items()}}
+    return {
+        "metric": "large-pad precision ablation: ms/step (mixed vs fp64), mixed-vs-fp64 error, extraction ms",
+        "value": round(res["mixed"]["ms_per_step"], 2), "unit": "ms/step", "n_gpus": 1, "steps": steps,
+        "higher_is_better": False, "scaling": "strong", "vs_baseline": None, "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "description": desc, "tets": int(e.pad.tets.shape[0])},
+        "fp64_ms_per_step": round(res["fp64"]["ms_per_step"], 2),
+        "newton_mixed": res["mixed"]["newton"], "newton_fp64": res["fp64"]["newton"],
+        "mixed_vs_fp64": {"positions": e_pos, "sigma": e_sig, "pressure": e_pn},
+        "extraction": ext,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -113,6 +355,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="batch60")
     ap.add_argument("--precision", default="mixed")
+    ap.add_argument("--sequential", action="store_true", help="step the pads one at a time")
+    ap.add_argument("--ablation", action="store_true", help="mixed vs fp64 episode + extraction timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true")
     ap.add_argument("--timing-stride", type=int, default=32,
@@ -132,100 +376,22 @@ def main():
     ap.add_argument("--cg-forcing", type=int, default=1)
     ap.add_argument("--hess-proj", type=int, default=12)
     ap.add_argument("--init-guess", type=int, default=None)
+    # serving
+    ap.add_argument("--rate", type=float, default=2000.0, help="request arrivals per second")
+    ap.add_argument("--duration", type=float, default=20.0, help="seconds of arrivals")
+    ap.add_argument("--max-slots", type=int, default=64)
+    ap.add_argument("--hbm-budget-gib", type=float, default=0.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); pads are independent, so N GPUs "
               "would each run their own batch (see DESIGN.md, sharding)", file=sys.stderr)
         sys.exit(2)
-
-    import numpy as np
-    import torch
-    import paper_2606_20426_amd as tc
-
-    if args.copy_probe:
-        copy_probe(args.copy_probe)
-    envs, desc = build_workload(args.workload)
-    log(f"workload {args.workload}: {len(envs)} pads, {sum(e.pad.tets.shape[0] for e in envs)} tets")
-    ctx = tc.Context(0)
-    t0 = time.perf_counter()
-    pads = []
-    extra = dict(cg_rel_tol=args.cg_rel_tol, cg_eta_max=args.cg_eta_max, cg_forcing=args.cg_forcing,
-                 hess_proj=args.hess_proj)
-    if args.init_guess is not None:
-        extra["init_guess"] = args.init_guess
-    for e in envs:
-        m = e.pad.material
-        kw = dict(precision=args.precision, dt=e.params.dt, dhat=e.params.dhat, kappa=e.params.kappa,
-                  newton_tol=e.params.newton_tol)
-        kw.update(extra)
-        pads.append(tc.Pad(ctx, e.pad.X, e.pad.tets, dict(E=m.E, nu=m.nu, density=m.density),
-                           tc.make_params(**kw)))
-    log(f"pads created in {time.perf_counter() - t0:.1f} s; HBM used {ctx.memory()[0] / 2**30:.2f} GiB")
-    ctx.set_launch(cg_block=args.cg_block, elem_block=args.elem_block, spmv_block=args.spmv_block,
-                   use_graphs=args.graphs)
-    if args.autotune:
-        chosen = ctx.autotune(pads, [[e.pose(1)] for e in envs])
-        log(f"autotune: vertex block {chosen[0]}, element block {chosen[1]}, SpMV block {chosen[2]}")
-
-    def step(s):
-        return tc.step_batch(ctx, pads, [[e.pose(s)] for e in envs])
-
-    for s in range(1, args.warmup + 1):
-        st = step(s)
-        log(f"warmup {s}: newton max {max(x.newton_iters for x in st)} cg sum {sum(x.cg_iters for x in st)} "
-            f"ms {st[0].ms:.1f}")
-    if not args.no_timing:
-        ctx.set_timing(True, stride=args.timing_stride)
-        ctx.reset_timing()
-    torch.cuda.synchronize()
-    lat = []
-    newton, cg = [], []
-    t_start = time.perf_counter()
-    for s in range(args.warmup + 1, args.warmup + args.steps + 1):
-        a = time.perf_counter()
-        st = step(s)
-        lat.append((time.perf_counter() - a) * 1e3)
-        newton.append(max(x.newton_iters for x in st))
-        cg.append(sum(x.cg_iters for x in st))
-        log(f"step {s}: {lat[-1]:.1f} ms, newton max {newton[-1]}, cg total {cg[-1]}")
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t_start
-    n_env = len(envs)
-    value = n_env * args.steps / total
-    timers = ctx.timing() if not args.no_timing else {}
-    roof = None
-    if timers:
-        # dominant kernel by total time
-        k = max(timers, key=lambda n: timers[n][0] * timers[n][1])
-        avg_ms, launches, bpl = timers[k]
-        achieved = bpl / (avg_ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "kernel": k, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(args.workload, k),
-                "avg_launch_ms": avg_ms, "launches": launches, "bytes_per_launch": bpl,
-                "timing_stride": args.timing_stride}
-        log("kernel timers (avg ms, launches, GB/s):")
-        for name, (a, n, b) in sorted(timers.items(), key=lambda kv: -kv[1][0] * kv[1][1]):
-            log(f"  {name:14s} {a:9.4f} {n:7d} {b / max(a, 1e-12) / 1e6:9.1f}")
-    lat_s = sorted(lat)
-    out = {
-        "metric": "aggregate IPC-FEM sensor steps/s (60 mixed envs) + p99 step latency",
-        "value": round(value, 2), "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(total / args.steps * 1e3, 3),
-        "p50_ms": round(float(np.percentile(lat_s, 50)), 3),
-        "p99_ms": round(float(np.percentile(lat_s, 99)), 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32+f64" if args.precision == "mixed" else "f64",
-        "data": "synthetic",
-        "config": {"workload": args.workload, "description": desc, "envs": n_env,
-                   "tets": int(sum(e.pad.tets.shape[0] for e in envs)),
-                   "newton_max_mean": float(np.mean(newton)), "cg_iters_mean": float(np.mean(cg)),
-                   "precision": args.precision, "graphs": bool(args.graphs and args.no_timing)},
-        "roofline": roof,
-    }
-    if not args.no_cpu_baseline:
-        log("timing the oracle on a bounded sample ...")
-        out["cpu_baseline"] = cpu_baseline(envs)
+    if args.workload == "serve256":
+        out = run_serve(args)
+    elif args.ablation:
+        out = run_ablation(args)
+    else:
+        out = run_steps(args)
     print(json.dumps(out), flush=True)
 
 
