@@ -15,7 +15,7 @@ constexpr int MAX_MAT = 8;
 constexpr int KE_STRIDE = 96;
 constexpr int KE_GRAD = 78;
 // rows handled by each lane group of the vectorised SpMV per tile
-constexpr int SPMV_ROWS_PER_GROUP = 8;
+constexpr int SPMV_ROWS_PER_GROUP = 4;
 
 // offset of block (a, b), a <= b, inside the record; diagonal blocks hold
 // (xx, xy, xz, yy, yz, zz), off-diagonal blocks row-major 3x3
