@@ -368,12 +368,14 @@ def main():
     ap.add_argument("--elem-block", type=int, default=0)
     ap.add_argument("--spmv-block", type=int, default=0)
     ap.add_argument("--autotune", action="store_true")
-    # solver settings of the timed run: adaptive CG forcing between 1e-3 and
-    # 0.1, element Hessians clamped, barrier Hessians unfiltered after the
-    # first full Newton step (same minimiser, fewer iterations)
-    ap.add_argument("--cg-rel-tol", type=float, default=1e-3)
+    # solver settings of the timed run: every CG solved to a relative
+    # residual of 0.1 (the Newton convergence test then sees that direction),
+    # element Hessians clamped, barrier Hessians unfiltered after the first
+    # full Newton step; the GPU tests check with the oracle that the final
+    # states meet the Newton tolerance
+    ap.add_argument("--cg-rel-tol", type=float, default=0.1)
     ap.add_argument("--cg-eta-max", type=float, default=0.1)
-    ap.add_argument("--cg-forcing", type=int, default=1)
+    ap.add_argument("--cg-forcing", type=int, default=2)
     ap.add_argument("--hess-proj", type=int, default=12)
     ap.add_argument("--init-guess", type=int, default=None)
     # serving

@@ -161,7 +161,9 @@ typedef struct {
                            cg_eta_max]: Eisenstat-Walker eta_k = 0.9 (|g_k| /
                            |g_k-1|)^2 (preconditioned norms, safeguarded)
                            while the gradient falls by 2x or more per
-                           iteration, eta_k = eta_k-1 / 4 otherwise */
+                           iteration, eta_k = eta_k-1 / 4 otherwise;
+                           2: Eisenstat-Walker choice 2 throughout (slow
+                           Newton progress keeps the solve loose) */
   int32_t hess_proj;    /* Hessian filters.  Bits 0-1, element eigenvalues:
                            0 clamp negatives to 0, 1 absolute value, 2 clamp
                            until a full Newton step is accepted, then the

@@ -1023,8 +1023,8 @@ __device__ __forceinline__ bool cg_head(const Tile tl, const EnvDesc& E, int par
     if (E.cg_forcing && !S->force_tight) {
       if (S->rz0_prev > 0.0) {
         const double r2 = rz / S->rz0_prev;      // (|g_k| / |g_k-1|)^2, preconditioned norms
-        if (r2 < 0.25) {
-          eta = 0.9 * r2;                        // fast progress: Eisenstat-Walker choice 2
+        if (r2 < 0.25 || E.cg_forcing == 2) {
+          eta = 0.9 * r2;                        // Eisenstat-Walker choice 2
           const double safe = 0.9 * S->eta_prev * S->eta_prev;
           if (safe > 0.1) eta = fmax(eta, safe);
         } else {
@@ -1331,7 +1331,10 @@ __global__ void k_env_dir(const EnvDesc* envs, int n) {
       S->dir_conv = 0;
     } else {
       S->dir_conv = dm <= E.tol_abs && tight;
-      S->force_tight = dm <= E.tol_abs && !tight;
+      // once a loose direction has looked converged, every further direction
+      // of this step is solved to the floor tolerance (no loose/tight
+      // alternation while the iterates creep towards the tolerance)
+      if (dm <= E.tol_abs && !tight) S->force_tight = 1;
     }
     S->ls_done = S->dir_conv;
     S->apply = S->dir_conv;

@@ -80,7 +80,7 @@ tc_status validate_params(const tc_params* p, std::string& err) {
   if (p->max_newton < 1 || p->max_cg < 1 || p->max_halvings < 0) { err = "iteration caps must be >= 1"; return TC_E_INVALID_ARG; }
   if (p->precision != TC_PREC_FP64 && p->precision != TC_PREC_MIXED) { err = "unknown precision"; return TC_E_INVALID_ARG; }
   if (p->precond != TC_PRECOND_BLOCK_JACOBI && p->precond != TC_PRECOND_JACOBI) { err = "unknown preconditioner"; return TC_E_INVALID_ARG; }
-  if (p->cg_forcing != 0 && p->cg_forcing != 1) { err = "cg_forcing must be 0 or 1"; return TC_E_INVALID_ARG; }
+  if (p->cg_forcing < 0 || p->cg_forcing > 2) { err = "cg_forcing must be 0, 1 or 2"; return TC_E_INVALID_ARG; }
   if (p->literal_alpha != 0 && p->literal_alpha != 1) { err = "literal_alpha must be 0 or 1"; return TC_E_INVALID_ARG; }
   if (p->quasi_static != 0 && p->quasi_static != 1) { err = "quasi_static must be 0 or 1"; return TC_E_INVALID_ARG; }
   if (!finite(p->cg_conv_tol) || p->cg_conv_tol < 0) { err = "cg_conv_tol must be >= 0"; return TC_E_INVALID_ARG; }
