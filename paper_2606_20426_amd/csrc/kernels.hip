@@ -1189,20 +1189,39 @@ __device__ __forceinline__ void cg_update_tile(const Tile tl, const EnvDesc* env
   if (threadIdx.x == 0) E.part_rz[tl.tile] = rzn;
 }
 
-template <typename R, int LPR>
-__global__ void __launch_bounds__(1024) k_cg_spmv(const Tile* tiles, int ntiles, const EnvDesc* envs, int parity) {
-  __shared__ double sh[16];
-  const int t = xcd_tile(ntiles);
-  if (t < 0) return;
-  cg_spmv_tile<R, LPR>(tiles[t], envs, parity, sh);
+// Optional self-timing of a launch on the GPU wall clock: every block stores
+// its start and end clock in its own pair of cells (plain stores, no
+// atomics); the host takes the earliest start and the latest end.
+__device__ __forceinline__ void clock_start(unsigned long long* clk) {
+  if (threadIdx.x == 0) clk[2 * blockIdx.x] = (unsigned long long)wall_clock64();
+}
+__device__ __forceinline__ void clock_end(unsigned long long* clk) {
+  __syncthreads();
+  if (threadIdx.x == 0) clk[2 * blockIdx.x + 1] = (unsigned long long)wall_clock64();
 }
 
-template <typename R>
-__global__ void __launch_bounds__(1024) k_cg_update(const Tile* tiles, int ntiles, const EnvDesc* envs, int parity) {
+// TIMED: the self-timing variant, launched only for the sampled launches
+// (the plain variant carries no timing code at all).
+template <typename R, int LPR, bool TIMED>
+__global__ void __launch_bounds__(1024) k_cg_spmv(const Tile* tiles, int ntiles, const EnvDesc* envs, int parity,
+                                                  unsigned long long* clk) {
   __shared__ double sh[16];
   const int t = xcd_tile(ntiles);
   if (t < 0) return;
+  if constexpr (TIMED) clock_start(clk);
+  cg_spmv_tile<R, LPR>(tiles[t], envs, parity, sh);
+  if constexpr (TIMED) clock_end(clk);
+}
+
+template <typename R, bool TIMED>
+__global__ void __launch_bounds__(1024) k_cg_update(const Tile* tiles, int ntiles, const EnvDesc* envs, int parity,
+                                                    unsigned long long* clk) {
+  __shared__ double sh[16];
+  const int t = xcd_tile(ntiles);
+  if (t < 0) return;
+  if constexpr (TIMED) clock_start(clk);
   cg_update_tile<R>(tiles[t], envs, parity, sh);
+  if constexpr (TIMED) clock_end(clk);
 }
 
 // ------------------------------------------------------ Newton direction, filter (a6)
@@ -1731,11 +1750,20 @@ hipError_t launch_typed(KernelId id, const LaunchArgs& a) {
       if (a.n_env > 0) TC_GO(k_env_newton_begin, a.n_env, 64, a.stream, a.envs, a.n_env);
       break;
     case KernelId::cg_spmv:
-      if (a.lpr == 16) TC_LAUNCH((k_cg_spmv<R, 16>), a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs, a.parity);
-      else if (a.lpr == 32) TC_LAUNCH((k_cg_spmv<R, 32>), a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs, a.parity);
-      else TC_LAUNCH((k_cg_spmv<R, 0>), a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs, a.parity);
+      if (a.clock) {
+        if (a.lpr == 16) TC_LAUNCH((k_cg_spmv<R, 16, true>), a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs, a.parity, a.clock);
+        else if (a.lpr == 32) TC_LAUNCH((k_cg_spmv<R, 32, true>), a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs, a.parity, a.clock);
+        else TC_LAUNCH((k_cg_spmv<R, 0, true>), a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs, a.parity, a.clock);
+      } else {
+        if (a.lpr == 16) TC_LAUNCH((k_cg_spmv<R, 16, false>), a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs, a.parity, nullptr);
+        else if (a.lpr == 32) TC_LAUNCH((k_cg_spmv<R, 32, false>), a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs, a.parity, nullptr);
+        else TC_LAUNCH((k_cg_spmv<R, 0, false>), a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs, a.parity, nullptr);
+      }
       break;
-    case KernelId::cg_update: TC_LAUNCH(k_cg_update<R>, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs, a.parity); break;
+    case KernelId::cg_update:
+      if (a.clock) TC_LAUNCH((k_cg_update<R, true>), a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs, a.parity, a.clock);
+      else TC_LAUNCH((k_cg_update<R, false>), a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs, a.parity, nullptr);
+      break;
     case KernelId::newton_dir: TC_LAUNCH(k_newton_dir<R>, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs); break;
     case KernelId::filter: TC_LAUNCH(k_filter<R>, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs); break;
     case KernelId::env_dir:

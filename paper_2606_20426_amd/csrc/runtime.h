@@ -80,7 +80,12 @@ struct tc_context {
   // timing
   bool timing = false;
   int timing_stride = 1;             // time every k-th launch of each kernel
-  struct Pending { tc::KernelId k; hipEvent_t a, b; };
+  // a timed launch: events, or (self-timed kernels) its blocks' clock cells
+  struct Pending { tc::KernelId k; hipEvent_t a, b; size_t cell; int blocks; };
+  // clock cells of self-timed launches since the last sync (device, zeroed)
+  unsigned long long* clock_cells = nullptr;
+  size_t clock_cap = 0, clock_used = 0;   // in cells (u64)
+  double clock_khz = 0.0;
   std::vector<Pending> pending;
   std::vector<hipEvent_t> free_events;
   tc::KernelTimer timers[(int)tc::KernelId::count];

@@ -195,15 +195,51 @@ static hipError_t timed_launch(tc_context* ctx, KernelId k, bool fp64, const Lau
   KernelTimer& t = ctx->timers[(int)k];
   if (t.launches++ % ctx->timing_stride != 0) return launch_kernel(k, fp64, a);
   LaunchArgs b = a;
+  const int blocks = ((a.ntiles + 7) / 8) * 8;   // the launch's grid
+  if (self_timed(k) && a.ntiles > 0 && ctx->clock_used + 2 * (size_t)blocks <= ctx->clock_cap) {
+    // every block stamps its own start and end
+    const size_t cell = ctx->clock_used;
+    ctx->clock_used += 2 * (size_t)blocks;
+    b.clock = ctx->clock_cells + cell;
+    const hipError_t e = launch_kernel(k, fp64, b);
+    ctx->pending.push_back({k, nullptr, nullptr, cell, blocks});
+    return e;
+  }
+  if (self_timed(k)) return launch_kernel(k, fp64, a);   // no room: not timed
   b.ev0 = get_event(ctx);
   b.ev1 = get_event(ctx);
   const hipError_t e = launch_kernel(k, fp64, b);
-  ctx->pending.push_back({k, b.ev0, b.ev1});
+  ctx->pending.push_back({k, b.ev0, b.ev1, 0, -1});
   return e;
 }
 
+// Called after the context stream has been synchronised.
 static void resolve_timing(tc_context* ctx) {
+  std::vector<unsigned long long> clk;
+  if (ctx->clock_used > 0) {
+    clk.resize(ctx->clock_used);
+    if (hipMemcpy(clk.data(), ctx->clock_cells, 8 * clk.size(), hipMemcpyDeviceToHost) != hipSuccess) clk.clear();
+    (void)hipMemsetAsync(ctx->clock_cells, 0, 8 * ctx->clock_used, ctx->stream);
+    ctx->clock_used = 0;
+  }
   for (auto& p : ctx->pending) {
+    if (p.blocks >= 0) {
+      if (p.cell + 2 * (size_t)p.blocks <= clk.size()) {
+        // blocks past the tile list store nothing (zero cells)
+        unsigned long long t0 = ~0ull, t1 = 0;
+        for (int b = 0; b < p.blocks; ++b) {
+          const unsigned long long s0 = clk[p.cell + 2 * b], s1 = clk[p.cell + 2 * b + 1];
+          if (s0 == 0 || s1 == 0) continue;
+          t0 = std::min(t0, s0);
+          t1 = std::max(t1, s1);
+        }
+        if (t1 >= t0 && t0 != ~0ull) {
+          ctx->timers[(int)p.k].ms += (double)(t1 - t0) / ctx->clock_khz;
+          ctx->timers[(int)p.k].timed += 1;
+        }
+      }
+      continue;
+    }
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
       ctx->timers[(int)p.k].ms += ms;
@@ -956,6 +992,7 @@ tc_status tc_context_destroy(tc_context* ctx) {
     ctx->arena.chunks.clear();
     resolve_timing(ctx);
     for (auto e : ctx->free_events) (void)hipEventDestroy(e);
+    if (ctx->clock_cells) (void)hipFree(ctx->clock_cells);
     pool_free(ctx->pool);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
   }
@@ -974,6 +1011,17 @@ tc_status tc_context_set_timing(tc_context* ctx, int32_t enable) {
   if (!ctx) return set_error(TC_E_INVALID_ARG, "ctx is null");
   std::lock_guard<std::recursive_mutex> lk(ctx->mu);
   if (enable < 0) return set_error(TC_E_INVALID_ARG, "enable must be >= 0");
+  if (enable > 0 && !ctx->clock_cells) {
+    TC_HIP(hipSetDevice(ctx->device));
+    int khz = 0;
+    TC_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, ctx->device));
+    if (khz <= 0) return set_error(TC_E_HIP, "device reports no wall clock rate");
+    ctx->clock_khz = khz;
+    ctx->clock_cap = (size_t)4 << 20;   // 32 MiB of cells
+    TC_HIP(hipMalloc(&ctx->clock_cells, 8 * ctx->clock_cap));
+    TC_HIP(hipMemsetAsync(ctx->clock_cells, 0, 8 * ctx->clock_cap, ctx->stream));
+    ctx->clock_used = 0;
+  }
   ctx->timing = enable != 0;
   if (enable > 0) ctx->timing_stride = enable;
   return TC_OK;

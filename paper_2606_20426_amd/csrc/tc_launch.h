@@ -57,7 +57,13 @@ struct LaunchArgs {
   hipStream_t stream = nullptr;
   hipEvent_t ev0 = nullptr;    // timing: recorded at the dispatch's start and end
   hipEvent_t ev1 = nullptr;
+  // timing of the CG kernels from inside: (start, end) GPU wall clock of
+  // every block, 2 x u64 per block (zero-initialised)
+  unsigned long long* clock = nullptr;
 };
+
+// Kernels that time themselves with the GPU wall clock when given a slot.
+inline bool self_timed(KernelId k) { return k == KernelId::cg_spmv || k == KernelId::cg_update; }
 
 // Launch errors surface through hipGetLastError.
 hipError_t launch_kernel(KernelId id, bool fp64, const LaunchArgs& a);
