@@ -359,8 +359,8 @@ def main():
     ap.add_argument("--ablation", action="store_true", help="mixed vs fp64 episode + extraction timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true")
-    ap.add_argument("--timing-stride", type=int, default=32,
-                    help="time every k-th launch of each kernel with events")
+    ap.add_argument("--timing-stride", type=int, default=29,
+                    help="time every k-th launch of each kernel (prime: the samples rotate through the positions of a CG chunk)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MiB",
                     help="run 4 device copies of this size first (counter calibration)")
     ap.add_argument("--graphs", type=int, default=0)
