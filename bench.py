@@ -115,7 +115,7 @@ def cpu_baseline(envs, budget_s=20.0):
 
 def make_pads(tc, ctx, envs, args, precision=None):
     extra = dict(cg_rel_tol=args.cg_rel_tol, cg_eta_max=args.cg_eta_max, cg_forcing=args.cg_forcing,
-                 hess_proj=args.hess_proj)
+                 hess_proj=args.hess_proj, ls_expand=args.ls_expand)
     if args.init_guess is not None:
         extra["init_guess"] = args.init_guess
     pads = []
@@ -371,12 +371,15 @@ def main():
     # solver settings of the timed run: every CG solved to a relative
     # residual of 0.1 (the Newton convergence test then sees that direction),
     # element Hessians clamped, barrier Hessians unfiltered after the first
-    # full Newton step; the GPU tests check with the oracle that the final
-    # states meet the Newton tolerance
+    # full Newton step, accepted full steps doubled while the energy keeps
+    # falling; the GPU tests check with the oracle that the final states meet
+    # the Newton tolerance
     ap.add_argument("--cg-rel-tol", type=float, default=0.1)
     ap.add_argument("--cg-eta-max", type=float, default=0.1)
     ap.add_argument("--cg-forcing", type=int, default=2)
     ap.add_argument("--hess-proj", type=int, default=12)
+    ap.add_argument("--ls-expand", type=int, default=4,
+                    help="doublings of an accepted full Newton step while the energy keeps falling")
     ap.add_argument("--init-guess", type=int, default=None)
     # serving
     ap.add_argument("--rate", type=float, default=2000.0, help="request arrivals per second")

@@ -178,6 +178,13 @@ typedef struct {
   double cg_conv_tol;   /* CG tolerance of the direction on which Newton
                            convergence is accepted (0 = cg_rel_tol) */
   double cg_eta_max;    /* largest forcing term (first Newton iteration) */
+  int32_t ls_expand;    /* after a full Newton step passes the line search,
+                           up to this many doublings of the step while the
+                           energy keeps falling (within the collision-free
+                           bound); 0 = off.  Same minimiser, fewer
+                           iterations where the filtered Hessian is stiffer
+                           than the energy along the direction. */
+  int32_t reserved;     /* 0 */
 } tc_params;
 
 /* Rigid indenter pose at the end of the step: world x = R y + c. */

@@ -995,6 +995,8 @@ __global__ void k_env_newton_begin(const EnvDesc* envs, int n) {
   S->apply = 0;
   S->ls_done = 0;
   S->ls_halv = 0;
+  S->ls_expanding = 0;
+  S->ls_expand_n = 0;
 }
 
 // Common head of the CG product for one tile: reduce this pad's r.z
@@ -1464,7 +1466,33 @@ __global__ void k_env_ls(const EnvDesc* envs, int n, int mode) {
     return;
   }
   const double a = S->ls_alpha;
-  if (Etot <= S->E_cur + 1e-4 * a * S->gTd + E.noise * fabs(S->E_cur)) {
+  const bool armijo = Etot <= S->E_cur + 1e-4 * a * S->gTd + E.noise * fabs(S->E_cur);
+  if (S->ls_expanding) {
+    // doubling an accepted full step: keep the larger step while it lowers
+    // the energy further (and still passes Armijo)
+    if (armijo && Etot < S->ls_best_E) {
+      S->ls_best_alpha = a;
+      S->ls_best_E = Etot;
+      S->ls_expand_n += 1;
+      if (S->ls_expand_n < E.ls_expand && 2.0 * a <= S->alpha_max) {
+        S->ls_alpha = 2.0 * a;
+        return;
+      }
+    }
+    S->ls_alpha = S->ls_best_alpha;
+    S->E_next = S->ls_best_E;
+    S->ls_done = 1;
+    S->apply = 1;
+    return;
+  }
+  if (armijo) {
+    if (E.ls_expand > 0 && S->ls_halv == 0 && a == 1.0 && 2.0 <= S->alpha_max) {
+      S->ls_expanding = 1;
+      S->ls_best_alpha = a;
+      S->ls_best_E = Etot;
+      S->ls_alpha = 2.0;
+      return;
+    }
     S->ls_done = 1;
     S->apply = 1;
     S->E_next = Etot;
@@ -1505,7 +1533,7 @@ __global__ void k_env_update(const EnvDesc* envs, int n) {
   S->newton_iters += 1;
   S->ls_total += S->ls_halv;
   const bool adaptive = (E.hess_proj & 3) == 2 || ((E.hess_proj >> 2) & 3) == 3;
-  if (adaptive && S->apply && S->ls_alpha == 1.0 && !S->no_true_hess) S->true_hess = 1;
+  if (adaptive && S->apply && S->ls_alpha >= 1.0 && !S->no_true_hess) S->true_hess = 1;
   if (!S->dir_conv) S->E_cur = S->E_next;
   if (S->dir_conv) {
     S->newton_done = 1;

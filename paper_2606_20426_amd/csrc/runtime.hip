@@ -592,7 +592,8 @@ tc_status Runner::tick(bool init) {
       }
     }
     int max_h = 0;
-    for (int i = 0; i < n; ++i) max_h = std::max(max_h, P->pads[i]->params.max_halvings);
+    for (int i = 0; i < n; ++i)
+      max_h = std::max(max_h, P->pads[i]->params.max_halvings + P->pads[i]->params.ls_expand);
     // first line-search round without waiting for the direction's flags
     // (pads that converged skip it on the device)
     View vl = debug ? view(ls_pending) : vr;
@@ -901,6 +902,8 @@ tc_status tc_params_default(tc_params* out) {
   out->init_guess = 0;
   out->cg_conv_tol = 0.0;
   out->cg_eta_max = 0.5;
+  out->ls_expand = 0;
+  out->reserved = 0;
   return TC_OK;
 }
 
@@ -1306,6 +1309,7 @@ tc_status tc_pad_set_params(tc_pad* pad, const tc_params* params) {
   E.cg_conv_tol = params->cg_conv_tol > 0 ? params->cg_conv_tol : params->cg_rel_tol;
   E.cg_eta_max = params->cg_eta_max;
   E.init_guess = params->init_guess;
+  E.ls_expand = params->ls_expand;
   for (int c = 0; c < 3; ++c) E.gravity[c] = params->gravity[c];
   E.quasi_static = params->quasi_static;
   E.max_cg = params->max_cg;

@@ -69,6 +69,10 @@ struct EnvState {
   int32_t ls_done;
   int32_t ls_halv;
   double ls_alpha;
+  int32_t ls_expanding;    // the line search is doubling an accepted full step
+  int32_t ls_expand_n;     // doublings taken
+  double ls_best_alpha;    // best accepted step and its energy while doubling
+  double ls_best_E;
   double alpha_max;
   double gTd;
   double E_cur;
@@ -161,6 +165,7 @@ struct EnvDesc {
   double h, dhat, kappa, tol_abs, noise, cg_rel_tol, cg_conv_tol, cg_eta_max;
   double gravity[3];
   int32_t quasi_static, max_cg, max_newton, max_halvings, precond, cg_forcing, hess_proj, init_guess;
+  int32_t ls_expand;
 };
 
 // One block of a launch: pad `env`, tile index `tile` within that pad's

@@ -85,6 +85,7 @@ tc_status validate_params(const tc_params* p, std::string& err) {
   if (p->quasi_static != 0 && p->quasi_static != 1) { err = "quasi_static must be 0 or 1"; return TC_E_INVALID_ARG; }
   if (!finite(p->cg_conv_tol) || p->cg_conv_tol < 0) { err = "cg_conv_tol must be >= 0"; return TC_E_INVALID_ARG; }
   if (!finite(p->cg_eta_max) || !(p->cg_eta_max > 0 && p->cg_eta_max < 1)) { err = "cg_eta_max must be in (0, 1)"; return TC_E_INVALID_ARG; }
+  if (p->ls_expand < 0 || p->ls_expand > 16) { err = "ls_expand must be in 0..16"; return TC_E_INVALID_ARG; }
   if (p->hess_proj < 0 || p->hess_proj > 15 || (p->hess_proj & 3) == 3) { err = "hess_proj: element mode 0..2 in bits 0-1, barrier mode 0..3 in bits 2-3"; return TC_E_INVALID_ARG; }
   if (p->init_guess != 0 && p->init_guess != 1) { err = "init_guess must be 0 or 1"; return TC_E_INVALID_ARG; }
   for (int c = 0; c < 3; ++c)
