@@ -265,6 +265,10 @@ def run_serve(args):
     st = srv.stats()
     srv.close()
     ok = [r for r in results if r["status"] == 0]
+    failed = {}
+    for r in results:
+        if r["status"] != 0:
+            failed[str(r["status"])] = failed.get(str(r["status"]), 0) + 1
     lat = np.array([r["t_done_ms"] - r["t_arrive_ms"] for r in ok])
     service = np.array([r["t_done_ms"] - r["t_admit_ms"] for r in ok])
     completion_rate = len(ok) / total
@@ -278,7 +282,8 @@ def run_serve(args):
         "dtype": "f32+f64" if args.precision == "mixed" else "f64", "data": "synthetic",
         "config": {"workload": args.workload, "description": desc, "pads": n_pads,
                    "arrival_rate_hz": args.rate, "duration_s": args.duration, "requests": int(len(t_arr)),
-                   "completed": len(ok), "failed": len(results) - len(ok), "max_slots": args.max_slots,
+                   "completed": len(ok), "failed": len(results) - len(ok), "failed_by_status": failed,
+                   "max_slots": args.max_slots,
                    "hbm_budget_gib": args.hbm_budget_gib, "resident_gib": round(resident / 2**30, 3),
                    "max_running_seen": st["max_running_seen"], "batched_iterations": st["ticks"],
                    "submit_span_s": round(submit_end, 2), "wall_s": round(total, 2),

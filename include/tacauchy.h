@@ -377,12 +377,16 @@ typedef struct {
   int32_t max_running_seen;
   int64_t ticks;           /* batched Newton iterations executed */
   uint64_t scratch_in_use; /* bytes of step scratch held by running requests */
+  int64_t evictions;       /* step scratch released to make room (context total) */
 } tc_server_stats;
 
 /* Continuous-batching request loop on its own host thread.  Pads stay
  * resident; a request (pad, poses) is admitted when a slot is free and its
  * step scratch fits the context budget, joins the running batch at the next
- * Newton-iteration boundary and leaves it when its step completes.
+ * Newton-iteration boundary and leaves it when its step completes.  When the
+ * budget is short, the step scratch of pads with no step on the device is
+ * released (their committed state stays resident); a request that cannot fit
+ * even then, with nothing running, completes with TC_E_NO_MEMORY.
  * max_slots: requests on the device at once (>= 1). */
 tc_status tc_server_create(tc_context* ctx, int32_t max_slots, tc_server** out);
 /* Queue one step request.  The pad must belong to the server's context;

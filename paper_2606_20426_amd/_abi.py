@@ -78,7 +78,7 @@ class TcServerStats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("admitted", C.c_int64), ("completed", C.c_int64),
                 ("rejected", C.c_int64), ("queued", C.c_int32), ("running", C.c_int32),
                 ("max_running_seen", C.c_int32), ("ticks", C.c_int64),
-                ("scratch_in_use", C.c_uint64)]
+                ("scratch_in_use", C.c_uint64), ("evictions", C.c_int64)]
 
 
 P = C.c_void_p

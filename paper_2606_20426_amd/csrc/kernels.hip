@@ -1257,10 +1257,18 @@ __global__ void k_newton_dir(const Tile* tiles, int ntiles, const EnvDesc* envs)
 
 // Largest safe step per contact vertex.  Convex indenters: phi(x + a p) >=
 // phi(x) + a grad(phi).p, so only approach (grad.p < 0) limits the step,
-// a <= 0.9 phi / (-grad.p).  The textured plate has a global curvature
-// bound, which gives a quadratic lower model of phi along the step.  The
-// torus advances conservatively with the 1-Lipschitz bound (at most 8
-// moves).  Each keeps phi >= 0.1 phi(x).
+// a <= 0.9 phi / (-grad.p).  The textured plate and the torus have curvature
+// bounds K along the step, which give the quadratic lower model
+// phi(x + a p) >= phi + a grad.p - K a^2 |p|^2 / 2.  Each keeps
+// phi >= 0.1 phi(x).  Steps are bounded for a <= FILTER_SPAN (the line
+// search may double an accepted full step up to there).
+constexpr double FILTER_SPAN = 16.0;
+
+__device__ __forceinline__ double quadratic_step(double phi, double gp, double K, double pn) {
+  const double qa = K * pn * pn;
+  return (gp + sqrt(gp * gp + 1.8 * qa * phi)) / qa;
+}
+
 template <typename R>
 __global__ void k_filter(const Tile* tiles, int ntiles, const EnvDesc* envs) {
   __shared__ double sh[16];
@@ -1285,30 +1293,30 @@ __global__ void k_filter(const Tile* tiles, int ntiles, const EnvDesc* envs) {
         sdf_world(P->ind[m], x, phi, g, H, false);
         double a = INFINITY;
         const double gp = g[0] * p[0] + g[1] * p[1] + g[2] * p[2];
-        if (convex_shape(P->ind[m].shape)) {
+        const DevIndenter& I = P->ind[m];
+        if (convex_shape(I.shape)) {
           if (gp < 0) a = 0.9 * phi / (-gp);
-        } else if (P->ind[m].shape == TC_TEXTURE) {
-          // |hess phi| <= K = k^2 A / c everywhere, so phi(x + a p) >= phi +
-          // a g.p - K a^2 |p|^2 / 2; largest a keeping that >= 0.1 phi
-          const double A = P->ind[m].prm[0], kk = 2.0 * M_PI / P->ind[m].prm[1];
-          const double K = kk * kk * A / sqrt(1.0 + (kk * A) * (kk * A));
-          const double qa = K * pn * pn;
-          a = (gp + sqrt(gp * gp + 1.8 * qa * phi)) / qa;
+        } else if (I.shape == TC_TEXTURE) {
+          // |hess phi| <= k^2 A / sqrt(1 + (kA)^2) everywhere
+          const double A = I.prm[0], kk = 2.0 * M_PI / I.prm[1];
+          a = quadratic_step(phi, gp, kk * kk * A / sqrt(1.0 + (kk * A) * (kk * A)), pn);
         } else {
-          // conservative advancement with the 1-Lipschitz bound: each move
-          // of 0.9 (phi - target) / |p| keeps phi >= target = 0.1 phi(x)
-          const double target = 0.1 * phi;
-          double acc = 0.0, dcur = phi;
-          for (int r = 0; r < 8 && acc < 1.0; ++r) {
-            const double da = 0.9 * (dcur - target) / pn;
-            if (!(da > 0.0)) break;
-            acc = fmin(1.0, acc + da);
-            const double y[3] = {x[0] + acc * p[0], x[1] + acc * p[1], x[2] + acc * p[2]};
-            double gy[3];
-            sdf_world(P->ind[m], y, dcur, gy, H, false);
+          // torus: outside the tube |hess phi| <= 1/r_t (tube) + 1/rho (ring),
+          // rho the distance from the torus axis, at its minimum over the
+          // segment a in [0, FILTER_SPAN] (local frame: y = R^T (x - c))
+          double y[3], q[3];
+          for (int i = 0; i < 3; ++i) {
+            y[i] = I.R[0 * 3 + i] * (x[0] - I.c[0]) + I.R[1 * 3 + i] * (x[1] - I.c[1]) + I.R[2 * 3 + i] * (x[2] - I.c[2]);
+            q[i] = I.R[0 * 3 + i] * p[0] + I.R[1 * 3 + i] * p[1] + I.R[2 * 3 + i] * p[2];
           }
-          a = acc;
+          const double qq = q[0] * q[0] + q[1] * q[1];
+          double as = qq > 0.0 ? -(y[0] * q[0] + y[1] * q[1]) / qq : 0.0;
+          as = fmin(fmax(as, 0.0), FILTER_SPAN);
+          const double rho = sqrt((y[0] + as * q[0]) * (y[0] + as * q[0]) + (y[1] + as * q[1]) * (y[1] + as * q[1]));
+          const double K = 1.0 / I.prm[1] + 1.0 / fmax(rho, 1e-9);
+          a = quadratic_step(phi, gp, K, pn);
         }
+        a = fmin(a, FILTER_SPAN);
         amax = fmin(amax, a);
       }
     }

@@ -37,6 +37,8 @@ class Arena {
   void* take(size_t bytes);          // nullptr if nothing fits
   void give(void* p, size_t bytes);
   bool add_chunk(char* base, size_t size);
+  // removes the chunks that are entirely free; returns them (base, size)
+  std::vector<std::pair<char*, size_t>> drop_empty();
   size_t held() const;
   std::vector<Chunk> chunks;
 };
@@ -94,6 +96,8 @@ struct tc_context {
   tc::SlotPool pool;                 // slots of synchronous steps
   std::recursive_mutex mu;           // serialises device work of API calls and the server
   int next_pad_id = 1;
+  std::vector<tc_pad*> pads;         // every live pad of the context
+  std::atomic<int64_t> evictions{0}; // step scratch released to make room
 
   void* dev_alloc(size_t bytes, tc_status* st);
   void dev_free(void* p, size_t bytes);
@@ -113,6 +117,7 @@ struct tc_pad {
   int64_t step_count = 0;
   uint64_t desc_version = 0;         // bumped whenever the device descriptor changes
   std::atomic<int> busy{0};
+  std::atomic<int> in_flight{0};     // a step of this pad is on the device (server slot)
   // resident device arrays (one allocation each, tracked for free)
   std::vector<std::pair<void*, size_t>> allocs;
   uint64_t resident_bytes = 0;
@@ -158,6 +163,10 @@ tc_status run_batch(tc_context* ctx, int n, tc_pad* const* pads, const int32_t* 
 
 tc_status newton_direction(tc_pad* pad, int n_ind, const tc_indenter* ind, double* dir, double* grad);
 tc_status ensure_scratch(tc_pad* pad);
+// The same, making room within the context budget when it is short: step
+// scratch of pads not in `keep` and not in flight is released (largest
+// first), then arena chunks left entirely free go back to the device.
+tc_status ensure_scratch_evicting(tc_pad* pad, const std::vector<tc_pad*>& keep);
 void release_scratch(tc_pad* pad);
 tc_status pool_reserve(tc_context* ctx, SlotPool& p, int cap);
 void pool_free(SlotPool& p);

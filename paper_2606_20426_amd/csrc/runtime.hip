@@ -82,6 +82,19 @@ bool Arena::add_chunk(char* base, size_t size) {
   return true;
 }
 
+std::vector<std::pair<char*, size_t>> Arena::drop_empty() {
+  std::vector<std::pair<char*, size_t>> out;
+  for (auto it = chunks.begin(); it != chunks.end();) {
+    if (it->free_.size() == 1 && it->free_.begin()->first == 0 && it->free_.begin()->second == it->size) {
+      out.push_back({it->base, it->size});
+      it = chunks.erase(it);
+    } else {
+      ++it;
+    }
+  }
+  return out;
+}
+
 size_t Arena::held() const {
   size_t s = 0;
   for (auto& c : chunks) s += c.size;
@@ -340,6 +353,27 @@ tc_status ensure_scratch(tc_pad* p) {
   p->scratch_bytes = need;
   bind_scratch_desc(p);
   return TC_OK;
+}
+
+tc_status ensure_scratch_evicting(tc_pad* p, const std::vector<tc_pad*>& keep) {
+  tc_status s = ensure_scratch(p);
+  if (s != TC_E_NO_MEMORY) return s;
+  tc_context* ctx = p->ctx;
+  std::vector<tc_pad*> idle;
+  for (tc_pad* q : ctx->pads)
+    if (q != p && q->scratch && !q->in_flight.load() && std::find(keep.begin(), keep.end(), q) == keep.end())
+      idle.push_back(q);
+  std::sort(idle.begin(), idle.end(), [](tc_pad* a, tc_pad* b) { return a->scratch_bytes > b->scratch_bytes; });
+  if (!idle.empty()) (void)hipStreamSynchronize(ctx->stream);   // no kernel may still use it
+  for (tc_pad* q : idle) {
+    release_scratch(q);
+    ctx->evictions++;
+    if ((s = ensure_scratch(p)) != TC_E_NO_MEMORY) return s;
+  }
+  // fragmentation: hand completely free chunks back and allocate anew
+  (void)hipStreamSynchronize(ctx->stream);
+  for (auto& c : ctx->arena.drop_empty()) ctx->dev_free(c.first, c.second);
+  return ensure_scratch(p);
 }
 
 void release_scratch(tc_pad* p) {
@@ -679,9 +713,12 @@ tc_status run_batch(tc_context* ctx, int n, tc_pad* const* pads, const int32_t* 
   }
   std::lock_guard<std::recursive_mutex> lk(ctx->mu);
   TC_HIP(hipSetDevice(ctx->device));
-  for (int i = 0; i < n; ++i) {
-    tc_status s = ensure_scratch(pads[i]);
-    if (s) return s;
+  {
+    const std::vector<tc_pad*> keep(pads, pads + n);
+    for (int i = 0; i < n; ++i) {
+      tc_status s = ensure_scratch_evicting(pads[i], keep);
+      if (s) return s;
+    }
   }
   SlotPool& pool = ctx->pool;
   {
@@ -1253,6 +1290,7 @@ tc_status tc_pad_create(tc_context* ctx, const tc_mesh* mesh, int32_t n_material
       (void)hipFree(dt);
     }
     p->scratch_need = scratch_layout(p).total;
+    ctx->pads.push_back(p);
     *out = guard.release();
     return TC_OK;
   });
@@ -1268,6 +1306,7 @@ tc_status tc_pad_destroy(tc_pad* pad) {
   release_scratch(pad);
   ctx->plan.reset();
   for (auto& a : pad->allocs) ctx->dev_free(a.first, a.second);
+  ctx->pads.erase(std::remove(ctx->pads.begin(), ctx->pads.end(), pad), ctx->pads.end());
   delete pad;
   return TC_OK;
 }

@@ -51,8 +51,9 @@ struct tc_server {
 };
 
 // Admit queued requests (FIFO, a pad's requests in order) while slots are
-// free and their step scratch fits the context budget; scratch of pads that
-// are idle on this server is released first when memory runs short.
+// free and their step scratch fits the context budget; when memory runs
+// short, the step scratch of pads without a step on the device is released
+// first.
 bool tc_server::admit(std::vector<int>& fresh) {
   std::vector<tc_pad*> running;
   for (int s = 0; s < max_slots; ++s)
@@ -69,21 +70,11 @@ bool tc_server::admit(std::vector<int>& fresh) {
     for (auto jt = queue.begin(); jt != it; ++jt)
       if (jt->pad == p) earlier_same_pad = true;
     if (earlier_same_pad) { ++it; continue; }
-    tc_status s = ensure_scratch(p);
-    if (s == TC_E_NO_MEMORY) {
-      // evict idle pads' scratch (largest first) and retry once
-      std::vector<tc_pad*> idle;
-      for (auto& q : queue)
-        if (q.pad != p && q.pad->scratch && std::find(running.begin(), running.end(), q.pad) == running.end() &&
-            std::find(idle.begin(), idle.end(), q.pad) == idle.end())
-          idle.push_back(q.pad);
-      std::sort(idle.begin(), idle.end(), [](tc_pad* a, tc_pad* b) { return a->scratch_bytes > b->scratch_bytes; });
-      for (tc_pad* q : idle) {
-        release_scratch(q);
-        if ((s = ensure_scratch(p)) != TC_E_NO_MEMORY) break;
-      }
-    }
-    if (s == TC_E_NO_MEMORY) { blocked = true; break; }
+    // running requests keep their scratch; any other pad's may go
+    tc_status s = ensure_scratch_evicting(p, running);
+    // short of memory: wait for running requests to finish; with none
+    // running the request can never fit and is rejected
+    if (s == TC_E_NO_MEMORY && !running.empty()) { blocked = true; break; }
     Req r = *it;
     it = queue.erase(it);
     if (s != TC_OK) {
@@ -100,6 +91,7 @@ bool tc_server::admit(std::vector<int>& fresh) {
       continue;
     }
     r.t_admit = now();
+    p->in_flight.store(1);
     slot_used[slot] = 1;
     slot_req[slot] = r;
     running.push_back(p);
@@ -178,6 +170,7 @@ void tc_server::loop() {
       res.stats.status = res.status;
       if (res.status == TC_OK) r.pad->step_count++;
       if (ctx->timing) account_bytes(ctx, r.pad, S);
+      r.pad->in_flight.store(0);
       r.pad->busy.store(0);
       done.push_back(res);
       slot_used[s] = 0;
@@ -275,6 +268,7 @@ tc_status tc_server_get_stats(tc_server* srv, tc_server_stats* out) {
   for (int s = 0; s < srv->max_slots; ++s)
     if (srv->slot_used[s]) sc += srv->slot_req[s].pad->scratch_bytes;
   out->scratch_in_use = sc;
+  out->evictions = srv->ctx->evictions.load();
   return TC_OK;
 }
 

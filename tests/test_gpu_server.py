@@ -108,3 +108,42 @@ def test_server_admission_by_memory_budget():
     budget = resident + int(2.2 * scratch) + (8 << 20)
     results, final, stats = _served(eps, budget=budget, max_slots=6)
     _check(eps, alone, results, final, stats, f"server, budget {budget / 2**20:.1f} MiB")
+
+
+def test_server_evicts_idle_scratch():
+    """A pad that has finished its requests keeps its step scratch until
+    memory is needed: with room for about one large pad's scratch, requests
+    of the other pads arriving afterwards still complete (the idle scratch
+    is released), with the same results as alone."""
+    eps = _episodes()
+    alone = _alone(eps)
+    ctx = tc.Context(0)
+    probe = [gpu_pad(ctx, e.pad, "mixed") for e in eps]
+    resident = sum(g.info["resident_bytes"] for g in probe)
+    scratch = max(g.info["scratch_bytes"] for g in probe)
+    total = sum(g.info["scratch_bytes"] for g in probe)
+    ctx.close()
+    room = int(1.3 * scratch) + (1 << 20)      # 1 MiB for plans and state slots
+    assert total > room + (1 << 20)            # not every pad's scratch fits at once
+    budget = resident + room
+    ctx = tc.Context(0, hbm_budget=budget)
+    pads = [gpu_pad(ctx, e.pad, "mixed") for e in eps]
+    srv = tc.Server(ctx, 4)
+    results = []
+    big = max(range(len(eps)), key=lambda k: pads[k].info["scratch_bytes"])
+    order = [big] + [k for k in range(len(eps)) if k != big]
+    t0 = time.perf_counter()
+    for k in order:
+        # one pad at a time: each finishes (and idles, holding its scratch)
+        # before the next pad's requests arrive
+        for s in range(1, N_STEPS + 1):
+            srv.submit(pads[k], [eps[k].pose(s)], tag=k * 100 + s)
+        while sum(1 for r in results if r["tag"] // 100 == k) < N_STEPS:
+            results += srv.poll(wait_us=2000)
+            assert time.perf_counter() - t0 < 60, "server did not finish"
+    stats = srv.stats()
+    srv.close()
+    final = [(g.read("positions"), g.read("sigma")) for g in pads]
+    ctx.close()
+    _check(eps, alone, results, final, stats, f"server, budget {budget / 2**20:.1f} MiB, one pad at a time")
+    assert stats["evictions"] > 0
