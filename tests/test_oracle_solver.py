@@ -120,6 +120,54 @@ def test_uniform_compression_closed_form_and_traction_balance():
     assert (pn[op.is_top.astype(bool)] < 0).all()
 
 
+def test_two_layer_confined_compression_closed_form():
+    """Per-tet materials: a soft layer on a stiff one, lateral motion blocked,
+    pressed by a flat plate (quasi-static).  Each layer is in uniaxial strain
+    F = diag(1, 1, s_i), J = s_i; equilibrium makes sigma_zz the same in both,
+    and with Eq. 2 (rest-stable shift) sigma_zz = (mu_i + lam_i) s_i -
+    lam_i alpha_i, so the layer stretches follow from the top height alone."""
+    Lx, Ly, H = 18 * MM, 14 * MM, 4 * MM
+    pad = scenes.box_pad(Lx, Ly, H, 5, 4, 4)
+    X, T = pad.X, pad.tets
+    zc = X[T, 2].mean(axis=1)
+    soft = zc > 2 * MM
+    E = np.where(soft, 0.15e6, 1.2e6)
+    nu = np.where(soft, 0.47, 0.42)
+    rho = np.where(soft, 1050.0, 1200.0)
+    fixed = np.full(X.shape[0], 3, np.uint8)                         # x, y blocked
+    fixed[X[:, 2] == 0] = 7
+    op = stepper.make_pad(X, T, E, nu, rho, fixed=fixed)
+    dhat = 0.1 * MM
+    depth = 0.3 * MM
+    plate = scenes.Indenter(contact.BOX, (60 * MM, 60 * MM, 5 * MM, 0), np.eye(3),
+                            np.array([Lx / 2, Ly / 2, H + dhat + 5 * MM - depth]))
+    prm = stepper.StepParams(newton_tol=1e-12, quasi_static=True, dhat=dhat)
+    x = stepper.step(op, [plate], prm).x
+    top = X[:, 2] == H
+    assert np.ptp(x[top, 2]) < 1e-12
+    h_top = x[top, 2].mean()
+    mu, lam, a = op.mu, op.lam, op.alpha
+    k = np.array([np.argmax(soft), np.argmax(~soft)])                 # one tet per layer
+    # h_top = 2 mm (s_soft + s_stiff), s_i = (sz + lam_i a_i) / (mu_i + lam_i)
+    c = (mu[k] + lam[k])
+    sz = (h_top / (2 * MM) - np.sum(lam[k] * a[k] / c)) / np.sum(1.0 / c)
+    s_i = (sz + lam[k] * a[k]) / c
+    F = np.stack([x[T[:, j]] - x[T[:, 0]] for j in (1, 2, 3)], axis=2) @ op.Dminv
+    for layer, sel in enumerate((soft, ~soft)):
+        expect = np.diag([1.0, 1.0, s_i[layer]])
+        assert np.abs(F[sel] - expect).max() < 1e-9
+    sig = extract.cauchy_per_tet(op, x)
+    scale = abs(sz)
+    assert np.abs(sig[:, 2, 2] - sz).max() < 1e-8 * scale
+    sxx = mu[k] / s_i + lam[k] * (s_i - a[k])                         # lateral stress per layer
+    for layer, sel in enumerate((soft, ~soft)):
+        assert np.abs(sig[sel, 0, 0] - sxx[layer]).max() < 1e-8 * scale
+        assert np.abs(sig[sel, 1, 1] - sxx[layer]).max() < 1e-8 * scale
+    assert s_i[0] < s_i[1] < 1.0                                      # the soft layer yields more
+    # per-tet density enters the lumped mass
+    assert np.isclose(op.mass.sum(), np.sum(rho * op.vol))
+
+
 def test_extraction_identities_on_config1_step():
     ep = scenes.config1()
     op = stepper.make_pad(ep.pad.X, ep.pad.tets, 0.3e6, 0.45, 1000.0)

@@ -193,6 +193,29 @@ def seeded_xy(rng, pad, margin):
 # ----------------------------------------------------------------------------
 # the five workloads
 
+def layered_materials(X, tets, z_split, top, bottom):
+    """Per-tet material index of a two-layer pad (the dual-layer gel of
+    Sec. IV-C): 0 above z_split (tet centroid), 1 below; returns (index,
+    [top, bottom])."""
+    zc = X[tets, 2].mean(axis=1)
+    return np.where(zc > z_split, 0, 1).astype(np.int32), [top, bottom]
+
+
+def dual_layer_episode():
+    """18x14x4 mm pad, 12x9x4 cells: a soft 2 mm top layer (E = 0.15 MPa,
+    nu = 0.47, rho = 1050) on a stiffer 2 mm base (E = 1.2 MPa, nu = 0.42,
+    rho = 1200); sphere r = 4 mm pressed 0.6 mm over 8 steps (seed 7)."""
+    pad = box_pad(18 * MM, 14 * MM, 4 * MM, 12, 9, 4, Material(0.15e6, 0.47, 1050.0), name="dual")
+    idx, mats = layered_materials(pad.X, pad.tets, 2 * MM, Material(0.15e6, 0.47, 1050.0),
+                                  Material(1.2e6, 0.42, 1200.0))
+    params = Params()
+    rng = np.random.default_rng(7)
+    r = 4 * MM
+    xy = (rng.uniform(r / 2, pad.dims[0] - r / 2), rng.uniform(r / 2, pad.dims[1] - r / 2))
+    ind = place_indenter(pad, SPHERE, xy, params.dhat, sphere_radius=r)
+    return Episode(pad, ind, 0.6 * MM, 8, params), idx, mats
+
+
 def config1():
     """Single 18x14x4 mm pad, 12x9x3 cells, sphere r = 5 mm at a seeded (x, y)
     on the top face shrunk by r/2 margins (seed 1), 0.5 mm over 10 steps."""
