@@ -14,7 +14,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import contact, fem, material, surface
+from . import contact, fem, friction, material, surface
 
 
 def cauchy_per_tet(pad, x):
@@ -34,11 +34,16 @@ def surface_traction(pad, x, sigma):
     return t, pn, t_tau, n, area
 
 
-def contact_forces(pad, x, inds, prm):
-    """Alg. 2 contact path per candidate vertex.
+def contact_forces(pad, x, inds, prm, fric=None):
+    """Alg. 2 contact path per candidate vertex: f_k = -g_k / dt^2 with g the
+    step potential's contact gradient (barrier, plus friction when `fric`,
+    the step's lagged friction data, is given).
     Returns dict of f, n, area, f_n, f_tau, p, reaction."""
     _, gb, _ = contact.barrier_terms(inds, x[pad.cand], pad.area, prm.dhat, prm.kappa)
     f = -gb
+    if fric is not None:
+        lagged, x_t_c = fric
+        f = f - friction.terms(lagged, x[pad.cand], x_t_c, prm.mu_f, prm.eps_v * prm.dt, 1.0)[1]
     face = pad.tris[pad.is_top.astype(bool)]
     n = surface.vertex_normals(x, face, pad.cand)
     A = surface.vertex_areas(x, face, pad.cand)

@@ -33,7 +33,7 @@ import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from . import contact, fem, material, surface
+from . import contact, fem, friction, material, surface
 
 
 ENERGY_NOISE = 1e-12
@@ -106,6 +106,8 @@ class StepParams:
     quasi_static: bool = False
     gravity: tuple = (0.0, 0.0, 0.0)
     max_halvings: int = 40
+    mu_f: float = 0.0        # friction ratio (0 = frictionless)
+    eps_v: float = 0.01      # friction velocity threshold [m/s]
 
 
 @dataclasses.dataclass
@@ -114,31 +116,49 @@ class StepResult:
     v: np.ndarray
     newton_iters: int
     energies: List[float]
+    fric: object = None      # lagged friction data of the step (None: frictionless)
 
 
-def energy(pad, x, xhat, inds, prm):
+def friction_lag(pad, inds, prm, inds_prev=None):
+    """Lagged friction data of a step from the committed state x_t and the
+    previous indenter poses (None when friction is off)."""
+    if prm.mu_f <= 0:
+        return None
+    prev = inds if inds_prev is None else inds_prev
+    return friction.lag(prev, inds, pad.x[pad.cand], pad.area, prm.dhat, prm.kappa), pad.x[pad.cand].copy()
+
+
+def _friction(pad, x, prm, fric):
+    lagged, x_t_c = fric
+    return friction.terms(lagged, x[pad.cand], x_t_c, prm.mu_f, prm.eps_v * prm.dt, prm.dt ** 2)
+
+
+def energy(pad, x, xhat, inds, prm, fric=None):
     """E(x) of the incremental potential (inf if a candidate penetrates)."""
     h2 = prm.dt ** 2
     Eel = float(np.sum(fem.elastic_energy(x, pad.tets, pad.Dminv, pad.vol,
                                           pad.mu, pad.lam, pad.alpha)))
     Eb, _, _ = contact.barrier_terms(inds, x[pad.cand], pad.area, prm.dhat, prm.kappa)
     Ein = 0.0 if prm.quasi_static else 0.5 * float(np.sum(pad.mass[:, None] * (x - xhat) ** 2))
-    return Ein + h2 * (Eel + Eb)
+    Ef = _friction(pad, x, prm, fric)[0] if fric is not None else 0.0
+    return Ein + h2 * (Eel + Eb) + Ef
 
 
-def gradient(pad, x, xhat, inds, prm):
+def gradient(pad, x, xhat, inds, prm, fric=None):
     """dE/dx as [V,3] (fixed components included, not masked)."""
     h2 = prm.dt ** 2
     ge = fem.elastic_gradient(x, pad.tets, pad.Dminv, pad.vol, pad.mu, pad.lam, pad.alpha)
     g = h2 * fem.scatter_vector(pad.tets, ge, x.shape[0])
     _, gb, _ = contact.barrier_terms(inds, x[pad.cand], pad.area, prm.dhat, prm.kappa)
     g[pad.cand] += h2 * gb
+    if fric is not None:
+        g[pad.cand] += _friction(pad, x, prm, fric)[1]
     if not prm.quasi_static:
         g += pad.mass[:, None] * (x - xhat)
     return g
 
 
-def hessian(pad, x, inds, prm, project=True):
+def hessian(pad, x, inds, prm, project=True, fric=None):
     """Assembled (3V x 3V) sparse Hessian of E."""
     h2 = prm.dt ** 2
     V = x.shape[0]
@@ -153,6 +173,11 @@ def hessian(pad, x, inds, prm, project=True):
     rows = np.concatenate([rows, np.repeat(cd, 3, axis=1).ravel()])
     cols = np.concatenate([cols, np.tile(cd, (1, 3)).ravel()])
     vals = np.concatenate([vals, h2 * Hb.ravel()])
+    if fric is not None:
+        Hf = _friction(pad, x, prm, fric)[2]
+        rows = np.concatenate([rows, np.repeat(cd, 3, axis=1).ravel()])
+        cols = np.concatenate([cols, np.tile(cd, (1, 3)).ravel()])
+        vals = np.concatenate([vals, Hf.ravel()])
     if not prm.quasi_static:
         d = np.arange(3 * V)
         rows = np.concatenate([rows, d])
@@ -201,19 +226,21 @@ def step_filter(pad, x, p, inds):
     return float(min(1.0, np.min(0.9 * d[moving] / pk[moving])))
 
 
-def step(pad, inds, prm, solver="direct", cg_tol=1e-12, verbose=False):
-    """Advance the pad one step under the end-of-step indenter poses `inds`.
+def step(pad, inds, prm, solver="direct", cg_tol=1e-12, verbose=False, inds_prev=None):
+    """Advance the pad one step under the end-of-step indenter poses `inds`
+    (friction lagged under the previous poses `inds_prev`, default `inds`).
     Returns StepResult; pad.x / pad.v are NOT modified (commit separately)."""
     h = prm.dt
     x_t, v_t = pad.x, pad.v
     xhat = x_t + h * v_t + h * h * np.asarray(prm.gravity)[None]
+    fric = friction_lag(pad, inds, prm, inds_prev)
     x = feasible_start(pad, x_t, inds, prm)
     free = pad.free.ravel()
     tol = prm.newton_tol * pad.L_diag
-    energies = [energy(pad, x, xhat, inds, prm)]
+    energies = [energy(pad, x, xhat, inds, prm, fric)]
     for it in range(1, prm.max_newton + 1):
-        g = gradient(pad, x, xhat, inds, prm).ravel()
-        H = hessian(pad, x, inds, prm)
+        g = gradient(pad, x, xhat, inds, prm, fric).ravel()
+        H = hessian(pad, x, inds, prm, fric=fric)
         Hff = H[free][:, free]
         if solver == "direct":
             pf = spla.spsolve(Hff.tocsc(), -g[free])
@@ -228,13 +255,13 @@ def step(pad, inds, prm, solver="direct", cg_tol=1e-12, verbose=False):
         pinf = float(np.max(np.abs(p))) if p.size else 0.0
         if pinf <= tol:
             x = x + a * P3
-            energies.append(energy(pad, x, xhat, inds, prm))
+            energies.append(energy(pad, x, xhat, inds, prm, fric))
             v = (x - x_t) / h
-            return StepResult(x, v, it, energies)
+            return StepResult(x, v, it, energies, fric)
         E0 = energies[-1]
         gTp = float(g @ p)
         for _ in range(prm.max_halvings + 1):
-            E1 = energy(pad, x + a * P3, xhat, inds, prm)
+            E1 = energy(pad, x + a * P3, xhat, inds, prm, fric)
             if E1 <= E0 + 1e-4 * a * gTp + ENERGY_NOISE * abs(E0):
                 break
             a *= 0.5
