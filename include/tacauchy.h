@@ -185,6 +185,21 @@ typedef struct {
                            iterations where the filtered Hessian is stiffer
                            than the energy along the direction. */
   int32_t reserved;     /* 0 */
+  double friction;      /* friction ratio mu >= 0 of the lagged smoothed
+                           Coulomb friction against the indenters (Sec.
+                           III-B: 0.5); 0 = frictionless.  Per contact
+                           vertex k and indenter m, at the step start (x_t
+                           and the previous poses): normal force lambda =
+                           -kappa A_k b'(d/d_hat), normal n = grad(phi);
+                           the indenter point at x_t moves by w = R R_prev^T
+                           (x_t - c_prev) + c - x_t.  The step potential gains
+                           dt^2 mu sum lambda f0(|u|), u = (I - n n^T)((x -
+                           x_t) - w), f0 the C1 cubic/linear mollifier with
+                           threshold eps_v dt.  Previous poses: those of the
+                           pad's last completed step when it had as many
+                           indenters, else the step's own (w = 0). */
+  double eps_v;         /* friction velocity threshold [m/s] > 0 (Sec.
+                           III-B: 0.01) */
 } tc_params;
 
 /* Rigid indenter pose at the end of the step: world x = R y + c. */
@@ -307,7 +322,7 @@ tc_status tc_pad_get_info(const tc_pad* pad, tc_pad_info* out);
 /* Replace solver parameters (precision cannot change; TC_E_INVALID_ARG).
  * TC_E_BUSY while the pad has a request in flight on a server. */
 tc_status tc_pad_set_params(tc_pad* pad, const tc_params* params);
-/* Back to rest: x = X, v = 0. */
+/* Back to rest: x = X, v = 0, no previous indenter poses. */
 tc_status tc_pad_reset(tc_pad* pad);
 /* Release the pad's step scratch back to the context pool (it is taken again
  * by the next step). */
@@ -330,7 +345,9 @@ tc_status tc_step_batch(tc_context* ctx, int32_t n, tc_pad* const* pads,
                         tc_step_stats* stats);
 
 /* Extraction only (Alg. 2 stress/traction/contact) on the committed positions
- * under the given poses: fills SIGMA ... TRACTION_SUM. */
+ * under the given poses: fills SIGMA ... TRACTION_SUM.  Its contact forces are
+ * the barrier's only: friction forces depend on the start state of the step
+ * that produced the positions and come with tc_step's extraction. */
 tc_status tc_extract(tc_pad* pad, int32_t n_ind, const tc_indenter* ind);
 
 /* Inspection: one Newton direction at the committed positions (taken as the
@@ -354,7 +371,7 @@ tc_status tc_pad_write(tc_pad* pad, int32_t field, const void* src, size_t bytes
                        int32_t src_is_device);
 
 /* ------------------------------------------------------ checkpoint/resume */
-/* Serialise x, v and the step counter.  With buf == NULL *bytes receives the
+/* Serialise x, v, the step counter and the previous indenter poses.  With buf == NULL *bytes receives the
  * size needed; otherwise *bytes is the capacity on input and the size written
  * on output.  load restores a buffer written for a pad with the same mesh. */
 tc_status tc_pad_save_state(const tc_pad* pad, void* buf, size_t* bytes);

@@ -382,6 +382,48 @@ __device__ __forceinline__ void load3(const double* p, int i, double v[3]) {
   v[0] = p[3 * i]; v[1] = p[3 * i + 1]; v[2] = p[3 * i + 2];
 }
 
+// ------------------------------------------------ friction (lagged, smoothed)
+
+// C1 mollifier of the slip y with threshold eps: f0 (potential), f1 = f0'
+// as f1 / y (finite at y = 0) and f1'; f1 rises from 0 to 1 on [0, eps].
+__device__ __forceinline__ double fr_f0(double y, double eps) {
+  return y < eps ? -y * y * y / (3.0 * eps * eps) + y * y / eps + eps / 3.0 : y;
+}
+__device__ __forceinline__ double fr_f1_over_y(double y, double eps) {
+  return y < eps ? 2.0 / eps - y / (eps * eps) : 1.0 / y;
+}
+__device__ __forceinline__ double fr_f1p(double y, double eps) {
+  return y < eps ? 2.0 / eps - 2.0 * y / (eps * eps) : 0.0;
+}
+
+__device__ __forceinline__ const double* fr_rec(const EnvDesc& E, int m, int k) {
+  return E.fric + ((size_t)m * E.C + k) * FRIC_STRIDE;
+}
+
+// Tangential slip over the step against one lagged record:
+// u = (I - n n^T)((x - x_t) - w); returns |u|.
+__device__ __forceinline__ double fr_slip(const double* f, const double x[3], const double xt[3], double u[3]) {
+  double r[3];
+  for (int i = 0; i < 3; ++i) r[i] = (x[i] - xt[i]) - f[FRIC_W + i];
+  const double rn = r[0] * f[FRIC_N] + r[1] * f[FRIC_N + 1] + r[2] * f[FRIC_N + 2];
+  for (int i = 0; i < 3; ++i) u[i] = r[i] - rn * f[FRIC_N + i];
+  return sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+}
+
+// Friction part of the step potential per dt^2 at one contact vertex:
+// sum_m mu lambda_m f0(|u_m|).
+__device__ __forceinline__ double fr_energy(const EnvDesc& E, int n_ind, int k, const double x[3],
+                                            const double xt[3]) {
+  double e = 0.0;
+  for (int m = 0; m < n_ind; ++m) {
+    const double* f = fr_rec(E, m, k);
+    if (!(f[FRIC_LAM] > 0)) continue;
+    double u[3];
+    e += E.fr_mu * f[FRIC_LAM] * fr_f0(fr_slip(f, x, xt, u), E.fr_eps);
+  }
+  return e;
+}
+
 // ------------------------------------------------ kinematics (cancellation-free)
 
 // Displacement gradient H = Du Dm^-1 with Du formed from float64 displacement
@@ -522,6 +564,11 @@ __global__ void k_setup_cand_area(const Tile* tiles, int ntiles, const EnvDesc* 
 
 // xhat = x + h v + h^2 g_ext; Newton starts from x (or x + h v on free
 // components when init_guess is set).
+//
+// With friction on, contact vertices also take the friction lag at x_t under
+// the previous poses, per indenter m: lambda = -kappa A b'(phi / d_hat),
+// n = grad(phi), and the motion over the step of the indenter's material
+// point at x_t, w = R R_prev^T (x_t - c_prev) + c - x_t.
 __global__ void k_predict(const Tile* tiles, int ntiles, const EnvDesc* envs) {
   const int t = xcd_tile(ntiles);
   if (t < 0) return;
@@ -535,6 +582,27 @@ __global__ void k_predict(const Tile* tiles, int ntiles, const EnvDesc* envs) {
     const double x = E.x[3 * i + c];
     E.xhat[3 * i + c] = x + h * E.v[3 * i + c] + h * h * E.gravity[c];
     E.xn[3 * i + c] = (E.init_guess && !((fm >> c) & 1)) ? x + h * E.v[3 * i + c] : x;
+  }
+  const int k = E.cand_of_vert[i];
+  if (!(E.fr_mu > 0) || k < 0) return;
+  const EnvPose* P = E.pose;
+  double xt[3], H[3][3];
+  load3(E.x, i, xt);
+  const double kA = E.kappa * E.cand_area[k];
+  for (int m = 0; m < P->n_ind; ++m) {
+    const DevIndenter& A = P->prev[m];
+    const DevIndenter& B = P->ind[m];
+    double phi, n[3], loc[3];
+    sdf_world(A, xt, phi, n, H, false);
+    for (int j = 0; j < 3; ++j)
+      loc[j] = A.R[0 * 3 + j] * (xt[0] - A.c[0]) + A.R[1 * 3 + j] * (xt[1] - A.c[1]) + A.R[2 * 3 + j] * (xt[2] - A.c[2]);
+    double* f = E.fric + ((size_t)m * E.C + k) * FRIC_STRIDE;
+    f[FRIC_LAM] = phi < E.dhat ? -kA * bar1(phi / E.dhat) : 0.0;
+    for (int j = 0; j < 3; ++j) {
+      f[FRIC_N + j] = n[j];
+      f[FRIC_W + j] = B.R[j * 3 + 0] * loc[0] + B.R[j * 3 + 1] * loc[1] + B.R[j * 3 + 2] * loc[2] + B.c[j] - xt[j];
+    }
+    f[7] = 0.0;
   }
 }
 
@@ -787,6 +855,30 @@ __global__ void k_barrier(const Tile* tiles, int ntiles, const EnvDesc* envs) {
   } else if (bmode == 2) {
     for (int i = 0; i < 3; ++i)
       for (int j = 0; j < 3; ++j) H[i][j] = Hn[i][j];
+  }
+  // lagged friction (PSD by construction, added after the filter):
+  // gradient mu lambda (f1/y) u, Hessian mu lambda [f1/y (P - uh uh^T) +
+  // f1' uh uh^T] with P = I - n n^T and uh = u / |u| (u lies in P's range)
+  if (E.fr_mu > 0) {
+    double xt[3];
+    load3(E.x, vi, xt);
+    for (int m = 0; m < P->n_ind; ++m) {
+      const double* f = fr_rec(E, m, k);
+      if (!(f[FRIC_LAM] > 0)) continue;
+      double u[3];
+      const double y = fr_slip(f, x, xt, u);
+      const double c = E.fr_mu * f[FRIC_LAM];
+      const double fy = fr_f1_over_y(y, E.fr_eps), fp = fr_f1p(y, E.fr_eps);
+      const double iy = y > 0 ? 1.0 / y : 0.0;
+      const double uh[3] = {u[0] * iy, u[1] * iy, u[2] * iy};
+      for (int i = 0; i < 3; ++i) {
+        g[i] += c * fy * u[i];
+        for (int j = 0; j < 3; ++j) {
+          const double Pij = (i == j ? 1.0 : 0.0) - f[FRIC_N + i] * f[FRIC_N + j];
+          H[i][j] += c * (fy * (Pij - uh[i] * uh[j]) + fp * uh[i] * uh[j]);
+        }
+      }
+    }
   }
   for (int i = 0; i < 3; ++i) E.gb[3 * k + i] = g[i];
   double* hb = E.Hb + 6 * k;
@@ -1375,7 +1467,7 @@ __global__ void k_env_dir(const EnvDesc* envs, int n) {
 
 // Incremental potential at y = x + alpha d (float64 throughout): tet tiles
 // give sum V_e Psi(F_e), vertex tiles the inertia term, candidate tiles the
-// barrier (+inf on contact).  mode 0: E(x) of pads being initialised (d is
+// barrier (+inf on contact) and friction.  mode 0: E(x) of pads being initialised (d is
 // not read); mode 1: trial step of pads still searching.
 template <typename R>
 __global__ void k_energy(const Tile* tiles, int ntiles, const EnvDesc* envs, int mode) {
@@ -1439,13 +1531,18 @@ __global__ void k_energy(const Tile* tiles, int ntiles, const EnvDesc* envs, int
         sdf_world(P->ind[m], y, phi, g, H, false);
         if (phi < E.dhat) acc += E.kappa * E.cand_area[k] * E.dhat * bar0(phi / E.dhat);
       }
+      if (E.fr_mu > 0) {
+        double xt[3];
+        load3(E.x, vi, xt);
+        acc += fr_energy(E, P->n_ind, k, y, xt);
+      }
     }
   }
   acc = block_reduce(acc, OpSum(), sh);
   if (threadIdx.x == 0) E.part_e[tl.tile] = acc;
 }
 
-// One block per pad: E = inertia + h^2 (elastic + barrier).  mode 0 stores
+// One block per pad: E = inertia + h^2 (elastic + barrier + friction).  mode 0 stores
 // E(x).  mode 1: Armijo test E(x + a d) <= E(x) + 1e-4 a g.d + noise |E(x)|,
 // accept or halve a.
 __global__ void k_env_ls(const EnvDesc* envs, int n, int mode) {
@@ -1651,7 +1748,8 @@ __global__ void k_traction(const Tile* tiles, int ntiles, const EnvDesc* envs) {
   }
 }
 
-// Alg. 2 contact path per contact vertex: f = -dE_b/dx (float64), vertex
+// Alg. 2 contact path per contact vertex: f = -dE_b/dx (plus the friction
+// force after a step with friction on; float64), vertex
 // normal = normalised sum of incident contact-face e1 x e2, A = 1/3 incident
 // area, f_n = (f.n) n, f_tau = f - f_n, p = |f| / A; partial sum of f.
 __global__ void k_contact(const Tile* tiles, int ntiles, const EnvDesc* envs) {
@@ -1678,6 +1776,20 @@ __global__ void k_contact(const Tile* tiles, int ntiles, const EnvDesc* envs) {
       if (phi < E.dhat) {
         const double b1 = bar1(phi / E.dhat);
         for (int c = 0; c < 3; ++c) f[c] -= kA * b1 * g[c];
+      }
+    }
+    // friction force of the step, -mu lambda (f1/y) u (extraction after a
+    // step only: the lag belongs to that step's start state)
+    if (S->mode == 0 && E.fr_mu > 0) {
+      double xt[3];
+      load3(E.x, vi, xt);
+      for (int m = 0; m < P->n_ind; ++m) {
+        const double* fr = fr_rec(E, m, k);
+        if (!(fr[FRIC_LAM] > 0)) continue;
+        double u[3];
+        const double y = fr_slip(fr, xv, xt, u);
+        const double c = E.fr_mu * fr[FRIC_LAM] * fr_f1_over_y(y, E.fr_eps);
+        for (int q = 0; q < 3; ++q) f[q] -= c * u[q];
       }
     }
     double nn[3] = {0, 0, 0}, A = 0;

@@ -115,6 +115,9 @@ struct tc_pad {
   double mu[tc::MAX_MAT], lam[tc::MAX_MAT], alpha[tc::MAX_MAT], rho[tc::MAX_MAT];
   double bbox_diag = 0.0;
   int64_t step_count = 0;
+  // indenter poses of the last completed step (friction lag), n_prev = 0: none
+  int n_prev = 0;
+  tc_indenter prev[TC_MAX_INDENTERS];
   uint64_t desc_version = 0;         // bumped whenever the device descriptor changes
   std::atomic<int> busy{0};
   std::atomic<int> in_flight{0};     // a step of this pad is on the device (server slot)
@@ -175,7 +178,11 @@ tc_status build_plan(tc_context* ctx, int n, tc_pad* const* pads, const int* slo
 bool plan_matches(const BatchPlan* P, tc_context* ctx, int n, tc_pad* const* pads, const int* slots,
                   const SlotPool& pool);
 void account_bytes(tc_context* ctx, const tc_pad* pad, const EnvState& s);
-void init_state(EnvState& S, EnvPose& Q, int mode, int n_ind, const tc_indenter* ind);
+// Step-start state and poses of one slot; the friction lag takes the pad's
+// previous poses when it has as many, else the current ones.
+void init_state(EnvState& S, EnvPose& Q, int mode, int n_ind, const tc_indenter* ind, const tc_pad* pad);
+// After a completed step: its poses become the pad's previous poses.
+void remember_pose(tc_pad* pad, const EnvPose& Q);
 void fill_stats(tc_step_stats& o, const EnvState& S, double ms);
 
 // Sequences the kernels of one Newton iteration over a plan.  Pad i of the

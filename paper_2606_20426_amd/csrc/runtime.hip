@@ -163,14 +163,23 @@ void pool_free(SlotPool& p) {
   p = SlotPool{};
 }
 
-void init_state(EnvState& S, EnvPose& Q, int mode, int n_ind, const tc_indenter* ind) {
+void init_state(EnvState& S, EnvPose& Q, int mode, int n_ind, const tc_indenter* ind, const tc_pad* pad) {
   std::memset(&S, 0, sizeof S);
   S.mode = mode;
   S.phase = mode == 0 ? PH_INIT : PH_FINISH;
   S.status = TC_OK;
   std::memset(&Q, 0, sizeof Q);
   Q.n_ind = n_ind;
-  for (int m = 0; m < n_ind; ++m) std::memcpy(&Q.ind[m], &ind[m], sizeof(DevIndenter));
+  const bool has_prev = pad && pad->n_prev == n_ind;
+  for (int m = 0; m < n_ind; ++m) {
+    std::memcpy(&Q.ind[m], &ind[m], sizeof(DevIndenter));
+    std::memcpy(&Q.prev[m], has_prev ? &pad->prev[m] : &ind[m], sizeof(DevIndenter));
+  }
+}
+
+void remember_pose(tc_pad* pad, const EnvPose& Q) {
+  pad->n_prev = Q.n_ind;
+  for (int m = 0; m < Q.n_ind; ++m) std::memcpy(&pad->prev[m], &Q.ind[m], sizeof(tc_indenter));
 }
 
 void fill_stats(tc_step_stats& o, const EnvState& S, double ms) {
@@ -267,7 +276,7 @@ static void resolve_timing(tc_context* ctx) {
 // ------------------------------------------------------------ scratch layout
 
 struct ScratchLayout {
-  size_t Ke, A, xn, xhat, g, d, r, z, p0, p1, q, Pinv, gb, Hb;
+  size_t Ke, A, xn, xhat, g, d, r, z, p0, p1, q, Pinv, gb, Hb, fric;
   size_t prz, ppq, pg2, pe, pdir, pfilt, pc3, ps3;
   size_t total;
 };
@@ -291,6 +300,7 @@ static ScratchLayout scratch_layout(const tc_pad* p) {
   L.Pinv = take(6 * V * R);
   L.gb = take(24 * C);
   L.Hb = take(48 * C);
+  L.fric = take(p->params.friction > 0 ? 8 * FRIC_STRIDE * MAX_IND * C : 0);
   const size_t nv = cdiv(V, 64), nt = cdiv(T, 64), nc = cdiv(C, 64), ns = cdiv(std::max<size_t>(S, 1), 64);
   L.prz = take(8 * nv);
   L.ppq = take(8 * ((size_t)cdiv(V, 2) + 1));
@@ -322,6 +332,7 @@ static void bind_scratch_desc(tc_pad* p) {
   E.Pinv = b + L.Pinv;
   E.gb = (double*)(b + L.gb);
   E.Hb = (double*)(b + L.Hb);
+  E.fric = (double*)(b + L.fric);
   E.part_rz = (double*)(b + L.prz);
   E.part_pq = (double*)(b + L.ppq);
   E.part_g2 = (double*)(b + L.pg2);
@@ -674,7 +685,8 @@ static double kernel_bytes(KernelId k, const tc_pad* p) {
     case KernelId::element: return T * (16 + 106 * R) + V * 48;
     case KernelId::asm_diag: return T * (16 + 36 * R) + V * (93 + 24 * R);
     case KernelId::asm_off: return T * (48 + 108 * R) + (W - 1) * V * (8 + 9 * R);
-    case KernelId::energy: return T * (16 + 10 * R) + V * (56 + 3 * R) + C * 40;
+    case KernelId::energy:   // friction: x_t and one indenter's lag record per contact vertex
+      return T * (16 + 10 * R) + V * (56 + 3 * R) + C * 40 + (p->params.friction > 0 ? C * 88 : 0);
     case KernelId::sigma: return T * (16 + 15 * R) + V * 24;
     case KernelId::traction: return S * (17 + 24 + 6 * R + 9 * R) + V * 24;
     default: return 0.0;
@@ -735,7 +747,7 @@ tc_status run_batch(tc_context* ctx, int n, tc_pad* const* pads, const int32_t* 
   BatchPlan* P = ctx->plan.get();
   off = 0;
   for (int i = 0; i < n; ++i) {
-    init_state(pool.h_state[i], pool.h_pose[i], mode, n_ind[i], ind ? ind + off : nullptr);
+    init_state(pool.h_state[i], pool.h_pose[i], mode, n_ind[i], ind ? ind + off : nullptr, pads[i]);
     off += n_ind[i];
   }
   static_assert(sizeof(DevIndenter) == sizeof(tc_indenter), "indenter layout");
@@ -761,7 +773,10 @@ tc_status run_batch(tc_context* ctx, int n, tc_pad* const* pads, const int32_t* 
   const double ms = now_ms() - t0;
   for (int i = 0; i < n; ++i) {
     const EnvState& S = pool.h_state[i];
-    if (S.status == TC_OK && mode == 0) pads[i]->step_count++;
+    if (S.status == TC_OK && mode == 0) {
+      pads[i]->step_count++;
+      remember_pose(pads[i], pool.h_pose[i]);
+    }
     if (S.status != TC_OK && first == TC_OK) first = S.status;
     if (stats) fill_stats(stats[i], S, ms);
     if (ctx->timing) account_bytes(ctx, pads[i], S);
@@ -793,7 +808,7 @@ tc_status newton_direction(tc_pad* pad, int n_ind, const tc_indenter* ind, doubl
     if ((s = build_plan(ctx, 1, pads, &slot, pool, ctx->plan))) return s;
   }
   BatchPlan* P = ctx->plan.get();
-  init_state(pool.h_state[0], pool.h_pose[0], 0, n_ind, ind);
+  init_state(pool.h_state[0], pool.h_pose[0], 0, n_ind, ind, pad);
   pool.h_state[0].force_tight = 1;   // CG straight to the convergence tolerance
   TC_HIP(hipMemcpyAsync(pool.d_state, pool.h_state, sizeof(EnvState), hipMemcpyHostToDevice, ctx->stream));
   TC_HIP(hipMemcpyAsync(pool.d_pose, pool.h_pose, sizeof(EnvPose), hipMemcpyHostToDevice, ctx->stream));
@@ -941,6 +956,8 @@ tc_status tc_params_default(tc_params* out) {
   out->cg_eta_max = 0.5;
   out->ls_expand = 0;
   out->reserved = 0;
+  out->friction = 0.0;
+  out->eps_v = 0.01;
   return TC_OK;
 }
 
@@ -1335,7 +1352,14 @@ tc_status tc_pad_set_params(tc_pad* pad, const tc_params* params) {
   if ((params->precision == TC_PREC_FP64) != pad->fp64) return set_error(TC_E_INVALID_ARG, "precision is fixed at pad creation");
   std::lock_guard<std::recursive_mutex> lk(pad->ctx->mu);
   if (pad->busy.load()) return set_error(TC_E_BUSY, "pad has a request in flight on a server");
+  const bool fric_layout = (pad->params.friction > 0) != (params->friction > 0);
   pad->params = *params;
+  if (fric_layout) {
+    // the step scratch holds the friction lag only while friction is on
+    (void)hipStreamSynchronize(pad->ctx->stream);
+    release_scratch(pad);
+    pad->scratch_need = scratch_layout(pad).total;
+  }
   EnvDesc& E = pad->desc;
   E.h = params->dt;
   E.dhat = params->dhat;
@@ -1349,6 +1373,8 @@ tc_status tc_pad_set_params(tc_pad* pad, const tc_params* params) {
   E.cg_eta_max = params->cg_eta_max;
   E.init_guess = params->init_guess;
   E.ls_expand = params->ls_expand;
+  E.fr_mu = params->friction;
+  E.fr_eps = params->eps_v * params->dt;
   for (int c = 0; c < 3; ++c) E.gravity[c] = params->gravity[c];
   E.quasi_static = params->quasi_static;
   E.max_cg = params->max_cg;
@@ -1370,6 +1396,7 @@ tc_status tc_pad_reset(tc_pad* pad) {
   TC_HIP(hipMemsetAsync(pad->desc.v, 0, 24 * (size_t)pad->V, ctx->stream));
   TC_HIP(hipStreamSynchronize(ctx->stream));
   pad->step_count = 0;
+  pad->n_prev = 0;
   return TC_OK;
 }
 
@@ -1442,39 +1469,54 @@ tc_status tc_pad_write(tc_pad* pad, int32_t field, const void* src, size_t bytes
   return TC_OK;
 }
 
-// state buffer: magic, version, V, T, step count, then x and v
+// state buffer: magic, version, V, T, step count, then x and v; version 2
+// appends the number of previous indenter poses and TC_MAX_INDENTERS poses
 static const uint64_t kStateMagic = 0x5441434155434859ULL;
+static const size_t kPoseBytes = 8 + sizeof(tc_indenter) * TC_MAX_INDENTERS;
 
 tc_status tc_pad_save_state(const tc_pad* pad, void* buf, size_t* bytes) {
   if (!pad || !bytes) return set_error(TC_E_INVALID_ARG, "pad or bytes is null");
-  const size_t need = 40 + 48 * (size_t)pad->V;
+  const size_t xv = 48 * (size_t)pad->V;
+  const size_t need = 40 + xv + kPoseBytes;
   if (!buf) { *bytes = need; return TC_OK; }
   if (*bytes < need) return set_error(TC_E_INVALID_ARG, "buffer too small");
-  uint64_t head[5] = {kStateMagic, 1, (uint64_t)pad->V, (uint64_t)pad->T, (uint64_t)pad->step_count};
+  uint64_t head[5] = {kStateMagic, 2, (uint64_t)pad->V, (uint64_t)pad->T, (uint64_t)pad->step_count};
   std::memcpy(buf, head, 40);
   char* b = static_cast<char*>(buf) + 40;
   tc_status s = tc_pad_read(pad, TC_F_POSITIONS, b, 24 * (size_t)pad->V, 0);
   if (s) return s;
   s = tc_pad_read(pad, TC_F_VELOCITIES, b + 24 * (size_t)pad->V, 24 * (size_t)pad->V, 0);
   if (s) return s;
+  const uint64_t np = (uint64_t)pad->n_prev;
+  std::memcpy(b + xv, &np, 8);
+  std::memset(b + xv + 8, 0, kPoseBytes - 8);
+  std::memcpy(b + xv + 8, pad->prev, sizeof(tc_indenter) * pad->n_prev);
   *bytes = need;
   return TC_OK;
 }
 
 tc_status tc_pad_load_state(tc_pad* pad, const void* buf, size_t bytes) {
   if (!pad || !buf) return set_error(TC_E_INVALID_ARG, "pad or buf is null");
-  const size_t need = 40 + 48 * (size_t)pad->V;
-  if (bytes < need) return set_error(TC_E_INVALID_ARG, "buffer too small");
+  const size_t xv = 48 * (size_t)pad->V;
+  if (bytes < 40 + xv) return set_error(TC_E_INVALID_ARG, "buffer too small");
   uint64_t head[5];
   std::memcpy(head, buf, 40);
-  if (head[0] != kStateMagic || head[1] != 1) return set_error(TC_E_INVALID_ARG, "not a pad state buffer");
+  if (head[0] != kStateMagic || (head[1] != 1 && head[1] != 2)) return set_error(TC_E_INVALID_ARG, "not a pad state buffer");
   if (head[2] != (uint64_t)pad->V || head[3] != (uint64_t)pad->T) return set_error(TC_E_INVALID_ARG, "state is for a different mesh");
+  if (head[1] == 2 && bytes < 40 + xv + kPoseBytes) return set_error(TC_E_INVALID_ARG, "buffer too small");
   const char* b = static_cast<const char*>(buf) + 40;
+  uint64_t np = 0;
+  if (head[1] == 2) {
+    std::memcpy(&np, b + xv, 8);
+    if (np > TC_MAX_INDENTERS) return set_error(TC_E_INVALID_ARG, "corrupt pose count in state buffer");
+  }
   tc_status s = tc_pad_write(pad, TC_F_POSITIONS, b, 24 * (size_t)pad->V, 0);
   if (s) return s;
   s = tc_pad_write(pad, TC_F_VELOCITIES, b + 24 * (size_t)pad->V, 24 * (size_t)pad->V, 0);
   if (s) return s;
   pad->step_count = (int64_t)head[4];
+  pad->n_prev = (int)np;
+  if (np) std::memcpy(pad->prev, b + xv + 8, sizeof(tc_indenter) * np);
   return TC_OK;
 }
 

@@ -138,7 +138,7 @@ void tc_server::loop() {
     const int n = (int)pads.size();
     for (int s : fresh) {
       const Req& r = slot_req[s];
-      init_state(pool.h_state[s], pool.h_pose[s], 0, r.n_ind, r.ind);
+      init_state(pool.h_state[s], pool.h_pose[s], 0, r.n_ind, r.ind, r.pad);
       (void)hipMemcpyAsync(pool.d_state + s, pool.h_state + s, sizeof(EnvState), hipMemcpyHostToDevice, ctx->stream);
       (void)hipMemcpyAsync(pool.d_pose + s, pool.h_pose + s, sizeof(EnvPose), hipMemcpyHostToDevice, ctx->stream);
     }
@@ -168,7 +168,10 @@ void tc_server::loop() {
       res.t_done_ms = t;
       fill_stats(res.stats, S, t - r.t_admit);
       res.stats.status = res.status;
-      if (res.status == TC_OK) r.pad->step_count++;
+      if (res.status == TC_OK) {
+        r.pad->step_count++;
+        remember_pose(r.pad, pool.h_pose[s]);
+      }
       if (ctx->timing) account_bytes(ctx, r.pad, S);
       r.pad->in_flight.store(0);
       r.pad->busy.store(0);

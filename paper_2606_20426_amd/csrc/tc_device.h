@@ -34,12 +34,20 @@ struct DevIndenter {
   double prm[4];
 };
 
-// Indenter poses of one pad for the current step (uploaded at step start).
+// Indenter poses of one pad for the current step (uploaded at step start)
+// and the poses the friction lag is taken under (the previous step's, or
+// the current ones when there is none).
 struct EnvPose {
   int32_t n_ind;
   int32_t reserved;
   DevIndenter ind[MAX_IND];
+  DevIndenter prev[MAX_IND];
 };
+
+// Lagged friction record of one (indenter, contact vertex) pair, float64:
+// normal force lambda (0 = no friction), normal n, indenter point motion w.
+constexpr int FRIC_STRIDE = 8;
+constexpr int FRIC_LAM = 0, FRIC_N = 1, FRIC_W = 4;
 
 // Life cycle of a pad's step inside a batch.
 enum Phase : int32_t {
@@ -149,6 +157,7 @@ struct EnvDesc {
   void* Pinv;                // real [V][6] symmetric preconditioner blocks
   double* gb;                // [C][3] barrier gradient
   double* Hb;                // [C][6] projected barrier Hessian
+  double* fric;              // [MAX_IND][C][FRIC_STRIDE] lagged friction (friction on)
   double* part_rz;           // [n_vt]
   double* part_pq;           // [n_spt]
   double* part_g2;           // [n_vt]
@@ -166,6 +175,7 @@ struct EnvDesc {
   double gravity[3];
   int32_t quasi_static, max_cg, max_newton, max_halvings, precond, cg_forcing, hess_proj, init_guess;
   int32_t ls_expand;
+  double fr_mu, fr_eps;      // friction ratio (0 = off) and slip threshold eps_v h [m]
 };
 
 // One block of a launch: pad `env`, tile index `tile` within that pad's

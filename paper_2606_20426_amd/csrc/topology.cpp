@@ -88,6 +88,8 @@ tc_status validate_params(const tc_params* p, std::string& err) {
   if (p->ls_expand < 0 || p->ls_expand > 16) { err = "ls_expand must be in 0..16"; return TC_E_INVALID_ARG; }
   if (p->hess_proj < 0 || p->hess_proj > 15 || (p->hess_proj & 3) == 3) { err = "hess_proj: element mode 0..2 in bits 0-1, barrier mode 0..3 in bits 2-3"; return TC_E_INVALID_ARG; }
   if (p->init_guess != 0 && p->init_guess != 1) { err = "init_guess must be 0 or 1"; return TC_E_INVALID_ARG; }
+  if (!finite(p->friction) || p->friction < 0) { err = "friction must be finite and >= 0"; return TC_E_INVALID_ARG; }
+  if (p->friction > 0 && (!finite(p->eps_v) || !(p->eps_v > 0))) { err = "eps_v must be finite and > 0 with friction on"; return TC_E_INVALID_ARG; }
   for (int c = 0; c < 3; ++c)
     if (!finite(p->gravity[c])) { err = "gravity must be finite"; return TC_E_INVALID_ARG; }
   return TC_OK;

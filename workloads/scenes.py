@@ -216,6 +216,30 @@ def dual_layer_episode():
     return Episode(pad, ind, 0.6 * MM, 8, params), idx, mats
 
 
+def _rot_z(angle):
+    c, s = math.cos(angle), math.sin(angle)
+    return np.array([[c, -s, 0], [s, c, 0], [0, 0, 1]], float)
+
+
+def press_slide_episode():
+    """Friction workload (friction ratio 0.5, eps_v = 0.01 m/s of Sec.
+    III-B): config1's 18x14x4 mm pad (12x9x3 cells), sphere r = 5 mm pressed
+    0.5 mm over 4 steps at (6, 7) mm, then slid 0.25 mm per step along +x
+    while twisting 3 degrees per step about its vertical axis, 6 steps.
+    Returns (pad, params, [pose of step 1 .. 10])."""
+    pad = box_pad(18 * MM, 14 * MM, 4 * MM, 12, 9, 3, Material(0.3e6, 0.45, 1000.0), name="slide")
+    params = Params()
+    r = 5 * MM
+    start = place_indenter(pad, SPHERE, (6 * MM, 7 * MM), params.dhat, sphere_radius=r)
+    poses = []
+    for s in range(1, 11):
+        depth = 0.5 * MM * min(s, 4) / 4
+        k = max(s - 4, 0)
+        c = start.c + np.array([0.25 * MM * k, 0.0, -depth])
+        poses.append(Indenter(SPHERE, start.prm, _rot_z(math.radians(3.0 * k)), c))
+    return pad, params, poses
+
+
 def config1():
     """Single 18x14x4 mm pad, 12x9x3 cells, sphere r = 5 mm at a seeded (x, y)
     on the top face shrunk by r/2 margins (seed 1), 0.5 mm over 10 steps."""
