@@ -19,12 +19,27 @@ Indenters are rigid: local coordinates y = R^T (x - c).  Signed distances
     texture  plate occupying y_z >= eta(y_x, y_y), eta = A sin(k y_x) sin(k y_y),
              k = 2 pi / lambda:  phi = (eta - y_z) / sqrt(1 + (k A)^2)
              (a 1-Lipschitz lower bound of the distance).
+    mesh     closed triangle mesh (V, F) in the local frame: signed distance
+             to its surface (meshsdf).
 """
 from __future__ import annotations
 
 import numpy as np
 
-SPHERE, CYLINDER, BOX, TORUS, TEXTURE = 0, 1, 2, 3, 4
+from . import meshsdf
+
+SPHERE, CYLINDER, BOX, TORUS, TEXTURE, MESH = 0, 1, 2, 3, 4, 5
+
+_MESHES = {}
+
+
+def _mesh_data(mesh):
+    """Tables of a rigid mesh indenter's (V, F), built once per mesh object."""
+    hit = _MESHES.get(id(mesh))
+    if hit is None or hit[0] is not mesh:
+        hit = (mesh, meshsdf.MeshData(*mesh))
+        _MESHES[id(mesh)] = hit
+    return hit[1]
 
 
 def barrier(s):
@@ -176,7 +191,10 @@ def sdf(ind, x):
     """World-frame phi, grad, hess for indenter `ind` (shape, prm, R, c)."""
     R = np.asarray(ind.R, dtype=np.float64)
     y = (np.atleast_2d(x) - np.asarray(ind.c)[None]) @ R     # = R^T (x - c)
-    phi, g, H = sdf_local(ind.shape, ind.prm, y)
+    if ind.shape == MESH:
+        phi, g, H = meshsdf.sdf_local(_mesh_data(ind.mesh), y)
+    else:
+        phi, g, H = sdf_local(ind.shape, ind.prm, y)
     return phi, g @ R.T, R[None] @ H @ R.T[None]
 
 

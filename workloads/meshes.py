@@ -159,3 +159,65 @@ def sizing_profile_axis(length, centre, h_f, inner=0.4, band=0.2, ratio=8.0,
     xs = np.unique(np.array(left + [centre] + right, dtype=np.float64))
     xs[0], xs[-1] = 0.0, float(length)
     return xs
+
+
+# ----------------------------------------------------------------------------
+# closed triangle surfaces for rigid mesh indenters (local frame, outward
+# counter-clockwise triangles, every edge shared by exactly two triangles)
+
+def box_surface(a, b, c):
+    """Box of half extents (a, b, c): 8 vertices, 12 triangles."""
+    V = np.array([[sx * a, sy * b, sz * c] for sz in (-1, 1) for sy in (-1, 1) for sx in (-1, 1)], float)
+    quads = [(0, 2, 3, 1), (4, 5, 7, 6), (0, 1, 5, 4), (2, 6, 7, 3), (0, 4, 6, 2), (1, 3, 7, 5)]
+    F = []
+    for q in quads:
+        F += [(q[0], q[1], q[2]), (q[0], q[2], q[3])]
+    return V, np.array(F, np.int32)
+
+
+def icosphere(r, level):
+    """Sphere of radius r: icosahedron subdivided `level` times, vertices
+    pushed to the sphere."""
+    t = (1 + 5 ** 0.5) / 2
+    V = [(-1, t, 0), (1, t, 0), (-1, -t, 0), (1, -t, 0), (0, -1, t), (0, 1, t), (0, -1, -t), (0, 1, -t),
+         (t, 0, -1), (t, 0, 1), (-t, 0, -1), (-t, 0, 1)]
+    F = [(0, 11, 5), (0, 5, 1), (0, 1, 7), (0, 7, 10), (0, 10, 11), (1, 5, 9), (5, 11, 4), (11, 10, 2),
+         (10, 7, 6), (7, 1, 8), (3, 9, 4), (3, 4, 2), (3, 2, 6), (3, 6, 8), (3, 8, 9), (4, 9, 5),
+         (2, 4, 11), (6, 2, 10), (8, 6, 7), (9, 8, 1)]
+    V = [np.array(v, float) / np.linalg.norm(v) for v in V]
+    for _ in range(level):
+        mid = {}
+
+        def midpoint(i, j):
+            key = (min(i, j), max(i, j))
+            if key not in mid:
+                m = V[i] + V[j]
+                V.append(m / np.linalg.norm(m))
+                mid[key] = len(V) - 1
+            return mid[key]
+        G = []
+        for a, b, c in F:
+            ab, bc, ca = midpoint(a, b), midpoint(b, c), midpoint(c, a)
+            G += [(a, ab, ca), (b, bc, ab), (c, ca, bc), (ab, bc, ca)]
+        F = G
+    return r * np.array(V), np.array(F, np.int32)
+
+
+def torus_surface(R, r, nu, nv):
+    """Torus about the local z axis (ring radius R, tube radius r), nu x nv
+    quads split into triangles."""
+    V = []
+    for i in range(nu):
+        u = 2 * np.pi * i / nu
+        for j in range(nv):
+            v = 2 * np.pi * j / nv
+            V.append(((R + r * np.cos(v)) * np.cos(u), (R + r * np.cos(v)) * np.sin(u), r * np.sin(v)))
+    F = []
+    for i in range(nu):
+        for j in range(nv):
+            a = i * nv + j
+            b = ((i + 1) % nu) * nv + j
+            c = ((i + 1) % nu) * nv + (j + 1) % nv
+            d = i * nv + (j + 1) % nv
+            F += [(a, b, c), (a, c, d)]
+    return np.array(V, float), np.array(F, np.int32)

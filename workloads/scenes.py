@@ -30,9 +30,9 @@ from . import meshes
 
 MM = 1e-3
 
-SPHERE, CYLINDER, BOX, TORUS, TEXTURE = 0, 1, 2, 3, 4
+SPHERE, CYLINDER, BOX, TORUS, TEXTURE, MESH = 0, 1, 2, 3, 4, 5
 SHAPE_NAMES = {SPHERE: "sphere", CYLINDER: "cylinder", BOX: "cube_edge",
-               TORUS: "torus", TEXTURE: "texture"}
+               TORUS: "torus", TEXTURE: "texture", MESH: "mesh"}
 
 
 @dataclasses.dataclass
@@ -62,11 +62,12 @@ class Indenter:
     prm: tuple               # shape parameters [m]
     R: np.ndarray            # 3x3 rotation, local -> world
     c: np.ndarray            # centre at the start of the episode [m]
+    mesh: Optional[tuple] = None   # (V [n,3], F [m,3]) local frame, shape MESH only
 
     def at_depth(self, depth):
         """Pose after travelling `depth` metres along world -z."""
         return Indenter(self.shape, self.prm, self.R.copy(),
-                        self.c - np.array([0.0, 0.0, depth]))
+                        self.c - np.array([0.0, 0.0, depth]), self.mesh)
 
 
 @dataclasses.dataclass
