@@ -71,12 +71,17 @@ typedef int32_t tc_status;
  *   TORUS    prm[0] = ring radius, prm[1] = tube radius, axis z
  *   TEXTURE  prm[0] = amplitude A, prm[1] = period L: plate occupying
  *            y_z >= A sin(2 pi y_x / L) sin(2 pi y_y / L); phi is the
- *            1-Lipschitz bound (eta - y_z) / sqrt(1 + (2 pi A / L)^2). */
+ *            1-Lipschitz bound (eta - y_z) / sqrt(1 + (2 pi A / L)^2).
+ *   MESH     a closed rigid triangle mesh registered with
+ *            tc_rigid_mesh_create; tc_indenter.reserved = its id, prm
+ *            unused (finite).  phi is the signed distance to its surface. */
 #define TC_SPHERE   0
 #define TC_CYLINDER 1
 #define TC_BOX      2
 #define TC_TORUS    3
 #define TC_TEXTURE  4
+#define TC_MESH     5
+#define TC_MAX_MESHES 64     /* rigid meshes per context */
 
 #define TC_MAX_INDENTERS 5   /* per pad and step */
 #define TC_MAX_MATERIALS 8   /* per pad */
@@ -204,8 +209,8 @@ typedef struct {
 
 /* Rigid indenter pose at the end of the step: world x = R y + c. */
 typedef struct {
-  int32_t shape;        /* TC_SPHERE ... TC_TEXTURE */
-  int32_t reserved;
+  int32_t shape;        /* TC_SPHERE ... TC_MESH */
+  int32_t reserved;     /* TC_MESH: mesh id; otherwise 0 */
   double R[9];          /* row-major rotation, orthonormal to 1e-9, det +1 */
   double c[3];          /* centre [m] */
   double prm[4];        /* shape parameters [m], see TC_SPHERE ... */
@@ -319,6 +324,73 @@ tc_status tc_pad_create(tc_context* ctx, const tc_mesh* mesh,
                         const tc_params* params, tc_pad** out);
 tc_status tc_pad_destroy(tc_pad* pad);
 tc_status tc_pad_get_info(const tc_pad* pad, tc_pad_info* out);
+/* ------------------------------------------------------- mesh refinement */
+/* Contact sizing field of Sec. III-A: the thickness axis (thinnest bounding-
+ * box axis unless given) and the contact face at its maximum (side +1) or
+ * minimum (-1); points within band x thickness of that face form the contact
+ * band, where a radial profile over the two planar axes applies with the
+ * radius normalised by the planar half-extents,
+ *   rho = |((p_u - c_u) / h_u, (p_v - c_v) / h_v)|   (u < v the planar axes):
+ * h = l_contact for rho <= inner, l_global for rho >= inner + transition,
+ * cosine blend l_g + (l_c - l_g) (1 + cos(pi (rho - inner) / transition)) / 2
+ * between; h = l_global outside the band.  Defaults (tc_sizing_default):
+ * band 0.15, inner 0.4, transition 0.2, l_contact 0.8 mm, l_global 3.2 mm,
+ * centre NaN = bounding-box centre, max_tets 2^24. */
+typedef struct {
+  int32_t axis;         /* 0..2, or -1 = thinnest bounding-box axis */
+  int32_t side;         /* +1 or -1 */
+  double band, inner, transition;
+  double l_contact, l_global;   /* [m] > 0 */
+  double centre[2];     /* (c_u, c_v) [m]; NaN = bounding-box centre */
+  int64_t max_tets;     /* refinement stops with TC_E_INVALID_ARG beyond this */
+} tc_sizing;
+
+tc_status tc_sizing_default(tc_sizing* out);   /* host only */
+
+/* Host only: conforming adaptive refinement of a valid tet mesh by
+ * terminal-edge bisection under the field above (the paper imposes the
+ * field inside WildMeshing's tetrahedralisation; here it drives bisection of
+ * a given mesh).  h is read as a cell size: edge ab is too long when
+ * |x_a - x_b|^2 > 3 h(m)^2, m its midpoint.  Edges are ordered by (squared
+ * length, smaller vertex id, larger vertex id); tets are visited first-in
+ * first-out from 0 .. T-1; while the visited tet has a too-long edge, its
+ * longest edge is replaced by the largest longest-edge of the tets around it
+ * until that is the edge itself (terminal edge), which is bisected: vertex
+ * m = 0.5 (x_a + x_b) is appended and each tet around ab (a < b), in
+ * ascending index, keeps its index with b replaced by m while a new tet
+ * with a replaced by m (same material) is appended; both are queued.  The
+ * result is conforming, positively oriented and reproducible bit for bit.
+ * Input vertices keep their indices.  Outputs (host): xyz_out [cap_verts][3],
+ * tets_out [cap_tets][4], mat_out [cap_tets] (may be NULL); n_verts_out and
+ * n_tets_out receive the sizes, also when the capacities are too small
+ * (then TC_E_INVALID_ARG and nothing is written). */
+tc_status tc_refine_mesh(const tc_mesh* in, const tc_sizing* sizing, int32_t cap_verts, int32_t cap_tets,
+                         double* xyz_out, int32_t* tets_out, int32_t* mat_out, int32_t* n_verts_out,
+                         int32_t* n_tets_out);
+
+/* ------------------------------------------------------- rigid meshes */
+/* Register a rigid triangle mesh as an indenter shape (the rigid objects of
+ * Sec. III-B and the grasped test objects of Sec. IV-E).  verts: host
+ * [n_verts][3] float64 in the indenter's local frame [m]; tris: host
+ * [n_tris][3] int32.  The surface must be closed and consistently oriented
+ * with outward normals: every edge shared by exactly two triangles in
+ * opposite directions, no zero-area triangle, positive enclosed volume,
+ * n_tris <= 2^24 (TC_E_INVALID_ARG otherwise).  The library copies the mesh
+ * to the device with its bounding-volume hierarchy and pseudonormals
+ * (context memory, counted in the budget); *id receives the handle for
+ * tc_indenter.reserved.  Against it phi is the signed distance to the
+ * surface: nearest point over the triangles, sign from the angle-weighted
+ * pseudonormal of the nearest feature; contact acts on pad vertices (as
+ * for the analytic shapes), the collision-free step bound is conservative
+ * advancement along each vertex's segment. */
+tc_status tc_rigid_mesh_create(tc_context* ctx, int32_t n_verts, const double* verts, int32_t n_tris,
+                               const int32_t* tris, int32_t* id);
+/* Host only: the checks of tc_rigid_mesh_create without a context. */
+tc_status tc_validate_rigid_mesh(int32_t n_verts, const double* verts, int32_t n_tris, const int32_t* tris);
+/* Release a mesh.  TC_E_BUSY while any pad of the context has a request on a
+ * server (it may name the mesh); TC_E_INVALID_ARG for an unknown id. */
+tc_status tc_rigid_mesh_destroy(tc_context* ctx, int32_t id);
+
 /* Replace solver parameters (precision cannot change; TC_E_INVALID_ARG).
  * TC_E_BUSY while the pad has a request in flight on a server. */
 tc_status tc_pad_set_params(tc_pad* pad, const tc_params* params);

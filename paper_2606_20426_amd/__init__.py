@@ -15,7 +15,7 @@ from typing import Iterable, List, Optional, Sequence
 import numpy as np
 
 from . import _abi
-from ._abi import (BOX, CYLINDER, FIELDS, PREC_FP64, PREC_MIXED, PRECOND_BLOCK_JACOBI,  # noqa: F401
+from ._abi import (BOX, CYLINDER, FIELDS, MESH, PREC_FP64, PREC_MIXED, PRECOND_BLOCK_JACOBI,  # noqa: F401
                    PRECOND_JACOBI, SPHERE, TEXTURE, TORUS, TcError, check, load)
 
 # Live library objects, closed in dependency order (servers, pads, contexts)
@@ -62,12 +62,15 @@ def make_params(**kw) -> _abi.TcParams:
 
 
 def to_indenter(ind) -> _abi.TcIndenter:
-    """Any object with shape, prm (<= 4), R (3x3), c (3) -> tc_indenter."""
+    """Any object with shape, prm (<= 4), R (3x3), c (3) -> tc_indenter;
+    a MESH indenter also carries mesh_id (from Context.add_mesh)."""
     if isinstance(ind, _abi.TcIndenter):
         return ind
     get = (lambda k: ind[k]) if isinstance(ind, dict) else (lambda k: getattr(ind, k))
     t = _abi.TcIndenter()
     t.shape = int(get("shape"))
+    if t.shape == MESH:
+        t.reserved = int(get("mesh_id"))
     R = np.asarray(get("R"), dtype=np.float64).reshape(9)
     c = np.asarray(get("c"), dtype=np.float64).reshape(3)
     prm = list(get("prm")) + [0.0] * 4
@@ -114,6 +117,39 @@ def _mesh(X, tets, fixed=None, tet_material=None):
     m = _abi.TcMesh(X.shape[0], tets.shape[0], _ptr(X, C.c_double), _ptr(tets, C.c_int32),
                     _ptr(fixed, C.c_uint8), _ptr(tm, C.c_int32))
     return m, (X, tets, fixed, tm)
+
+
+def sizing(**kw) -> _abi.TcSizing:
+    """tc_sizing with library defaults, overridden by keyword arguments
+    (axis, side, band, inner, transition, l_contact, l_global, centre,
+    max_tets)."""
+    sz = _abi.TcSizing()
+    check(load().tc_sizing_default(C.byref(sz)))
+    for k, v in kw.items():
+        if k == "centre":
+            sz.centre[0], sz.centre[1] = float(v[0]), float(v[1])
+        elif not hasattr(sz, k):
+            raise TypeError(f"unknown sizing field {k}")
+        else:
+            setattr(sz, k, type(getattr(sz, k))(v))
+    return sz
+
+
+def refine_mesh(X, tets, tet_material=None, max_tets=2_000_000, **kw):
+    """Host-only conforming refinement under the contact sizing field:
+    returns (X', tets', material') with the input vertices first."""
+    lib = load()
+    m, keep = _mesh(X, tets, None, tet_material)
+    sz = sizing(max_tets=max_tets, **kw)
+    cap_t = int(max_tets)
+    cap_v = int(np.asarray(X).shape[0]) + cap_t
+    xo = np.empty((cap_v, 3))
+    to = np.empty((cap_t, 4), np.int32)
+    mo = np.empty(cap_t, np.int32)
+    nv, nt = C.c_int32(), C.c_int32()
+    check(lib.tc_refine_mesh(C.byref(m), C.byref(sz), cap_v, cap_t, _ptr(xo, C.c_double), _ptr(to, C.c_int32),
+                             _ptr(mo, C.c_int32), C.byref(nv), C.byref(nt)))
+    return xo[:nv.value].copy(), to[:nt.value].copy(), mo[:nt.value].copy()
 
 
 def mesh_surface(X, tets, fixed=None):
@@ -163,6 +199,19 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def add_mesh(self, verts, tris) -> int:
+        """Register a closed, outward-oriented rigid triangle mesh (local
+        frame, metres) as an indenter shape; returns its mesh_id."""
+        V = np.ascontiguousarray(verts, dtype=np.float64).reshape(-1, 3)
+        F = np.ascontiguousarray(tris, dtype=np.int32).reshape(-1, 3)
+        mid = C.c_int32()
+        check(self.lib.tc_rigid_mesh_create(self.h, V.shape[0], V.ctypes.data_as(C.POINTER(C.c_double)),
+                                            F.shape[0], F.ctypes.data_as(C.POINTER(C.c_int32)), C.byref(mid)))
+        return mid.value
+
+    def remove_mesh(self, mesh_id: int):
+        check(self.lib.tc_rigid_mesh_destroy(self.h, int(mesh_id)))
 
     def memory(self):
         u, b = C.c_uint64(), C.c_uint64()
@@ -368,9 +417,15 @@ class Server:
             pass
 
 
-def validate(mesh=None, materials=None, params=None, indenters=None):
-    """Host-only argument checks; raises TcError on the first problem."""
+def validate(mesh=None, materials=None, params=None, indenters=None, rigid_mesh=None):
+    """Host-only argument checks; raises TcError on the first problem.
+    rigid_mesh: (verts, tris) of a TC_MESH indenter shape."""
     lib = load()
+    if rigid_mesh is not None:
+        V = np.ascontiguousarray(rigid_mesh[0], dtype=np.float64).reshape(-1, 3)
+        F = np.ascontiguousarray(rigid_mesh[1], dtype=np.int32).reshape(-1, 3)
+        check(lib.tc_validate_rigid_mesh(V.shape[0], V.ctypes.data_as(C.POINTER(C.c_double)),
+                                         F.shape[0], F.ctypes.data_as(C.POINTER(C.c_int32))))
     if mesh is not None:
         X, tets = mesh[0], mesh[1]
         fixed = mesh[2] if len(mesh) > 2 else None

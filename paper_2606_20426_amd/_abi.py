@@ -12,7 +12,8 @@ OK, E_INVALID_ARG, E_BAD_MESH, E_NO_MEMORY, E_HIP = 0, -1, -2, -3, -4
 E_INFEASIBLE, E_NOT_CONVERGED, E_LINESEARCH, E_NO_DEVICE, E_BUSY = -5, -6, -7, -8, -9
 PREC_FP64, PREC_MIXED = 0, 1
 PRECOND_BLOCK_JACOBI, PRECOND_JACOBI = 0, 1
-SPHERE, CYLINDER, BOX, TORUS, TEXTURE = 0, 1, 2, 3, 4
+SPHERE, CYLINDER, BOX, TORUS, TEXTURE, MESH = 0, 1, 2, 3, 4, 5
+MAX_MESHES = 64
 MAX_INDENTERS, MAX_MATERIALS = 5, 8
 DT_F64, DT_F32, DT_I32, DT_U8 = 0, 1, 2, 3
 TIMER_NAME_LEN = 32
@@ -48,6 +49,12 @@ class TcParams(C.Structure):
                 ("cg_conv_tol", C.c_double), ("cg_eta_max", C.c_double),
                 ("ls_expand", C.c_int32), ("reserved", C.c_int32),
                 ("friction", C.c_double), ("eps_v", C.c_double)]
+
+
+class TcSizing(C.Structure):
+    _fields_ = [("axis", C.c_int32), ("side", C.c_int32), ("band", C.c_double), ("inner", C.c_double),
+                ("transition", C.c_double), ("l_contact", C.c_double), ("l_global", C.c_double),
+                ("centre", C.c_double * 2), ("max_tets", C.c_int64)]
 
 
 class TcIndenter(C.Structure):
@@ -104,6 +111,12 @@ PROTOS = {
     "tc_context_reset_timing": (S, [P]),
     "tc_autotune": (S, [P, S, C.POINTER(P), C.POINTER(S), C.POINTER(TcIndenter), C.POINTER(S)]),
     "tc_set_launch": (S, [P, S, S, S, S, S]),
+    "tc_rigid_mesh_create": (S, [P, S, C.POINTER(C.c_double), S, C.POINTER(S), C.POINTER(S)]),
+    "tc_rigid_mesh_destroy": (S, [P, S]),
+    "tc_validate_rigid_mesh": (S, [S, C.POINTER(C.c_double), S, C.POINTER(S)]),
+    "tc_sizing_default": (S, [C.POINTER(TcSizing)]),
+    "tc_refine_mesh": (S, [C.POINTER(TcMesh), C.POINTER(TcSizing), S, S, C.POINTER(C.c_double), C.POINTER(S),
+                           C.POINTER(S), C.POINTER(S), C.POINTER(S)]),
     "tc_pad_create": (S, [P, C.POINTER(TcMesh), S, C.POINTER(TcMaterial), C.POINTER(TcParams), C.POINTER(P)]),
     "tc_pad_destroy": (S, [P]),
     "tc_pad_get_info": (S, [P, C.POINTER(TcPadInfo)]),

@@ -135,6 +135,34 @@ def test_validation_error_codes(tc):
     assert _status(lambda: V(indenters=[dict(good, shape=2, prm=(1e-3, 1e-3, 0.0))])) == -1
 
 
+def test_rigid_mesh_validation(tc):
+    from workloads import meshes
+    V = tc.validate
+    for good in (meshes.box_surface(1e-3, 2e-3, 3e-3), meshes.icosphere(2e-3, 2),
+                 meshes.torus_surface(4e-3, 1e-3, 16, 8)):
+        assert _status(lambda: V(rigid_mesh=good)) == 0
+    Vb, Fb = meshes.box_surface(1e-3, 1e-3, 1e-3)
+    assert _status(lambda: V(rigid_mesh=(Vb, Fb[:, ::-1]))) == -1        # inward normals
+    assert _status(lambda: V(rigid_mesh=(Vb, Fb[:-1]))) == -1            # open surface
+    flip = Fb.copy(); flip[0] = flip[0, ::-1]
+    assert _status(lambda: V(rigid_mesh=(Vb, flip))) == -1               # inconsistent orientation
+    bad = Fb.copy(); bad[0, 0] = 99
+    assert _status(lambda: V(rigid_mesh=(Vb, bad))) == -1                # index out of range
+    dup = Fb.copy(); dup[0, 1] = dup[0, 0]
+    assert _status(lambda: V(rigid_mesh=(Vb, dup))) == -1                # repeated vertex
+    flat = Vb.copy(); flat[:, 2] = 0.0
+    assert _status(lambda: V(rigid_mesh=(flat, Fb))) == -1               # degenerate triangles
+    nan = Vb.copy(); nan[3, 0] = np.nan
+    assert _status(lambda: V(rigid_mesh=(nan, Fb))) == -1
+    # mesh indenters: id range and finite (unused) parameters
+    I = np.eye(3)
+    m = dict(shape=tc.MESH, prm=(0.0,), R=I, c=(0, 0, 0), mesh_id=0)
+    assert _status(lambda: V(indenters=[m])) == 0
+    assert _status(lambda: V(indenters=[dict(m, mesh_id=64)])) == -1
+    assert _status(lambda: V(indenters=[dict(m, mesh_id=-1)])) == -1
+    assert _status(lambda: V(indenters=[dict(m, prm=(np.inf,))])) == -1
+
+
 def test_context_without_device_fails_loudly(tc):
     import torch
     if torch.cuda.is_available():
@@ -142,3 +170,45 @@ def test_context_without_device_fails_loudly(tc):
     with pytest.raises(tc.TcError) as e:
         tc.Context(0)
     assert e.value.status == -8
+
+
+@pytest.mark.parametrize("case", ["box", "config1_fine", "dome_offset", "side_minus_layers"])
+def test_refine_mesh_bit_exact_vs_oracle(tc, case):
+    """Library refinement (host C++) equals the oracle's: integers and
+    positions bit for bit."""
+    from oracle import refine
+    MM = 1e-3
+    mat = None
+    kw = {}
+    if case == "box":
+        pad = scenes.box_pad(18 * MM, 14 * MM, 4 * MM, 6, 5, 2)
+    elif case == "config1_fine":
+        pad = scenes.config1().pad
+        kw = dict(l_contact=0.5 * MM, l_global=2.0 * MM)
+    elif case == "dome_offset":
+        pad = scenes.dome_pad(19 * MM, 16 * MM, 3 * MM, 6, 5, 2)
+        kw = dict(centre=(7 * MM, 9 * MM), inner=0.3, transition=0.3)
+    else:
+        pad = scenes.box_pad(18 * MM, 14 * MM, 4 * MM, 6, 5, 2)
+        mat, _ = scenes.layered_materials(pad.X, pad.tets, 2 * MM, None, None)
+        kw = dict(side=-1, band=0.3)
+    s = refine.Sizing(pad.X, **kw)
+    Xo, To, Mo = refine.refine(pad.X, pad.tets, s, mat=mat)
+    Xl, Tl, Ml = tc.refine_mesh(pad.X, pad.tets, tet_material=mat, **kw)
+    assert Tl.shape == To.shape and Xl.shape == Xo.shape
+    assert np.array_equal(Tl, To) and np.array_equal(Ml, Mo)
+    assert np.array_equal(Xl.view(np.int64), Xo.view(np.int64))
+    assert To.shape[0] > pad.tets.shape[0]
+
+
+def test_refine_mesh_errors(tc):
+    p = scenes.one_cube_pad()
+    with pytest.raises(tc.TcError):
+        tc.refine_mesh(p.X, p.tets, l_contact=0.0)
+    with pytest.raises(tc.TcError):
+        tc.refine_mesh(p.X, p.tets, side=0)
+    with pytest.raises(tc.TcError):                  # growth beyond max_tets
+        tc.refine_mesh(p.X, p.tets, l_contact=1e-5, l_global=1e-5, max_tets=100)
+    bad = p.tets.copy(); bad[0, [2, 3]] = bad[0, [3, 2]]
+    with pytest.raises(tc.TcError):
+        tc.refine_mesh(p.X, bad)
