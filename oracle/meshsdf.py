@@ -55,70 +55,63 @@ class MeshData:
                 self.vert_n[tri[k]] += ang * self.fn[t]
 
 
-def _segment(y, p0, p1):
-    """Nearest point on segments p0-p1 to points y (all [K,3]): point, t."""
-    e = p1 - p0
-    t = np.clip(np.einsum("ki,ki->k", y - p0, e) / np.einsum("ki,ki->k", e, e), 0.0, 1.0)
-    return p0 + t[:, None] * e, t
-
-
-def closest(mesh, y):
-    """For points y [K,3]: distance d, closest point c, feature kind, feature
-    id (triangle, edge or vertex index) and, for edges, the edge direction."""
-    y = np.atleast_2d(np.asarray(y, dtype=np.float64))
+def _closest_block(mesh, y):
+    """closest() for a block of points, all triangles at once ([K, M] pairs)."""
     K = y.shape[0]
-    best = np.full(K, np.inf)
-    cp = np.zeros((K, 3))
-    kind = np.zeros(K, np.int64)
-    fid = np.zeros(K, np.int64)
-    tdir = np.zeros((K, 3))
-    for t, tri in enumerate(mesh.F):
-        a, b, c = mesh.V[tri[0]], mesh.V[tri[1]], mesh.V[tri[2]]
-        n = mesh.fn[t]
-        q = y - np.outer((y - a) @ n, n)
-        # barycentric coordinates of the projection
-        v0, v1, v2 = b - a, c - a, q - a
-        d00, d01, d11 = v0 @ v0, v0 @ v1, v1 @ v1
-        d20, d21 = v2 @ v0, v2 @ v1
-        den = d00 * d11 - d01 * d01
-        l1 = (d11 * d20 - d01 * d21) / den
-        l2 = (d00 * d21 - d01 * d20) / den
-        inside = (l1 >= 0) & (l2 >= 0) & (l1 + l2 <= 1)
-        pt = q.copy()
-        knd = np.full(K, FACE)
-        idx = np.full(K, t)
-        dr = np.zeros((K, 3))
-        if not inside.all():
-            out = ~inside
-            yo = y[out]
-            bd = np.full(yo.shape[0], np.inf)
-            bp = np.zeros_like(yo)
-            bk = np.zeros(yo.shape[0], np.int64)
-            bi = np.zeros(yo.shape[0], np.int64)
-            bdir = np.zeros_like(yo)
-            corners = (a, b, c)
-            for k in range(3):
-                p0, p1 = corners[k], corners[(k + 1) % 3]
-                P0 = np.broadcast_to(p0, yo.shape)
-                P1 = np.broadcast_to(p1, yo.shape)
-                pk, s = _segment(yo, P0, P1)
-                dk = np.linalg.norm(yo - pk, axis=1)
-                better = dk < bd
-                bd = np.where(better, dk, bd)
-                bp[better] = pk[better]
-                at0, at1 = s <= 0.0, s >= 1.0
-                kk = np.where(at0 | at1, VERTEX, EDGE)
-                ii = np.where(at0, tri[k], np.where(at1, tri[(k + 1) % 3], mesh.tri_edge[t, k]))
-                bk = np.where(better, kk, bk)
-                bi = np.where(better, ii, bi)
-                e = (p1 - p0) / np.linalg.norm(p1 - p0)
-                bdir[better] = e
-            pt[out], knd[out], idx[out], dr[out] = bp, bk, bi, bdir
-        dist = np.linalg.norm(y - pt, axis=1)
-        better = dist < best
-        best = np.where(better, dist, best)
-        cp[better], kind[better], fid[better], tdir[better] = pt[better], knd[better], idx[better], dr[better]
-    return best, cp, kind, fid, tdir
+    A, B, Cc = (mesh.V[mesh.F[:, k]][None] for k in range(3))          # [1,M,3]
+    n = mesh.fn[None]
+    Y = y[:, None, :]                                                   # [K,1,3]
+    q = Y - np.einsum("kmi,kmi->km", Y - A, np.broadcast_to(n, (K,) + n.shape[1:]))[..., None] * n
+    # barycentric coordinates of the projection onto each triangle's plane
+    v0, v1 = B - A, Cc - A
+    v2 = q - A
+    d00 = np.einsum("kmi,kmi->km", v0, v0)
+    d01 = np.einsum("kmi,kmi->km", v0, v1)
+    d11 = np.einsum("kmi,kmi->km", v1, v1)
+    d20 = np.einsum("kmi,kmi->km", v2, np.broadcast_to(v0, v2.shape))
+    d21 = np.einsum("kmi,kmi->km", v2, np.broadcast_to(v1, v2.shape))
+    den = d00 * d11 - d01 * d01
+    l1 = (d11 * d20 - d01 * d21) / den
+    l2 = (d00 * d21 - d01 * d20) / den
+    inside = (l1 >= 0) & (l2 >= 0) & (l1 + l2 <= 1)
+    M = mesh.F.shape[0]
+    pt = q.copy()
+    kind = np.full((K, M), FACE)
+    fid = np.broadcast_to(np.arange(M)[None], (K, M)).copy()
+    tdir = np.zeros((K, M, 3))
+    # outside the triangle: nearest point over the three edge segments
+    best = np.full((K, M), np.inf)
+    corners = (A, B, Cc)
+    for k in range(3):
+        p0, p1 = corners[k], corners[(k + 1) % 3]
+        e = p1 - p0
+        t = np.clip(np.einsum("kmi,kmi->km", Y - p0, np.broadcast_to(e, (K,) + e.shape[1:]))
+                    / np.einsum("kmi,kmi->km", e, e), 0.0, 1.0)
+        pk = p0 + t[..., None] * e
+        dk = np.linalg.norm(Y - pk, axis=2)
+        better = (~inside) & (dk < best)
+        best = np.where(better, dk, best)
+        pt = np.where(better[..., None], pk, pt)
+        vert = np.where(t <= 0.0, mesh.F[None, :, k], mesh.F[None, :, (k + 1) % 3])
+        kk = np.where((t <= 0.0) | (t >= 1.0), VERTEX, EDGE)
+        ii = np.where(kk == VERTEX, vert, mesh.tri_edge[None, :, k])
+        kind = np.where(better, kk, kind)
+        fid = np.where(better, ii, fid)
+        ed = e / np.linalg.norm(e, axis=2, keepdims=True)
+        tdir = np.where(better[..., None], np.broadcast_to(ed, tdir.shape), tdir)
+    dist = np.linalg.norm(Y - pt, axis=2)
+    j = np.argmin(dist, axis=1)
+    r = np.arange(K)
+    return dist[r, j], pt[r, j], kind[r, j], fid[r, j], tdir[r, j]
+
+
+def closest(mesh, y, block=128):
+    """For points y [K,3]: distance d, closest point c, feature kind, feature
+    id (triangle, edge or vertex index) and, for edges, the edge direction.
+    Every triangle is tried (brute force); the first of equal distances wins."""
+    y = np.atleast_2d(np.asarray(y, dtype=np.float64))
+    parts = [_closest_block(mesh, y[i:i + block]) for i in range(0, y.shape[0], block)]
+    return tuple(np.concatenate([p[k] for p in parts]) for k in range(5))
 
 
 def sdf_local(mesh, y):

@@ -342,14 +342,125 @@ __device__ void sdf_local(int shape, const double* prm, const double y[3], doubl
   }
 }
 
+// ------------------------------------------------ rigid triangle meshes
+
+// Closest point on triangle (a, b, c) to y by its Voronoi regions (Ericson,
+// Real-Time Collision Detection, 2005, Sec. 5.1.5).  region: 0 face, 1..3
+// vertex a, b, c, 4..6 edge ab, bc, ca.
+__device__ __forceinline__ int tri_closest(const double* t, const double y[3], double c[3]) {
+  const double a[3] = {t[0], t[1], t[2]}, b[3] = {t[3], t[4], t[5]}, q[3] = {t[6], t[7], t[8]};
+  double ab[3], ac[3], ap[3], bp[3], cp[3];
+  for (int i = 0; i < 3; ++i) {
+    ab[i] = b[i] - a[i]; ac[i] = q[i] - a[i]; ap[i] = y[i] - a[i]; bp[i] = y[i] - b[i]; cp[i] = y[i] - q[i];
+  }
+  auto dot = [](const double* u, const double* v) { return u[0] * v[0] + u[1] * v[1] + u[2] * v[2]; };
+  const double d1 = dot(ab, ap), d2 = dot(ac, ap);
+  if (d1 <= 0 && d2 <= 0) { for (int i = 0; i < 3; ++i) c[i] = a[i]; return 1; }
+  const double d3 = dot(ab, bp), d4 = dot(ac, bp);
+  if (d3 >= 0 && d4 <= d3) { for (int i = 0; i < 3; ++i) c[i] = b[i]; return 2; }
+  const double vc = d1 * d4 - d3 * d2;
+  if (vc <= 0 && d1 >= 0 && d3 <= 0) {
+    const double v = d1 / (d1 - d3);
+    for (int i = 0; i < 3; ++i) c[i] = a[i] + v * ab[i];
+    return 4;
+  }
+  const double d5 = dot(ab, cp), d6 = dot(ac, cp);
+  if (d6 >= 0 && d5 <= d6) { for (int i = 0; i < 3; ++i) c[i] = q[i]; return 3; }
+  const double vb = d5 * d2 - d1 * d6;
+  if (vb <= 0 && d2 >= 0 && d6 <= 0) {
+    const double w = d2 / (d2 - d6);
+    for (int i = 0; i < 3; ++i) c[i] = a[i] + w * ac[i];
+    return 6;
+  }
+  const double va = d3 * d6 - d5 * d4;
+  if (va <= 0 && d4 - d3 >= 0 && d5 - d6 >= 0) {
+    const double w = (d4 - d3) / ((d4 - d3) + (d5 - d6));
+    for (int i = 0; i < 3; ++i) c[i] = b[i] + w * (q[i] - b[i]);
+    return 5;
+  }
+  const double den = 1.0 / (va + vb + vc);
+  const double v = vb * den, w = vc * den;
+  for (int i = 0; i < 3; ++i) c[i] = a[i] + v * ab[i] + w * ac[i];
+  return 0;
+}
+
+// Signed distance to a closed mesh: nearest triangle over the BVH (nearer
+// child first, subtrees pruned by box distance), sign from the pseudonormal
+// of the closest feature (negative inside); gradient s (y - c) / d, Hessian
+// 0 on a face, s (I - t t^T - g g^T) / d on an edge of direction t,
+// s (I - g g^T) / d at a vertex.
+__device__ void mesh_sdf(const DevMesh& M, const double y[3], double& phi, double g[3], double H[3][3],
+                         bool wantH) {
+  double best = INFINITY, cb[3] = {0, 0, 0};
+  int bt = -1, br = 0;
+  int stack[BVH_STACK];
+  int sp = 0;
+  stack[sp++] = 0;
+  auto box_d2 = [&](const BvhNode& nd) {
+    double s = 0.0;
+    for (int i = 0; i < 3; ++i) {
+      const double v = fmax(fmax(nd.lo[i] - y[i], y[i] - nd.hi[i]), 0.0);
+      s += v * v;
+    }
+    return s;
+  };
+  while (sp > 0) {
+    const BvhNode& nd = M.nodes[stack[--sp]];
+    if (box_d2(nd) >= best) continue;
+    if (nd.count > 0) {
+      for (int t = nd.first; t < nd.first + nd.count; ++t) {
+        double c[3];
+        const int r = tri_closest(M.tv + 9 * (size_t)t, y, c);
+        const double d2 = (y[0] - c[0]) * (y[0] - c[0]) + (y[1] - c[1]) * (y[1] - c[1]) + (y[2] - c[2]) * (y[2] - c[2]);
+        if (d2 < best) { best = d2; bt = t; br = r; cb[0] = c[0]; cb[1] = c[1]; cb[2] = c[2]; }
+      }
+    } else if (sp + 2 <= BVH_STACK) {
+      const int l = (int)(&nd - M.nodes) + 1, r = nd.first;
+      const double dl = box_d2(M.nodes[l]), dr = box_d2(M.nodes[r]);
+      // nearer child on top
+      if (dl <= dr) { stack[sp++] = r; stack[sp++] = l; }
+      else { stack[sp++] = l; stack[sp++] = r; }
+    }
+  }
+  if (wantH)
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) H[i][j] = 0.0;
+  if (bt < 0) { phi = INFINITY; g[0] = g[1] = 0.0; g[2] = 1.0; return; }
+  const int32_t* id = M.tid + 6 * (size_t)bt;
+  const double* N = br == 0 ? M.tn + 3 * (size_t)bt
+                  : br <= 3 ? M.vn + 3 * (size_t)id[br - 1]
+                  : M.en + 3 * (size_t)id[3 + br - 4];
+  const double diff[3] = {y[0] - cb[0], y[1] - cb[1], y[2] - cb[2]};
+  const double s = diff[0] * N[0] + diff[1] * N[1] + diff[2] * N[2] >= 0 ? 1.0 : -1.0;
+  const double d = sqrt(best);
+  const double id_ = d > 0 ? 1.0 / d : 1.0;
+  for (int i = 0; i < 3; ++i) g[i] = s * diff[i] * id_;
+  phi = s * d;
+  if (!wantH || br == 0) return;
+  double t[3] = {0, 0, 0};
+  if (br >= 4) {
+    const double* T = M.tv + 9 * (size_t)bt;
+    const int e0 = br - 4, e1 = (br - 4 + 1) % 3;
+    for (int i = 0; i < 3; ++i) t[i] = T[3 * e1 + i] - T[3 * e0 + i];
+    const double L = sqrt(t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+    for (int i = 0; i < 3; ++i) t[i] /= L;
+  }
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      H[i][j] = s * id_ * ((i == j ? 1.0 : 0.0) - t[i] * t[j] - g[i] * g[j]);
+}
+
 // World frame: y = R^T (x - c), grad = R g, hess = R H R^T.
-__device__ void sdf_world(const DevIndenter& ind, const double x[3], double& phi, double g[3],
-                          double H[3][3], bool wantH) {
+__device__ void sdf_world(const DevIndenter& ind, const DevMesh* meshes, const double x[3], double& phi,
+                          double g[3], double H[3][3], bool wantH) {
   const double dx[3] = {x[0] - ind.c[0], x[1] - ind.c[1], x[2] - ind.c[2]};
   double y[3];
   for (int i = 0; i < 3; ++i) y[i] = ind.R[0 * 3 + i] * dx[0] + ind.R[1 * 3 + i] * dx[1] + ind.R[2 * 3 + i] * dx[2];
   double gl[3], Hl[3][3];
-  sdf_local(ind.shape, ind.prm, y, phi, gl, Hl, wantH);
+  if (ind.shape == TC_MESH)
+    mesh_sdf(meshes[ind.reserved], y, phi, gl, Hl, wantH);
+  else
+    sdf_local(ind.shape, ind.prm, y, phi, gl, Hl, wantH);
   for (int i = 0; i < 3; ++i) g[i] = ind.R[i * 3 + 0] * gl[0] + ind.R[i * 3 + 1] * gl[1] + ind.R[i * 3 + 2] * gl[2];
   if (wantH) {
     double T[3][3];
@@ -593,7 +704,7 @@ __global__ void k_predict(const Tile* tiles, int ntiles, const EnvDesc* envs) {
     const DevIndenter& A = P->prev[m];
     const DevIndenter& B = P->ind[m];
     double phi, n[3], loc[3];
-    sdf_world(A, xt, phi, n, H, false);
+    sdf_world(A, E.meshes, xt, phi, n, H, false);
     for (int j = 0; j < 3; ++j)
       loc[j] = A.R[0 * 3 + j] * (xt[0] - A.c[0]) + A.R[1 * 3 + j] * (xt[1] - A.c[1]) + A.R[2 * 3 + j] * (xt[2] - A.c[2]);
     double* f = E.fric + ((size_t)m * E.C + k) * FRIC_STRIDE;
@@ -627,7 +738,7 @@ __global__ void k_project(const Tile* tiles, int ntiles, const EnvDesc* envs) {
     bool moved = false;
     for (int m = 0; m < P->n_ind; ++m) {
       double phi, g[3];
-      sdf_world(P->ind[m], x, phi, g, H, false);
+      sdf_world(P->ind[m], E.meshes, x, phi, g, H, false);
       if (phi < dsafe * (1.0 - 1e-9)) {
         moved = true;
         for (int c = 0; c < 3; ++c)
@@ -639,7 +750,7 @@ __global__ void k_project(const Tile* tiles, int ntiles, const EnvDesc* envs) {
   double dmin = INFINITY;
   for (int m = 0; m < P->n_ind; ++m) {
     double phi, g[3];
-    sdf_world(P->ind[m], x, phi, g, H, false);
+    sdf_world(P->ind[m], E.meshes, x, phi, g, H, false);
     dmin = fmin(dmin, phi);
   }
   for (int c = 0; c < 3; ++c) E.xn[3 * vi + c] = x[c];
@@ -833,7 +944,7 @@ __global__ void k_barrier(const Tile* tiles, int ntiles, const EnvDesc* envs) {
   double g[3] = {0, 0, 0}, H[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, Hn[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
   for (int m = 0; m < P->n_ind; ++m) {
     double phi, n[3], Hp[3][3];
-    sdf_world(P->ind[m], x, phi, n, Hp, true);
+    sdf_world(P->ind[m], E.meshes, x, phi, n, Hp, true);
     if (phi < E.dhat) {
       const double s = phi / E.dhat;
       const double b1 = bar1(s), b2 = bar2(s);
@@ -1382,12 +1493,26 @@ __global__ void k_filter(const Tile* tiles, int ntiles, const EnvDesc* envs) {
     if (pn > 0) {
       for (int m = 0; m < P->n_ind; ++m) {
         double phi, g[3];
-        sdf_world(P->ind[m], x, phi, g, H, false);
+        sdf_world(P->ind[m], E.meshes, x, phi, g, H, false);
         double a = INFINITY;
         const double gp = g[0] * p[0] + g[1] * p[1] + g[2] * p[2];
         const DevIndenter& I = P->ind[m];
         if (convex_shape(I.shape)) {
           if (gp < 0) a = 0.9 * phi / (-gp);
+        } else if (I.shape == TC_MESH) {
+          // conservative advancement: phi is 1-Lipschitz, so phi >= 0.1 phi(x)
+          // holds on [a, a + (phi(x + a p) - 0.1 phi(x)) / |p|]; advance until
+          // that gap is within 0.1 % of the floor (or the span is covered)
+          const double floor_ = 0.1 * phi;
+          a = 0.0;
+          for (int it = 0; it < 32 && a < FILTER_SPAN; ++it) {
+            const double y[3] = {x[0] + a * p[0], x[1] + a * p[1], x[2] + a * p[2]};
+            double ph, gy[3];
+            sdf_world(I, E.meshes, y, ph, gy, H, false);
+            const double gap = ph - floor_;
+            if (gap <= 1e-3 * floor_) break;
+            a += gap / pn;
+          }
         } else if (I.shape == TC_TEXTURE) {
           // |hess phi| <= k^2 A / sqrt(1 + (kA)^2) everywhere
           const double A = I.prm[0], kk = 2.0 * M_PI / I.prm[1];
@@ -1528,7 +1653,7 @@ __global__ void k_energy(const Tile* tiles, int ntiles, const EnvDesc* envs, int
       for (int c = 0; c < 3; ++c) y[c] = E.xn[3 * vi + c] + (mode ? al * (double)d[3 * vi + c] : 0.0);
       for (int m = 0; m < P->n_ind; ++m) {
         double phi;
-        sdf_world(P->ind[m], y, phi, g, H, false);
+        sdf_world(P->ind[m], E.meshes, y, phi, g, H, false);
         if (phi < E.dhat) acc += E.kappa * E.cand_area[k] * E.dhat * bar0(phi / E.dhat);
       }
       if (E.fr_mu > 0) {
@@ -1772,7 +1897,7 @@ __global__ void k_contact(const Tile* tiles, int ntiles, const EnvDesc* envs) {
     double f[3] = {0, 0, 0};
     for (int m = 0; m < P->n_ind; ++m) {
       double phi, g[3];
-      sdf_world(P->ind[m], xv, phi, g, H, false);
+      sdf_world(P->ind[m], E.meshes, xv, phi, g, H, false);
       if (phi < E.dhat) {
         const double b1 = bar1(phi / E.dhat);
         for (int c = 0; c < 3; ++c) f[c] -= kA * b1 * g[c];

@@ -1,0 +1,293 @@
+// Rigid triangle meshes as indenter shapes (TC_MESH): validation,
+// pseudonormals and a bounding-volume hierarchy built on the host, one
+// device allocation per mesh, registered in the context's device table that
+// the kernels index by tc_indenter.reserved.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <utility>
+#include <vector>
+
+#include "runtime.h"
+
+namespace tc {
+
+namespace {
+
+constexpr int kLeaf = 4;   // triangles per leaf
+
+using Vec3 = std::array<double, 3>;
+
+Vec3 sub(const Vec3& a, const Vec3& b) { return {a[0] - b[0], a[1] - b[1], a[2] - b[2]}; }
+Vec3 cross(const Vec3& a, const Vec3& b) {
+  return {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
+}
+double dot(const Vec3& a, const Vec3& b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+double norm(const Vec3& a) { return std::sqrt(dot(a, a)); }
+
+struct Tree {
+  std::vector<BvhNode> nodes;
+  std::vector<int> order;   // triangle of each leaf slot
+};
+
+// Median split on the longest axis of the centroids' box (ties broken by
+// triangle index, so the tree is deterministic); depth-first node order.
+int build(Tree& t, int lo, int hi, const std::vector<Vec3>& cen, const std::vector<std::array<double, 6>>& box) {
+  const int me = (int)t.nodes.size();
+  t.nodes.push_back(BvhNode{});
+  BvhNode nd{};
+  for (int i = 0; i < 3; ++i) { nd.lo[i] = INFINITY; nd.hi[i] = -INFINITY; }
+  Vec3 clo{INFINITY, INFINITY, INFINITY}, chi{-INFINITY, -INFINITY, -INFINITY};
+  for (int k = lo; k < hi; ++k) {
+    const int f = t.order[k];
+    for (int i = 0; i < 3; ++i) {
+      nd.lo[i] = std::min(nd.lo[i], box[f][i]);
+      nd.hi[i] = std::max(nd.hi[i], box[f][3 + i]);
+      clo[i] = std::min(clo[i], cen[f][i]);
+      chi[i] = std::max(chi[i], cen[f][i]);
+    }
+  }
+  if (hi - lo <= kLeaf) {
+    nd.first = lo;
+    nd.count = hi - lo;
+    t.nodes[me] = nd;
+    return me;
+  }
+  int ax = 0;
+  for (int i = 1; i < 3; ++i)
+    if (chi[i] - clo[i] > chi[ax] - clo[ax]) ax = i;
+  const int mid = (lo + hi) / 2;
+  std::nth_element(t.order.begin() + lo, t.order.begin() + mid, t.order.begin() + hi, [&](int a, int b) {
+    return cen[a][ax] < cen[b][ax] || (cen[a][ax] == cen[b][ax] && a < b);
+  });
+  build(t, lo, mid, cen, box);
+  const int right = build(t, mid, hi, cen, box);
+  nd.first = right;
+  nd.count = 0;
+  t.nodes[me] = nd;
+  return me;
+}
+
+size_t a256(size_t b) { return (b + 255) & ~size_t(255); }
+
+}  // namespace
+
+tc_status check_meshes(const tc_context* ctx, int n_ind, const tc_indenter* ind) {
+  for (int k = 0; k < n_ind; ++k)
+    if (ind[k].shape == TC_MESH) {
+      const int id = ind[k].reserved;
+      if (id < 0 || id >= (int)ctx->mesh_slots.size() || !ctx->mesh_slots[id].live)
+        return set_error(TC_E_INVALID_ARG, "indenter " + std::to_string(k) + ": mesh id " + std::to_string(id) +
+                                               " is not registered");
+    }
+  return TC_OK;
+}
+
+void free_meshes(tc_context* ctx) {
+  for (auto& m : ctx->mesh_slots)
+    if (m.live) {
+      ctx->dev_free(m.mem, m.bytes);
+      m = tc_context::MeshSlot{};
+    }
+}
+
+}  // namespace tc
+
+using namespace tc;
+
+namespace {
+
+// Host tables of a mesh: hierarchy nodes, triangles in leaf order with their
+// normals and feature ids, edge and vertex pseudonormals.
+struct Tables {
+  Tree tree;
+  std::vector<double> tv, tn, enf, vnf;
+  std::vector<int32_t> tid_l;
+};
+
+tc_status mesh_tables(int32_t n_verts, const double* verts, int32_t n_tris, const int32_t* tris, Tables& out) {
+  if (!verts || !tris) return set_error(TC_E_INVALID_ARG, "null argument");
+  if (n_verts < 4 || n_tris < 4 || n_tris > (1 << 24))
+    return set_error(TC_E_INVALID_ARG, "a closed mesh needs >= 4 vertices and 4..2^24 triangles");
+  {
+    std::vector<Vec3> V(n_verts);
+    for (int i = 0; i < n_verts; ++i) {
+      for (int c = 0; c < 3; ++c) {
+        V[i][c] = verts[3 * i + c];
+        if (!std::isfinite(V[i][c])) return set_error(TC_E_INVALID_ARG, "vertex coordinates must be finite");
+      }
+    }
+    // closed and consistently oriented: each directed edge once, its
+    // reverse once
+    std::map<std::pair<int, int>, int> directed;
+    std::vector<Vec3> fn(n_tris), cen(n_tris);
+    std::vector<std::array<double, 6>> box(n_tris);
+    double vol6 = 0.0;
+    for (int f = 0; f < n_tris; ++f) {
+      const int a = tris[3 * f], b = tris[3 * f + 1], c = tris[3 * f + 2];
+      if (a < 0 || b < 0 || c < 0 || a >= n_verts || b >= n_verts || c >= n_verts || a == b || b == c || a == c)
+        return set_error(TC_E_INVALID_ARG, "triangle " + std::to_string(f) + ": bad vertex index");
+      const int t[3] = {a, b, c};
+      for (int k = 0; k < 3; ++k)
+        if (++directed[{t[k], t[(k + 1) % 3]}] > 1)
+          return set_error(TC_E_INVALID_ARG, "mesh is not consistently oriented (directed edge used twice)");
+      const Vec3 cr = cross(sub(V[b], V[a]), sub(V[c], V[a]));
+      const double L = norm(cr);
+      const double e2 = std::max({dot(sub(V[b], V[a]), sub(V[b], V[a])), dot(sub(V[c], V[a]), sub(V[c], V[a])),
+                                  dot(sub(V[c], V[b]), sub(V[c], V[b]))});
+      if (!(L > 1e-12 * e2)) return set_error(TC_E_INVALID_ARG, "triangle " + std::to_string(f) + " is degenerate");
+      fn[f] = {cr[0] / L, cr[1] / L, cr[2] / L};
+      vol6 += dot(V[a], cross(V[b], V[c]));
+      for (int i = 0; i < 3; ++i) {
+        cen[f][i] = (V[a][i] + V[b][i] + V[c][i]) / 3.0;
+        box[f][i] = std::min({V[a][i], V[b][i], V[c][i]});
+        box[f][3 + i] = std::max({V[a][i], V[b][i], V[c][i]});
+      }
+    }
+    for (const auto& e : directed)
+      if (!directed.count({e.first.second, e.first.first}))
+        return set_error(TC_E_INVALID_ARG, "mesh is not closed (an edge has one triangle)");
+    if (!(vol6 > 0)) return set_error(TC_E_INVALID_ARG, "mesh normals must point outward (enclosed volume <= 0)");
+    // edge ids and pseudonormals
+    std::map<std::pair<int, int>, int> edge_id;
+    std::vector<int32_t> tid(6 * (size_t)n_tris);
+    std::vector<Vec3> en, vn(n_verts, Vec3{0, 0, 0});
+    for (int f = 0; f < n_tris; ++f) {
+      const int t[3] = {tris[3 * f], tris[3 * f + 1], tris[3 * f + 2]};
+      for (int k = 0; k < 3; ++k) {
+        const std::pair<int, int> key{std::min(t[k], t[(k + 1) % 3]), std::max(t[k], t[(k + 1) % 3])};
+        auto it = edge_id.find(key);
+        if (it == edge_id.end()) {
+          it = edge_id.emplace(key, (int)en.size()).first;
+          en.push_back(Vec3{0, 0, 0});
+        }
+        for (int i = 0; i < 3; ++i) en[it->second][i] += fn[f][i];
+        tid[6 * (size_t)f + k] = t[k];
+        tid[6 * (size_t)f + 3 + k] = it->second;
+        // interior angle at corner k
+        const Vec3 u = sub(V[t[(k + 1) % 3]], V[t[k]]), w = sub(V[t[(k + 2) % 3]], V[t[k]]);
+        const double ang = std::acos(std::max(-1.0, std::min(1.0, dot(u, w) / (norm(u) * norm(w)))));
+        for (int i = 0; i < 3; ++i) vn[t[k]][i] += ang * fn[f][i];
+      }
+    }
+    // hierarchy; triangles stored in leaf order
+    Tree tree;
+    tree.order.resize(n_tris);
+    std::iota(tree.order.begin(), tree.order.end(), 0);
+    build(tree, 0, n_tris, cen, box);
+    std::vector<double> tv(9 * (size_t)n_tris), tn(3 * (size_t)n_tris);
+    std::vector<int32_t> tid_l(6 * (size_t)n_tris);
+    for (int s = 0; s < n_tris; ++s) {
+      const int f = tree.order[s];
+      for (int k = 0; k < 3; ++k)
+        for (int i = 0; i < 3; ++i) tv[9 * (size_t)s + 3 * k + i] = V[tris[3 * f + k]][i];
+      for (int i = 0; i < 3; ++i) tn[3 * (size_t)s + i] = fn[f][i];
+      for (int j = 0; j < 6; ++j) tid_l[6 * (size_t)s + j] = tid[6 * (size_t)f + j];
+    }
+    std::vector<double> enf(3 * en.size()), vnf(3 * (size_t)n_verts);
+    for (size_t e = 0; e < en.size(); ++e)
+      for (int i = 0; i < 3; ++i) enf[3 * e + i] = en[e][i];
+    for (int v = 0; v < n_verts; ++v)
+      for (int i = 0; i < 3; ++i) vnf[3 * (size_t)v + i] = vn[v][i];
+    out.tree = std::move(tree);
+    out.tv = std::move(tv);
+    out.tn = std::move(tn);
+    out.tid_l = std::move(tid_l);
+    out.enf = std::move(enf);
+    out.vnf = std::move(vnf);
+  }
+  return TC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tc_status tc_validate_rigid_mesh(int32_t n_verts, const double* verts, int32_t n_tris, const int32_t* tris) {
+  try {
+    Tables t;
+    return mesh_tables(n_verts, verts, n_tris, tris, t);
+  } catch (const std::bad_alloc&) {
+    return set_error(TC_E_NO_MEMORY, "host allocation failed");
+  }
+}
+
+tc_status tc_rigid_mesh_create(tc_context* ctx, int32_t n_verts, const double* verts, int32_t n_tris,
+                               const int32_t* tris, int32_t* id) {
+  if (!ctx || !id) return set_error(TC_E_INVALID_ARG, "null argument");
+  *id = -1;
+  try {
+    Tables tb;
+    tc_status vs = mesh_tables(n_verts, verts, n_tris, tris, tb);
+    if (vs) return vs;
+    const Tree& tree = tb.tree;
+    const std::vector<double>& tv = tb.tv;
+    const std::vector<double>& tn = tb.tn;
+    const std::vector<int32_t>& tid_l = tb.tid_l;
+    const std::vector<double>& enf = tb.enf;
+    const std::vector<double>& vnf = tb.vnf;
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    int slot = -1;
+    for (int k = 0; k < (int)ctx->mesh_slots.size(); ++k)
+      if (!ctx->mesh_slots[k].live) { slot = k; break; }
+    if (slot < 0) return set_error(TC_E_NO_MEMORY, "all TC_MAX_MESHES mesh slots are in use");
+    TC_HIP(hipSetDevice(ctx->device));
+    const size_t b_nodes = a256(sizeof(BvhNode) * tree.nodes.size()), b_tv = a256(8 * tv.size()),
+                 b_tn = a256(8 * tn.size()), b_tid = a256(4 * tid_l.size()), b_en = a256(8 * enf.size()),
+                 b_vn = a256(8 * vnf.size());
+    const size_t total = b_nodes + b_tv + b_tn + b_tid + b_en + b_vn;
+    tc_status st;
+    char* mem = static_cast<char*>(ctx->dev_alloc(total, &st));
+    if (!mem) return st;
+    DevMesh dm{};
+    dm.n_tri = n_tris;
+    dm.n_node = (int)tree.nodes.size();
+    char* p = mem;
+    dm.nodes = reinterpret_cast<const BvhNode*>(p); p += b_nodes;
+    dm.tv = reinterpret_cast<const double*>(p); p += b_tv;
+    dm.tn = reinterpret_cast<const double*>(p); p += b_tn;
+    dm.tid = reinterpret_cast<const int32_t*>(p); p += b_tid;
+    dm.en = reinterpret_cast<const double*>(p); p += b_en;
+    dm.vn = reinterpret_cast<const double*>(p);
+    hipError_t e = hipMemcpy((void*)dm.nodes, tree.nodes.data(), sizeof(BvhNode) * tree.nodes.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy((void*)dm.tv, tv.data(), 8 * tv.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy((void*)dm.tn, tn.data(), 8 * tn.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy((void*)dm.tid, tid_l.data(), 4 * tid_l.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy((void*)dm.en, enf.data(), 8 * enf.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy((void*)dm.vn, vnf.data(), 8 * vnf.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(ctx->d_meshes + slot, &dm, sizeof(DevMesh), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      ctx->dev_free(mem, total);
+      return hip_fail(e, "mesh upload");
+    }
+    ctx->mesh_slots[slot] = tc_context::MeshSlot{true, mem, total};
+    *id = slot;
+    return TC_OK;
+  } catch (const std::bad_alloc&) {
+    return set_error(TC_E_NO_MEMORY, "host allocation failed");
+  }
+}
+
+tc_status tc_rigid_mesh_destroy(tc_context* ctx, int32_t id) {
+  if (!ctx) return set_error(TC_E_INVALID_ARG, "ctx is null");
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  if (id < 0 || id >= (int)ctx->mesh_slots.size() || !ctx->mesh_slots[id].live)
+    return set_error(TC_E_INVALID_ARG, "unknown mesh id");
+  for (const tc_pad* p : ctx->pads)
+    if (p->busy.load()) return set_error(TC_E_BUSY, "a pad has a request on a server");
+  TC_HIP(hipSetDevice(ctx->device));
+  TC_HIP(hipStreamSynchronize(ctx->stream));
+  const DevMesh zero{};
+  TC_HIP(hipMemcpy(ctx->d_meshes + id, &zero, sizeof(DevMesh), hipMemcpyHostToDevice));
+  auto& m = ctx->mesh_slots[id];
+  ctx->dev_free(m.mem, m.bytes);
+  m = tc_context::MeshSlot{};
+  return TC_OK;
+}
+
+}  // extern "C"

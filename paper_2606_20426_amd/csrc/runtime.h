@@ -98,6 +98,11 @@ struct tc_context {
   int next_pad_id = 1;
   std::vector<tc_pad*> pads;         // every live pad of the context
   std::atomic<int64_t> evictions{0}; // step scratch released to make room
+  // rigid meshes (TC_MESH indenters): device table [MAX_MESHES], zeroed
+  // slots are free; each live slot owns one device allocation
+  tc::DevMesh* d_meshes = nullptr;
+  struct MeshSlot { bool live = false; void* mem = nullptr; size_t bytes = 0; };
+  std::vector<MeshSlot> mesh_slots;
 
   void* dev_alloc(size_t bytes, tc_status* st);
   void dev_free(void* p, size_t bytes);
@@ -183,6 +188,10 @@ void account_bytes(tc_context* ctx, const tc_pad* pad, const EnvState& s);
 void init_state(EnvState& S, EnvPose& Q, int mode, int n_ind, const tc_indenter* ind, const tc_pad* pad);
 // After a completed step: its poses become the pad's previous poses.
 void remember_pose(tc_pad* pad, const EnvPose& Q);
+// Every TC_MESH indenter names a live mesh of the context.
+tc_status check_meshes(const tc_context* ctx, int n_ind, const tc_indenter* ind);
+// Release every mesh of a context (context destruction).
+void free_meshes(tc_context* ctx);
 void fill_stats(tc_step_stats& o, const EnvState& S, double ms);
 
 // Sequences the kernels of one Newton iteration over a plan.  Pad i of the

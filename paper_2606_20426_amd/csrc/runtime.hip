@@ -721,6 +721,7 @@ tc_status run_batch(tc_context* ctx, int n, tc_pad* const* pads, const int32_t* 
     if (pads[i]->busy.load()) return set_error(TC_E_BUSY, "pad has a request in flight on a server");
     tc_status s = validate_indenters(n_ind[i], ind ? ind + off : nullptr, err);
     if (s) return set_error(s, "pad " + std::to_string(i) + ": " + err);
+    if ((s = check_meshes(ctx, n_ind[i], ind ? ind + off : nullptr))) return s;
     off += n_ind[i];
   }
   std::lock_guard<std::recursive_mutex> lk(ctx->mu);
@@ -795,6 +796,7 @@ tc_status newton_direction(tc_pad* pad, int n_ind, const tc_indenter* ind, doubl
   std::string err;
   tc_status s = validate_indenters(n_ind, ind, err);
   if (s) return set_error(s, err);
+  if ((s = check_meshes(ctx, n_ind, ind))) return s;
   if (!dir) return set_error(TC_E_INVALID_ARG, "dir is null");
   std::lock_guard<std::recursive_mutex> lk(ctx->mu);
   TC_HIP(hipSetDevice(ctx->device));
@@ -1033,6 +1035,18 @@ tc_status tc_context_create(int32_t device, void* hip_stream, uint64_t hbm_budge
       if (e != hipSuccess) { delete ctx; return hip_fail(e, "hipStreamCreate"); }
       ctx->own_stream = true;
     }
+    {
+      const size_t tb = sizeof(DevMesh) * MAX_MESHES;
+      hipError_t e = hipMalloc(&ctx->d_meshes, tb);
+      if (e == hipSuccess) e = hipMemset(ctx->d_meshes, 0, tb);
+      if (e != hipSuccess) {
+        if (ctx->d_meshes) (void)hipFree(ctx->d_meshes);
+        if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+        delete ctx;
+        return hip_fail(e, "mesh table");
+      }
+      ctx->mesh_slots.resize(MAX_MESHES);
+    }
     *out = ctx;
     return TC_OK;
   });
@@ -1050,6 +1064,8 @@ tc_status tc_context_destroy(tc_context* ctx) {
     resolve_timing(ctx);
     for (auto e : ctx->free_events) (void)hipEventDestroy(e);
     if (ctx->clock_cells) (void)hipFree(ctx->clock_cells);
+    free_meshes(ctx);
+    if (ctx->d_meshes) (void)hipFree(ctx->d_meshes);
     pool_free(ctx->pool);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
   }
@@ -1268,6 +1284,7 @@ tc_status tc_pad_create(tc_context* ctx, const tc_mesh* mesh, int32_t n_material
     E.mass = mass; E.fixed = fixed; E.cand = cand; E.cand_of_vert = cov; E.cand_area = carea;
     E.tris = tris; E.parent = parent; E.is_top = istop; E.ctri_ptr = ctp; E.ctri_idx = cti;
     E.col = col; E.cptr = cptr; E.clist = clist;
+    E.meshes = ctx->d_meshes;
     for (int k = 0; k < MAX_MAT; ++k) {
       E.mu[k] = p->mu[k]; E.lam[k] = p->lam[k]; E.alpha[k] = p->alpha[k]; E.rho[k] = p->rho[k];
       E.cshift[k] = (k < n_materials && !params->literal_alpha) ? p->mu[k] : 0.0;

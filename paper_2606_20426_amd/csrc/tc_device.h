@@ -34,6 +34,33 @@ struct DevIndenter {
   double prm[4];
 };
 
+// Rigid triangle meshes registered with a context (TC_MESH indenters).
+constexpr int MAX_MESHES = 64;
+// stack of the closest-triangle traversal; the host builds trees of depth
+// below this (median splits, at most 2^24 triangles)
+constexpr int BVH_STACK = 64;
+
+// Bounding-volume hierarchy node, depth-first order (an inner node's left
+// child follows it).  count > 0: leaf over triangles [first, first + count);
+// count == 0: inner node whose right child is node `first`.
+struct BvhNode {
+  double lo[3], hi[3];
+  int32_t first;
+  int32_t count;
+};
+
+// One registered mesh (local frame), triangles in leaf order.  n_tri == 0:
+// free slot.
+struct DevMesh {
+  int32_t n_tri, n_node;
+  const double* tv;        // [n_tri][9] corners a, b, c (counter-clockwise from outside)
+  const double* tn;        // [n_tri][3] unit outward face normal
+  const int32_t* tid;      // [n_tri][6] vertex ids of a, b, c; edge ids of ab, bc, ca
+  const double* en;        // [n_edge][3] edge pseudonormal (sum of the two face normals)
+  const double* vn;        // [n_vert][3] vertex pseudonormal (angle-weighted normal sum)
+  const BvhNode* nodes;
+};
+
 // Indenter poses of one pad for the current step (uploaded at step start)
 // and the poses the friction lag is taken under (the previous step's, or
 // the current ones when there is none).
@@ -168,6 +195,7 @@ struct EnvDesc {
   double* part_s3;           // [3 n_st]
   EnvState* st;
   const EnvPose* pose;
+  const DevMesh* meshes;     // [MAX_MESHES] the context's rigid meshes
   // material table (Eq. 1) and parameters
   // cshift = lam (alpha - 1): mu for the rest-stable shift, 0 for alpha = 1
   double mu[MAX_MAT], lam[MAX_MAT], alpha[MAX_MAT], rho[MAX_MAT], cshift[MAX_MAT];

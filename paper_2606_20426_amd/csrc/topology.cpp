@@ -100,10 +100,16 @@ tc_status validate_indenters(int n, const tc_indenter* ind, std::string& err) {
   if (n > 0 && !ind) { err = "indenter array is null"; return TC_E_INVALID_ARG; }
   for (int k = 0; k < n; ++k) {
     const tc_indenter& q = ind[k];
-    if (q.shape < TC_SPHERE || q.shape > TC_TEXTURE) { err = fmt("indenter %lld: unknown shape", k); return TC_E_INVALID_ARG; }
-    const int need = q.shape == TC_SPHERE ? 1 : q.shape == TC_BOX ? 3 : 2;
-    for (int j = 0; j < need; ++j)
-      if (!finite(q.prm[j]) || !(q.prm[j] > 0)) { err = fmt("indenter %lld: parameter %lld must be > 0", k, j); return TC_E_INVALID_ARG; }
+    if (q.shape < TC_SPHERE || q.shape > TC_MESH) { err = fmt("indenter %lld: unknown shape", k); return TC_E_INVALID_ARG; }
+    if (q.shape == TC_MESH) {
+      if (q.reserved < 0 || q.reserved >= TC_MAX_MESHES) { err = fmt("indenter %lld: mesh id out of range", k); return TC_E_INVALID_ARG; }
+      for (int j = 0; j < 4; ++j)
+        if (!finite(q.prm[j])) { err = fmt("indenter %lld: parameter %lld not finite", k, j); return TC_E_INVALID_ARG; }
+    } else {
+      const int need = q.shape == TC_SPHERE ? 1 : q.shape == TC_BOX ? 3 : 2;
+      for (int j = 0; j < need; ++j)
+        if (!finite(q.prm[j]) || !(q.prm[j] > 0)) { err = fmt("indenter %lld: parameter %lld must be > 0", k, j); return TC_E_INVALID_ARG; }
+    }
     for (int j = 0; j < 3; ++j)
       if (!finite(q.c[j])) { err = fmt("indenter %lld: centre not finite", k); return TC_E_INVALID_ARG; }
     // R^T R = I and det R = +1

@@ -203,14 +203,15 @@ def icosphere(r, level):
     return r * np.array(V), np.array(F, np.int32)
 
 
-def torus_surface(R, r, nu, nv):
+def torus_surface(R, r, nu, nv, phase=0.0):
     """Torus about the local z axis (ring radius R, tube radius r), nu x nv
-    quads split into triangles."""
+    quads split into triangles; the tube polygon starts `phase` segments
+    round (0.5 puts a facet, not a polygon edge, at the bottom)."""
     V = []
     for i in range(nu):
         u = 2 * np.pi * i / nu
         for j in range(nv):
-            v = 2 * np.pi * j / nv
+            v = 2 * np.pi * (j + phase) / nv
             V.append(((R + r * np.cos(v)) * np.cos(u), (R + r * np.cos(v)) * np.sin(u), r * np.sin(v)))
     F = []
     for i in range(nu):

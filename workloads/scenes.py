@@ -241,6 +241,28 @@ def press_slide_episode():
     return pad, params, poses
 
 
+def mesh_press_episode():
+    """Rigid triangle-mesh indenters on config1's pad: a torus surface (ring
+    4 mm, tube 1.5 mm, 16 x 8 quads, a facet strip at the bottom) lying flat
+    at (9, 7) mm, pressed 0.5 mm over 5 steps.  Returns (pad, params, [pose
+    of step 1 .. 5])."""
+    pad = box_pad(18 * MM, 14 * MM, 4 * MM, 12, 9, 3, Material(0.3e6, 0.45, 1000.0), name="mesh")
+    params = Params()
+    mesh = meshes.torus_surface(4 * MM, 1.5 * MM, 16, 8, phase=0.5)
+    low = -mesh[0][:, 2].min()
+    c = np.array([9 * MM, 7 * MM, pad.X[:, 2].max() + params.dhat + low])
+    start = Indenter(MESH, (0.0, 0.0, 0.0, 0.0), np.eye(3), c, mesh)
+    return pad, params, [start.at_depth(0.5 * MM * s / 5) for s in range(1, 6)]
+
+
+def mesh_slide_episode():
+    """press_slide_episode with the sphere given as an icosphere surface
+    (r = 5 mm, 320 triangles): the facets turn with the twist."""
+    pad, params, poses = press_slide_episode()
+    mesh = meshes.icosphere(5 * MM, 2)
+    return pad, params, [Indenter(MESH, (0.0, 0.0, 0.0, 0.0), p.R, p.c, mesh) for p in poses]
+
+
 def config1():
     """Single 18x14x4 mm pad, 12x9x3 cells, sphere r = 5 mm at a seeded (x, y)
     on the top face shrunk by r/2 margins (seed 1), 0.5 mm over 10 steps."""
