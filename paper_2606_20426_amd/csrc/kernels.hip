@@ -757,6 +757,30 @@ __global__ void k_project(const Tile* tiles, int ntiles, const EnvDesc* envs) {
   if (!(dmin > 0.0)) atomicOr(&S->infeasible, 1);
 }
 
+// Block (a, b) of a per-tet record (the 10 stored blocks, a <= b; the
+// transpose for a > b).
+template <typename R>
+__device__ __forceinline__ void load_block(const R* rec, int a, int b, R blk[3][3]) {
+  if (a == b) {
+    const R* p = rec + ke_block_offset(a, a);
+    blk[0][0] = p[0]; blk[0][1] = p[1]; blk[0][2] = p[2];
+    blk[1][0] = p[1]; blk[1][1] = p[3]; blk[1][2] = p[4];
+    blk[2][0] = p[2]; blk[2][1] = p[4]; blk[2][2] = p[5];
+  } else if (a < b) {
+    const R* p = rec + ke_block_offset(a, b);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) blk[i][k] = p[3 * i + k];
+  } else {
+    const R* p = rec + ke_block_offset(b, a);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) blk[i][k] = p[3 * k + i];
+  }
+}
+
 // ------------------------------------------------------ element (a3)
 
 // Per tet: F = Ds Dm^-1, P (Eq. 2 with shift alpha), gradient V_e P G_a^T and
@@ -898,17 +922,35 @@ __global__ void __launch_bounds__(256) k_element(const Tile* tiles, int ntiles, 
       }
     }
   }
-  R* out = (R*)E.Ke + (size_t)KE_STRIDE * e;
-  if constexpr (sizeof(R) == 4) {
-    float4* o4 = reinterpret_cast<float4*>(out);
+  // scatter the 16 blocks to their places in the contribution stream
+  R* Kc = (R*)E.Ke;
+  int cp[16];
+  const int4* cp4 = reinterpret_cast<const int4*>(E.cpos) + 4 * (size_t)e;
 #pragma unroll
-    for (int k = 0; k < KE_STRIDE / 4; ++k)
-      o4[k] = make_float4(rec[4 * k], rec[4 * k + 1], rec[4 * k + 2], rec[4 * k + 3]);
-  } else {
-    double2* o2 = reinterpret_cast<double2*>(out);
-#pragma unroll
-    for (int k = 0; k < KE_STRIDE / 2; ++k) o2[k] = make_double2(rec[2 * k], rec[2 * k + 1]);
+  for (int q = 0; q < 4; ++q) {
+    const int4 v = cp4[q];
+    cp[4 * q] = v.x; cp[4 * q + 1] = v.y; cp[4 * q + 2] = v.z; cp[4 * q + 3] = v.w;
   }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      R* o = Kc + (size_t)KC * cp[4 * a + b];
+      if (a == b) {
+        const R* p = rec + ke_block_offset(a, a);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) o[k] = p[k];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) o[6 + r] = rec[KE_GRAD + 3 * a + r];
+      } else {
+        R blk[3][3];
+        load_block(rec, a, b, blk);
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+          for (int q = 0; q < 3; ++q) o[3 * r + q] = blk[r][q];
+      }
+    }
 }
 
 // ------------------------------------------------------ barrier (a4)
@@ -998,28 +1040,6 @@ __global__ void k_barrier(const Tile* tiles, int ntiles, const EnvDesc* envs) {
 
 // ------------------------------------------------------ assembly
 
-template <typename R>
-__device__ __forceinline__ void load_block(const R* rec, int a, int b, R blk[3][3]) {
-  if (a == b) {
-    const R* p = rec + ke_block_offset(a, a);
-    blk[0][0] = p[0]; blk[0][1] = p[1]; blk[0][2] = p[2];
-    blk[1][0] = p[1]; blk[1][1] = p[3]; blk[1][2] = p[4];
-    blk[2][0] = p[2]; blk[2][1] = p[4]; blk[2][2] = p[5];
-  } else if (a < b) {
-    const R* p = rec + ke_block_offset(a, b);
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int k = 0; k < 3; ++k) blk[i][k] = p[3 * i + k];
-  } else {
-    const R* p = rec + ke_block_offset(b, a);
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int k = 0; k < 3; ++k) blk[i][k] = p[3 * k + i];
-  }
-}
-
 // Diagonal block rows (slot 0): sum of element blocks, inertia, barrier,
 // Dirichlet masking, gradient, preconditioner, and CG initialisation
 // (d = 0, r = -g, z = P^-1 r, partial r.z and g.g).
@@ -1037,19 +1057,15 @@ __global__ void k_asm_diag(const Tile* tiles, int ntiles, const EnvDesc* envs) {
   if (valid) {
     double D[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
     double gs[3] = {0, 0, 0};
-    const R* Ke = (const R*)E.Ke;
+    const R* Kc = (const R*)E.Ke;
     const size_t it0 = (size_t)i * E.W;
     for (int c = E.cptr[it0]; c < E.cptr[it0 + 1]; ++c) {
-      const uint32_t code = E.clist[c];
-      const int e = (int)(code >> 4), a = (int)((code >> 2) & 3);
-      const R* rec = Ke + (size_t)KE_STRIDE * e;
-      R blk[3][3];
-      load_block(rec, a, a, blk);
-      for (int r = 0; r < 3; ++r) {
-        for (int q = 0; q < 3; ++q) D[r][q] += (double)blk[r][q];
-        gs[r] += (double)rec[KE_GRAD + 3 * a + r];
-      }
+      const R* p = Kc + (size_t)KC * c;
+      D[0][0] += (double)p[0]; D[0][1] += (double)p[1]; D[0][2] += (double)p[2];
+      D[1][1] += (double)p[3]; D[1][2] += (double)p[4]; D[2][2] += (double)p[5];
+      for (int r = 0; r < 3; ++r) gs[r] += (double)p[6 + r];
     }
+    D[1][0] = D[0][1]; D[2][0] = D[0][2]; D[2][1] = D[1][2];
     const double h2 = E.h * E.h;
     double xi[3], xh[3];
     load3(E.xn, i, xi);
@@ -1147,16 +1163,13 @@ __global__ void k_asm_off(const Tile* tiles, int ntiles, const EnvDesc* envs) {
   const int j = E.col[item];
   R acc[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
   if (j >= 0) {
-    const R* Ke = (const R*)E.Ke;
+    const R* Kc = (const R*)E.Ke;
     for (int c = E.cptr[item]; c < E.cptr[item + 1]; ++c) {
-      const uint32_t code = E.clist[c];
-      const int e = (int)(code >> 4), a = (int)((code >> 2) & 3), b = (int)(code & 3);
-      R blk[3][3];
-      load_block(Ke + (size_t)KE_STRIDE * e, a, b, blk);
+      const R* p = Kc + (size_t)KC * c;
 #pragma unroll
       for (int r = 0; r < 3; ++r)
 #pragma unroll
-        for (int q = 0; q < 3; ++q) acc[r][q] += blk[r][q];
+        for (int q = 0; q < 3; ++q) acc[r][q] += p[3 * r + q];
     }
     const R h2 = (R)(E.h * E.h);
     const uint8_t fi = E.fixed[i], fj = E.fixed[j];

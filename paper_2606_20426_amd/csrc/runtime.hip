@@ -286,7 +286,7 @@ static ScratchLayout scratch_layout(const tc_pad* p) {
   size_t o = 0;
   auto take = [&](size_t b) { const size_t r = o; o += align256(b == 0 ? 8 : b); return r; };
   const size_t R = (size_t)p->rsize, V = p->V, T = p->T, C = std::max(p->C, 1), S = p->S;
-  L.Ke = take(T * KE_STRIDE * R);
+  L.Ke = take(16 * T * KC * R);
   L.A = take((size_t)p->W * 9 * V * R);
   L.xn = take(24 * V);
   L.xhat = take(24 * V);
@@ -682,9 +682,9 @@ static double kernel_bytes(KernelId k, const tc_pad* p) {
   switch (k) {
     case KernelId::cg_spmv: return nnzb * (9 * R + 4) + V * 12 * R;
     case KernelId::cg_update: return V * (21 * R + 48);
-    case KernelId::element: return T * (16 + 106 * R) + V * 48;
-    case KernelId::asm_diag: return T * (16 + 36 * R) + V * (93 + 24 * R);
-    case KernelId::asm_off: return T * (48 + 108 * R) + (W - 1) * V * (8 + 9 * R);
+    case KernelId::element: return T * (80 + 154 * R) + V * 48;
+    case KernelId::asm_diag: return T * (36 * R) + V * (93 + 24 * R);
+    case KernelId::asm_off: return T * (108 * R) + (W - 1) * V * (8 + 9 * R);
     case KernelId::energy:   // friction: x_t and one indenter's lag record per contact vertex
       return T * (16 + 10 * R) + V * (56 + 3 * R) + C * 40 + (p->params.friction > 0 ? C * 88 : 0);
     case KernelId::sigma: return T * (16 + 15 * R) + V * 24;
@@ -1217,6 +1217,7 @@ tc_status tc_pad_create(tc_context* ctx, const tc_mesh* mesh, int32_t n_material
     double *X, *x, *v, *mass, *carea;
     int32_t *tets, *cand, *cov, *tris, *parent, *ctp, *cti, *col, *cptr;
     uint32_t* clist;
+    int32_t* cpos;
     uint8_t *fixed, *istop;
     int8_t* mat = nullptr;
     void *Dminv, *vol;
@@ -1240,6 +1241,7 @@ tc_status tc_pad_create(tc_context* ctx, const tc_mesh* mesh, int32_t n_material
     ALLOC(col, int32_t*, 4 * t.col.size());
     ALLOC(cptr, int32_t*, 4 * t.cptr.size());
     ALLOC(clist, uint32_t*, 4 * t.clist.size());
+    ALLOC(cpos, int32_t*, 4 * t.cpos.size());
     ALLOC(E.sigma, void*, 6 * T * R);
     ALLOC(E.traction, void*, 3 * S * R);
     ALLOC(E.pressure, void*, S * R);
@@ -1278,12 +1280,13 @@ tc_status tc_pad_create(tc_context* ctx, const tc_mesh* mesh, int32_t n_material
     if ((s = upload(ctx, col, t.col.data(), 4 * t.col.size()))) return s;
     if ((s = upload(ctx, cptr, t.cptr.data(), 4 * t.cptr.size()))) return s;
     if ((s = upload(ctx, clist, t.clist.data(), 4 * t.clist.size()))) return s;
+    if ((s = upload(ctx, cpos, t.cpos.data(), 4 * t.cpos.size()))) return s;
     TC_HIP(hipMemsetAsync(E.reaction, 0, 24, ctx->stream));
     TC_HIP(hipMemsetAsync(E.traction_sum, 0, 24, ctx->stream));
     E.X = X; E.x = x; E.v = v; E.tets = tets; E.Dminv = Dminv; E.vol = vol; E.mat = mat;
     E.mass = mass; E.fixed = fixed; E.cand = cand; E.cand_of_vert = cov; E.cand_area = carea;
     E.tris = tris; E.parent = parent; E.is_top = istop; E.ctri_ptr = ctp; E.ctri_idx = cti;
-    E.col = col; E.cptr = cptr; E.clist = clist;
+    E.col = col; E.cptr = cptr; E.clist = clist; E.cpos = cpos;
     E.meshes = ctx->d_meshes;
     for (int k = 0; k < MAX_MAT; ++k) {
       E.mu[k] = p->mu[k]; E.lam[k] = p->lam[k]; E.alpha[k] = p->alpha[k]; E.rho[k] = p->rho[k];

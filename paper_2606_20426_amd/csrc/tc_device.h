@@ -9,11 +9,17 @@ namespace tc {
 
 constexpr int MAX_IND = 5;
 constexpr int MAX_MAT = 8;
-// Per-tet record written by the element kernel: the 78 independent entries
-// of the symmetric 12x12 element Hessian in 10 blocks (a <= b), then the 12
-// gradient entries, padded to 96 values.
+// Per-tet record the element kernel accumulates in registers: the 78
+// independent entries of the symmetric 12x12 element Hessian in 10 blocks
+// (a <= b), then the 12 gradient entries, padded to 96 values.
 constexpr int KE_STRIDE = 96;
 constexpr int KE_GRAD = 78;
+// Values per block of the element contribution stream: the element kernel
+// scatters each tet's 16 blocks (a, b) to their positions in the
+// contribution list (row, slot, ascending tet), so assembly reads every row's
+// contributions contiguously.  Diagonal block: xx, xy, xz, yy, yz, zz and
+// the gradient of vertex a; off-diagonal block: 3x3 row-major.
+constexpr int KC = 9;
 // rows handled by each lane group of the vectorised SpMV per tile
 constexpr int SPMV_ROWS_PER_GROUP = 4;
 
@@ -153,6 +159,7 @@ struct EnvDesc {
   const int32_t* col;        // [V][W] block column of each stored block, -1 = empty
   const int32_t* cptr;       // [V*W+1] contribution ranges per (row, slot)
   const uint32_t* clist;     // (tet << 4) | (a << 2) | b
+  const int32_t* cpos;       // [T][16] position of block (a, b) of tet e in clist
   // outputs
   void* sigma;               // real [T][6]
   void* traction;            // real [S][3]
@@ -170,7 +177,7 @@ struct EnvDesc {
   double* reaction;          // [3]
   double* traction_sum;      // [3]
   // step scratch
-  void* Ke;                  // real [T][KE_STRIDE]
+  void* Ke;                  // real [16 T][KC] element blocks in clist order
   void* A;                   // real [V][W][9] row-major 3x3 blocks
   double* xn;                // Newton iterate [V][3]
   double* xhat;

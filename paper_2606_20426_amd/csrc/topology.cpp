@@ -270,11 +270,13 @@ void build_sparsity(const tc_mesh* m, Topology& t) {
   for (int64_t k = 0; k < NI; ++k) cnt[k + 1] += cnt[k];
   t.cptr = cnt;
   t.clist.assign(16LL * T, 0);
+  t.cpos.assign(16LL * T, 0);
   std::vector<int32_t> pos(cnt.begin(), cnt.end() - 1);
   for (int e = 0; e < T; ++e)
     for (int a = 0; a < 4; ++a)
       for (int b = 0; b < 4; ++b) {
         const int64_t it = item[16LL * e + 4 * a + b];
+        t.cpos[16LL * e + 4 * a + b] = pos[it];
         t.clist[pos[it]++] = ((uint32_t)e << 4) | ((uint32_t)a << 2) | (uint32_t)b;
       }
 }

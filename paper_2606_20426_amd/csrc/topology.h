@@ -30,6 +30,7 @@ struct Topology {
   std::vector<int32_t> col;       // [W*V]
   std::vector<int32_t> cptr;      // [V*W+1] gather range of each (row, slot)
   std::vector<uint32_t> clist;    // (tet << 4) | (a << 2) | b, ascending tet
+  std::vector<int32_t> cpos;      // [T][16] position of block (a, b) of tet e in clist
 };
 
 // Checks of tacauchy.h (tc_validate_mesh); err receives the message.
