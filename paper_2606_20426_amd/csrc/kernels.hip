@@ -922,35 +922,36 @@ __global__ void __launch_bounds__(256) k_element(const Tile* tiles, int ntiles, 
       }
     }
   }
-  // scatter the 16 blocks to their places in the contribution stream
-  R* Kc = (R*)E.Ke;
-  int cp[16];
-  const int4* cp4 = reinterpret_cast<const int4*>(E.cpos) + 4 * (size_t)e;
+  // scatter the 4 diagonal and 6 edge blocks to their places in the streams
+  R* Kd = (R*)E.Ke;
+  R* Ko = Kd + (size_t)KC * 4 * E.T;
+  const int32_t* cp = E.cpos + 10 * (size_t)e;
+  const int vv[4] = {tv.x, tv.y, tv.z, tv.w};
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int4 v = cp4[q];
-    cp[4 * q] = v.x; cp[4 * q + 1] = v.y; cp[4 * q + 2] = v.z; cp[4 * q + 3] = v.w;
+  for (int a = 0; a < 4; ++a) {
+    R* o = Kd + (size_t)KC * cp[a];
+    const R* p = rec + ke_block_offset(a, a);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) o[k] = p[k];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) o[6 + r] = rec[KE_GRAD + 3 * a + r];
   }
+  constexpr int pa[6] = {0, 0, 0, 1, 1, 2}, pb[6] = {1, 2, 3, 2, 3, 3};
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int k = 0; k < 6; ++k) {
+    // block (row min, column max) of the edge: (a, b) or its transpose
+    R* o = Ko + (size_t)KC * cp[4 + k];
+    const R* p = rec + ke_block_offset(pa[k], pb[k]);
+    if (vv[pa[k]] < vv[pb[k]]) {
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      R* o = Kc + (size_t)KC * cp[4 * a + b];
-      if (a == b) {
-        const R* p = rec + ke_block_offset(a, a);
+      for (int q = 0; q < 9; ++q) o[q] = p[q];
+    } else {
 #pragma unroll
-        for (int k = 0; k < 6; ++k) o[k] = p[k];
+      for (int r = 0; r < 3; ++r)
 #pragma unroll
-        for (int r = 0; r < 3; ++r) o[6 + r] = rec[KE_GRAD + 3 * a + r];
-      } else {
-        R blk[3][3];
-        load_block(rec, a, b, blk);
-#pragma unroll
-        for (int r = 0; r < 3; ++r)
-#pragma unroll
-          for (int q = 0; q < 3; ++q) o[3 * r + q] = blk[r][q];
-      }
+        for (int q = 0; q < 3; ++q) o[3 * r + q] = p[3 * q + r];
     }
+  }
 }
 
 // ------------------------------------------------------ barrier (a4)
@@ -1057,10 +1058,10 @@ __global__ void k_asm_diag(const Tile* tiles, int ntiles, const EnvDesc* envs) {
   if (valid) {
     double D[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
     double gs[3] = {0, 0, 0};
-    const R* Kc = (const R*)E.Ke;
+    const R* Kd = (const R*)E.Ke;
     const size_t it0 = (size_t)i * E.W;
-    for (int c = E.cptr[it0]; c < E.cptr[it0 + 1]; ++c) {
-      const R* p = Kc + (size_t)KC * c;
+    for (int c = E.dptr[i]; c < E.dptr[i + 1]; ++c) {
+      const R* p = Kd + (size_t)KC * c;
       D[0][0] += (double)p[0]; D[0][1] += (double)p[1]; D[0][2] += (double)p[2];
       D[1][1] += (double)p[3]; D[1][2] += (double)p[4]; D[2][2] += (double)p[5];
       for (int r = 0; r < 3; ++r) gs[r] += (double)p[6 + r];
@@ -1146,44 +1147,39 @@ __global__ void k_asm_diag(const Tile* tiles, int ntiles, const EnvDesc* envs) {
   }
 }
 
-// Off-diagonal blocks (slots >= 1): sum of element blocks (a, b) of every tet
-// sharing the edge, times h^2, Dirichlet rows and columns zeroed.
+// Off-diagonal blocks, one thread per unique edge i < j: sum of the edge
+// blocks of every tet sharing it, times h^2, written to (i, slot of j) and
+// transposed to (j, slot of i), Dirichlet rows and columns zeroed.
 template <typename R>
 __global__ void k_asm_off(const Tile* tiles, int ntiles, const EnvDesc* envs) {
   const int t = xcd_tile(ntiles);
   if (t < 0) return;
   const EnvDesc& E = envs[tiles[t].env];
   if (!running(E.st)) return;
-  const int W1 = E.W - 1;
-  if (W1 <= 0) return;
-  const int64_t t2 = (int64_t)tiles[t].tile * blockDim.x + threadIdx.x;
-  if (t2 >= (int64_t)E.V * W1) return;
-  const int i = (int)(t2 / W1), s = 1 + (int)(t2 - (int64_t)i * W1);
-  const size_t item = (size_t)i * E.W + s;       // row-major (row, slot)
-  const int j = E.col[item];
+  const int k = tiles[t].tile * blockDim.x + threadIdx.x;
+  if (k >= E.V_E) return;
+  const R* Ko = (const R*)E.Ke + (size_t)KC * 4 * E.T;
   R acc[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-  if (j >= 0) {
-    const R* Kc = (const R*)E.Ke;
-    for (int c = E.cptr[item]; c < E.cptr[item + 1]; ++c) {
-      const R* p = Kc + (size_t)KC * c;
-#pragma unroll
-      for (int r = 0; r < 3; ++r)
-#pragma unroll
-        for (int q = 0; q < 3; ++q) acc[r][q] += p[3 * r + q];
-    }
-    const R h2 = (R)(E.h * E.h);
-    const uint8_t fi = E.fixed[i], fj = E.fixed[j];
+  for (int c = E.eptr[k]; c < E.eptr[k + 1]; ++c) {
+    const R* p = Ko + (size_t)KC * c;
 #pragma unroll
     for (int r = 0; r < 3; ++r)
 #pragma unroll
-      for (int q = 0; q < 3; ++q)
-        acc[r][q] = (((fi >> r) & 1) || ((fj >> q) & 1)) ? R(0) : acc[r][q] * h2;
+      for (int q = 0; q < 3; ++q) acc[r][q] += p[3 * r + q];
   }
-  R* A = (R*)E.A + item * 9;
+  const int2 it = reinterpret_cast<const int2*>(E.eitem)[k];
+  const int i = it.x / E.W, j = it.y / E.W;
+  const R h2 = (R)(E.h * E.h);
+  const uint8_t fi = E.fixed[i], fj = E.fixed[j];
+  R* Aij = (R*)E.A + (size_t)it.x * 9;
+  R* Aji = (R*)E.A + (size_t)it.y * 9;
 #pragma unroll
   for (int r = 0; r < 3; ++r)
 #pragma unroll
-    for (int q = 0; q < 3; ++q) A[3 * r + q] = acc[r][q];
+    for (int q = 0; q < 3; ++q) {
+      Aij[3 * r + q] = (((fi >> r) & 1) || ((fj >> q) & 1)) ? R(0) : acc[r][q] * h2;
+      Aji[3 * q + r] = (((fj >> q) & 1) || ((fi >> r) & 1)) ? R(0) : acc[r][q] * h2;
+    }
 }
 
 // ------------------------------------------------------ CG (a5)

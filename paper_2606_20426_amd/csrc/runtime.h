@@ -113,6 +113,7 @@ struct tc_pad {
   int id = 0;
   int V = 0, T = 0, C = 0, S = 0, S_top = 0, W = 0;
   int64_t nnz_blocks = 0;
+  int64_t n_edges = 0;               // unique edges (off-diagonal block pairs)
   bool fp64 = false;
   int rsize = 4;
   tc_params params{};

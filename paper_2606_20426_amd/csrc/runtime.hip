@@ -286,7 +286,7 @@ static ScratchLayout scratch_layout(const tc_pad* p) {
   size_t o = 0;
   auto take = [&](size_t b) { const size_t r = o; o += align256(b == 0 ? 8 : b); return r; };
   const size_t R = (size_t)p->rsize, V = p->V, T = p->T, C = std::max(p->C, 1), S = p->S;
-  L.Ke = take(16 * T * KC * R);
+  L.Ke = take(10 * T * KC * R);
   L.A = take((size_t)p->W * 9 * V * R);
   L.xn = take(24 * V);
   L.xhat = take(24 * V);
@@ -422,7 +422,7 @@ tc_status build_plan(tc_context* ctx, int n, tc_pad* const* pads, const int* slo
     E.n_tt = cdiv(p->T, BT);
     E.n_ct = p->C > 0 ? cdiv(p->C, BV) : 0;
     E.n_st = cdiv(p->S, BV);
-    E.n_at = cdiv((int64_t)(p->W - 1) * p->V, BV);
+    E.n_at = cdiv((int64_t)E.V_E, BV);
     E.n_te = cdiv(p->T, BV);
     E.n_spt = cdiv(p->V, rows_spmv);
     E.st = pool.d_state + slots[i];
@@ -682,9 +682,9 @@ static double kernel_bytes(KernelId k, const tc_pad* p) {
   switch (k) {
     case KernelId::cg_spmv: return nnzb * (9 * R + 4) + V * 12 * R;
     case KernelId::cg_update: return V * (21 * R + 48);
-    case KernelId::element: return T * (80 + 154 * R) + V * 48;
-    case KernelId::asm_diag: return T * (36 * R) + V * (93 + 24 * R);
-    case KernelId::asm_off: return T * (108 * R) + (W - 1) * V * (8 + 9 * R);
+    case KernelId::element: return T * (56 + 100 * R) + V * 48;
+    case KernelId::asm_diag: return T * (36 * R) + V * (97 + 24 * R);
+    case KernelId::asm_off: return T * (54 * R) + p->n_edges * (14 + 18 * R);
     case KernelId::energy:   // friction: x_t and one indenter's lag record per contact vertex
       return T * (16 + 10 * R) + V * (56 + 3 * R) + C * 40 + (p->params.friction > 0 ? C * 88 : 0);
     case KernelId::sigma: return T * (16 + 15 * R) + V * 24;
@@ -1179,6 +1179,7 @@ tc_status tc_pad_create(tc_context* ctx, const tc_mesh* mesh, int32_t n_material
     for (auto v : t.is_top) p->S_top += v;
     p->W = t.W;
     p->nnz_blocks = t.nnz_blocks;
+    p->n_edges = (int64_t)(t.eitem.size() / 2);
     p->fp64 = params->precision == TC_PREC_FP64;
     p->rsize = p->fp64 ? 8 : 4;
     p->params = *params;
@@ -1217,7 +1218,7 @@ tc_status tc_pad_create(tc_context* ctx, const tc_mesh* mesh, int32_t n_material
     double *X, *x, *v, *mass, *carea;
     int32_t *tets, *cand, *cov, *tris, *parent, *ctp, *cti, *col, *cptr;
     uint32_t* clist;
-    int32_t* cpos;
+    int32_t *cpos, *dptr, *eptr, *eitem;
     uint8_t *fixed, *istop;
     int8_t* mat = nullptr;
     void *Dminv, *vol;
@@ -1242,6 +1243,9 @@ tc_status tc_pad_create(tc_context* ctx, const tc_mesh* mesh, int32_t n_material
     ALLOC(cptr, int32_t*, 4 * t.cptr.size());
     ALLOC(clist, uint32_t*, 4 * t.clist.size());
     ALLOC(cpos, int32_t*, 4 * t.cpos.size());
+    ALLOC(dptr, int32_t*, 4 * t.dptr.size());
+    ALLOC(eptr, int32_t*, 4 * t.eptr.size());
+    ALLOC(eitem, int32_t*, 4 * std::max<size_t>(t.eitem.size(), 1));
     ALLOC(E.sigma, void*, 6 * T * R);
     ALLOC(E.traction, void*, 3 * S * R);
     ALLOC(E.pressure, void*, S * R);
@@ -1281,12 +1285,17 @@ tc_status tc_pad_create(tc_context* ctx, const tc_mesh* mesh, int32_t n_material
     if ((s = upload(ctx, cptr, t.cptr.data(), 4 * t.cptr.size()))) return s;
     if ((s = upload(ctx, clist, t.clist.data(), 4 * t.clist.size()))) return s;
     if ((s = upload(ctx, cpos, t.cpos.data(), 4 * t.cpos.size()))) return s;
+    if ((s = upload(ctx, dptr, t.dptr.data(), 4 * t.dptr.size()))) return s;
+    if ((s = upload(ctx, eptr, t.eptr.data(), 4 * t.eptr.size()))) return s;
+    if (!t.eitem.empty() && (s = upload(ctx, eitem, t.eitem.data(), 4 * t.eitem.size()))) return s;
     TC_HIP(hipMemsetAsync(E.reaction, 0, 24, ctx->stream));
     TC_HIP(hipMemsetAsync(E.traction_sum, 0, 24, ctx->stream));
     E.X = X; E.x = x; E.v = v; E.tets = tets; E.Dminv = Dminv; E.vol = vol; E.mat = mat;
     E.mass = mass; E.fixed = fixed; E.cand = cand; E.cand_of_vert = cov; E.cand_area = carea;
     E.tris = tris; E.parent = parent; E.is_top = istop; E.ctri_ptr = ctp; E.ctri_idx = cti;
     E.col = col; E.cptr = cptr; E.clist = clist; E.cpos = cpos;
+    E.dptr = dptr; E.eptr = eptr; E.eitem = eitem;
+    E.V_E = (int32_t)(t.eitem.size() / 2);
     E.meshes = ctx->d_meshes;
     for (int k = 0; k < MAX_MAT; ++k) {
       E.mu[k] = p->mu[k]; E.lam[k] = p->lam[k]; E.alpha[k] = p->alpha[k]; E.rho[k] = p->rho[k];

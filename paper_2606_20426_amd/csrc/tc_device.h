@@ -14,11 +14,13 @@ constexpr int MAX_MAT = 8;
 // (a <= b), then the 12 gradient entries, padded to 96 values.
 constexpr int KE_STRIDE = 96;
 constexpr int KE_GRAD = 78;
-// Values per block of the element contribution stream: the element kernel
-// scatters each tet's 16 blocks (a, b) to their positions in the
-// contribution list (row, slot, ascending tet), so assembly reads every row's
-// contributions contiguously.  Diagonal block: xx, xy, xz, yy, yz, zz and
-// the gradient of vertex a; off-diagonal block: 3x3 row-major.
+// Values per block of the element block streams.  The element kernel
+// scatters each tet's 4 diagonal blocks into the diagonal stream (grouped by
+// vertex row, tets ascending) and its 6 edge blocks into the edge stream
+// (grouped by unique edge i < j, tets ascending), so assembly reads every row
+// and every edge contiguously.  Diagonal block: xx, xy, xz, yy, yz, zz and the
+// gradient of the vertex; edge block: the 3x3 block (row i, column j),
+// row-major.
 constexpr int KC = 9;
 // rows handled by each lane group of the vectorised SpMV per tile
 constexpr int SPMV_ROWS_PER_GROUP = 4;
@@ -137,6 +139,7 @@ struct EnvState {
 // arrays, step scratch and outputs, sizes, material table and parameters.
 struct EnvDesc {
   int32_t V, T, C, S, W;
+  int32_t V_E;               // unique edges (off-diagonal block pairs)
   int32_t n_vt, n_tt, n_ct, n_st, n_at, n_te, n_spt;   // tiles per kernel class
   // resident inputs
   const double* X;
@@ -159,7 +162,10 @@ struct EnvDesc {
   const int32_t* col;        // [V][W] block column of each stored block, -1 = empty
   const int32_t* cptr;       // [V*W+1] contribution ranges per (row, slot)
   const uint32_t* clist;     // (tet << 4) | (a << 2) | b
-  const int32_t* cpos;       // [T][16] position of block (a, b) of tet e in clist
+  const int32_t* dptr;       // [V+1] diagonal-stream range of each row
+  const int32_t* eptr;       // [V_E+1] edge-stream range of each edge
+  const int32_t* eitem;      // [V_E][2] blocks (i, slot of j), (j, slot of i)
+  const int32_t* cpos;       // [T][10] stream positions: 4 diagonal, 6 edge blocks
   // outputs
   void* sigma;               // real [T][6]
   void* traction;            // real [S][3]
@@ -177,7 +183,7 @@ struct EnvDesc {
   double* reaction;          // [3]
   double* traction_sum;      // [3]
   // step scratch
-  void* Ke;                  // real [16 T][KC] element blocks in clist order
+  void* Ke;                  // real [4 T][KC] diagonal stream, then [6 T][KC] edge stream
   void* A;                   // real [V][W][9] row-major 3x3 blocks
   double* xn;                // Newton iterate [V][3]
   double* xhat;

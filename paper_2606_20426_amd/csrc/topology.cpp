@@ -270,15 +270,46 @@ void build_sparsity(const tc_mesh* m, Topology& t) {
   for (int64_t k = 0; k < NI; ++k) cnt[k + 1] += cnt[k];
   t.cptr = cnt;
   t.clist.assign(16LL * T, 0);
-  t.cpos.assign(16LL * T, 0);
   std::vector<int32_t> pos(cnt.begin(), cnt.end() - 1);
   for (int e = 0; e < T; ++e)
     for (int a = 0; a < 4; ++a)
       for (int b = 0; b < 4; ++b) {
         const int64_t it = item[16LL * e + 4 * a + b];
-        t.cpos[16LL * e + 4 * a + b] = pos[it];
         t.clist[pos[it]++] = ((uint32_t)e << 4) | ((uint32_t)a << 2) | (uint32_t)b;
       }
+  // streams: diagonal blocks grouped by row, off-diagonal blocks grouped by
+  // unique edge (i < j, in row-major (i, slot) order), tets ascending in each
+  t.dptr.assign(V + 1, 0);
+  for (int i = 0; i < V; ++i) t.dptr[i + 1] = t.dptr[i] + (cnt[(int64_t)i * W + 1] - cnt[(int64_t)i * W]);
+  std::vector<int64_t> edge_of(NI, -1);
+  t.eitem.clear();
+  for (int i = 0; i < V; ++i)
+    for (size_t sl = 1; sl < nb[i].size(); ++sl) {
+      const int j = nb[i][sl];
+      if (j < i) continue;
+      edge_of[(int64_t)i * W + sl] = (int64_t)(t.eitem.size() / 2);
+      t.eitem.push_back((int32_t)((int64_t)i * W + sl));
+      t.eitem.push_back((int32_t)((int64_t)j * W + slot_of(j, i)));
+    }
+  const int64_t NE = (int64_t)t.eitem.size() / 2;
+  t.eptr.assign(NE + 1, 0);
+  for (int64_t k = 0; k < NE; ++k) {
+    const int64_t it = t.eitem[2 * k];
+    t.eptr[k + 1] = t.eptr[k] + (cnt[it + 1] - cnt[it]);
+  }
+  t.cpos.assign(10LL * T, 0);
+  std::vector<int32_t> dfill(t.dptr.begin(), t.dptr.end() - 1);
+  std::vector<int32_t> efill(t.eptr.begin(), t.eptr.end() - 1);
+  static const int kPair[6][2] = {{0, 1}, {0, 2}, {0, 3}, {1, 2}, {1, 3}, {2, 3}};
+  for (int e = 0; e < T; ++e) {
+    const int32_t* tv = m->tets + 4LL * e;
+    for (int a = 0; a < 4; ++a) t.cpos[10LL * e + a] = dfill[tv[a]]++;
+    for (int k = 0; k < 6; ++k) {
+      const int i = std::min(tv[kPair[k][0]], tv[kPair[k][1]]), j = std::max(tv[kPair[k][0]], tv[kPair[k][1]]);
+      const int64_t ek = edge_of[(int64_t)i * W + slot_of(i, j)];
+      t.cpos[10LL * e + 4 + k] = efill[ek]++;
+    }
+  }
 }
 
 }  // namespace tc

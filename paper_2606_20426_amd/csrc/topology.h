@@ -30,7 +30,13 @@ struct Topology {
   std::vector<int32_t> col;       // [W*V]
   std::vector<int32_t> cptr;      // [V*W+1] gather range of each (row, slot)
   std::vector<uint32_t> clist;    // (tet << 4) | (a << 2) | b, ascending tet
-  std::vector<int32_t> cpos;      // [T][16] position of block (a, b) of tet e in clist
+  // element block streams of assembly: diagonal blocks by row (ascending
+  // tet), off-diagonal blocks by unique edge i < j (ascending tet)
+  std::vector<int32_t> dptr;      // [V+1] diagonal-stream range of each row
+  std::vector<int32_t> eptr;      // [NE+1] off-diagonal-stream range of each edge
+  std::vector<int32_t> eitem;     // [NE][2] blocks (i, slot of j) and (j, slot of i)
+  std::vector<int32_t> cpos;      // [T][10] stream positions: diagonal a = 0..3,
+                                  // then pairs (0,1) (0,2) (0,3) (1,2) (1,3) (2,3)
 };
 
 // Checks of tacauchy.h (tc_validate_mesh); err receives the message.
