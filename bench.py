@@ -163,6 +163,7 @@ def run_steps(args):
     log(f"pads created in {time.perf_counter() - t0:.1f} s; HBM used {ctx.memory()[0] / 2**30:.2f} GiB")
     ctx.set_launch(cg_block=args.cg_block, elem_block=args.elem_block, spmv_block=args.spmv_block,
                    use_graphs=args.graphs)
+    ctx.set_cg_variant(args.cg_variant)
     if args.autotune:
         chosen = ctx.autotune(pads, [[e.pose(1)] for e in envs])
         log(f"autotune: vertex block {chosen[0]}, element block {chosen[1]}, SpMV block {chosen[2]}")
@@ -206,7 +207,8 @@ def run_steps(args):
         "config": {"workload": args.workload, "description": desc, "envs": n_env,
                    "tets": int(sum(e.pad.tets.shape[0] for e in envs)), "mode": mode,
                    "newton_max_mean": float(np.mean(newton)), "cg_iters_mean": float(np.mean(cg)),
-                   "precision": args.precision, "graphs": bool(args.graphs and args.no_timing)},
+                   "precision": args.precision, "graphs": bool(args.graphs and args.no_timing),
+                   "cg_variant": "pipelined" if args.cg_variant else "classic"},
         "roofline": roof,
     }
     if not args.no_cpu_baseline:
@@ -225,6 +227,7 @@ def run_serve(args):
     envs, desc = build_workload(args.workload)
     n_pads = len(envs)
     ctx = tc.Context(0, hbm_budget=int(args.hbm_budget_gib * 2**30) if args.hbm_budget_gib else 0)
+    ctx.set_cg_variant(args.cg_variant)
     t0 = time.perf_counter()
     pads = make_pads(tc, ctx, envs, args)
     resident = sum(p.info["resident_bytes"] for p in pads)
@@ -302,6 +305,7 @@ def run_ablation(args):
     envs, desc = build_workload(args.workload)
     e = envs[0]
     ctx = tc.Context(0)
+    ctx.set_cg_variant(args.cg_variant)
     res = {}
     steps = min(args.steps, e.n_steps) if args.steps else e.n_steps
     for prec in ("mixed", "fp64"):
@@ -369,6 +373,7 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MiB",
                     help="run 4 device copies of this size first (counter calibration)")
     ap.add_argument("--graphs", type=int, default=0)
+    ap.add_argument("--cg-variant", type=int, default=0, help="0 classic PCG, 1 pipelined PCG")
     ap.add_argument("--cg-block", type=int, default=0)
     ap.add_argument("--elem-block", type=int, default=0)
     ap.add_argument("--spmv-block", type=int, default=0)

@@ -314,6 +314,17 @@ tc_status tc_autotune(tc_context* ctx, int32_t n, tc_pad* const* pads,
 tc_status tc_set_launch(tc_context* ctx, int32_t cg_block, int32_t elem_block, int32_t spmv_block,
                         int32_t cg_per_replay, int32_t use_graphs);
 
+/* Linear solver of every pad of the context: 0 (default) classic
+ * preconditioned CG, two launches per iteration (product; update) with two
+ * global reductions; 1 pipelined preconditioned CG (Ghysels and Vanroose,
+ * Parallel Computing 40, 2014): one fused launch per iteration (product,
+ * recurrences and both dot products), the same stop test on r . M^-1 r and
+ * the same breakdown test on p . Ap, at the cost of five more vectors of step
+ * scratch and recurrences for w = A u and A M^-1 s.  Releases the step
+ * scratch of every pad (its size changes); TC_E_BUSY while a pad has a
+ * request on a server. */
+tc_status tc_set_cg_variant(tc_context* ctx, int32_t variant);
+
 /* ------------------------------------------------------------------- pads */
 /* Copies the mesh and materials into HBM and runs the setup kernels: Eq. 1
  * Lame parameters, Dm^-1 and V_e, lumped mass, rest contact areas; builds the

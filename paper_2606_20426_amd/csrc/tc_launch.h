@@ -32,6 +32,8 @@ enum class KernelId : int {
   contact,
   env_extract,
   commit,
+  cg_pipe_init,
+  cg_pipe,
   count
 };
 
@@ -40,7 +42,7 @@ inline const char* kernel_name(KernelId k) {
                                 "element",    "barrier",    "asm_diag",   "asm_off",   "newton_begin",
                                 "cg_spmv",    "cg_update",  "newton_dir", "filter",    "env_dir",
                                 "energy",     "env_ls",     "update",     "env_update", "sigma",     "traction",
-                                "contact",    "env_extract", "commit"};
+                                "contact",    "env_extract", "commit",    "cg_pipe_init", "cg_pipe"};
   return names[static_cast<int>(k)];
 }
 
@@ -63,7 +65,9 @@ struct LaunchArgs {
 };
 
 // Kernels that time themselves with the GPU wall clock when given a slot.
-inline bool self_timed(KernelId k) { return k == KernelId::cg_spmv || k == KernelId::cg_update; }
+inline bool self_timed(KernelId k) {
+  return k == KernelId::cg_spmv || k == KernelId::cg_update || k == KernelId::cg_pipe;
+}
 
 // Launch errors surface through hipGetLastError.
 hipError_t launch_kernel(KernelId id, bool fp64, const LaunchArgs& a);
