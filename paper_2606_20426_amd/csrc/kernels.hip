@@ -936,13 +936,12 @@ __global__ void __launch_bounds__(256) k_element(const Tile* tiles, int ntiles, 
 #pragma unroll
     for (int r = 0; r < 3; ++r) o[6 + r] = rec[KE_GRAD + 3 * a + r];
   }
-  constexpr int pa[6] = {0, 0, 0, 1, 1, 2}, pb[6] = {1, 2, 3, 2, 3, 3};
-#pragma unroll
-  for (int k = 0; k < 6; ++k) {
-    // block (row min, column max) of the edge: (a, b) or its transpose
+  // edge k = (a, b): block (row min, column max) of the edge, i.e. (a, b) or
+  // its transpose (constant a, b per call: no indexed local arrays)
+  auto edge_out = [&](int k, int a, int b) {
     R* o = Ko + (size_t)KC * cp[4 + k];
-    const R* p = rec + ke_block_offset(pa[k], pb[k]);
-    if (vv[pa[k]] < vv[pb[k]]) {
+    const R* p = rec + ke_block_offset(a, b);
+    if (vv[a] < vv[b]) {
 #pragma unroll
       for (int q = 0; q < 9; ++q) o[q] = p[q];
     } else {
@@ -951,7 +950,9 @@ __global__ void __launch_bounds__(256) k_element(const Tile* tiles, int ntiles, 
 #pragma unroll
         for (int q = 0; q < 3; ++q) o[3 * r + q] = p[3 * q + r];
     }
-  }
+  };
+  edge_out(0, 0, 1); edge_out(1, 0, 2); edge_out(2, 0, 3);
+  edge_out(3, 1, 2); edge_out(4, 1, 3); edge_out(5, 2, 3);
 }
 
 // ------------------------------------------------------ barrier (a4)
