@@ -1,0 +1,129 @@
+"""Edge cases of the step: no indenter at all, the maximum number of
+indenters at once (against the oracle), a pad without contact vertices (alone
+and inside a batch), and friction pads on the server (their previous poses
+advance with served steps exactly as with synchronous ones)."""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+import pytest
+
+from gpu_util import context, errors, gpu_pad, log, oracle_pad, outputs, tc
+from oracle import stepper
+from workloads import scenes
+
+pytestmark = pytest.mark.gpu
+
+MM = scenes.MM
+
+
+@pytest.mark.parametrize("friction", [0.0, 0.5])
+def test_empty_indenter_list_keeps_rest_state(friction):
+    ep = scenes.config1()
+    gp = gpu_pad(context(), ep.pad, "mixed", friction=friction)
+    for _ in range(3):
+        st = gp.step([])
+        assert st.status == 0 and st.newton_iters >= 1
+    assert np.array_equal(gp.read("positions"), ep.pad.X)
+    assert np.abs(gp.read("reaction")).max() == 0.0
+    # and the pad steps normally afterwards (the previous pose count differs:
+    # the friction lag takes the current pose)
+    st = gp.step([ep.pose(1)])
+    assert st.status == 0
+    gp.close()
+
+
+def _five_indenters(pad):
+    spots = [(3.5, 3.5), (14.5, 3.5), (3.5, 10.5), (14.5, 10.5), (9.0, 7.0)]
+    shapes = [scenes.SPHERE, scenes.CYLINDER, scenes.SPHERE, scenes.TORUS, scenes.BOX]
+    radii = [2.0, None, 2.5, None, None]
+    out = []
+    for (x, y), sh, r in zip(spots, shapes, radii):
+        out.append(scenes.place_indenter(pad, sh, (x * MM, y * MM), 1e-4,
+                                         sphere_radius=None if r is None else r * MM))
+    return out
+
+
+@pytest.mark.parametrize("prec,newton_tol,cg_rel_tol,tol", [("fp64", 1e-9, 1e-9, 1e-6), ("mixed", 1e-6, 1e-4, 1e-4)])
+def test_five_indenters_match_oracle(prec, newton_tol, cg_rel_tol, tol):
+    ep = scenes.config1()
+    starts = _five_indenters(ep.pad)
+    assert len(starts) == tc._abi.MAX_INDENTERS
+    op = oracle_pad(ep.pad)
+    prm = stepper.StepParams(newton_tol=1e-10)
+    gp = gpu_pad(context(), ep.pad, prec, newton_tol=newton_tol, cg_rel_tol=cg_rel_tol)
+    top = op.is_top.astype(bool)
+    worst = np.zeros(3)
+    for s in range(1, 5):
+        inds = [i.at_depth(0.1 * MM * s) for i in starts]
+        res = stepper.step(op, inds, prm)
+        stepper.commit(op, res)
+        ref = outputs(op, op.x, inds, prm)
+        st = gp.step(inds)
+        e = np.array(errors(gp, ref, ep.pad.X, top))
+        R, Rref = gp.read("reaction"), ref["cf"]["reaction"]
+        log(f"{prec} step {s}: {st} oracle newton {res.newton_iters} err {e} reaction {R} ref {Rref}")
+        assert np.abs(R - Rref).max() <= 1e-3 * np.abs(Rref).max()
+        worst = np.maximum(worst, e)
+    assert (worst < tol).all(), worst
+    assert np.abs(gp.read("reaction").ravel()[2]) > 0
+    gp.close()
+
+
+def test_pad_without_contact_vertices():
+    """Every contact-face vertex fixed: no candidates, nothing moves; in a
+    batch with a normal pad the other pad's result is the same as alone."""
+    ep = scenes.config1()
+    X = ep.pad.X
+    fixed = np.where((X[:, 2] == 0) | (X[:, 2] == X[:, 2].max()), 7, 0).astype(np.uint8)
+    ctx = context()
+    held = gpu_pad(ctx, ep.pad, "mixed", fixed=fixed)
+    assert held.info["n_candidates"] == 0
+    st = held.step([ep.pose(3)])
+    assert st.status == 0
+    assert np.array_equal(held.read("positions"), X)
+    a = gpu_pad(ctx, ep.pad, "mixed")
+    b = gpu_pad(ctx, ep.pad, "mixed")
+    for s in (1, 2):
+        a.step([ep.pose(s)])
+        tc.step_batch(ctx, [held, b], [[ep.pose(s)], [ep.pose(s)]])
+    assert np.array_equal(a.read("positions"), b.read("positions"))
+    assert np.array_equal(held.read("positions"), X)
+    for g in (held, a, b):
+        g.close()
+
+
+def test_server_friction_pads_equal_synchronous():
+    """Served steps keep each pad's previous pose like synchronous steps:
+    press-slide episodes with friction, interleaved on a server, end bitwise
+    equal to the same episodes stepped one call at a time."""
+    pad, params, poses = scenes.press_slide_episode()
+    shifts = [0.0, 1.5 * MM, -1.5 * MM]
+    eps = [[scenes.Indenter(p.shape, p.prm, p.R, p.c + np.array([0, d, 0])) for p in poses] for d in shifts]
+    ctx = tc.Context(0)
+    alone = []
+    for ep in eps:
+        g = gpu_pad(ctx, pad, "mixed", friction=0.5)
+        for ind in ep:
+            g.step([ind])
+        alone.append(g.read("positions"))
+        g.close()
+    pads = [gpu_pad(ctx, pad, "mixed", friction=0.5) for _ in eps]
+    srv = tc.Server(ctx, 2)
+    results = []
+    for s in range(len(poses)):
+        for k, ep in enumerate(eps):
+            srv.submit(pads[k], [ep[s]], tag=100 * k + s)
+        time.sleep(0.001)
+        results += srv.poll()
+    t0 = time.perf_counter()
+    while len(results) < len(eps) * len(poses):
+        results += srv.poll(wait_us=2000)
+        assert time.perf_counter() - t0 < 60, "server did not finish"
+    srv.close()
+    assert all(r["status"] == 0 for r in results)
+    for k, g in enumerate(pads):
+        assert np.array_equal(g.read("positions"), alone[k]), k
+        g.close()
+    ctx.close()
