@@ -162,7 +162,7 @@ def run_steps(args):
     pads = make_pads(tc, ctx, envs, args)
     log(f"pads created in {time.perf_counter() - t0:.1f} s; HBM used {ctx.memory()[0] / 2**30:.2f} GiB")
     ctx.set_launch(cg_block=args.cg_block, elem_block=args.elem_block, spmv_block=args.spmv_block,
-                   use_graphs=args.graphs)
+                   cg_per_replay=args.cg_per_replay, use_graphs=args.graphs)
     ctx.set_cg_variant(args.cg_variant)
     if args.autotune:
         chosen = ctx.autotune(pads, [[e.pose(1)] for e in envs])
@@ -374,6 +374,8 @@ def main():
                     help="run 4 device copies of this size first (counter calibration)")
     ap.add_argument("--graphs", type=int, default=0)
     ap.add_argument("--cg-variant", type=int, default=0, help="0 classic PCG, 1 pipelined PCG")
+    ap.add_argument("--cg-per-replay", type=int, default=0,
+                    help="CG iterations launched between host checks (even; 0 = library default 16)")
     ap.add_argument("--cg-block", type=int, default=0)
     ap.add_argument("--elem-block", type=int, default=0)
     ap.add_argument("--spmv-block", type=int, default=0)
@@ -390,7 +392,8 @@ def main():
     ap.add_argument("--hess-proj", type=int, default=12)
     ap.add_argument("--ls-expand", type=int, default=4,
                     help="doublings of an accepted full Newton step while the energy keeps falling")
-    ap.add_argument("--init-guess", type=int, default=None)
+    ap.add_argument("--init-guess", type=int, default=1,
+                    help="Newton start: 0 = x_t, 1 = x_t + dt v_t (then made feasible)")
     # serving
     ap.add_argument("--rate", type=float, default=2000.0, help="request arrivals per second")
     ap.add_argument("--duration", type=float, default=20.0, help="seconds of arrivals")
