@@ -288,6 +288,7 @@ def run_serve(args):
                    "completed": len(ok), "failed": len(results) - len(ok), "failed_by_status": failed,
                    "max_slots": args.max_slots,
                    "hbm_budget_gib": args.hbm_budget_gib, "resident_gib": round(resident / 2**30, 3),
+                   "evictions": int(st.get("evictions", 0)), "hbm_used_gib": round(ctx.memory()[0] / 2**30, 3),
                    "max_running_seen": st["max_running_seen"], "batched_iterations": st["ticks"],
                    "submit_span_s": round(submit_end, 2), "wall_s": round(total, 2),
                    "saturated": bool(saturated)},
@@ -386,10 +387,10 @@ def main():
     # full Newton step, accepted full steps doubled while the energy keeps
     # falling; the GPU tests check with the oracle that the final states meet
     # the Newton tolerance
-    ap.add_argument("--cg-rel-tol", type=float, default=0.1)
-    ap.add_argument("--cg-eta-max", type=float, default=0.1)
+    ap.add_argument("--cg-rel-tol", type=float, default=0.2)
+    ap.add_argument("--cg-eta-max", type=float, default=0.2)
     ap.add_argument("--cg-forcing", type=int, default=2)
-    ap.add_argument("--hess-proj", type=int, default=12)
+    ap.add_argument("--hess-proj", type=int, default=4)
     ap.add_argument("--ls-expand", type=int, default=4,
                     help="doublings of an accepted full Newton step while the energy keeps falling")
     ap.add_argument("--init-guess", type=int, default=1,

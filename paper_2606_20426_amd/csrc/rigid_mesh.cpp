@@ -78,6 +78,7 @@ size_t a256(size_t b) { return (b + 255) & ~size_t(255); }
 }  // namespace
 
 tc_status check_meshes(const tc_context* ctx, int n_ind, const tc_indenter* ind) {
+  std::lock_guard<std::mutex> lk(ctx->mesh_mu);
   for (int k = 0; k < n_ind; ++k)
     if (ind[k].shape == TC_MESH) {
       const int id = ind[k].reserved;
@@ -89,6 +90,7 @@ tc_status check_meshes(const tc_context* ctx, int n_ind, const tc_indenter* ind)
 }
 
 void free_meshes(tc_context* ctx) {
+  std::lock_guard<std::mutex> lk(ctx->mesh_mu);
   for (auto& m : ctx->mesh_slots)
     if (m.live) {
       ctx->dev_free(m.mem, m.bytes);
@@ -233,17 +235,26 @@ tc_status tc_rigid_mesh_create(tc_context* ctx, int32_t n_verts, const double* v
     const std::vector<double>& vnf = tb.vnf;
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
     int slot = -1;
-    for (int k = 0; k < (int)ctx->mesh_slots.size(); ++k)
-      if (!ctx->mesh_slots[k].live) { slot = k; break; }
+    {
+      std::lock_guard<std::mutex> ml(ctx->mesh_mu);
+      for (int k = 0; k < (int)ctx->mesh_slots.size(); ++k)
+        if (!ctx->mesh_slots[k].live && !ctx->mesh_slots[k].mem) { slot = k; break; }
+      // reserve the slot while the tables upload (mem set, not yet live)
+      if (slot >= 0) ctx->mesh_slots[slot].mem = reinterpret_cast<void*>(1);
+    }
     if (slot < 0) return set_error(TC_E_NO_MEMORY, "all TC_MAX_MESHES mesh slots are in use");
-    TC_HIP(hipSetDevice(ctx->device));
+    auto unreserve = [&] {
+      std::lock_guard<std::mutex> ml(ctx->mesh_mu);
+      ctx->mesh_slots[slot] = tc_context::MeshSlot{};
+    };
+    if (hipSetDevice(ctx->device) != hipSuccess) { unreserve(); return set_error(TC_E_HIP, "hipSetDevice"); }
     const size_t b_nodes = a256(sizeof(BvhNode) * tree.nodes.size()), b_tv = a256(8 * tv.size()),
                  b_tn = a256(8 * tn.size()), b_tid = a256(4 * tid_l.size()), b_en = a256(8 * enf.size()),
                  b_vn = a256(8 * vnf.size());
     const size_t total = b_nodes + b_tv + b_tn + b_tid + b_en + b_vn;
     tc_status st;
     char* mem = static_cast<char*>(ctx->dev_alloc(total, &st));
-    if (!mem) return st;
+    if (!mem) { unreserve(); return st; }
     DevMesh dm{};
     dm.n_tri = n_tris;
     dm.n_node = (int)tree.nodes.size();
@@ -263,9 +274,13 @@ tc_status tc_rigid_mesh_create(tc_context* ctx, int32_t n_verts, const double* v
     if (e == hipSuccess) e = hipMemcpy(ctx->d_meshes + slot, &dm, sizeof(DevMesh), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
       ctx->dev_free(mem, total);
+      unreserve();
       return hip_fail(e, "mesh upload");
     }
-    ctx->mesh_slots[slot] = tc_context::MeshSlot{true, mem, total};
+    {
+      std::lock_guard<std::mutex> ml(ctx->mesh_mu);
+      ctx->mesh_slots[slot] = tc_context::MeshSlot{true, mem, total};
+    }
     *id = slot;
     return TC_OK;
   } catch (const std::bad_alloc&) {
@@ -276,17 +291,30 @@ tc_status tc_rigid_mesh_create(tc_context* ctx, int32_t n_verts, const double* v
 tc_status tc_rigid_mesh_destroy(tc_context* ctx, int32_t id) {
   if (!ctx) return set_error(TC_E_INVALID_ARG, "ctx is null");
   std::lock_guard<std::recursive_mutex> lk(ctx->mu);
-  if (id < 0 || id >= (int)ctx->mesh_slots.size() || !ctx->mesh_slots[id].live)
-    return set_error(TC_E_INVALID_ARG, "unknown mesh id");
+  {
+    std::lock_guard<std::mutex> ml(ctx->mesh_mu);
+    if (id < 0 || id >= (int)ctx->mesh_slots.size() || !ctx->mesh_slots[id].live)
+      return set_error(TC_E_INVALID_ARG, "unknown mesh id");
+  }
   for (const tc_pad* p : ctx->pads)
     if (p->busy.load()) return set_error(TC_E_BUSY, "a pad has a request on a server");
   TC_HIP(hipSetDevice(ctx->device));
   TC_HIP(hipStreamSynchronize(ctx->stream));
+  tc_context::MeshSlot m;
+  {
+    // not live from here on: new requests naming it are rejected
+    std::lock_guard<std::mutex> ml(ctx->mesh_mu);
+    m = ctx->mesh_slots[id];
+    ctx->mesh_slots[id].live = false;
+  }
   const DevMesh zero{};
-  TC_HIP(hipMemcpy(ctx->d_meshes + id, &zero, sizeof(DevMesh), hipMemcpyHostToDevice));
-  auto& m = ctx->mesh_slots[id];
+  const hipError_t e = hipMemcpy(ctx->d_meshes + id, &zero, sizeof(DevMesh), hipMemcpyHostToDevice);
   ctx->dev_free(m.mem, m.bytes);
-  m = tc_context::MeshSlot{};
+  {
+    std::lock_guard<std::mutex> ml(ctx->mesh_mu);
+    ctx->mesh_slots[id] = tc_context::MeshSlot{};
+  }
+  if (e != hipSuccess) return hip_fail(e, "mesh table update");
   return TC_OK;
 }
 

@@ -104,6 +104,9 @@ struct tc_context {
   tc::DevMesh* d_meshes = nullptr;
   struct MeshSlot { bool live = false; void* mem = nullptr; size_t bytes = 0; };
   std::vector<MeshSlot> mesh_slots;
+  // guards mesh_slots' live flags: request submission checks them without
+  // waiting for the device mutex (held by the server for a whole tick)
+  mutable std::mutex mesh_mu;
 
   void* dev_alloc(size_t bytes, tc_status* st);
   void dev_free(void* p, size_t bytes);

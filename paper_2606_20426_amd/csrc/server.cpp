@@ -232,10 +232,7 @@ tc_status tc_server_submit(tc_server* srv, tc_pad* pad, int32_t tag, int32_t n_i
   std::string err;
   tc_status s = validate_indenters(n_ind, ind, err);
   if (s) return set_error(s, err);
-  {
-    std::lock_guard<std::recursive_mutex> dl(srv->ctx->mu);
-    if ((s = check_meshes(srv->ctx, n_ind, ind))) return s;
-  }
+  if ((s = check_meshes(srv->ctx, n_ind, ind))) return s;
   std::lock_guard<std::mutex> lk(srv->m);
   if (srv->stop) return set_error(TC_E_BUSY, "server is stopping");
   tc_server::Req r;
