@@ -172,3 +172,55 @@ def test_batch60_bench_configuration(batch60_run, step, ks):
         check_state(out, oracle_pad(e.pad), x_prev, v_prev, [e.pose(step)], prm,
                     f"batch pad {k} ({e.pad.name}, {e.pad.tets.shape[0]} tets, indenter "
                     f"{e.indenter.shape}) step {step}")
+
+
+def _hertz_run(ep, steps=(12, 18, 24)):
+    m = ep.pad.material
+    mu = m.E / (2 * (1 + m.nu))
+    lam = m.E * m.nu / ((1 + m.nu) * (1 - 2 * m.nu)) - mu
+    E_eff = mu * (3 * lam + 2 * mu) / (lam + mu)
+    nu_eff = lam / (2 * (lam + mu))
+    E_star = E_eff / (1 - nu_eff ** 2)
+    R = ep.indenter.prm[0]
+    ctx = tc.Context(0)
+    pad = tc.Pad(ctx, ep.pad.X, ep.pad.tets, dict(E=m.E, nu=m.nu, density=m.density),
+                 tc.make_params(precision="mixed", dt=ep.params.dt, dhat=ep.params.dhat,
+                                kappa=ep.params.kappa, newton_tol=ep.params.newton_tol))
+    z_top = ep.pad.X[:, 2].max()
+    cand = pad.read("candidates")
+    out = []
+    for s in range(1, max(steps) + 1):
+        pose = ep.pose(s)
+        assert pad.step([pose]).status == 0
+        if s in steps:
+            x = pad.read("positions")[cand]
+            gap = np.linalg.norm(x - pose.c[None], axis=1).min() - R
+            delta = (z_top - (pose.c[2] - R)) - gap
+            F = pad.read("reaction").ravel()[2]
+            F_h = 4.0 / 3.0 * E_star * np.sqrt(R) * delta ** 1.5
+            log(f"{ep.pad.tets.shape[0]} tets step {s}: delta {delta * 1e3:.4f} mm (gap {gap * 1e6:.2f} um), "
+                f"contact radius {np.sqrt(R * delta) * 1e3:.3f} mm, F {F:.5f} N, Hertz {F_h:.5f} N, ratio {F / F_h:.3f}")
+            out.append((delta, F, F / F_h))
+    pad.close()
+    ctx.close()
+    return out
+
+
+def test_large_pad_hertz_sanity():
+    """Loose physical check (not a parity pin): a 3 mm sphere pressed into the
+    5 mm thick pad against Hertz, F = (4/3) E* sqrt(R) delta^1.5, while the
+    contact radius stays small against the thickness.  The rest-stable shift
+    makes the small-strain Lame pair (mu, lambda - mu), hence E*; delta is the
+    sphere's overlap with the undeformed surface less the barrier gap left at
+    the contact.  Linear tets at nu_eff = 0.44 are too stiff (volumetric
+    locking, few elements across the contact), so the check is the power law
+    on the 1.2 M-tet pad and a force excess that shrinks under refinement."""
+    coarse = _hertz_run(scenes.config5(target=0.15e6))
+    fine = _hertz_run(scenes.config5())
+    (d1, F1, _), (d2, F2, _) = fine[1], fine[2]
+    exponent = np.log(F2 / F1) / np.log(d2 / d1)
+    log(f"exponent (delta {d1 * 1e3:.3f} -> {d2 * 1e3:.3f} mm): {exponent:.3f}")
+    assert abs(exponent - 1.5) < 0.1
+    for (_, _, rc), (_, _, rf) in zip(coarse, fine):
+        assert 1.0 <= rf < rc, (rf, rc)
+    assert fine[-1][2] < 1.4
