@@ -127,3 +127,36 @@ def test_server_friction_pads_equal_synchronous():
         assert np.array_equal(g.read("positions"), alone[k]), k
         g.close()
     ctx.close()
+
+
+def test_autotune_keeps_state_and_stepping_valid():
+    """The launch-shape autotuner picks shapes from its candidate sets, leaves
+    every pad's committed state (and friction pose) untouched, and stepping
+    afterwards reaches the same minimiser as the default launch shape."""
+    eps = scenes.config3(n_envs=4)
+    ctxs = [tc.Context(0), tc.Context(0)]
+    pads = [[gpu_pad(c, e.pad, "mixed", newton_tol=1e-6, cg_rel_tol=1e-4) for e in eps] for c in ctxs]
+    for s in (1, 2):
+        for c, ps in zip(ctxs, pads):
+            tc.step_batch(c, ps, [[e.pose(s)] for e in eps])
+    before = [p.read("positions") for p in pads[1]]
+    chosen = ctxs[1].autotune(pads[1], [[e.pose(3)] for e in eps])
+    log(f"autotune chose {chosen}")
+    assert chosen[0] in (128, 256, 512, 1024) and chosen[1] in (64, 128, 256)
+    assert chosen[2] % 64 == 0 and 64 <= chosen[2] <= 1024 and chosen[3] >= 2 and chosen[3] % 2 == 0
+    for p, x in zip(pads[1], before):
+        assert np.array_equal(p.read("positions"), x)
+    for s in (3, 4):
+        for c, ps in zip(ctxs, pads):
+            st = tc.step_batch(c, ps, [[e.pose(s)] for e in eps])
+            assert all(x.status == 0 for x in st)
+    for e, pa, pb in zip(eps, *pads):
+        xa, xb = pa.read("positions"), pb.read("positions")
+        disp = np.abs(xa - e.pad.X).max()
+        tol = max(1e-3 * disp, 2e-6 * np.linalg.norm(e.pad.X.max(0) - e.pad.X.min(0)))
+        assert np.abs(xa - xb).max() <= tol
+    for ps in pads:
+        for p in ps:
+            p.close()
+    for c in ctxs:
+        c.close()
