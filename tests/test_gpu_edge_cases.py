@@ -160,3 +160,40 @@ def test_autotune_keeps_state_and_stepping_valid():
             p.close()
     for c in ctxs:
         c.close()
+
+
+def test_runtime_switches_relayout_scratch():
+    """Turning friction on or off for a live pad, and switching the
+    context's CG variant, change the step scratch layout: the next steps run
+    on the new layout and reach the same minimiser as a pad configured that
+    way from the start."""
+    ep = scenes.config1()
+    ref_ctx, ctx = tc.Context(0), tc.Context(0)
+    kw = dict(newton_tol=1e-6, cg_rel_tol=1e-4)
+    ref = gpu_pad(ref_ctx, ep.pad, "mixed", friction=0.5, **kw)
+    pad = gpu_pad(ctx, ep.pad, "mixed", **kw)
+    other = gpu_pad(ctx, ep.pad, "mixed", friction=0.5, **kw)
+    ref.step([ep.pose(1)])
+    pad.step([ep.pose(1)])
+    other.step([ep.pose(1)])
+    pad.set_params(tc.make_params(precision="mixed", friction=0.5, **kw))   # friction on: new layout
+    ctx.set_cg_variant(1)                                                    # every pad re-laid out
+    for s in (2, 3):
+        ref.step([ep.pose(s)])
+        st = tc.step_batch(ctx, [pad, other], [[ep.pose(s)], [ep.pose(s)]])
+        assert all(x.status == 0 for x in st)
+    ctx.set_cg_variant(0)
+    pad.set_params(tc.make_params(precision="mixed", friction=0.5, **kw))   # unchanged layout
+    for s in (4, 5):
+        ref.step([ep.pose(s)])
+        tc.step_batch(ctx, [pad, other], [[ep.pose(s)], [ep.pose(s)]])
+    xr = ref.read("positions")
+    tol = 2e-6 * np.linalg.norm(ep.pad.X.max(0) - ep.pad.X.min(0))
+    for g in (pad, other):
+        assert np.abs(g.read("positions") - xr).max() <= max(tol, 1e-3 * np.abs(xr - ep.pad.X).max())
+    pad.set_params(tc.make_params(precision="mixed", **kw))                  # friction off again
+    assert pad.step([ep.pose(6)]).status == 0
+    for g in (ref, pad, other):
+        g.close()
+    ref_ctx.close()
+    ctx.close()
