@@ -10,6 +10,8 @@ contact forces and commit, all in one fused set of launches.
     python bench.py --sequential --precision fp64                 # the same pads one at a time
     python bench.py --workload serve256 [--rate 2000] [--duration 20]
     python bench.py --workload large1.2m --ablation               # FP32/FP64 CG ablation + extraction
+    python bench.py --workload batch60-friction                   # the 60 pads with friction (also
+                                                                  # batch60-slide, -layers, -mesh)
 
 Each mode prints one JSON line.
 """
@@ -41,6 +43,14 @@ def build_workload(name):
     from workloads import scenes
     if name == "batch60":
         return scenes.config3(), "60 mixed pads (flat 18x14x4 / dome 19x16x3 R30 / flat 24x24x5 mm), 20k-80k tets each, random indenters, SeedSequence(3)"
+    if name.startswith("batch60-") and name[8:] in scenes.VARIANTS:
+        kind = name[8:]
+        what = {"slide": "pressed over 15 steps then slid 0.1 mm/step (texture plates 0.02) in a seeded direction, friction off",
+                "friction": "pressed over 15 steps then slid 0.1 mm/step (texture plates 0.02) in a seeded direction, friction 0.5",
+                "layers": "two layers split at half thickness, base 8x stiffer (nu 0.42, rho 1200)",
+                "mesh": "bounded indenters as triangle meshes (icosphere 1,280 tris, 32-gon cylinder, "
+                        "12-tri cube, 768-tri torus), texture plates analytic"}[kind]
+        return scenes.config3_variant(kind), f"the batch60 pads and poses, {what}, SeedSequence(3) and (5)"
     if name == "single1944":
         return [scenes.config1()], "single 18x14x4 mm pad, 1,944 tets, sphere r=5 mm"
     if name == "large1.2m":
@@ -122,11 +132,28 @@ def make_pads(tc, ctx, envs, args, precision=None):
     for e in envs:
         m = e.pad.material
         kw = dict(precision=precision or args.precision, dt=e.params.dt, dhat=e.params.dhat,
-                  kappa=e.params.kappa, newton_tol=e.params.newton_tol)
+                  kappa=e.params.kappa, newton_tol=e.params.newton_tol, friction=e.friction)
         kw.update(extra)
-        pads.append(tc.Pad(ctx, e.pad.X, e.pad.tets, dict(E=m.E, nu=m.nu, density=m.density),
-                           tc.make_params(**kw)))
+        mats, idx = [dict(E=m.E, nu=m.nu, density=m.density)], None
+        if e.layers is not None:
+            idx = e.layers[0]
+            mats = [dict(E=q.E, nu=q.nu, density=q.density) for q in e.layers[1]]
+        if e.indenter.mesh is not None and id(e.indenter.mesh) not in MESH_IDS:
+            MESH_IDS[id(e.indenter.mesh)] = ctx.add_mesh(*e.indenter.mesh)
+        pads.append(tc.Pad(ctx, e.pad.X, e.pad.tets, mats, tc.make_params(**kw), tet_material=idx))
     return pads
+
+
+MESH_IDS = {}    # id(surface) -> registry slot of the one context a run uses
+
+
+def poses(e, s):
+    """End-of-step indenter poses of episode e at step s, rigid meshes by
+    their registry slot."""
+    ind = e.pose(s)
+    if ind.mesh is None:
+        return [ind]
+    return [dict(shape=ind.shape, prm=ind.prm, R=ind.R, c=ind.c, mesh_id=MESH_IDS[id(ind.mesh)])]
 
 
 def roofline(ctx, args):
@@ -165,13 +192,13 @@ def run_steps(args):
                    cg_per_replay=args.cg_per_replay, use_graphs=args.graphs)
     ctx.set_cg_variant(args.cg_variant)
     if args.autotune:
-        chosen = ctx.autotune(pads, [[e.pose(1)] for e in envs])
+        chosen = ctx.autotune(pads, [poses(e, 1) for e in envs])
         log(f"autotune: vertex block {chosen[0]}, element block {chosen[1]}, SpMV block {chosen[2]}")
 
     def step(s):
         if args.sequential:
-            return [p.step([e.pose(s)]) for p, e in zip(pads, envs)]
-        return tc.step_batch(ctx, pads, [[e.pose(s)] for e in envs])
+            return [p.step(poses(e, s)) for p, e in zip(pads, envs)]
+        return tc.step_batch(ctx, pads, [poses(e, s) for e in envs])
 
     for s in range(1, args.warmup + 1):
         st = step(s)
@@ -211,7 +238,7 @@ def run_steps(args):
                    "cg_variant": "pipelined" if args.cg_variant else "classic"},
         "roofline": roof,
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not args.workload.startswith("batch60-"):
         log("timing the oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(envs)
     return out
@@ -253,7 +280,7 @@ def run_serve(args):
         if delay > 0:
             time.sleep(delay)
         step_of[k] += 1
-        srv.submit(pads[k], [envs[k].pose(step_of[k])], tag=int(k))
+        srv.submit(pads[k], poses(envs[k], step_of[k]), tag=int(k))
         if time.perf_counter() - last_log > 5.0:
             last_log = time.perf_counter()
             log(f"t={last_log - start:.1f} s: submitted {i + 1}, completed {len(results)}")

@@ -139,7 +139,7 @@ def test_rigid_mesh_validation(tc):
     from workloads import meshes
     V = tc.validate
     for good in (meshes.box_surface(1e-3, 2e-3, 3e-3), meshes.icosphere(2e-3, 2),
-                 meshes.torus_surface(4e-3, 1e-3, 16, 8)):
+                 meshes.torus_surface(4e-3, 1e-3, 16, 8), meshes.cylinder_surface(2.5e-3, 5e-3, 32)):
         assert _status(lambda: V(rigid_mesh=good)) == 0
     Vb, Fb = meshes.box_surface(1e-3, 1e-3, 1e-3)
     assert _status(lambda: V(rigid_mesh=(Vb, Fb[:, ::-1]))) == -1        # inward normals
@@ -212,3 +212,36 @@ def test_refine_mesh_errors(tc):
     bad = p.tets.copy(); bad[0, [2, 3]] = bad[0, [3, 2]]
     with pytest.raises(tc.TcError):
         tc.refine_mesh(p.X, bad)
+
+
+def test_batch_variants_keep_the_batch():
+    """The NEXT-row variants of the 60-pad batch keep its pads, materials
+    and start poses and change only their own feature; the mesh variant's
+    surfaces lie inside their analytic shapes (the start stays feasible)."""
+    from oracle import contact
+    from workloads import scenes
+    base = scenes.config3(8)
+    for kind in scenes.VARIANTS:
+        envs = scenes.config3_variant(kind, 8)
+        for b, e in zip(base, envs):
+            assert e.pad is b.pad or np.array_equal(e.pad.X, b.pad.X)
+            assert e.depth == b.depth and np.array_equal(e.indenter.c, b.indenter.c)
+            if kind in ("slide", "friction"):
+                assert e.friction == (0.5 if kind == "friction" else 0.0) and e.n_steps == 15
+                step = np.linalg.norm(e.pose(17).c - e.pose(16).c)
+                assert np.isclose(step, 0.02e-3 if b.indenter.shape == scenes.TEXTURE else 0.1e-3)
+                assert np.array_equal(e.pose(15).c, b.indenter.at_depth(b.depth).c)
+            elif kind == "layers":
+                idx, mats = e.layers
+                assert set(np.unique(idx)) == {0, 1} and mats[0] == b.pad.material
+                assert mats[1].E == 8 * mats[0].E
+            else:
+                if b.indenter.shape == scenes.TEXTURE:
+                    assert e.indenter.shape == scenes.TEXTURE and e.indenter.mesh is None
+                    continue
+                assert e.indenter.shape == scenes.MESH
+                V, F = e.indenter.mesh
+                assert _status(lambda: __import__("paper_2606_20426_amd").validate(rigid_mesh=(V, F))) == 0
+                # every mesh vertex on or inside the analytic surface
+                phi, _, _ = contact.sdf_local(b.indenter.shape, b.indenter.prm, V)
+                assert phi.max() <= 1e-12 * np.abs(V).max()

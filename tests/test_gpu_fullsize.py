@@ -34,12 +34,12 @@ FORCE_TOL = 1e-8
 KKT_FACTOR = 3.0        # oracle direction <= KKT_FACTOR * newton_tol * L
 
 
-def oracle_direction(op, x_prev, v_prev, x, inds, prm):
+def oracle_direction(op, x_prev, v_prev, x, inds, prm, fric=None):
     """The oracle's Newton direction at x for the step that started at
     (x_prev, v_prev): PSD-projected Hessian, Jacobi-preconditioned CG."""
     xhat = x_prev + prm.dt * v_prev
-    g = stepper.gradient(op, x, xhat, inds, prm).ravel()
-    H = stepper.hessian(op, x, inds, prm)
+    g = stepper.gradient(op, x, xhat, inds, prm, fric=fric).ravel()
+    H = stepper.hessian(op, x, inds, prm, fric=fric)
     free = op.free.ravel()
     Hff = H[free][:, free]
     pf, info = spla.cg(Hff, -g[free], rtol=1e-7, maxiter=200000, M=sp.diags(1.0 / Hff.diagonal()))
@@ -55,10 +55,15 @@ def snapshot(gp):
     return {f: gp.read(f) for f in FIELDS}
 
 
-def check_state(out, op, x_prev, v_prev, inds, prm, label):
-    """out: the GPU's outputs after the step (snapshot)."""
+def check_state(out, op, x_prev, v_prev, inds, prm, label, inds_prev=None):
+    """out: the GPU's outputs after the step (snapshot); inds_prev: the
+    indenter poses of the step before (the friction lag)."""
     x = out["positions"]
-    p_inf = oracle_direction(op, x_prev, v_prev, x, inds, prm)
+    fric = None
+    if prm.mu_f > 0:
+        op.x = x_prev.copy()
+        fric = stepper.friction_lag(op, inds, prm, inds_prev)
+    p_inf = oracle_direction(op, x_prev, v_prev, x, inds, prm, fric)
     tol = prm.newton_tol * op.L_diag
     # extraction from the GPU's positions
     sig_ref = extract.cauchy_per_tet(op, x)
@@ -74,7 +79,7 @@ def check_state(out, op, x_prev, v_prev, inds, prm, label):
     tt = out["tangential"].astype(np.float64)
     e_t = np.abs(t - t_ref).max() / max(np.abs(t_ref).max(), floor)
     e_pn = np.abs(pn - pn_ref).max() / max(np.abs(pn_ref).max(), floor)
-    cf_ref = extract.contact_forces(op, x, inds, prm)
+    cf_ref = extract.contact_forces(op, x, inds, prm, fric=fric)
     f = out["contact_force"]
     fscale = max(np.abs(cf_ref["f"]).max(), 1e-300)
     e_f = np.abs(f - cf_ref["f"]).max() / fscale
@@ -172,6 +177,94 @@ def test_batch60_bench_configuration(batch60_run, step, ks):
         check_state(out, oracle_pad(e.pad), x_prev, v_prev, [e.pose(step)], prm,
                     f"batch pad {k} ({e.pad.name}, {e.pad.tets.shape[0]} tets, indenter "
                     f"{e.indenter.shape}) step {step}")
+
+
+# pads checked per variant at the last step: every indenter shape the
+# variant changes (pads 0-5 carry cube, sphere, sphere, cylinder, torus,
+# texture) on all three pad shapes
+VARIANT_CHECKS = {"friction": (0, 3, 5), "layers": (1, 4, 5)}
+
+
+@pytest.fixture(scope="module", params=sorted(VARIANT_CHECKS))
+def variant_run(request):
+    """One variant of the 60-pad batch (friction, two layers, mesh
+    indenters) in the benchmark's settings, steps 1-33, as the benchmark
+    sets the pads up."""
+    kind = request.param
+    envs = scenes.config3_variant(kind)
+    ctx = tc.Context(0)
+    kw = dict(precision="mixed", cg_rel_tol=0.2, cg_eta_max=0.2, cg_forcing=2, hess_proj=4, ls_expand=4,
+              init_guess=1)
+    ids, pads = {}, []
+    try:
+        return _run_variant(kind, envs, ctx, kw, ids, pads)
+    finally:
+        for p in pads:
+            p.close()
+        for i in ids.values():
+            ctx.remove_mesh(i)
+        ctx.close()
+
+
+def _run_variant(kind, envs, ctx, kw, ids, pads):
+    for e in envs:
+        m = e.pad.material
+        mats, idx = [dict(E=m.E, nu=m.nu, density=m.density)], None
+        if e.layers is not None:
+            idx = e.layers[0]
+            mats = [dict(E=q.E, nu=q.nu, density=q.density) for q in e.layers[1]]
+        if e.indenter.mesh is not None and id(e.indenter.mesh) not in ids:
+            ids[id(e.indenter.mesh)] = ctx.add_mesh(*e.indenter.mesh)
+        pads.append(tc.Pad(ctx, e.pad.X, e.pad.tets, mats,
+                           tc.make_params(dt=e.params.dt, dhat=e.params.dhat, kappa=e.params.kappa,
+                                          newton_tol=e.params.newton_tol, friction=e.friction, **kw),
+                           tet_material=idx))
+
+    def poses(e, s):
+        ind = e.pose(s)
+        if ind.mesh is None:
+            return [ind]
+        return [dict(shape=tc.MESH, prm=ind.prm, R=ind.R, c=ind.c, mesh_id=ids[id(ind.mesh)])]
+
+    last, saved, newton = 33, {}, []
+    t0 = time.perf_counter()
+    for s in range(1, last + 1):
+        prev = {k: (pads[k].read("positions"), pads[k].read("velocities")) for k in VARIANT_CHECKS[kind]} \
+            if s == last else {}
+        st = tc.step_batch(ctx, pads, [poses(e, s) for e in envs], raise_on_error=False)
+        assert all(x.status == 0 for x in st), (s, [(k, x) for k, x in enumerate(st) if x.status])
+        newton.append(max(x.newton_iters for x in st))
+        for k in prev:
+            saved[k] = (prev[k][0], prev[k][1], snapshot(pads[k]))
+    log(f"batch60-{kind}: {last} steps in {time.perf_counter() - t0:.1f} s, newton max per step {newton}")
+    return kind, envs, last, saved
+
+
+def test_batch60_variants(variant_run):
+    """The 60-pad batch with friction (press then slide), with two-layer
+    pads, or with triangle-mesh indenters, checked at the last step by the
+    oracle with the same physics: stationarity of the incremental potential
+    (friction lagged from the GPU's previous state and the previous poses),
+    extraction and contact forces (friction included)."""
+    kind, envs, step, saved = variant_run
+    for k, (x_prev, v_prev, out) in saved.items():
+        e = envs[k]
+        m = e.pad.material
+        if e.layers is not None:
+            idx, mats = e.layers
+            op = stepper.make_pad(e.pad.X, e.pad.tets, np.array([q.E for q in mats])[idx],
+                                  np.array([q.nu for q in mats])[idx],
+                                  np.array([q.density for q in mats])[idx], fixed=e.pad.fixed)
+        else:
+            op = stepper.make_pad(e.pad.X, e.pad.tets, m.E, m.nu, m.density, fixed=e.pad.fixed)
+        prm = stepper.StepParams(dt=e.params.dt, dhat=e.params.dhat, kappa=e.params.kappa,
+                                 newton_tol=e.params.newton_tol, mu_f=e.friction, eps_v=0.01)
+        check_state(out, op, x_prev, v_prev, [e.pose(step)], prm,
+                    f"batch60-{kind} pad {k} ({e.pad.name}, {e.pad.tets.shape[0]} tets, indenter "
+                    f"{e.indenter.shape}) step {step}", inds_prev=[e.pose(step - 1)])
+        if kind == "friction":
+            r = out["reaction"].ravel()
+            log(f"  tangential / normal reaction {np.hypot(r[0], r[1]) / max(abs(r[2]), 1e-300):.3f}")
 
 
 def _hertz_run(ep, steps=(12, 18, 24)):

@@ -175,6 +175,20 @@ def box_surface(a, b, c):
     return V, np.array(F, np.int32)
 
 
+def cylinder_surface(r, a, n):
+    """Closed cylinder about the local z axis (radius r, half length a): an
+    n-gon prism with vertices on the circle, caps fanned from their centres."""
+    th = 2 * np.pi * np.arange(n) / n
+    ring = np.stack([r * np.cos(th), r * np.sin(th)], axis=1)
+    V = np.concatenate([np.column_stack([ring, np.full(n, -a)]), np.column_stack([ring, np.full(n, a)]),
+                        [[0.0, 0.0, -a], [0.0, 0.0, a]]])
+    F = []
+    for i in range(n):
+        j = (i + 1) % n
+        F += [(i, j, n + j), (i, n + j, n + i), (2 * n, j, i), (2 * n + 1, n + i, n + j)]
+    return V, np.array(F, np.int32)
+
+
 def icosphere(r, level):
     """Sphere of radius r: icosahedron subdivided `level` times, vertices
     pushed to the sphere."""

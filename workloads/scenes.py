@@ -88,6 +88,9 @@ class Episode:
     n_steps: int             # steps to reach `depth`
     params: Params
     schedule: str = "press"  # "press": ramp then hold; "triangle": press/release
+    slide: Optional[np.ndarray] = None   # world xy travel per step once the ramp is done [m]
+    friction: float = 0.0                # friction ratio of the pad
+    layers: Optional[tuple] = None       # (per-tet material index [T], [Material, ...])
 
     def depth_at(self, step):
         """Indenter travel after `step` steps (step >= 1)."""
@@ -100,7 +103,11 @@ class Episode:
         return self.depth * frac
 
     def pose(self, step):
-        return self.indenter.at_depth(self.depth_at(step))
+        ind = self.indenter.at_depth(self.depth_at(step))
+        if self.slide is not None:
+            k = max(step - self.n_steps, 0)
+            ind.c = ind.c + np.array([self.slide[0] * k, self.slide[1] * k, 0.0])
+        return ind
 
 
 # ----------------------------------------------------------------------------
@@ -324,6 +331,65 @@ def config3(n_envs=60):
     seqs = np.random.SeedSequence(3).spawn(60)
     return [_random_env(np.random.default_rng(s), 20e3, 80e3, False, 30, "press")
             for s in seqs[:n_envs]]
+
+
+def mesh_indenter(ind):
+    """The same indenter given as a closed triangle surface (MESH), where
+    the shape is bounded: sphere -> icosphere (1,280 triangles, vertices on
+    the sphere), cylinder -> 32-gon prism, cube -> its 12 triangles, torus ->
+    32 x 12 quads with a facet strip at the bottom.  Every mesh lies inside
+    its analytic shape, so a start pose feasible for the shape stays
+    feasible.  The texture plate (unbounded) stays analytic."""
+    p = ind.prm
+    if ind.shape == SPHERE:
+        mesh = meshes.icosphere(p[0], 3)
+    elif ind.shape == CYLINDER:
+        mesh = meshes.cylinder_surface(p[0], p[1], 32)
+    elif ind.shape == BOX:
+        mesh = meshes.box_surface(p[0], p[1], p[2])
+    elif ind.shape == TORUS:
+        mesh = meshes.torus_surface(p[0], p[1], 32, 12, phase=0.5)
+    else:
+        return ind
+    return Indenter(MESH, (0.0, 0.0, 0.0, 0.0), ind.R.copy(), ind.c.copy(), mesh)
+
+
+VARIANTS = ("slide", "friction", "layers", "mesh")
+
+
+def config3_variant(kind, n_envs=60):
+    """config3's pads, materials and start poses with one feature beyond the
+    frictionless press switched on for every pad (variant draws from
+    SeedSequence(5), one per pad):
+      slide    : pressed to depth over 15 steps, then slid in a seeded
+                 direction, 0.1 mm per step (6 mm/s), the texture plate 0.02
+                 mm per step: its bumps pass under every vertex of the face,
+                 and at 0.1 mm per step each gap would change by 0.6 d_hat
+                 per step (friction off);
+      friction : the same press-slide with friction ratio 0.5 (Sec. III-B);
+      layers   : two layers split at half thickness, the drawn material on
+                 top and a base 8x stiffer (nu = 0.42, rho = 1200), the
+                 dual-layer gel of Sec. IV-C;
+      mesh     : bounded indenters given as triangle meshes (mesh_indenter)."""
+    if kind not in VARIANTS:
+        raise ValueError(kind)
+    rng = np.random.default_rng(np.random.SeedSequence(5))
+    out = []
+    for e in config3(n_envs):
+        ang = rng.uniform(0.0, 2.0 * math.pi)
+        if kind in ("slide", "friction"):
+            speed = 0.02 * MM if e.indenter.shape == TEXTURE else 0.1 * MM
+            v = speed * np.array([math.cos(ang), math.sin(ang)])
+            e = dataclasses.replace(e, n_steps=15, slide=v, friction=0.5 if kind == "friction" else 0.0)
+        elif kind == "layers":
+            m = e.pad.material
+            idx, mats = layered_materials(e.pad.X, e.pad.tets, e.pad.X[:, 2].min() + 0.5 * e.pad.dims[2], m,
+                                          Material(8.0 * m.E, 0.42, 1200.0))
+            e = dataclasses.replace(e, layers=(idx, mats))
+        else:
+            e = dataclasses.replace(e, indenter=mesh_indenter(e.indenter))
+        out.append(e)
+    return out
 
 
 def config4(n_pads=256):
