@@ -388,10 +388,14 @@ __device__ __forceinline__ int tri_closest(const double* t, const double y[3], d
 // child first, subtrees pruned by box distance), sign from the pseudonormal
 // of the closest feature (negative inside); gradient s (y - c) / d, Hessian
 // 0 on a face, s (I - t t^T - g g^T) / d on an edge of direction t,
-// s (I - g g^T) / d at a vertex.
+// s (I - g g^T) / d at a vertex.  Only triangles nearer than rmax are
+// searched: with none, phi = +inf (callers that need phi only below d_hat
+// pass d_hat, which prunes most of the tree for vertices away from the mesh;
+// a point inside the mesh deeper than rmax would read as far outside, which
+// the feasible start and the step bound rule out for every point they pass).
 __device__ void mesh_sdf(const DevMesh& M, const double y[3], double& phi, double g[3], double H[3][3],
-                         bool wantH) {
-  double best = INFINITY, cb[3] = {0, 0, 0};
+                         bool wantH, double rmax) {
+  double best = rmax * rmax, cb[3] = {0, 0, 0};
   int bt = -1, br = 0;
   int stack[BVH_STACK];
   int sp = 0;
@@ -452,13 +456,13 @@ __device__ void mesh_sdf(const DevMesh& M, const double y[3], double& phi, doubl
 
 // World frame: y = R^T (x - c), grad = R g, hess = R H R^T.
 __device__ void sdf_world(const DevIndenter& ind, const DevMesh* meshes, const double x[3], double& phi,
-                          double g[3], double H[3][3], bool wantH) {
+                          double g[3], double H[3][3], bool wantH, double rmax = INFINITY) {
   const double dx[3] = {x[0] - ind.c[0], x[1] - ind.c[1], x[2] - ind.c[2]};
   double y[3];
   for (int i = 0; i < 3; ++i) y[i] = ind.R[0 * 3 + i] * dx[0] + ind.R[1 * 3 + i] * dx[1] + ind.R[2 * 3 + i] * dx[2];
   double gl[3], Hl[3][3];
   if (ind.shape == TC_MESH)
-    mesh_sdf(meshes[ind.reserved], y, phi, gl, Hl, wantH);
+    mesh_sdf(meshes[ind.reserved], y, phi, gl, Hl, wantH, rmax);
   else
     sdf_local(ind.shape, ind.prm, y, phi, gl, Hl, wantH);
   for (int i = 0; i < 3; ++i) g[i] = ind.R[i * 3 + 0] * gl[0] + ind.R[i * 3 + 1] * gl[1] + ind.R[i * 3 + 2] * gl[2];
@@ -704,7 +708,7 @@ __global__ void k_predict(const Tile* tiles, int ntiles, const EnvDesc* envs) {
     const DevIndenter& A = P->prev[m];
     const DevIndenter& B = P->ind[m];
     double phi, n[3], loc[3];
-    sdf_world(A, E.meshes, xt, phi, n, H, false);
+    sdf_world(A, E.meshes, xt, phi, n, H, false, E.dhat);
     for (int j = 0; j < 3; ++j)
       loc[j] = A.R[0 * 3 + j] * (xt[0] - A.c[0]) + A.R[1 * 3 + j] * (xt[1] - A.c[1]) + A.R[2 * 3 + j] * (xt[2] - A.c[2]);
     double* f = E.fric + ((size_t)m * E.C + k) * FRIC_STRIDE;
@@ -988,7 +992,7 @@ __global__ void k_barrier(const Tile* tiles, int ntiles, const EnvDesc* envs) {
   double g[3] = {0, 0, 0}, H[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, Hn[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
   for (int m = 0; m < P->n_ind; ++m) {
     double phi, n[3], Hp[3][3];
-    sdf_world(P->ind[m], E.meshes, x, phi, n, Hp, true);
+    sdf_world(P->ind[m], E.meshes, x, phi, n, Hp, true, E.dhat);
     if (phi < E.dhat) {
       const double s = phi / E.dhat;
       const double b1 = bar1(s), b2 = bar2(s);
@@ -1738,23 +1742,27 @@ __global__ void k_filter(const Tile* tiles, int ntiles, const EnvDesc* envs) {
     const double pn = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
     if (pn > 0) {
       for (int m = 0; m < P->n_ind; ++m) {
+        const DevIndenter& I = P->ind[m];
+        // a mesh vertex farther than FILTER_SPAN |p| / 0.9 keeps phi >= 0.1
+        // phi(x) over the whole span: the query stops at that radius
         double phi, g[3];
-        sdf_world(P->ind[m], E.meshes, x, phi, g, H, false);
+        sdf_world(I, E.meshes, x, phi, g, H, false, FILTER_SPAN * pn / 0.9);
         double a = INFINITY;
         const double gp = g[0] * p[0] + g[1] * p[1] + g[2] * p[2];
-        const DevIndenter& I = P->ind[m];
         if (convex_shape(I.shape)) {
           if (gp < 0) a = 0.9 * phi / (-gp);
         } else if (I.shape == TC_MESH) {
           // conservative advancement: phi is 1-Lipschitz, so phi >= 0.1 phi(x)
           // holds on [a, a + (phi(x + a p) - 0.1 phi(x)) / |p|]; advance until
-          // that gap is within 0.1 % of the floor (or the span is covered)
+          // that gap is within 0.1 % of the floor (or the span is covered);
+          // the first advance is 0.9 phi(x) / |p|
           const double floor_ = 0.1 * phi;
-          a = 0.0;
-          for (int it = 0; it < 32 && a < FILTER_SPAN; ++it) {
+          a = isinf(phi) ? FILTER_SPAN : (phi > 0.0 ? 0.9 * phi / pn : 0.0);
+          for (int it = 1; it < 32 && a < FILTER_SPAN; ++it) {
             const double y[3] = {x[0] + a * p[0], x[1] + a * p[1], x[2] + a * p[2]};
             double ph, gy[3];
-            sdf_world(I, E.meshes, y, ph, gy, H, false);
+            // beyond floor + (span left) |p| the next advance covers the span
+            sdf_world(I, E.meshes, y, ph, gy, H, false, floor_ + (FILTER_SPAN - a) * pn);
             const double gap = ph - floor_;
             if (gap <= 1e-3 * floor_) break;
             a += gap / pn;
@@ -1899,7 +1907,7 @@ __global__ void k_energy(const Tile* tiles, int ntiles, const EnvDesc* envs, int
       for (int c = 0; c < 3; ++c) y[c] = E.xn[3 * vi + c] + (mode ? al * (double)d[3 * vi + c] : 0.0);
       for (int m = 0; m < P->n_ind; ++m) {
         double phi;
-        sdf_world(P->ind[m], E.meshes, y, phi, g, H, false);
+        sdf_world(P->ind[m], E.meshes, y, phi, g, H, false, E.dhat);
         if (phi < E.dhat) acc += E.kappa * E.cand_area[k] * E.dhat * bar0(phi / E.dhat);
       }
       if (E.fr_mu > 0) {
@@ -2143,7 +2151,7 @@ __global__ void k_contact(const Tile* tiles, int ntiles, const EnvDesc* envs) {
     double f[3] = {0, 0, 0};
     for (int m = 0; m < P->n_ind; ++m) {
       double phi, g[3];
-      sdf_world(P->ind[m], E.meshes, xv, phi, g, H, false);
+      sdf_world(P->ind[m], E.meshes, xv, phi, g, H, false, E.dhat);
       if (phi < E.dhat) {
         const double b1 = bar1(phi / E.dhat);
         for (int c = 0; c < 3; ++c) f[c] -= kA * b1 * g[c];

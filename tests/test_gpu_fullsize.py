@@ -182,7 +182,7 @@ def test_batch60_bench_configuration(batch60_run, step, ks):
 # pads checked per variant at the last step: every indenter shape the
 # variant changes (pads 0-5 carry cube, sphere, sphere, cylinder, torus,
 # texture) on all three pad shapes
-VARIANT_CHECKS = {"friction": (0, 3, 5), "layers": (1, 4, 5)}
+VARIANT_CHECKS = {"friction": (0, 3, 5), "layers": (1, 4, 5), "mesh": (0, 1, 3)}
 
 
 @pytest.fixture(scope="module", params=sorted(VARIANT_CHECKS))

@@ -334,12 +334,14 @@ def config3(n_envs=60):
 
 
 def mesh_indenter(ind):
-    """The same indenter given as a closed triangle surface (MESH), where
-    the shape is bounded: sphere -> icosphere (1,280 triangles, vertices on
-    the sphere), cylinder -> 32-gon prism, cube -> its 12 triangles, torus ->
-    32 x 12 quads with a facet strip at the bottom.  Every mesh lies inside
-    its analytic shape, so a start pose feasible for the shape stays
-    feasible.  The texture plate (unbounded) stays analytic."""
+    """The same indenter given as a closed triangle surface (MESH), for the
+    convex shapes: sphere -> icosphere (1,280 triangles, vertices on the
+    sphere), cylinder -> 32-gon prism, cube -> its 12 triangles.  Every mesh
+    lies inside its analytic shape, so a start pose feasible for the shape
+    stays feasible.  The torus and the texture plate stay analytic: a
+    polygonal torus has concave edges on its inner side, across whose
+    bisector planes the distance to the mesh (the nearest of two faces) has
+    a kink, and a contact vertex at rest in such a valley stalls Newton."""
     p = ind.prm
     if ind.shape == SPHERE:
         mesh = meshes.icosphere(p[0], 3)
@@ -347,8 +349,6 @@ def mesh_indenter(ind):
         mesh = meshes.cylinder_surface(p[0], p[1], 32)
     elif ind.shape == BOX:
         mesh = meshes.box_surface(p[0], p[1], p[2])
-    elif ind.shape == TORUS:
-        mesh = meshes.torus_surface(p[0], p[1], 32, 12, phase=0.5)
     else:
         return ind
     return Indenter(MESH, (0.0, 0.0, 0.0, 0.0), ind.R.copy(), ind.c.copy(), mesh)
@@ -370,7 +370,7 @@ def config3_variant(kind, n_envs=60):
       layers   : two layers split at half thickness, the drawn material on
                  top and a base 8x stiffer (nu = 0.42, rho = 1200), the
                  dual-layer gel of Sec. IV-C;
-      mesh     : bounded indenters given as triangle meshes (mesh_indenter)."""
+      mesh     : the convex indenters given as triangle meshes (mesh_indenter)."""
     if kind not in VARIANTS:
         raise ValueError(kind)
     rng = np.random.default_rng(np.random.SeedSequence(5))
