@@ -48,8 +48,8 @@ def build_workload(name):
         what = {"slide": "pressed over 15 steps then slid 0.1 mm/step (texture plates 0.02) in a seeded direction, friction off",
                 "friction": "pressed over 15 steps then slid 0.1 mm/step (texture plates 0.02) in a seeded direction, friction 0.5",
                 "layers": "two layers split at half thickness, base 8x stiffer (nu 0.42, rho 1200)",
-                "mesh": "convex indenters as triangle meshes (icosphere 1,280 tris, 32-gon cylinder, "
-                        "12-tri cube), torus and texture plates analytic"}[kind]
+                "mesh": "bounded indenters as triangle meshes (icosphere 1,280 tris, 32-gon cylinder, "
+                        "12-tri cube, 768-tri torus with the triangle-pair barrier), texture plates analytic"}[kind]
         return scenes.config3_variant(kind), f"the batch60 pads and poses, {what}, SeedSequence(3) and (5)"
     if name == "single1944":
         return [scenes.config1()], "single 18x14x4 mm pad, 1,944 tets, sphere r=5 mm"
@@ -132,7 +132,8 @@ def make_pads(tc, ctx, envs, args, precision=None):
     for e in envs:
         m = e.pad.material
         kw = dict(precision=precision or args.precision, dt=e.params.dt, dhat=e.params.dhat,
-                  kappa=e.params.kappa, newton_tol=e.params.newton_tol, friction=e.friction)
+                  kappa=e.params.kappa, newton_tol=e.params.newton_tol, friction=e.friction,
+                  mesh_contact=e.mesh_contact)
         kw.update(extra)
         mats, idx = [dict(E=m.E, nu=m.nu, density=m.density)], None
         if e.layers is not None:

@@ -189,7 +189,19 @@ typedef struct {
                            bound); 0 = off.  Same minimiser, fewer
                            iterations where the filtered Hessian is stiffer
                            than the energy along the direction. */
-  int32_t reserved;     /* 0 */
+  int32_t mesh_contact; /* rigid meshes (TC_MESH): 0 = barrier of the
+                           distance to the whole surface, b(phi / d_hat);
+                           1 = barrier summed over the mesh's triangles
+                           nearer than d_hat, sum_t b(d_t / d_hat) (IPC's
+                           point-triangle pairs, Sec. III-B).  The distance
+                           to a whole non-convex mesh has a kink on the
+                           bisector plane of every concave edge, where
+                           Newton can stall; each d_t is C1 off its
+                           triangle.  A point near an edge or a vertex
+                           counts once per triangle in reach.  The step
+                           bound and the feasible start use phi in both
+                           modes.  1 needs friction = 0.  Analytic shapes
+                           ignore it. */
   double friction;      /* friction ratio mu >= 0 of the lagged smoothed
                            Coulomb friction against the indenters (Sec.
                            III-B: 0.5); 0 = frictionless.  Per contact

@@ -198,16 +198,34 @@ def sdf(ind, x):
     return phi, g @ R.T, R[None] @ H @ R.T[None]
 
 
-def barrier_terms(indenters, x_c, area, dhat, kappa, project=True):
+def barrier_terms(indenters, x_c, area, dhat, kappa, project=True, mesh_pairs=False):
     """Barrier energy (scalar), gradient [C,3] and Hessian [C,3,3] of E_b over
     candidate positions x_c with rest areas `area`, summed over indenters.
     The per-vertex 3x3 Hessian is PSD-projected (eigenvalues clamped at 0)
-    unless project=False."""
+    unless project=False.
+
+    mesh_pairs: a rigid mesh's barrier is summed over its triangles nearer
+    than d_hat, kappa A_k d_hat sum_t b(d_t / d_hat) with d_t the distance to
+    triangle t (IPC's point-triangle pairs, Sec. III-B), instead of taken at
+    the distance to the whole mesh."""
     C = x_c.shape[0]
     E = 0.0
     g = np.zeros((C, 3))
     H = np.zeros((C, 3, 3))
     for ind in indenters:
+        if mesh_pairs and ind.shape == MESH:
+            R = np.asarray(ind.R, dtype=np.float64)
+            y = (x_c - np.asarray(ind.c)[None]) @ R
+            k, _, d, gl, Hl = meshsdf.pair_distances(_mesh_data(ind.mesh), y, dhat)
+            s = d / dhat
+            w = kappa * area[k]
+            b1, b2 = barrier_d1(s), barrier_d2(s)
+            n = gl @ R.T
+            E += float(np.sum(w * dhat * barrier(s)))
+            np.add.at(g, k, (w * b1)[:, None] * n)
+            np.add.at(H, k, w[:, None, None] * ((b2 / dhat)[:, None, None] * _outer(n, n)
+                                                + b1[:, None, None] * (R[None] @ Hl @ R.T[None])))
+            continue
         phi, n, Hphi = sdf(ind, x_c)
         s = phi / dhat
         E += float(np.sum(kappa * area * dhat * barrier(s)))

@@ -39,7 +39,8 @@ def contact_forces(pad, x, inds, prm, fric=None):
     step potential's contact gradient (barrier, plus friction when `fric`,
     the step's lagged friction data, is given).
     Returns dict of f, n, area, f_n, f_tau, p, reaction."""
-    _, gb, _ = contact.barrier_terms(inds, x[pad.cand], pad.area, prm.dhat, prm.kappa)
+    _, gb, _ = contact.barrier_terms(inds, x[pad.cand], pad.area, prm.dhat, prm.kappa,
+                                     mesh_pairs=prm.mesh_pairs)
     f = -gb
     if fric is not None:
         lagged, x_t_c = fric

@@ -55,8 +55,10 @@ class MeshData:
                 self.vert_n[tri[k]] += ang * self.fn[t]
 
 
-def _closest_block(mesh, y):
-    """closest() for a block of points, all triangles at once ([K, M] pairs)."""
+def _pairs_block(mesh, y):
+    """Closest point on every triangle for a block of points: distance [K,M],
+    point [K,M,3], feature kind [K,M], feature id [K,M], edge direction
+    [K,M,3] (zero unless kind is EDGE)."""
     K = y.shape[0]
     A, B, Cc = (mesh.V[mesh.F[:, k]][None] for k in range(3))          # [1,M,3]
     n = mesh.fn[None]
@@ -100,8 +102,14 @@ def _closest_block(mesh, y):
         ed = e / np.linalg.norm(e, axis=2, keepdims=True)
         tdir = np.where(better[..., None], np.broadcast_to(ed, tdir.shape), tdir)
     dist = np.linalg.norm(Y - pt, axis=2)
+    return dist, pt, kind, fid, tdir
+
+
+def _closest_block(mesh, y):
+    """closest() for a block of points, all triangles at once ([K, M] pairs)."""
+    dist, pt, kind, fid, tdir = _pairs_block(mesh, y)
     j = np.argmin(dist, axis=1)
-    r = np.arange(K)
+    r = np.arange(y.shape[0])
     return dist[r, j], pt[r, j], kind[r, j], fid[r, j], tdir[r, j]
 
 
@@ -133,3 +141,30 @@ def sdf_local(mesh, y):
                  np.where((kind == EDGE)[:, None, None], I - tt - gg, I - gg))
     H = (s / safe)[:, None, None] * H
     return s * d, g, H
+
+
+def pair_distances(mesh, y, dmax, block=128):
+    """Every (point, triangle) pair nearer than dmax: the unsigned distance
+    to the closed triangle and its derivatives in the mesh's frame.
+    Returns (point index [P], triangle [P], d [P], grad [P,3], hess [P,3,3])
+    with grad = (y - c) / d and hess = 0 (face), (I - t t^T - grad grad^T)
+    / d (edge of direction t), (I - grad grad^T) / d (vertex): the distance
+    to one triangle is C1 off the triangle, unlike the distance to the whole
+    mesh, which has a kink on the bisector plane of every concave edge."""
+    y = np.atleast_2d(np.asarray(y, dtype=np.float64))
+    out = []
+    for i0 in range(0, y.shape[0], block):
+        yb = y[i0:i0 + block]
+        dist, pt, kind, _, tdir = _pairs_block(mesh, yb)
+        ki, ti = np.nonzero(dist < dmax)
+        d = dist[ki, ti]
+        safe = np.where(d > 0, d, 1.0)
+        g = (yb[ki] - pt[ki, ti]) / safe[:, None]
+        I = np.eye(3)[None]
+        gg = g[:, :, None] * g[:, None, :]
+        t = tdir[ki, ti]
+        tt = t[:, :, None] * t[:, None, :]
+        k = kind[ki, ti]
+        H = np.where((k == FACE)[:, None, None], 0.0, np.where((k == EDGE)[:, None, None], I - tt - gg, I - gg))
+        out.append((ki + i0, ti, d, g, H / safe[:, None, None]))
+    return tuple(np.concatenate([o[j] for o in out]) for j in range(5))

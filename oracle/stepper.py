@@ -108,6 +108,7 @@ class StepParams:
     max_halvings: int = 40
     mu_f: float = 0.0        # friction ratio (0 = frictionless)
     eps_v: float = 0.01      # friction velocity threshold [m/s]
+    mesh_pairs: bool = False  # rigid meshes: barrier summed over triangles nearer than d_hat
 
 
 @dataclasses.dataclass
@@ -138,7 +139,7 @@ def energy(pad, x, xhat, inds, prm, fric=None):
     h2 = prm.dt ** 2
     Eel = float(np.sum(fem.elastic_energy(x, pad.tets, pad.Dminv, pad.vol,
                                           pad.mu, pad.lam, pad.alpha)))
-    Eb, _, _ = contact.barrier_terms(inds, x[pad.cand], pad.area, prm.dhat, prm.kappa)
+    Eb, _, _ = contact.barrier_terms(inds, x[pad.cand], pad.area, prm.dhat, prm.kappa, mesh_pairs=prm.mesh_pairs)
     Ein = 0.0 if prm.quasi_static else 0.5 * float(np.sum(pad.mass[:, None] * (x - xhat) ** 2))
     Ef = _friction(pad, x, prm, fric)[0] if fric is not None else 0.0
     return Ein + h2 * (Eel + Eb) + Ef
@@ -149,7 +150,7 @@ def gradient(pad, x, xhat, inds, prm, fric=None):
     h2 = prm.dt ** 2
     ge = fem.elastic_gradient(x, pad.tets, pad.Dminv, pad.vol, pad.mu, pad.lam, pad.alpha)
     g = h2 * fem.scatter_vector(pad.tets, ge, x.shape[0])
-    _, gb, _ = contact.barrier_terms(inds, x[pad.cand], pad.area, prm.dhat, prm.kappa)
+    _, gb, _ = contact.barrier_terms(inds, x[pad.cand], pad.area, prm.dhat, prm.kappa, mesh_pairs=prm.mesh_pairs)
     g[pad.cand] += h2 * gb
     if fric is not None:
         g[pad.cand] += _friction(pad, x, prm, fric)[1]
@@ -168,7 +169,7 @@ def hessian(pad, x, inds, prm, project=True, fric=None):
     rows = np.repeat(dof, 12, axis=1).ravel()
     cols = np.tile(dof, (1, 12)).ravel()
     vals = h2 * Ke.ravel()
-    _, _, Hb = contact.barrier_terms(inds, x[pad.cand], pad.area, prm.dhat, prm.kappa)
+    _, _, Hb = contact.barrier_terms(inds, x[pad.cand], pad.area, prm.dhat, prm.kappa, mesh_pairs=prm.mesh_pairs)
     cd = (3 * pad.cand[:, None] + np.arange(3)[None, :])
     rows = np.concatenate([rows, np.repeat(cd, 3, axis=1).ravel()])
     cols = np.concatenate([cols, np.tile(cd, (1, 3)).ravel()])

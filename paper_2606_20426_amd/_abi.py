@@ -47,7 +47,7 @@ class TcParams(C.Structure):
                 ("max_halvings", C.c_int32), ("cg_forcing", C.c_int32),
                 ("hess_proj", C.c_int32), ("init_guess", C.c_int32),
                 ("cg_conv_tol", C.c_double), ("cg_eta_max", C.c_double),
-                ("ls_expand", C.c_int32), ("reserved", C.c_int32),
+                ("ls_expand", C.c_int32), ("mesh_contact", C.c_int32),
                 ("friction", C.c_double), ("eps_v", C.c_double)]
 
 

@@ -493,6 +493,90 @@ __device__ __forceinline__ double bar2(double s) {
          : -2.0 * log(s) - 4.0 * (s - 1.0) / s + (s - 1.0) * (s - 1.0) / (s * s);
 }
 
+// Barrier of one pad vertex against a rigid mesh summed over its triangles
+// nearer than d_hat (mesh_contact 1): per triangle t the unsigned distance
+// d_t to the closed triangle, grad d_t = (y - c_t) / d_t and hess d_t as for
+// the nearest feature (0 on the face, (I - t t^T - g g^T) / d on an edge,
+// (I - g g^T) / d at a vertex).  World-frame results per unit kappa A:
+// e = sum d_hat b(s_t), g = sum b'(s_t) grad d_t, H = sum b''(s_t) / d_hat
+// grad grad^T + b'(s_t) hess d_t (wantH), Hn its first part; s_t = d_t /
+// d_hat.  A vertex on a triangle (d_t = 0) gives e = +inf.
+__device__ void mesh_pair_world(const DevIndenter& ind, const DevMesh* meshes, const double x[3], double dhat,
+                                bool wantH, double& e, double g[3], double H[3][3], double Hn[3][3]) {
+  const DevMesh& M = meshes[ind.reserved];
+  double y[3];
+  for (int i = 0; i < 3; ++i)
+    y[i] = ind.R[0 * 3 + i] * (x[0] - ind.c[0]) + ind.R[1 * 3 + i] * (x[1] - ind.c[1]) +
+           ind.R[2 * 3 + i] * (x[2] - ind.c[2]);
+  double gl[3] = {0, 0, 0}, Hl[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, Hnl[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  e = 0.0;
+  const double r2 = dhat * dhat;
+  int stack[BVH_STACK];
+  int sp = 0;
+  stack[sp++] = 0;
+  auto box_d2 = [&](const BvhNode& nd) {
+    double s2 = 0.0;
+    for (int i = 0; i < 3; ++i) {
+      const double v = fmax(fmax(nd.lo[i] - y[i], y[i] - nd.hi[i]), 0.0);
+      s2 += v * v;
+    }
+    return s2;
+  };
+  while (sp > 0) {
+    const BvhNode& nd = M.nodes[stack[--sp]];
+    if (box_d2(nd) >= r2) continue;
+    if (nd.count > 0) {
+      for (int t = nd.first; t < nd.first + nd.count; ++t) {
+        double c[3];
+        const double* T = M.tv + 9 * (size_t)t;
+        const int r = tri_closest(T, y, c);
+        const double df[3] = {y[0] - c[0], y[1] - c[1], y[2] - c[2]};
+        const double d2 = df[0] * df[0] + df[1] * df[1] + df[2] * df[2];
+        if (!(d2 < r2)) continue;
+        const double d = sqrt(d2);
+        const double s = d / dhat;
+        e += dhat * bar0(s);
+        if (!(d > 0.0)) continue;
+        const double b1 = bar1(s);
+        const double gd[3] = {df[0] / d, df[1] / d, df[2] / d};
+        for (int i = 0; i < 3; ++i) gl[i] += b1 * gd[i];
+        if (!wantH) continue;
+        const double b2 = bar2(s) / dhat;
+        double tv[3] = {0, 0, 0};
+        if (r >= 4) {
+          const int e0 = r - 4, e1 = (r - 4 + 1) % 3;
+          for (int i = 0; i < 3; ++i) tv[i] = T[3 * e1 + i] - T[3 * e0 + i];
+          const double L = sqrt(tv[0] * tv[0] + tv[1] * tv[1] + tv[2] * tv[2]);
+          for (int i = 0; i < 3; ++i) tv[i] /= L;
+        }
+        const double curv = r == 0 ? 0.0 : b1 / d;
+        for (int i = 0; i < 3; ++i)
+          for (int j = 0; j < 3; ++j) {
+            const double nn = b2 * gd[i] * gd[j];
+            Hnl[i][j] += nn;
+            Hl[i][j] += nn + curv * ((i == j ? 1.0 : 0.0) - tv[i] * tv[j] - gd[i] * gd[j]);
+          }
+      }
+    } else if (sp + 2 <= BVH_STACK) {
+      stack[sp++] = nd.first;
+      stack[sp++] = (int)(&nd - M.nodes) + 1;
+    }
+  }
+  for (int i = 0; i < 3; ++i) g[i] = ind.R[i * 3 + 0] * gl[0] + ind.R[i * 3 + 1] * gl[1] + ind.R[i * 3 + 2] * gl[2];
+  if (!wantH) return;
+  auto rot = [&](const double A[3][3], double B[3][3]) {
+    double T[3][3];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        T[i][j] = ind.R[i * 3 + 0] * A[0][j] + ind.R[i * 3 + 1] * A[1][j] + ind.R[i * 3 + 2] * A[2][j];
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        B[i][j] = T[i][0] * ind.R[j * 3 + 0] + T[i][1] * ind.R[j * 3 + 1] + T[i][2] * ind.R[j * 3 + 2];
+  };
+  rot(Hl, H);
+  rot(Hnl, Hn);
+}
+
 __device__ __forceinline__ void load3(const double* p, int i, double v[3]) {
   v[0] = p[3 * i]; v[1] = p[3 * i + 1]; v[2] = p[3 * i + 2];
 }
@@ -991,6 +1075,18 @@ __global__ void k_barrier(const Tile* tiles, int ntiles, const EnvDesc* envs) {
   const double kA = E.kappa * E.cand_area[k];
   double g[3] = {0, 0, 0}, H[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, Hn[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
   for (int m = 0; m < P->n_ind; ++m) {
+    if (E.mesh_pairs && P->ind[m].shape == TC_MESH) {
+      double e, gp[3], Hq[3][3], Hnq[3][3];
+      mesh_pair_world(P->ind[m], E.meshes, x, E.dhat, true, e, gp, Hq, Hnq);
+      for (int i = 0; i < 3; ++i) {
+        g[i] += kA * gp[i];
+        for (int j = 0; j < 3; ++j) {
+          H[i][j] += kA * Hq[i][j];
+          Hn[i][j] += kA * Hnq[i][j];
+        }
+      }
+      continue;
+    }
     double phi, n[3], Hp[3][3];
     sdf_world(P->ind[m], E.meshes, x, phi, n, Hp, true, E.dhat);
     if (phi < E.dhat) {
@@ -1907,6 +2003,12 @@ __global__ void k_energy(const Tile* tiles, int ntiles, const EnvDesc* envs, int
       for (int c = 0; c < 3; ++c) y[c] = E.xn[3 * vi + c] + (mode ? al * (double)d[3 * vi + c] : 0.0);
       for (int m = 0; m < P->n_ind; ++m) {
         double phi;
+        if (E.mesh_pairs && P->ind[m].shape == TC_MESH) {
+          double Hn[3][3];
+          mesh_pair_world(P->ind[m], E.meshes, y, E.dhat, false, phi, g, H, Hn);
+          acc += E.kappa * E.cand_area[k] * phi;
+          continue;
+        }
         sdf_world(P->ind[m], E.meshes, y, phi, g, H, false, E.dhat);
         if (phi < E.dhat) acc += E.kappa * E.cand_area[k] * E.dhat * bar0(phi / E.dhat);
       }
@@ -2151,6 +2253,12 @@ __global__ void k_contact(const Tile* tiles, int ntiles, const EnvDesc* envs) {
     double f[3] = {0, 0, 0};
     for (int m = 0; m < P->n_ind; ++m) {
       double phi, g[3];
+      if (E.mesh_pairs && P->ind[m].shape == TC_MESH) {
+        double Hn[3][3];
+        mesh_pair_world(P->ind[m], E.meshes, xv, E.dhat, false, phi, g, H, Hn);
+        for (int c = 0; c < 3; ++c) f[c] -= kA * g[c];
+        continue;
+      }
       sdf_world(P->ind[m], E.meshes, xv, phi, g, H, false, E.dhat);
       if (phi < E.dhat) {
         const double b1 = bar1(phi / E.dhat);

@@ -991,7 +991,7 @@ tc_status tc_params_default(tc_params* out) {
   out->cg_conv_tol = 0.0;
   out->cg_eta_max = 0.5;
   out->ls_expand = 0;
-  out->reserved = 0;
+  out->mesh_contact = 0;
   out->friction = 0.0;
   out->eps_v = 0.01;
   return TC_OK;
@@ -1457,6 +1457,7 @@ tc_status tc_pad_set_params(tc_pad* pad, const tc_params* params) {
   E.ls_expand = params->ls_expand;
   E.fr_mu = params->friction;
   E.fr_eps = params->eps_v * params->dt;
+  E.mesh_pairs = params->mesh_contact;
   for (int c = 0; c < 3; ++c) E.gravity[c] = params->gravity[c];
   E.quasi_static = params->quasi_static;
   E.max_cg = params->max_cg;

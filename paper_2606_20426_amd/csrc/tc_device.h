@@ -227,6 +227,7 @@ struct EnvDesc {
   double gravity[3];
   int32_t quasi_static, max_cg, max_newton, max_halvings, precond, cg_forcing, hess_proj, init_guess;
   int32_t ls_expand;
+  int32_t mesh_pairs;        // rigid meshes: barrier summed over triangles within d_hat
   double fr_mu, fr_eps;      // friction ratio (0 = off) and slip threshold eps_v h [m]
 };
 

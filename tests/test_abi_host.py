@@ -117,11 +117,13 @@ def test_validation_error_codes(tc):
     for kw in (dict(dt=0.0), dict(dhat=-1.0), dict(kappa=float("inf")), dict(max_newton=0),
                dict(precision=7), dict(precond=3), dict(cg_rel_tol=0.0), dict(friction=-0.5),
                dict(friction=float("nan")), dict(friction=0.5, eps_v=0.0), dict(ls_expand=17),
+               dict(mesh_contact=2), dict(mesh_contact=-1), dict(mesh_contact=1, friction=0.5),
                dict(hess_proj=3), dict(cg_forcing=3), dict(cg_eta_max=1.0)):
         assert _status(lambda: V(params=tc.make_params(**kw))) == -1
     # friction off: the threshold is not used
     assert _status(lambda: V(params=tc.make_params(friction=0.0, eps_v=0.0))) == 0
     assert _status(lambda: V(params=tc.make_params(friction=0.5, eps_v=0.01))) == 0
+    assert _status(lambda: V(params=tc.make_params(mesh_contact=1))) == 0
     d = tc.make_params()
     assert d.friction == 0.0 and d.eps_v == 0.01
     I = np.eye(3)
@@ -236,10 +238,11 @@ def test_batch_variants_keep_the_batch():
                 assert set(np.unique(idx)) == {0, 1} and mats[0] == b.pad.material
                 assert mats[1].E == 8 * mats[0].E
             else:
-                if b.indenter.shape in (scenes.TORUS, scenes.TEXTURE):
-                    assert e.indenter.shape == b.indenter.shape and e.indenter.mesh is None
+                if b.indenter.shape == scenes.TEXTURE:
+                    assert e.indenter.shape == scenes.TEXTURE and e.indenter.mesh is None
                     continue
                 assert e.indenter.shape == scenes.MESH
+                assert e.mesh_contact == (1 if b.indenter.shape == scenes.TORUS else 0)
                 V, F = e.indenter.mesh
                 assert _status(lambda: __import__("paper_2606_20426_amd").validate(rigid_mesh=(V, F))) == 0
                 # every mesh vertex on or inside the analytic surface

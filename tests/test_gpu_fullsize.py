@@ -182,7 +182,7 @@ def test_batch60_bench_configuration(batch60_run, step, ks):
 # pads checked per variant at the last step: every indenter shape the
 # variant changes (pads 0-5 carry cube, sphere, sphere, cylinder, torus,
 # texture) on all three pad shapes
-VARIANT_CHECKS = {"friction": (0, 3, 5), "layers": (1, 4, 5), "mesh": (0, 1, 3)}
+VARIANT_CHECKS = {"friction": (0, 3, 5), "layers": (1, 4, 5), "mesh": (0, 1, 3, 4)}
 
 
 @pytest.fixture(scope="module", params=sorted(VARIANT_CHECKS))
@@ -217,7 +217,8 @@ def _run_variant(kind, envs, ctx, kw, ids, pads):
             ids[id(e.indenter.mesh)] = ctx.add_mesh(*e.indenter.mesh)
         pads.append(tc.Pad(ctx, e.pad.X, e.pad.tets, mats,
                            tc.make_params(dt=e.params.dt, dhat=e.params.dhat, kappa=e.params.kappa,
-                                          newton_tol=e.params.newton_tol, friction=e.friction, **kw),
+                                          newton_tol=e.params.newton_tol, friction=e.friction,
+                                          mesh_contact=e.mesh_contact, **kw),
                            tet_material=idx))
 
     def poses(e, s):
@@ -258,7 +259,8 @@ def test_batch60_variants(variant_run):
         else:
             op = stepper.make_pad(e.pad.X, e.pad.tets, m.E, m.nu, m.density, fixed=e.pad.fixed)
         prm = stepper.StepParams(dt=e.params.dt, dhat=e.params.dhat, kappa=e.params.kappa,
-                                 newton_tol=e.params.newton_tol, mu_f=e.friction, eps_v=0.01)
+                                 newton_tol=e.params.newton_tol, mu_f=e.friction, eps_v=0.01,
+                                 mesh_pairs=bool(e.mesh_contact))
         check_state(out, op, x_prev, v_prev, [e.pose(step)], prm,
                     f"batch60-{kind} pad {k} ({e.pad.name}, {e.pad.tets.shape[0]} tets, indenter "
                     f"{e.indenter.shape}) step {step}", inds_prev=[e.pose(step - 1)])

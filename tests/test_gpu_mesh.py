@@ -26,12 +26,12 @@ def _gpu_inds(ids, inds):
     return out
 
 
-def _oracle_run(name, mu_f):
+def _oracle_run(name, mu_f, pairs=False):
     pad, params, poses = getattr(scenes, name)()
     m = pad.material
     op = stepper.make_pad(pad.X, pad.tets, m.E, m.nu, m.density, fixed=pad.fixed)
     prm = stepper.StepParams(dt=params.dt, dhat=params.dhat, kappa=params.kappa, newton_tol=1e-10,
-                             mu_f=mu_f, eps_v=0.01)
+                             mu_f=mu_f, eps_v=0.01, mesh_pairs=pairs)
     refs = []
     for s, ind in enumerate(poses, start=1):
         prev = [poses[s - 2]] if s > 1 else None
@@ -54,7 +54,12 @@ def slide():
     return _oracle_run("mesh_slide_episode", 0.5)
 
 
-def _compare(run, prec, newton_tol, cg_rel_tol, mu_f):
+@pytest.fixture(scope="module")
+def press_pairs():
+    return _oracle_run("mesh_press_episode", 0.0, pairs=True)
+
+
+def _compare(run, prec, newton_tol, cg_rel_tol, mu_f, pairs=0):
     pad, poses, op, refs = run
     ctx = context()
     mesh = poses[0].mesh
@@ -62,7 +67,7 @@ def _compare(run, prec, newton_tol, cg_rel_tol, mu_f):
     m = pad.material
     gp = tc.Pad(ctx, pad.X, pad.tets, [dict(E=m.E, nu=m.nu, density=m.density)],
                 tc.make_params(precision=prec, newton_tol=newton_tol, cg_rel_tol=cg_rel_tol,
-                               friction=mu_f, eps_v=0.01), fixed=pad.fixed)
+                               friction=mu_f, eps_v=0.01, mesh_contact=pairs), fixed=pad.fixed)
     top = op.is_top.astype(bool)
     worst = np.zeros(4)
     for s, (ind, ref) in enumerate(zip(poses, refs), start=1):
@@ -81,6 +86,15 @@ def _compare(run, prec, newton_tol, cg_rel_tol, mu_f):
 @pytest.mark.parametrize("prec,newton_tol,cg_rel_tol,tol", [("fp64", 1e-9, 1e-9, 1e-6), ("mixed", 1e-6, 1e-4, 1e-4)])
 def test_torus_mesh_press_matches_oracle(press, prec, newton_tol, cg_rel_tol, tol):
     worst = _compare(press, prec, newton_tol, cg_rel_tol, 0.0)
+    assert (worst[:3] < tol).all() and worst[3] < 10 * tol, worst
+
+
+@pytest.mark.parametrize("prec,newton_tol,cg_rel_tol,tol", [("fp64", 1e-9, 1e-9, 1e-6), ("mixed", 1e-7, 1e-4, 1e-4)])
+def test_torus_mesh_pair_barrier_matches_oracle(press_pairs, prec, newton_tol, cg_rel_tol, tol):
+    """mesh_contact 1: the barrier summed over the triangles within d_hat.
+    The mixed run stops at 1e-7 of the bounding box: at the first contact
+    step the displacement is small, and 1e-6 leaves 1.8e-4 of it."""
+    worst = _compare(press_pairs, prec, newton_tol, cg_rel_tol, 0.0, pairs=1)
     assert (worst[:3] < tol).all() and worst[3] < 10 * tol, worst
 
 

@@ -112,3 +112,111 @@ def test_step_with_box_mesh_equals_analytic_box():
         assert ra.newton_iters == rm.newton_iters
         assert np.abs(ra.x - rm.x).max() <= 1e-12 * np.abs(ra.x - pad.X).max()
     assert np.abs(op_m.x - pad.X).max() > 0.1 * MM
+
+
+# ---------------------------------------------------------------- pair barrier
+
+class _Ind:
+    def __init__(self, mesh, R=None, c=None):
+        self.shape, self.prm, self.mesh = contact.MESH, (0.0,), mesh
+        self.R = np.eye(3) if R is None else R
+        self.c = np.zeros(3) if c is None else c
+
+
+def test_pair_barrier_closed_forms_on_a_split_face():
+    """Above a box face made of two triangles (split along a diagonal): a
+    point over the diagonal is at height h from both triangles, a point off
+    it is at h from its own triangle and at sqrt(h^2 + delta^2) from the
+    diagonal edge of the other.  The pair barrier is the sum of the two
+    barriers; the distance barrier takes the nearer only."""
+    dhat, kappa, area = 0.3, 2.0, np.array([0.7])
+    V, F = meshes.box_surface(5.0, 5.0, 5.0)
+    ind = _Ind((V, F))
+    top = F[np.all(V[F][:, :, 2] > 4.9, axis=1)]
+    assert len(top) == 2
+    shared = sorted(set(top[0]) & set(top[1]))
+    p0, p1 = V[shared[0]], V[shared[1]]
+    e = (p1 - p0) / np.linalg.norm(p1 - p0)
+    m = np.cross(e, [0, 0, 1.0])                       # in-plane normal of the diagonal
+    B = lambda s: kappa * area[0] * dhat * contact.barrier(np.array([s]))[0]
+    for h, delta in [(0.1, 0.0), (0.05, 0.2), (0.2, 0.25), (0.1, 0.4)]:
+        y = 0.5 * (p0 + p1) + 0.3 * e + delta * m + np.array([0, 0, h])
+        Ep, _, _ = contact.barrier_terms([ind], y[None], area, dhat, kappa, mesh_pairs=True)
+        Ed, _, _ = contact.barrier_terms([ind], y[None], area, dhat, kappa)
+        other = np.hypot(h, delta)
+        want = B(h / dhat) + (B(other / dhat) if other < dhat else 0.0)
+        assert Ep == pytest.approx(want, rel=1e-12), (h, delta)
+        assert Ed == pytest.approx(B(h / dhat), rel=1e-12)
+
+
+def test_pair_barrier_derivatives_fd():
+    """Gradient and (unprojected) Hessian of the pair barrier against central
+    differences of the energy and of the gradient, near a rotated, shifted
+    torus mesh (faces, edges and vertices all in reach)."""
+    V, F = meshes.torus_surface(4.0, 1.5, 16, 8, phase=0.5)
+    R = scenes._rot_z(0.4) @ scenes._rot_x(0.3)
+    c = np.array([0.3, -0.2, 0.1])
+    ind = _Ind((V, F), R, c)
+    dhat, kappa = 0.6, 3.0
+    rng = np.random.default_rng(5)
+    # points just outside the tube: along outward normals of random surface points
+    t = rng.integers(len(F), size=60)
+    w = rng.dirichlet(np.ones(3), size=60)
+    P = np.einsum("kj,kji->ki", w, V[F[t]])
+    fn = np.cross(V[F[t, 1]] - V[F[t, 0]], V[F[t, 2]] - V[F[t, 0]])
+    fn /= np.linalg.norm(fn, axis=1)[:, None]
+    y = P + rng.uniform(0.05, 0.5, (60, 1)) * fn
+    x = y @ R.T + c
+    area = rng.uniform(0.5, 1.5, 60)
+    E0, g, H = contact.barrier_terms([ind], x, area, dhat, kappa, project=False, mesh_pairs=True)
+    assert E0 > 0 and np.abs(g).max() > 0
+    h = 1e-6
+    for k in range(60):
+        for i in range(3):
+            dx = np.zeros((60, 3))
+            dx[k, i] = h
+            Ep, gp, _ = contact.barrier_terms([ind], x + dx, area, dhat, kappa, mesh_pairs=True)
+            Em, gm, _ = contact.barrier_terms([ind], x - dx, area, dhat, kappa, mesh_pairs=True)
+            assert (Ep - Em) / (2 * h) == pytest.approx(g[k, i], rel=1e-5, abs=1e-7 * np.abs(g).max())
+            assert np.abs((gp[k] - gm[k]) / (2 * h) - H[k, :, i]).max() <= 1e-4 * np.abs(H[k]).max() + 1e-6
+
+
+def test_pair_barrier_smooth_across_a_concave_edge():
+    """On the torus's inner side the ring-direction edges are concave.  On
+    the bisector plane of such an edge the distance to the mesh switches
+    between the two faces, so the distance barrier's gradient jumps across
+    the plane; the pair barrier's gradient is continuous there."""
+    V, F = meshes.torus_surface(4.0, 1.5, 16, 8, phase=0.5)
+    mesh = meshsdf.MeshData(V, F)
+    ind = _Ind((V, F))
+    dhat, kappa, area = 0.5, 1.0, np.array([1.0])
+    # a concave edge: shared by two triangles whose normals turn towards each
+    # other (the far vertex of one lies on the outer side of the other's plane)
+    found = None
+    for t1 in range(len(F)):
+        for t2 in range(t1 + 1, len(F)):
+            sh = set(F[t1]) & set(F[t2])
+            if len(sh) != 2:
+                continue
+            far = (set(F[t2]) - sh).pop()
+            side = mesh.fn[t1] @ (V[far] - V[F[t1, 0]])
+            angle = np.arccos(np.clip(mesh.fn[t1] @ mesh.fn[t2], -1, 1))
+            if side > 1e-9 and angle > 0.2:
+                found = (t1, t2, sorted(sh))
+                break
+        if found:
+            break
+    assert found is not None
+    t1, t2, (a, b) = found
+    nA, nB = mesh.fn[t1], mesh.fn[t2]
+    mid = 0.5 * (V[a] + V[b])
+    bis = (nA + nB) / np.linalg.norm(nA + nB)
+    across = (nA - nB) / np.linalg.norm(nA - nB)
+    y0 = mid + 0.1 * bis
+    eps = 1e-7
+    gd = [contact.barrier_terms([ind], (y0 + s * eps * across)[None], area, dhat, kappa)[1][0] for s in (-1, 1)]
+    gp = [contact.barrier_terms([ind], (y0 + s * eps * across)[None], area, dhat, kappa, mesh_pairs=True)[1][0]
+          for s in (-1, 1)]
+    scale = np.linalg.norm(gd[0])
+    assert np.linalg.norm(gd[1] - gd[0]) > 0.1 * scale          # the kink
+    assert np.linalg.norm(gp[1] - gp[0]) < 1e-4 * scale         # smooth

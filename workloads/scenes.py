@@ -91,6 +91,7 @@ class Episode:
     slide: Optional[np.ndarray] = None   # world xy travel per step once the ramp is done [m]
     friction: float = 0.0                # friction ratio of the pad
     layers: Optional[tuple] = None       # (per-tet material index [T], [Material, ...])
+    mesh_contact: int = 0                # rigid meshes: 1 = barrier summed over triangle pairs
 
     def depth_at(self, step):
         """Indenter travel after `step` steps (step >= 1)."""
@@ -334,14 +335,12 @@ def config3(n_envs=60):
 
 
 def mesh_indenter(ind):
-    """The same indenter given as a closed triangle surface (MESH), for the
-    convex shapes: sphere -> icosphere (1,280 triangles, vertices on the
-    sphere), cylinder -> 32-gon prism, cube -> its 12 triangles.  Every mesh
-    lies inside its analytic shape, so a start pose feasible for the shape
-    stays feasible.  The torus and the texture plate stay analytic: a
-    polygonal torus has concave edges on its inner side, across whose
-    bisector planes the distance to the mesh (the nearest of two faces) has
-    a kink, and a contact vertex at rest in such a valley stalls Newton."""
+    """The same indenter given as a closed triangle surface (MESH), where
+    the shape is bounded: sphere -> icosphere (1,280 triangles, vertices on
+    the sphere), cylinder -> 32-gon prism, cube -> its 12 triangles, torus ->
+    32 x 12 quads with a facet strip at the bottom.  Every mesh lies inside
+    its analytic shape, so a start pose feasible for the shape stays
+    feasible.  The texture plate (unbounded) stays analytic."""
     p = ind.prm
     if ind.shape == SPHERE:
         mesh = meshes.icosphere(p[0], 3)
@@ -349,6 +348,8 @@ def mesh_indenter(ind):
         mesh = meshes.cylinder_surface(p[0], p[1], 32)
     elif ind.shape == BOX:
         mesh = meshes.box_surface(p[0], p[1], p[2])
+    elif ind.shape == TORUS:
+        mesh = meshes.torus_surface(p[0], p[1], 32, 12, phase=0.5)
     else:
         return ind
     return Indenter(MESH, (0.0, 0.0, 0.0, 0.0), ind.R.copy(), ind.c.copy(), mesh)
@@ -370,7 +371,11 @@ def config3_variant(kind, n_envs=60):
       layers   : two layers split at half thickness, the drawn material on
                  top and a base 8x stiffer (nu = 0.42, rho = 1200), the
                  dual-layer gel of Sec. IV-C;
-      mesh     : the convex indenters given as triangle meshes (mesh_indenter)."""
+      mesh     : the bounded indenters given as triangle meshes (mesh_indenter);
+                 the torus, whose mesh has concave edges on the inner side
+                 of the tube, with the barrier summed over triangle pairs
+                 (mesh_contact 1: the distance to the whole mesh has a kink
+                 across each concave edge, where Newton can stall)."""
     if kind not in VARIANTS:
         raise ValueError(kind)
     rng = np.random.default_rng(np.random.SeedSequence(5))
@@ -387,7 +392,8 @@ def config3_variant(kind, n_envs=60):
                                           Material(8.0 * m.E, 0.42, 1200.0))
             e = dataclasses.replace(e, layers=(idx, mats))
         else:
-            e = dataclasses.replace(e, indenter=mesh_indenter(e.indenter))
+            e = dataclasses.replace(e, indenter=mesh_indenter(e.indenter),
+                                    mesh_contact=int(e.indenter.shape == TORUS))
         out.append(e)
     return out
 
