@@ -431,7 +431,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); pads are independent, so N GPUs "
-              "would each run their own batch (see DESIGN.md, sharding)", file=sys.stderr)
+              "would each run their own share of the batch; this benchmark measures one", file=sys.stderr)
         sys.exit(2)
     if args.workload == "serve256":
         out = run_serve(args)
