@@ -92,3 +92,68 @@ def test_friction_state_round_trip_and_reset():
     gp.step([poses[6]])
     assert not np.array_equal(gp.read("positions"), xa)
     gp.close()
+
+
+def _punch_pads(friction):
+    """A 18 x 14 x 4 mm pad (48,384 tets) under the flat cylinder punch
+    (r = 2.5 mm), pressed 0.3 mm over 6 steps."""
+    pad = scenes.box_pad(18e-3, 14e-3, 4e-3, 36, 28, 8, scenes.Material(0.3e6, 0.45, 1000.0))
+    start = scenes.place_indenter(pad, scenes.CYLINDER, (9e-3, 7e-3), 1e-4)
+    m = pad.material
+    gp = tc.Pad(context(), pad.X, pad.tets, dict(E=m.E, nu=m.nu, density=m.density),
+                tc.make_params(precision="mixed", friction=friction, eps_v=EPS_V))
+    for s in range(1, 7):
+        assert gp.step([start.at_depth(0.05e-3 * s)]).status == 0
+    return gp, start.at_depth(0.3e-3)
+
+
+def _forces(gp, axis_xy):
+    cand = gp.read("candidates")
+    p = gp.read("positions")[cand]
+    f = gp.read("contact_force")
+    r = p[:, :2] - axis_xy[None]
+    rn = np.linalg.norm(r, axis=1)
+    er = r / np.maximum(rn, 1e-12)[:, None]
+    et = np.stack([-er[:, 1], er[:, 0]], axis=1)
+    ft = f[:, :2]
+    return f, ft, np.einsum("ki,ki->k", ft, et), np.einsum("ki,ki->k", ft, er), r
+
+
+def test_contact_modes_translation_and_torsion():
+    """The two frictional contact modes of Sec. IV-C under a flat punch.
+    Lateral translation: the pad is dragged along the motion, with no
+    sideways force.  Axial rotation: the tangential contact forces circulate
+    with the rotation (a vortex: azimuthal, no net force, positive torque);
+    without friction the same twist leaves no torque."""
+    # translation: +x, 0.05 mm per step
+    gp, pose = _punch_pads(MU)
+    for s in range(1, 6):
+        pose = scenes.Indenter(pose.shape, pose.prm, pose.R, pose.c + np.array([0.05e-3, 0.0, 0.0]))
+        assert gp.step([pose]).status == 0
+    f, ft, _, _, _ = _forces(gp, pose.c[:2])
+    F = f.sum(axis=0)
+    log(f"translation: net contact force on the pad {F}, |F_t| / F_z {np.hypot(F[0], F[1]) / abs(F[2]):.3f}")
+    assert F[0] > 0 and abs(F[1]) < 0.02 * F[0]
+    assert np.hypot(F[0], F[1]) <= 1.05 * MU * abs(F[2])
+    gp.close()
+    # torsion: 2 degrees per step about the punch axis
+    torque = {}
+    for mu in (MU, 0.0):
+        gp, pose = _punch_pads(mu)
+        for s in range(1, 6):
+            pose = scenes.Indenter(pose.shape, pose.prm, scenes._rot_z(np.radians(2.0 * s)), pose.c)
+            assert gp.step([pose]).status == 0
+        f, ft, f_theta, f_r, r = _forces(gp, pose.c[:2])
+        mag = np.linalg.norm(ft, axis=1)
+        torque[mu] = float(np.sum(r[:, 0] * ft[:, 1] - r[:, 1] * ft[:, 0]))
+        net = np.linalg.norm(ft.sum(axis=0))
+        log(f"torsion mu {mu}: torque {torque[mu]:.4e} N m, azimuthal share {np.abs(f_theta).sum() / max(mag.sum(), 1e-300):.3f}, "
+            f"net tangential {net:.3e} of {mag.sum():.3e}")
+        if mu > 0:
+            big = mag > 0.01 * mag.max()
+            assert torque[mu] > 0
+            assert np.abs(f_theta).sum() > 0.8 * mag.sum()
+            assert (f_theta[big] > 0).mean() > 0.9
+            assert net < 0.05 * mag.sum()
+        gp.close()
+    assert abs(torque[0.0]) < 0.01 * torque[MU]
