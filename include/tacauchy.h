@@ -200,7 +200,9 @@ typedef struct {
                            triangle.  A point near an edge or a vertex
                            counts once per triangle in reach.  The step
                            bound and the feasible start use phi in both
-                           modes.  1 needs friction = 0.  Analytic shapes
+                           modes.  With friction, mode 1 lags lambda n =
+                           -kappa A sum_t b'(d_t / d_hat) grad d_t (lambda
+                           its length, n its direction).  Analytic shapes
                            ignore it. */
   double friction;      /* friction ratio mu >= 0 of the lagged smoothed
                            Coulomb friction against the indenters (Sec.

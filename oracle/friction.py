@@ -62,13 +62,24 @@ def indenter_motion(ind_old, ind_new, p):
     return local @ R_new.T + np.asarray(ind_new.c)[None] - p
 
 
-def lag(inds_old, inds_new, x_t_c, area, dhat, kappa):
-    """Per (indenter, candidate): lambda [M,C], n [M,C,3], w [M,C,3]."""
+def lag(inds_old, inds_new, x_t_c, area, dhat, kappa, mesh_pairs=False):
+    """Per (indenter, candidate): lambda [M,C], n [M,C,3], w [M,C,3].
+    lambda n is the barrier's contact force on the vertex at x_t under the
+    previous pose: -kappa A b'(phi / d_hat) grad phi, or, for a rigid mesh
+    with mesh_pairs, -kappa A sum_t b'(d_t / d_hat) grad d_t over the
+    triangles within d_hat (lambda its length, n its direction)."""
     lam, nrm, w = [], [], []
     for old, new in zip(inds_old, inds_new):
-        phi, n, _ = contact.sdf(old, x_t_c)
-        lam.append(-kappa * area * contact.barrier_d1(phi / dhat))
-        nrm.append(n)
+        if mesh_pairs and old.shape == contact.MESH:
+            _, g, _ = contact.barrier_terms([old], x_t_c, np.ones(len(x_t_c)), dhat, 1.0, project=False,
+                                            mesh_pairs=True)
+            mag = np.linalg.norm(g, axis=1)
+            lam.append(kappa * area * mag)
+            nrm.append(-g / np.where(mag > 0, mag, 1.0)[:, None])
+        else:
+            phi, n, _ = contact.sdf(old, x_t_c)
+            lam.append(-kappa * area * contact.barrier_d1(phi / dhat))
+            nrm.append(n)
         w.append(indenter_motion(old, new, x_t_c))
     return np.array(lam), np.array(nrm), np.array(w)
 

@@ -126,7 +126,8 @@ def friction_lag(pad, inds, prm, inds_prev=None):
     if prm.mu_f <= 0:
         return None
     prev = inds if inds_prev is None else inds_prev
-    return friction.lag(prev, inds, pad.x[pad.cand], pad.area, prm.dhat, prm.kappa), pad.x[pad.cand].copy()
+    return (friction.lag(prev, inds, pad.x[pad.cand], pad.area, prm.dhat, prm.kappa, mesh_pairs=prm.mesh_pairs),
+            pad.x[pad.cand].copy())
 
 
 def _friction(pad, x, prm, fric):

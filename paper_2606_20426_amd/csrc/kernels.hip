@@ -791,12 +791,23 @@ __global__ void k_predict(const Tile* tiles, int ntiles, const EnvDesc* envs) {
   for (int m = 0; m < P->n_ind; ++m) {
     const DevIndenter& A = P->prev[m];
     const DevIndenter& B = P->ind[m];
-    double phi, n[3], loc[3];
-    sdf_world(A, E.meshes, xt, phi, n, H, false, E.dhat);
+    double phi, n[3], loc[3], lam;
+    if (E.mesh_pairs && A.shape == TC_MESH) {
+      // the summed pair force -kappa A sum_t b'(s_t) grad d_t: lambda its
+      // length, n its direction
+      double gs[3], Hn[3][3];
+      mesh_pair_world(A, E.meshes, xt, E.dhat, false, phi, gs, H, Hn);
+      const double gm = sqrt(gs[0] * gs[0] + gs[1] * gs[1] + gs[2] * gs[2]);
+      lam = kA * gm;
+      for (int j = 0; j < 3; ++j) n[j] = gm > 0.0 ? -gs[j] / gm : 0.0;
+    } else {
+      sdf_world(A, E.meshes, xt, phi, n, H, false, E.dhat);
+      lam = phi < E.dhat ? -kA * bar1(phi / E.dhat) : 0.0;
+    }
     for (int j = 0; j < 3; ++j)
       loc[j] = A.R[0 * 3 + j] * (xt[0] - A.c[0]) + A.R[1 * 3 + j] * (xt[1] - A.c[1]) + A.R[2 * 3 + j] * (xt[2] - A.c[2]);
     double* f = E.fric + ((size_t)m * E.C + k) * FRIC_STRIDE;
-    f[FRIC_LAM] = phi < E.dhat ? -kA * bar1(phi / E.dhat) : 0.0;
+    f[FRIC_LAM] = lam;
     for (int j = 0; j < 3; ++j) {
       f[FRIC_N + j] = n[j];
       f[FRIC_W + j] = B.R[j * 3 + 0] * loc[0] + B.R[j * 3 + 1] * loc[1] + B.R[j * 3 + 2] * loc[2] + B.c[j] - xt[j];

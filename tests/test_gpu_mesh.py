@@ -59,6 +59,11 @@ def press_pairs():
     return _oracle_run("mesh_press_episode", 0.0, pairs=True)
 
 
+@pytest.fixture(scope="module")
+def slide_pairs():
+    return _oracle_run("mesh_slide_episode", 0.5, pairs=True)
+
+
 def _compare(run, prec, newton_tol, cg_rel_tol, mu_f, pairs=0):
     pad, poses, op, refs = run
     ctx = context()
@@ -95,6 +100,13 @@ def test_torus_mesh_pair_barrier_matches_oracle(press_pairs, prec, newton_tol, c
     The mixed run stops at 1e-7 of the bounding box: at the first contact
     step the displacement is small, and 1e-6 leaves 1.8e-4 of it."""
     worst = _compare(press_pairs, prec, newton_tol, cg_rel_tol, 0.0, pairs=1)
+    assert (worst[:3] < tol).all() and worst[3] < 10 * tol, worst
+
+
+@pytest.mark.parametrize("prec,newton_tol,cg_rel_tol,tol", [("fp64", 1e-9, 1e-9, 1e-6), ("mixed", 1e-7, 1e-4, 1e-4)])
+def test_icosphere_slide_pair_barrier_with_friction_matches_oracle(slide_pairs, prec, newton_tol, cg_rel_tol, tol):
+    """mesh_contact 1 with friction: the lag takes the summed pair force."""
+    worst = _compare(slide_pairs, prec, newton_tol, cg_rel_tol, 0.5, pairs=1)
     assert (worst[:3] < tol).all() and worst[3] < 10 * tol, worst
 
 

@@ -220,3 +220,26 @@ def test_pair_barrier_smooth_across_a_concave_edge():
     scale = np.linalg.norm(gd[0])
     assert np.linalg.norm(gd[1] - gd[0]) > 0.1 * scale          # the kink
     assert np.linalg.norm(gp[1] - gp[0]) < 1e-4 * scale         # smooth
+
+
+def test_pair_friction_lag_closed_forms():
+    """The friction lag under the pair barrier is the summed pair force:
+    over a split face's diagonal both triangles push along the face normal,
+    so lambda doubles and n stays the normal; over one triangle's interior,
+    away from the others, it equals the distance barrier's lag."""
+    from oracle import friction
+    dhat, kappa = 0.3, 2.0
+    V, F = meshes.box_surface(5.0, 5.0, 5.0)
+    ind = _Ind((V, F))
+    top = F[np.all(V[F][:, :, 2] > 4.9, axis=1)]
+    a, b = sorted(set(top[0]) & set(top[1]))
+    mid = 0.5 * (V[a] + V[b])
+    e = (V[b] - V[a]) / np.linalg.norm(V[b] - V[a])
+    m = np.cross(e, [0, 0, 1.0])
+    x = np.array([mid + np.array([0, 0, 0.1]), mid + 0.5 * m + np.array([0, 0, 0.1])])
+    area = np.array([0.7, 0.9])
+    l0, n0, _ = friction.lag([ind], [ind], x, area, dhat, kappa)
+    l1, n1, _ = friction.lag([ind], [ind], x, area, dhat, kappa, mesh_pairs=True)
+    assert l1[0, 0] == pytest.approx(2 * l0[0, 0], rel=1e-12) and l0[0, 0] > 0
+    assert np.allclose(n1[0, 0], [0, 0, 1], atol=1e-12) and np.allclose(n0[0, 0], [0, 0, 1], atol=1e-12)
+    assert l1[0, 1] == pytest.approx(l0[0, 1], rel=1e-12) and np.allclose(n1[0, 1], n0[0, 1], atol=1e-12)
