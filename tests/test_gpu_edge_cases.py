@@ -197,3 +197,19 @@ def test_runtime_switches_relayout_scratch():
         g.close()
     ref_ctx.close()
     ctx.close()
+
+
+def test_mesh_contact_mode_leaves_analytic_shapes_alone():
+    """mesh_contact changes the barrier of rigid meshes only: a pad under an
+    analytic sphere steps bitwise the same in either mode."""
+    ep = scenes.config1()
+    ctx = context()
+    a = gpu_pad(ctx, ep.pad, "mixed", mesh_contact=0)
+    b = gpu_pad(ctx, ep.pad, "mixed", mesh_contact=1)
+    for s in range(1, 5):
+        sa, sb = a.step([ep.pose(s)]), b.step([ep.pose(s)])
+        assert sa.newton_iters == sb.newton_iters and sa.cg_iters == sb.cg_iters
+    for f in ("positions", "sigma", "contact_force", "reaction"):
+        assert np.array_equal(a.read(f), b.read(f)), f
+    a.close()
+    b.close()
