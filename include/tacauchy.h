@@ -274,7 +274,7 @@ tc_status tc_validate_materials(int32_t n, const tc_material* m);
 tc_status tc_validate_params(const tc_params* p);
 tc_status tc_validate_indenters(int32_t n, const tc_indenter* ind);
 
-/* Alg. 1 lines 1-3 on the host: surface triangles (faces owned by exactly
+/* Alg. 1 (surface extraction) on the host: surface triangles (faces owned by exactly
  * one tet, outward winding, ascending (tet, local face) order), their parent
  * tets, the contact-face label (rest outward normal >= 0.5 along the thinnest
  * bounding-box axis, on the side away from the base) and the contact vertices
@@ -342,7 +342,7 @@ tc_status tc_set_cg_variant(tc_context* ctx, int32_t variant);
 /* ------------------------------------------------------------------- pads */
 /* Copies the mesh and materials into HBM and runs the setup kernels: Eq. 1
  * Lame parameters, Dm^-1 and V_e, lumped mass, rest contact areas; builds the
- * surface (Alg. 1 lines 1-3) and the sparsity of the assembled Hessian on
+ * surface (Alg. 1 (surface extraction)) and the sparsity of the assembled Hessian on
  * the host.  State starts at rest (x = X, v = 0). */
 tc_status tc_pad_create(tc_context* ctx, const tc_mesh* mesh,
                         int32_t n_materials, const tc_material* materials,

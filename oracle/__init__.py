@@ -7,7 +7,7 @@ check and the benchmark's CPU-baseline leg may import it; the product path
 never calls it.
 
 Modules (each function cites the passage it follows):
-  surface   Alg. 1 lines 1-3: surface triangles, parent tets, contact-face
+  surface   Alg. 1 (surface extraction): surface triangles, parent tets, contact-face
             labels, candidates, rest vertex areas, lumped mass
   material  Eq. 1 (Lame), Eq. 2 (first Piola stress), Eq. 3/4 (Cauchy stress),
             the energy density whose derivative is Eq. 2, its Hessian and

@@ -1,6 +1,6 @@
 """Stress and force extraction (oracle, FP64, test infrastructure).
 
-Alg. 2 line "Stress": sigma_i per tet from Eq. 4 (with the same rest shift as
+Alg. 2 (the stress step): sigma_i per tet from Eq. 4 (with the same rest shift as
 the energy).  Alg. 1: per surface triangle j, from current vertex positions,
 n_j = e1 x e2 / |e1 x e2|, sigma of the parent tet, t_j = sigma n_j (Eq. 6/7),
 p_n = t . n (Eq. 8, positive = tension), t_tau = t - p_n n (Eq. 9).

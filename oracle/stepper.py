@@ -1,7 +1,7 @@
 """One implicit incremental-potential step and its Newton minimiser
 (oracle, FP64, test infrastructure).
 
-Sec. III-B / Alg. 2 line "Physics": the pad advances by minimising, over the
+Sec. III-B / Alg. 2 (the physics step): the pad advances by minimising, over the
 free degrees of freedom,
 
     E(x) = 1/2 sum_a m_a |x_a - xhat_a|^2 + h^2 [ sum_e V_e Psi(F_e) + E_b(x) ],

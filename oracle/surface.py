@@ -1,6 +1,6 @@
 """Surface topology and per-vertex setup (oracle, FP64, test infrastructure).
 
-Alg. 1 lines 1-3 (Sec. III-C-2): extract the boundary triangles of the tet
+Alg. 1 (surface extraction) (Sec. III-C-2): extract the boundary triangles of the tet
 mesh and the parent tetrahedron of each.  Sec. III-A: the thinnest bounding
 box axis is the pad thickness and a 15 % thickness band marks the contact
 surface (here the face opposite the fixed base; see `contact_face_labels`).
@@ -15,7 +15,7 @@ LOCAL_FACES = ((1, 2, 3), (0, 3, 2), (0, 1, 3), (0, 2, 1))
 
 
 def surface_triangles(tets):
-    """Alg. 1 lines 1-3.  A face is on the surface iff its vertex set occurs
+    """Alg. 1 (surface extraction).  A face is on the surface iff its vertex set occurs
     in exactly one tet.  Returns (tris int32 [S,3] with outward winding,
     parent int32 [S]) in ascending (tet id, local face) order."""
     tets = np.asarray(tets, dtype=np.int64)

@@ -153,7 +153,7 @@ def refine_mesh(X, tets, tet_material=None, max_tets=2_000_000, **kw):
 
 
 def mesh_surface(X, tets, fixed=None):
-    """Host-only Alg. 1 lines 1-3: dict(tris, parent, is_top, candidates)."""
+    """Host-only Alg. 1 (surface extraction): dict(tris, parent, is_top, candidates)."""
     lib = load()
     m, keep = _mesh(X, tets, fixed)
     ns, nc = C.c_int32(), C.c_int32()

@@ -1,5 +1,5 @@
 // Host-side mesh topology of a pad: validation, surface extraction
-// (Alg. 1 lines 1-3), contact-face labels and contact vertices, and the
+// (Alg. 1 (surface extraction)), contact-face labels and contact vertices, and the
 // sparsity of the assembled Hessian with its per-block gather lists.
 #pragma once
 

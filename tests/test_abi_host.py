@@ -1,5 +1,5 @@
 """Host-only checks of the C-ABI library: it loads, exports every entry point
-declared in include/tacauchy.h, its surface extraction (Alg. 1 lines 1-3)
+declared in include/tacauchy.h, its surface extraction (Alg. 1 (surface extraction))
 matches the oracle bit for bit, and argument validation returns the
 documented error codes.  No GPU is touched."""
 import ctypes as C

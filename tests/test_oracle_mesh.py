@@ -1,6 +1,6 @@
-"""Pins of the oracle's surface extraction and per-vertex setup (Alg. 1 lines
-1-3, contact-surface band rule) against exact integer counts and
-geometric identities."""
+"""Pins of the oracle's surface extraction and per-vertex setup (Alg. 1's
+surface extraction, contact-surface band rule) against exact integer counts
+and geometric identities."""
 import json
 import os
 
