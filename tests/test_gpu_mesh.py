@@ -175,3 +175,59 @@ def test_mesh_registry():
         ctx.remove_mesh(i)
     assert before - ctx.memory()[0] == mesh_bytes
     ctx.close()
+
+
+def test_pair_mode_served_and_extracted():
+    """Rigid-mesh pads in pair mode (mesh_contact 1) through the server end
+    bitwise equal to synchronous stepping; standalone extraction at the
+    final state gives the oracle's pair-barrier contact forces."""
+    import time
+    pad, params, poses = scenes.mesh_press_episode()
+    mesh = poses[0].mesh
+    ctx = tc.Context(0)
+    mid = ctx.add_mesh(*mesh)
+    m = pad.material
+    shifts = [0.0, 1.0 * MM, -1.0 * MM]
+    eps = [[dict(shape=tc.MESH, prm=(0.0,), R=p.R, c=p.c + np.array([d, 0, 0]), mesh_id=mid) for p in poses]
+           for d in shifts]
+
+    def make():
+        return tc.Pad(ctx, pad.X, pad.tets, dict(E=m.E, nu=m.nu, density=m.density),
+                      tc.make_params(precision="mixed", mesh_contact=1), fixed=pad.fixed)
+    alone = []
+    for ep in eps:
+        g = make()
+        for ind in ep:
+            assert g.step([ind]).status == 0
+        alone.append(g.read("positions"))
+        g.close()
+    pads = [make() for _ in eps]
+    srv = tc.Server(ctx, 2)
+    results = []
+    for s in range(len(poses)):
+        for k, ep in enumerate(eps):
+            srv.submit(pads[k], [ep[s]], tag=100 * k + s)
+        results += srv.poll()
+    t0 = time.perf_counter()
+    while len(results) < len(eps) * len(poses):
+        results += srv.poll(wait_us=2000)
+        assert time.perf_counter() - t0 < 60, "server did not finish"
+    srv.close()
+    assert all(r["status"] == 0 for r in results)
+    for k, g in enumerate(pads):
+        assert np.array_equal(g.read("positions"), alone[k]), k
+    # standalone extraction against the oracle at the GPU's positions
+    g = pads[0]
+    g.extract([eps[0][-1]])
+    x = g.read("positions")
+    op = stepper.make_pad(pad.X, pad.tets, m.E, m.nu, m.density, fixed=pad.fixed)
+    prm = stepper.StepParams(dt=params.dt, dhat=params.dhat, kappa=params.kappa, mesh_pairs=True)
+    ref = extract.contact_forces(op, x, [poses[-1]], prm)
+    f = g.read("contact_force")
+    err = np.abs(f - ref["f"]).max() / np.abs(ref["f"]).max()
+    log(f"served pair-mode pads bitwise equal; extraction contact forces vs oracle {err:.2e}")
+    assert err < 1e-9 and np.abs(ref["f"]).max() > 0
+    for g in pads:
+        g.close()
+    ctx.remove_mesh(mid)
+    ctx.close()
