@@ -1856,7 +1856,9 @@ __global__ void k_filter(const Tile* tiles, int ntiles, const EnvDesc* envs) {
         sdf_world(I, E.meshes, x, phi, g, H, false, FILTER_SPAN * pn / 0.9);
         double a = INFINITY;
         const double gp = g[0] * p[0] + g[1] * p[1] + g[2] * p[2];
-        if (convex_shape(I.shape)) {
+        if (convex_shape(I.shape) || (I.shape == TC_MESH && E.meshes[I.reserved].convex)) {
+          // phi convex along the segment (outside a convex body): it stays
+          // above its tangent line, which reaches 0.1 phi(x) at this a
           if (gp < 0) a = 0.9 * phi / (-gp);
         } else if (I.shape == TC_MESH) {
           // conservative advancement: phi is 1-Lipschitz, so phi >= 0.1 phi(x)

@@ -110,7 +110,43 @@ struct Tables {
   Tree tree;
   std::vector<double> tv, tn, enf, vnf;
   std::vector<int32_t> tid_l;
+  bool convex = false;
 };
+
+// A closed, consistently oriented surface bounds a convex body when it is
+// connected and no edge is concave (the far corner of each neighbouring
+// triangle lies on or below a triangle's plane); the distance to it is then
+// a convex function outside.
+bool surface_is_convex(const std::vector<Vec3>& V, const int32_t* tris, int n_tris, const std::vector<Vec3>& fn) {
+  std::map<std::pair<int, int>, int> dir_tri;
+  for (int f = 0; f < n_tris; ++f)
+    for (int k = 0; k < 3; ++k) dir_tri[{tris[3 * f + k], tris[3 * f + (k + 1) % 3]}] = f;
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (const Vec3& v : V)
+    for (int i = 0; i < 3; ++i) { lo[i] = std::min(lo[i], v[i]); hi[i] = std::max(hi[i], v[i]); }
+  const double tol = 1e-9 * std::sqrt((hi[0] - lo[0]) * (hi[0] - lo[0]) + (hi[1] - lo[1]) * (hi[1] - lo[1]) +
+                                      (hi[2] - lo[2]) * (hi[2] - lo[2]));
+  std::vector<int> parent(n_tris);
+  std::iota(parent.begin(), parent.end(), 0);
+  auto root = [&](int x) {
+    while (parent[x] != x) x = parent[x] = parent[parent[x]];
+    return x;
+  };
+  bool convex = true;
+  for (const auto& de : dir_tri) {
+    const int f1 = de.second, f2 = dir_tri.at({de.first.second, de.first.first});
+    parent[root(f1)] = root(f2);
+    int far = -1;
+    for (int k = 0; k < 3; ++k) {
+      const int v = tris[3 * f2 + k];
+      if (v != de.first.first && v != de.first.second) far = v;
+    }
+    if (dot(fn[f1], sub(V[far], V[de.first.first])) > tol) convex = false;
+  }
+  for (int f = 0; f < n_tris; ++f)
+    if (root(f) != root(0)) convex = false;
+  return convex;
+}
 
 tc_status mesh_tables(int32_t n_verts, const double* verts, int32_t n_tris, const int32_t* tris, Tables& out) {
   if (!verts || !tris) return set_error(TC_E_INVALID_ARG, "null argument");
@@ -196,6 +232,7 @@ tc_status mesh_tables(int32_t n_verts, const double* verts, int32_t n_tris, cons
       for (int i = 0; i < 3; ++i) enf[3 * e + i] = en[e][i];
     for (int v = 0; v < n_verts; ++v)
       for (int i = 0; i < 3; ++i) vnf[3 * (size_t)v + i] = vn[v][i];
+    out.convex = surface_is_convex(V, tris, n_tris, fn);
     out.tree = std::move(tree);
     out.tv = std::move(tv);
     out.tn = std::move(tn);
@@ -258,6 +295,7 @@ tc_status tc_rigid_mesh_create(tc_context* ctx, int32_t n_verts, const double* v
     DevMesh dm{};
     dm.n_tri = n_tris;
     dm.n_node = (int)tree.nodes.size();
+    dm.convex = tb.convex ? 1 : 0;
     char* p = mem;
     dm.nodes = reinterpret_cast<const BvhNode*>(p); p += b_nodes;
     dm.tv = reinterpret_cast<const double*>(p); p += b_tv;

@@ -61,6 +61,8 @@ struct BvhNode {
 // free slot.
 struct DevMesh {
   int32_t n_tri, n_node;
+  int32_t convex;          // 1: one component, no concave edge (the distance outside is convex)
+  int32_t unused;
   const double* tv;        // [n_tri][9] corners a, b, c (counter-clockwise from outside)
   const double* tn;        // [n_tri][3] unit outward face normal
   const int32_t* tid;      // [n_tri][6] vertex ids of a, b, c; edge ids of ab, bc, ca

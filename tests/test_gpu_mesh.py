@@ -118,8 +118,8 @@ def test_icosphere_slide_with_friction_matches_oracle(slide, prec, newton_tol, c
 
 def test_box_mesh_equals_analytic_box():
     """The same pad pressed by a face-down, slightly tilted cube given as 12
-    triangles and as the analytic box: the same minimiser (the Newton paths
-    differ only through the step bound)."""
+    triangles and as the analytic box: the same minimiser, by the same
+    Newton path (a convex mesh's step bound is the convex shapes')."""
     pad = scenes.config1().pad
     ctx = context()
     a = 3 * MM
@@ -139,6 +139,8 @@ def test_box_mesh_equals_analytic_box():
         disp = np.abs(xa - pad.X).max()
         log(f"step {s}: box {sa} mesh {sm} diff {np.abs(xa - xm).max() / disp:.2e}")
         assert np.abs(xa - xm).max() <= 1e-6 * disp
+        # a convex mesh takes the convex shapes' step bound: the same path
+        assert sa.newton_iters == sm.newton_iters
         ra, rm = pads[0].read("reaction"), pads[1].read("reaction")
         assert np.abs(ra - rm).max() <= 1e-5 * np.abs(ra).max()
     assert disp > 0.2 * MM
