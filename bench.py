@@ -10,6 +10,7 @@ contact forces and commit, all in one fused set of launches.
     python bench.py --sequential --precision fp64                 # the same pads one at a time
     python bench.py --workload serve256 [--rate 2000] [--duration 20]
     python bench.py --workload large1.2m --ablation               # FP32/FP64 CG ablation + extraction
+    python bench.py --workload large-refined --ablation           # the same on an adaptively refined pad
     python bench.py --workload batch60-friction                   # the 60 pads with friction (also
                                                                   # batch60-slide, -layers, -mesh)
 
@@ -55,6 +56,13 @@ def build_workload(name):
         return [scenes.config1()], "single 18x14x4 mm pad, 1,944 tets, sphere r=5 mm"
     if name == "large1.2m":
         return [scenes.config5()], "24x24x5 mm pad, ~1.2M tets, 4-level refinement, sphere r=3 mm, 1.0 mm over 60 steps"
+    if name == "large-refined":
+        import paper_2606_20426_amd as tc
+        base, kw = scenes.config5_refine_base()
+        X, T, _ = tc.refine_mesh(base.X, base.tets, max_tets=4_000_000, **kw)
+        return [scenes.config5_refined(X, T)], (f"24x24x5 mm pad refined by terminal-edge bisection under the "
+                                                 f"contact sizing field from 28x28x6 cells to {T.shape[0]} tets, "
+                                                 f"sphere r=3 mm, 1.0 mm over 60 steps")
     if name == "serve256":
         return scenes.config4(), "256 resident pads, 5k-150k tets log-uniform (SeedSequence(4)), press/release episodes"
     raise SystemExit(f"unknown workload {name}")

@@ -269,19 +269,27 @@ def test_batch60_variants(variant_run):
             log(f"  tangential / normal reaction {np.hypot(r[0], r[1]) / max(abs(r[2]), 1e-300):.3f}")
 
 
-def test_large_pad_final_state():
-    """The 1.2 M-tet pad (the largest workload) through its whole episode,
+@pytest.mark.parametrize("kind", ["graded", "refined"])
+def test_large_pad_final_state(kind):
+    """The 1.2 M-tet pad (the largest workload; graded grid, or the 1.35 M
+    tets of the library's adaptive refinement) through its whole episode,
     60 steps to 1.0 mm, in mixed precision with the benchmark's solver
     settings; the oracle then checks the final step from the outside:
     stationarity with its own Newton direction, extraction element by
     element, contact forces and the identities."""
-    ep = scenes.config5()
+    if kind == "graded":
+        ep = scenes.config5()
+    else:
+        base, kw = scenes.config5_refine_base()
+        X, T, _ = tc.refine_mesh(base.X, base.tets, max_tets=4_000_000, **kw)
+        ep = scenes.config5_refined(X, T)
     ctx = tc.Context(0)
     m = ep.pad.material
     gp = tc.Pad(ctx, ep.pad.X, ep.pad.tets, dict(E=m.E, nu=m.nu, density=m.density),
                 tc.make_params(precision="mixed", dt=ep.params.dt, dhat=ep.params.dhat, kappa=ep.params.kappa,
                                newton_tol=ep.params.newton_tol, cg_rel_tol=0.2, cg_eta_max=0.2, cg_forcing=2,
                                hess_proj=4, ls_expand=4, init_guess=1))
+    gp_width = gp.info["ell_width"]
     try:
         newton = []
         for s in range(1, ep.n_steps + 1):
@@ -292,12 +300,12 @@ def test_large_pad_final_state():
     finally:
         gp.close()
         ctx.close()
-    log(f"large pad ({ep.pad.tets.shape[0]} tets): newton per step {newton}")
+    log(f"large pad, {kind} ({ep.pad.tets.shape[0]} tets, ELL width {gp_width}): newton per step {newton}")
     prm = stepper.StepParams(dt=ep.params.dt, dhat=ep.params.dhat, kappa=ep.params.kappa,
                              newton_tol=ep.params.newton_tol)
     t0 = time.perf_counter()
     check_state(out, oracle_pad(ep.pad), x_prev, v_prev, [ep.pose(ep.n_steps)], prm,
-                f"large pad step {ep.n_steps}")
+                f"large pad, {kind}, step {ep.n_steps}")
     log(f"oracle check {time.perf_counter() - t0:.0f} s")
     assert np.abs(out["reaction"]).max() > 0
 

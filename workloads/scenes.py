@@ -450,3 +450,28 @@ def config5(target=1.2e6):
     params = Params()
     ind = place_indenter(pad, SPHERE, centre, params.dhat, sphere_radius=3 * MM)
     return Episode(pad, ind, 1.0 * MM, 60, params)
+
+
+def config5_refine_base():
+    """The large pad built by conforming refinement instead of a graded grid:
+    a uniform 28 x 28 x 6-cell Kuhn mesh of the 24 x 24 x 5 mm pad (28,224
+    tets) and the Sec. III-A sizing field around config5's seeded patch
+    centre (l_c = 0.075 mm, l_g = 1.6 mm, other constants default), which
+    refines it to about 1.35 M tets.  Returns (coarse pad, sizing keywords);
+    the episode is config5's: sphere r = 3 mm at the centre, 1.0 mm over 60
+    steps, placed on the refined pad."""
+    rng = np.random.default_rng(np.random.SeedSequence(5))
+    L = 24 * MM
+    centre = (rng.uniform(0.35 * L, 0.65 * L), rng.uniform(0.35 * L, 0.65 * L))
+    pad = box_pad(L, L, 5 * MM, 28, 28, 6, Material(0.3e6, 0.45, 1000.0), name="config5_refined")
+    return pad, dict(l_contact=0.075 * MM, l_global=1.6 * MM, centre=centre)
+
+
+def config5_refined(X, tets):
+    """config5's episode on a refined pad (X, tets from refining the
+    config5_refine_base mesh)."""
+    base, kw = config5_refine_base()
+    pad = Pad("config5_refined", np.asarray(X, np.float64), np.asarray(tets, np.int32), base.material, base.dims)
+    params = Params()
+    ind = place_indenter(pad, SPHERE, kw["centre"], params.dhat, sphere_radius=3 * MM)
+    return Episode(pad, ind, 1.0 * MM, 60, params)
