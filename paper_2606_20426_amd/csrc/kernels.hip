@@ -1435,10 +1435,12 @@ __device__ __forceinline__ void cg_spmv_rows(const Tile tl, const EnvDesc* envs,
   if (threadIdx.x == 0) E.part_pq[tl.tile] = pq;
 }
 
-// The same product with LPR lanes per matrix row (one stored 3x3 block per
-// lane, blocks of a row contiguous): every lane issues its own independent
-// neighbour gather, and the row sum is a shuffle reduction inside the lane
-// group.  A tile is blockDim.x / LPR lane groups x SPMV_ROWS_PER_GROUP rows.
+// The same product with LPR lanes per matrix row (lane l takes the stored
+// 3x3 blocks l, l + LPR, ... of its row, blocks of a row contiguous): every
+// lane issues its own independent neighbour gathers, and the row sum is a
+// shuffle reduction inside the lane group.  A row's padding slots (col -1)
+// come after its blocks, so a lane stops at its first one.  A tile is
+// blockDim.x / LPR lane groups x SPMV_ROWS_PER_GROUP rows.
 template <typename R, int LPR>
 __device__ __forceinline__ void cg_spmv_lanes(const Tile tl, const EnvDesc* envs, int parity, double* sh) {
   const EnvDesc& E = envs[tl.env];
@@ -1456,18 +1458,34 @@ __device__ __forceinline__ void cg_spmv_lanes(const Tile tl, const EnvDesc* envs
 #pragma unroll 2
   for (int k = 0; k < SPMV_ROWS_PER_GROUP; ++k) {
     const int i = row0 + k * groups;
-    R y0 = 0, y1 = 0, y2 = 0, pj0 = 0, pj1 = 0, pj2 = 0;
-    if (i < E.V && lane < E.W) {
-      const size_t item = (size_t)i * E.W + lane;
-      const int j = E.col[item];
-      if (j >= 0) {
-        pj0 = z[3 * j] + beta * pold[3 * j];
-        pj1 = z[3 * j + 1] + beta * pold[3 * j + 1];
-        pj2 = z[3 * j + 2] + beta * pold[3 * j + 2];
+    R y0 = 0, y1 = 0, y2 = 0, pd0 = 0, pd1 = 0, pd2 = 0;
+    if (E.W <= LPR) {             // one slot per lane (the common case)
+      if (i < E.V && lane < E.W) {
+        const size_t item = (size_t)i * E.W + lane;
+        const int j = E.col[item];
+        if (j >= 0) {
+          pd0 = z[3 * j] + beta * pold[3 * j];
+          pd1 = z[3 * j + 1] + beta * pold[3 * j + 1];
+          pd2 = z[3 * j + 2] + beta * pold[3 * j + 2];
+          const R* As = (const R*)E.A + item * 9;
+          y0 = As[0] * pd0 + As[1] * pd1 + As[2] * pd2;
+          y1 = As[3] * pd0 + As[4] * pd1 + As[5] * pd2;
+          y2 = As[6] * pd0 + As[7] * pd1 + As[8] * pd2;
+        }
+      }
+    } else if (i < E.V) {
+      for (int sl = lane; sl < E.W; sl += LPR) {
+        const size_t item = (size_t)i * E.W + sl;
+        const int j = E.col[item];
+        if (j < 0) break;
+        const R pj0 = z[3 * j] + beta * pold[3 * j];
+        const R pj1 = z[3 * j + 1] + beta * pold[3 * j + 1];
+        const R pj2 = z[3 * j + 2] + beta * pold[3 * j + 2];
+        if (sl == 0) { pd0 = pj0; pd1 = pj1; pd2 = pj2; }
         const R* As = (const R*)E.A + item * 9;
-        y0 = As[0] * pj0 + As[1] * pj1 + As[2] * pj2;
-        y1 = As[3] * pj0 + As[4] * pj1 + As[5] * pj2;
-        y2 = As[6] * pj0 + As[7] * pj1 + As[8] * pj2;
+        y0 += As[0] * pj0 + As[1] * pj1 + As[2] * pj2;
+        y1 += As[3] * pj0 + As[4] * pj1 + As[5] * pj2;
+        y2 += As[6] * pj0 + As[7] * pj1 + As[8] * pj2;
       }
     }
 #pragma unroll
@@ -1476,10 +1494,10 @@ __device__ __forceinline__ void cg_spmv_lanes(const Tile tl, const EnvDesc* envs
       y1 += __shfl_xor(y1, o, LPR);
       y2 += __shfl_xor(y2, o, LPR);
     }
-    if (lane == 0 && i < E.V) {   // slot 0 is the diagonal: pj = p_new of row i
-      pnew[3 * i] = pj0; pnew[3 * i + 1] = pj1; pnew[3 * i + 2] = pj2;
+    if (lane == 0 && i < E.V) {   // slot 0 is the diagonal: pd = p_new of row i
+      pnew[3 * i] = pd0; pnew[3 * i + 1] = pd1; pnew[3 * i + 2] = pd2;
       q[3 * i] = y0; q[3 * i + 1] = y1; q[3 * i + 2] = y2;
-      pq += (double)pj0 * y0 + (double)pj1 * y1 + (double)pj2 * y2;
+      pq += (double)pd0 * y0 + (double)pd1 * y1 + (double)pd2 * y2;
     }
   }
   pq = block_reduce(pq, OpSum(), sh);
@@ -1612,8 +1630,9 @@ __device__ __forceinline__ void cg_pipe_row(const EnvDesc& E, int i, R n0, R n1,
   }
 }
 
-// y = (A v)_i with LPR lanes per row (one stored block per lane), or one
-// thread per row (LPR == 0); returns true in the thread that owns the sum.
+// y = (A v)_i with LPR lanes per row (lane l takes blocks l, l + LPR, ...),
+// or one thread per row (LPR == 0); returns true in the thread that owns
+// the sum.
 template <typename R, int LPR>
 __device__ __forceinline__ bool row_product(const EnvDesc& E, int i, int lane, const R* v, R& y0, R& y1, R& y2) {
   y0 = y1 = y2 = 0;
@@ -1632,15 +1651,16 @@ __device__ __forceinline__ bool row_product(const EnvDesc& E, int i, int lane, c
     }
     return true;
   } else {
-    if (i < E.V && lane < E.W) {
-      const size_t item = (size_t)i * E.W + lane;
-      const int j = E.col[item];
-      if (j >= 0) {
+    if (i < E.V) {
+      for (int sl = lane; sl < E.W; sl += LPR) {
+        const size_t item = (size_t)i * E.W + sl;
+        const int j = E.col[item];
+        if (j < 0) break;
         const R* As = (const R*)E.A + item * 9;
         const R v0 = v[3 * j], v1 = v[3 * j + 1], v2 = v[3 * j + 2];
-        y0 = As[0] * v0 + As[1] * v1 + As[2] * v2;
-        y1 = As[3] * v0 + As[4] * v1 + As[5] * v2;
-        y2 = As[6] * v0 + As[7] * v1 + As[8] * v2;
+        y0 += As[0] * v0 + As[1] * v1 + As[2] * v2;
+        y1 += As[3] * v0 + As[4] * v1 + As[5] * v2;
+        y2 += As[6] * v0 + As[7] * v1 + As[8] * v2;
       }
     }
 #pragma unroll

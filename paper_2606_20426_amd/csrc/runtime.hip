@@ -432,8 +432,17 @@ tc_status build_plan(tc_context* ctx, int n, tc_pad* const* pads, const int* slo
   P->pads.assign(pads, pads + n);
   P->h_desc.resize(n);
   int Wmax = 0;
-  for (int i = 0; i < n; ++i) Wmax = std::max(Wmax, pads[i]->W);
-  P->lpr = Wmax <= 16 ? 16 : Wmax <= 32 ? 32 : 0;
+  int64_t blocks = 0, rows = 0;
+  for (int i = 0; i < n; ++i) {
+    Wmax = std::max(Wmax, pads[i]->W);
+    blocks += pads[i]->nnz_blocks;
+    rows += pads[i]->V;
+  }
+  // SpMV lanes per row: 16 while the rows hold 16 blocks or fewer on
+  // average (a lane then takes every 16th slot of a wider row), else 32;
+  // one thread per row beyond 64 slots
+  const double fill = rows ? (double)blocks / (double)rows : 0.0;
+  P->lpr = Wmax > 64 ? 0 : (Wmax <= 16 || fill <= 16.0) ? 16 : 32;
   const int rows_spmv = P->lpr ? (ctx->spmv_block / P->lpr) * SPMV_ROWS_PER_GROUP : P->BV;
   std::vector<Tile> tiles;
   const int BV = P->BV, BT = P->BT;
