@@ -713,7 +713,7 @@ tc_status Runner::tick(bool init) {
 // Algorithmic HBM bytes of one launch's work on one pad (each array element
 // read or written once; gathers of shared vertex data counted once).
 static double kernel_bytes(KernelId k, const tc_pad* p) {
-  const double R = p->rsize, V = p->V, T = p->T, C = p->C, S = p->S, W = p->W;
+  const double R = p->rsize, V = p->V, T = p->T, C = p->C, S = p->S;
   const double nnzb = (double)p->nnz_blocks;
   switch (k) {
     case KernelId::cg_spmv: return nnzb * (9 * R + 4) + V * 12 * R;
@@ -1387,11 +1387,11 @@ tc_status tc_pad_create(tc_context* ctx, const tc_mesh* mesh, int32_t n_material
       a.block = B;
       a.stream = ctx->stream;
       a.tiles = dt; a.ntiles = Ed.n_tt;
-      launch_kernel(KernelId::setup_tets, p->fp64, a);
+      TC_HIP(launch_kernel(KernelId::setup_tets, p->fp64, a));
       a.tiles = dt + Ed.n_tt; a.ntiles = Ed.n_vt; a.out = mass;
-      launch_kernel(KernelId::setup_mass, p->fp64, a);
+      TC_HIP(launch_kernel(KernelId::setup_mass, p->fp64, a));
       a.tiles = dt + Ed.n_tt + Ed.n_vt; a.ntiles = Ed.n_ct; a.out = carea;
-      launch_kernel(KernelId::setup_area, p->fp64, a);
+      TC_HIP(launch_kernel(KernelId::setup_area, p->fp64, a));
       TC_HIP(hipGetLastError());
       TC_HIP(hipStreamSynchronize(ctx->stream));
       (void)hipFree(dd);
