@@ -406,8 +406,11 @@ tc_status tc_refine_mesh(const tc_mesh* in, const tc_sizing* sizing, int32_t cap
  * tc_indenter.reserved.  Against it phi is the signed distance to the
  * surface: nearest point over the triangles, sign from the angle-weighted
  * pseudonormal of the nearest feature; contact acts on pad vertices (as
- * for the analytic shapes), the collision-free step bound is conservative
- * advancement along each vertex's segment. */
+ * for the analytic shapes; tc_params.mesh_contact selects the distance or
+ * the point-triangle pair barrier).  The collision-free step bound is
+ * conservative advancement along each vertex's segment; a mesh that is one
+ * connected surface without concave edges (checked here) bounds a convex
+ * body, and takes the convex shapes' tangent-line bound instead. */
 tc_status tc_rigid_mesh_create(tc_context* ctx, int32_t n_verts, const double* verts, int32_t n_tris,
                                const int32_t* tris, int32_t* id);
 /* Host only: the checks of tc_rigid_mesh_create without a context. */
