@@ -46,12 +46,16 @@ def build_workload(name):
         return scenes.config3(), "60 mixed pads (flat 18x14x4 / dome 19x16x3 R30 / flat 24x24x5 mm), 20k-80k tets each, random indenters, SeedSequence(3)"
     if name.startswith("batch60-") and name[8:] in scenes.VARIANTS:
         kind = name[8:]
-        what = {"slide": "pressed over 15 steps then slid 0.1 mm/step (texture plates 0.02) in a seeded direction, friction off",
-                "friction": "pressed over 15 steps then slid 0.1 mm/step (texture plates 0.02) in a seeded direction, friction 0.5",
+        what = {"slide": "pressed over 15 steps then slid 0.1 mm/step in a seeded direction, friction off",
+                "friction": "pressed over 15 steps then slid 0.1 mm/step in a seeded direction, friction 0.5",
                 "layers": "two layers split at half thickness, base 8x stiffer (nu 0.42, rho 1200)",
                 "mesh": "bounded indenters as triangle meshes (icosphere 1,280 tris, 32-gon cylinder, "
                         "12-tri cube, 768-tri torus with the triangle-pair barrier), texture plates analytic"}[kind]
         return scenes.config3_variant(kind), f"the batch60 pads and poses, {what}, SeedSequence(3) and (5)"
+    if name == "paper60":
+        return scenes.paper60(), ("60 copies of the 18x14x4 mm pad (1,944 tets) under seeded indenters, d_hat 1 mm, "
+                                  "friction 0.5, pressed 0.2-1.0 mm over 30 steps (SeedSequence(6)): a stand-in for "
+                                  "the paper's 60-environment GelSight Mini run")
     if name == "single1944":
         return [scenes.config1()], "single 18x14x4 mm pad, 1,944 tets, sphere r=5 mm"
     if name == "large1.2m":
@@ -247,7 +251,11 @@ def run_steps(args):
                    "cg_variant": "pipelined" if args.cg_variant else "classic"},
         "roofline": roof,
     }
-    if not args.no_cpu_baseline and not args.workload.startswith("batch60-"):
+    if args.workload == "paper60":
+        # context only: the paper's own 60-environment aggregate, another
+        # machine and solver (RTX 5090, UIPC), Sec. IV-A
+        out["config"]["paper_aggregate_steps_per_s"] = 555.0
+    if not args.no_cpu_baseline and not args.workload.startswith("batch60-") and args.workload != "paper60":
         log("timing the oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(envs)
     return out

@@ -67,7 +67,8 @@ def lag(inds_old, inds_new, x_t_c, area, dhat, kappa, mesh_pairs=False):
     lambda n is the barrier's contact force on the vertex at x_t under the
     previous pose: -kappa A b'(phi / d_hat) grad phi, or, for a rigid mesh
     with mesh_pairs, -kappa A sum_t b'(d_t / d_hat) grad d_t over the
-    triangles within d_hat (lambda its length, n its direction)."""
+    triangles within d_hat; lambda is its length and n its direction (a
+    unit vector, so that I - n n^T projects)."""
     lam, nrm, w = [], [], []
     for old, new in zip(inds_old, inds_new):
         if mesh_pairs and old.shape == contact.MESH:
@@ -77,9 +78,12 @@ def lag(inds_old, inds_new, x_t_c, area, dhat, kappa, mesh_pairs=False):
             lam.append(kappa * area * mag)
             nrm.append(-g / np.where(mag > 0, mag, 1.0)[:, None])
         else:
+            # the unit normal and the force's length: the texture plate's phi
+            # is not a distance (|grad phi| < 1 off its extrema)
             phi, n, _ = contact.sdf(old, x_t_c)
-            lam.append(-kappa * area * contact.barrier_d1(phi / dhat))
-            nrm.append(n)
+            gn = np.linalg.norm(n, axis=1)
+            lam.append(-kappa * area * contact.barrier_d1(phi / dhat) * gn)
+            nrm.append(n / np.where(gn > 0, gn, 1.0)[:, None])
         w.append(indenter_motion(old, new, x_t_c))
     return np.array(lam), np.array(nrm), np.array(w)
 

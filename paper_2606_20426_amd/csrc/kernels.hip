@@ -801,8 +801,13 @@ __global__ void k_predict(const Tile* tiles, int ntiles, const EnvDesc* envs) {
       lam = kA * gm;
       for (int j = 0; j < 3; ++j) n[j] = gm > 0.0 ? -gs[j] / gm : 0.0;
     } else {
+      // lambda n = the barrier force: n the unit normal, lambda the force's
+      // length (phi of the texture plate is not a distance, |grad phi| < 1)
       sdf_world(A, E.meshes, xt, phi, n, H, false, E.dhat);
-      lam = phi < E.dhat ? -kA * bar1(phi / E.dhat) : 0.0;
+      const double gn = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+      lam = phi < E.dhat ? -kA * bar1(phi / E.dhat) * gn : 0.0;
+      if (gn > 0.0)
+        for (int j = 0; j < 3; ++j) n[j] /= gn;
     }
     for (int j = 0; j < 3; ++j)
       loc[j] = A.R[0 * 3 + j] * (xt[0] - A.c[0]) + A.R[1 * 3 + j] * (xt[1] - A.c[1]) + A.R[2 * 3 + j] * (xt[2] - A.c[2]);

@@ -232,7 +232,7 @@ def test_batch_variants_keep_the_batch():
             if kind in ("slide", "friction"):
                 assert e.friction == (0.5 if kind == "friction" else 0.0) and e.n_steps == 15
                 step = np.linalg.norm(e.pose(17).c - e.pose(16).c)
-                assert np.isclose(step, 0.02e-3 if b.indenter.shape == scenes.TEXTURE else 0.1e-3)
+                assert np.isclose(step, 0.1e-3)
                 assert np.array_equal(e.pose(15).c, b.indenter.at_depth(b.depth).c)
             elif kind == "layers":
                 idx, mats = e.layers

@@ -182,7 +182,7 @@ def test_batch60_bench_configuration(batch60_run, step, ks):
 # pads checked per variant at the last step: every indenter shape the
 # variant changes (pads 0-5 carry cube, sphere, sphere, cylinder, torus,
 # texture) on all three pad shapes
-VARIANT_CHECKS = {"friction": (0, 3, 5), "layers": (1, 4, 5), "mesh": (0, 1, 3, 4)}
+VARIANT_CHECKS = {"friction": (0, 3, 5), "layers": (1, 4, 5), "mesh": (0, 1, 3, 4), "paper60": (0, 1, 2, 3, 4)}
 
 
 @pytest.fixture(scope="module", params=sorted(VARIANT_CHECKS))
@@ -191,7 +191,7 @@ def variant_run(request):
     indenters) in the benchmark's settings, steps 1-33, as the benchmark
     sets the pads up."""
     kind = request.param
-    envs = scenes.config3_variant(kind)
+    envs = scenes.paper60() if kind == "paper60" else scenes.config3_variant(kind)
     ctx = tc.Context(0)
     kw = dict(precision="mixed", cg_rel_tol=0.2, cg_eta_max=0.2, cg_forcing=2, hess_proj=4, ls_expand=4,
               init_guess=1)

@@ -164,3 +164,35 @@ def test_sliding_impulse_closed_form():
     assert np.allclose(op.mass[k] * dx[:, 0], h2 * prm.mu_f * lam, rtol=1e-6)
     assert np.abs(dx[:, 1]).max() < 1e-6 * np.abs(dx[:, 0]).max()
     assert (2 * MM - np.abs(dx[:, 0]) > 10 * prm.eps_v * prm.dt).all()     # slip >> eps: sliding
+
+
+def test_lag_normal_is_unit_and_lambda_the_force_for_a_non_distance_phi():
+    """The texture plate's phi is a scaled height function, |grad phi| < 1
+    off its extrema.  The lag must hold the unit contact normal and the
+    barrier force's magnitude, lambda = -kappa A b'(phi / d_hat) |grad phi|,
+    so that lambda n is the contact force and the slip projector I - n n^T
+    is a projector; then the friction gradient is the derivative of the
+    friction energy (central differences) for vertices under the plate."""
+    dhat, kappa, mu, eps, h2 = 1e-3, 1e3, 0.5, 1e-4, 1.0 / 3600
+    A, lam_t = 0.2e-3, 2e-3
+    plate = scenes.Indenter(contact.TEXTURE, (A, lam_t, 0, 0), np.eye(3), np.zeros(3))
+    rng = np.random.default_rng(9)
+    x_t = np.column_stack([rng.uniform(0, 4e-3, 8), rng.uniform(0, 4e-3, 8), np.full(8, -0.5e-3)])
+    area = rng.uniform(0.5e-6, 1.5e-6, 8)
+    lam, nrm, w = friction.lag([plate], [plate], x_t, area, dhat, kappa)
+    phi, g, _ = contact.sdf(plate, x_t)
+    assert np.allclose(np.linalg.norm(nrm[0], axis=1), 1.0, atol=1e-12)
+    assert (np.linalg.norm(g, axis=1) < 1 - 1e-3).any()             # not a distance
+    _, gb, _ = contact.barrier_terms([plate], x_t, area, dhat, kappa)
+    assert np.allclose(lam[0][:, None] * nrm[0], -gb, rtol=1e-12, atol=0)
+    x = x_t + rng.normal(scale=3e-5, size=x_t.shape)
+    E, gf, _ = friction.terms((lam, nrm, w), x, x_t, mu, eps, h2)
+    d = 1e-10
+    for k in range(8):
+        for i in range(3):
+            xp, xm = x.copy(), x.copy()
+            xp[k, i] += d
+            xm[k, i] -= d
+            fd = (friction.terms((lam, nrm, w), xp, x_t, mu, eps, h2)[0]
+                  - friction.terms((lam, nrm, w), xm, x_t, mu, eps, h2)[0]) / (2 * d)
+            assert abs(fd - gf[k, i]) <= 1e-6 * np.abs(gf).max()

@@ -362,11 +362,8 @@ def config3_variant(kind, n_envs=60):
     """config3's pads, materials and start poses with one feature beyond the
     frictionless press switched on for every pad (variant draws from
     SeedSequence(5), one per pad):
-      slide    : pressed to depth over 15 steps, then slid in a seeded
-                 direction, 0.1 mm per step (6 mm/s), the texture plate 0.02
-                 mm per step: its bumps pass under every vertex of the face,
-                 and at 0.1 mm per step each gap would change by 0.6 d_hat
-                 per step (friction off);
+      slide    : pressed to depth over 15 steps, then slid 0.1 mm per step
+                 (6 mm/s) in a seeded direction (friction off);
       friction : the same press-slide with friction ratio 0.5 (Sec. III-B);
       layers   : two layers split at half thickness, the drawn material on
                  top and a base 8x stiffer (nu = 0.42, rho = 1200), the
@@ -383,8 +380,7 @@ def config3_variant(kind, n_envs=60):
     for e in config3(n_envs):
         ang = rng.uniform(0.0, 2.0 * math.pi)
         if kind in ("slide", "friction"):
-            speed = 0.02 * MM if e.indenter.shape == TEXTURE else 0.1 * MM
-            v = speed * np.array([math.cos(ang), math.sin(ang)])
+            v = 0.1 * MM * np.array([math.cos(ang), math.sin(ang)])
             e = dataclasses.replace(e, n_steps=15, slide=v, friction=0.5 if kind == "friction" else 0.0)
         elif kind == "layers":
             m = e.pad.material
@@ -395,6 +391,31 @@ def config3_variant(kind, n_envs=60):
             e = dataclasses.replace(e, indenter=mesh_indenter(e.indenter),
                                     mesh_contact=int(e.indenter.shape == TORUS))
         out.append(e)
+    return out
+
+
+def paper60(n_envs=60):
+    """A stand-in for the paper's own multi-environment run (Sec. IV-A: 60
+    environments of a GelSight Mini pad of about 1,900 tets, d_hat = 1 mm,
+    friction ratio 0.5): 60 copies of config1's 18x14x4 mm pad (1,944 tets,
+    E = 0.3 MPa, nu = 0.45), each under its own indenter drawn from
+    SeedSequence(6) (shape uniform over the five, sphere radius U[2, 8] mm,
+    seeded position on the face), d_hat = 1 mm, friction 0.5, pressed
+    U[0.2, 1.0] mm over 30 steps."""
+    seqs = np.random.SeedSequence(6).spawn(n_envs)
+    out = []
+    for s in seqs:
+        rng = np.random.default_rng(s)
+        pad = box_pad(18 * MM, 14 * MM, 4 * MM, 12, 9, 3, Material(0.3e6, 0.45, 1000.0), name="paper60")
+        params = Params(dhat=1.0 * MM)
+        shape = int(rng.integers(5))
+        r = rng.uniform(2, 8) * MM if shape == SPHERE else None
+        _, _, foot, _ = indenter_geometry(shape, rng, r)
+        margin = 0.5 * foot if np.isfinite(foot) else 0.0
+        xy = seeded_xy(rng, pad, margin)
+        depth = rng.uniform(0.2, 1.0) * MM
+        ind = place_indenter(pad, shape, xy, params.dhat, sphere_radius=r)
+        out.append(Episode(pad, ind, depth, 30, params, friction=0.5))
     return out
 
 
