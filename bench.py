@@ -11,6 +11,7 @@ contact forces and commit, all in one fused set of launches.
     python bench.py --workload serve256 [--rate 2000] [--duration 20]
     python bench.py --workload large1.2m --ablation               # FP32/FP64 CG ablation + extraction
     python bench.py --workload large-refined --ablation           # the same on an adaptively refined pad
+    python bench.py --workload paper60                            # 60 small pads, d_hat 1 mm, friction 0.5
     python bench.py --workload batch60-friction                   # the 60 pads with friction (also
                                                                   # batch60-slide, -layers, -mesh)
 
