@@ -157,3 +157,34 @@ def test_contact_modes_translation_and_torsion():
             assert net < 0.05 * mag.sum()
         gp.close()
     assert abs(torque[0.0]) < 0.01 * torque[MU]
+
+
+def test_texture_plate_friction_regression():
+    """Friction under the texture plate (phi not a distance): one pad of the
+    paper-like 60-environment workload (d_hat = 1 mm, friction 0.5) whose
+    steps once stalled at the Newton cap while the lag's normal was not a
+    unit vector.  Twelve steps against the oracle, step by step, with few
+    Newton iterations each."""
+    e = scenes.paper60()[38]
+    assert e.indenter.shape == scenes.TEXTURE
+    pad = e.pad
+    m = pad.material
+    op = stepper.make_pad(pad.X, pad.tets, m.E, m.nu, m.density)
+    prm = stepper.StepParams(dt=e.params.dt, dhat=e.params.dhat, kappa=e.params.kappa, newton_tol=1e-10,
+                             mu_f=MU, eps_v=EPS_V)
+    gp = tc.Pad(context(), pad.X, pad.tets, dict(E=m.E, nu=m.nu, density=m.density),
+                tc.make_params(precision="mixed", dt=e.params.dt, dhat=e.params.dhat, kappa=e.params.kappa,
+                               newton_tol=1e-7, cg_rel_tol=1e-4, friction=MU, eps_v=EPS_V))
+    worst = 0.0
+    for s in range(1, 13):
+        prev = [e.pose(s - 1)] if s > 1 else None
+        res = stepper.step(op, [e.pose(s)], prm, inds_prev=prev)
+        stepper.commit(op, res)
+        st = gp.step([e.pose(s)])
+        x = gp.read("positions")
+        err = np.abs(x - op.x).max() / max(np.abs(op.x - pad.X).max(), 1e-300)
+        log(f"step {s}: {st} oracle newton {res.newton_iters} err pos {err:.2e}")
+        assert st.status == 0 and st.newton_iters < 40 and res.newton_iters < 40
+        worst = max(worst, err)
+    assert worst < 1e-4, worst
+    gp.close()
