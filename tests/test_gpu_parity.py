@@ -229,3 +229,35 @@ def test_tiny_meshes_match_oracle():
         disp = np.abs(res.x - p.X).max()
         log(which, st, np.abs(x - res.x).max() / disp)
         assert np.abs(x - res.x).max() <= 1e-6 * disp
+
+
+@pytest.mark.parametrize("n", [24, 40])
+def test_high_valence_fan_matches_oracle(n):
+    """A disc pad of n prism sectors: its axis vertices hold about 2n
+    Hessian blocks per row, so the SpMV takes several slots per lane (n =
+    24) or one thread per row (n = 40, more than 64 slots).  A sphere
+    pressed on the axis, FP64 and mixed, against the oracle."""
+    from workloads import meshes
+    X, T = meshes.fan_prisms(n, 6e-3, 2e-3, 2)
+    mat = scenes.Material(0.3e6, 0.45, 1000.0)
+    pad = scenes.Pad("fan", X, T, mat, (12e-3, 12e-3, 2e-3))
+    params = scenes.Params()
+    start = scenes.place_indenter(pad, scenes.SPHERE, (0.0, 0.0), params.dhat, sphere_radius=5e-3)
+    op = stepper.make_pad(X, T, mat.E, mat.nu, mat.density)
+    prm = stepper.StepParams(dt=params.dt, dhat=params.dhat, kappa=params.kappa, newton_tol=1e-10)
+    refs = []
+    for s in range(1, 5):
+        res = stepper.step(op, [start.at_depth(0.08e-3 * s)], prm)
+        stepper.commit(op, res)
+        refs.append(op.x.copy())
+    for prec, ntol, ctol, tol in (("fp64", 1e-9, 1e-9, 1e-6), ("mixed", 1e-7, 1e-4, 1e-4)):
+        gp = gpu_pad(context(), pad, prec, newton_tol=ntol, cg_rel_tol=ctol)
+        assert gp.info["ell_width"] > (64 if n == 40 else 32)
+        worst = 0.0
+        for s, ref in enumerate(refs, start=1):
+            st = gp.step([start.at_depth(0.08e-3 * s)])
+            x = gp.read("positions")
+            worst = max(worst, np.abs(x - ref).max() / max(np.abs(ref - X).max(), 1e-300))
+        log(f"fan n={n} {prec}: ELL width {gp.info['ell_width']}, last {st}, worst pos err {worst:.2e}")
+        assert worst < tol
+        gp.close()

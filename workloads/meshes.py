@@ -161,6 +161,44 @@ def sizing_profile_axis(length, centre, h_f, inner=0.4, band=0.2, ratio=8.0,
     return xs
 
 
+def fan_prisms(n, radius, height, nz):
+    """A disc pad of n triangular prism sectors around its vertical axis,
+    nz layers, each prism split into 3 tets conformingly (each quad face
+    cut by the diagonal through its smallest vertex index, Dompierre et
+    al. 1999).  The axis vertices touch every sector: a row of the assembled
+    Hessian with about 2n blocks.  Returns (X [V,3], tets [T,4])."""
+    th = 2 * np.pi * np.arange(n) / n
+    X = []
+    for k in range(nz + 1):
+        z = height * k / nz
+        X.append([0.0, 0.0, z])
+        X += [[radius * np.cos(t), radius * np.sin(t), z] for t in th]
+    X = np.array(X)
+
+    def vid(k, j):
+        return k * (n + 1) + j
+
+    def split(a, b):
+        m = int(np.argmin(a + b))
+        if m >= 3:
+            a, b, m = b, a, m - 3
+        a, b = a[m:] + a[:m], b[m:] + b[:m]
+        (a0, a1, a2), (b0, b1, b2) = a, b
+        if min(a1, b2) < min(a2, b1):
+            return [[a0, a1, a2, b2], [a0, a1, b2, b1], [a0, b1, b2, b0]]
+        return [[a0, a1, a2, b1], [a0, b1, a2, b2], [a0, b1, b2, b0]]
+    T = []
+    for k in range(nz):
+        for i in range(n):
+            j = (i + 1) % n
+            T += split([vid(k, 0), vid(k, 1 + i), vid(k, 1 + j)], [vid(k + 1, 0), vid(k + 1, 1 + i), vid(k + 1, 1 + j)])
+    T = np.array(T, np.int64)
+    e1, e2, e3 = (X[T[:, c]] - X[T[:, 0]] for c in (1, 2, 3))
+    neg = np.einsum("ij,ij->i", np.cross(e1, e2), e3) < 0
+    T[neg] = T[neg][:, [0, 2, 1, 3]]
+    return X, T.astype(np.int32)
+
+
 # ----------------------------------------------------------------------------
 # closed triangle surfaces for rigid mesh indenters (local frame, outward
 # counter-clockwise triangles, every edge shared by exactly two triangles)
