@@ -161,7 +161,8 @@ def gradient(pad, x, xhat, inds, prm, fric=None):
 
 
 def hessian(pad, x, inds, prm, project=True, fric=None):
-    """Assembled (3V x 3V) sparse Hessian of E."""
+    """Assembled (3V x 3V) sparse Hessian of E; element and barrier parts
+    PSD-projected unless project=False (then the exact Hessian)."""
     h2 = prm.dt ** 2
     V = x.shape[0]
     Ke = fem.elastic_hessian(x, pad.tets, pad.Dminv, pad.vol, pad.mu, pad.lam,
@@ -170,7 +171,8 @@ def hessian(pad, x, inds, prm, project=True, fric=None):
     rows = np.repeat(dof, 12, axis=1).ravel()
     cols = np.tile(dof, (1, 12)).ravel()
     vals = h2 * Ke.ravel()
-    _, _, Hb = contact.barrier_terms(inds, x[pad.cand], pad.area, prm.dhat, prm.kappa, mesh_pairs=prm.mesh_pairs)
+    _, _, Hb = contact.barrier_terms(inds, x[pad.cand], pad.area, prm.dhat, prm.kappa, project=project,
+                                     mesh_pairs=prm.mesh_pairs)
     cd = (3 * pad.cand[:, None] + np.arange(3)[None, :])
     rows = np.concatenate([rows, np.repeat(cd, 3, axis=1).ravel()])
     cols = np.concatenate([cols, np.tile(cd, (1, 3)).ravel()])

@@ -62,3 +62,37 @@ def test_potential_gradient_matches_central_differences(name):
               - stepper.energy(op, x - h * v, xhat, [now], prm, fric=fric)) / (2 * h)
         gv = float(np.sum(g * v))
         assert fd == pytest.approx(gv, rel=2e-5, abs=1e-9 * np.abs(g).sum()), (name, fd, gv)
+
+
+
+@pytest.mark.parametrize("name", ["sphere", "cylinder", "cube_edge", "torus", "texture", "icosphere_mesh",
+                                  "torus_mesh_pairs"])
+def test_exact_hessian_matches_gradient_differences(name):
+    """The unprojected Hessian (elastic, barrier, friction, inertia) against
+    central differences of the gradient along random directions, same
+    states as above."""
+    ep = scenes.config1()
+    pad = ep.pad
+    m = pad.material
+    op = stepper.make_pad(pad.X, pad.tets, m.E, m.nu, m.density)
+    dhat = ep.params.dhat
+    ind, pairs = _indenters(pad, dhat)[name]
+    prm = stepper.StepParams(dt=ep.params.dt, dhat=dhat, kappa=ep.params.kappa, mu_f=0.5, eps_v=0.01,
+                             mesh_pairs=pairs)
+    now = ind.at_depth(0.6 * dhat)
+    prev = scenes.Indenter(now.shape, now.prm, now.R, now.c + np.array([0.05 * MM, -0.03 * MM, 0.02 * MM]), now.mesh)
+    fric = stepper.friction_lag(op, [now], prm, [prev])
+    rng = np.random.default_rng(12)
+    x = op.x + 2e-6 * rng.standard_normal(op.x.shape) * op.free
+    xhat = op.x.copy()
+    H = stepper.hessian(op, x, [now], prm, project=False, fric=fric)
+    for _ in range(4):
+        v = rng.standard_normal(x.shape) * op.free
+        v[op.cand] *= 10.0
+        v /= np.abs(v).max()
+        h = 1e-10
+        gp = stepper.gradient(op, x + h * v, xhat, [now], prm, fric=fric).ravel()
+        gm = stepper.gradient(op, x - h * v, xhat, [now], prm, fric=fric).ravel()
+        fd = (gp - gm) / (2 * h)
+        Hv = H @ v.ravel()
+        assert np.abs(fd - Hv).max() <= 2e-4 * np.abs(Hv).max(), (name, np.abs(fd - Hv).max() / np.abs(Hv).max())
