@@ -100,7 +100,8 @@ typedef int32_t tc_status;
 #define TC_F_TRI_NORMAL       8  /* real [S][3] current unit normal */
 #define TC_F_CONTACT_FORCE    9  /* f64 [C][3] f_k = -dE_b/dx_k */
 #define TC_F_CONTACT_NORMAL  10  /* f64 [C][3] area-weighted vertex normal */
-#define TC_F_CONTACT_AREA    11  /* f64 [C] 1/3 of incident contact-face area */
+#define TC_F_CONTACT_AREA    11  /* f64 [C] 1/3 of incident contact-face area
+                                     (side-face vertices: of incident surface area) */
 #define TC_F_CONTACT_FN      12  /* f64 [C][3] (f . n) n */
 #define TC_F_CONTACT_FT      13  /* f64 [C][3] f - f_n */
 #define TC_F_CONTACT_PRESSURE 14 /* f64 [C] |f| / A */
@@ -278,7 +279,8 @@ tc_status tc_validate_indenters(int32_t n, const tc_indenter* ind);
  * one tet, outward winding, ascending (tet, local face) order), their parent
  * tets, the contact-face label (rest outward normal >= 0.5 along the thinnest
  * bounding-box axis, on the side away from the base) and the contact vertices
- * (vertices of contact-face triangles with a free component, ascending).
+ * (every surface vertex with a free component, side faces included,
+ * ascending; Sec. III-B puts the IPC barrier on the whole pad surface).
  * Two-call pattern: with tris == NULL only the counts are written.  Capacity
  * arguments are element counts of the caller's arrays (host only). */
 tc_status tc_mesh_surface(const tc_mesh* mesh,
@@ -294,6 +296,9 @@ tc_status tc_mesh_surface(const tc_mesh* mesh,
  * beyond the device. */
 tc_status tc_context_create(int32_t device, void* hip_stream, uint64_t hbm_budget,
                             tc_context** out);
+/* Destroys the context.  Its pads and servers hold pointers into it, so they
+ * must be destroyed first: while any remains the call returns TC_E_BUSY and
+ * changes nothing. */
 tc_status tc_context_destroy(tc_context* ctx);
 /* Bytes currently held (resident + scratch pool) and the budget. */
 tc_status tc_context_memory(const tc_context* ctx, uint64_t* used, uint64_t* budget);

@@ -5,8 +5,8 @@ the energy).  Alg. 1: per surface triangle j, from current vertex positions,
 n_j = e1 x e2 / |e1 x e2|, sigma of the parent tet, t_j = sigma n_j (Eq. 6/7),
 p_n = t . n (Eq. 8, positive = tension), t_tau = t - p_n n (Eq. 9).
 Alg. 2 "Contact": f_k = -(contact gradient) / dt^2, i.e. -dE_b/dx_k; vertex
-normal and area from the incident contact-surface triangles (current
-positions);
+normal and area from the incident contact-face triangles, or for a vertex of
+the side faces only from its incident surface triangles (current positions);
 f_n = (f . n) n, f_tau = f - f_n, p_k = |f_k| / A_k; the indenter reaction is
 -sum_k f_k.
 """
@@ -45,9 +45,7 @@ def contact_forces(pad, x, inds, prm, fric=None):
     if fric is not None:
         lagged, x_t_c = fric
         f = f - friction.terms(lagged, x[pad.cand], x_t_c, prm.mu_f, prm.eps_v * prm.dt, 1.0)[1]
-    face = pad.tris[pad.is_top.astype(bool)]
-    n = surface.vertex_normals(x, face, pad.cand)
-    A = surface.vertex_areas(x, face, pad.cand)
+    n, A = surface.contact_vertex_geometry(x, pad.tris, pad.is_top, pad.cand)
     fn = np.einsum("ki,ki->k", f, n)[:, None] * n
     ft = f - fn
     p = np.linalg.norm(f, axis=1) / A

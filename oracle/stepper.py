@@ -67,7 +67,7 @@ class OraclePad:
     parent: np.ndarray
     is_top: np.ndarray
     cand: np.ndarray
-    area: np.ndarray        # rest contact-face areas of the candidates
+    area: np.ndarray        # rest areas of the candidates (surface.contact_vertex_geometry)
     L_diag: float
     free: np.ndarray        # [V,3] bool
     x: np.ndarray           # committed state
@@ -88,8 +88,8 @@ def make_pad(X, tets, E, nu, density, fixed=None, literal_alpha=False):
     fixed = surface.default_fixed(X) if fixed is None else np.asarray(fixed, np.uint8)
     tris, parent = surface.surface_triangles(tets)
     is_top = surface.contact_face_labels(X, tris)
-    cand = surface.candidates(tris, is_top, fixed, X.shape[0])
-    area = surface.vertex_areas(X, tris[is_top.astype(bool)], cand)
+    cand = surface.candidates(tris, fixed, X.shape[0])
+    area = surface.contact_vertex_geometry(X, tris, is_top, cand)[1]
     L = float(np.linalg.norm(X.max(axis=0) - X.min(axis=0)))
     free = np.stack([(fixed >> b) & 1 == 0 for b in range(3)], axis=1)
     return OraclePad(X, tets, mu, lam, alpha, density, Dminv, vol, mass, fixed,

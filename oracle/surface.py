@@ -67,11 +67,14 @@ def contact_face_labels(X, tris):
     return (n[:, a] >= 0.5).astype(np.uint8)
 
 
-def candidates(tris, is_top, fixed, n_verts):
-    """Contact vertices of Alg. 2 / barrier candidates: every vertex of a
-    contact-surface triangle with at least one free component, ascending id."""
+def candidates(tris, fixed, n_verts):
+    """Contact vertices of Alg. 2 and barrier candidates (Sec. III-B runs the
+    IPC barrier over the pad's surface): every vertex of a surface triangle
+    with at least one free component, ascending id.  Vertices of the side
+    faces are included, so an indenter that reaches past the contact face
+    still meets a barrier."""
     on_face = np.zeros(n_verts, dtype=bool)
-    on_face[np.asarray(tris)[np.asarray(is_top).astype(bool)].ravel()] = True
+    on_face[np.asarray(tris).ravel()] = True
     return np.nonzero(on_face & (np.asarray(fixed) != 7))[0].astype(np.int32)
 
 
@@ -86,7 +89,7 @@ def vertex_areas(P, tris, verts):
 
 def vertex_normals(P, tris, verts):
     """Area-weighted unit normal at each vertex: normalised sum of the given
-    incident triangles' e1 x e2 (Alg. 2 contact-vertex normal)."""
+    incident triangles' e1 x e2, whose length is twice the triangle's area."""
     v0, v1, v2 = P[tris[:, 0]], P[tris[:, 1]], P[tris[:, 2]]
     c = np.cross(v1 - v0, v2 - v0)
     acc = np.zeros_like(P)
@@ -94,6 +97,34 @@ def vertex_normals(P, tris, verts):
         np.add.at(acc, tris[:, k], c)
     n = acc[verts]
     return n / np.linalg.norm(n, axis=1)[:, None]
+
+
+def contact_vertex_tris(tris, is_top, verts, n_verts):
+    """The triangles whose share a contact vertex takes (its barrier weight
+    at rest, and Alg. 2's vertex normal and area): the incident
+    contact-face triangles for a vertex on the contact face, else all its
+    incident surface triangles (a vertex of the side faces only).  Returns a
+    boolean mask [len(verts)] of the vertices on the contact face."""
+    top = np.asarray(is_top).astype(bool)
+    on_top = np.zeros(n_verts, dtype=bool)
+    on_top[np.asarray(tris)[top].ravel()] = True
+    return on_top[verts]
+
+
+def contact_vertex_geometry(P, tris, is_top, verts):
+    """Unit normal and area of each contact vertex from the triangles
+    `contact_vertex_tris` gives it (positions P)."""
+    tris = np.asarray(tris)
+    top = np.asarray(is_top).astype(bool)
+    sel = contact_vertex_tris(tris, is_top, verts, P.shape[0])
+    A = vertex_areas(P, tris, verts)
+    n = np.zeros((len(verts), 3))
+    if (~sel).any():
+        n[~sel] = vertex_normals(P, tris, verts[~sel])
+    if sel.any():
+        A[sel] = vertex_areas(P, tris[top], verts[sel])
+        n[sel] = vertex_normals(P, tris[top], verts[sel])
+    return n, A
 
 
 def lumped_mass(X, tets, density):

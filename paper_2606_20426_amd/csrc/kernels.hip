@@ -737,8 +737,9 @@ __global__ void k_setup_mass(const Tile* tiles, int ntiles, const EnvDesc* envs,
   mass_out[i] = m;
 }
 
-// Per contact vertex: rest barrier weight A_k = 1/3 sum of incident
-// contact-face triangle areas.
+// Per contact vertex: rest barrier weight A_k = 1/3 sum of the areas of its
+// triangles (incident contact-face triangles; a side-face vertex: all its
+// incident surface triangles).
 __global__ void k_setup_cand_area(const Tile* tiles, int ntiles, const EnvDesc* envs, double* area_out) {
   const int t = xcd_tile(ntiles);
   if (t < 0) return;
@@ -2269,8 +2270,8 @@ __global__ void k_traction(const Tile* tiles, int ntiles, const EnvDesc* envs) {
 
 // Alg. 2 contact path per contact vertex: f = -dE_b/dx (plus the friction
 // force after a step with friction on; float64), vertex
-// normal = normalised sum of incident contact-face e1 x e2, A = 1/3 incident
-// area, f_n = (f.n) n, f_tau = f - f_n, p = |f| / A; partial sum of f.
+// normal = normalised sum of e1 x e2 over the vertex's triangles (contact
+// face, else its side faces), A = 1/3 their area, f_n = (f.n) n, f_tau = f - f_n, p = |f| / A; partial sum of f.
 __global__ void k_contact(const Tile* tiles, int ntiles, const EnvDesc* envs) {
   __shared__ double sh[16];
   const int t = xcd_tile(ntiles);

@@ -99,6 +99,7 @@ struct tc_context {
   int next_pad_id = 1;
   std::vector<tc_pad*> pads;         // every live pad of the context
   std::atomic<int64_t> evictions{0}; // step scratch released to make room
+  std::atomic<int> n_servers{0};     // live servers of the context
   // rigid meshes (TC_MESH indenters): device table [MAX_MESHES], zeroed
   // slots are free; each live slot owns one device allocation
   tc::DevMesh* d_meshes = nullptr;
@@ -128,7 +129,7 @@ struct tc_pad {
   // indenter poses of the last completed step (friction lag), n_prev = 0: none
   int n_prev = 0;
   tc_indenter prev[TC_MAX_INDENTERS];
-  uint64_t desc_version = 0;         // bumped whenever the device descriptor changes
+  uint64_t desc_version = 0;         // new (process-unique) value whenever the descriptor changes
   std::atomic<int> busy{0};
   std::atomic<int> in_flight{0};     // a step of this pad is on the device (server slot)
   // resident device arrays (one allocation each, tracked for free)
@@ -176,6 +177,7 @@ tc_status run_batch(tc_context* ctx, int n, tc_pad* const* pads, const int32_t* 
 
 tc_status newton_direction(tc_pad* pad, int n_ind, const tc_indenter* ind, double* dir, double* grad);
 tc_status ensure_scratch(tc_pad* pad);
+uint64_t next_desc_version();
 // The same, making room within the context budget when it is short: step
 // scratch of pads not in `keep` and not in flight is released (largest
 // first), then arena chunks left entirely free go back to the device.

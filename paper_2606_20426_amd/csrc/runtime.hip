@@ -102,12 +102,22 @@ size_t Arena::held() const {
 }
 
 BatchPlan::~BatchPlan() {
-  if (d_ctiles) (void)hipFree(d_ctiles);
-  if (h_ctiles) (void)hipHostFree(h_ctiles);
+  // the graph's kernel nodes hold the tile and descriptor pointers below:
+  // the executable graph goes first
   if (cg_exec) (void)hipGraphExecDestroy(cg_exec);
   if (cg_graph) (void)hipGraphDestroy(cg_graph);
+  if (d_ctiles) (void)hipFree(d_ctiles);
+  if (h_ctiles) (void)hipHostFree(h_ctiles);
   if (d_desc) (void)hipFree(d_desc);
   if (d_tiles) (void)hipFree(d_tiles);
+}
+
+// Descriptor versions are unique across all pads of the process: a plan
+// built for a pad that was destroyed can never match a later pad that
+// happens to reuse its address and scratch.
+uint64_t next_desc_version() {
+  static std::atomic<uint64_t> counter{0};
+  return counter.fetch_add(1, std::memory_order_relaxed) + 1;
 }
 
 }  // namespace tc
@@ -331,7 +341,7 @@ static void bind_scratch_desc(tc_pad* p) {
   const ScratchLayout L = scratch_layout(p);
   // plans copy the descriptor: a rebinding (even at the same address, with
   // another layout) invalidates them
-  p->desc_version++;
+  p->desc_version = next_desc_version();
   char* b = static_cast<char*>(p->scratch);
   EnvDesc& E = p->desc;
   E.Ke = b + L.Ke;
@@ -1099,6 +1109,11 @@ tc_status tc_context_destroy(tc_context* ctx) {
   if (!ctx) return TC_OK;
   {
     std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    // pads and servers keep a pointer to the context and lock its mutex
+    // when they are destroyed: they must go first
+    if (!ctx->pads.empty() || ctx->n_servers.load() > 0)
+      return set_error(TC_E_BUSY, "context still has " + std::to_string(ctx->pads.size()) + " pads and " +
+                                      std::to_string(ctx->n_servers.load()) + " servers");
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     ctx->plan.reset();
@@ -1473,7 +1488,7 @@ tc_status tc_pad_set_params(tc_pad* pad, const tc_params* params) {
   E.max_newton = params->max_newton;
   E.max_halvings = params->max_halvings;
   E.precond = params->precond;
-  pad->desc_version++;
+  pad->desc_version = next_desc_version();
   pad->ctx->plan.reset();
   return TC_OK;
 }

@@ -220,6 +220,7 @@ tc_status tc_server_create(tc_context* ctx, int32_t max_slots, tc_server** out) 
     hipError_t e = hipMemcpy(s->pool.d_state, s->pool.h_state, sizeof(EnvState) * s->pool.cap, hipMemcpyHostToDevice);
     if (e != hipSuccess) { pool_free(s->pool); delete s; return hip_fail(e, "server state upload"); }
   }
+  ctx->n_servers++;
   s->th = std::thread([s] { s->loop(); });
   *out = s;
   return TC_OK;
@@ -288,6 +289,7 @@ tc_status tc_server_destroy(tc_server* srv) {
     std::lock_guard<std::recursive_mutex> dl(srv->ctx->mu);
     srv->plan.reset();
     pool_free(srv->pool);
+    srv->ctx->n_servers--;
   }
   delete srv;
   return TC_OK;

@@ -160,7 +160,8 @@ struct EnvDesc {
   const int32_t* tris;       // [S][3]
   const int32_t* parent;     // [S]
   const uint8_t* is_top;     // [S]
-  const int32_t* ctri_ptr;   // [C+1] incident contact-face tris per candidate
+  const int32_t* ctri_ptr;   // [C+1] triangles of each candidate: incident contact-face tris, or
+                             // all incident surface tris for a side-face vertex
   const int32_t* ctri_idx;
   const int32_t* col;        // [V][W] block column of each stored block, -1 = empty
   const int32_t* cptr;       // [V*W+1] contribution ranges per (row, slot)

@@ -198,11 +198,12 @@ void build_surface(const tc_mesh* m, Topology& t) {
     for (int i = 0; i < V; ++i)
       if (X[3 * i + a] <= lo[a] + 1e-9 * ext[a]) t.fixed[i] = 7;
   }
-  // contact vertices: vertices of contact-face triangles with a free component
+  // contact vertices (barrier candidates): every surface vertex with a free
+  // component, side faces included, so that an indenter reaching past the
+  // contact face still meets a barrier
   std::vector<uint8_t> on(V, 0);
   for (int j = 0; j < S; ++j)
-    if (t.is_top[j])
-      for (int c = 0; c < 3; ++c) on[t.tris[3 * j + c]] = 1;
+    for (int c = 0; c < 3; ++c) on[t.tris[3 * j + c]] = 1;
   t.cand.clear();
   t.cand_of_vert.assign(V, -1);
   for (int i = 0; i < V; ++i)
@@ -211,22 +212,30 @@ void build_surface(const tc_mesh* m, Topology& t) {
       t.cand.push_back(i);
     }
   const int C = (int)t.cand.size();
-  t.ctri_ptr.assign(C + 1, 0);
+  // triangles whose share each contact vertex takes (rest barrier weight,
+  // Alg. 2 normal and area): its incident contact-face triangles when it
+  // lies on the contact face, else all its incident surface triangles
+  std::vector<uint8_t> on_top(V, 0);
   for (int j = 0; j < S; ++j)
     if (t.is_top[j])
-      for (int c = 0; c < 3; ++c) {
-        const int k = t.cand_of_vert[t.tris[3 * j + c]];
-        if (k >= 0) t.ctri_ptr[k + 1]++;
-      }
+      for (int c = 0; c < 3; ++c) on_top[t.tris[3 * j + c]] = 1;
+  auto takes = [&](int j, int vtx) { return t.is_top[j] || !on_top[vtx]; };
+  t.ctri_ptr.assign(C + 1, 0);
+  for (int j = 0; j < S; ++j)
+    for (int c = 0; c < 3; ++c) {
+      const int v = t.tris[3 * j + c];
+      const int k = t.cand_of_vert[v];
+      if (k >= 0 && takes(j, v)) t.ctri_ptr[k + 1]++;
+    }
   for (int k = 0; k < C; ++k) t.ctri_ptr[k + 1] += t.ctri_ptr[k];
   t.ctri_idx.assign(t.ctri_ptr[C], 0);
   std::vector<int32_t> fill(t.ctri_ptr.begin(), t.ctri_ptr.end() - 1);
   for (int j = 0; j < S; ++j)
-    if (t.is_top[j])
-      for (int c = 0; c < 3; ++c) {
-        const int k = t.cand_of_vert[t.tris[3 * j + c]];
-        if (k >= 0) t.ctri_idx[fill[k]++] = j;
-      }
+    for (int c = 0; c < 3; ++c) {
+      const int v = t.tris[3 * j + c];
+      const int k = t.cand_of_vert[v];
+      if (k >= 0 && takes(j, v)) t.ctri_idx[fill[k]++] = j;
+    }
 }
 
 void build_sparsity(const tc_mesh* m, Topology& t) {

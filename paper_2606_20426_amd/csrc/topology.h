@@ -21,7 +21,7 @@ struct Topology {
   std::vector<uint8_t> fixed;     // [V]
   std::vector<int32_t> cand;      // [C] ascending
   std::vector<int32_t> cand_of_vert;  // [V]
-  std::vector<int32_t> ctri_ptr;  // [C+1] incident contact-face triangles
+  std::vector<int32_t> ctri_ptr;  // [C+1] triangles of each contact vertex (contact face first)
   std::vector<int32_t> ctri_idx;
   // assembled Hessian: W stored 3x3 blocks per vertex row, slot 0 = diagonal,
   // then neighbours ascending; col[i * W + s] = -1 past the row's end

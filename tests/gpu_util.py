@@ -12,7 +12,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 import paper_2606_20426_amd as tc  # noqa: E402
-from oracle import extract, stepper  # noqa: E402
+from oracle import contact, extract, stepper, surface  # noqa: E402
 
 
 def log(*a):
@@ -80,3 +80,26 @@ def errors(gp, ref, X, top):
         np.linalg.norm(ref["sigma"], axis=(1, 2)).max(), 1e-300)
     e_pn = np.abs(pn[top] - ref["pn"][top]).max() / max(np.abs(ref["pn"][top]).max(), 1e-300)
     return e_pos, e_sig, e_pn
+
+
+def free_surface_vertices(tets, fixed):
+    """Vertices of surface triangles with a free component (side faces
+    included): the set the barrier must keep outside every indenter."""
+    tris, _ = surface.surface_triangles(tets)
+    verts = np.unique(tris)
+    return verts[np.asarray(fixed)[verts] != 7]
+
+
+def surface_gap(verts, x, inds):
+    """Smallest signed distance from the given vertices at positions x to
+    any indenter (the no-penetration invariant of the step)."""
+    gap = np.inf
+    for ind in inds:
+        for lo in range(0, verts.size, 4096):
+            gap = min(gap, float(contact.sdf(ind, x[verts[lo:lo + 4096]])[0].min()))
+    return gap
+
+
+def min_surface_gap(op, x, inds):
+    """surface_gap over every free surface vertex of an oracle pad."""
+    return surface_gap(free_surface_vertices(op.tets, op.fixed), x, inds)

@@ -47,7 +47,7 @@ def _oracle_surface(X, tets, fixed=None):
     tris, parent = osurf.surface_triangles(tets)
     top = osurf.contact_face_labels(X, tris)
     fixed = osurf.default_fixed(X) if fixed is None else fixed
-    cand = osurf.candidates(tris, top, fixed, X.shape[0])
+    cand = osurf.candidates(tris, fixed, X.shape[0])
     return tris, parent, top, cand
 
 

@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 from gpu_util import context, errors, gpu_pad, log, oracle_pad, outputs, tc
-from oracle import stepper
+from oracle import stepper, surface
 from workloads import scenes
 
 pytestmark = pytest.mark.gpu
@@ -72,11 +72,13 @@ def test_five_indenters_match_oracle(prec, newton_tol, cg_rel_tol, tol):
 
 
 def test_pad_without_contact_vertices():
-    """Every contact-face vertex fixed: no candidates, nothing moves; in a
+    """Every surface vertex fixed: no candidates, nothing moves; in a
     batch with a normal pad the other pad's result is the same as alone."""
     ep = scenes.config1()
     X = ep.pad.X
-    fixed = np.where((X[:, 2] == 0) | (X[:, 2] == X[:, 2].max()), 7, 0).astype(np.uint8)
+    tris, _ = surface.surface_triangles(ep.pad.tets)
+    fixed = np.zeros(X.shape[0], np.uint8)
+    fixed[np.unique(tris)] = 7
     ctx = context()
     held = gpu_pad(ctx, ep.pad, "mixed", fixed=fixed)
     assert held.info["n_candidates"] == 0

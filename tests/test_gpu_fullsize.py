@@ -22,7 +22,8 @@ import pytest
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from gpu_util import context, gpu_pad, log, oracle_pad, tc, voigt_to_mat
+from gpu_util import (context, free_surface_vertices, gpu_pad, log, oracle_pad, surface_gap, tc,
+                      voigt_to_mat)
 from oracle import extract, stepper
 from workloads import scenes
 
@@ -48,7 +49,7 @@ def oracle_direction(op, x_prev, v_prev, x, inds, prm, fric=None):
 
 
 FIELDS = ("positions", "sigma", "traction", "pressure", "tangential", "tri_normal", "contact_force",
-          "reaction")
+          "contact_pressure", "reaction")
 
 
 def snapshot(gp):
@@ -83,16 +84,19 @@ def check_state(out, op, x_prev, v_prev, inds, prm, label, inds_prev=None):
     f = out["contact_force"]
     fscale = max(np.abs(cf_ref["f"]).max(), 1e-300)
     e_f = np.abs(f - cf_ref["f"]).max() / fscale
+    e_p = np.abs(out["contact_pressure"] - cf_ref["p"]).max() / max(np.abs(cf_ref["p"]).max(), 1e-300)
     reaction = out["reaction"]
     e_r = np.abs(reaction + f.sum(axis=0)).max() / max(np.abs(reaction).max(), 1e-300)
+    gap = surface_gap(free_surface_vertices(op.tets, op.fixed), x, inds)
     n = out["tri_normal"].astype(np.float64)
     orth = np.abs(np.einsum("si,si->s", tt, n)).max() / max(np.abs(t).max(), floor)
     log(f"{label}: oracle |p|inf / tol {p_inf / tol:.3f}, sigma {e_sig:.2e}, traction {e_t:.2e}, "
-        f"pressure {e_pn:.2e}, contact force {e_f:.2e}, reaction {e_r:.1e}, t_tau.n {orth:.1e}, "
-        f"|reaction| {np.linalg.norm(reaction):.4e} N")
+        f"pressure {e_pn:.2e}, contact force {e_f:.2e}, contact pressure {e_p:.2e}, reaction {e_r:.1e}, "
+        f"t_tau.n {orth:.1e}, |reaction| {np.linalg.norm(reaction):.4e} N, min surface gap {gap:.3e} m")
     assert p_inf <= KKT_FACTOR * tol, label
     assert e_sig <= SIGMA_TOL and e_t <= SIGMA_TOL and e_pn <= SIGMA_TOL, label
-    assert e_f <= FORCE_TOL and e_r <= 1e-12 and orth <= 1e-5, label
+    assert e_f <= FORCE_TOL and e_p <= FORCE_TOL and e_r <= 1e-12 and orth <= 1e-5, label
+    assert gap > 0, label
 
 
 @pytest.mark.parametrize("i", range(5), ids=["sphere", "cylinder", "cube_edge", "torus", "texture"])
@@ -104,6 +108,7 @@ def test_graded_pad_episode(i):
     op = oracle_pad(pad)
     prm = stepper.StepParams(dt=ep.params.dt, dhat=ep.params.dhat, kappa=ep.params.kappa,
                              newton_tol=ep.params.newton_tol)
+    free_v = free_surface_vertices(pad.tets, op.fixed)
     t0 = time.perf_counter()
     newton = []
     for s in range(1, ep.n_steps + 1):
@@ -111,6 +116,8 @@ def test_graded_pad_episode(i):
             x_prev, v_prev = gp.read("positions"), gp.read("velocities")
         st = gp.step([ep.pose(s)])
         newton.append(st.newton_iters)
+        gap = surface_gap(free_v, gp.read("positions"), [ep.pose(s)])
+        assert gap > 0, (s, gap)
         if s in (15, ep.n_steps):
             check_state(snapshot(gp), op, x_prev, v_prev, [ep.pose(s)], prm,
                         f"graded {ep.indenter.shape} step {s}")
@@ -150,16 +157,21 @@ def batch60_run():
     for s, ks in BATCH_CHECKS:
         want.setdefault(s, set()).update(ks)
     saved = {}
+    free_v = [free_surface_vertices(e.pad.tets, pads[k].read("fixed")) for k, e in enumerate(envs)]
     t0 = time.perf_counter()
-    newton = []
+    newton, gaps = [], []
     for s in range(1, 34):
         prev = {k: (pads[k].read("positions"), pads[k].read("velocities")) for k in want.get(s, ())}
         st = tc.step_batch(ctx, pads, [[e.pose(s)] for e in envs])
         assert all(x.status == 0 for x in st)
         newton.append(max(x.newton_iters for x in st))
+        gaps.append(min(surface_gap(free_v[k], pads[k].read("positions"), [e.pose(s)])
+                        for k, e in enumerate(envs)))
+        assert gaps[-1] > 0, (s, gaps[-1])
         for k in want.get(s, ()):
             saved[(s, k)] = (prev[k][0], prev[k][1], snapshot(pads[k]))
-    log(f"batch60: 33 steps in {time.perf_counter() - t0:.1f} s, newton max per step {newton}")
+    log(f"batch60: 33 steps in {time.perf_counter() - t0:.1f} s, newton max per step {newton}, "
+        f"smallest free-surface gap {min(gaps):.3e} m")
     for p in pads:
         p.close()
     ctx.close()
@@ -182,7 +194,8 @@ def test_batch60_bench_configuration(batch60_run, step, ks):
 # pads checked per variant at the last step: every indenter shape the
 # variant changes (pads 0-5 carry cube, sphere, sphere, cylinder, torus,
 # texture) on all three pad shapes
-VARIANT_CHECKS = {"friction": (0, 3, 5), "layers": (1, 4, 5), "mesh": (0, 1, 3, 4), "paper60": (0, 1, 2, 3, 4)}
+VARIANT_CHECKS = {"friction": (0, 3, 5), "slide": (0, 3, 5), "layers": (1, 4, 5), "mesh": (0, 1, 3, 4),
+                  "paper60": (0, 1, 2, 3, 4)}
 
 
 @pytest.fixture(scope="module", params=sorted(VARIANT_CHECKS))
@@ -227,7 +240,8 @@ def _run_variant(kind, envs, ctx, kw, ids, pads):
             return [ind]
         return [dict(shape=tc.MESH, prm=ind.prm, R=ind.R, c=ind.c, mesh_id=ids[id(ind.mesh)])]
 
-    last, saved, newton = 33, {}, []
+    last, saved, newton, gaps = 33, {}, [], []
+    free_v = [free_surface_vertices(e.pad.tets, pads[k].read("fixed")) for k, e in enumerate(envs)]
     t0 = time.perf_counter()
     for s in range(1, last + 1):
         prev = {k: (pads[k].read("positions"), pads[k].read("velocities")) for k in VARIANT_CHECKS[kind]} \
@@ -235,9 +249,13 @@ def _run_variant(kind, envs, ctx, kw, ids, pads):
         st = tc.step_batch(ctx, pads, [poses(e, s) for e in envs], raise_on_error=False)
         assert all(x.status == 0 for x in st), (s, [(k, x) for k, x in enumerate(st) if x.status])
         newton.append(max(x.newton_iters for x in st))
+        gaps.append(min(surface_gap(free_v[k], pads[k].read("positions"), [e.pose(s)])
+                        for k, e in enumerate(envs)))
+        assert gaps[-1] > 0, (s, gaps[-1])
         for k in prev:
             saved[k] = (prev[k][0], prev[k][1], snapshot(pads[k]))
-    log(f"batch60-{kind}: {last} steps in {time.perf_counter() - t0:.1f} s, newton max per step {newton}")
+    log(f"batch60-{kind}: {last} steps in {time.perf_counter() - t0:.1f} s, newton max per step {newton}, "
+        f"smallest free-surface gap {min(gaps):.3e} m")
     return kind, envs, last, saved
 
 

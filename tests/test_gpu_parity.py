@@ -3,7 +3,8 @@
 import numpy as np
 import pytest
 
-from gpu_util import context, errors, gpu_pad, log, oracle_episode, oracle_pad, outputs, tc, voigt_to_mat
+from gpu_util import (context, errors, gpu_pad, log, min_surface_gap, oracle_episode, oracle_pad, outputs, tc,
+                      voigt_to_mat)
 from oracle import contact, extract, material, stepper, surface
 from workloads import scenes
 
@@ -25,7 +26,7 @@ def test_setup_matches_oracle(prec):
     assert np.allclose(gp.read("mass"), op.mass, rtol=1e-13, atol=0)
     assert np.allclose(gp.read("cand_rest_area"), op.area, rtol=1e-13, atol=0)
     assert np.array_equal(gp.read("positions"), ep.pad.X)
-    assert gp.info["n_surface_tris"] == 684 and gp.info["n_candidates"] == 130
+    assert gp.info["n_surface_tris"] == 684 and gp.info["n_candidates"] == 214
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-11), ("mixed", 2e-5)])
@@ -67,7 +68,7 @@ def test_extraction_on_prescribed_positions(prec, tol):
         # contact path (float64 on both sides)
         cf = ref["cf"]
         for f, key in (("contact_force", "f"), ("contact_normal", "n"), ("contact_area", "area"),
-                       ("contact_fn", "f_n"), ("contact_ft", "f_tau")):
+                       ("contact_fn", "f_n"), ("contact_ft", "f_tau"), ("contact_pressure", "p")):
             g = gp.read(f)
             s = max(np.abs(cf[key]).max(), 1e-300)
             assert np.abs(g - cf[key]).max() / s < 1e-9, f
@@ -91,10 +92,15 @@ def _episode(prec, steps, newton_tol, cg_rel_tol):
         eR = np.abs(R - Rref).max() / max(np.abs(Rref).max(), 1e-12)
         ts = gp.read("traction_sum")
         eT = np.abs(ts - refs[s - 1]["tsum"]).max() / max(np.abs(refs[s - 1]["tsum"]).max(), 1e-12)
+        cf = refs[s - 1]["cf"]
+        eP = np.abs(gp.read("contact_pressure") - cf["p"]).max() / max(np.abs(cf["p"]).max(), 1e-300)
+        gap = min_surface_gap(op, gp.read("positions"), [ep.pose(s)])
         log(f"{prec} step {s}: {st} oracle newton {refs[s - 1]['newton']} "
-            f"err pos {e[0]:.2e} sigma {e[1]:.2e} p_n {e[2]:.2e} reaction {eR:.2e} tsum {eT:.2e}")
+            f"err pos {e[0]:.2e} sigma {e[1]:.2e} p_n {e[2]:.2e} reaction {eR:.2e} tsum {eT:.2e} "
+            f"p_k {eP:.2e} min gap {gap:.3e}")
         worst = np.maximum(worst, e)
-        assert eR < 1e-3 and eT < 1e-3
+        assert eR < 1e-3 and eT < 1e-3 and eP < 1e-3
+        assert gap > 0
     return worst
 
 

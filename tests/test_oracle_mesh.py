@@ -51,10 +51,11 @@ def test_config_sizes():
     assert surface.contact_face_labels(e1.pad.X, tris).sum() == 216
     assert np.unique(tris).size == 344
     fixed = surface.default_fixed(e1.pad.X)
-    top = surface.contact_face_labels(e1.pad.X, tris)
-    cand = surface.candidates(tris, top, fixed, 520)
-    assert cand.size == 13 * 10                        # the top-face vertices
+    cand = surface.candidates(tris, fixed, 520)
     assert (fixed == 7).sum() == 13 * 10               # the base
+    assert cand.size == 344 - 13 * 10                  # every other surface vertex
+    top_v = np.unique(tris[surface.contact_face_labels(e1.pad.X, tris).astype(bool)])
+    assert np.isin(top_v, cand).all() and top_v.size == 13 * 10
     p2 = scenes.config2_pad()
     assert p2.tets.shape[0] == 122850 and p2.X.shape[0] == 23184
     zs = np.unique(p2.X[:, 2])
