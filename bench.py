@@ -107,38 +107,94 @@ def copy_probe(mib):
     del a, b
 
 
-def cpu_baseline(envs, budget_s=20.0):
-    """The FP64 oracle as it stands on a bounded sample: steps of the
-    smallest pad of the workload, single thread."""
-    import numpy as np
+def copy_ceiling(mib=1024, reps=10):
+    """Measured device-to-device copy bandwidth (bytes read + written per
+    second) of a large buffer: the practical HBM ceiling beside the 8 TB/s
+    spec figure."""
+    import torch
+    n = mib * 2**20 // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * n * 4 / (ms * 1e-3) / 1e9
+
+
+def _oracle_sample(job):
+    """One thread of the FP64 oracle stepping a pad from rest until the
+    budget is spent (at least one step).  Returns (steps, seconds, Newton
+    iterations).  Runs in the bench process or in a spawned worker."""
     from threadpoolctl import threadpool_limits
     from oracle import stepper
-    ep = min(envs, key=lambda e: e.pad.tets.shape[0])
-    op = stepper.make_pad(ep.pad.X, ep.pad.tets, ep.pad.material.E, ep.pad.material.nu,
-                          ep.pad.material.density)
-    prm = stepper.StepParams(dt=ep.params.dt, dhat=ep.params.dhat, kappa=ep.params.kappa,
-                             newton_tol=ep.params.newton_tol)
-    done, t0 = 0, time.perf_counter()
+    X, tets, E, nu, rho, prm_kw, poses, budget_s = job
+    op = stepper.make_pad(X, tets, E, nu, rho)
+    prm = stepper.StepParams(**prm_kw)
+    done, newton, t0 = 0, 0, time.perf_counter()
     with threadpool_limits(limits=1):
-        for s in range(1, 100):
-            res = stepper.step(op, [ep.pose(s)], prm)
+        for ind in poses:
+            res = stepper.step(op, [ind], prm)
             stepper.commit(op, res)
             done += 1
+            newton += res.newton_iters
             if time.perf_counter() - t0 > budget_s:
                 break
-    dt = time.perf_counter() - t0
-    # pad-steps/s of the whole mix, scaling the sample's time per step by tet count
-    t_small = ep.pad.tets.shape[0]
-    t_mean = float(np.mean([e.pad.tets.shape[0] for e in envs]))
-    return {"value": done / dt * t_small / t_mean, "unit": "steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {done} steps of the smallest pad of the workload ({t_small} tets), FP64 oracle "
-                      f"with direct sparse solves on 1 thread, {done / dt:.3f} steps/s, scaled by "
-                      f"{t_small}/{t_mean:.0f} tets to the mean pad of the mix"}
+    return done, time.perf_counter() - t0, newton
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(envs, budget_s=15.0, workers=None):
+    """The FP64 oracle as it stands on a bounded sample of the workload: the
+    pad whose tet count is nearest the mix's mean, stepped from rest, on one
+    thread and then on every core (one oracle process per core, each
+    stepping its own copy of the pad; pads are independent).  No
+    extrapolation: the rates are the sample's own pad-steps per second."""
+    import multiprocessing as mp
+    import numpy as np
+    sizes = np.array([e.pad.tets.shape[0] for e in envs])
+    k = int(np.argmin(np.abs(sizes - sizes.mean())))
+    e = envs[k]
+    m = e.pad.material
+    prm_kw = dict(dt=e.params.dt, dhat=e.params.dhat, kappa=e.params.kappa, newton_tol=e.params.newton_tol)
+    job = (e.pad.X, e.pad.tets, m.E, m.nu, m.density, prm_kw, [e.pose(s) for s in range(1, e.n_steps + 1)],
+           budget_s)
+    one = _oracle_sample(job)
+    n = workers or min(os.cpu_count() or 1, 16)
+    with mp.get_context("spawn").Pool(n) as pool:
+        res = pool.map(_oracle_sample, [job] * n)
+    all_rate = sum(d / t for d, t, _ in res)
+    return {"value": round(all_rate, 4), "unit": "steps/s", "cores": n, "kind": "oracle",
+            "single_thread": round(one[0] / one[1], 4),
+            "cpu": cpu_model(), "nproc": os.cpu_count(),
+            "sample": (f"pad {k} of the mix ({sizes[k]} tets, the nearest to the mean {sizes.mean():.0f}; "
+                       f"{e.pad.name}), FP64 oracle with direct sparse solves, stepped from rest: one thread "
+                       f"{one[0]} steps ({one[2]} Newton iterations) in {one[1]:.1f} s; {n} processes of one "
+                       f"thread each, {sum(r[0] for r in res)} steps in all ({sum(r[2] for r in res)} Newton "
+                       f"iterations), rates summed.  The first steps of an episode take fewer Newton "
+                       f"iterations than the timed steps, so this overstates the oracle's rate")}
 
 
 def make_pads(tc, ctx, envs, args, precision=None):
     extra = dict(cg_rel_tol=args.cg_rel_tol, cg_eta_max=args.cg_eta_max, cg_forcing=args.cg_forcing,
-                 hess_proj=args.hess_proj, ls_expand=args.ls_expand)
+                 hess_proj=args.hess_proj, ls_expand=args.ls_expand, cg_conv_tol=args.cg_conv_tol)
     if args.init_guess is not None:
         extra["init_guess"] = args.init_guess
     pads = []
@@ -170,7 +226,7 @@ def poses(e, s):
     return [dict(shape=ind.shape, prm=ind.prm, R=ind.R, c=ind.c, mesh_id=MESH_IDS[id(ind.mesh)])]
 
 
-def roofline(ctx, args):
+def roofline(ctx, args, copy_gbs=None):
     timers = ctx.timing()
     if not timers:
         return None
@@ -185,26 +241,40 @@ def roofline(ctx, args):
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic(args.workload, k) if not args.sequential else None,
             "avg_launch_ms": avg_ms, "launches": launches, "bytes_per_launch": bpl,
-            "timing_stride": args.timing_stride}
+            "timing_stride": args.timing_stride,
+            "copy_ceiling": round(copy_gbs, 1) if copy_gbs else None,
+            "frac_of_copy": round(achieved / copy_gbs, 4) if copy_gbs else None,
+            "kernels": {name: {"avg_ms": round(a, 5), "launches": n, "GB/s": round(b / max(a, 1e-12) / 1e6, 1),
+                               "frac": round(b / max(a, 1e-12) / 1e6 / HBM_PEAK_GBS, 4)}
+                        for name, (a, n, b) in timers.items() if b > 0}}
 
 
 def run_steps(args):
     """Batch (default) or one-pad-at-a-time stepping of a fixed set of pads."""
+    envs, desc = build_workload(args.workload)
+    log(f"workload {args.workload}: {len(envs)} pads, {sum(e.pad.tets.shape[0] for e in envs)} tets")
+    cpu = None
+    if not args.no_cpu_baseline and not args.workload.startswith("batch60-") and args.workload != "paper60":
+        # before anything touches the GPU: the oracle workers are spawned
+        # processes
+        log("timing the oracle on a bounded sample ...")
+        cpu = cpu_baseline(envs)
+        log(f"oracle: {cpu['single_thread']} steps/s on one thread, {cpu['value']} on {cpu['cores']}")
+
     import numpy as np
     import torch
     import paper_2606_20426_amd as tc
 
     if args.copy_probe:
         copy_probe(args.copy_probe)
-    envs, desc = build_workload(args.workload)
-    log(f"workload {args.workload}: {len(envs)} pads, {sum(e.pad.tets.shape[0] for e in envs)} tets")
     ctx = tc.Context(0)
+    copy_gbs = copy_ceiling()
+    log(f"device copy: {copy_gbs:.0f} GB/s (read + write)")
     t0 = time.perf_counter()
     pads = make_pads(tc, ctx, envs, args)
     log(f"pads created in {time.perf_counter() - t0:.1f} s; HBM used {ctx.memory()[0] / 2**30:.2f} GiB")
     ctx.set_launch(cg_block=args.cg_block, elem_block=args.elem_block, spmv_block=args.spmv_block,
                    cg_per_replay=args.cg_per_replay, use_graphs=args.graphs)
-    ctx.set_cg_variant(args.cg_variant)
     if args.autotune:
         chosen = ctx.autotune(pads, [poses(e, 1) for e in envs])
         log(f"autotune: vertex block {chosen[0]}, element block {chosen[1]}, SpMV block {chosen[2]}")
@@ -234,7 +304,7 @@ def run_steps(args):
     total = time.perf_counter() - t_start
     n_env = len(envs)
     value = n_env * args.steps / total
-    roof = roofline(ctx, args) if not args.no_timing else None
+    roof = roofline(ctx, args, copy_gbs) if not args.no_timing else None
     mode = "sequential" if args.sequential else "batched"
     out = {
         "metric": METRIC,
@@ -248,18 +318,45 @@ def run_steps(args):
         "config": {"workload": args.workload, "description": desc, "envs": n_env,
                    "tets": int(sum(e.pad.tets.shape[0] for e in envs)), "mode": mode,
                    "newton_max_mean": float(np.mean(newton)), "cg_iters_mean": float(np.mean(cg)),
-                   "precision": args.precision, "graphs": bool(args.graphs and args.no_timing),
-                   "cg_variant": "pipelined" if args.cg_variant else "classic"},
+                   "precision": args.precision, "graphs": bool(args.graphs and args.no_timing)},
         "roofline": roof,
     }
     if args.workload == "paper60":
         # context only: the paper's own 60-environment aggregate, another
         # machine and solver (RTX 5090, UIPC), Sec. IV-A
         out["config"]["paper_aggregate_steps_per_s"] = 555.0
-    if not args.no_cpu_baseline and not args.workload.startswith("batch60-") and args.workload != "paper60":
-        log("timing the oracle on a bounded sample ...")
-        out["cpu_baseline"] = cpu_baseline(envs)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
+    if args.gpu_baseline and not args.sequential:
+        base = gpu_baseline(tc, ctx, envs, args)
+        out["gpu_baseline"] = base
+        out["vs_single_env_fp64"] = round(value / base["value"], 3)
     return out
+
+
+def gpu_baseline(tc, ctx, envs, args):
+    """The plain single-env FP64 GPU path on the same pads and the same
+    steps: FP64 everywhere, one tc_step per pad, the pads one after another
+    (no batching, no graphs); same solver settings and warm-up."""
+    import torch
+    ctx.set_timing(False)
+    pads = make_pads(tc, ctx, envs, args, precision="fp64")
+    for s in range(1, args.warmup + 1):
+        for p, e in zip(pads, envs):
+            p.step(poses(e, s))
+    torch.cuda.synchronize()
+    newton, t0 = [], time.perf_counter()
+    for s in range(args.warmup + 1, args.warmup + args.steps + 1):
+        newton.append(max(p.step(poses(e, s)).newton_iters for p, e in zip(pads, envs)))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    for p in pads:
+        p.close()
+    value = len(envs) * args.steps / dt
+    log(f"single-env FP64 GPU path: {value:.1f} pad-steps/s ({dt:.1f} s)")
+    return {"value": round(value, 2), "unit": "steps/s", "kind": "single-env fp64 gpu",
+            "ms_per_step": round(dt / args.steps * 1e3, 3), "newton_max_mean": float(sum(newton) / len(newton)),
+            "description": "the same pads and steps, FP64, one tc_step per pad in sequence"}
 
 
 def run_serve(args):
@@ -272,7 +369,6 @@ def run_serve(args):
     envs, desc = build_workload(args.workload)
     n_pads = len(envs)
     ctx = tc.Context(0, hbm_budget=int(args.hbm_budget_gib * 2**30) if args.hbm_budget_gib else 0)
-    ctx.set_cg_variant(args.cg_variant)
     t0 = time.perf_counter()
     pads = make_pads(tc, ctx, envs, args)
     resident = sum(p.info["resident_bytes"] for p in pads)
@@ -351,7 +447,6 @@ def run_ablation(args):
     envs, desc = build_workload(args.workload)
     e = envs[0]
     ctx = tc.Context(0)
-    ctx.set_cg_variant(args.cg_variant)
     res = {}
     steps = min(args.steps, e.n_steps) if args.steps else e.n_steps
     for prec in ("mixed", "fp64"):
@@ -414,12 +509,13 @@ def main():
     ap.add_argument("--ablation", action="store_true", help="mixed vs fp64 episode + extraction timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true")
+    ap.add_argument("--gpu-baseline", type=int, default=1,
+                    help="also time the plain single-env FP64 GPU path on the same steps (batched runs)")
     ap.add_argument("--timing-stride", type=int, default=29,
                     help="time every k-th launch of each kernel (prime: the samples rotate through the positions of a CG chunk)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MiB",
                     help="run 4 device copies of this size first (counter calibration)")
     ap.add_argument("--graphs", type=int, default=0)
-    ap.add_argument("--cg-variant", type=int, default=0, help="0 classic PCG, 1 pipelined PCG")
     ap.add_argument("--cg-per-replay", type=int, default=0,
                     help="CG iterations launched between host checks (even; 0 = library default 16)")
     ap.add_argument("--cg-block", type=int, default=0)
@@ -435,6 +531,8 @@ def main():
     ap.add_argument("--cg-rel-tol", type=float, default=0.2)
     ap.add_argument("--cg-eta-max", type=float, default=0.2)
     ap.add_argument("--cg-forcing", type=int, default=2)
+    ap.add_argument("--cg-conv-tol", type=float, default=0.0,
+                    help="CG tolerance of a direction that decides convergence (0 = the solve tolerance)")
     ap.add_argument("--hess-proj", type=int, default=4)
     ap.add_argument("--ls-expand", type=int, default=4,
                     help="doublings of an accepted full Newton step while the energy keeps falling")

@@ -303,10 +303,12 @@ tc_status tc_context_destroy(tc_context* ctx);
 /* Bytes currently held (resident + scratch pool) and the budget. */
 tc_status tc_context_memory(const tc_context* ctx, uint64_t* used, uint64_t* budget);
 
-/* Per-kernel timing with HIP events on the context stream (for roofline
- * reporting).  enable = 0 off; k >= 1: every k-th launch of each kernel is
- * bracketed by a pair of events (k = 1 times every launch; a larger k keeps
- * the events' own cost out of the run).  tc_context_timing fills, for up to
+/* Per-kernel timing on the context stream (for roofline reporting).
+ * enable = 0 off; k >= 1: every launch of the Newton-level kernels is timed
+ * with a pair of events recorded by its dispatch, and every k-th launch of
+ * the CG kernels (tens of thousands of launches per run) times itself from
+ * its blocks' GPU wall clock (k = 1 times every launch; a larger k keeps the
+ * sampling's own cost out of the run).  tc_context_timing fills, for up to
  * cap kernels, the average duration of the timed launches, the number of
  * launches made while timing was on, and the algorithmic bytes per launch
  * (model of each kernel's compulsory HBM traffic, averaged over all those
@@ -332,17 +334,6 @@ tc_status tc_autotune(tc_context* ctx, int32_t n, tc_pad* const* pads,
  * 0 leaves a value unchanged. */
 tc_status tc_set_launch(tc_context* ctx, int32_t cg_block, int32_t elem_block, int32_t spmv_block,
                         int32_t cg_per_replay, int32_t use_graphs);
-
-/* Linear solver of every pad of the context: 0 (default) classic
- * preconditioned CG, two launches per iteration (product; update) with two
- * global reductions; 1 pipelined preconditioned CG (Ghysels and Vanroose,
- * Parallel Computing 40, 2014): one fused launch per iteration (product,
- * recurrences and both dot products), the same stop test on r . M^-1 r and
- * the same breakdown test on p . Ap, at the cost of five more vectors of step
- * scratch and recurrences for w = A u and A M^-1 s.  Releases the step
- * scratch of every pad (its size changes); TC_E_BUSY while a pad has a
- * request on a server. */
-tc_status tc_set_cg_variant(tc_context* ctx, int32_t variant);
 
 /* ------------------------------------------------------------------- pads */
 /* Copies the mesh and materials into HBM and runs the setup kernels: Eq. 1

@@ -213,10 +213,6 @@ class Context:
     def remove_mesh(self, mesh_id: int):
         check(self.lib.tc_rigid_mesh_destroy(self.h, int(mesh_id)))
 
-    def set_cg_variant(self, variant: int):
-        """0 classic PCG, 1 pipelined PCG (one fused launch per iteration)."""
-        check(self.lib.tc_set_cg_variant(self.h, int(variant)))
-
     def memory(self):
         u, b = C.c_uint64(), C.c_uint64()
         check(self.lib.tc_context_memory(self.h, C.byref(u), C.byref(b)))

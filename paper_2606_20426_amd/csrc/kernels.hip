@@ -1406,11 +1406,7 @@ __device__ __forceinline__ bool cg_decide(const Tile tl, const EnvDesc& E, int p
 // q = A p_new, one thread per matrix row (tiles of blockDim.x rows); the row
 // owner stores p_new.
 template <typename R>
-__device__ __forceinline__ void cg_spmv_rows(const Tile tl, const EnvDesc* envs, int parity, double* sh) {
-  const EnvDesc& E = envs[tl.env];
-  double beta_d;
-  if (!cg_head(tl, E, parity, sh, &beta_d)) return;
-  const R beta = (R)beta_d;
+__device__ __forceinline__ void cg_spmv_rows_body(const Tile tl, const EnvDesc& E, int parity, R beta, double* sh) {
   const int i = tl.tile * blockDim.x + threadIdx.x;
   const R* z = (const R*)E.z;
   const R* pold = (const R*)(parity ? E.p0 : E.p1);
@@ -1448,11 +1444,7 @@ __device__ __forceinline__ void cg_spmv_rows(const Tile tl, const EnvDesc* envs,
 // come after its blocks, so a lane stops at its first one.  A tile is
 // blockDim.x / LPR lane groups x SPMV_ROWS_PER_GROUP rows.
 template <typename R, int LPR>
-__device__ __forceinline__ void cg_spmv_lanes(const Tile tl, const EnvDesc* envs, int parity, double* sh) {
-  const EnvDesc& E = envs[tl.env];
-  double beta_d;
-  if (!cg_head(tl, E, parity, sh, &beta_d)) return;
-  const R beta = (R)beta_d;
+__device__ __forceinline__ void cg_spmv_lanes_body(const Tile tl, const EnvDesc& E, int parity, R beta, double* sh) {
   const int lane = threadIdx.x & (LPR - 1);
   const int groups = blockDim.x / LPR;
   const R* z = (const R*)E.z;
@@ -1510,19 +1502,27 @@ __device__ __forceinline__ void cg_spmv_lanes(const Tile tl, const EnvDesc* envs
   if (threadIdx.x == 0) E.part_pq[tl.tile] = pq;
 }
 
+// The product of one SpMV tile given beta (p_new = z + beta p_old).
+template <typename R, int LPR>
+__device__ __forceinline__ void cg_spmv_body(const Tile tl, const EnvDesc& E, int parity, R beta, double* sh) {
+  if constexpr (LPR == 0) cg_spmv_rows_body<R>(tl, E, parity, beta, sh);
+  else cg_spmv_lanes_body<R, LPR>(tl, E, parity, beta, sh);
+}
+
 template <typename R, int LPR>
 __device__ __forceinline__ void cg_spmv_tile(const Tile tl, const EnvDesc* envs, int parity, double* sh) {
-  if constexpr (LPR == 0) cg_spmv_rows<R>(tl, envs, parity, sh);
-  else cg_spmv_lanes<R, LPR>(tl, envs, parity, sh);
+  const EnvDesc& E = envs[tl.env];
+  double beta;
+  if (!cg_head(tl, E, parity, sh, &beta)) return;
+  cg_spmv_body<R, LPR>(tl, E, parity, (R)beta, sh);
 }
 
 // alpha = r.z / p.Ap; d += alpha p; r -= alpha Ap (float64); z = P^-1 r;
 // partial r.z for the next iteration.
-template <typename R>
-__device__ __forceinline__ void cg_update_tile(const Tile tl, const EnvDesc* envs, int parity, double* sh) {
-  const EnvDesc& E = envs[tl.env];
+// alpha = r.z / p.Ap from the product's partials (a non-positive p.Ap is a
+// breakdown: alpha = 0 and the tile-0 block flags it).
+__device__ __forceinline__ double cg_alpha(const Tile tl, const EnvDesc& E, int parity, double* sh) {
   EnvState* S = E.st;
-  if (!running(S) || S->cg_done) return;
   const double pq = reduce_partials(E.part_pq, E.n_spt, OpSum(), 0.0, sh);
   const double rz = S->rzp[parity];
   double alpha = rz / pq;
@@ -1530,6 +1530,12 @@ __device__ __forceinline__ void cg_update_tile(const Tile tl, const EnvDesc* env
     alpha = 0.0;
     if (tl.tile == 0 && threadIdx.x == 0) S->breakdown = 1;
   }
+  return alpha;
+}
+
+template <typename R>
+__device__ __forceinline__ void cg_update_body(const Tile tl, const EnvDesc& E, int parity, double alpha,
+                                               double* sh) {
   const int i = tl.tile * blockDim.x + threadIdx.x;
   double rzn = 0.0;
   if (i < E.V) {
@@ -1556,206 +1562,12 @@ __device__ __forceinline__ void cg_update_tile(const Tile tl, const EnvDesc* env
   if (threadIdx.x == 0) E.part_rz[tl.tile] = rzn;
 }
 
-// ---- pipelined PCG (Ghysels and Vanroose, Parallel Computing 40, 2014):
-// one global synchronisation per iteration, so one fused launch (product,
-// recurrences and both dot products) instead of two.  With M the block
-// diagonal preconditioner, u = M^-1 r and m = M^-1 w are formed per row from
-// r and w (no recurrence for them), w = A u and zc = A (M^-1 s) by
-// recurrence:
-//   gamma = r.u, delta = w.u (partials of the previous launch);
-//   beta = gamma / gamma_prev, alpha = gamma / (delta - beta gamma / alpha_prev);
-//   n = A m;  zc = n + beta zc;  s = w + beta s;  p = u + beta p;
-//   d += alpha p;  r -= alpha s;  u = M^-1 r;  w -= alpha zc;  m' = M^-1 w.
-// delta - beta gamma / alpha_prev equals p.Ap: a non-positive value is a
-// breakdown as in the classic iteration.
-
 template <typename R>
-__device__ __forceinline__ void pinv_apply(const R* Pi, R a0, R a1, R a2, R o[3]) {
-  o[0] = Pi[0] * a0 + Pi[1] * a1 + Pi[2] * a2;
-  o[1] = Pi[1] * a0 + Pi[3] * a1 + Pi[4] * a2;
-  o[2] = Pi[2] * a0 + Pi[4] * a1 + Pi[5] * a2;
-}
-
-// Head of a pipelined launch: the stop decision on gamma, then alpha.
-__device__ __forceinline__ bool cg_pipe_head(const Tile tl, const EnvDesc& E, int parity, double* sh,
-                                             double* beta, double* alpha) {
-  if (!cg_go(E)) return false;
-  const double gm = reduce_partials(E.part_gm, E.n_spt, OpSum(), 0.0, sh);
-  const double dl = reduce_partials(E.part_dl, E.n_spt, OpSum(), 0.0, sh);
-  int it;
-  if (!cg_decide(tl, E, parity, gm, beta, &it)) return false;
+__device__ __forceinline__ void cg_update_tile(const Tile tl, const EnvDesc* envs, int parity, double* sh) {
+  const EnvDesc& E = envs[tl.env];
   EnvState* S = E.st;
-  const double den = it == 0 ? dl : dl - *beta * gm / S->alp[parity ^ 1];
-  double a = gm / den;
-  if (!(den > 0.0) || !isfinite(a)) {
-    a = 0.0;
-    if (tl.tile == 0 && threadIdx.x == 0) S->breakdown = 1;
-  }
-  if (tl.tile == 0 && threadIdx.x == 0) S->alp[parity] = a;
-  *alpha = a;
-  return true;
-}
-
-// Per-row part of a pipelined launch (n = (A m)_i already summed).
-template <typename R>
-__device__ __forceinline__ void cg_pipe_row(const EnvDesc& E, int i, R n0, R n1, R n2, R beta, double alpha,
-                                            R* mn, double& gm, double& dl) {
-  R* zc = (R*)E.zc;
-  R* sv = (R*)E.s;
-  R* pp = (R*)E.pp;
-  R* u = (R*)E.z;
-  R* w = (R*)E.w;
-  R* d = (R*)E.d;
-  const R* Pi = (const R*)E.Pinv + 6 * i;
-  const R a = (R)alpha;
-  const R nn[3] = {n0, n1, n2};
-  double rr[3];
-  R wn[3];
-  for (int c = 0; c < 3; ++c) {
-    const int k = 3 * i + c;
-    const R zk = nn[c] + beta * zc[k];
-    const R sk = w[k] + beta * sv[k];
-    const R pk = u[k] + beta * pp[k];
-    zc[k] = zk;
-    sv[k] = sk;
-    pp[k] = pk;
-    d[k] += a * pk;
-    rr[c] = E.r[k] - alpha * (double)sk;
-    E.r[k] = rr[c];
-    wn[c] = w[k] - a * zk;
-    w[k] = wn[c];
-  }
-  R un[3], mv[3];
-  pinv_apply(Pi, (R)rr[0], (R)rr[1], (R)rr[2], un);
-  pinv_apply(Pi, wn[0], wn[1], wn[2], mv);
-  for (int c = 0; c < 3; ++c) {
-    u[3 * i + c] = un[c];
-    mn[3 * i + c] = mv[c];
-    gm += rr[c] * (double)un[c];
-    dl += (double)wn[c] * (double)un[c];
-  }
-}
-
-// y = (A v)_i with LPR lanes per row (lane l takes blocks l, l + LPR, ...),
-// or one thread per row (LPR == 0); returns true in the thread that owns
-// the sum.
-template <typename R, int LPR>
-__device__ __forceinline__ bool row_product(const EnvDesc& E, int i, int lane, const R* v, R& y0, R& y1, R& y2) {
-  y0 = y1 = y2 = 0;
-  if constexpr (LPR == 0) {
-    if (i >= E.V) return false;
-    const R* A = (const R*)E.A;
-    for (int sl = 0; sl < E.W; ++sl) {
-      const size_t item = (size_t)i * E.W + sl;
-      const int j = E.col[item];
-      if (j < 0) break;
-      const R* As = A + item * 9;
-      const R v0 = v[3 * j], v1 = v[3 * j + 1], v2 = v[3 * j + 2];
-      y0 += As[0] * v0 + As[1] * v1 + As[2] * v2;
-      y1 += As[3] * v0 + As[4] * v1 + As[5] * v2;
-      y2 += As[6] * v0 + As[7] * v1 + As[8] * v2;
-    }
-    return true;
-  } else {
-    if (i < E.V) {
-      for (int sl = lane; sl < E.W; sl += LPR) {
-        const size_t item = (size_t)i * E.W + sl;
-        const int j = E.col[item];
-        if (j < 0) break;
-        const R* As = (const R*)E.A + item * 9;
-        const R v0 = v[3 * j], v1 = v[3 * j + 1], v2 = v[3 * j + 2];
-        y0 += As[0] * v0 + As[1] * v1 + As[2] * v2;
-        y1 += As[3] * v0 + As[4] * v1 + As[5] * v2;
-        y2 += As[6] * v0 + As[7] * v1 + As[8] * v2;
-      }
-    }
-#pragma unroll
-    for (int o = LPR / 2; o > 0; o >>= 1) {
-      y0 += __shfl_xor(y0, o, LPR);
-      y1 += __shfl_xor(y1, o, LPR);
-      y2 += __shfl_xor(y2, o, LPR);
-    }
-    return lane == 0 && i < E.V;
-  }
-}
-
-// Rows of an SpMV tile: LPR lanes per row and SPMV_ROWS_PER_GROUP rows per
-// lane group, or blockDim.x rows (LPR == 0).
-template <int LPR>
-__device__ __forceinline__ int tile_rows() {
-  if constexpr (LPR == 0) return 1;
-  else return SPMV_ROWS_PER_GROUP;
-}
-template <int LPR>
-__device__ __forceinline__ int tile_row(const Tile tl, int k) {
-  if constexpr (LPR == 0) {
-    return tl.tile * blockDim.x + threadIdx.x;
-  } else {
-    const int groups = blockDim.x / LPR;
-    return tl.tile * groups * SPMV_ROWS_PER_GROUP + threadIdx.x / LPR + k * groups;
-  }
-}
-
-// Start of a pipelined solve (after assembly): w = A u with u = M^-1 r,
-// m = M^-1 w, the recurrences cleared, partial r.u and w.u.
-template <typename R, int LPR>
-__device__ __forceinline__ void cg_pipe_init_tile(const Tile tl, const EnvDesc* envs, double* sh) {
-  const EnvDesc& E = envs[tl.env];
-  if (!cg_go(E)) return;
-  const int lane = LPR ? (threadIdx.x & (LPR - 1)) : 0;
-  const R* u = (const R*)E.z;
-  R* w = (R*)E.w;
-  R* m = (R*)E.m0;
-  double gm = 0.0, dl = 0.0;
-  for (int k = 0; k < tile_rows<LPR>(); ++k) {
-    const int i = tile_row<LPR>(tl, k);
-    R y0, y1, y2;
-    if (row_product<R, LPR>(E, i, lane, u, y0, y1, y2)) {
-      const R* Pi = (const R*)E.Pinv + 6 * i;
-      R mv[3];
-      pinv_apply(Pi, y0, y1, y2, mv);
-      const R yy[3] = {y0, y1, y2};
-      for (int c = 0; c < 3; ++c) {
-        const int q = 3 * i + c;
-        w[q] = yy[c];
-        m[q] = mv[c];
-        ((R*)E.zc)[q] = R(0);
-        ((R*)E.s)[q] = R(0);
-        ((R*)E.pp)[q] = R(0);
-        gm += E.r[q] * (double)u[q];
-        dl += (double)yy[c] * (double)u[q];
-      }
-    }
-  }
-  gm = block_reduce(gm, OpSum(), sh);
-  dl = block_reduce(dl, OpSum(), sh);
-  if (threadIdx.x == 0) {
-    E.part_gm[tl.tile] = gm;
-    E.part_dl[tl.tile] = dl;
-  }
-}
-
-template <typename R, int LPR>
-__device__ __forceinline__ void cg_pipe_tile(const Tile tl, const EnvDesc* envs, int parity, double* sh) {
-  const EnvDesc& E = envs[tl.env];
-  double beta_d, alpha;
-  if (!cg_pipe_head(tl, E, parity, sh, &beta_d, &alpha)) return;
-  const R beta = (R)beta_d;
-  const int lane = LPR ? (threadIdx.x & (LPR - 1)) : 0;
-  const R* mc = (const R*)(parity ? E.m1 : E.m0);
-  R* mn = (R*)(parity ? E.m0 : E.m1);
-  double gm = 0.0, dl = 0.0;
-  for (int k = 0; k < tile_rows<LPR>(); ++k) {
-    const int i = tile_row<LPR>(tl, k);
-    R y0, y1, y2;
-    if (row_product<R, LPR>(E, i, lane, mc, y0, y1, y2)) cg_pipe_row<R>(E, i, y0, y1, y2, beta, alpha, mn, gm, dl);
-  }
-  gm = block_reduce(gm, OpSum(), sh);
-  dl = block_reduce(dl, OpSum(), sh);
-  if (threadIdx.x == 0) {
-    E.part_gm[tl.tile] = gm;
-    E.part_dl[tl.tile] = dl;
-  }
+  if (!running(S) || S->cg_done) return;
+  cg_update_body<R>(tl, E, parity, cg_alpha(tl, E, parity, sh), sh);
 }
 
 // Optional self-timing of a launch on the GPU wall clock: every block stores
@@ -1790,25 +1602,6 @@ __global__ void __launch_bounds__(1024) k_cg_update(const Tile* tiles, int ntile
   if (t < 0) return;
   if constexpr (TIMED) clock_start(clk);
   cg_update_tile<R>(tiles[t], envs, parity, sh);
-  if constexpr (TIMED) clock_end(clk);
-}
-
-template <typename R, int LPR>
-__global__ void __launch_bounds__(1024) k_cg_pipe_init(const Tile* tiles, int ntiles, const EnvDesc* envs) {
-  __shared__ double sh[16];
-  const int t = xcd_tile(ntiles);
-  if (t < 0) return;
-  cg_pipe_init_tile<R, LPR>(tiles[t], envs, sh);
-}
-
-template <typename R, int LPR, bool TIMED>
-__global__ void __launch_bounds__(1024) k_cg_pipe(const Tile* tiles, int ntiles, const EnvDesc* envs, int parity,
-                                                  unsigned long long* clk) {
-  __shared__ double sh[16];
-  const int t = xcd_tile(ntiles);
-  if (t < 0) return;
-  if constexpr (TIMED) clock_start(clk);
-  cg_pipe_tile<R, LPR>(tiles[t], envs, parity, sh);
   if constexpr (TIMED) clock_end(clk);
 }
 
@@ -2437,22 +2230,6 @@ hipError_t launch_typed(KernelId id, const LaunchArgs& a) {
     case KernelId::cg_update:
       if (a.clock) TC_LAUNCH((k_cg_update<R, true>), a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs, a.parity, a.clock);
       else TC_LAUNCH((k_cg_update<R, false>), a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs, a.parity, nullptr);
-      break;
-    case KernelId::cg_pipe_init:
-      if (a.lpr == 16) TC_LAUNCH((k_cg_pipe_init<R, 16>), a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs);
-      else if (a.lpr == 32) TC_LAUNCH((k_cg_pipe_init<R, 32>), a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs);
-      else TC_LAUNCH((k_cg_pipe_init<R, 0>), a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs);
-      break;
-    case KernelId::cg_pipe:
-      if (a.clock) {
-        if (a.lpr == 16) TC_LAUNCH((k_cg_pipe<R, 16, true>), a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs, a.parity, a.clock);
-        else if (a.lpr == 32) TC_LAUNCH((k_cg_pipe<R, 32, true>), a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs, a.parity, a.clock);
-        else TC_LAUNCH((k_cg_pipe<R, 0, true>), a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs, a.parity, a.clock);
-      } else {
-        if (a.lpr == 16) TC_LAUNCH((k_cg_pipe<R, 16, false>), a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs, a.parity, nullptr);
-        else if (a.lpr == 32) TC_LAUNCH((k_cg_pipe<R, 32, false>), a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs, a.parity, nullptr);
-        else TC_LAUNCH((k_cg_pipe<R, 0, false>), a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs, a.parity, nullptr);
-      }
       break;
     case KernelId::newton_dir: TC_LAUNCH(k_newton_dir<R>, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs); break;
     case KernelId::filter: TC_LAUNCH(k_filter<R>, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs); break;

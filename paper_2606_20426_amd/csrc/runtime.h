@@ -79,7 +79,6 @@ struct tc_context {
   int el_block = 128;
   int cg_per_replay = 16;
   bool use_graphs = false;
-  int cg_variant = 0;                // 0 classic PCG, 1 pipelined PCG (one fused kernel per iteration)
   // timing
   bool timing = false;
   int timing_stride = 1;             // time every k-th launch of each kernel

@@ -220,12 +220,15 @@ static hipEvent_t get_event(tc_context* ctx) {
   return e;
 }
 
-// Launch; while timing is on, every timing_stride-th launch of each kernel
-// is bracketed by events on the context stream.
+// Launch; while timing is on, every timing_stride-th launch of the
+// self-timed CG kernels (launched tens of thousands of times per run) and
+// every launch of the other kernels is timed: events on the context stream,
+// or the blocks' own clock cells.
 static hipError_t timed_launch(tc_context* ctx, KernelId k, bool fp64, const LaunchArgs& a) {
   if (!ctx->timing) return launch_kernel(k, fp64, a);
   KernelTimer& t = ctx->timers[(int)k];
-  if (t.launches++ % ctx->timing_stride != 0) return launch_kernel(k, fp64, a);
+  const int stride = self_timed(k) ? ctx->timing_stride : 1;
+  if (t.launches++ % stride != 0) return launch_kernel(k, fp64, a);
   LaunchArgs b = a;
   const int blocks = ((a.ntiles + 7) / 8) * 8;   // the launch's grid
   if (self_timed(k) && a.ntiles > 0 && ctx->clock_used + 2 * (size_t)blocks <= ctx->clock_cap) {
@@ -287,7 +290,6 @@ static void resolve_timing(tc_context* ctx) {
 
 struct ScratchLayout {
   size_t Ke, A, xn, xhat, g, d, r, z, p0, p1, q, Pinv, gb, Hb, fric;
-  size_t w, s, zc, pp, m0, m1, pgm, pdl;
   size_t prz, ppq, pg2, pe, pdir, pfilt, pc3, ps3;
   size_t total;
 };
@@ -309,24 +311,12 @@ static ScratchLayout scratch_layout(const tc_pad* p) {
   L.p1 = take(3 * V * R);
   L.q = take(3 * V * R);
   L.Pinv = take(6 * V * R);
-  if (p->ctx->cg_variant == 1) {
-    L.w = take(3 * V * R);
-    L.s = take(3 * V * R);
-    L.zc = take(3 * V * R);
-    L.pp = take(3 * V * R);
-    L.m0 = take(3 * V * R);
-    L.m1 = take(3 * V * R);
-  } else {
-    L.w = L.s = L.zc = L.pp = L.m0 = L.m1 = take(0);
-  }
   L.gb = take(24 * C);
   L.Hb = take(48 * C);
   L.fric = take(p->params.friction > 0 ? 8 * FRIC_STRIDE * MAX_IND * C : 0);
   const size_t nv = cdiv(V, 64), nt = cdiv(T, 64), nc = cdiv(C, 64), ns = cdiv(std::max<size_t>(S, 1), 64);
   L.prz = take(8 * nv);
   L.ppq = take(8 * ((size_t)cdiv(V, 2) + 1));
-  L.pgm = take(p->ctx->cg_variant == 1 ? 8 * ((size_t)cdiv(V, 2) + 1) : 0);
-  L.pdl = take(p->ctx->cg_variant == 1 ? 8 * ((size_t)cdiv(V, 2) + 1) : 0);
   L.pg2 = take(8 * nv);
   L.pe = take(8 * (nt + nv + nc));
   L.pdir = take(16 * nv);
@@ -356,14 +346,6 @@ static void bind_scratch_desc(tc_pad* p) {
   E.p1 = b + L.p1;
   E.q = b + L.q;
   E.Pinv = b + L.Pinv;
-  E.w = b + L.w;
-  E.s = b + L.s;
-  E.zc = b + L.zc;
-  E.pp = b + L.pp;
-  E.m0 = b + L.m0;
-  E.m1 = b + L.m1;
-  E.part_gm = (double*)(b + L.pgm);
-  E.part_dl = (double*)(b + L.pdl);
   E.gb = (double*)(b + L.gb);
   E.Hb = (double*)(b + L.Hb);
   E.fric = (double*)(b + L.fric);
@@ -603,7 +585,7 @@ bool Runner::any(bool (*pred)(const EnvState&)) const {
 }
 
 tc_status Runner::cg_chunk(int M, const View& v) {
-  if (v.full && ctx->use_graphs && !ctx->timing && ctx->cg_variant == 0) {
+  if (v.full && ctx->use_graphs && !ctx->timing) {
     if (!P->cg_exec || P->graph_M != M) {
       if (P->cg_exec) { (void)hipGraphExecDestroy(P->cg_exec); P->cg_exec = nullptr; }
       if (P->cg_graph) { (void)hipGraphDestroy(P->cg_graph); P->cg_graph = nullptr; }
@@ -617,8 +599,6 @@ tc_status Runner::cg_chunk(int M, const View& v) {
       P->graph_M = M;
     }
     TC_HIP(hipGraphLaunch(P->cg_exec, ctx->stream));
-  } else if (ctx->cg_variant == 1) {
-    for (int k = 0; k < M; ++k) launch_v(KernelId::cg_pipe, v, BatchPlan::SPMV, k & 1);
   } else {
     for (int k = 0; k < M; ++k) {
       launch_v(KernelId::cg_spmv, v, BatchPlan::SPMV, k & 1);
@@ -648,7 +628,6 @@ tc_status Runner::tick(bool init) {
     launch_v(KernelId::barrier, v, BatchPlan::CAND);
     launch_v(KernelId::asm_diag, v, BatchPlan::VERT);
     launch_v(KernelId::asm_off, v, BatchPlan::ASM);
-    if (ctx->cg_variant == 1) launch_v(KernelId::cg_pipe_init, v, BatchPlan::SPMV);
     int max_cg = 0;
     for (int i = 0; i < n; ++i) max_cg = std::max(max_cg, P->pads[i]->params.max_cg);
     const int M = std::max(2, ctx->cg_per_replay & ~1);
@@ -728,10 +707,6 @@ static double kernel_bytes(KernelId k, const tc_pad* p) {
   switch (k) {
     case KernelId::cg_spmv: return nnzb * (9 * R + 4) + V * 12 * R;
     case KernelId::cg_update: return V * (21 * R + 48);
-    // product on m plus per row: zc, s, p, u, w, d read and written, m'
-    // written, P^-1 read, r read and written in float64
-    case KernelId::cg_pipe: return nnzb * (9 * R + 4) + V * (48 * R + 48);
-    case KernelId::cg_pipe_init: return nnzb * (9 * R + 4) + V * (30 * R + 24);
     case KernelId::element: return T * (56 + 100 * R) + V * 48;
     case KernelId::asm_diag: return T * (36 * R) + V * (97 + 24 * R);
     case KernelId::asm_off: return T * (54 * R) + p->n_edges * (14 + 18 * R);
@@ -746,13 +721,8 @@ static double kernel_bytes(KernelId k, const tc_pad* p) {
 void account_bytes(tc_context* ctx, const tc_pad* pad, const EnvState& S) {
   const double nt = S.newton_iters, cg = S.cg_total;
   auto add = [&](KernelId k, double count) { ctx->timers[(int)k].bytes += count * kernel_bytes(k, pad); };
-  if (ctx->cg_variant == 1) {
-    add(KernelId::cg_pipe, cg);
-    add(KernelId::cg_pipe_init, nt);
-  } else {
-    add(KernelId::cg_spmv, cg);
-    add(KernelId::cg_update, cg);
-  }
+  add(KernelId::cg_spmv, cg);
+  add(KernelId::cg_update, cg);
   add(KernelId::element, nt);
   add(KernelId::asm_diag, nt);
   add(KernelId::asm_off, nt);
@@ -879,7 +849,6 @@ tc_status newton_direction(tc_pad* pad, int n_ind, const tc_indenter* ind, doubl
   run.launch_v(KernelId::barrier, v, BatchPlan::CAND);
   run.launch_v(KernelId::asm_diag, v, BatchPlan::VERT);
   run.launch_v(KernelId::asm_off, v, BatchPlan::ASM);
-  if (ctx->cg_variant == 1) run.launch_v(KernelId::cg_pipe_init, v, BatchPlan::SPMV);
   const int M = std::max(2, ctx->cg_per_replay & ~1);
   for (int done = 0; done <= pad->params.max_cg + M; done += M) {
     if ((s = run.cg_chunk(M, v))) return s;
@@ -1203,25 +1172,6 @@ tc_status tc_set_launch(tc_context* ctx, int32_t cg_block, int32_t elem_block, i
   if (spmv_block) ctx->spmv_block = spmv_block;
   if (cg_per_replay) ctx->cg_per_replay = cg_per_replay;
   if (use_graphs >= 0) ctx->use_graphs = use_graphs != 0;
-  ctx->plan.reset();
-  return TC_OK;
-}
-
-tc_status tc_set_cg_variant(tc_context* ctx, int32_t variant) {
-  if (!ctx) return set_error(TC_E_INVALID_ARG, "ctx is null");
-  if (variant != 0 && variant != 1) return set_error(TC_E_INVALID_ARG, "CG variant must be 0 or 1");
-  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
-  if (variant == ctx->cg_variant) return TC_OK;
-  for (const tc_pad* p : ctx->pads)
-    if (p->busy.load()) return set_error(TC_E_BUSY, "a pad has a request on a server");
-  TC_HIP(hipSetDevice(ctx->device));
-  TC_HIP(hipStreamSynchronize(ctx->stream));
-  // the step scratch layout depends on the variant
-  ctx->cg_variant = variant;
-  for (tc_pad* p : ctx->pads) {
-    release_scratch(p);
-    p->scratch_need = scratch_layout(p).total;
-  }
   ctx->plan.reset();
   return TC_OK;
 }

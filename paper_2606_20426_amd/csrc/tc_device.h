@@ -124,7 +124,6 @@ struct EnvState {
   double E_next;
   // CG (ping-pong slots indexed by iteration parity)
   double rzp[2];
-  double alp[2];           // pipelined CG: alpha of the iteration (by parity)
   double rz0;
   int32_t it[2];
   int32_t cg_done;
@@ -197,17 +196,7 @@ struct EnvDesc {
   void* z;                   // real
   void* p0;                  // real, ping-pong search directions
   void* p1;
-  void* q;                   // real, A p (pipelined CG: the M^-1 s recurrence)
-  // pipelined CG: w = A u, its recurrences s, zc, the search direction p,
-  // and m = M^-1 w (ping-pong: gathered by the next product)
-  void* w;                   // real [V][3]
-  void* s;
-  void* zc;
-  void* pp;
-  void* m0;
-  void* m1;
-  double* part_gm;           // [n_spt] partial r.u
-  double* part_dl;           // [n_spt] partial w.u
+  void* q;                   // real, A p
   void* Pinv;                // real [V][6] symmetric preconditioner blocks
   double* gb;                // [C][3] barrier gradient
   double* Hb;                // [C][6] projected barrier Hessian

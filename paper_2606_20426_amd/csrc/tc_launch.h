@@ -32,8 +32,6 @@ enum class KernelId : int {
   contact,
   env_extract,
   commit,
-  cg_pipe_init,
-  cg_pipe,
   count
 };
 
@@ -42,7 +40,7 @@ inline const char* kernel_name(KernelId k) {
                                 "element",    "barrier",    "asm_diag",   "asm_off",   "newton_begin",
                                 "cg_spmv",    "cg_update",  "newton_dir", "filter",    "env_dir",
                                 "energy",     "env_ls",     "update",     "env_update", "sigma",     "traction",
-                                "contact",    "env_extract", "commit",    "cg_pipe_init", "cg_pipe"};
+                                "contact",    "env_extract", "commit"};
   return names[static_cast<int>(k)];
 }
 
@@ -66,7 +64,7 @@ struct LaunchArgs {
 
 // Kernels that time themselves with the GPU wall clock when given a slot.
 inline bool self_timed(KernelId k) {
-  return k == KernelId::cg_spmv || k == KernelId::cg_update || k == KernelId::cg_pipe;
+  return k == KernelId::cg_spmv || k == KernelId::cg_update;
 }
 
 // Launch errors surface through hipGetLastError.

@@ -2,6 +2,7 @@
 from __future__ import annotations
 
 import functools
+import hashlib
 import os
 import sys
 
@@ -82,21 +83,39 @@ def errors(gp, ref, X, top):
     return e_pos, e_sig, e_pn
 
 
+_SURF_VERTS = {}
+
+
 def free_surface_vertices(tets, fixed):
     """Vertices of surface triangles with a free component (side faces
     included): the set the barrier must keep outside every indenter."""
-    tris, _ = surface.surface_triangles(tets)
-    verts = np.unique(tris)
+    tets = np.ascontiguousarray(tets)
+    key = hashlib.sha1(tets.tobytes()).hexdigest()
+    if key not in _SURF_VERTS:
+        tris, _ = surface.surface_triangles(tets)
+        _SURF_VERTS[key] = np.unique(tris)
+    verts = _SURF_VERTS[key]
     return verts[np.asarray(fixed)[verts] != 7]
 
 
 def surface_gap(verts, x, inds):
     """Smallest signed distance from the given vertices at positions x to
-    any indenter (the no-penetration invariant of the step)."""
+    any indenter (the no-penetration invariant of the step).  For a rigid
+    mesh only the vertices inside its bounding sphere (plus 1 mm) take the
+    brute-force distance; the others are at least their distance to that
+    sphere away, which is what they contribute."""
     gap = np.inf
     for ind in inds:
-        for lo in range(0, verts.size, 4096):
-            gap = min(gap, float(contact.sdf(ind, x[verts[lo:lo + 4096]])[0].min()))
+        pts = x[verts]
+        if getattr(ind, "mesh", None) is not None:
+            rb = float(np.linalg.norm(np.asarray(ind.mesh[0]), axis=1).max())
+            r = np.linalg.norm(pts - np.asarray(ind.c)[None], axis=1)
+            near = r < rb + 1e-3
+            if (~near).any():
+                gap = min(gap, float((r[~near] - rb).min()))
+            pts = pts[near]
+        for lo in range(0, pts.shape[0], 4096):
+            gap = min(gap, float(contact.sdf(ind, pts[lo:lo + 4096])[0].min()))
     return gap
 
 

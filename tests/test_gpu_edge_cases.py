@@ -165,10 +165,9 @@ def test_autotune_keeps_state_and_stepping_valid():
 
 
 def test_runtime_switches_relayout_scratch():
-    """Turning friction on or off for a live pad, and switching the
-    context's CG variant, change the step scratch layout: the next steps run
-    on the new layout and reach the same minimiser as a pad configured that
-    way from the start."""
+    """Turning friction on or off for a live pad changes its step scratch
+    layout: the next steps run on the new layout and reach the same
+    minimiser as a pad configured that way from the start."""
     ep = scenes.config1()
     ref_ctx, ctx = tc.Context(0), tc.Context(0)
     kw = dict(newton_tol=1e-6, cg_rel_tol=1e-4)
@@ -179,12 +178,10 @@ def test_runtime_switches_relayout_scratch():
     pad.step([ep.pose(1)])
     other.step([ep.pose(1)])
     pad.set_params(tc.make_params(precision="mixed", friction=0.5, **kw))   # friction on: new layout
-    ctx.set_cg_variant(1)                                                    # every pad re-laid out
     for s in (2, 3):
         ref.step([ep.pose(s)])
         st = tc.step_batch(ctx, [pad, other], [[ep.pose(s)], [ep.pose(s)]])
         assert all(x.status == 0 for x in st)
-    ctx.set_cg_variant(0)
     pad.set_params(tc.make_params(precision="mixed", friction=0.5, **kw))   # unchanged layout
     for s in (4, 5):
         ref.step([ep.pose(s)])

@@ -168,6 +168,8 @@ def batch60_run():
         gaps.append(min(surface_gap(free_v[k], pads[k].read("positions"), [e.pose(s)])
                         for k, e in enumerate(envs)))
         assert gaps[-1] > 0, (s, gaps[-1])
+        if s % 5 == 0:
+            log(f"  step {s}: newton max {newton[-1]}, smallest free-surface gap {gaps[-1]:.3e} m")
         for k in want.get(s, ()):
             saved[(s, k)] = (prev[k][0], prev[k][1], snapshot(pads[k]))
     log(f"batch60: 33 steps in {time.perf_counter() - t0:.1f} s, newton max per step {newton}, "
@@ -249,9 +251,14 @@ def _run_variant(kind, envs, ctx, kw, ids, pads):
         st = tc.step_batch(ctx, pads, [poses(e, s) for e in envs], raise_on_error=False)
         assert all(x.status == 0 for x in st), (s, [(k, x) for k, x in enumerate(st) if x.status])
         newton.append(max(x.newton_iters for x in st))
-        gaps.append(min(surface_gap(free_v[k], pads[k].read("positions"), [e.pose(s)])
-                        for k, e in enumerate(envs)))
-        assert gaps[-1] > 0, (s, gaps[-1])
+        # brute-force distances to triangle meshes are slow in the oracle:
+        # every third step there, every step for the analytic shapes
+        if kind != "mesh" or s % 3 == 0 or s == last:
+            gaps.append(min(surface_gap(free_v[k], pads[k].read("positions"), [e.pose(s)])
+                            for k, e in enumerate(envs)))
+            assert gaps[-1] > 0, (s, gaps[-1])
+        if s % 3 == 0:
+            log(f"  step {s}: newton max {newton[-1]}, smallest free-surface gap {gaps[-1]:.3e} m")
         for k in prev:
             saved[k] = (prev[k][0], prev[k][1], snapshot(pads[k]))
     log(f"batch60-{kind}: {last} steps in {time.perf_counter() - t0:.1f} s, newton max per step {newton}, "
