@@ -275,9 +275,13 @@ def run_steps(args):
     log(f"pads created in {time.perf_counter() - t0:.1f} s; HBM used {ctx.memory()[0] / 2**30:.2f} GiB")
     ctx.set_launch(cg_block=args.cg_block, elem_block=args.elem_block, spmv_block=args.spmv_block,
                    cg_per_replay=args.cg_per_replay, use_graphs=args.graphs)
+    ctx.set_streams(args.streams)
+    tuned = None
     if args.autotune:
+        # tuned on the first warm-up step's poses from the rest state
         chosen = ctx.autotune(pads, [poses(e, 1) for e in envs])
-        log(f"autotune: vertex block {chosen[0]}, element block {chosen[1]}, SpMV block {chosen[2]}")
+        tuned = dict(zip(("vertex_block", "element_block", "spmv_block", "cg_per_check", "streams"), chosen))
+        log(f"autotune: {tuned}")
 
     def step(s):
         if args.sequential:
@@ -318,7 +322,8 @@ def run_steps(args):
         "config": {"workload": args.workload, "description": desc, "envs": n_env,
                    "tets": int(sum(e.pad.tets.shape[0] for e in envs)), "mode": mode,
                    "newton_max_mean": float(np.mean(newton)), "cg_iters_mean": float(np.mean(cg)),
-                   "precision": args.precision, "graphs": bool(args.graphs and args.no_timing)},
+                   "precision": args.precision, "graphs": bool(args.graphs and args.no_timing),
+                   "streams": tuned["streams"] if tuned else args.streams, "autotuned": tuned},
         "roofline": roof,
     }
     if args.workload == "paper60":
@@ -531,6 +536,7 @@ def main():
     ap.add_argument("--cg-rel-tol", type=float, default=0.2)
     ap.add_argument("--cg-eta-max", type=float, default=0.2)
     ap.add_argument("--cg-forcing", type=int, default=2)
+    ap.add_argument("--streams", type=int, default=1, help="streams a batch step is split over (1..4)")
     ap.add_argument("--cg-conv-tol", type=float, default=0.0,
                     help="CG tolerance of a direction that decides convergence (0 = the solve tolerance)")
     ap.add_argument("--hess-proj", type=int, default=4)

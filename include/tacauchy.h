@@ -320,10 +320,15 @@ tc_status tc_context_timing(tc_context* ctx, int32_t cap, int32_t* n,
                             int64_t* launches, double* bytes_per_launch);
 tc_status tc_context_reset_timing(tc_context* ctx);
 
-/* Launch-shape autotuner: times the element and CG kernels on the given pads
- * for each candidate block size and keeps the fastest for the context.
- * Committed pad state is not modified.  chosen[0..3] = (vertex-row block,
- * element block, SpMV block, CG iterations per replay) when chosen != NULL. */
+/* Launch-shape autotuner.  First it times the element and CG kernels on
+ * the given pads for each candidate block size (vertex rows and SpMV 128 to
+ * 1024, element 64 to 256) and keeps the fastest per kernel; then, by the
+ * wall time of whole probe steps, the number of streams a batch is split
+ * over (1 to 4, at least 2 pads each) and the CG iterations between host
+ * checks (8, 16, 32), a candidate winning only by more than 2 %.  Every
+ * probe starts from the same saved state and leaves the committed pad state
+ * unmodified.  chosen (may be NULL) receives 5 values: vertex-row block,
+ * element block, SpMV block, CG iterations per host check, streams. */
 tc_status tc_autotune(tc_context* ctx, int32_t n, tc_pad* const* pads,
                       const int32_t* n_ind, const tc_indenter* ind, int32_t* chosen);
 /* Force a launch shape: block sizes of the vertex-row kernels (64..1024),
@@ -334,6 +339,17 @@ tc_status tc_autotune(tc_context* ctx, int32_t n, tc_pad* const* pads,
  * 0 leaves a value unchanged. */
 tc_status tc_set_launch(tc_context* ctx, int32_t cg_block, int32_t elem_block, int32_t spmv_block,
                         int32_t cg_per_replay, int32_t use_graphs);
+
+/* Streams a batch step is split over (default 1).  With n > 1, tc_step_batch
+ * divides its pads into n groups of about equal tet counts; each group is
+ * stepped on a stream of its own, driven by a host thread of its own, so
+ * one group's last CG iterations and host round trips overlap with the
+ * other groups' launches.  Every pad's result is bitwise the same for any n
+ * (pads never share arithmetic).  Streams keep the default priority.  The
+ * setting takes effect from the next batch; extraction-only calls and
+ * single pads use the context stream. */
+#define TC_MAX_STREAMS 4
+tc_status tc_set_streams(tc_context* ctx, int32_t n_streams);
 
 /* ------------------------------------------------------------------- pads */
 /* Copies the mesh and materials into HBM and runs the setup kernels: Eq. 1
@@ -391,7 +407,7 @@ tc_status tc_refine_mesh(const tc_mesh* in, const tc_sizing* sizing, int32_t cap
 
 /* ------------------------------------------------------- rigid meshes */
 /* Register a rigid triangle mesh as an indenter shape (the rigid objects of
- * Sec. III-B and the grasped test objects of Sec. IV-E).  verts: host
+ * Sec. III-B and the grasped test objects of Sec. IV-D).  verts: host
  * [n_verts][3] float64 in the indenter's local frame [m]; tris: host
  * [n_tris][3] int32.  The surface must be closed and consistently oriented
  * with outward normals: every edge shared by exactly two triangles in
@@ -445,6 +461,7 @@ tc_status tc_step_batch(tc_context* ctx, int32_t n, tc_pad* const* pads,
  * the barrier's only: friction forces depend on the start state of the step
  * that produced the positions and come with tc_step's extraction. */
 tc_status tc_extract(tc_pad* pad, int32_t n_ind, const tc_indenter* ind);
+
 
 /* Inspection: one Newton direction at the committed positions (taken as the
  * current iterate as they are: no feasible-start projection) under the given

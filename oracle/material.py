@@ -95,9 +95,3 @@ def cauchy(F, mu, lam, alpha):
     J = det(F)
     b = F @ np.swapaxes(F, -1, -2)
     return _m(mu / J) * b + _m(lam * (J - alpha)) * np.eye(3)
-
-
-def voigt(sig):
-    """Symmetric 3x3 -> (xx, yy, zz, yz, xz, xy)."""
-    return np.stack([sig[..., 0, 0], sig[..., 1, 1], sig[..., 2, 2],
-                     sig[..., 1, 2], sig[..., 0, 2], sig[..., 0, 1]], axis=-1)

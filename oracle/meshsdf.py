@@ -1,7 +1,7 @@
 """Signed distance to a closed rigid triangle mesh (oracle, FP64, test
 infrastructure).
 
-The paper's rigid objects (the Franka-held test objects of Sec. IV-E, and
+The paper's rigid objects (the Franka-held test objects of Sec. IV-D, and
 the rigid bodies of the contact solver of Sec. III-B) are triangle meshes.
 Against a rigid mesh the contact measure of a pad vertex is its distance to
 the mesh surface, which this module computes by brute force:

@@ -240,12 +240,16 @@ class Context:
     def set_launch(self, cg_block=0, elem_block=0, spmv_block=0, cg_per_replay=0, use_graphs=-1):
         check(self.lib.tc_set_launch(self.h, cg_block, elem_block, spmv_block, cg_per_replay, use_graphs))
 
+    def set_streams(self, n: int):
+        """Split batch steps over n streams (1..4), one host thread each."""
+        check(self.lib.tc_set_streams(self.h, int(n)))
+
     def autotune(self, pads: Sequence["Pad"], indenters: Sequence[Sequence]):
         n = len(pads)
         ph = (C.c_void_p * n)(*[p.h for p in pads])
         nind = (C.c_int32 * n)(*[len(i) for i in indenters])
         flat = _indenter_array([x for inds in indenters for x in inds])
-        chosen = (C.c_int32 * 4)()
+        chosen = (C.c_int32 * 5)()
         check(self.lib.tc_autotune(self.h, n, ph, nind, flat, chosen))
         return tuple(chosen)
 

@@ -1161,7 +1161,92 @@ __global__ void k_barrier(const Tile* tiles, int ntiles, const EnvDesc* envs) {
 
 // Diagonal block rows (slot 0): sum of element blocks, inertia, barrier,
 // Dirichlet masking, gradient, preconditioner, and CG initialisation
-// (d = 0, r = -g, z = P^-1 r, partial r.z and g.g).
+// (d = 0, r = -g, z = P^-1 r, partial r.z and g.g).  A tile is blockDim.x
+// rows; groups of ASM_LPR lanes take one row at a time, each lane summing
+// every ASM_LPR-th record of the row's contiguous run of diagonal-stream
+// records (so a wavefront reads a few long runs instead of 64 scattered
+// records), then a shuffle reduction gives the row's sums to its lane 0,
+// which finishes the row.
+constexpr int ASM_LPR = 8;
+
+template <typename R>
+__device__ __forceinline__ void asm_diag_row(const EnvDesc& E, int i, double D[3][3], double gs[3], double& rz,
+                                             double& gg) {
+  D[1][0] = D[0][1]; D[2][0] = D[0][2]; D[2][1] = D[1][2];
+  const size_t it0 = (size_t)i * E.W;
+  const double h2 = E.h * E.h;
+  double xi[3], xh[3];
+  load3(E.xn, i, xi);
+  load3(E.xhat, i, xh);
+  const double m = E.quasi_static ? 0.0 : E.mass[i];
+  for (int r = 0; r < 3; ++r) {
+    for (int q = 0; q < 3; ++q) D[r][q] *= h2;
+    D[r][r] += m;
+    gs[r] = h2 * gs[r] + m * (xi[r] - xh[r]);
+  }
+  const int k = E.cand_of_vert[i];
+  if (k >= 0) {
+    const double* hb = E.Hb + 6 * k;
+    const double Hk[3][3] = {{hb[0], hb[1], hb[2]}, {hb[1], hb[3], hb[4]}, {hb[2], hb[4], hb[5]}};
+    for (int r = 0; r < 3; ++r) {
+      for (int q = 0; q < 3; ++q) D[r][q] += h2 * Hk[r][q];
+      gs[r] += h2 * E.gb[3 * k + r];
+    }
+  }
+  const uint8_t fm = E.fixed[i];
+  for (int r = 0; r < 3; ++r)
+    if ((fm >> r) & 1) {
+      for (int q = 0; q < 3; ++q) { D[r][q] = 0; D[q][r] = 0; }
+      D[r][r] = 1.0;
+      gs[r] = 0.0;
+    }
+  R* A = (R*)E.A + it0 * 9;
+  for (int r = 0; r < 3; ++r)
+    for (int q = 0; q < 3; ++q) A[3 * r + q] = (R)D[r][q];
+  // preconditioner: inverse of the 3x3 diagonal block, or of its diagonal
+  double P[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  const double c00 = D[1][1] * D[2][2] - D[1][2] * D[2][1];
+  const double c01 = D[1][2] * D[2][0] - D[1][0] * D[2][2];
+  const double c02 = D[1][0] * D[2][1] - D[1][1] * D[2][0];
+  const double det = D[0][0] * c00 + D[0][1] * c01 + D[0][2] * c02;
+  // the block must be positive definite (leading minors) to serve as a CG
+  // preconditioner; otherwise fall back to the absolute diagonal
+  const bool spd = D[0][0] > 0 && D[0][0] * D[1][1] - D[0][1] * D[1][0] > 0 && det > 0;
+  if (E.precond == TC_PRECOND_BLOCK_JACOBI && spd) {
+    const double id = 1.0 / det;
+    P[0][0] = c00 * id;
+    P[0][1] = (D[0][2] * D[2][1] - D[0][1] * D[2][2]) * id;
+    P[0][2] = (D[0][1] * D[1][2] - D[0][2] * D[1][1]) * id;
+    P[1][1] = (D[0][0] * D[2][2] - D[0][2] * D[2][0]) * id;
+    P[1][2] = (D[0][2] * D[1][0] - D[0][0] * D[1][2]) * id;
+    P[2][2] = (D[0][0] * D[1][1] - D[0][1] * D[1][0]) * id;
+    P[1][0] = P[0][1]; P[2][0] = P[0][2]; P[2][1] = P[1][2];
+  } else {
+    for (int r = 0; r < 3; ++r) P[r][r] = 1.0 / fmax(fabs(D[r][r]), 1e-300);
+  }
+  R* Pi = (R*)E.Pinv + 6 * i;
+  Pi[0] = (R)P[0][0]; Pi[1] = (R)P[0][1]; Pi[2] = (R)P[0][2];
+  Pi[3] = (R)P[1][1]; Pi[4] = (R)P[1][2]; Pi[5] = (R)P[2][2];
+  R Pr[3][3] = {{Pi[0], Pi[1], Pi[2]}, {Pi[1], Pi[3], Pi[4]}, {Pi[2], Pi[4], Pi[5]}};
+  R* d = (R*)E.d;
+  R* z = (R*)E.z;
+  R* p1 = (R*)E.p1;
+  double rr[3];
+  for (int r = 0; r < 3; ++r) {
+    E.g[3 * i + r] = gs[r];
+    rr[r] = -gs[r];
+    E.r[3 * i + r] = rr[r];
+    d[3 * i + r] = R(0);
+    p1[3 * i + r] = R(0);
+    gg += gs[r] * gs[r];
+  }
+  for (int r = 0; r < 3; ++r) {
+    const R zr = Pr[r][0] * (R)rr[0] + Pr[r][1] * (R)rr[1] + Pr[r][2] * (R)rr[2];
+    z[3 * i + r] = zr;
+    rz += rr[r] * (double)zr;
+  }
+}
+
 template <typename R>
 __global__ void k_asm_diag(const Tile* tiles, int ntiles, const EnvDesc* envs) {
   __shared__ double sh[16];
@@ -1170,91 +1255,28 @@ __global__ void k_asm_diag(const Tile* tiles, int ntiles, const EnvDesc* envs) {
   const Tile tl = tiles[t];
   const EnvDesc& E = envs[tl.env];
   if (!running(E.st)) return;
-  const int i = tl.tile * blockDim.x + threadIdx.x;
-  const bool valid = i < E.V;
+  const int lane = threadIdx.x & (ASM_LPR - 1);
+  const int groups = blockDim.x / ASM_LPR;
+  const int row0 = tl.tile * blockDim.x + threadIdx.x / ASM_LPR;
+  const R* Kd = (const R*)E.Ke;
   double rz = 0.0, gg = 0.0;
-  if (valid) {
-    double D[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-    double gs[3] = {0, 0, 0};
-    const R* Kd = (const R*)E.Ke;
-    const size_t it0 = (size_t)i * E.W;
-    for (int c = E.dptr[i]; c < E.dptr[i + 1]; ++c) {
-      const R* p = Kd + (size_t)KC * c;
-      D[0][0] += (double)p[0]; D[0][1] += (double)p[1]; D[0][2] += (double)p[2];
-      D[1][1] += (double)p[3]; D[1][2] += (double)p[4]; D[2][2] += (double)p[5];
-      for (int r = 0; r < 3; ++r) gs[r] += (double)p[6 + r];
-    }
-    D[1][0] = D[0][1]; D[2][0] = D[0][2]; D[2][1] = D[1][2];
-    const double h2 = E.h * E.h;
-    double xi[3], xh[3];
-    load3(E.xn, i, xi);
-    load3(E.xhat, i, xh);
-    const double m = E.quasi_static ? 0.0 : E.mass[i];
-    for (int r = 0; r < 3; ++r) {
-      for (int q = 0; q < 3; ++q) D[r][q] *= h2;
-      D[r][r] += m;
-      gs[r] = h2 * gs[r] + m * (xi[r] - xh[r]);
-    }
-    const int k = E.cand_of_vert[i];
-    if (k >= 0) {
-      const double* hb = E.Hb + 6 * k;
-      const double Hk[3][3] = {{hb[0], hb[1], hb[2]}, {hb[1], hb[3], hb[4]}, {hb[2], hb[4], hb[5]}};
-      for (int r = 0; r < 3; ++r) {
-        for (int q = 0; q < 3; ++q) D[r][q] += h2 * Hk[r][q];
-        gs[r] += h2 * E.gb[3 * k + r];
+  for (int k = 0; k < ASM_LPR; ++k) {
+    const int i = row0 + k * groups;
+    double v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};   // xx xy xz yy yz zz, gradient
+    if (i < E.V)
+      for (int c = E.dptr[i] + lane; c < E.dptr[i + 1]; c += ASM_LPR) {
+        const R* p = Kd + (size_t)KC * c;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) v[q] += (double)p[q];
       }
-    }
-    const uint8_t fm = E.fixed[i];
-    for (int r = 0; r < 3; ++r)
-      if ((fm >> r) & 1) {
-        for (int q = 0; q < 3; ++q) { D[r][q] = 0; D[q][r] = 0; }
-        D[r][r] = 1.0;
-        gs[r] = 0.0;
-      }
-    R* A = (R*)E.A + it0 * 9;
-    for (int r = 0; r < 3; ++r)
-      for (int q = 0; q < 3; ++q) A[3 * r + q] = (R)D[r][q];
-    // preconditioner: inverse of the 3x3 diagonal block, or of its diagonal
-    double P[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-    const double c00 = D[1][1] * D[2][2] - D[1][2] * D[2][1];
-    const double c01 = D[1][2] * D[2][0] - D[1][0] * D[2][2];
-    const double c02 = D[1][0] * D[2][1] - D[1][1] * D[2][0];
-    const double det = D[0][0] * c00 + D[0][1] * c01 + D[0][2] * c02;
-    // the block must be positive definite (leading minors) to serve as a CG
-    // preconditioner; otherwise fall back to the absolute diagonal
-    const bool spd = D[0][0] > 0 && D[0][0] * D[1][1] - D[0][1] * D[1][0] > 0 && det > 0;
-    if (E.precond == TC_PRECOND_BLOCK_JACOBI && spd) {
-      const double id = 1.0 / det;
-      P[0][0] = c00 * id;
-      P[0][1] = (D[0][2] * D[2][1] - D[0][1] * D[2][2]) * id;
-      P[0][2] = (D[0][1] * D[1][2] - D[0][2] * D[1][1]) * id;
-      P[1][1] = (D[0][0] * D[2][2] - D[0][2] * D[2][0]) * id;
-      P[1][2] = (D[0][2] * D[1][0] - D[0][0] * D[1][2]) * id;
-      P[2][2] = (D[0][0] * D[1][1] - D[0][1] * D[1][0]) * id;
-      P[1][0] = P[0][1]; P[2][0] = P[0][2]; P[2][1] = P[1][2];
-    } else {
-      for (int r = 0; r < 3; ++r) P[r][r] = 1.0 / fmax(fabs(D[r][r]), 1e-300);
-    }
-    R* Pi = (R*)E.Pinv + 6 * i;
-    Pi[0] = (R)P[0][0]; Pi[1] = (R)P[0][1]; Pi[2] = (R)P[0][2];
-    Pi[3] = (R)P[1][1]; Pi[4] = (R)P[1][2]; Pi[5] = (R)P[2][2];
-    R Pr[3][3] = {{Pi[0], Pi[1], Pi[2]}, {Pi[1], Pi[3], Pi[4]}, {Pi[2], Pi[4], Pi[5]}};
-    R* d = (R*)E.d;
-    R* z = (R*)E.z;
-    R* p1 = (R*)E.p1;
-    double rr[3];
-    for (int r = 0; r < 3; ++r) {
-      E.g[3 * i + r] = gs[r];
-      rr[r] = -gs[r];
-      E.r[3 * i + r] = rr[r];
-      d[3 * i + r] = R(0);
-      p1[3 * i + r] = R(0);
-      gg += gs[r] * gs[r];
-    }
-    for (int r = 0; r < 3; ++r) {
-      const R zr = Pr[r][0] * (R)rr[0] + Pr[r][1] * (R)rr[1] + Pr[r][2] * (R)rr[2];
-      z[3 * i + r] = zr;
-      rz += rr[r] * (double)zr;
+#pragma unroll
+    for (int o = ASM_LPR / 2; o > 0; o >>= 1)
+#pragma unroll
+      for (int q = 0; q < 9; ++q) v[q] += __shfl_xor(v[q], o, ASM_LPR);
+    if (lane == 0 && i < E.V) {
+      double D[3][3] = {{v[0], v[1], v[2]}, {0, v[3], v[4]}, {0, 0, v[5]}};
+      double gs[3] = {v[6], v[7], v[8]};
+      asm_diag_row<R>(E, i, D, gs, rz, gg);
     }
   }
   rz = block_reduce(rz, OpSum(), sh);

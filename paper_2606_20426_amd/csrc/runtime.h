@@ -52,6 +52,23 @@ struct KernelTimer {
 
 struct BatchPlan;
 
+// A timed launch: its events, or (self-timed kernels) its blocks' clock
+// cells at offset `cell` of its slice.
+struct Pending {
+  KernelId k;
+  hipEvent_t a, b;
+  size_t cell;
+  int blocks;          // -1: events
+};
+
+// The clock cells [base, base + cap) of the context's array that one stream
+// uses for its self-timed launches (cap 0: the whole array), and the timed
+// launches of that stream not yet read back.
+struct TimingSlice {
+  std::vector<Pending> pending;
+  size_t base = 0, cap = 0, used = 0;
+};
+
 // Device array of per-step states and poses with pinned host mirrors; a pad
 // in a batch occupies one slot.
 struct SlotPool {
@@ -60,6 +77,20 @@ struct SlotPool {
   EnvPose* d_pose = nullptr;
   EnvState* h_state = nullptr;
   EnvPose* h_pose = nullptr;
+};
+
+// A stream that steps a group of a batch's pads, with its own batch plan,
+// state slots and timing slice.  The context's lane 0 points at the
+// context's own stream, plan, pool and slice; the lanes of a batch split
+// into groups own theirs.
+struct Lane {
+  hipStream_t stream = nullptr;
+  std::unique_ptr<BatchPlan>* plan = nullptr;
+  SlotPool* pool = nullptr;
+  TimingSlice* ts = nullptr;
+  std::unique_ptr<BatchPlan> own_plan;
+  SlotPool own_pool;
+  TimingSlice own_ts;
 };
 
 }  // namespace tc
@@ -82,18 +113,20 @@ struct tc_context {
   // timing
   bool timing = false;
   int timing_stride = 1;             // time every k-th launch of each kernel
-  // a timed launch: events, or (self-timed kernels) its blocks' clock cells
-  struct Pending { tc::KernelId k; hipEvent_t a, b; size_t cell; int blocks; };
   // clock cells of self-timed launches since the last sync (device, zeroed)
   unsigned long long* clock_cells = nullptr;
-  size_t clock_cap = 0, clock_used = 0;   // in cells (u64)
+  size_t clock_cap = 0;              // in cells (u64)
   double clock_khz = 0.0;
-  std::vector<Pending> pending;
+  tc::TimingSlice tslice;            // launches on the context stream
+  std::mutex tmu;                    // timers and the event pool (streams of several host threads)
   std::vector<hipEvent_t> free_events;
   tc::KernelTimer timers[(int)tc::KernelId::count];
   // per-step algorithmic byte counts are added when the step finishes
   std::unique_ptr<tc::BatchPlan> plan;
   tc::SlotPool pool;                 // slots of synchronous steps
+  tc::Lane lane0;                    // the context's stream, plan, pool, slice
+  int n_lanes = 1;                   // streams a batch is split over
+  std::vector<std::unique_ptr<tc::Lane>> lanes;   // lanes of split batches
   std::recursive_mutex mu;           // serialises device work of API calls and the server
   int next_pad_id = 1;
   std::vector<tc_pad*> pads;         // every live pad of the context
@@ -185,7 +218,14 @@ void release_scratch(tc_pad* pad);
 tc_status pool_reserve(tc_context* ctx, SlotPool& p, int cap);
 void pool_free(SlotPool& p);
 tc_status build_plan(tc_context* ctx, int n, tc_pad* const* pads, const int* slots, const SlotPool& pool,
-                     std::unique_ptr<BatchPlan>& out);
+                     std::unique_ptr<BatchPlan>& out, hipStream_t stream = nullptr);
+// Lane g of split batches (created on first use, default-priority stream).
+tc_status get_lane(tc_context* ctx, int g);
+// Drops every cached batch plan of the context (lanes' streams idle).
+void drop_plans(tc_context* ctx);
+// Frees the split-batch lanes (streams idle).
+void free_lanes(tc_context* ctx);
+const std::string& last_error();
 bool plan_matches(const BatchPlan* P, tc_context* ctx, int n, tc_pad* const* pads, const int* slots,
                   const SlotPool& pool);
 void account_bytes(tc_context* ctx, const tc_pad* pad, const EnvState& s);
@@ -208,6 +248,13 @@ struct Runner {
   int n;
   SlotPool* pool;
   int span;
+  // the stream the launches go to and its timing slice (null: the
+  // context's own)
+  hipStream_t stream = nullptr;
+  TimingSlice* ts = nullptr;
+
+  hipStream_t strm() const { return stream ? stream : ctx->stream; }
+  TimingSlice& slice() const { return ts ? *ts : ctx->tslice; }
 
   const EnvState& state(int i) const { return pool->h_state[P->slots[i]]; }
   void launch(KernelId k, int cls, int parity = 0, int mode = 0);

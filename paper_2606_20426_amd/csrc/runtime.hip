@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <thread>
 
 namespace tc {
 
@@ -222,42 +223,56 @@ static hipEvent_t get_event(tc_context* ctx) {
 
 // Launch; while timing is on, every timing_stride-th launch of the
 // self-timed CG kernels (launched tens of thousands of times per run) and
-// every launch of the other kernels is timed: events on the context stream,
-// or the blocks' own clock cells.
-static hipError_t timed_launch(tc_context* ctx, KernelId k, bool fp64, const LaunchArgs& a) {
+// every launch of the other kernels is timed: events recorded by the
+// dispatch, or the blocks' own clock cells in the slice of the stream that
+// launches.  Streams driven by different host threads each have a slice.
+static hipError_t timed_launch(tc_context* ctx, TimingSlice& ts, KernelId k, bool fp64, const LaunchArgs& a) {
   if (!ctx->timing) return launch_kernel(k, fp64, a);
-  KernelTimer& t = ctx->timers[(int)k];
-  const int stride = self_timed(k) ? ctx->timing_stride : 1;
-  if (t.launches++ % stride != 0) return launch_kernel(k, fp64, a);
+  bool sample;
+  {
+    std::lock_guard<std::mutex> lk(ctx->tmu);
+    const int stride = self_timed(k) ? ctx->timing_stride : 1;
+    sample = ctx->timers[(int)k].launches++ % stride == 0;
+  }
+  if (!sample) return launch_kernel(k, fp64, a);
   LaunchArgs b = a;
   const int blocks = ((a.ntiles + 7) / 8) * 8;   // the launch's grid
-  if (self_timed(k) && a.ntiles > 0 && ctx->clock_used + 2 * (size_t)blocks <= ctx->clock_cap) {
+  const size_t cap = ts.cap ? ts.cap : ctx->clock_cap;
+  if (self_timed(k) && a.ntiles > 0 && ts.used + 2 * (size_t)blocks <= cap) {
     // every block stamps its own start and end
-    const size_t cell = ctx->clock_used;
-    ctx->clock_used += 2 * (size_t)blocks;
+    const size_t cell = ts.base + ts.used;
+    ts.used += 2 * (size_t)blocks;
     b.clock = ctx->clock_cells + cell;
     const hipError_t e = launch_kernel(k, fp64, b);
-    ctx->pending.push_back({k, nullptr, nullptr, cell, blocks});
+    ts.pending.push_back({k, nullptr, nullptr, cell - ts.base, blocks});
     return e;
   }
   if (self_timed(k)) return launch_kernel(k, fp64, a);   // no room: not timed
-  b.ev0 = get_event(ctx);
-  b.ev1 = get_event(ctx);
+  {
+    std::lock_guard<std::mutex> lk(ctx->tmu);
+    b.ev0 = get_event(ctx);
+    b.ev1 = get_event(ctx);
+  }
   const hipError_t e = launch_kernel(k, fp64, b);
-  ctx->pending.push_back({k, b.ev0, b.ev1, 0, -1});
+  ts.pending.push_back({k, b.ev0, b.ev1, 0, -1});
   return e;
 }
 
-// Called after the context stream has been synchronised.
-static void resolve_timing(tc_context* ctx) {
+// Called after `stream`, the one the slice's launches went to, has been
+// synchronised.
+static void resolve_timing(tc_context* ctx, TimingSlice& ts, hipStream_t stream) {
   std::vector<unsigned long long> clk;
-  if (ctx->clock_used > 0) {
-    clk.resize(ctx->clock_used);
-    if (hipMemcpy(clk.data(), ctx->clock_cells, 8 * clk.size(), hipMemcpyDeviceToHost) != hipSuccess) clk.clear();
-    (void)hipMemsetAsync(ctx->clock_cells, 0, 8 * ctx->clock_used, ctx->stream);
-    ctx->clock_used = 0;
+  if (ts.used > 0) {
+    clk.resize(ts.used);
+    if (hipMemcpyAsync(clk.data(), ctx->clock_cells + ts.base, 8 * clk.size(), hipMemcpyDeviceToHost, stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess)
+      clk.clear();
+    (void)hipMemsetAsync(ctx->clock_cells + ts.base, 0, 8 * ts.used, stream);
+    ts.used = 0;
   }
-  for (auto& p : ctx->pending) {
+  std::lock_guard<std::mutex> lk(ctx->tmu);
+  for (auto& p : ts.pending) {
     if (p.blocks >= 0) {
       if (p.cell + 2 * (size_t)p.blocks <= clk.size()) {
         // blocks past the tile list store nothing (zero cells)
@@ -283,8 +298,10 @@ static void resolve_timing(tc_context* ctx) {
     ctx->free_events.push_back(p.a);
     ctx->free_events.push_back(p.b);
   }
-  ctx->pending.clear();
+  ts.pending.clear();
 }
+
+static void resolve_timing(tc_context* ctx) { resolve_timing(ctx, ctx->tslice, ctx->stream); }
 
 // ------------------------------------------------------------ scratch layout
 
@@ -408,13 +425,47 @@ void release_scratch(tc_pad* p) {
   p->ctx->arena.give(p->scratch, p->scratch_bytes);
   p->scratch = nullptr;
   p->scratch_bytes = 0;
-  if (p->ctx->plan) p->ctx->plan.reset();   // plans hold scratch pointers
+  drop_plans(p->ctx);   // plans hold scratch pointers
 }
 
 // ------------------------------------------------------------- batch plan
 
+tc_status get_lane(tc_context* ctx, int g) {
+  while ((int)ctx->lanes.size() <= g) {
+    auto L = std::make_unique<Lane>();
+    TC_HIP(hipStreamCreateWithFlags(&L->stream, hipStreamNonBlocking));
+    L->plan = &L->own_plan;
+    L->pool = &L->own_pool;
+    L->ts = &L->own_ts;
+    ctx->lanes.push_back(std::move(L));
+  }
+  return TC_OK;
+}
+
+void drop_plans(tc_context* ctx) {
+  ctx->plan.reset();
+  for (auto& L : ctx->lanes) L->own_plan.reset();
+}
+
+void free_lanes(tc_context* ctx) {
+  for (auto& L : ctx->lanes) {
+    (void)hipStreamSynchronize(L->stream);
+    L->own_plan.reset();
+    pool_free(L->own_pool);
+    for (auto& p : L->own_ts.pending) {
+      if (p.blocks < 0) {
+        ctx->free_events.push_back(p.a);
+        ctx->free_events.push_back(p.b);
+      }
+    }
+    (void)hipStreamDestroy(L->stream);
+  }
+  ctx->lanes.clear();
+}
+
 tc_status build_plan(tc_context* ctx, int n, tc_pad* const* pads, const int* slots, const SlotPool& pool,
-                     std::unique_ptr<BatchPlan>& out) {
+                     std::unique_ptr<BatchPlan>& out, hipStream_t stream) {
+  if (!stream) stream = ctx->stream;
   auto P = std::make_unique<BatchPlan>();
   P->slots.assign(slots, slots + n);
   P->BV = ctx->cg_block;
@@ -474,9 +525,9 @@ tc_status build_plan(tc_context* ctx, int n, tc_pad* const* pads, const int* slo
   P->ctiles_cap = 4 * (int)tiles.size() + 64;
   TC_HIP(hipMalloc(&P->d_ctiles, sizeof(Tile) * std::max(P->ctiles_cap, 1)));
   TC_HIP(hipHostMalloc(&P->h_ctiles, sizeof(Tile) * std::max(P->ctiles_cap, 1), hipHostMallocDefault));
-  TC_HIP(hipMemcpyAsync(P->d_desc, P->h_desc.data(), sizeof(EnvDesc) * n, hipMemcpyHostToDevice, ctx->stream));
-  TC_HIP(hipMemcpyAsync(P->d_tiles, tiles.data(), sizeof(Tile) * tiles.size(), hipMemcpyHostToDevice, ctx->stream));
-  TC_HIP(hipStreamSynchronize(ctx->stream));
+  TC_HIP(hipMemcpyAsync(P->d_desc, P->h_desc.data(), sizeof(EnvDesc) * n, hipMemcpyHostToDevice, stream));
+  TC_HIP(hipMemcpyAsync(P->d_tiles, tiles.data(), sizeof(Tile) * tiles.size(), hipMemcpyHostToDevice, stream));
+  TC_HIP(hipStreamSynchronize(stream));
   P->d_state = pool.d_state;
   out = std::move(P);
   return TC_OK;
@@ -502,14 +553,14 @@ void Runner::launch(KernelId k, int cls, int parity, int mode) {
   a.n_env = n;
   a.parity = parity;
   a.mode = mode;
-  a.stream = ctx->stream;
+  a.stream = strm();
   if (cls != BatchPlan::NCLS) {
     a.tiles = P->d_tiles + P->off[cls];
     a.ntiles = P->cnt[cls];
     a.block = cls == BatchPlan::TET ? P->BT : (cls == BatchPlan::SPMV && P->lpr) ? P->BS : P->BV;
     a.lpr = P->lpr;
   }
-  (void)timed_launch(ctx, k, P->fp64, a);
+  (void)timed_launch(ctx, slice(), k, P->fp64, a);
 }
 
 void Runner::launch_tiles(KernelId k, const Tile* tiles, int ntiles, int block, int parity, int mode) {
@@ -518,12 +569,12 @@ void Runner::launch_tiles(KernelId k, const Tile* tiles, int ntiles, int block, 
   a.n_env = n;
   a.parity = parity;
   a.mode = mode;
-  a.stream = ctx->stream;
+  a.stream = strm();
   a.tiles = tiles;
   a.ntiles = ntiles;
   a.block = block;
   a.lpr = P->lpr;
-  (void)timed_launch(ctx, k, P->fp64, a);
+  (void)timed_launch(ctx, slice(), k, P->fp64, a);
 }
 
 Runner::View Runner::view(bool (*pred)(const EnvState&)) {
@@ -560,7 +611,7 @@ Runner::View Runner::view(bool (*pred)(const EnvState&)) {
   const int len = P->ctiles_off - base;
   if (len > 0)
     (void)hipMemcpyAsync(P->d_ctiles + base, P->h_ctiles + base, sizeof(Tile) * len, hipMemcpyHostToDevice,
-                         ctx->stream);
+                         strm());
   return v;
 }
 
@@ -571,10 +622,10 @@ void Runner::launch_v(KernelId k, const View& v, int cls, int parity, int mode) 
 
 tc_status Runner::readback() {
   TC_HIP(hipGetLastError());
-  TC_HIP(hipMemcpyAsync(pool->h_state, pool->d_state, sizeof(EnvState) * span, hipMemcpyDeviceToHost, ctx->stream));
-  TC_HIP(hipStreamSynchronize(ctx->stream));
+  TC_HIP(hipMemcpyAsync(pool->h_state, pool->d_state, sizeof(EnvState) * span, hipMemcpyDeviceToHost, strm()));
+  TC_HIP(hipStreamSynchronize(strm()));
   P->ctiles_off = 0;
-  if (ctx->timing) resolve_timing(ctx);
+  if (ctx->timing) resolve_timing(ctx, slice(), strm());
   return TC_OK;
 }
 
@@ -589,16 +640,16 @@ tc_status Runner::cg_chunk(int M, const View& v) {
     if (!P->cg_exec || P->graph_M != M) {
       if (P->cg_exec) { (void)hipGraphExecDestroy(P->cg_exec); P->cg_exec = nullptr; }
       if (P->cg_graph) { (void)hipGraphDestroy(P->cg_graph); P->cg_graph = nullptr; }
-      TC_HIP(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+      TC_HIP(hipStreamBeginCapture(strm(), hipStreamCaptureModeThreadLocal));
       for (int k = 0; k < M; ++k) {
         launch_v(KernelId::cg_spmv, v, BatchPlan::SPMV, k & 1);
         launch_v(KernelId::cg_update, v, BatchPlan::VERT, k & 1);
       }
-      TC_HIP(hipStreamEndCapture(ctx->stream, &P->cg_graph));
+      TC_HIP(hipStreamEndCapture(strm(), &P->cg_graph));
       TC_HIP(hipGraphInstantiate(&P->cg_exec, P->cg_graph, nullptr, nullptr, 0));
       P->graph_M = M;
     }
-    TC_HIP(hipGraphLaunch(P->cg_exec, ctx->stream));
+    TC_HIP(hipGraphLaunch(P->cg_exec, strm()));
   } else {
     for (int k = 0; k < M; ++k) {
       launch_v(KernelId::cg_spmv, v, BatchPlan::SPMV, k & 1);
@@ -758,54 +809,135 @@ tc_status run_batch(tc_context* ctx, int n, tc_pad* const* pads, const int32_t* 
       if (s) return s;
     }
   }
-  SlotPool& pool = ctx->pool;
-  {
-    tc_status s = pool_reserve(ctx, pool, n);
-    if (s) return s;
+  // pads split into groups, each stepped on its own stream by its own host
+  // thread (the first group on this one): one group's CG tail and host
+  // round trips overlap with the other groups' launches
+  const int G = mode == 0 ? std::max(1, std::min(ctx->n_lanes, n / 2)) : 1;
+  std::vector<std::vector<int>> groups(G);
+  if (G == 1) {
+    for (int i = 0; i < n; ++i) groups[0].push_back(i);
+  } else {
+    // largest pads first to the group with the fewest tets; each group keeps
+    // the batch order
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return pads[x]->T > pads[y]->T; });
+    std::vector<int64_t> load(G, 0);
+    for (int i : order) {
+      const int g = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      groups[g].push_back(i);
+      load[g] += pads[i]->T;
+    }
+    for (auto& gr : groups) std::sort(gr.begin(), gr.end());
   }
-  std::vector<int> slots(n);
-  for (int i = 0; i < n; ++i) slots[i] = i;
-  if (!plan_matches(ctx->plan.get(), ctx, n, pads, slots.data(), pool)) {
-    ctx->plan.reset();
-    tc_status s = build_plan(ctx, n, pads, slots.data(), pool, ctx->plan);
-    if (s) return s;
-  }
-  BatchPlan* P = ctx->plan.get();
+  std::vector<int> first_of(n, 0);   // index of each pad's first pose
   off = 0;
   for (int i = 0; i < n; ++i) {
-    init_state(pool.h_state[i], pool.h_pose[i], mode, n_ind[i], ind ? ind + off : nullptr, pads[i]);
+    first_of[i] = off;
     off += n_ind[i];
   }
-  static_assert(sizeof(DevIndenter) == sizeof(tc_indenter), "indenter layout");
-  TC_HIP(hipMemcpyAsync(pool.d_state, pool.h_state, sizeof(EnvState) * n, hipMemcpyHostToDevice, ctx->stream));
-  TC_HIP(hipMemcpyAsync(pool.d_pose, pool.h_pose, sizeof(EnvPose) * n, hipMemcpyHostToDevice, ctx->stream));
-  Runner run{ctx, P, n, &pool, n};
-  tc_status st = TC_OK;
-  bool init = mode == 0;
-  int guard = 0;
-  int max_newton = 0;
-  for (int i = 0; i < n; ++i) max_newton = std::max(max_newton, pads[i]->params.max_newton);
-  if (mode == 1) {
-    if ((st = run.tick(false))) return st;
-  } else {
-    while (true) {
-      if ((st = run.tick(init))) return st;
-      init = false;
-      if (!run.any(Runner::not_done)) break;
-      if (++guard > max_newton + 2) return set_error(TC_E_HIP, "Newton driver did not terminate");
+  struct Job {
+    Lane* lane;
+    std::vector<tc_pad*> pads;
+    std::vector<int> idx;
+    tc_status st = TC_OK;
+    std::string err;
+  };
+  std::vector<Job> jobs(G);
+  for (int g = 0; g < G; ++g) {
+    Job& J = jobs[g];
+    if (G == 1) {
+      J.lane = &ctx->lane0;
+    } else {
+      tc_status s = get_lane(ctx, g);
+      if (s) return s;
+      J.lane = ctx->lanes[g].get();
+    }
+    J.idx = groups[g];
+    for (int i : J.idx) J.pads.push_back(pads[i]);
+    Lane& L = *J.lane;
+    const int m = (int)J.pads.size();
+    tc_status s = pool_reserve(ctx, *L.pool, m);
+    if (s) return s;
+    std::vector<int> slots(m);
+    for (int i = 0; i < m; ++i) slots[i] = i;
+    if (!plan_matches(L.plan->get(), ctx, m, J.pads.data(), slots.data(), *L.pool)) {
+      L.plan->reset();
+      if ((s = build_plan(ctx, m, J.pads.data(), slots.data(), *L.pool, *L.plan, L.stream))) return s;
+    }
+    for (int k = 0; k < m; ++k) {
+      const int i = J.idx[k];
+      init_state(L.pool->h_state[k], L.pool->h_pose[k], mode, n_ind[i], ind ? ind + first_of[i] : nullptr, pads[i]);
+    }
+    static_assert(sizeof(DevIndenter) == sizeof(tc_indenter), "indenter layout");
+    TC_HIP(hipMemcpyAsync(L.pool->d_state, L.pool->h_state, sizeof(EnvState) * m, hipMemcpyHostToDevice, L.stream));
+    TC_HIP(hipMemcpyAsync(L.pool->d_pose, L.pool->h_pose, sizeof(EnvPose) * m, hipMemcpyHostToDevice, L.stream));
+    if (G > 1) {
+      // every lane's slice of the clock cells
+      L.ts->base = (size_t)g * (ctx->clock_cap / G);
+      L.ts->cap = ctx->clock_cap / G;
     }
   }
+  auto drive = [ctx, mode](Job& J) {
+    Lane& L = *J.lane;
+    const int m = (int)J.pads.size();
+    Runner run{ctx, L.plan->get(), m, L.pool, m, L.stream, L.ts};
+    int max_newton = 0;
+    for (tc_pad* p : J.pads) max_newton = std::max(max_newton, p->params.max_newton);
+    tc_status st = TC_OK;
+    if (mode == 1) {
+      st = run.tick(false);
+    } else {
+      bool init = true;
+      for (int guard = 0;; ++guard) {
+        if ((st = run.tick(init))) break;
+        init = false;
+        if (!run.any(Runner::not_done)) break;
+        if (guard > max_newton + 2) {
+          st = set_error(TC_E_HIP, "Newton driver did not terminate");
+          break;
+        }
+      }
+    }
+    J.st = st;
+    if (st) J.err = last_error();
+  };
+  if (G == 1) {
+    drive(jobs[0]);
+  } else {
+    std::vector<std::thread> th;
+    for (int g = 1; g < G; ++g)
+      th.emplace_back([&, g] {
+        if (hipSetDevice(ctx->device) != hipSuccess) {
+          jobs[g].st = set_error(TC_E_HIP, "hipSetDevice in a lane thread");
+          jobs[g].err = last_error();
+          return;
+        }
+        drive(jobs[g]);
+      });
+    drive(jobs[0]);
+    for (auto& t : th) t.join();
+    for (int g = 0; g < G; ++g) {
+      jobs[g].lane->ts->base = 0;
+      jobs[g].lane->ts->cap = 0;
+    }
+  }
+  for (auto& J : jobs)
+    if (J.st) return set_error(J.st, J.err);
   tc_status first = TC_OK;
   const double ms = now_ms() - t0;
-  for (int i = 0; i < n; ++i) {
-    const EnvState& S = pool.h_state[i];
-    if (S.status == TC_OK && mode == 0) {
-      pads[i]->step_count++;
-      remember_pose(pads[i], pool.h_pose[i]);
+  for (auto& J : jobs) {
+    for (size_t k = 0; k < J.pads.size(); ++k) {
+      const int i = J.idx[k];
+      const EnvState& S = J.lane->pool->h_state[k];
+      if (S.status == TC_OK && mode == 0) {
+        pads[i]->step_count++;
+        remember_pose(pads[i], J.lane->pool->h_pose[k]);
+      }
+      if (S.status != TC_OK && first == TC_OK) first = S.status;
+      if (stats) fill_stats(stats[i], S, ms);
+      if (ctx->timing) account_bytes(ctx, pads[i], S);
     }
-    if (S.status != TC_OK && first == TC_OK) first = S.status;
-    if (stats) fill_stats(stats[i], S, ms);
-    if (ctx->timing) account_bytes(ctx, pads[i], S);
   }
   if (first != TC_OK) {
     char buf[160];
@@ -1057,6 +1189,10 @@ tc_status tc_context_create(int32_t device, void* hip_stream, uint64_t hbm_budge
       if (e != hipSuccess) { delete ctx; return hip_fail(e, "hipStreamCreate"); }
       ctx->own_stream = true;
     }
+    ctx->lane0.stream = ctx->stream;
+    ctx->lane0.plan = &ctx->plan;
+    ctx->lane0.pool = &ctx->pool;
+    ctx->lane0.ts = &ctx->tslice;
     {
       const size_t tb = sizeof(DevMesh) * MAX_MESHES;
       hipError_t e = hipMalloc(&ctx->d_meshes, tb);
@@ -1085,6 +1221,7 @@ tc_status tc_context_destroy(tc_context* ctx) {
                                       std::to_string(ctx->n_servers.load()) + " servers");
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
+    free_lanes(ctx);
     ctx->plan.reset();
     for (auto& c : ctx->arena.chunks) (void)hipFree(c.base);
     ctx->arena.chunks.clear();
@@ -1120,7 +1257,8 @@ tc_status tc_context_set_timing(tc_context* ctx, int32_t enable) {
     ctx->clock_cap = (size_t)4 << 20;   // 32 MiB of cells
     TC_HIP(hipMalloc(&ctx->clock_cells, 8 * ctx->clock_cap));
     TC_HIP(hipMemsetAsync(ctx->clock_cells, 0, 8 * ctx->clock_cap, ctx->stream));
-    ctx->clock_used = 0;
+    TC_HIP(hipStreamSynchronize(ctx->stream));   // other streams use the cells too
+    ctx->tslice.used = 0;
   }
   ctx->timing = enable != 0;
   if (enable > 0) ctx->timing_stride = enable;
@@ -1172,7 +1310,15 @@ tc_status tc_set_launch(tc_context* ctx, int32_t cg_block, int32_t elem_block, i
   if (spmv_block) ctx->spmv_block = spmv_block;
   if (cg_per_replay) ctx->cg_per_replay = cg_per_replay;
   if (use_graphs >= 0) ctx->use_graphs = use_graphs != 0;
-  ctx->plan.reset();
+  drop_plans(ctx);
+  return TC_OK;
+}
+
+tc_status tc_set_streams(tc_context* ctx, int32_t n_streams) {
+  if (!ctx) return set_error(TC_E_INVALID_ARG, "ctx is null");
+  if (n_streams < 1 || n_streams > TC_MAX_STREAMS) return set_error(TC_E_INVALID_ARG, "n_streams must be 1..4");
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  ctx->n_lanes = n_streams;
   return TC_OK;
 }
 
@@ -1377,7 +1523,7 @@ tc_status tc_pad_destroy(tc_pad* pad) {
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
   release_scratch(pad);
-  ctx->plan.reset();
+  drop_plans(ctx);
   for (auto& a : pad->allocs) ctx->dev_free(a.first, a.second);
   ctx->pads.erase(std::remove(ctx->pads.begin(), ctx->pads.end(), pad), ctx->pads.end());
   delete pad;
@@ -1439,7 +1585,7 @@ tc_status tc_pad_set_params(tc_pad* pad, const tc_params* params) {
   E.max_halvings = params->max_halvings;
   E.precond = params->precond;
   pad->desc_version = next_desc_version();
-  pad->ctx->plan.reset();
+  drop_plans(pad->ctx);
   return TC_OK;
 }
 
@@ -1596,7 +1742,7 @@ tc_status tc_autotune(tc_context* ctx, int32_t n, tc_pad* const* pads, const int
       ctx->cg_block = vb;
       ctx->el_block = eb;
       ctx->spmv_block = sb;
-      ctx->plan.reset();
+      drop_plans(ctx);
       for (auto& t : ctx->timers) t = KernelTimer{};
       std::vector<std::vector<char>> saved(n);
       std::vector<int64_t> steps(n);
@@ -1644,12 +1790,65 @@ tc_status tc_autotune(tc_context* ctx, int32_t n, tc_pad* const* pads, const int
     ctx->cg_block = bcg;
     ctx->el_block = bel;
     ctx->spmv_block = bsp;
+    // second phase, by the wall time of whole probe steps with timing off:
+    // streams the batch is split over, then CG iterations between host
+    // checks (best of two probes each; the probes repeat identical work)
+    ctx->timing = false;
+    auto wall = [&](double* ms) -> tc_status {
+      double best = 1e30;
+      for (int rep = 0; rep < 2; ++rep) {
+        std::vector<std::vector<char>> saved(n);
+        std::vector<int64_t> steps(n);
+        for (int i = 0; i < n; ++i) {
+          size_t b = 0;
+          tc_pad_save_state(pads[i], nullptr, &b);
+          saved[i].resize(b);
+          tc_status s = tc_pad_save_state(pads[i], saved[i].data(), &b);
+          if (s) return s;
+          steps[i] = pads[i]->step_count;
+        }
+        const double t0 = now_ms();
+        tc_status s = run_batch(ctx, n, pads, n_ind, ind, nullptr, 0);
+        const double dt = now_ms() - t0;
+        for (int i = 0; i < n; ++i) {
+          tc_pad_load_state(pads[i], saved[i].data(), saved[i].size());
+          pads[i]->step_count = steps[i];
+        }
+        if (s && s != TC_E_NOT_CONVERGED && s != TC_E_LINESEARCH) return s;
+        best = std::min(best, dt);
+      }
+      *ms = best;
+      return TC_OK;
+    };
+    int best_lanes = ctx->n_lanes;
+    double best_ms = 1e30;
+    for (int nl = 1; nl <= TC_MAX_STREAMS && nl <= std::max(1, n / 2); ++nl) {
+      ctx->n_lanes = nl;
+      double ms;
+      tc_status s = wall(&ms);
+      if (s) return s;
+      if (ms < best_ms * 0.98) { best_ms = ms; best_lanes = nl; }
+    }
+    ctx->n_lanes = best_lanes;
+    int best_chunk = ctx->cg_per_replay;
+    best_ms = 1e30;
+    for (int ch : {8, 16, 32}) {
+      ctx->cg_per_replay = ch;
+      double ms;
+      tc_status s = wall(&ms);
+      if (s) return s;
+      if (ms < best_ms * 0.98) { best_ms = ms; best_chunk = ch; }
+    }
+    ctx->cg_per_replay = best_chunk;
     ctx->timing = old_timing;
     ctx->timing_stride = old_stride;
     ctx->use_graphs = old_graphs;
-    ctx->plan.reset();
+    drop_plans(ctx);
     for (auto& t : ctx->timers) t = KernelTimer{};
-    if (chosen) { chosen[0] = bcg; chosen[1] = bel; chosen[2] = bsp; chosen[3] = ctx->cg_per_replay; }
+    if (chosen) {
+      chosen[0] = bcg; chosen[1] = bel; chosen[2] = bsp; chosen[3] = ctx->cg_per_replay;
+      chosen[4] = ctx->n_lanes;
+    }
     return TC_OK;
   });
 }

@@ -1,5 +1,5 @@
 """Heterogeneous materials (per-tet material index, the dual-layer gel of
-Sec. IV-C): a soft top layer on a stiffer base under a sphere, GPU against
+Sec. IV-D): a soft top layer on a stiffer base under a sphere, GPU against
 the FP64 oracle with per-tet Lame parameters and densities, step by step."""
 from __future__ import annotations
 

@@ -113,6 +113,21 @@ def dome_map(X, thickness, cap_radius, centre_xy):
     return X
 
 
+def cylinder_map(X, thickness, cap_radius, centre_x):
+    """Stretch each vertical column so the top becomes a cylindrical cap
+    curved along x (axis along y):
+
+    z' = z * (H + cap(x)) / H, cap = sqrt(Rc^2 - u^2) - sqrt(Rc^2 - u_max^2),
+    u = x - centre_x, u_max = its largest magnitude over the pad (so the cap
+    is zero at the two curved edges)."""
+    X = np.array(X, dtype=np.float64, copy=True)
+    u = X[:, 0] - centre_x
+    u_max = np.abs(u).max()
+    cap = np.sqrt(cap_radius ** 2 - u ** 2) - np.sqrt(cap_radius ** 2 - u_max ** 2)
+    X[:, 2] = X[:, 2] * (thickness + cap) / thickness
+    return X
+
+
 def cells_for_target(Lx, Ly, Lz, target_tets):
     """Cell counts nx:ny:nz ~ Lx:Ly:(2 Lz) closest to target_tets / 6."""
     cells = target_tets / 6.0

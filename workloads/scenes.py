@@ -204,7 +204,7 @@ def seeded_xy(rng, pad, margin):
 
 def layered_materials(X, tets, z_split, top, bottom):
     """Per-tet material index of a two-layer pad (the dual-layer gel of
-    Sec. IV-C): 0 above z_split (tet centroid), 1 below; returns (index,
+    Sec. IV-D): 0 above z_split (tet centroid), 1 below; returns (index,
     [top, bottom])."""
     zc = X[tets, 2].mean(axis=1)
     return np.where(zc > z_split, 0, 1).astype(np.int32), [top, bottom]
@@ -221,6 +221,44 @@ def dual_layer_episode():
     rng = np.random.default_rng(7)
     r = 4 * MM
     xy = (rng.uniform(r / 2, pad.dims[0] - r / 2), rng.uniform(r / 2, pad.dims[1] - r / 2))
+    ind = place_indenter(pad, SPHERE, xy, params.dhat, sphere_radius=r)
+    return Episode(pad, ind, 0.6 * MM, 8, params), idx, mats
+
+
+def curved_gel_episode(nx=14, ny=10, nz=3):
+    """Stand-in for a curved sensor gel (the paper's DIGIT, Sec. IV-D; its
+    CAD is not available): a 20x14 mm pad, 2.5 mm thick at its two curved
+    edges, whose top is a cylindrical cap of radius 30 mm curved along x
+    (1.7 mm higher at the ridge).  E = 0.3 MPa, nu = 0.45; sphere r = 5 mm at
+    a seeded point (seed 11) pressed 0.5 mm over 8 steps."""
+    Lx, Ly, H = 20 * MM, 14 * MM, 2.5 * MM
+    pad = box_pad(Lx, Ly, H, nx, ny, nz, Material(0.3e6, 0.45, 1000.0), name="curved")
+    pad.X = meshes.cylinder_map(pad.X, H, 30 * MM, 0.5 * Lx)
+    params = Params()
+    rng = np.random.default_rng(11)
+    r = 5 * MM
+    xy = (rng.uniform(0.35 * Lx, 0.65 * Lx), rng.uniform(r / 2, Ly - r / 2))
+    ind = place_indenter(pad, SPHERE, xy, params.dhat, sphere_radius=r)
+    return Episode(pad, ind, 0.5 * MM, 8, params)
+
+
+def stiff_skin_episode(nx=12, ny=12, nz=6):
+    """Stand-in for a dual-layer gel whose surface layer is the stiffer one
+    (the paper's 9DTact, Sec. IV-D: a soft translucent base under a stiffer
+    black surface layer; its CAD and moduli are not given): a 20x20x4 mm
+    pad, the top 0.67 mm (one cell layer) with E = 1.2 MPa, nu = 0.45,
+    rho = 1100 over a base with E = 0.2 MPa, nu = 0.47, rho = 1050; sphere
+    r = 4 mm at a seeded point (seed 12) pressed 0.6 mm over 8 steps.
+    Returns (episode, per-tet material index, [skin, base])."""
+    Lx, Ly, H = 20 * MM, 20 * MM, 4 * MM
+    base = Material(0.2e6, 0.47, 1050.0)
+    skin = Material(1.2e6, 0.45, 1100.0)
+    pad = box_pad(Lx, Ly, H, nx, ny, nz, base, name="stiff_skin")
+    idx, mats = layered_materials(pad.X, pad.tets, H - H / nz, skin, base)
+    params = Params()
+    rng = np.random.default_rng(12)
+    r = 4 * MM
+    xy = (rng.uniform(r / 2, Lx - r / 2), rng.uniform(r / 2, Ly - r / 2))
     ind = place_indenter(pad, SPHERE, xy, params.dhat, sphere_radius=r)
     return Episode(pad, ind, 0.6 * MM, 8, params), idx, mats
 
@@ -367,7 +405,7 @@ def config3_variant(kind, n_envs=60):
       friction : the same press-slide with friction ratio 0.5 (Sec. III-B);
       layers   : two layers split at half thickness, the drawn material on
                  top and a base 8x stiffer (nu = 0.42, rho = 1200), the
-                 dual-layer gel of Sec. IV-C;
+                 dual-layer gel of Sec. IV-D;
       mesh     : the bounded indenters given as triangle meshes (mesh_indenter);
                  the torus, whose mesh has concave edges on the inner side
                  of the tube, with the barrier summed over triangle pairs
