@@ -364,23 +364,14 @@ def gpu_baseline(tc, ctx, envs, args):
             "description": "the same pads and steps, FP64, one tc_step per pad in sequence"}
 
 
-def run_serve(args):
-    """Poisson step requests from many resident pads into the continuous-
-    batching server; latency = arrival (submit) to result."""
-    import numpy as np
-    import paper_2606_20426_amd as tc
+def serve_once(tc, ctx, pads, envs, step_of, rate, duration, max_slots):
+    """One Poisson run into a fresh server: returns the completed requests
+    (dicts from Server.poll), the wall time, the submit span and the
+    server's statistics.  step_of continues each pad's episode."""
     from workloads import scenes
-
-    envs, desc = build_workload(args.workload)
-    n_pads = len(envs)
-    ctx = tc.Context(0, hbm_budget=int(args.hbm_budget_gib * 2**30) if args.hbm_budget_gib else 0)
-    t0 = time.perf_counter()
-    pads = make_pads(tc, ctx, envs, args)
-    resident = sum(p.info["resident_bytes"] for p in pads)
-    log(f"{n_pads} pads created in {time.perf_counter() - t0:.1f} s; resident {resident / 2**30:.2f} GiB")
-    t_arr, which = scenes.config4_arrivals(args.rate, args.duration, n_pads)
-    srv = tc.Server(ctx, args.max_slots)
-    step_of = [0] * n_pads
+    n_pads = len(pads)
+    t_arr, which = scenes.config4_arrivals(rate, duration, n_pads)
+    srv = tc.Server(ctx, max_slots)
     results = []
     done_evt = threading.Event()
 
@@ -402,43 +393,82 @@ def run_serve(args):
         srv.submit(pads[k], poses(envs[k], step_of[k]), tag=int(k))
         if time.perf_counter() - last_log > 5.0:
             last_log = time.perf_counter()
-            log(f"t={last_log - start:.1f} s: submitted {i + 1}, completed {len(results)}")
+            log(f"rate {rate:g}: t={last_log - start:.1f} s: submitted {i + 1}, completed {len(results)}")
     submit_end = time.perf_counter() - start
     done_evt.set()
     while th.is_alive():
         th.join(timeout=5.0)
-        log(f"draining: completed {len(results)} of {len(t_arr)}")
-        if time.perf_counter() - start > args.duration + 600:
+        log(f"rate {rate:g}: draining, completed {len(results)} of {len(t_arr)}")
+        if time.perf_counter() - start > duration + 600:
             raise SystemExit("server did not drain")
     total = time.perf_counter() - start
     st = srv.stats()
     srv.close()
+    return results, len(t_arr), total, submit_end, st
+
+
+def serve_summary(results, n_req, total, duration):
+    import numpy as np
     ok = [r for r in results if r["status"] == 0]
+    lat = np.array([r["t_done_ms"] - r["t_arrive_ms"] for r in ok])
+    service = np.array([r["t_done_ms"] - r["t_admit_ms"] for r in ok])
     failed = {}
     for r in results:
         if r["status"] != 0:
             failed[str(r["status"])] = failed.get(str(r["status"]), 0) + 1
-    lat = np.array([r["t_done_ms"] - r["t_arrive_ms"] for r in ok])
-    service = np.array([r["t_done_ms"] - r["t_admit_ms"] for r in ok])
-    completion_rate = len(ok) / total
-    saturated = total > args.duration * 1.05 + 0.5
-    return {
+    return {"completed_per_s": round(len(ok) / total, 1),
+            "p50_ms": round(float(np.percentile(lat, 50)), 2), "p99_ms": round(float(np.percentile(lat, 99)), 2),
+            "service_p50_ms": round(float(np.percentile(service, 50)), 2),
+            "requests": int(n_req), "completed": len(ok), "failed_by_status": failed,
+            "wall_s": round(total, 2), "saturated": bool(total > duration * 1.05 + 0.5)}
+
+
+def run_serve(args):
+    """Poisson step requests from many resident pads into the continuous-
+    batching server; latency = arrival (submit) to result.  With --rates,
+    one run per arrival rate on the same resident pads, and the highest rate
+    the server sustains (drains within 5 % of the arrival span)."""
+    import paper_2606_20426_amd as tc
+
+    envs, desc = build_workload(args.workload)
+    n_pads = len(envs)
+    ctx = tc.Context(0, hbm_budget=int(args.hbm_budget_gib * 2**30) if args.hbm_budget_gib else 0)
+    t0 = time.perf_counter()
+    pads = make_pads(tc, ctx, envs, args)
+    resident = sum(p.info["resident_bytes"] for p in pads)
+    log(f"{n_pads} pads created in {time.perf_counter() - t0:.1f} s; resident {resident / 2**30:.2f} GiB")
+    step_of = [0] * n_pads
+    rates = [float(r) for r in args.rates.split(",")] if args.rates else [args.rate]
+    sweep = []
+    head = None
+    for rate in rates:
+        results, n_req, total, submit_end, st = serve_once(tc, ctx, pads, envs, step_of, rate, args.duration,
+                                                           args.max_slots)
+        summ = serve_summary(results, n_req, total, args.duration)
+        summ.update({"arrival_rate_hz": rate, "submit_span_s": round(submit_end, 2),
+                     "max_running_seen": st["max_running_seen"], "batched_iterations": st["ticks"],
+                     "evictions": int(st.get("evictions", 0))})
+        log(f"rate {rate:g}: {summ}")
+        sweep.append(summ)
+        if rate == args.rate or head is None:
+            head = summ
+    sustained = [s_["arrival_rate_hz"] for s_ in sweep if not s_["saturated"] and not s_["failed_by_status"]]
+    out = {
         "metric": "serving: step requests/s completed and p50/p99 latency (arrival to result)",
-        "value": round(completion_rate, 1), "unit": "steps/s", "n_gpus": 1,
-        "p50_ms": round(float(np.percentile(lat, 50)), 2), "p99_ms": round(float(np.percentile(lat, 99)), 2),
-        "service_p50_ms": round(float(np.percentile(service, 50)), 2),
+        "value": head["completed_per_s"], "unit": "steps/s", "n_gpus": 1,
+        "p50_ms": head["p50_ms"], "p99_ms": head["p99_ms"], "service_p50_ms": head["service_p50_ms"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+f64" if args.precision == "mixed" else "f64", "data": "synthetic",
         "config": {"workload": args.workload, "description": desc, "pads": n_pads,
-                   "arrival_rate_hz": args.rate, "duration_s": args.duration, "requests": int(len(t_arr)),
-                   "completed": len(ok), "failed": len(results) - len(ok), "failed_by_status": failed,
-                   "max_slots": args.max_slots,
-                   "hbm_budget_gib": args.hbm_budget_gib, "resident_gib": round(resident / 2**30, 3),
-                   "evictions": int(st.get("evictions", 0)), "hbm_used_gib": round(ctx.memory()[0] / 2**30, 3),
-                   "max_running_seen": st["max_running_seen"], "batched_iterations": st["ticks"],
-                   "submit_span_s": round(submit_end, 2), "wall_s": round(total, 2),
-                   "saturated": bool(saturated)},
+                   "arrival_rate_hz": head["arrival_rate_hz"], "duration_s": args.duration,
+                   "max_slots": args.max_slots, "hbm_budget_gib": args.hbm_budget_gib,
+                   "resident_gib": round(resident / 2**30, 3), "hbm_used_gib": round(ctx.memory()[0] / 2**30, 3),
+                   "requests": head["requests"], "completed": head["completed"],
+                   "failed_by_status": head["failed_by_status"], "saturated": head["saturated"]},
+        "max_sustained_rate_hz": max(sustained) if sustained else None,
+        "sweep": sweep if len(sweep) > 1 else None,
     }
+    return out
 
 
 def run_ablation(args):
@@ -546,6 +576,7 @@ def main():
                     help="Newton start: 0 = x_t, 1 = x_t + dt v_t (then made feasible)")
     # serving
     ap.add_argument("--rate", type=float, default=2000.0, help="request arrivals per second")
+    ap.add_argument("--rates", default="", help="comma-separated arrival rates to sweep (serving)")
     ap.add_argument("--duration", type=float, default=20.0, help="seconds of arrivals")
     ap.add_argument("--max-slots", type=int, default=64)
     ap.add_argument("--hbm-budget-gib", type=float, default=0.0)

@@ -177,8 +177,11 @@ typedef struct {
                            curvature; a breakdown reverts to clamping for the
                            rest of the step).  Bits 2-3, barrier 3x3: 0 clamp,
                            1 unfiltered, 2 normal term only, 3 clamp until a
-                           full Newton step is accepted, then unfiltered (with
-                           the same safeguards). */
+                           full Newton step is accepted, then unfiltered.  In
+                           every mode a CG breakdown (negative curvature)
+                           never counts as convergence: its iterate is used
+                           as a descent direction and every Hessian is
+                           clamped for the rest of the step. */
   int32_t init_guess;   /* Newton start: 0 = x_t, 1 = x_t + dt v_t (free
                            components); either is then made feasible */
   double cg_conv_tol;   /* CG tolerance of the direction on which Newton

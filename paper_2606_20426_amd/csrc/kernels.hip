@@ -1122,6 +1122,7 @@ __global__ void k_barrier(const Tile* tiles, int ntiles, const EnvDesc* envs) {
   // is accepted, then as is
   int bmode = (E.hess_proj >> 2) & 3;
   if (bmode == 3) bmode = E.st->true_hess ? 1 : 0;
+  if (E.st->filt_all) bmode = 0;   // a CG breakdown earlier in this step
   if (bmode == 0) {
     project_psd3(H);
   } else if (bmode == 2) {
@@ -1772,12 +1773,14 @@ __global__ void k_env_dir(const EnvDesc* envs, int n) {
     // a direction from a loose CG solve can be short only because the soft
     // modes are unresolved: convergence is judged on a floor-tolerance solve
     const bool tight = S->cg_tol2 <= E.cg_conv_tol * E.cg_conv_tol * (1.0 + 1e-12) || S->cg_iters >= E.max_cg;
-    if (S->breakdown && S->true_hess) {
-      // negative curvature met with the unfiltered Hessian: keep the CG
-      // iterate (a descent direction, possibly zero) but judge nothing on it
-      // and use filtered Hessians for the rest of the step
+    if (S->breakdown) {
+      // negative curvature met (an unfiltered element or barrier Hessian):
+      // keep the CG iterate (a descent direction, possibly zero: a breakdown
+      // at the first iteration leaves d = 0) but judge nothing on it, and
+      // filter every Hessian for the rest of the step
       S->no_true_hess = 1;
       S->true_hess = 0;
+      S->filt_all = 1;
       S->dir_conv = 0;
     } else {
       S->dir_conv = dm <= E.tol_abs && tight;

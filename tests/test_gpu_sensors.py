@@ -66,6 +66,10 @@ def test_sensor_pad_episode_matches_oracle(kind, prec, newton_tol, cg_rel_tol, t
         ind = [ep.pose(s)]
         newton, ref = refs[s - 1]
         st = gp.step(ind)
+        if np.abs(ref["x"] - ep.pad.X).max() < 1e-12:
+            # no contact yet: both sides at rest (the relative norms are 0/0)
+            assert np.abs(gp.read("positions") - ref["x"]).max() < 1e-15 and st.status == 0
+            continue
         e = np.array(errors(gp, ref, ep.pad.X, top))
         R, Rref = gp.read("reaction"), ref["cf"]["reaction"]
         eR = np.abs(R - Rref).max() / max(np.abs(Rref).max(), 1e-12)
