@@ -14,7 +14,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import contact, fem, friction, material, surface
+from . import contact, fem, friction, material, mesh_pairs, surface
 
 
 def cauchy_per_tet(pad, x):
@@ -40,8 +40,14 @@ def contact_forces(pad, x, inds, prm, fric=None):
     the step's lagged friction data, is given).
     Returns dict of f, n, area, f_n, f_tau, p, reaction."""
     _, gb, _ = contact.barrier_terms(inds, x[pad.cand], pad.area, prm.dhat, prm.kappa,
-                                     mesh_pairs=prm.mesh_pairs)
+                                     mesh_pairs=bool(prm.mesh_pairs))
     f = -gb
+    for ind in inds:
+        if prm.mesh_pairs == 2 and ind.shape == contact.MESH:
+            # the mesh-vertex/pad-triangle and edge-edge pairs' forces on the
+            # pad's contact vertices
+            f = f - mesh_pairs.pair_terms(ind, x, pad.tris, pad.pedges, pad.pedge_len0, prm.dhat,
+                                          prm.kappa)[1][pad.cand]
     if fric is not None:
         lagged, x_t_c = fric
         f = f - friction.terms(lagged, x[pad.cand], x_t_c, prm.mu_f, prm.eps_v * prm.dt, 1.0)[1]

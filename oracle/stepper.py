@@ -33,7 +33,7 @@ import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from . import contact, fem, friction, material, surface
+from . import contact, fem, friction, material, mesh_pairs, surface
 
 
 ENERGY_NOISE = 1e-12
@@ -68,6 +68,8 @@ class OraclePad:
     is_top: np.ndarray
     cand: np.ndarray
     area: np.ndarray        # rest areas of the candidates (surface.contact_vertex_geometry)
+    pedges: np.ndarray      # surface edges (i < j), for rigid-mesh edge-edge pairs
+    pedge_len0: np.ndarray  # their rest lengths
     L_diag: float
     free: np.ndarray        # [V,3] bool
     x: np.ndarray           # committed state
@@ -92,8 +94,10 @@ def make_pad(X, tets, E, nu, density, fixed=None, literal_alpha=False):
     area = surface.contact_vertex_geometry(X, tris, is_top, cand)[1]
     L = float(np.linalg.norm(X.max(axis=0) - X.min(axis=0)))
     free = np.stack([(fixed >> b) & 1 == 0 for b in range(3)], axis=1)
+    pedges = mesh_pairs.surface_edges(tris)
+    plen = np.linalg.norm(X[pedges[:, 1]] - X[pedges[:, 0]], axis=1)
     return OraclePad(X, tets, mu, lam, alpha, density, Dminv, vol, mass, fixed,
-                     tris, parent, is_top, cand, area, L, free, X.copy(), np.zeros_like(X))
+                     tris, parent, is_top, cand, area, pedges, plen, L, free, X.copy(), np.zeros_like(X))
 
 
 @dataclasses.dataclass
@@ -108,7 +112,8 @@ class StepParams:
     max_halvings: int = 40
     mu_f: float = 0.0        # friction ratio (0 = frictionless)
     eps_v: float = 0.01      # friction velocity threshold [m/s]
-    mesh_pairs: bool = False  # rigid meshes: barrier summed over triangles nearer than d_hat
+    mesh_pairs: int = 0      # rigid meshes: 0 distance to the mesh; 1 barrier summed over the triangles
+                             # nearer than d_hat; 2 that plus mesh-vertex/pad-triangle and edge-edge pairs
 
 
 @dataclasses.dataclass
@@ -126,7 +131,8 @@ def friction_lag(pad, inds, prm, inds_prev=None):
     if prm.mu_f <= 0:
         return None
     prev = inds if inds_prev is None else inds_prev
-    return (friction.lag(prev, inds, pad.x[pad.cand], pad.area, prm.dhat, prm.kappa, mesh_pairs=prm.mesh_pairs),
+    return (friction.lag(prev, inds, pad.x[pad.cand], pad.area, prm.dhat, prm.kappa,
+                         mesh_pairs=bool(prm.mesh_pairs)),
             pad.x[pad.cand].copy())
 
 
@@ -135,12 +141,25 @@ def _friction(pad, x, prm, fric):
     return friction.terms(lagged, x[pad.cand], x_t_c, prm.mu_f, prm.eps_v * prm.dt, prm.dt ** 2)
 
 
+def _pair_meshes(inds, prm):
+    """Rigid mesh indenters that take the mesh-vertex/pad-triangle and
+    edge-edge pairs (mesh_contact 2)."""
+    return [ind for ind in inds if prm.mesh_pairs == 2 and ind.shape == contact.MESH]
+
+
+def _pairs(pad, x, ind, prm):
+    return mesh_pairs.pair_terms(ind, x, pad.tris, pad.pedges, pad.pedge_len0, prm.dhat, prm.kappa)
+
+
 def energy(pad, x, xhat, inds, prm, fric=None):
     """E(x) of the incremental potential (inf if a candidate penetrates)."""
     h2 = prm.dt ** 2
     Eel = float(np.sum(fem.elastic_energy(x, pad.tets, pad.Dminv, pad.vol,
                                           pad.mu, pad.lam, pad.alpha)))
-    Eb, _, _ = contact.barrier_terms(inds, x[pad.cand], pad.area, prm.dhat, prm.kappa, mesh_pairs=prm.mesh_pairs)
+    Eb, _, _ = contact.barrier_terms(inds, x[pad.cand], pad.area, prm.dhat, prm.kappa,
+                                     mesh_pairs=bool(prm.mesh_pairs))
+    for ind in _pair_meshes(inds, prm):
+        Eb += _pairs(pad, x, ind, prm)[0]
     Ein = 0.0 if prm.quasi_static else 0.5 * float(np.sum(pad.mass[:, None] * (x - xhat) ** 2))
     Ef = _friction(pad, x, prm, fric)[0] if fric is not None else 0.0
     return Ein + h2 * (Eel + Eb) + Ef
@@ -151,8 +170,11 @@ def gradient(pad, x, xhat, inds, prm, fric=None):
     h2 = prm.dt ** 2
     ge = fem.elastic_gradient(x, pad.tets, pad.Dminv, pad.vol, pad.mu, pad.lam, pad.alpha)
     g = h2 * fem.scatter_vector(pad.tets, ge, x.shape[0])
-    _, gb, _ = contact.barrier_terms(inds, x[pad.cand], pad.area, prm.dhat, prm.kappa, mesh_pairs=prm.mesh_pairs)
+    _, gb, _ = contact.barrier_terms(inds, x[pad.cand], pad.area, prm.dhat, prm.kappa,
+                                     mesh_pairs=bool(prm.mesh_pairs))
     g[pad.cand] += h2 * gb
+    for ind in _pair_meshes(inds, prm):
+        g += h2 * _pairs(pad, x, ind, prm)[1]
     if fric is not None:
         g[pad.cand] += _friction(pad, x, prm, fric)[1]
     if not prm.quasi_static:
@@ -172,11 +194,19 @@ def hessian(pad, x, inds, prm, project=True, fric=None):
     cols = np.tile(dof, (1, 12)).ravel()
     vals = h2 * Ke.ravel()
     _, _, Hb = contact.barrier_terms(inds, x[pad.cand], pad.area, prm.dhat, prm.kappa, project=project,
-                                     mesh_pairs=prm.mesh_pairs)
+                                     mesh_pairs=bool(prm.mesh_pairs))
     cd = (3 * pad.cand[:, None] + np.arange(3)[None, :])
     rows = np.concatenate([rows, np.repeat(cd, 3, axis=1).ravel()])
     cols = np.concatenate([cols, np.tile(cd, (1, 3)).ravel()])
     vals = np.concatenate([vals, h2 * Hb.ravel()])
+    for ind in _pair_meshes(inds, prm):
+        # Gauss-Newton blocks of the pairs (positive semi-definite)
+        bi, bj, bv = _pairs(pad, x, ind, prm)[2]
+        ri = (3 * bi[:, None, None] + np.arange(3)[None, :, None]) + 0 * np.arange(3)[None, None, :]
+        ci = (3 * bj[:, None, None] + np.arange(3)[None, None, :]) + 0 * np.arange(3)[None, :, None]
+        rows = np.concatenate([rows, ri.ravel()])
+        cols = np.concatenate([cols, ci.ravel()])
+        vals = np.concatenate([vals, h2 * bv.ravel()])
     if fric is not None:
         Hf = _friction(pad, x, prm, fric)[2]
         rows = np.concatenate([rows, np.repeat(cd, 3, axis=1).ravel()])
@@ -199,12 +229,28 @@ def candidate_distances(pad, x, inds):
     return d
 
 
-def feasible_start(pad, x, inds, prm):
+def _travel(ind, ind_prev):
+    """Largest displacement of a rigid mesh's vertices from the previous
+    pose to this one."""
+    if ind_prev is None:
+        return 0.0
+    V = np.asarray(ind.mesh[0], dtype=np.float64)
+    a = V @ np.asarray(ind.R).T + np.asarray(ind.c)[None]
+    b = V @ np.asarray(ind_prev.R).T + np.asarray(ind_prev.c)[None]
+    return float(np.linalg.norm(a - b, axis=1).max())
+
+
+def feasible_start(pad, x, inds, prm, inds_prev=None):
     """Initial guess: push candidates closer than 0.1 d_hat out along
-    grad(phi), free components only, at most 8 rounds."""
+    grad(phi), free components only, at most 8 rounds.  With mesh_contact 2,
+    pad triangles and edges that a rigid mesh's vertex or edge came through
+    (or nearer than 0.1 d_hat to, on their inner side) within the mesh's own
+    travel since the previous pose plus d_hat are pushed back along their
+    outward normal in the same rounds."""
     x = x.copy()
     d_safe = 0.1 * prm.dhat
     free_c = pad.free[pad.cand]
+    prev = inds_prev if inds_prev is not None and len(inds_prev) == len(inds) else [None] * len(inds)
     for _ in range(8):
         moved = False
         for ind in inds:
@@ -213,21 +259,38 @@ def feasible_start(pad, x, inds, prm):
             if low.any():
                 moved = True
                 x[pad.cand[low]] += ((d_safe - phi[low])[:, None] * n[low]) * free_c[low]
+        for ind, ip in zip(inds, prev):
+            if not (prm.mesh_pairs == 2 and ind.shape == contact.MESH):
+                continue
+            window = _travel(ind, ip) + prm.dhat
+            for verts, n, sd in mesh_pairs.signed_pairs(ind, x, pad.tris, pad.pedges, window,
+                                                        below=d_safe * (1.0 - 1e-9)):
+                moved = True
+                x[verts] += (sd - d_safe) * n[None] * pad.free[verts]
         if not moved:
             break
     if np.any(candidate_distances(pad, x, inds) <= 0.0):
         raise Infeasible("indenter pose leaves no feasible start")
+    for ind, ip in zip(inds, prev):
+        if prm.mesh_pairs == 2 and ind.shape == contact.MESH:
+            if mesh_pairs.signed_pairs(ind, x, pad.tris, pad.pedges, _travel(ind, ip) + prm.dhat):
+                raise Infeasible("a rigid mesh stays through the pad surface")
     return x
 
 
-def step_filter(pad, x, p, inds):
-    """alpha_max = min(1, min_k 0.9 d_k / |p_k|)."""
+def step_filter(pad, x, p, inds, prm=None):
+    """alpha_max = min(1, min_k 0.9 d_k / |p_k|), and with mesh_contact 2 the
+    bound of the rigid meshes' vertex-face and edge-edge pairs."""
     d = candidate_distances(pad, x, inds)
     pk = np.linalg.norm(p[pad.cand], axis=1)
     moving = pk > 0
-    if not moving.any():
-        return 1.0
-    return float(min(1.0, np.min(0.9 * d[moving] / pk[moving])))
+    a = 1.0
+    if moving.any():
+        a = float(min(1.0, np.min(0.9 * d[moving] / pk[moving])))
+    if prm is not None:
+        for ind in _pair_meshes(inds, prm):
+            a = min(a, mesh_pairs.step_bound(ind, x, p, pad.tris, pad.pedges))
+    return a
 
 
 def step(pad, inds, prm, solver="direct", cg_tol=1e-12, verbose=False, inds_prev=None):
@@ -238,7 +301,7 @@ def step(pad, inds, prm, solver="direct", cg_tol=1e-12, verbose=False, inds_prev
     x_t, v_t = pad.x, pad.v
     xhat = x_t + h * v_t + h * h * np.asarray(prm.gravity)[None]
     fric = friction_lag(pad, inds, prm, inds_prev)
-    x = feasible_start(pad, x_t, inds, prm)
+    x = feasible_start(pad, x_t, inds, prm, inds_prev)
     free = pad.free.ravel()
     tol = prm.newton_tol * pad.L_diag
     energies = [energy(pad, x, xhat, inds, prm, fric)]
@@ -255,7 +318,7 @@ def step(pad, inds, prm, solver="direct", cg_tol=1e-12, verbose=False, inds_prev
         p = np.zeros_like(g)
         p[free] = pf
         P3 = p.reshape(-1, 3)
-        a = step_filter(pad, x, P3, inds)
+        a = step_filter(pad, x, P3, inds, prm)
         pinf = float(np.max(np.abs(p))) if p.size else 0.0
         if pinf <= tol:
             x = x + a * P3

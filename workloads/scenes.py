@@ -263,6 +263,37 @@ def stiff_skin_episode(nx=12, ny=12, nz=6):
     return Episode(pad, ind, 0.6 * MM, 8, params), idx, mats
 
 
+def corner_press_episode(mesh_contact=2):
+    """A sharp rigid feature between pad vertices: a 2 mm cube as a
+    12-triangle mesh with one corner pointing straight down (body diagonal
+    vertical) over the centroid of a top triangle of a coarse 18x14x4 mm pad
+    (6x5x2 cells, vertices 3 mm apart), its tip d_hat above the surface at
+    step 0, pressed 0.3 mm over 3 steps.  Every pad vertex stays more than
+    1.5 mm from the corner's axis, where the cube's faces rise about 2 mm, so
+    only the corner-against-triangle pair sees the contact."""
+    pad = box_pad(18 * MM, 14 * MM, 4 * MM, 6, 5, 2, Material(0.3e6, 0.45, 1000.0), name="coarse")
+    V, F = meshes.box_surface(1 * MM, 1 * MM, 1 * MM)
+    a = np.ones(3) / math.sqrt(3.0)                    # corner (-1,-1,-1) -> straight down
+    b = np.array([0.0, 0.0, 1.0])
+    k = np.cross(a, b)
+    sk = np.linalg.norm(k)
+    k /= sk
+    th = math.atan2(sk, a @ b)
+    K = np.array([[0, -k[2], k[1]], [k[2], 0, -k[0]], [-k[1], k[0], 0]])
+    R = np.eye(3) + math.sin(th) * K + (1 - math.cos(th)) * K @ K
+    X = pad.X
+    top = np.nonzero(np.isclose(X[:, 2], 4 * MM))[0]
+    # the top-face triangle of the cell left of the pad's centre
+    cx = X[top, 0][np.argmin(np.abs(X[top, 0] - 9 * MM))]
+    cy = X[top, 1][np.argmin(np.abs(X[top, 1] - 7 * MM))]
+    tip_xy = np.array([cx - 2.0 * MM, cy + 0.9 * MM])
+    params = Params()
+    tip = (V @ R.T)[np.argmin((V @ R.T)[:, 2])]
+    c = np.array([tip_xy[0], tip_xy[1], 4 * MM + params.dhat]) - tip
+    ind = Indenter(MESH, (0.0, 0.0, 0.0, 0.0), R, c, mesh=(V, F))
+    return Episode(pad, ind, 0.3 * MM, 3, params, mesh_contact=mesh_contact)
+
+
 def _rot_z(angle):
     c, s = math.cos(angle), math.sin(angle)
     return np.array([[c, -s, 0], [s, c, 0], [0, 0, 1]], float)
