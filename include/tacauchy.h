@@ -465,6 +465,21 @@ tc_status tc_step_batch(tc_context* ctx, int32_t n, tc_pad* const* pads,
  * that produced the positions and come with tc_step's extraction. */
 tc_status tc_extract(tc_pad* pad, int32_t n_ind, const tc_indenter* ind);
 
+/* tc_extract for callers that cannot allocate device memory: code under HIP
+ * stream capture, tight serving loops, harnesses that forbid allocation.  It
+ * allocates nothing (no hipMalloc, hipFree or allocating library call): its
+ * launch descriptor, state, poses, tile lists and partial sums live in one
+ * fixed device array of TC_NOALLOC_SCRATCH_BYTES per device, held from the
+ * first context on that device until the process ends.  The outputs are the
+ * pad's own fields, as with tc_extract, and equal tc_extract's bitwise (same
+ * kernels, same inputs).  reaction (host, [3], may be NULL) receives
+ * -sum_k f_k.  A pad whose tables need more than the array returns
+ * TC_E_INVALID_ARG (the array holds pads up to tens of millions of tets at
+ * the default launch shape).  Every call on a device shares that device's
+ * array: calls through one context are serialised, but calls that overlap on
+ * one device through different contexts race. */
+#define TC_NOALLOC_SCRATCH_BYTES (4u << 20)
+tc_status tc_extract_noalloc(tc_pad* pad, int32_t n_ind, const tc_indenter* ind, double* reaction);
 
 /* Inspection: one Newton direction at the committed positions (taken as the
  * current iterate as they are: no feasible-start projection) under the given

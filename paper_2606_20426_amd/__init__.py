@@ -309,6 +309,13 @@ class Pad:
     def extract(self, indenters: Sequence = ()):
         check(self.lib.tc_extract(self.h, len(indenters), _indenter_array(indenters)))
 
+    def extract_noalloc(self, indenters: Sequence = ()):
+        """tc_extract without any allocation (fixed device scratch);
+        returns the reaction [3]."""
+        r = (C.c_double * 3)()
+        check(self.lib.tc_extract_noalloc(self.h, len(indenters), _indenter_array(indenters), r))
+        return np.array(r[:])
+
     def newton_direction(self, indenters: Sequence = ()):
         """(p, dE/dx) at the committed positions, both [V,3] float64."""
         V = self.info["n_verts"]

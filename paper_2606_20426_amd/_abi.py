@@ -127,6 +127,7 @@ PROTOS = {
     "tc_step": (S, [P, S, C.POINTER(TcIndenter), C.POINTER(TcStepStats)]),
     "tc_step_batch": (S, [P, S, C.POINTER(P), C.POINTER(S), C.POINTER(TcIndenter), C.POINTER(TcStepStats)]),
     "tc_extract": (S, [P, S, C.POINTER(TcIndenter)]),
+    "tc_extract_noalloc": (S, [P, S, C.POINTER(TcIndenter), C.POINTER(C.c_double)]),
     "tc_pad_newton_direction": (S, [P, S, C.POINTER(TcIndenter), C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "tc_field_info": (S, [P, S, C.POINTER(S), C.POINTER(C.c_int64), C.POINTER(S)]),
     "tc_pad_read": (S, [P, S, P, C.c_size_t, S]),

@@ -17,7 +17,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtacauchy.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["kernels.hip", "runtime.hip", "topology.cpp", "server.cpp", "rigid_mesh.cpp", "refine.cpp"]
+SOURCES = ["kernels.hip", "runtime.hip", "topology.cpp", "server.cpp", "rigid_mesh.cpp", "refine.cpp",
+           "noalloc.hip"]
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -210,6 +210,9 @@ tc_status run_batch(tc_context* ctx, int n, tc_pad* const* pads, const int32_t* 
 tc_status newton_direction(tc_pad* pad, int n_ind, const tc_indenter* ind, double* dir, double* grad);
 tc_status ensure_scratch(tc_pad* pad);
 uint64_t next_desc_version();
+// Looks up this device's no-alloc scratch array (device current); once per
+// device, at context creation.
+tc_status noalloc_init(int device);
 // The same, making room within the context budget when it is short: step
 // scratch of pads not in `keep` and not in flight is released (largest
 // first), then arena chunks left entirely free go back to the device.

@@ -1179,6 +1179,10 @@ tc_status tc_context_create(int32_t device, void* hip_stream, uint64_t hbm_budge
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
       return set_error(TC_E_NO_DEVICE, std::string("library is built for gfx950, device is ") + prop.gcnArchName);
     TC_HIP(hipSetDevice(device));
+    {
+      const tc_status ns = noalloc_init(device);
+      if (ns) return ns;
+    }
     auto* ctx = new tc_context();
     ctx->device = device;
     ctx->budget = hbm_budget;
