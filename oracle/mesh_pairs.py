@@ -30,7 +30,7 @@ it.
 Tunnelling: the indenter jumps to its new pose at every step, which can carry
 a mesh corner or edge through a pad triangle or edge that the unsigned
 distances above cannot see.  signed_pairs gives the pairs whose mesh feature
-lies on the inner side of the pad surface within a window (the feature's own
+lies on the inner side of the pad surface within a window (the mesh's
 travel over the step plus d_hat), which the feasible start pushes back.
 """
 from __future__ import annotations
@@ -267,7 +267,9 @@ def signed_pairs(ind, x, tris, pedges, window, below=0.0):
     edge-edge pairs with both closest points inside their segments, signed
     along the pad edge's outward direction (the sum of the normals of the
     pad triangles sharing the edge).  Returns a list of
-    (pad vertex ids [k], outward unit normal [3], signed distance)."""
+    (pad vertex ids [k], outward unit normal [3], signed distance,
+    primitive) with primitive = triangle index for vertex-face pairs and
+    number of triangles + edge index for edge-edge pairs."""
     V0, F = ind.mesh
     _, medges = mesh_tables(V0, F)
     Yw, _ = _world(ind)
@@ -279,7 +281,7 @@ def signed_pairs(ind, x, tris, pedges, window, below=0.0):
     sd = np.einsum("pi,pi->p", Yw[iv] - a, n)
     interior = (lam > 0).all(axis=1)
     for k in np.nonzero(interior & (sd < below))[0]:
-        out.append((tris[it[k]], n[k], float(sd[k])))
+        out.append((tris[it[k]], n[k], float(sd[k]), int(it[k])))
     # outward direction of each pad edge: sum of its triangles' normals
     tn = np.cross(x[tris[:, 1]] - x[tris[:, 0]], x[tris[:, 2]] - x[tris[:, 0]])
     tn /= np.linalg.norm(tn, axis=1)[:, None]
@@ -296,5 +298,5 @@ def signed_pairs(ind, x, tris, pedges, window, below=0.0):
     sd = np.einsum("pi,pi->p", p - q, en[jf])
     interior = (s > 0) & (s < 1) & (t > 0) & (t < 1)
     for k in np.nonzero(interior & (sd < below))[0]:
-        out.append((pedges[jf[k]], en[jf[k]], float(sd[k])))
+        out.append((pedges[jf[k]], en[jf[k]], float(sd[k]), tris.shape[0] + int(jf[k])))
     return out

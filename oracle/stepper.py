@@ -244,9 +244,13 @@ def feasible_start(pad, x, inds, prm, inds_prev=None):
     """Initial guess: push candidates closer than 0.1 d_hat out along
     grad(phi), free components only, at most 8 rounds.  With mesh_contact 2,
     pad triangles and edges that a rigid mesh's vertex or edge came through
-    (or nearer than 0.1 d_hat to, on their inner side) within the mesh's own
+    (or nearer than 0.1 d_hat to, on their inner side) within the mesh's
     travel since the previous pose plus d_hat are pushed back along their
-    outward normal in the same rounds."""
+    outward normal in the same rounds (reading): a primitive asks its
+    vertices to move by (sd - 0.1 d_hat) n for its deepest pair, and each
+    vertex takes the largest push asked of it (the first primitive, in
+    order, on ties; triangles before edges), so that pushes from the
+    primitives around a vertex do not add up past the barrier's reach."""
     x = x.copy()
     d_safe = 0.1 * prm.dhat
     free_c = pad.free[pad.cand]
@@ -263,10 +267,20 @@ def feasible_start(pad, x, inds, prm, inds_prev=None):
             if not (prm.mesh_pairs == 2 and ind.shape == contact.MESH):
                 continue
             window = _travel(ind, ip) + prm.dhat
-            for verts, n, sd in mesh_pairs.signed_pairs(ind, x, pad.tris, pad.pedges, window,
-                                                        below=d_safe * (1.0 - 1e-9)):
+            deepest = {}
+            for verts, n, sd, prim in mesh_pairs.signed_pairs(ind, x, pad.tris, pad.pedges, window,
+                                                              below=d_safe * (1.0 - 1e-9)):
+                if prim not in deepest or sd < deepest[prim][2]:
+                    deepest[prim] = (verts, n, sd)
+            push = {}
+            for prim in sorted(deepest):
+                verts, n, sd = deepest[prim]
+                for v in verts:
+                    if int(v) not in push or d_safe - sd > push[int(v)][0]:
+                        push[int(v)] = (d_safe - sd, (sd - d_safe) * n)
+            for v, (_, dv) in push.items():
                 moved = True
-                x[verts] += (sd - d_safe) * n[None] * pad.free[verts]
+                x[v] += dv * pad.free[v]
         if not moved:
             break
     if np.any(candidate_distances(pad, x, inds) <= 0.0):
