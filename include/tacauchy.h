@@ -206,8 +206,29 @@ typedef struct {
                            bound and the feasible start use phi in both
                            modes.  With friction, mode 1 lags lambda n =
                            -kappa A sum_t b'(d_t / d_hat) grad d_t (lambda
-                           its length, n its direction).  Analytic shapes
-                           ignore it. */
+                           its length, n its direction).  2 = mode 1
+                           plus the pairs whose pad side is a surface
+                           triangle or edge (IPC's other primitives, Sec.
+                           III-B): every mesh vertex y against every pad
+                           surface triangle t, kappa a_y d_hat b(d / d_hat)
+                           with a_y a third of the area of y's mesh
+                           triangles; every mesh edge e against every pad
+                           surface edge f, kappa (|e| |f|_0 / 4) d_hat m(c)
+                           b(d / d_hat) with IPC's mollifier m(c) = (2 -
+                           c/c0) c/c0 below c0 = 1e-3 |e|^2 |f|_0^2 (1
+                           above), c = |e x f|^2 (|f|_0 the rest length);
+                           d the distance between the closed features.
+                           Their Hessians are Gauss-Newton (PSD); their
+                           step bound is alpha <= 0.9 d / max |p| over the
+                           pad feature's vertices; the feasible start also
+                           pushes a pad triangle or edge that a mesh vertex
+                           or edge came through (within the mesh's travel
+                           since the previous pose plus d_hat) back along
+                           its outward normal, and fails with
+                           TC_E_INFEASIBLE if one stays through.  A mesh
+                           corner or edge pressed between pad vertices is
+                           then seen.  Friction takes the pad-vertex pairs
+                           only.  Analytic shapes ignore it. */
   double friction;      /* friction ratio mu >= 0 of the lagged smoothed
                            Coulomb friction against the indenters (Sec.
                            III-B: 0.5); 0 = frictionless.  Per contact
@@ -475,7 +496,9 @@ tc_status tc_extract(tc_pad* pad, int32_t n_ind, const tc_indenter* ind);
  * kernels, same inputs).  reaction (host, [3], may be NULL) receives
  * -sum_k f_k.  A pad whose tables need more than the array returns
  * TC_E_INVALID_ARG (the array holds pads up to tens of millions of tets at
- * the default launch shape).  Every call on a device shares that device's
+ * the default launch shape), and so does a pad with vertex-face / edge-edge
+ * pairs on (mesh_contact 2 with a TC_MESH indenter), whose pair records
+ * live in its step scratch.  Every call on a device shares that device's
  * array: calls through one context are serialised, but calls that overlap on
  * one device through different contexts race. */
 #define TC_NOALLOC_SCRATCH_BYTES (4u << 20)

@@ -581,6 +581,266 @@ __device__ __forceinline__ void load3(const double* p, int i, double v[3]) {
   v[0] = p[3 * i]; v[1] = p[3 * i + 1]; v[2] = p[3 * i + 2];
 }
 
+// ------------------------------------------------ rigid-mesh pairs (mesh_contact 2)
+
+// IPC's contact primitives between two surfaces are point-triangle and
+// edge-edge pairs, both ways (Sec. III-B).  Besides the pad-vertex pairs
+// above, mesh_contact 2 takes the two kinds whose pad side is a surface
+// triangle or a surface edge:
+//   vertex-face: mesh vertex y against pad triangle t, kappa a_y d_hat
+//     b(d / d_hat), a_y a third of the area of y's mesh triangles;
+//   edge-edge: mesh edge e against pad surface edge f, kappa w d_hat m(c)
+//     b(d / d_hat) with w = |e| |f|_0 / 4 and IPC's mollifier m(c) =
+//     (2 - c / c0) c / c0 below c0 = 1e-3 |e|^2 |f|_0^2 (1 above), c =
+//     |e x f|^2: the term fades out as the edges turn parallel.
+// d is the distance between the closed features.  With q = sum_a lam_a x_a
+// the pad's closest point and u the unit vector from q to the mesh's
+// closest point, dd/dx_a = -lam_a u (envelope theorem); dc/dx_1 = 2 (|e|^2
+// f - (e.f) e) = -dc/dx_0.  Hessians are Gauss-Newton, w m b''/d_hat
+// (grad d)(grad d)^T, positive semi-definite.
+//
+// Pad primitives are numbered j < S (surface triangles) and S + f (surface
+// edges).  The mesh side is found through the mesh's hierarchy with the
+// primitive's box grown by the query radius; a mesh vertex or edge is met
+// once, through the leaf triangle that owns it.
+
+// One pair as the kernels use it (world frame).
+struct PairTerm {
+  double d;         // distance between the features
+  double lam[3];    // weights of the pad primitive's vertices at its closest point
+  double u[3];      // unit vector from the pad's closest point to the mesh's (0 when d = 0)
+  double diff[3];   // the same vector unnormalised
+  double wt;        // weight without kappa: a_y, or |e| |f|_0 / 4
+  double m, dm;     // mollifier and dm/dc (1 and 0 for vertex-face)
+  double dc1[3];    // dc/dx_1 of the pad edge (edge-edge)
+  bool interior;    // both closest points interior to their features
+};
+
+// Closest point of triangle (a, b, c) to y by Voronoi regions (Ericson,
+// Real-Time Collision Detection, 2005, Sec. 5.1.5), as barycentric weights;
+// returns |y - q|^2 and diff = y - q.
+__device__ double pt_tri_lam(const double y[3], const double a[3], const double b[3], const double c[3],
+                             double lam[3], double diff[3]) {
+  double ab[3], ac[3], ap[3], bp[3], cp[3];
+  for (int i = 0; i < 3; ++i) {
+    ab[i] = b[i] - a[i]; ac[i] = c[i] - a[i]; ap[i] = y[i] - a[i]; bp[i] = y[i] - b[i]; cp[i] = y[i] - c[i];
+  }
+  auto dot = [](const double* p, const double* q) { return p[0] * q[0] + p[1] * q[1] + p[2] * q[2]; };
+  const double d1 = dot(ab, ap), d2 = dot(ac, ap);
+  const double d3 = dot(ab, bp), d4 = dot(ac, bp);
+  const double d5 = dot(ab, cp), d6 = dot(ac, cp);
+  const double vc = d1 * d4 - d3 * d2, vb = d5 * d2 - d1 * d6, va = d3 * d6 - d5 * d4;
+  if (d1 <= 0 && d2 <= 0) {
+    lam[0] = 1; lam[1] = 0; lam[2] = 0;
+  } else if (d3 >= 0 && d4 <= d3) {
+    lam[0] = 0; lam[1] = 1; lam[2] = 0;
+  } else if (vc <= 0 && d1 >= 0 && d3 <= 0) {
+    const double v = d1 / (d1 - d3);
+    lam[0] = 1 - v; lam[1] = v; lam[2] = 0;
+  } else if (d6 >= 0 && d5 <= d6) {
+    lam[0] = 0; lam[1] = 0; lam[2] = 1;
+  } else if (vb <= 0 && d2 >= 0 && d6 <= 0) {
+    const double w = d2 / (d2 - d6);
+    lam[0] = 1 - w; lam[1] = 0; lam[2] = w;
+  } else if (va <= 0 && d4 - d3 >= 0 && d5 - d6 >= 0) {
+    const double w = (d4 - d3) / ((d4 - d3) + (d5 - d6));
+    lam[0] = 0; lam[1] = 1 - w; lam[2] = w;
+  } else {
+    const double den = 1.0 / (va + vb + vc);
+    const double v = vb * den, w = vc * den;
+    lam[0] = 1 - v - w; lam[1] = v; lam[2] = w;
+  }
+  double s = 0.0;
+  for (int i = 0; i < 3; ++i) {
+    diff[i] = y[i] - (lam[0] * a[i] + lam[1] * b[i] + lam[2] * c[i]);
+    s += diff[i] * diff[i];
+  }
+  return s;
+}
+
+// Closest points of segments p0 p1 and q0 q1 (Ericson, Sec. 5.1.9): the
+// lines' closest point parameter s on the first, clamped to [0, 1], the
+// second's t for it, and if t leaves [0, 1] the clamped t with s recomputed.
+// Parallel segments (denominator <= 1e-14 |d1|^2 |d2|^2) start from s = 0.
+// Returns |p - q|^2 and diff = p - q.
+__device__ double seg_seg(const double p0[3], const double p1[3], const double q0[3], const double q1[3],
+                          double& s, double& t, double diff[3]) {
+  double d1[3], d2[3], r[3];
+  for (int i = 0; i < 3; ++i) { d1[i] = p1[i] - p0[i]; d2[i] = q1[i] - q0[i]; r[i] = p0[i] - q0[i]; }
+  const double a = d1[0] * d1[0] + d1[1] * d1[1] + d1[2] * d1[2];
+  const double e = d2[0] * d2[0] + d2[1] * d2[1] + d2[2] * d2[2];
+  const double f = d2[0] * r[0] + d2[1] * r[1] + d2[2] * r[2];
+  const double c = d1[0] * r[0] + d1[1] * r[1] + d1[2] * r[2];
+  const double b = d1[0] * d2[0] + d1[1] * d2[1] + d1[2] * d2[2];
+  const double den = a * e - b * b;
+  s = den > 1e-14 * a * e ? fmin(fmax((b * f - c * e) / den, 0.0), 1.0) : 0.0;
+  t = (b * s + f) / e;
+  if (t < 0.0) {
+    t = 0.0;
+    s = fmin(fmax(-c / a, 0.0), 1.0);
+  } else if (t > 1.0) {
+    t = 1.0;
+    s = fmin(fmax((b - c) / a, 0.0), 1.0);
+  }
+  double q = 0.0;
+  for (int i = 0; i < 3; ++i) {
+    diff[i] = (p0[i] + s * d1[i]) - (q0[i] + t * d2[i]);
+    q += diff[i] * diff[i];
+  }
+  return q;
+}
+
+// Leaves of M's hierarchy whose boxes meet [lo, hi]: leaf(s) per triangle
+// slot s.
+template <typename Leaf>
+__device__ void bvh_overlap(const DevMesh& M, const double lo[3], const double hi[3], Leaf&& leaf) {
+  int stack[BVH_STACK];
+  int sp = 0;
+  stack[sp++] = 0;
+  while (sp > 0) {
+    const BvhNode& nd = M.nodes[stack[--sp]];
+    if (nd.lo[0] > hi[0] || nd.hi[0] < lo[0] || nd.lo[1] > hi[1] || nd.hi[1] < lo[1] || nd.lo[2] > hi[2] ||
+        nd.hi[2] < lo[2])
+      continue;
+    if (nd.count > 0) {
+      for (int s = nd.first; s < nd.first + nd.count; ++s) leaf(s);
+    } else if (sp + 2 <= BVH_STACK) {
+      stack[sp++] = nd.first;
+      stack[sp++] = (int)(&nd - M.nodes) + 1;
+    }
+  }
+}
+
+__device__ __forceinline__ bool pair_active(const EnvDesc& E, const EnvPose* P) {
+  return E.n_pt > 0 && P->pairs != 0;
+}
+
+// World positions of pad primitive j's vertices (3 for a triangle, 2 for an
+// edge) from x; returns the count.
+__device__ __forceinline__ int prim_verts(const EnvDesc& E, int j, int vid[3]) {
+  if (j < E.S) {
+    vid[0] = E.tris[3 * j]; vid[1] = E.tris[3 * j + 1]; vid[2] = E.tris[3 * j + 2];
+    return 3;
+  }
+  const int f = j - E.S;
+  vid[0] = E.sedge[2 * f]; vid[1] = E.sedge[2 * f + 1]; vid[2] = -1;
+  return 2;
+}
+
+// Every pair of pad primitive j (vertices xw, world) with the mesh
+// indenters nearer than r[m]: fn(m, PairTerm).
+template <typename Fn>
+__device__ void visit_pairs(const EnvDesc& E, const EnvPose* P, int j, const double xw[3][3], const double* r,
+                            Fn&& fn) {
+  const bool tri = j < E.S;
+  const int nv = tri ? 3 : 2;
+  const double len0 = tri ? 0.0 : E.sedge_len0[j - E.S];
+  for (int m = 0; m < P->n_ind; ++m) {
+    const DevIndenter& I = P->ind[m];
+    if (I.shape != TC_MESH || !(r[m] > 0.0)) continue;
+    const DevMesh& M = E.meshes[I.reserved];
+    double xl[3][3], lo[3], hi[3];
+    for (int k = 0; k < nv; ++k)
+      for (int i = 0; i < 3; ++i)
+        xl[k][i] = I.R[0 * 3 + i] * (xw[k][0] - I.c[0]) + I.R[1 * 3 + i] * (xw[k][1] - I.c[1]) +
+                   I.R[2 * 3 + i] * (xw[k][2] - I.c[2]);
+    for (int i = 0; i < 3; ++i) {
+      lo[i] = xl[0][i];
+      hi[i] = xl[0][i];
+      for (int k = 1; k < nv; ++k) { lo[i] = fmin(lo[i], xl[k][i]); hi[i] = fmax(hi[i], xl[k][i]); }
+      lo[i] -= r[m];
+      hi[i] += r[m];
+    }
+    const double r2 = r[m] * r[m];
+    auto world = [&](const double* l, double* w) {
+      for (int i = 0; i < 3; ++i) w[i] = I.R[i * 3 + 0] * l[0] + I.R[i * 3 + 1] * l[1] + I.R[i * 3 + 2] * l[2];
+    };
+    auto outside = [&](const double* y) {
+      return y[0] < lo[0] || y[0] > hi[0] || y[1] < lo[1] || y[1] > hi[1] || y[2] < lo[2] || y[2] > hi[2];
+    };
+    bvh_overlap(M, lo, hi, [&](int s) {
+      const unsigned own = M.own[s];
+      const int32_t* id = M.tid + 6 * (size_t)s;
+      for (int k = 0; k < 3; ++k) {
+        PairTerm pt;
+        double dl[3];
+        if (tri) {
+          if (!((own >> k) & 1u)) continue;
+          const int v = id[k];
+          const double* y = M.mv + 3 * (size_t)v;
+          if (outside(y)) continue;
+          const double d2 = pt_tri_lam(y, xl[0], xl[1], xl[2], pt.lam, dl);
+          if (!(d2 < r2)) continue;
+          pt.d = sqrt(d2);
+          pt.wt = M.va[v];
+          pt.m = 1.0;
+          pt.dm = 0.0;
+          pt.dc1[0] = pt.dc1[1] = pt.dc1[2] = 0.0;
+          pt.interior = pt.lam[0] > 0 && pt.lam[1] > 0 && pt.lam[2] > 0;
+        } else {
+          if (!((own >> (3 + k)) & 1u)) continue;
+          const int e = id[3 + k];
+          const double* p0 = M.mv + 3 * (size_t)M.me[2 * e];
+          const double* p1 = M.mv + 3 * (size_t)M.me[2 * e + 1];
+          if (fmin(p0[0], p1[0]) > hi[0] || fmax(p0[0], p1[0]) < lo[0] || fmin(p0[1], p1[1]) > hi[1] ||
+              fmax(p0[1], p1[1]) < lo[1] || fmin(p0[2], p1[2]) > hi[2] || fmax(p0[2], p1[2]) < lo[2])
+            continue;
+          double sp, tp;
+          const double d2 = seg_seg(p0, p1, xl[0], xl[1], sp, tp, dl);
+          if (!(d2 < r2)) continue;
+          pt.d = sqrt(d2);
+          pt.lam[0] = 1.0 - tp; pt.lam[1] = tp; pt.lam[2] = 0.0;
+          const double le = M.mel[e];
+          pt.wt = 0.25 * le * len0;
+          double ev[3], fv[3], cr[3];
+          for (int i = 0; i < 3; ++i) { ev[i] = p1[i] - p0[i]; fv[i] = xl[1][i] - xl[0][i]; }
+          cr[0] = ev[1] * fv[2] - ev[2] * fv[1];
+          cr[1] = ev[2] * fv[0] - ev[0] * fv[2];
+          cr[2] = ev[0] * fv[1] - ev[1] * fv[0];
+          const double cc = cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2];
+          const double c0 = 1e-3 * le * le * len0 * len0;
+          const double xq = cc / c0;
+          pt.m = xq < 1.0 ? (2.0 - xq) * xq : 1.0;
+          pt.dm = xq < 1.0 ? (2.0 - 2.0 * xq) / c0 : 0.0;
+          const double ee = ev[0] * ev[0] + ev[1] * ev[1] + ev[2] * ev[2];
+          const double ef = ev[0] * fv[0] + ev[1] * fv[1] + ev[2] * fv[2];
+          double dcl[3];
+          for (int i = 0; i < 3; ++i) dcl[i] = 2.0 * (ee * fv[i] - ef * ev[i]);
+          world(dcl, pt.dc1);
+          pt.interior = sp > 0.0 && sp < 1.0 && tp > 0.0 && tp < 1.0;
+        }
+        world(dl, pt.diff);
+        const double id_ = pt.d > 0.0 ? 1.0 / pt.d : 0.0;
+        for (int i = 0; i < 3; ++i) pt.u[i] = pt.diff[i] * id_;
+        fn(m, pt);
+      }
+    });
+  }
+}
+
+// Loads pad primitive j's vertex positions x (+ al * d when d is given).
+template <typename R>
+__device__ __forceinline__ int prim_load(const EnvDesc& E, int j, const double* x, const R* d, double al, int vid[3],
+                                         double xw[3][3]) {
+  const int nv = prim_verts(E, j, vid);
+  for (int k = 0; k < nv; ++k)
+    for (int c = 0; c < 3; ++c)
+      xw[k][c] = x[3 * vid[k] + c] + (d ? al * (double)d[3 * vid[k] + c] : 0.0);
+  return nv;
+}
+
+// Pair energy of primitive j at positions xw (barrier units: the h^2 factor
+// is the caller's); +inf for a touching pair.
+__device__ double prim_pair_energy(const EnvDesc& E, const EnvPose* P, int j, const double xw[3][3]) {
+  double r[MAX_IND];
+  for (int m = 0; m < MAX_IND; ++m) r[m] = E.dhat;
+  double e = 0.0;
+  visit_pairs(E, P, j, xw, r, [&](int, const PairTerm& pt) {
+    if (pt.m > 0.0) e += E.kappa * pt.wt * E.dhat * pt.m * bar0(pt.d / E.dhat);
+  });
+  return e;
+}
+
 // ------------------------------------------------ friction (lagged, smoothed)
 
 // C1 mollifier of the slip y with threshold eps: f0 (potential), f1 = f0'
@@ -824,13 +1084,18 @@ __global__ void k_predict(const Tile* tiles, int ntiles, const EnvDesc* envs) {
 
 // Feasible start: contact vertices closer than 0.1 d_hat to an indenter are
 // pushed out along grad(phi) (free components only), at most 8 rounds.
-__global__ void k_project(const Tile* tiles, int ntiles, const EnvDesc* envs) {
+// mode 0: all rounds, then the check phi > 0 (pads without pairs); for pads
+// with vertex-face / edge-edge pairs the rounds alternate with the
+// primitives' pushes (k_pair_push, k_pair_apply): mode 1 is one round,
+// mode 2 the check.
+__global__ void k_project(const Tile* tiles, int ntiles, const EnvDesc* envs, int mode) {
   const int t = xcd_tile(ntiles);
   if (t < 0) return;
   const EnvDesc& E = envs[tiles[t].env];
   EnvState* S = E.st;
   const EnvPose* P = E.pose;
   if (!initialising(S)) return;
+  if (pair_active(E, P) != (mode != 0)) return;
   const int k = tiles[t].tile * blockDim.x + threadIdx.x;
   if (k >= E.C) return;
   const int vi = E.cand[k];
@@ -839,7 +1104,8 @@ __global__ void k_project(const Tile* tiles, int ntiles, const EnvDesc* envs) {
   load3(E.xn, vi, x);
   const double dsafe = 0.1 * E.dhat;
   double H[3][3];
-  for (int round = 0; round < 8; ++round) {
+  const int rounds = mode == 0 ? 8 : mode == 1 ? 1 : 0;
+  for (int round = 0; round < rounds; ++round) {
     bool moved = false;
     for (int m = 0; m < P->n_ind; ++m) {
       double phi, g[3];
@@ -852,13 +1118,14 @@ __global__ void k_project(const Tile* tiles, int ntiles, const EnvDesc* envs) {
     }
     if (!moved) break;
   }
+  for (int c = 0; c < 3; ++c) E.xn[3 * vi + c] = x[c];
+  if (mode == 1) return;
   double dmin = INFINITY;
   for (int m = 0; m < P->n_ind; ++m) {
     double phi, g[3];
     sdf_world(P->ind[m], E.meshes, x, phi, g, H, false);
     dmin = fmin(dmin, phi);
   }
-  for (int c = 0; c < 3; ++c) E.xn[3 * vi + c] = x[c];
   if (!(dmin > 0.0)) atomicOr(&S->infeasible, 1);
 }
 
@@ -1060,6 +1327,228 @@ __global__ void __launch_bounds__(256) k_element(const Tile* tiles, int ntiles, 
   edge_out(3, 1, 2); edge_out(4, 1, 3); edge_out(5, 2, 3);
 }
 
+// ------------------------------------------------------ rigid-mesh pairs (a4, mesh_contact 2)
+
+__device__ __forceinline__ bool extract_ok(const EnvState* S);
+
+// Pair records at the Newton iterate (mode 0, pads running) or at the
+// extraction positions (mode 1): gradient and Gauss-Newton blocks of every
+// surface primitive's pairs within d_hat, flag 0 for a primitive without
+// pairs (its record is then not written).
+__global__ void k_pairs(const Tile* tiles, int ntiles, const EnvDesc* envs, int mode) {
+  const int t = xcd_tile(ntiles);
+  if (t < 0) return;
+  const EnvDesc& E = envs[tiles[t].env];
+  const EnvState* S = E.st;
+  const EnvPose* P = E.pose;
+  if (mode == 0 ? !running(S) : !extract_ok(S)) return;
+  if (!pair_active(E, P)) return;
+  const int j = tiles[t].tile * blockDim.x + threadIdx.x;
+  if (j >= E.S + E.Se) return;
+  const double* x = (mode == 1 && S->mode == 1) ? E.x : E.xn;
+  int vid[3];
+  double xw[3][3];
+  prim_load<double>(E, j, x, nullptr, 0.0, vid, xw);
+  double g[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, B[6][6];
+  for (int q = 0; q < 6; ++q)
+    for (int c = 0; c < 6; ++c) B[q][c] = 0.0;
+  double r[MAX_IND];
+  for (int m = 0; m < MAX_IND; ++m) r[m] = E.dhat;
+  int n = 0;
+  // vertex pairs of the blocks (0,0) (1,1) (2,2) (0,1) (1,2) (2,0)
+  const int ba[6] = {0, 1, 2, 0, 1, 2}, bc[6] = {0, 1, 2, 1, 2, 0};
+  visit_pairs(E, P, j, xw, r, [&](int, const PairTerm& pt) {
+    ++n;
+    const double s = pt.d / E.dhat;
+    const double w = E.kappa * pt.wt;
+    const double b0 = bar0(s), b1 = bar1(s), b2 = bar2(s);
+    for (int a = 0; a < 3; ++a)
+      for (int i = 0; i < 3; ++i) {
+        // w d_hat dm b sign(a) dc/dx_1 (edge-edge) + w m b' dd/dx_a
+        double ga = -w * pt.m * b1 * pt.lam[a] * pt.u[i];
+        if (pt.dm != 0.0 && a < 2) ga += w * E.dhat * pt.dm * b0 * (a == 1 ? 1.0 : -1.0) * pt.dc1[i];
+        g[a][i] += ga;
+      }
+    const double c2 = w * pt.m * b2 / E.dhat;
+    const double uu[6] = {pt.u[0] * pt.u[0], pt.u[0] * pt.u[1], pt.u[0] * pt.u[2],
+                          pt.u[1] * pt.u[1], pt.u[1] * pt.u[2], pt.u[2] * pt.u[2]};
+    for (int q = 0; q < 6; ++q) {
+      const double cq = c2 * pt.lam[ba[q]] * pt.lam[bc[q]];
+      for (int c = 0; c < 6; ++c) B[q][c] += cq * uu[c];
+    }
+  });
+  E.pflag[j] = n > 0;
+  if (n == 0) return;
+  double* rec = E.prec + (size_t)PREC * j;
+  for (int a = 0; a < 3; ++a)
+    for (int i = 0; i < 3; ++i) rec[3 * a + i] = g[a][i];
+  for (int q = 0; q < 6; ++q)
+    for (int c = 0; c < 6; ++c) rec[9 + 6 * q + c] = B[q][c];
+}
+
+// Outward direction of pad primitive j at positions x: a triangle's unit
+// normal, or for a surface edge the normalised sum of its two triangles'.
+__device__ __forceinline__ void prim_outward(const EnvDesc& E, int j, const double* x, double n[3]) {
+  auto tri_n = [&](int tj, double* o) {
+    const int a = E.tris[3 * tj], b = E.tris[3 * tj + 1], c = E.tris[3 * tj + 2];
+    double e1[3], e2[3];
+    for (int i = 0; i < 3; ++i) { e1[i] = x[3 * b + i] - x[3 * a + i]; e2[i] = x[3 * c + i] - x[3 * a + i]; }
+    const double cr[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+    const double L = sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+    for (int i = 0; i < 3; ++i) o[i] += cr[i] / L;
+  };
+  n[0] = n[1] = n[2] = 0.0;
+  if (j < E.S) {
+    tri_n(j, n);
+    return;
+  }
+  const int f = j - E.S;
+  for (int q = 0; q < 2; ++q) {
+    const int code = E.sedge_adj[2 * f + q];
+    if (code >= 0) tri_n(code >> 3, n);
+  }
+  const double L = sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+  for (int i = 0; i < 3; ++i) n[i] /= L;
+}
+
+// Feasible start, pads with pairs: a mesh vertex or edge that the
+// indenter's jump to its new pose carried through the pad surface shows as
+// a pair with both closest points interior and the mesh feature on the
+// inner side.  mode 0: a primitive whose pairs (within the mesh's travel
+// plus d_hat) come below d_safe along its outward direction n asks its
+// vertices to move by (sd - d_safe) n for its deepest pair: the push and
+// its length go to its record, and k_pair_apply moves each vertex by the
+// longest push asked of it.  mode 1 (after the last round): any pair still
+// on the inner side makes the start infeasible.
+__global__ void k_pair_push(const Tile* tiles, int ntiles, const EnvDesc* envs, int mode) {
+  const int t = xcd_tile(ntiles);
+  if (t < 0) return;
+  const EnvDesc& E = envs[tiles[t].env];
+  EnvState* S = E.st;
+  const EnvPose* P = E.pose;
+  if (!initialising(S) || !pair_active(E, P)) return;
+  const int j = tiles[t].tile * blockDim.x + threadIdx.x;
+  if (j >= E.S + E.Se) return;
+  int vid[3];
+  double xw[3][3];
+  prim_load<double>(E, j, E.xn, nullptr, 0.0, vid, xw);
+  double r[MAX_IND];
+  for (int m = 0; m < MAX_IND; ++m) r[m] = P->travel[m] + E.dhat;
+  double n[3];
+  prim_outward(E, j, E.xn, n);
+  const double dsafe = 0.1 * E.dhat;
+  const double below = mode == 0 ? dsafe * (1.0 - 1e-9) : 0.0;
+  double sdmin = INFINITY;
+  int cnt = 0;
+  visit_pairs(E, P, j, xw, r, [&](int, const PairTerm& pt) {
+    if (!pt.interior) return;
+    const double sd = pt.diff[0] * n[0] + pt.diff[1] * n[1] + pt.diff[2] * n[2];
+    if (!(sd < below)) return;
+    ++cnt;
+    sdmin = fmin(sdmin, sd);
+  });
+  if (mode == 1) {
+    if (cnt) atomicOr(&S->infeasible, 1);
+    return;
+  }
+  E.pflag[j] = cnt > 0;
+  if (cnt == 0) return;
+  double* rec = E.prec + (size_t)PREC * j;
+  for (int i = 0; i < 3; ++i) rec[i] = (sdmin - dsafe) * n[i];
+  rec[3] = dsafe - sdmin;
+}
+
+// Feasible start, pads with pairs: each contact vertex moves by the
+// longest push its surface primitives ask of it (the first primitive in
+// order on ties: triangles by index, then edges), free components only.
+__global__ void k_pair_apply(const Tile* tiles, int ntiles, const EnvDesc* envs) {
+  const int t = xcd_tile(ntiles);
+  if (t < 0) return;
+  const EnvDesc& E = envs[tiles[t].env];
+  const EnvState* S = E.st;
+  if (!initialising(S) || !pair_active(E, E.pose)) return;
+  const int k = tiles[t].tile * blockDim.x + threadIdx.x;
+  if (k >= E.C) return;
+  const double* best = nullptr;
+  for (int c = E.vp_ptr[k]; c < E.vp_ptr[k + 1]; ++c) {
+    const int j = E.vp_idx[c] >> 2;
+    if (!E.pflag[j]) continue;
+    const double* rec = E.prec + (size_t)PREC * j;
+    if (!best || rec[3] > best[3]) best = rec;
+  }
+  if (!best) return;
+  const double dx[3] = {best[0], best[1], best[2]};
+  const int vi = E.cand[k];
+  const uint8_t fm = E.fixed[vi];
+  for (int i = 0; i < 3; ++i)
+    if (!((fm >> i) & 1)) E.xn[3 * vi + i] += dx[i];
+}
+
+// Pair gradient (and with H the Gauss-Newton diagonal block) of contact
+// vertex k gathered from its primitives' records.
+__device__ __forceinline__ void pair_gather(const EnvDesc& E, int k, double g[3], double (*H)[3]) {
+  for (int c = E.vp_ptr[k]; c < E.vp_ptr[k + 1]; ++c) {
+    const int code = E.vp_idx[c];
+    const int j = code >> 2, a = code & 3;
+    if (!E.pflag[j]) continue;
+    const double* rec = E.prec + (size_t)PREC * j;
+    for (int i = 0; i < 3; ++i) g[i] += rec[3 * a + i];
+    if (H) {
+      const double* b = rec + 9 + 6 * a;
+      H[0][0] += b[0]; H[0][1] += b[1]; H[0][2] += b[2];
+      H[1][0] += b[1]; H[1][1] += b[3]; H[1][2] += b[4];
+      H[2][0] += b[2]; H[2][1] += b[4]; H[2][2] += b[5];
+    }
+  }
+}
+
+// Pair Gauss-Newton block between the ends of unique edge k (symmetric, 6
+// values) when it is a surface edge: its two triangles' blocks plus its own
+// edge-edge block.  Returns false when there is none.
+__device__ __forceinline__ bool pair_edge_block(const EnvDesc& E, int k, double b[6]) {
+  const int f = E.edge_sedge[k];
+  if (f < 0) return false;
+  bool any = false;
+  for (int c = 0; c < 6; ++c) b[c] = 0.0;
+  for (int q = 0; q < 2; ++q) {
+    const int code = E.sedge_adj[2 * f + q];
+    if (code < 0 || !E.pflag[code >> 3]) continue;
+    const double* r = E.prec + (size_t)PREC * (code >> 3) + 9 + 6 * (code & 7);
+    for (int c = 0; c < 6; ++c) b[c] += r[c];
+    any = true;
+  }
+  const int j = E.S + f;
+  if (E.pflag[j]) {
+    const double* r = E.prec + (size_t)PREC * j + 9 + 6 * 3;
+    for (int c = 0; c < 6; ++c) b[c] += r[c];
+    any = true;
+  }
+  return any;
+}
+
+// Collision-free step bound of pad primitive j moving by alpha p (p the
+// direction at its vertices): the distance to a fixed mesh feature shrinks
+// at most by alpha max_a |p_a|, so alpha <= 0.9 d / max |p_a| keeps every
+// pair apart; pairs farther than FILTER_SPAN max |p_a| / 0.9 cannot bind.
+template <typename R>
+__device__ double prim_pair_bound(const EnvDesc& E, const EnvPose* P, int j, const R* d, double span) {
+  int vid[3];
+  double xw[3][3];
+  const int nv = prim_load<R>(E, j, E.xn, nullptr, 0.0, vid, xw);
+  double pm = 0.0;
+  for (int k = 0; k < nv; ++k) {
+    double q = 0.0;
+    for (int c = 0; c < 3; ++c) q += (double)d[3 * vid[k] + c] * (double)d[3 * vid[k] + c];
+    pm = fmax(pm, sqrt(q));
+  }
+  if (!(pm > 0.0)) return INFINITY;
+  double r[MAX_IND];
+  for (int m = 0; m < MAX_IND; ++m) r[m] = span * pm / 0.9;
+  double a = INFINITY;
+  visit_pairs(E, P, j, xw, r, [&](int, const PairTerm& pt) { a = fmin(a, 0.9 * pt.d / pm); });
+  return a;
+}
+
 // ------------------------------------------------------ barrier (a4)
 
 __device__ void project_psd3(double H[3][3]) {
@@ -1129,6 +1618,9 @@ __global__ void k_barrier(const Tile* tiles, int ntiles, const EnvDesc* envs) {
     for (int i = 0; i < 3; ++i)
       for (int j = 0; j < 3; ++j) H[i][j] = Hn[i][j];
   }
+  // vertex-face and edge-edge pairs of the vertex's surface primitives
+  // (Gauss-Newton, PSD: added after the filter)
+  if (pair_active(E, P)) pair_gather(E, k, g, H);
   // lagged friction (PSD by construction, added after the filter):
   // gradient mu lambda (f1/y) u, Hessian mu lambda [f1/y (P - uh uh^T) +
   // f1' uh uh^T] with P = I - n n^T and uh = u / |u| (u lies in P's range)
@@ -1307,6 +1799,15 @@ __global__ void k_asm_off(const Tile* tiles, int ntiles, const EnvDesc* envs) {
     for (int r = 0; r < 3; ++r)
 #pragma unroll
       for (int q = 0; q < 3; ++q) acc[r][q] += p[3 * r + q];
+  }
+  // pair Gauss-Newton block of a surface edge (mesh_contact 2)
+  double pb[6];
+  if (pair_active(E, E.pose) && pair_edge_block(E, k, pb)) {
+    const double B[3][3] = {{pb[0], pb[1], pb[2]}, {pb[1], pb[3], pb[4]}, {pb[2], pb[4], pb[5]}};
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int q = 0; q < 3; ++q) acc[r][q] = (R)((double)acc[r][q] + B[r][q]);
   }
   const int2 it = reinterpret_cast<const int2*>(E.eitem)[k];
   const int i = it.x / E.W, j = it.y / E.W;
@@ -1682,7 +2183,12 @@ __global__ void k_filter(const Tile* tiles, int ntiles, const EnvDesc* envs) {
   if (!running(E.st)) return;
   const int k = tl.tile * blockDim.x + threadIdx.x;
   double amax = INFINITY;
-  if (k < E.C) {
+  if (tl.tile >= E.n_ct) {
+    // pair tiles (mesh_contact 2): the bound of the surface primitives
+    const int j = (tl.tile - E.n_ct) * blockDim.x + threadIdx.x;
+    if (j < E.S + E.Se && pair_active(E, P))
+      amax = fmin(prim_pair_bound<R>(E, P, j, (const R*)E.d, FILTER_SPAN), FILTER_SPAN);
+  } else if (k < E.C) {
     const int vi = E.cand[k];
     double x[3], p[3], H[3][3];
     load3(E.xn, vi, x);
@@ -1761,7 +2267,7 @@ __global__ void k_env_dir(const EnvDesc* envs, int n) {
     dm = fmax(dm, E.part_dir[2 * k]);
     gd += E.part_dir[2 * k + 1];
   }
-  for (int k = threadIdx.x; k < E.n_ct; k += blockDim.x) am = fmin(am, E.part_filt[k]);
+  for (int k = threadIdx.x; k < E.n_ct + E.n_pt; k += blockDim.x) am = fmin(am, E.part_filt[k]);
   dm = block_reduce(dm, OpMax(), sh);
   gd = block_reduce(gd, OpSum(), sh);
   am = block_reduce(am, OpMin(), sh);
@@ -1851,8 +2357,16 @@ __global__ void k_energy(const Tile* tiles, int ntiles, const EnvDesc* envs, int
       }
       acc = 0.5 * E.mass[i] * s;
     }
+  } else if ((tt -= E.n_vt) >= E.n_ct) {
+    // pair tiles (mesh_contact 2)
+    const int j = (tt - E.n_ct) * blockDim.x + threadIdx.x;
+    if (j < E.S + E.Se && pair_active(E, P)) {
+      int vid[3];
+      double xw[3][3];
+      prim_load<R>(E, j, E.xn, mode ? d : nullptr, al, vid, xw);
+      acc = prim_pair_energy(E, P, j, xw);
+    }
   } else {
-    tt -= E.n_vt;
     const int k = tt * blockDim.x + threadIdx.x;
     if (k < E.C) {
       const int vi = E.cand[k];
@@ -1892,7 +2406,7 @@ __global__ void k_env_ls(const EnvDesc* envs, int n, int mode) {
   double el = 0, in = 0, ba = 0;
   for (int k = threadIdx.x; k < E.n_te; k += blockDim.x) el += E.part_e[k];
   for (int k = threadIdx.x; k < E.n_vt; k += blockDim.x) in += E.part_e[E.n_te + k];
-  for (int k = threadIdx.x; k < E.n_ct; k += blockDim.x) ba += E.part_e[E.n_te + E.n_vt + k];
+  for (int k = threadIdx.x; k < E.n_ct + E.n_pt; k += blockDim.x) ba += E.part_e[E.n_te + E.n_vt + k];
   el = block_reduce(el, OpSum(), sh);
   in = block_reduce(in, OpSum(), sh);
   ba = block_reduce(ba, OpSum(), sh);
@@ -2122,6 +2636,12 @@ __global__ void k_contact(const Tile* tiles, int ntiles, const EnvDesc* envs) {
         for (int c = 0; c < 3; ++c) f[c] -= kA * b1 * g[c];
       }
     }
+    // vertex-face and edge-edge pairs of the vertex's surface primitives
+    if (pair_active(E, P)) {
+      double gp[3] = {0, 0, 0};
+      pair_gather(E, k, gp, nullptr);
+      for (int c = 0; c < 3; ++c) f[c] -= gp[c];
+    }
     // friction force of the step, -mu lambda (f1/y) u (extraction after a
     // step only: the lag belongs to that step's start state)
     if (S->mode == 0 && E.fr_mu > 0) {
@@ -2233,7 +2753,7 @@ hipError_t launch_typed(KernelId id, const LaunchArgs& a) {
     case KernelId::setup_mass: TC_LAUNCH(k_setup_mass<R>, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs, a.out); break;
     case KernelId::setup_area: TC_LAUNCH(k_setup_cand_area, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs, a.out); break;
     case KernelId::predict: TC_LAUNCH(k_predict, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs); break;
-    case KernelId::project: TC_LAUNCH(k_project, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs); break;
+    case KernelId::project: TC_LAUNCH(k_project, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs, a.mode); break;
     case KernelId::element: TC_LAUNCH(k_element<R>, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs); break;
     case KernelId::barrier: TC_LAUNCH(k_barrier, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs); break;
     case KernelId::asm_diag: TC_LAUNCH(k_asm_diag<R>, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs); break;
@@ -2276,6 +2796,11 @@ hipError_t launch_typed(KernelId id, const LaunchArgs& a) {
       if (a.n_env > 0) TC_GO(k_env_extract, a.n_env, 256, a.stream, a.envs, a.n_env);
       break;
     case KernelId::commit: TC_LAUNCH(k_commit, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs); break;
+    case KernelId::pairs: TC_LAUNCH(k_pairs, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs, a.mode); break;
+    case KernelId::pair_push:
+      TC_LAUNCH(k_pair_push, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs, a.mode);
+      break;
+    case KernelId::pair_apply: TC_LAUNCH(k_pair_apply, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs); break;
     default: break;
   }
   return err;

@@ -94,6 +94,10 @@ tc_status tc_extract_noalloc(tc_pad* pad, int32_t n_ind, const tc_indenter* ind,
   EnvState S;
   EnvPose Q;
   init_state(S, Q, 1, n_ind, ind, pad);
+  if (Q.pairs)
+    return set_error(TC_E_INVALID_ARG,
+                     "vertex-face / edge-edge pairs (mesh_contact 2 with a mesh indenter) need the pad's step "
+                     "scratch: use tc_extract");
   hipStream_t st = ctx->stream;
   TC_HIP(hipMemcpyAsync(base + o_desc, &E, sizeof E, hipMemcpyHostToDevice, st));
   TC_HIP(hipMemcpyAsync(base + o_state, &S, sizeof S, hipMemcpyHostToDevice, st));

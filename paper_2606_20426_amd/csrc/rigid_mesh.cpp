@@ -110,6 +110,13 @@ struct Tables {
   Tree tree;
   std::vector<double> tv, tn, enf, vnf;
   std::vector<int32_t> tid_l;
+  // vertex-face and edge-edge pairs: vertex positions and areas (a third of
+  // the incident triangle areas), edge ends and lengths, and per leaf slot
+  // the vertices and edges that slot owns (first slot in leaf order that
+  // has them)
+  std::vector<double> mv, va, mel;
+  std::vector<int32_t> me;
+  std::vector<uint8_t> own;
   bool convex = false;
 };
 
@@ -232,6 +239,31 @@ tc_status mesh_tables(int32_t n_verts, const double* verts, int32_t n_tris, cons
       for (int i = 0; i < 3; ++i) enf[3 * e + i] = en[e][i];
     for (int v = 0; v < n_verts; ++v)
       for (int i = 0; i < 3; ++i) vnf[3 * (size_t)v + i] = vn[v][i];
+    std::vector<double> mv(3 * (size_t)n_verts), va(n_verts, 0.0), mel(en.size());
+    std::vector<int32_t> me(2 * en.size());
+    for (int v = 0; v < n_verts; ++v)
+      for (int i = 0; i < 3; ++i) mv[3 * (size_t)v + i] = V[v][i];
+    for (int f = 0; f < n_tris; ++f) {
+      const Vec3 cr = cross(sub(V[tris[3 * f + 1]], V[tris[3 * f]]), sub(V[tris[3 * f + 2]], V[tris[3 * f]]));
+      for (int k = 0; k < 3; ++k) va[tris[3 * f + k]] += 0.5 * norm(cr) / 3.0;
+    }
+    for (const auto& kv : edge_id) {
+      me[2 * (size_t)kv.second] = kv.first.first;
+      me[2 * (size_t)kv.second + 1] = kv.first.second;
+      mel[kv.second] = norm(sub(V[kv.first.second], V[kv.first.first]));
+    }
+    std::vector<uint8_t> own(n_tris, 0), v_seen(n_verts, 0), e_seen(en.size(), 0);
+    for (int s = 0; s < n_tris; ++s)
+      for (int k = 0; k < 3; ++k) {
+        const int v = tid_l[6 * (size_t)s + k], e = tid_l[6 * (size_t)s + 3 + k];
+        if (!v_seen[v]) { v_seen[v] = 1; own[s] |= (uint8_t)(1u << k); }
+        if (!e_seen[e]) { e_seen[e] = 1; own[s] |= (uint8_t)(1u << (3 + k)); }
+      }
+    out.mv = std::move(mv);
+    out.va = std::move(va);
+    out.mel = std::move(mel);
+    out.me = std::move(me);
+    out.own = std::move(own);
     out.convex = surface_is_convex(V, tris, n_tris, fn);
     out.tree = std::move(tree);
     out.tv = std::move(tv);
@@ -287,8 +319,9 @@ tc_status tc_rigid_mesh_create(tc_context* ctx, int32_t n_verts, const double* v
     if (hipSetDevice(ctx->device) != hipSuccess) { unreserve(); return set_error(TC_E_HIP, "hipSetDevice"); }
     const size_t b_nodes = a256(sizeof(BvhNode) * tree.nodes.size()), b_tv = a256(8 * tv.size()),
                  b_tn = a256(8 * tn.size()), b_tid = a256(4 * tid_l.size()), b_en = a256(8 * enf.size()),
-                 b_vn = a256(8 * vnf.size());
-    const size_t total = b_nodes + b_tv + b_tn + b_tid + b_en + b_vn;
+                 b_vn = a256(8 * vnf.size()), b_mv = a256(8 * tb.mv.size()), b_va = a256(8 * tb.va.size()),
+                 b_me = a256(4 * tb.me.size()), b_mel = a256(8 * tb.mel.size()), b_own = a256(tb.own.size());
+    const size_t total = b_nodes + b_tv + b_tn + b_tid + b_en + b_vn + b_mv + b_va + b_me + b_mel + b_own;
     tc_status st;
     char* mem = static_cast<char*>(ctx->dev_alloc(total, &st));
     if (!mem) { unreserve(); return st; }
@@ -296,19 +329,30 @@ tc_status tc_rigid_mesh_create(tc_context* ctx, int32_t n_verts, const double* v
     dm.n_tri = n_tris;
     dm.n_node = (int)tree.nodes.size();
     dm.convex = tb.convex ? 1 : 0;
+    dm.n_vert = n_verts;
     char* p = mem;
     dm.nodes = reinterpret_cast<const BvhNode*>(p); p += b_nodes;
     dm.tv = reinterpret_cast<const double*>(p); p += b_tv;
     dm.tn = reinterpret_cast<const double*>(p); p += b_tn;
     dm.tid = reinterpret_cast<const int32_t*>(p); p += b_tid;
     dm.en = reinterpret_cast<const double*>(p); p += b_en;
-    dm.vn = reinterpret_cast<const double*>(p);
+    dm.vn = reinterpret_cast<const double*>(p); p += b_vn;
+    dm.mv = reinterpret_cast<const double*>(p); p += b_mv;
+    dm.va = reinterpret_cast<const double*>(p); p += b_va;
+    dm.me = reinterpret_cast<const int32_t*>(p); p += b_me;
+    dm.mel = reinterpret_cast<const double*>(p); p += b_mel;
+    dm.own = reinterpret_cast<const uint8_t*>(p);
     hipError_t e = hipMemcpy((void*)dm.nodes, tree.nodes.data(), sizeof(BvhNode) * tree.nodes.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy((void*)dm.tv, tv.data(), 8 * tv.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy((void*)dm.tn, tn.data(), 8 * tn.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy((void*)dm.tid, tid_l.data(), 4 * tid_l.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy((void*)dm.en, enf.data(), 8 * enf.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy((void*)dm.vn, vnf.data(), 8 * vnf.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy((void*)dm.mv, tb.mv.data(), 8 * tb.mv.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy((void*)dm.va, tb.va.data(), 8 * tb.va.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy((void*)dm.me, tb.me.data(), 4 * tb.me.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy((void*)dm.mel, tb.mel.data(), 8 * tb.mel.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy((void*)dm.own, tb.own.data(), tb.own.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(ctx->d_meshes + slot, &dm, sizeof(DevMesh), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
       ctx->dev_free(mem, total);
@@ -317,7 +361,7 @@ tc_status tc_rigid_mesh_create(tc_context* ctx, int32_t n_verts, const double* v
     }
     {
       std::lock_guard<std::mutex> ml(ctx->mesh_mu);
-      ctx->mesh_slots[slot] = tc_context::MeshSlot{true, mem, total};
+      ctx->mesh_slots[slot] = tc_context::MeshSlot{true, mem, total, tb.mv};
     }
     *id = slot;
     return TC_OK;

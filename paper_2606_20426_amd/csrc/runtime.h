@@ -135,7 +135,12 @@ struct tc_context {
   // rigid meshes (TC_MESH indenters): device table [MAX_MESHES], zeroed
   // slots are free; each live slot owns one device allocation
   tc::DevMesh* d_meshes = nullptr;
-  struct MeshSlot { bool live = false; void* mem = nullptr; size_t bytes = 0; };
+  struct MeshSlot {
+    bool live = false;
+    void* mem = nullptr;
+    size_t bytes = 0;
+    std::vector<double> verts;   // host copy of the vertices (local frame): a pose change's travel
+  };
   std::vector<MeshSlot> mesh_slots;
   // guards mesh_slots' live flags: request submission checks them without
   // waiting for the device mutex (held by the server for a whole tick)
@@ -149,6 +154,7 @@ struct tc_pad {
   tc_context* ctx = nullptr;
   int id = 0;
   int V = 0, T = 0, C = 0, S = 0, S_top = 0, W = 0;
+  int Se = 0;                        // surface edges
   int64_t nnz_blocks = 0;
   int64_t n_edges = 0;               // unique edges (off-diagonal block pairs)
   bool fp64 = false;
@@ -189,7 +195,9 @@ struct BatchPlan {
   EnvState* h_state = nullptr;      // pinned
   Tile* d_tiles = nullptr;
   size_t dev_bytes = 0;
-  enum Cls { VERT, TET, CAND, SURF, ASM, ENERGY, SPMV, NCLS };
+  // PAIR: surface triangles and edges (mesh_contact 2); FILT: contact
+  // vertices, then PAIR
+  enum Cls { VERT, TET, CAND, SURF, ASM, ENERGY, SPMV, PAIR, FILT, NCLS };
   int lpr = 0;                       // SpMV lanes per row
   int off[NCLS] = {0}, cnt[NCLS] = {0};
   std::vector<EnvDesc> h_desc;
@@ -263,11 +271,13 @@ struct Runner {
   void launch(KernelId k, int cls, int parity = 0, int mode = 0);
   tc_status readback();
   bool any(bool (*pred)(const EnvState&)) const;
+  // some pad matching pred has vertex-face / edge-edge pairs this step
+  bool any_pairs(bool (*pred)(const EnvState&)) const;
   // tile lists of the kernel classes restricted to the pads matching a
   // predicate (the plan's own lists when every pad matches)
   struct View {
-    const Tile* t[8];
-    int c[8];
+    const Tile* t[BatchPlan::NCLS];
+    int c[BatchPlan::NCLS];
     bool full;
   };
   View view(bool (*pred)(const EnvState&));

@@ -186,6 +186,31 @@ void init_state(EnvState& S, EnvPose& Q, int mode, int n_ind, const tc_indenter*
     std::memcpy(&Q.ind[m], &ind[m], sizeof(DevIndenter));
     std::memcpy(&Q.prev[m], has_prev ? &pad->prev[m] : &ind[m], sizeof(DevIndenter));
   }
+  // vertex-face / edge-edge pairs: on with mesh_contact 2 and a mesh
+  // indenter; the feasible start looks for features carried through the
+  // pad surface within each mesh's travel since the previous pose
+  if (!pad || pad->params.mesh_contact != 2 || pad->Se == 0) return;
+  for (int m = 0; m < n_ind; ++m) {
+    if (ind[m].shape != TC_MESH) continue;
+    Q.pairs = 1;
+    const int id = ind[m].reserved;
+    const auto& slots = pad->ctx->mesh_slots;
+    if (!has_prev || id < 0 || id >= (int)slots.size()) continue;
+    const std::vector<double>& V = slots[id].verts;
+    const DevIndenter& A = Q.ind[m];
+    const DevIndenter& B = Q.prev[m];
+    double t2 = 0.0;
+    for (size_t v = 0; v + 2 < V.size(); v += 3) {
+      double d2 = 0.0;
+      for (int i = 0; i < 3; ++i) {
+        const double a = A.R[3 * i] * V[v] + A.R[3 * i + 1] * V[v + 1] + A.R[3 * i + 2] * V[v + 2] + A.c[i];
+        const double b = B.R[3 * i] * V[v] + B.R[3 * i + 1] * V[v + 1] + B.R[3 * i + 2] * V[v + 2] + B.c[i];
+        d2 += (a - b) * (a - b);
+      }
+      t2 = std::max(t2, d2);
+    }
+    Q.travel[m] = std::sqrt(t2);
+  }
 }
 
 void remember_pose(tc_pad* pad, const EnvPose& Q) {
@@ -307,9 +332,14 @@ static void resolve_timing(tc_context* ctx) { resolve_timing(ctx, ctx->tslice, c
 
 struct ScratchLayout {
   size_t Ke, A, xn, xhat, g, d, r, z, p0, p1, q, Pinv, gb, Hb, fric;
-  size_t prz, ppq, pg2, pe, pdir, pfilt, pc3, ps3;
+  size_t prz, ppq, pg2, pe, pdir, pfilt, pc3, ps3, prec, pflag;
   size_t total;
 };
+
+// Surface primitives with pair records (mesh_contact 2), else 0.
+static size_t pair_prims(const tc_pad* p) {
+  return p->params.mesh_contact == 2 ? (size_t)p->S + p->Se : 0;
+}
 
 static ScratchLayout scratch_layout(const tc_pad* p) {
   ScratchLayout L{};
@@ -332,14 +362,17 @@ static ScratchLayout scratch_layout(const tc_pad* p) {
   L.Hb = take(48 * C);
   L.fric = take(p->params.friction > 0 ? 8 * FRIC_STRIDE * MAX_IND * C : 0);
   const size_t nv = cdiv(V, 64), nt = cdiv(T, 64), nc = cdiv(C, 64), ns = cdiv(std::max<size_t>(S, 1), 64);
+  const size_t NP = pair_prims(p), np = cdiv(NP, 64);
   L.prz = take(8 * nv);
   L.ppq = take(8 * ((size_t)cdiv(V, 2) + 1));
   L.pg2 = take(8 * nv);
-  L.pe = take(8 * (nt + nv + nc));
+  L.pe = take(8 * (nt + nv + nc + np));
   L.pdir = take(16 * nv);
-  L.pfilt = take(8 * nc);
+  L.pfilt = take(8 * (nc + np));
   L.pc3 = take(24 * nc);
   L.ps3 = take(24 * ns);
+  L.prec = take(8 * PREC * NP);
+  L.pflag = take(4 * NP);
   L.total = o;
   return L;
 }
@@ -374,6 +407,9 @@ static void bind_scratch_desc(tc_pad* p) {
   E.part_filt = (double*)(b + L.pfilt);
   E.part_c3 = (double*)(b + L.pc3);
   E.part_s3 = (double*)(b + L.ps3);
+  const bool pairs = pair_prims(p) > 0;
+  E.prec = pairs ? (double*)(b + L.prec) : nullptr;
+  E.pflag = pairs ? (int32_t*)(b + L.pflag) : nullptr;
 }
 
 tc_status ensure_scratch(tc_pad* p) {
@@ -501,6 +537,7 @@ tc_status build_plan(tc_context* ctx, int n, tc_pad* const* pads, const int* slo
     E.n_at = cdiv((int64_t)E.V_E, BV);
     E.n_te = cdiv(p->T, BV);
     E.n_spt = cdiv(p->V, rows_spmv);
+    E.n_pt = E.prec ? cdiv((int64_t)p->S + p->Se, BV) : 0;
     E.st = pool.d_state + slots[i];
     E.pose = pool.d_pose + slots[i];
     P->h_desc[i] = E;
@@ -518,8 +555,10 @@ tc_status build_plan(tc_context* ctx, int n, tc_pad* const* pads, const int* slo
   add_cls(BatchPlan::CAND, [](const EnvDesc& E) { return E.n_ct; });
   add_cls(BatchPlan::SURF, [](const EnvDesc& E) { return E.n_st; });
   add_cls(BatchPlan::ASM, [](const EnvDesc& E) { return E.n_at; });
-  add_cls(BatchPlan::ENERGY, [](const EnvDesc& E) { return E.n_te + E.n_vt + E.n_ct; });
+  add_cls(BatchPlan::ENERGY, [](const EnvDesc& E) { return E.n_te + E.n_vt + E.n_ct + E.n_pt; });
   add_cls(BatchPlan::SPMV, [](const EnvDesc& E) { return E.n_spt; });
+  add_cls(BatchPlan::PAIR, [](const EnvDesc& E) { return E.n_pt; });
+  add_cls(BatchPlan::FILT, [](const EnvDesc& E) { return E.n_ct + E.n_pt; });
   TC_HIP(hipMalloc(&P->d_desc, sizeof(EnvDesc) * n));
   TC_HIP(hipMalloc(&P->d_tiles, sizeof(Tile) * std::max<size_t>(tiles.size(), 1)));
   P->ctiles_cap = 4 * (int)tiles.size() + 64;
@@ -599,7 +638,8 @@ Runner::View Runner::view(bool (*pred)(const EnvState&)) {
       const EnvDesc& E = P->h_desc[i];
       const int cnt = c == BatchPlan::VERT ? E.n_vt : c == BatchPlan::TET ? E.n_tt : c == BatchPlan::CAND ? E.n_ct
                     : c == BatchPlan::SURF ? E.n_st : c == BatchPlan::ASM ? E.n_at
-                    : c == BatchPlan::ENERGY ? E.n_te + E.n_vt + E.n_ct : E.n_spt;
+                    : c == BatchPlan::ENERGY ? E.n_te + E.n_vt + E.n_ct + E.n_pt
+                    : c == BatchPlan::PAIR ? E.n_pt : c == BatchPlan::FILT ? E.n_ct + E.n_pt : E.n_spt;
       if (k + cnt > P->ctiles_cap) break;   // ring full: cannot happen (4x capacity)
       for (int t = 0; t < cnt; ++t) P->h_ctiles[k++] = Tile{i, t};
     }
@@ -632,6 +672,12 @@ tc_status Runner::readback() {
 bool Runner::any(bool (*pred)(const EnvState&)) const {
   for (int i = 0; i < n; ++i)
     if (pred(state(i))) return true;
+  return false;
+}
+
+bool Runner::any_pairs(bool (*pred)(const EnvState&)) const {
+  for (int i = 0; i < n; ++i)
+    if (pred(state(i)) && P->h_desc[i].n_pt > 0 && pool->h_pose[P->slots[i]].pairs) return true;
   return false;
 }
 
@@ -668,7 +714,18 @@ tc_status Runner::tick(bool init) {
   if (init) {
     const View vi = view(is_init);
     launch_v(KernelId::predict, vi, BatchPlan::VERT);
-    launch_v(KernelId::project, vi, BatchPlan::CAND);
+    launch_v(KernelId::project, vi, BatchPlan::CAND, 0, 0);
+    if (any_pairs(is_init)) {
+      // pads with vertex-face / edge-edge pairs: vertex rounds alternate
+      // with the surface primitives' pushes, then both checks
+      for (int r = 0; r < 8; ++r) {
+        launch_v(KernelId::project, vi, BatchPlan::CAND, 0, 1);
+        launch_v(KernelId::pair_push, vi, BatchPlan::PAIR, 0, 0);
+        launch_v(KernelId::pair_apply, vi, BatchPlan::CAND);
+      }
+      launch_v(KernelId::project, vi, BatchPlan::CAND, 0, 2);
+      launch_v(KernelId::pair_push, vi, BatchPlan::PAIR, 0, 1);
+    }
     launch_v(KernelId::energy, vi, BatchPlan::ENERGY, 0, 0);
     launch(KernelId::env_ls, BatchPlan::NCLS, 0, 0);
   }
@@ -676,6 +733,7 @@ tc_status Runner::tick(bool init) {
     const View v = view(init ? init_or_run : is_run);
     launch(KernelId::newton_begin, BatchPlan::NCLS);
     launch_v(KernelId::element, v, BatchPlan::TET);
+    if (any_pairs(init ? init_or_run : is_run)) launch_v(KernelId::pairs, v, BatchPlan::PAIR, 0, 0);
     launch_v(KernelId::barrier, v, BatchPlan::CAND);
     launch_v(KernelId::asm_diag, v, BatchPlan::VERT);
     launch_v(KernelId::asm_off, v, BatchPlan::ASM);
@@ -702,7 +760,7 @@ tc_status Runner::tick(bool init) {
     // the views are rebuilt after the sync: pads may have failed meanwhile
     const View vr = view(is_run);
     launch_v(KernelId::newton_dir, vr, BatchPlan::VERT);
-    launch_v(KernelId::filter, vr, BatchPlan::CAND);
+    launch_v(KernelId::filter, vr, BatchPlan::FILT);
     launch(KernelId::env_dir, BatchPlan::NCLS);
     if (debug) {
       if ((st = readback())) return st;
@@ -742,6 +800,7 @@ tc_status Runner::tick(bool init) {
     const View vf = view(is_finish);
     launch_v(KernelId::sigma, vf, BatchPlan::TET);
     launch_v(KernelId::traction, vf, BatchPlan::SURF);
+    if (any_pairs(is_finish)) launch_v(KernelId::pairs, vf, BatchPlan::PAIR, 0, 1);
     launch_v(KernelId::contact, vf, BatchPlan::CAND);
     launch_v(KernelId::commit, vf, BatchPlan::VERT);
     launch(KernelId::env_extract, BatchPlan::NCLS);
@@ -978,6 +1037,7 @@ tc_status newton_direction(tc_pad* pad, int n_ind, const tc_indenter* ind, doubl
   run.launch(KernelId::env_ls, BatchPlan::NCLS, 0, 0);
   run.launch(KernelId::newton_begin, BatchPlan::NCLS);
   run.launch_v(KernelId::element, v, BatchPlan::TET);
+  if (run.any_pairs(Runner::init_or_run)) run.launch_v(KernelId::pairs, v, BatchPlan::PAIR, 0, 0);
   run.launch_v(KernelId::barrier, v, BatchPlan::CAND);
   run.launch_v(KernelId::asm_diag, v, BatchPlan::VERT);
   run.launch_v(KernelId::asm_off, v, BatchPlan::ASM);
@@ -1438,6 +1498,80 @@ tc_status tc_pad_create(tc_context* ctx, const tc_mesh* mesh, int32_t n_material
     ALLOC(E.c_press, double*, 8 * C);
     ALLOC(E.reaction, double*, 24);
     ALLOC(E.traction_sum, double*, 24);
+    // surface edges and the incidence tables of the vertex-face / edge-edge
+    // pairs against rigid meshes (mesh_contact 2)
+    {
+      std::map<std::pair<int, int>, int> key;
+      for (size_t j = 0; j < S; ++j)
+        for (int k = 0; k < 3; ++k) {
+          const int a = t.tris[3 * j + k], b = t.tris[3 * j + (k + 1) % 3];
+          key.emplace(std::make_pair(std::min(a, b), std::max(a, b)), 0);
+        }
+      std::vector<int32_t> sedge, sadj, esed, vptr, vidx;
+      std::vector<double> slen;
+      int Se = 0;
+      for (auto& kv : key) {
+        kv.second = Se++;
+        sedge.push_back(kv.first.first);
+        sedge.push_back(kv.first.second);
+        const double* A = mesh->rest_xyz + 3 * (size_t)kv.first.first;
+        const double* B = mesh->rest_xyz + 3 * (size_t)kv.first.second;
+        slen.push_back(std::sqrt((B[0] - A[0]) * (B[0] - A[0]) + (B[1] - A[1]) * (B[1] - A[1]) +
+                                 (B[2] - A[2]) * (B[2] - A[2])));
+      }
+      sadj.assign(2 * (size_t)Se, -1);
+      std::vector<std::vector<int32_t>> vl(V);
+      for (size_t j = 0; j < S; ++j)
+        for (int k = 0; k < 3; ++k) {
+          const int a = t.tris[3 * j + k], b = t.tris[3 * j + (k + 1) % 3];
+          const int f = key.at({std::min(a, b), std::max(a, b)});
+          int32_t* slot = &sadj[2 * (size_t)f];
+          const int32_t code = (int32_t)((j << 3) | (3 + k));
+          if (slot[0] < 0) slot[0] = code;
+          else if (slot[1] < 0) slot[1] = code;
+          vl[a].push_back((int32_t)((j << 2) | k));
+        }
+      for (int f = 0; f < Se; ++f)
+        for (int e = 0; e < 2; ++e) vl[sedge[2 * f + e]].push_back((int32_t)(((S + f) << 2) | e));
+      const size_t VE = t.eitem.size() / 2;
+      esed.assign(std::max<size_t>(VE, 1), -1);
+      for (size_t k = 0; k < VE; ++k) {
+        const int i = t.eitem[2 * k] / p->W, j = t.eitem[2 * k + 1] / p->W;
+        auto it = key.find({std::min(i, j), std::max(i, j)});
+        if (it != key.end()) esed[k] = it->second;
+      }
+      vptr.push_back(0);
+      for (int c = 0; c < p->C; ++c) {
+        std::vector<int32_t>& l = vl[t.cand[c]];
+        std::sort(l.begin(), l.end());
+        vidx.insert(vidx.end(), l.begin(), l.end());
+        vptr.push_back((int32_t)vidx.size());
+      }
+      p->Se = Se;
+      int32_t *d_sedge, *d_sadj, *d_esed, *d_vptr, *d_vidx;
+      double* d_slen;
+      ALLOC(d_sedge, int32_t*, 4 * std::max<size_t>(sedge.size(), 1));
+      ALLOC(d_slen, double*, 8 * std::max<size_t>(slen.size(), 1));
+      ALLOC(d_sadj, int32_t*, 4 * std::max<size_t>(sadj.size(), 1));
+      ALLOC(d_esed, int32_t*, 4 * esed.size());
+      ALLOC(d_vptr, int32_t*, 4 * vptr.size());
+      ALLOC(d_vidx, int32_t*, 4 * std::max<size_t>(vidx.size(), 1));
+      if (Se > 0) {
+        if ((s = upload(ctx, d_sedge, sedge.data(), 4 * sedge.size()))) return s;
+        if ((s = upload(ctx, d_slen, slen.data(), 8 * slen.size()))) return s;
+        if ((s = upload(ctx, d_sadj, sadj.data(), 4 * sadj.size()))) return s;
+      }
+      if ((s = upload(ctx, d_esed, esed.data(), 4 * esed.size()))) return s;
+      if ((s = upload(ctx, d_vptr, vptr.data(), 4 * vptr.size()))) return s;
+      if (!vidx.empty() && (s = upload(ctx, d_vidx, vidx.data(), 4 * vidx.size()))) return s;
+      E.Se = Se;
+      E.sedge = d_sedge;
+      E.sedge_len0 = d_slen;
+      E.sedge_adj = d_sadj;
+      E.edge_sedge = d_esed;
+      E.vp_ptr = d_vptr;
+      E.vp_idx = d_vidx;
+    }
 #undef ALLOC
     if ((s = upload(ctx, X, mesh->rest_xyz, 24 * V))) return s;
     if ((s = upload(ctx, x, mesh->rest_xyz, 24 * V))) return s;
@@ -1558,10 +1692,12 @@ tc_status tc_pad_set_params(tc_pad* pad, const tc_params* params) {
   if ((params->precision == TC_PREC_FP64) != pad->fp64) return set_error(TC_E_INVALID_ARG, "precision is fixed at pad creation");
   std::lock_guard<std::recursive_mutex> lk(pad->ctx->mu);
   if (pad->busy.load()) return set_error(TC_E_BUSY, "pad has a request in flight on a server");
-  const bool fric_layout = (pad->params.friction > 0) != (params->friction > 0);
+  const bool fric_layout = (pad->params.friction > 0) != (params->friction > 0) ||
+                           (pad->params.mesh_contact == 2) != (params->mesh_contact == 2);
   pad->params = *params;
   if (fric_layout) {
-    // the step scratch holds the friction lag only while friction is on
+    // the step scratch holds the friction lag only while friction is on,
+    // the pair records only with mesh_contact 2
     (void)hipStreamSynchronize(pad->ctx->stream);
     release_scratch(pad);
     pad->scratch_need = scratch_layout(pad).total;

@@ -62,13 +62,21 @@ struct BvhNode {
 struct DevMesh {
   int32_t n_tri, n_node;
   int32_t convex;          // 1: one component, no concave edge (the distance outside is convex)
-  int32_t unused;
+  int32_t n_vert;
   const double* tv;        // [n_tri][9] corners a, b, c (counter-clockwise from outside)
   const double* tn;        // [n_tri][3] unit outward face normal
   const int32_t* tid;      // [n_tri][6] vertex ids of a, b, c; edge ids of ab, bc, ca
   const double* en;        // [n_edge][3] edge pseudonormal (sum of the two face normals)
   const double* vn;        // [n_vert][3] vertex pseudonormal (angle-weighted normal sum)
   const BvhNode* nodes;
+  // vertex-face and edge-edge pairs (mesh_contact 2)
+  const double* mv;        // [n_vert][3] vertex positions
+  const double* va;        // [n_vert] a third of the area of the vertex's triangles
+  const int32_t* me;       // [n_edge][2] edge end vertex ids
+  const double* mel;       // [n_edge] edge length
+  const uint8_t* own;      // [n_tri] bit k: this triangle owns vertex tid[k], bit 3 + k: edge
+                           // tid[3 + k] (each vertex and edge owned by its first triangle in
+                           // leaf order, so a traversal meets it once)
 };
 
 // Indenter poses of one pad for the current step (uploaded at step start)
@@ -76,10 +84,19 @@ struct DevMesh {
 // the current ones when there is none).
 struct EnvPose {
   int32_t n_ind;
-  int32_t reserved;
+  int32_t pairs;             // vertex-face / edge-edge pairs on (mesh_contact 2 and a mesh indenter)
   DevIndenter ind[MAX_IND];
   DevIndenter prev[MAX_IND];
+  double travel[MAX_IND];    // largest move of a mesh vertex from the previous pose (mesh indenters)
 };
+
+// Pair record of one pad surface primitive (triangle j < S, surface edge
+// S + f), float64: gradient of its vertices' pair terms [3][3] (edges use
+// the first two), then the symmetric 3x3 Gauss-Newton blocks (6 values
+// each: 00 01 02 11 12 22) of vertex pairs (0,0) (1,1) (2,2) (0,1) (1,2)
+// (2,0).  During the feasible start the first four values hold the push
+// of the primitive's vertices and the number of pushes.
+constexpr int PREC = 48;
 
 // Lagged friction record of one (indenter, contact vertex) pair, float64:
 // normal force lambda (0 = no friction), normal n, indenter point motion w.
@@ -143,7 +160,9 @@ struct EnvState {
 struct EnvDesc {
   int32_t V, T, C, S, W;
   int32_t V_E;               // unique edges (off-diagonal block pairs)
+  int32_t Se;                // surface edges
   int32_t n_vt, n_tt, n_ct, n_st, n_at, n_te, n_spt;   // tiles per kernel class
+  int32_t n_pt;              // pair tiles over S + Se surface primitives (mesh_contact 2, else 0)
   // resident inputs
   const double* X;
   double* x;
@@ -170,6 +189,12 @@ struct EnvDesc {
   const int32_t* eptr;       // [V_E+1] edge-stream range of each edge
   const int32_t* eitem;      // [V_E][2] blocks (i, slot of j), (j, slot of i)
   const int32_t* cpos;       // [T][10] stream positions: 4 diagonal, 6 edge blocks
+  const int32_t* sedge;      // [Se][2] surface edges (i < j), ascending
+  const double* sedge_len0;  // [Se] rest length
+  const int32_t* sedge_adj;  // [Se][2] its surface triangles: tri << 3 | pair block (3 ab, 4 bc, 5 ca)
+  const int32_t* edge_sedge; // [V_E] surface edge of each unique edge, -1 if interior
+  const int32_t* vp_ptr;     // [C+1] surface primitives of each contact vertex
+  const int32_t* vp_idx;     //   primitive << 2 | its local vertex (triangles j, edges S + f)
   // outputs
   void* sigma;               // real [T][6]
   void* traction;            // real [S][3]
@@ -205,11 +230,13 @@ struct EnvDesc {
   double* part_rz;           // [n_vt]
   double* part_pq;           // [n_spt]
   double* part_g2;           // [n_vt]
-  double* part_e;            // [n_te + n_vt + n_ct]
+  double* part_e;            // [n_te + n_vt + n_ct + n_pt]
   double* part_dir;          // [2 n_vt]
-  double* part_filt;         // [n_ct]
+  double* part_filt;         // [n_ct + n_pt]
   double* part_c3;           // [3 n_ct]
   double* part_s3;           // [3 n_st]
+  double* prec;              // [S + Se][PREC] pair records (mesh_contact 2)
+  int32_t* pflag;            // [S + Se] 1 where the record holds pairs
   EnvState* st;
   const EnvPose* pose;
   const DevMesh* meshes;     // [MAX_MESHES] the context's rigid meshes
@@ -220,7 +247,8 @@ struct EnvDesc {
   double gravity[3];
   int32_t quasi_static, max_cg, max_newton, max_halvings, precond, cg_forcing, hess_proj, init_guess;
   int32_t ls_expand;
-  int32_t mesh_pairs;        // rigid meshes: barrier summed over triangles within d_hat
+  int32_t mesh_pairs;        // rigid meshes: 0 distance; 1 barrier summed over triangles within
+                             // d_hat; 2 that plus vertex-face and edge-edge pairs
   double fr_mu, fr_eps;      // friction ratio (0 = off) and slip threshold eps_v h [m]
 };
 

@@ -32,6 +32,9 @@ enum class KernelId : int {
   contact,
   env_extract,
   commit,
+  pairs,
+  pair_push,
+  pair_apply,
   count
 };
 
@@ -40,7 +43,8 @@ inline const char* kernel_name(KernelId k) {
                                 "element",    "barrier",    "asm_diag",   "asm_off",   "newton_begin",
                                 "cg_spmv",    "cg_update",  "newton_dir", "filter",    "env_dir",
                                 "energy",     "env_ls",     "update",     "env_update", "sigma",     "traction",
-                                "contact",    "env_extract", "commit"};
+                                "contact",    "env_extract", "commit",     "pairs",     "pair_push",
+                                "pair_apply"};
   return names[static_cast<int>(k)];
 }
 

@@ -117,13 +117,14 @@ def test_validation_error_codes(tc):
     for kw in (dict(dt=0.0), dict(dhat=-1.0), dict(kappa=float("inf")), dict(max_newton=0),
                dict(precision=7), dict(precond=3), dict(cg_rel_tol=0.0), dict(friction=-0.5),
                dict(friction=float("nan")), dict(friction=0.5, eps_v=0.0), dict(ls_expand=17),
-               dict(mesh_contact=2), dict(mesh_contact=-1),
+               dict(mesh_contact=3), dict(mesh_contact=-1),
                dict(hess_proj=3), dict(cg_forcing=3), dict(cg_eta_max=1.0)):
         assert _status(lambda: V(params=tc.make_params(**kw))) == -1
     # friction off: the threshold is not used
     assert _status(lambda: V(params=tc.make_params(friction=0.0, eps_v=0.0))) == 0
     assert _status(lambda: V(params=tc.make_params(friction=0.5, eps_v=0.01))) == 0
     assert _status(lambda: V(params=tc.make_params(mesh_contact=1))) == 0
+    assert _status(lambda: V(params=tc.make_params(mesh_contact=2))) == 0
     assert _status(lambda: V(params=tc.make_params(mesh_contact=1, friction=0.5))) == 0
     d = tc.make_params()
     assert d.friction == 0.0 and d.eps_v == 0.01
