@@ -51,7 +51,9 @@ def build_workload(name):
                 "friction": "pressed over 15 steps then slid 0.1 mm/step in a seeded direction, friction 0.5",
                 "layers": "two layers split at half thickness, base 8x stiffer (nu 0.42, rho 1200)",
                 "mesh": "bounded indenters as triangle meshes (icosphere 1,280 tris, 32-gon cylinder, "
-                        "12-tri cube, 768-tri torus with the triangle-pair barrier), texture plates analytic"}[kind]
+                        "12-tri cube, 768-tri torus with the triangle-pair barrier), texture plates analytic",
+                "mesh2": "the same triangle meshes with mesh_contact 2 (mesh vertices against pad triangles, "
+                         "edge-edge pairs), texture plates analytic"}[kind]
         return scenes.config3_variant(kind), f"the batch60 pads and poses, {what}, SeedSequence(3) and (5)"
     if name == "paper60":
         return scenes.paper60(), ("60 copies of the 18x14x4 mm pad (1,944 tets) under seeded indenters, d_hat 1 mm, "
@@ -268,8 +270,11 @@ def run_steps(args):
     if args.copy_probe:
         copy_probe(args.copy_probe)
     ctx = tc.Context(0)
-    copy_gbs = copy_ceiling()
-    log(f"device copy: {copy_gbs:.0f} GB/s (read + write)")
+    # (counter runs skip it: their scale is the probe copy, the largest
+    # copy of the run)
+    copy_gbs = None if args.copy_probe else copy_ceiling()
+    if copy_gbs:
+        log(f"device copy: {copy_gbs:.0f} GB/s (read + write)")
     t0 = time.perf_counter()
     pads = make_pads(tc, ctx, envs, args)
     log(f"pads created in {time.perf_counter() - t0:.1f} s; HBM used {ctx.memory()[0] / 2**30:.2f} GiB")
@@ -291,24 +296,47 @@ def run_steps(args):
     for s in range(1, args.warmup + 1):
         st = step(s)
         log(f"warmup {s}: newton max {max(x.newton_iters for x in st)} cg sum {sum(x.cg_iters for x in st)}")
-    if not args.no_timing:
-        ctx.set_timing(True, stride=args.timing_stride)
-        ctx.reset_timing()
-    torch.cuda.synchronize()
-    lat, newton, cg = [], [], []
-    t_start = time.perf_counter()
-    for s in range(args.warmup + 1, args.warmup + args.steps + 1):
-        a = time.perf_counter()
-        st = step(s)
-        lat.append((time.perf_counter() - a) * 1e3)
-        newton.append(max(x.newton_iters for x in st))
-        cg.append(sum(x.cg_iters for x in st))
-        log(f"step {s}: {lat[-1]:.1f} ms, newton max {newton[-1]}, cg total {cg[-1]}")
-    torch.cuda.synchronize()
-    total = time.perf_counter() - t_start
+    streams = tuned["streams"] if tuned else args.streams
+
+    def timed(label):
+        if not args.no_timing:
+            ctx.set_timing(True, stride=args.timing_stride)
+            ctx.reset_timing()
+        torch.cuda.synchronize()
+        lat, newton, cg = [], [], []
+        t_start = time.perf_counter()
+        for s in range(args.warmup + 1, args.warmup + args.steps + 1):
+            a = time.perf_counter()
+            st = step(s)
+            lat.append((time.perf_counter() - a) * 1e3)
+            newton.append(max(x.newton_iters for x in st))
+            cg.append(sum(x.cg_iters for x in st))
+            log(f"{label} step {s}: {lat[-1]:.1f} ms, newton max {newton[-1]}, cg total {cg[-1]}")
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t_start
+        roof = roofline(ctx, args, copy_gbs) if not args.no_timing else None
+        return total, lat, newton, cg, roof
+
     n_env = len(envs)
+    single = None
+    if streams > 1 and not args.sequential and not args.no_timing:
+        # kernels of several streams overlap, which stretches each launch's
+        # duration: the kernel roofline comes from the same steps on one
+        # stream first, then the pads go back to their state after warm-up
+        saved = [p.save_state() for p in pads]
+        ctx.set_streams(1)
+        total1, _, _, _, roof1 = timed("one stream:")
+        single = (total1, roof1)
+        for p, b in zip(pads, saved):
+            p.load_state(b)
+        ctx.set_streams(streams)
+    total, lat, newton, cg, roof = timed(f"{streams} streams:" if streams > 1 else "")
     value = n_env * args.steps / total
-    roof = roofline(ctx, args, copy_gbs) if not args.no_timing else None
+    if single is not None:
+        concurrent = roof
+        roof = dict(single[1], streams=1, concurrent={
+            "streams": streams, "frac": concurrent["frac"], "avg_launch_ms": concurrent["avg_launch_ms"],
+            "kernels": concurrent["kernels"]}) if single[1] else None
     mode = "sequential" if args.sequential else "batched"
     out = {
         "metric": METRIC,
@@ -323,7 +351,8 @@ def run_steps(args):
                    "tets": int(sum(e.pad.tets.shape[0] for e in envs)), "mode": mode,
                    "newton_max_mean": float(np.mean(newton)), "cg_iters_mean": float(np.mean(cg)),
                    "precision": args.precision, "graphs": bool(args.graphs and args.no_timing),
-                   "streams": tuned["streams"] if tuned else args.streams, "autotuned": tuned},
+                   "streams": streams, "autotuned": tuned,
+                   "one_stream_steps_per_s": round(n_env * args.steps / single[0], 2) if single else None},
         "roofline": roof,
     }
     if args.workload == "paper60":
@@ -566,7 +595,7 @@ def main():
     ap.add_argument("--cg-rel-tol", type=float, default=0.2)
     ap.add_argument("--cg-eta-max", type=float, default=0.2)
     ap.add_argument("--cg-forcing", type=int, default=2)
-    ap.add_argument("--streams", type=int, default=1, help="streams a batch step is split over (1..4)")
+    ap.add_argument("--streams", type=int, default=2, help="streams a batch step is split over (1..4)")
     ap.add_argument("--cg-conv-tol", type=float, default=0.0,
                     help="CG tolerance of a direction that decides convergence (0 = the solve tolerance)")
     ap.add_argument("--hess-proj", type=int, default=4)

@@ -144,12 +144,22 @@ def _world(ind):
     return np.asarray(V, dtype=np.float64) @ R.T + np.asarray(ind.c)[None], np.asarray(F, dtype=np.int64)
 
 
+def _near_boxes(P, lo, hi, dmax):
+    """Index pairs (i, j) with point P[i] within dmax of the box [lo_j, hi_j]
+    in every coordinate: a superset of the pairs nearer than dmax (a point
+    farther than dmax from a feature's bounding box is farther from the
+    feature), taken in order of i, then j."""
+    if not np.isfinite(dmax):
+        return np.repeat(np.arange(P.shape[0]), lo.shape[0]), np.tile(np.arange(lo.shape[0]), P.shape[0])
+    near = np.all((P[:, None, :] >= lo[None] - dmax) & (P[:, None, :] <= hi[None] + dmax), axis=2)
+    return np.nonzero(near)
+
+
 def vf_pairs(Yw, x, tris, dmax):
     """Every (mesh vertex, pad triangle) pair nearer than dmax:
     (vertex [P], triangle [P], d [P], lam [P, 3], u [P, 3])."""
-    nv, nt = Yw.shape[0], tris.shape[0]
-    iv = np.repeat(np.arange(nv), nt)
-    it = np.tile(np.arange(nt), nv)
+    corners = x[tris]
+    iv, it = _near_boxes(Yw, corners.min(axis=1), corners.max(axis=1), dmax)
     d, lam = closest_on_triangles(Yw[iv], x[tris[it, 0]], x[tris[it, 1]], x[tris[it, 2]])
     keep = d < dmax
     iv, it, d, lam = iv[keep], it[keep], d[keep], lam[keep]
@@ -161,9 +171,18 @@ def vf_pairs(Yw, x, tris, dmax):
 def ee_pairs(Yw, medges, x, pedges, dmax):
     """Every (mesh edge, pad edge) pair nearer than dmax:
     (mesh edge [P], pad edge [P], d [P], s [P], t [P], u [P, 3])."""
-    ne, nf = medges.shape[0], pedges.shape[0]
-    ie = np.repeat(np.arange(ne), nf)
-    jf = np.tile(np.arange(nf), ne)
+    # the closest point of the mesh edge lies within dmax of the pad edge's
+    # box, so some point of the mesh edge does: test the mesh edge's box
+    # against the pad edge's box grown by dmax
+    ends = x[pedges]
+    elo, ehi = Yw[medges].min(axis=1), Yw[medges].max(axis=1)
+    flo, fhi = ends.min(axis=1), ends.max(axis=1)
+    if np.isfinite(dmax):
+        near = np.all((elo[:, None, :] <= fhi[None] + dmax) & (ehi[:, None, :] >= flo[None] - dmax), axis=2)
+        ie, jf = np.nonzero(near)
+    else:
+        ie = np.repeat(np.arange(medges.shape[0]), pedges.shape[0])
+        jf = np.tile(np.arange(pedges.shape[0]), medges.shape[0])
     p0, p1 = Yw[medges[ie, 0]], Yw[medges[ie, 1]]
     q0, q1 = x[pedges[jf, 0]], x[pedges[jf, 1]]
     d, s, t = closest_on_segments(p0, p1, q0, q1)

@@ -127,9 +127,6 @@ __device__ void sym_eig3(R A[3][3], R Q[3][3], R w[3]) {
   w[0] = A[0][0]; w[1] = A[1][1]; w[2] = A[2][2];
 }
 
-template <typename R>
-__device__ __forceinline__ void swap_cols(R M[3][3], R w[3], int) {}
-
 template <int i, int j, typename R>
 __device__ __forceinline__ void sort_pair(R V[3][3], R w[3]) {
   if (w[i] < w[j]) {
@@ -1127,30 +1124,6 @@ __global__ void k_project(const Tile* tiles, int ntiles, const EnvDesc* envs, in
     dmin = fmin(dmin, phi);
   }
   if (!(dmin > 0.0)) atomicOr(&S->infeasible, 1);
-}
-
-// Block (a, b) of a per-tet record (the 10 stored blocks, a <= b; the
-// transpose for a > b).
-template <typename R>
-__device__ __forceinline__ void load_block(const R* rec, int a, int b, R blk[3][3]) {
-  if (a == b) {
-    const R* p = rec + ke_block_offset(a, a);
-    blk[0][0] = p[0]; blk[0][1] = p[1]; blk[0][2] = p[2];
-    blk[1][0] = p[1]; blk[1][1] = p[3]; blk[1][2] = p[4];
-    blk[2][0] = p[2]; blk[2][1] = p[4]; blk[2][2] = p[5];
-  } else if (a < b) {
-    const R* p = rec + ke_block_offset(a, b);
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int k = 0; k < 3; ++k) blk[i][k] = p[3 * i + k];
-  } else {
-    const R* p = rec + ke_block_offset(b, a);
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-      for (int k = 0; k < 3; ++k) blk[i][k] = p[3 * k + i];
-  }
 }
 
 // ------------------------------------------------------ element (a3)

@@ -147,3 +147,37 @@ def test_server_evicts_idle_scratch():
     ctx.close()
     _check(eps, alone, results, final, stats, f"server, budget {budget / 2**20:.1f} MiB, one pad at a time")
     assert stats["evictions"] > 0
+
+
+def test_server_plan_rebuilt_after_pad_recreated():
+    """A pad destroyed between two requests of a live server and a new pad
+    created in its place (on the host often at the same address, with the
+    same arena scratch): the server must not replay the old pad's batch
+    plan.  The new pad's steps equal the same steps run alone, bitwise."""
+    eps = _episodes()
+    a, b = eps[1], eps[3]
+    alone_b = _alone([b])[0]
+    ctx = tc.Context(0)
+    srv = tc.Server(ctx, 2)
+
+    def serve(g, ep, steps):
+        out = []
+        for s in steps:
+            srv.submit(g, [ep.pose(s)], tag=s)
+            t0 = time.perf_counter()
+            while not out or out[-1]["tag"] != s:
+                out += srv.poll(wait_us=2000)
+                assert time.perf_counter() - t0 < 60, "server did not finish"
+        return out
+
+    ga = gpu_pad(ctx, a.pad, "mixed")
+    assert all(r["status"] == 0 for r in serve(ga, a, [1, 2]))
+    ga.close()
+    gb = gpu_pad(ctx, b.pad, "mixed")
+    res = serve(gb, b, range(1, N_STEPS + 1))
+    assert [(r["stats"].newton_iters, r["stats"].cg_iters) for r in res] == alone_b[2]
+    assert np.array_equal(gb.read("positions"), alone_b[0]) and np.array_equal(gb.read("sigma"), alone_b[1])
+    log(f"recreated pad: {len(res)} requests equal the pad alone")
+    srv.close()
+    gb.close()
+    ctx.close()

@@ -424,7 +424,7 @@ def mesh_indenter(ind):
     return Indenter(MESH, (0.0, 0.0, 0.0, 0.0), ind.R.copy(), ind.c.copy(), mesh)
 
 
-VARIANTS = ("slide", "friction", "layers", "mesh")
+VARIANTS = ("slide", "friction", "layers", "mesh", "mesh2")
 
 
 def config3_variant(kind, n_envs=60):
@@ -441,7 +441,9 @@ def config3_variant(kind, n_envs=60):
                  the torus, whose mesh has concave edges on the inner side
                  of the tube, with the barrier summed over triangle pairs
                  (mesh_contact 1: the distance to the whole mesh has a kink
-                 across each concave edge, where Newton can stall)."""
+                 across each concave edge, where Newton can stall);
+      mesh2    : the same meshes, every one with mesh_contact 2 (also mesh
+                 vertices against pad triangles and edge-edge pairs)."""
     if kind not in VARIANTS:
         raise ValueError(kind)
     rng = np.random.default_rng(np.random.SeedSequence(5))
@@ -456,9 +458,12 @@ def config3_variant(kind, n_envs=60):
             idx, mats = layered_materials(e.pad.X, e.pad.tets, e.pad.X[:, 2].min() + 0.5 * e.pad.dims[2], m,
                                           Material(8.0 * m.E, 0.42, 1200.0))
             e = dataclasses.replace(e, layers=(idx, mats))
-        else:
+        elif kind == "mesh":
             e = dataclasses.replace(e, indenter=mesh_indenter(e.indenter),
                                     mesh_contact=int(e.indenter.shape == TORUS))
+        else:
+            mi = mesh_indenter(e.indenter)
+            e = dataclasses.replace(e, indenter=mi, mesh_contact=2 if mi.shape == MESH else 0)
         out.append(e)
     return out
 
