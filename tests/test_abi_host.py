@@ -244,7 +244,10 @@ def test_batch_variants_keep_the_batch():
                     assert e.indenter.shape == scenes.TEXTURE and e.indenter.mesh is None
                     continue
                 assert e.indenter.shape == scenes.MESH
-                assert e.mesh_contact == (1 if b.indenter.shape == scenes.TORUS else 0)
+                if kind == "mesh2":
+                    assert e.mesh_contact == 2
+                else:
+                    assert e.mesh_contact == (1 if b.indenter.shape == scenes.TORUS else 0)
                 V, F = e.indenter.mesh
                 assert _status(lambda: __import__("paper_2606_20426_amd").validate(rigid_mesh=(V, F))) == 0
                 # every mesh vertex on or inside the analytic surface
