@@ -253,28 +253,43 @@ def pair_terms(ind, x, tris, pedges, pedge_len0, dhat, kappa):
     return E, g, (np.zeros(0, np.int64), np.zeros(0, np.int64), np.zeros((0, 3, 3)))
 
 
+def _pair_bound(d, pm, sep, pu):
+    """Per pair, the larger of two safe step fractions (reading; both keep
+    the pair apart): 0.9 d / pm, since the distance shrinks at most by alpha
+    times the largest vertex displacement pm; and, with u the unit vector
+    between the closest points, sep = min over the mesh feature of w.u -
+    max over the pad feature's vertices of x_a.u (the features' separation
+    along u, a lower bound on their distance for any positions) and pu =
+    max_a p_a.u, 0.9 sep / pu (no bound when pu <= 0), so that motion
+    across u does not count."""
+    with np.errstate(divide="ignore", invalid="ignore"):
+        a = np.where(pm > 0, 0.9 * d / pm, np.inf)
+        b = np.where(sep > 0, np.where(pu > 0, 0.9 * sep / pu, np.inf), 0.0)
+    return np.maximum(a, b)
+
+
 def step_bound(ind, x, p, tris, pedges):
     """Largest safe step fraction for the pad's surface triangles and edges
-    moving by alpha p against the rigid mesh: the distance between a fixed
-    point (or segment) and a moving triangle (or segment) shrinks at most by
-    alpha times the largest displacement of the moving one's vertices, so
-    alpha <= 0.9 d / max |p_a| keeps every pair apart."""
+    moving by alpha p against the rigid mesh (_pair_bound per pair, the
+    minimum over all pairs, at most 1)."""
     V0, F = ind.mesh
     _, medges = mesh_tables(V0, F)
     Yw, _ = _world(ind)
     pn = np.linalg.norm(p, axis=1)
     a = 1.0
     big = np.inf
-    iv, it, d, _, _ = vf_pairs(Yw, x, tris, big)
-    ptri = pn[tris].max(axis=1)[it]
-    mov = ptri > 0
-    if mov.any():
-        a = min(a, float(np.min(0.9 * d[mov] / ptri[mov])))
-    ie, jf, d, _, _, _ = ee_pairs(Yw, medges, x, pedges, big)
-    pe = pn[pedges].max(axis=1)[jf]
-    mov = pe > 0
-    if mov.any():
-        a = min(a, float(np.min(0.9 * d[mov] / pe[mov])))
+    iv, it, d, _, u = vf_pairs(Yw, x, tris, big)
+    if iv.size:
+        xu = np.einsum("pki,pi->pk", x[tris[it]], u)
+        pu = np.einsum("pki,pi->pk", p[tris[it]], u).max(axis=1)
+        sep = np.einsum("pi,pi->p", Yw[iv], u) - xu.max(axis=1)
+        a = min(a, float(np.min(_pair_bound(d, pn[tris].max(axis=1)[it], sep, pu))))
+    ie, jf, d, _, _, u = ee_pairs(Yw, medges, x, pedges, big)
+    if ie.size:
+        wu = np.einsum("pki,pi->pk", Yw[medges[ie]], u).min(axis=1)
+        xu = np.einsum("pki,pi->pk", x[pedges[jf]], u).max(axis=1)
+        pu = np.einsum("pki,pi->pk", p[pedges[jf]], u).max(axis=1)
+        a = min(a, float(np.min(_pair_bound(d, pn[pedges].max(axis=1)[jf], wu - xu, pu))))
     return a
 
 
@@ -285,7 +300,13 @@ def signed_pairs(ind, x, tris, pedges, window, below=0.0):
     closest point is inside the triangle, signed along its outward normal;
     edge-edge pairs with both closest points inside their segments, signed
     along the pad edge's outward direction (the sum of the normals of the
-    pad triangles sharing the edge).  Returns a list of
+    pad triangles sharing the edge).  A pair counts only when the vector
+    between its closest points lies within 60 degrees of the primitive's
+    normal line (|signed distance| >= d / 2, always true for a vertex over
+    a triangle's interior): next to a pad edge or corner, a mesh feature
+    above one surface region can sit behind the plane of a neighbouring
+    one (a side face's plane extends above the top face) without being
+    inside the pad (reading).  Returns a list of
     (pad vertex ids [k], outward unit normal [3], signed distance,
     primitive) with primitive = triangle index for vertex-face pairs and
     number of triangles + edge index for edge-edge pairs."""
@@ -298,7 +319,7 @@ def signed_pairs(ind, x, tris, pedges, window, below=0.0):
     n = np.cross(b - a, c - a)
     n /= np.linalg.norm(n, axis=1)[:, None]
     sd = np.einsum("pi,pi->p", Yw[iv] - a, n)
-    interior = (lam > 0).all(axis=1)
+    interior = (lam > 0).all(axis=1) & (np.abs(sd) >= 0.5 * d)
     for k in np.nonzero(interior & (sd < below))[0]:
         out.append((tris[it[k]], n[k], float(sd[k]), int(it[k])))
     # outward direction of each pad edge: sum of its triangles' normals
@@ -315,7 +336,7 @@ def signed_pairs(ind, x, tris, pedges, window, below=0.0):
     p = Yw[medges[ie, 0]] + s[:, None] * (Yw[medges[ie, 1]] - Yw[medges[ie, 0]])
     q = x[pedges[jf, 0]] + t[:, None] * (x[pedges[jf, 1]] - x[pedges[jf, 0]])
     sd = np.einsum("pi,pi->p", p - q, en[jf])
-    interior = (s > 0) & (s < 1) & (t > 0) & (t < 1)
+    interior = (s > 0) & (s < 1) & (t > 0) & (t < 1) & (np.abs(sd) >= 0.5 * d)
     for k in np.nonzero(interior & (sd < below))[0]:
         out.append((pedges[jf[k]], en[jf[k]], float(sd[k]), tris.shape[0] + int(jf[k])))
     return out

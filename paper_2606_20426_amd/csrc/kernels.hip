@@ -610,6 +610,8 @@ struct PairTerm {
   double wt;        // weight without kappa: a_y, or |e| |f|_0 / 4
   double m, dm;     // mollifier and dm/dc (1 and 0 for vertex-face)
   double dc1[3];    // dc/dx_1 of the pad edge (edge-edge)
+  double sep;       // separation along u: min over the mesh feature of w.u - max over the pad
+                    // feature's vertices of x_a.u (a lower bound on the distance; 0 when d = 0)
   bool interior;    // both closest points interior to their features
 };
 
@@ -774,6 +776,12 @@ __device__ void visit_pairs(const EnvDesc& E, const EnvPose* P, int j, const dou
           pt.dm = 0.0;
           pt.dc1[0] = pt.dc1[1] = pt.dc1[2] = 0.0;
           pt.interior = pt.lam[0] > 0 && pt.lam[1] > 0 && pt.lam[2] > 0;
+          pt.sep = 0.0;
+          if (pt.d > 0.0) {
+            const double iu = 1.0 / pt.d;
+            auto pr = [&](const double* q) { return (q[0] * dl[0] + q[1] * dl[1] + q[2] * dl[2]) * iu; };
+            pt.sep = pr(y) - fmax(fmax(pr(xl[0]), pr(xl[1])), pr(xl[2]));
+          }
         } else {
           if (!((own >> (3 + k)) & 1u)) continue;
           const int e = id[3 + k];
@@ -805,6 +813,12 @@ __device__ void visit_pairs(const EnvDesc& E, const EnvPose* P, int j, const dou
           for (int i = 0; i < 3; ++i) dcl[i] = 2.0 * (ee * fv[i] - ef * ev[i]);
           world(dcl, pt.dc1);
           pt.interior = sp > 0.0 && sp < 1.0 && tp > 0.0 && tp < 1.0;
+          pt.sep = 0.0;
+          if (pt.d > 0.0) {
+            const double iu = 1.0 / pt.d;
+            auto pr = [&](const double* q) { return (q[0] * dl[0] + q[1] * dl[1] + q[2] * dl[2]) * iu; };
+            pt.sep = fmin(pr(p0), pr(p1)) - fmax(pr(xl[0]), pr(xl[1]));
+          }
         }
         world(dl, pt.diff);
         const double id_ = pt.d > 0.0 ? 1.0 / pt.d : 0.0;
@@ -1387,7 +1401,8 @@ __device__ __forceinline__ void prim_outward(const EnvDesc& E, int j, const doub
 // Feasible start, pads with pairs: a mesh vertex or edge that the
 // indenter's jump to its new pose carried through the pad surface shows as
 // a pair with both closest points interior and the mesh feature on the
-// inner side.  mode 0: a primitive whose pairs (within the mesh's travel
+// inner side (sd < 0, the vector between the closest points within 60
+// degrees of the primitive's normal line).  mode 0: a primitive whose pairs (within the mesh's travel
 // plus d_hat) come below d_safe along its outward direction n asks its
 // vertices to move by (sd - d_safe) n for its deepest pair: the push and
 // its length go to its record, and k_pair_apply moves each vertex by the
@@ -1416,7 +1431,10 @@ __global__ void k_pair_push(const Tile* tiles, int ntiles, const EnvDesc* envs, 
   visit_pairs(E, P, j, xw, r, [&](int, const PairTerm& pt) {
     if (!pt.interior) return;
     const double sd = pt.diff[0] * n[0] + pt.diff[1] * n[1] + pt.diff[2] * n[2];
-    if (!(sd < below)) return;
+    // the closest points' vector within 60 degrees of the normal line: next
+    // to a pad edge or corner a feature above one surface region can sit
+    // behind the plane of a neighbouring one without being inside the pad
+    if (!(fabs(sd) >= 0.5 * pt.d) || !(sd < below)) return;
     ++cnt;
     sdmin = fmin(sdmin, sd);
   });
@@ -1500,25 +1518,36 @@ __device__ __forceinline__ bool pair_edge_block(const EnvDesc& E, int k, double 
 }
 
 // Collision-free step bound of pad primitive j moving by alpha p (p the
-// direction at its vertices): the distance to a fixed mesh feature shrinks
-// at most by alpha max_a |p_a|, so alpha <= 0.9 d / max |p_a| keeps every
-// pair apart; pairs farther than FILTER_SPAN max |p_a| / 0.9 cannot bind.
+// direction at its vertices).  Per pair the larger of two safe bounds: the
+// distance shrinks at most by alpha max_a |p_a|, so alpha <= 0.9 d /
+// max |p_a|; and the separation along the pair's unit vector u (a lower
+// bound on the distance) shrinks at most by alpha max_a p_a.u, so alpha <=
+// 0.9 sep / max_a p_a.u (none when that is <= 0): motion across u does not
+// count.  Pairs farther than FILTER_SPAN max |p_a| / 0.9 cannot bind.
 template <typename R>
 __device__ double prim_pair_bound(const EnvDesc& E, const EnvPose* P, int j, const R* d, double span) {
   int vid[3];
-  double xw[3][3];
+  double xw[3][3], pv[3][3];
   const int nv = prim_load<R>(E, j, E.xn, nullptr, 0.0, vid, xw);
   double pm = 0.0;
   for (int k = 0; k < nv; ++k) {
     double q = 0.0;
-    for (int c = 0; c < 3; ++c) q += (double)d[3 * vid[k] + c] * (double)d[3 * vid[k] + c];
+    for (int c = 0; c < 3; ++c) {
+      pv[k][c] = (double)d[3 * vid[k] + c];
+      q += pv[k][c] * pv[k][c];
+    }
     pm = fmax(pm, sqrt(q));
   }
   if (!(pm > 0.0)) return INFINITY;
   double r[MAX_IND];
   for (int m = 0; m < MAX_IND; ++m) r[m] = span * pm / 0.9;
   double a = INFINITY;
-  visit_pairs(E, P, j, xw, r, [&](int, const PairTerm& pt) { a = fmin(a, 0.9 * pt.d / pm); });
+  visit_pairs(E, P, j, xw, r, [&](int, const PairTerm& pt) {
+    double pu = -INFINITY;
+    for (int k = 0; k < nv; ++k) pu = fmax(pu, pv[k][0] * pt.u[0] + pv[k][1] * pt.u[1] + pv[k][2] * pt.u[2]);
+    const double b = pt.sep > 0.0 ? (pu > 0.0 ? 0.9 * pt.sep / pu : INFINITY) : 0.0;
+    a = fmin(a, fmax(0.9 * pt.d / pm, b));
+  });
   return a;
 }
 

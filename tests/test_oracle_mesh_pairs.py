@@ -235,3 +235,32 @@ def test_corner_between_pad_vertices_needs_the_triangle_pairs():
     assert np.abs(r1).max() == 0 and m1 < 1e-15 and t1            # through the surface, unseen
     assert min(p[2] for p in t1) < -0.15 * MM
     assert r2[2] > 0.5 and not t2 and m2 > 0.1 * MM              # held: force, deformation, no crossing
+
+
+def test_step_bound_lets_tangential_motion_through():
+    """A pad sliding sideways under a mesh vertex held just above a triangle:
+    the separation along the pair direction does not change, so the bound
+    allows the full step where the displacement bound 0.9 d / |p| would cut
+    it to a fraction; every pair stays apart along the step."""
+    X, tris, edges, elen = _flat_pad(2, 2 * MM)
+    t0 = X[tris[3]].mean(axis=0)
+    V = np.array([[0, 0, 0], [1, 0, 3], [-1, 1, 3], [-1, -1, 3.]]) * MM
+    F = np.array([[0, 2, 1], [0, 3, 2], [0, 1, 3], [1, 2, 3]])
+    h = 0.01 * MM
+    ind = _Mesh(V, F, t0 + [0, 0, h])
+    p = np.zeros_like(X)
+    p[:, 0] = 0.2 * MM                               # sideways, 20 h
+    a = mp.step_bound(ind, X, p, tris, edges)
+    assert a == 1.0
+    p[:, 2] = -0.5 * h                               # and half the gap away from the apex
+    assert mp.step_bound(ind, X, p, tris, edges) == 1.0
+    p[:, 2] = 2.0 * h                                # towards it: 0.9 h / 2 h
+    a = mp.step_bound(ind, X, p, tris, edges)
+    assert np.isclose(a, 0.45)
+    Yw, _ = mp._world(ind)
+    _, medges = mp.mesh_tables(*ind.mesh)
+    for f in np.linspace(0, 1, 21):
+        Xa = X + f * a * p
+        d0 = mp.vf_pairs(Yw, Xa, tris, np.inf)[2].min()
+        d1 = mp.ee_pairs(Yw, medges, Xa, edges, np.inf)[2].min()
+        assert min(d0, d1) > 0
