@@ -7,6 +7,9 @@
 `stats` turns a `--kernel-trace --stats` kernel_stats CSV into a table of
 calls, average and total duration per kernel.
 
+`counters` turns one `--pmc` counter CSV (any counters) into a table of
+per-dispatch averages per kernel.
+
 `traffic` turns two `--pmc FETCH_SIZE` / `--pmc WRITE_SIZE` counter CSVs
 (KiB per dispatch) into HBM bytes per launch.  The counters are scaled by
 what they read for a device copy of known size run in the same process
@@ -89,6 +92,12 @@ def main(argv=None):
     s.add_argument("out")
     s.add_argument("--command", required=True)
     s.add_argument("--title", default="Kernel trace statistics")
+    c = sub.add_parser("counters")
+    c.add_argument("csv")
+    c.add_argument("out")
+    c.add_argument("--command", required=True)
+    c.add_argument("--title", default="Counters per dispatch")
+    c.add_argument("--top", type=int, default=12)
     t = sub.add_parser("traffic")
     t.add_argument("fetch_csv")
     t.add_argument("write_csv")
@@ -106,6 +115,29 @@ def main(argv=None):
                  "```", a.command, "```", "",
                  f"- kernel_sources_sha256: `{kernel_sources_hash()}`",
                  f"- total kernel time: {total / 1e6:.1f} ms", ""] + table + [""]
+        open(a.out, "w").write("\n".join(lines))
+        return
+
+    if a.cmd == "counters":
+        acc = collections.defaultdict(lambda: collections.defaultdict(list))
+        calls = collections.Counter()
+        for r in csv.DictReader(open(a.csv)):
+            name = short_name(r["Kernel_Name"])
+            acc[name][r["Counter_Name"]].append(float(r["Counter_Value"]))
+        names = sorted({c for d in acc.values() for c in d})
+        for k, d in acc.items():
+            calls[k] = max(len(v) for v in d.values())
+        lines = [f"# {a.title}", "", "Command (from the repository root, after `cd /tmp && export TMPDIR=/tmp`):", "",
+                 "```", a.command, "```", "",
+                 f"- kernel_sources_sha256: `{kernel_sources_hash()}`",
+                 "- values: averages over the kernel's dispatches of what rocprofv3 reports per dispatch", "",
+                 "| kernel | dispatches | " + " | ".join(names) + " |",
+                 "|---|---:|" + "---:|" * len(names)]
+        for k, _ in calls.most_common(a.top):
+            d = acc[k]
+            vals = [("%.4g" % (sum(d[n]) / len(d[n]))) if d.get(n) else "" for n in names]
+            lines.append(f"| `{k}` | {calls[k]} | " + " | ".join(vals) + " |")
+        lines.append("")
         open(a.out, "w").write("\n".join(lines))
         return
 

@@ -24,7 +24,7 @@ import scipy.sparse.linalg as spla
 
 from gpu_util import (context, free_surface_vertices, gpu_pad, log, oracle_pad, surface_gap, tc,
                       voigt_to_mat)
-from oracle import extract, stepper
+from oracle import extract, mesh_pairs, stepper
 from workloads import scenes
 
 pytestmark = pytest.mark.gpu
@@ -197,7 +197,7 @@ def test_batch60_bench_configuration(batch60_run, step, ks):
 # variant changes (pads 0-5 carry cube, sphere, sphere, cylinder, torus,
 # texture) on all three pad shapes
 VARIANT_CHECKS = {"friction": (0, 3, 5), "slide": (0, 3, 5), "layers": (1, 4, 5), "mesh": (0, 1, 3, 4),
-                  "paper60": (0, 1, 2, 3, 4)}
+                  "mesh2": (0, 1, 3, 13), "paper60": (0, 1, 2, 3, 4)}
 
 
 @pytest.fixture(scope="module", params=sorted(VARIANT_CHECKS))
@@ -253,7 +253,7 @@ def _run_variant(kind, envs, ctx, kw, ids, pads):
         newton.append(max(x.newton_iters for x in st))
         # brute-force distances to triangle meshes are slow in the oracle:
         # every third step there, every step for the analytic shapes
-        if kind != "mesh" or s % 3 == 0 or s == last:
+        if kind not in ("mesh", "mesh2") or s % 3 == 0 or s == last:
             gaps.append(min(surface_gap(free_v[k], pads[k].read("positions"), [e.pose(s)])
                             for k, e in enumerate(envs)))
             assert gaps[-1] > 0, (s, gaps[-1])
@@ -285,10 +285,15 @@ def test_batch60_variants(variant_run):
             op = stepper.make_pad(e.pad.X, e.pad.tets, m.E, m.nu, m.density, fixed=e.pad.fixed)
         prm = stepper.StepParams(dt=e.params.dt, dhat=e.params.dhat, kappa=e.params.kappa,
                                  newton_tol=e.params.newton_tol, mu_f=e.friction, eps_v=0.01,
-                                 mesh_pairs=bool(e.mesh_contact))
+                                 mesh_pairs=int(e.mesh_contact))
         check_state(out, op, x_prev, v_prev, [e.pose(step)], prm,
                     f"batch60-{kind} pad {k} ({e.pad.name}, {e.pad.tets.shape[0]} tets, indenter "
                     f"{e.indenter.shape}) step {step}", inds_prev=[e.pose(step - 1)])
+        if e.mesh_contact == 2:
+            # no mesh vertex or edge through the pad surface
+            through = [q for q in mesh_pairs.signed_pairs(e.pose(step), out["positions"], op.tris, op.pedges,
+                                                           e.params.dhat) if q[2] < 0]
+            assert not through, through[:3]
         if kind == "friction":
             r = out["reaction"].ravel()
             log(f"  tangential / normal reaction {np.hypot(r[0], r[1]) / max(abs(r[2]), 1e-300):.3f}")
