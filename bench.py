@@ -298,9 +298,9 @@ def run_steps(args):
         log(f"warmup {s}: newton max {max(x.newton_iters for x in st)} cg sum {sum(x.cg_iters for x in st)}")
     streams = tuned["streams"] if tuned else args.streams
 
-    def timed(label):
-        if not args.no_timing:
-            ctx.set_timing(True, stride=args.timing_stride)
+    def timed(label, timing):
+        ctx.set_timing(bool(timing), stride=args.timing_stride)
+        if timing:
             ctx.reset_timing()
         torch.cuda.synchronize()
         lat, newton, cg = [], [], []
@@ -314,29 +314,31 @@ def run_steps(args):
             log(f"{label} step {s}: {lat[-1]:.1f} ms, newton max {newton[-1]}, cg total {cg[-1]}")
         torch.cuda.synchronize()
         total = time.perf_counter() - t_start
-        roof = roofline(ctx, args, copy_gbs) if not args.no_timing else None
+        roof = roofline(ctx, args, copy_gbs) if timing else None
+        ctx.set_timing(False)
         return total, lat, newton, cg, roof
 
     n_env = len(envs)
     single = None
-    if streams > 1 and not args.sequential and not args.no_timing:
-        # kernels of several streams overlap, which stretches each launch's
-        # duration: the kernel roofline comes from the same steps on one
-        # stream first, then the pads go back to their state after warm-up
+    if not args.no_timing:
+        # the kernel roofline: the timed steps on one stream with every
+        # kernel timed (kernels of several streams overlap, which stretches
+        # each launch's duration, and the timing itself costs about a tenth
+        # of the throughput); then the pads go back to their state after
+        # warm-up and the same steps run untimed for the headline
         saved = [p.save_state() for p in pads]
-        ctx.set_streams(1)
-        total1, _, _, _, roof1 = timed("one stream:")
+        if not args.sequential:
+            ctx.set_streams(1)
+        total1, _, _, _, roof1 = timed("timed, one stream:", True)
         single = (total1, roof1)
         for p, b in zip(pads, saved):
             p.load_state(b)
-        ctx.set_streams(streams)
-    total, lat, newton, cg, roof = timed(f"{streams} streams:" if streams > 1 else "")
+        if not args.sequential:
+            ctx.set_streams(streams)
+    total, lat, newton, cg, _ = timed(f"{streams} stream(s):", False)
     value = n_env * args.steps / total
-    if single is not None:
-        concurrent = roof
-        roof = dict(single[1], streams=1, concurrent={
-            "streams": streams, "frac": concurrent["frac"], "avg_launch_ms": concurrent["avg_launch_ms"],
-            "kernels": concurrent["kernels"]}) if single[1] else None
+    roof = dict(single[1], streams=1, measured_on="the same steps on one stream, every kernel timed") \
+        if single and single[1] else None
     mode = "sequential" if args.sequential else "batched"
     out = {
         "metric": METRIC,
@@ -352,7 +354,7 @@ def run_steps(args):
                    "newton_max_mean": float(np.mean(newton)), "cg_iters_mean": float(np.mean(cg)),
                    "precision": args.precision, "graphs": bool(args.graphs and args.no_timing),
                    "streams": streams, "autotuned": tuned,
-                   "one_stream_steps_per_s": round(n_env * args.steps / single[0], 2) if single else None},
+                   "timed_one_stream_steps_per_s": round(n_env * args.steps / single[0], 2) if single else None},
         "roofline": roof,
     }
     if args.workload == "paper60":

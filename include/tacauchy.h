@@ -180,8 +180,10 @@ typedef struct {
                            full Newton step is accepted, then unfiltered.  In
                            every mode a CG breakdown (negative curvature)
                            never counts as convergence: its iterate is used
-                           as a descent direction and every Hessian is
-                           clamped for the rest of the step. */
+                           as a descent direction, the element Hessians are
+                           clamped for the rest of the step, and so are the
+                           barrier Hessians once a breakdown leaves a zero
+                           iterate or happens a second time. */
   int32_t init_guess;   /* Newton start: 0 = x_t, 1 = x_t + dt v_t (free
                            components); either is then made feasible */
   double cg_conv_tol;   /* CG tolerance of the direction on which Newton

@@ -2283,12 +2283,14 @@ __global__ void k_env_dir(const EnvDesc* envs, int n) {
     const bool tight = S->cg_tol2 <= E.cg_conv_tol * E.cg_conv_tol * (1.0 + 1e-12) || S->cg_iters >= E.max_cg;
     if (S->breakdown) {
       // negative curvature met (an unfiltered element or barrier Hessian):
-      // keep the CG iterate (a descent direction, possibly zero: a breakdown
-      // at the first iteration leaves d = 0) but judge nothing on it, and
-      // filter every Hessian for the rest of the step
+      // keep the CG iterate (a descent direction) but judge nothing on it,
+      // and filter the element Hessians for the rest of the step.  The
+      // barrier Hessians too once the iterate is zero (a breakdown at the
+      // first iteration) or at the second breakdown of the step: the
+      // unfiltered ones would give the same breakdown again
       S->no_true_hess = 1;
       S->true_hess = 0;
-      S->filt_all = 1;
+      if (!(dm > 0.0) || ++S->n_breakdown >= 2) S->filt_all = 1;
       S->dir_conv = 0;
     } else {
       S->dir_conv = dm <= E.tol_abs && tight;

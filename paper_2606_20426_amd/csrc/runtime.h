@@ -164,6 +164,7 @@ struct tc_pad {
   double mu[tc::MAX_MAT], lam[tc::MAX_MAT], alpha[tc::MAX_MAT], rho[tc::MAX_MAT];
   double bbox_diag = 0.0;
   int64_t step_count = 0;
+  int last_newton = 0;               // Newton iterations of the last completed step (batch grouping)
   // indenter poses of the last completed step (friction lag), n_prev = 0: none
   int n_prev = 0;
   tc_indenter prev[TC_MAX_INDENTERS];

@@ -284,10 +284,14 @@ static hipError_t timed_launch(tc_context* ctx, TimingSlice& ts, KernelId k, boo
 }
 
 // Called after `stream`, the one the slice's launches went to, has been
-// synchronised.
-static void resolve_timing(tc_context* ctx, TimingSlice& ts, hipStream_t stream) {
+// synchronised.  Events are read at every call; the clock cells (one more
+// copy and synchronisation) only when `all` is set or the slice is half
+// full, so the readbacks inside a step do not pay for them.
+static void resolve_timing(tc_context* ctx, TimingSlice& ts, hipStream_t stream, bool all) {
   std::vector<unsigned long long> clk;
-  if (ts.used > 0) {
+  const size_t cap = ts.cap ? ts.cap : ctx->clock_cap;
+  const bool cells = all || 2 * ts.used > cap;
+  if (cells && ts.used > 0) {
     clk.resize(ts.used);
     if (hipMemcpyAsync(clk.data(), ctx->clock_cells + ts.base, 8 * clk.size(), hipMemcpyDeviceToHost, stream) !=
             hipSuccess ||
@@ -297,8 +301,13 @@ static void resolve_timing(tc_context* ctx, TimingSlice& ts, hipStream_t stream)
     ts.used = 0;
   }
   std::lock_guard<std::mutex> lk(ctx->tmu);
+  std::vector<Pending> keep;
   for (auto& p : ts.pending) {
     if (p.blocks >= 0) {
+      if (!cells) {
+        keep.push_back(p);
+        continue;
+      }
       if (p.cell + 2 * (size_t)p.blocks <= clk.size()) {
         // blocks past the tile list store nothing (zero cells)
         unsigned long long t0 = ~0ull, t1 = 0;
@@ -323,10 +332,10 @@ static void resolve_timing(tc_context* ctx, TimingSlice& ts, hipStream_t stream)
     ctx->free_events.push_back(p.a);
     ctx->free_events.push_back(p.b);
   }
-  ts.pending.clear();
+  ts.pending.swap(keep);
 }
 
-static void resolve_timing(tc_context* ctx) { resolve_timing(ctx, ctx->tslice, ctx->stream); }
+static void resolve_timing(tc_context* ctx) { resolve_timing(ctx, ctx->tslice, ctx->stream, true); }
 
 // ------------------------------------------------------------ scratch layout
 
@@ -665,7 +674,7 @@ tc_status Runner::readback() {
   TC_HIP(hipMemcpyAsync(pool->h_state, pool->d_state, sizeof(EnvState) * span, hipMemcpyDeviceToHost, strm()));
   TC_HIP(hipStreamSynchronize(strm()));
   P->ctiles_off = 0;
-  if (ctx->timing) resolve_timing(ctx, slice(), strm());
+  if (ctx->timing) resolve_timing(ctx, slice(), strm(), false);
   return TC_OK;
 }
 
@@ -876,16 +885,19 @@ tc_status run_batch(tc_context* ctx, int n, tc_pad* const* pads, const int32_t* 
   if (G == 1) {
     for (int i = 0; i < n; ++i) groups[0].push_back(i);
   } else {
-    // largest pads first to the group with the fewest tets; each group keeps
-    // the batch order
+    // a pad's cost is taken as its tets times the Newton iterations of its
+    // last step (a step's length is set by the pads that iterate longest:
+    // they go to different groups); largest cost first to the group with
+    // the least, each group keeping the batch order
+    auto cost = [&](int i) { return (int64_t)pads[i]->T * std::max(1, pads[i]->last_newton); };
     std::vector<int> order(n);
     for (int i = 0; i < n; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return pads[x]->T > pads[y]->T; });
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost(x) > cost(y); });
     std::vector<int64_t> load(G, 0);
     for (int i : order) {
       const int g = (int)(std::min_element(load.begin(), load.end()) - load.begin());
       groups[g].push_back(i);
-      load[g] += pads[i]->T;
+      load[g] += cost(i);
     }
     for (auto& gr : groups) std::sort(gr.begin(), gr.end());
   }
@@ -958,6 +970,9 @@ tc_status run_batch(tc_context* ctx, int n, tc_pad* const* pads, const int32_t* 
         }
       }
     }
+    // the step's remaining clock cells (the stream is synchronised: every
+    // tick ends with a readback)
+    if (ctx->timing) resolve_timing(ctx, *L.ts, L.stream, true);
     J.st = st;
     if (st) J.err = last_error();
   };
@@ -991,6 +1006,7 @@ tc_status run_batch(tc_context* ctx, int n, tc_pad* const* pads, const int32_t* 
       const EnvState& S = J.lane->pool->h_state[k];
       if (S.status == TC_OK && mode == 0) {
         pads[i]->step_count++;
+        pads[i]->last_newton = S.newton_iters;
         remember_pose(pads[i], J.lane->pool->h_pose[k]);
       }
       if (S.status != TC_OK && first == TC_OK) first = S.status;
@@ -1739,6 +1755,7 @@ tc_status tc_pad_reset(tc_pad* pad) {
   TC_HIP(hipMemsetAsync(pad->desc.v, 0, 24 * (size_t)pad->V, ctx->stream));
   TC_HIP(hipStreamSynchronize(ctx->stream));
   pad->step_count = 0;
+  pad->last_newton = 0;
   pad->n_prev = 0;
   return TC_OK;
 }

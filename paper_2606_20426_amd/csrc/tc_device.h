@@ -150,6 +150,7 @@ struct EnvState {
   int32_t true_hess;       // element Hessians unfiltered in this iteration
   int32_t no_true_hess;    // a breakdown happened: filtered for the rest of the step
   int32_t filt_all;        // the same for the barrier Hessians (any unfiltered mode)
+  int32_t n_breakdown;     // CG breakdowns in this step
   double cg_tol2;
   double rz0_prev;         // r0.z0 of the previous Newton iteration (< 0: none)
   double eta_prev;
