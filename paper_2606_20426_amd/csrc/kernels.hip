@@ -578,6 +578,10 @@ __device__ __forceinline__ void load3(const double* p, int i, double v[3]) {
   v[0] = p[3 * i]; v[1] = p[3 * i + 1]; v[2] = p[3 * i + 2];
 }
 
+// Step fractions the collision-free bounds cover: the line search may
+// double an accepted full step up to this.
+constexpr double FILTER_SPAN = 16.0;
+
 // ------------------------------------------------ rigid-mesh pairs (mesh_contact 2)
 
 // IPC's contact primitives between two surfaces are point-triangle and
@@ -1318,34 +1322,70 @@ __global__ void __launch_bounds__(256) k_element(const Tile* tiles, int ntiles, 
 
 __device__ __forceinline__ bool extract_ok(const EnvState* S);
 
-// Pair records at the Newton iterate (mode 0, pads running) or at the
-// extraction positions (mode 1): gradient and Gauss-Newton blocks of every
-// surface primitive's pairs within d_hat, flag 0 for a primitive without
-// pairs (its record is then not written).
+template <typename R>
+__device__ double prim_pair_bound(const EnvDesc& E, const EnvPose* P, int j, const R* d, double span);
+
+// Per surface primitive (pad triangles, then surface edges) of pads with
+// vertex-face / edge-edge pairs:
+//   mode 0: records at the Newton iterate (pads running), mode 1: at the
+//           extraction positions: gradient and Gauss-Newton blocks of the
+//           primitive's pairs within d_hat, flag 0 for a primitive without
+//           pairs (its record is then not written);
+//   mode 2: pair energy at the line search's trial x + alpha d (pads still
+//           searching), mode 4: at the start x (pads being initialised),
+//           partial sums after the barrier's in the energy partials;
+//   mode 3: the pairs' step bound along the Newton direction, partial
+//           minima after the contact vertices' in the filter partials.
+// The pair work has its own launches so that its traversal state does not
+// raise the register use of the energy and filter kernels.
+template <typename R>
 __global__ void k_pairs(const Tile* tiles, int ntiles, const EnvDesc* envs, int mode) {
+  __shared__ double sh[16];
   const int t = xcd_tile(ntiles);
   if (t < 0) return;
-  const EnvDesc& E = envs[tiles[t].env];
+  const Tile tl = tiles[t];
+  const EnvDesc& E = envs[tl.env];
   const EnvState* S = E.st;
   const EnvPose* P = E.pose;
-  if (mode == 0 ? !running(S) : !extract_ok(S)) return;
   if (!pair_active(E, P)) return;
-  const int j = tiles[t].tile * blockDim.x + threadIdx.x;
+  const int j = tl.tile * blockDim.x + threadIdx.x;
+  if (mode >= 2) {
+    // block reductions: every thread of the block takes part
+    if (mode == 2 ? (!running(S) || S->ls_done) : mode == 4 ? !initialising(S) : !running(S)) return;
+    const bool in = j < E.S + E.Se;
+    if (mode == 3) {
+      double a = INFINITY;
+      if (in) a = fmin(prim_pair_bound<R>(E, P, j, (const R*)E.d, FILTER_SPAN), FILTER_SPAN);
+      a = block_reduce(a, OpMin(), sh);
+      if (threadIdx.x == 0) E.part_filt[E.n_ct + tl.tile] = a;
+      return;
+    }
+    double e = 0.0;
+    if (in) {
+      int vid[3];
+      double xw[3][3];
+      prim_load<R>(E, j, E.xn, mode == 2 ? (const R*)E.d : nullptr, mode == 2 ? S->ls_alpha : 0.0, vid, xw);
+      e = prim_pair_energy(E, P, j, xw);
+    }
+    e = block_reduce(e, OpSum(), sh);
+    if (threadIdx.x == 0) E.part_e[E.n_te + E.n_vt + E.n_ct + tl.tile] = e;
+    return;
+  }
+  if (mode == 0 ? !running(S) : !extract_ok(S)) return;
   if (j >= E.S + E.Se) return;
   const double* x = (mode == 1 && S->mode == 1) ? E.x : E.xn;
   int vid[3];
   double xw[3][3];
   prim_load<double>(E, j, x, nullptr, 0.0, vid, xw);
-  double g[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, B[6][6];
-  for (int q = 0; q < 6; ++q)
-    for (int c = 0; c < 6; ++c) B[q][c] = 0.0;
   double r[MAX_IND];
   for (int m = 0; m < MAX_IND; ++m) r[m] = E.dhat;
   int n = 0;
-  // vertex pairs of the blocks (0,0) (1,1) (2,2) (0,1) (1,2) (2,0)
-  const int ba[6] = {0, 1, 2, 0, 1, 2}, bc[6] = {0, 1, 2, 1, 2, 0};
+  // a primitive has few pairs: each adds straight into the record (cleared
+  // at the first), which keeps the 45 sums out of registers
+  double* rec = E.prec + (size_t)PREC * j;
   visit_pairs(E, P, j, xw, r, [&](int, const PairTerm& pt) {
-    ++n;
+    if (n++ == 0)
+      for (int q = 0; q < 45; ++q) rec[q] = 0.0;
     const double s = pt.d / E.dhat;
     const double w = E.kappa * pt.wt;
     const double b0 = bar0(s), b1 = bar1(s), b2 = bar2(s);
@@ -1354,23 +1394,18 @@ __global__ void k_pairs(const Tile* tiles, int ntiles, const EnvDesc* envs, int 
         // w d_hat dm b sign(a) dc/dx_1 (edge-edge) + w m b' dd/dx_a
         double ga = -w * pt.m * b1 * pt.lam[a] * pt.u[i];
         if (pt.dm != 0.0 && a < 2) ga += w * E.dhat * pt.dm * b0 * (a == 1 ? 1.0 : -1.0) * pt.dc1[i];
-        g[a][i] += ga;
+        rec[3 * a + i] += ga;
       }
+    // vertex pairs of the blocks (0,0) (1,1) (2,2) (0,1) (1,2) (2,0)
     const double c2 = w * pt.m * b2 / E.dhat;
     const double uu[6] = {pt.u[0] * pt.u[0], pt.u[0] * pt.u[1], pt.u[0] * pt.u[2],
                           pt.u[1] * pt.u[1], pt.u[1] * pt.u[2], pt.u[2] * pt.u[2]};
-    for (int q = 0; q < 6; ++q) {
-      const double cq = c2 * pt.lam[ba[q]] * pt.lam[bc[q]];
-      for (int c = 0; c < 6; ++c) B[q][c] += cq * uu[c];
-    }
+    const double la[6] = {pt.lam[0] * pt.lam[0], pt.lam[1] * pt.lam[1], pt.lam[2] * pt.lam[2],
+                          pt.lam[0] * pt.lam[1], pt.lam[1] * pt.lam[2], pt.lam[2] * pt.lam[0]};
+    for (int q = 0; q < 6; ++q)
+      for (int c = 0; c < 6; ++c) rec[9 + 6 * q + c] += c2 * la[q] * uu[c];
   });
   E.pflag[j] = n > 0;
-  if (n == 0) return;
-  double* rec = E.prec + (size_t)PREC * j;
-  for (int a = 0; a < 3; ++a)
-    for (int i = 0; i < 3; ++i) rec[3 * a + i] = g[a][i];
-  for (int q = 0; q < 6; ++q)
-    for (int c = 0; c < 6; ++c) rec[9 + 6 * q + c] = B[q][c];
 }
 
 // Outward direction of pad primitive j at positions x: a triangle's unit
@@ -2167,7 +2202,6 @@ __global__ void k_newton_dir(const Tile* tiles, int ntiles, const EnvDesc* envs)
 // phi(x + a p) >= phi + a grad.p - K a^2 |p|^2 / 2.  Each keeps
 // phi >= 0.1 phi(x).  Steps are bounded for a <= FILTER_SPAN (the line
 // search may double an accepted full step up to there).
-constexpr double FILTER_SPAN = 16.0;
 
 __device__ __forceinline__ double quadratic_step(double phi, double gp, double K, double pn) {
   const double qa = K * pn * pn;
@@ -2185,12 +2219,7 @@ __global__ void k_filter(const Tile* tiles, int ntiles, const EnvDesc* envs) {
   if (!running(E.st)) return;
   const int k = tl.tile * blockDim.x + threadIdx.x;
   double amax = INFINITY;
-  if (tl.tile >= E.n_ct) {
-    // pair tiles (mesh_contact 2): the bound of the surface primitives
-    const int j = (tl.tile - E.n_ct) * blockDim.x + threadIdx.x;
-    if (j < E.S + E.Se && pair_active(E, P))
-      amax = fmin(prim_pair_bound<R>(E, P, j, (const R*)E.d, FILTER_SPAN), FILTER_SPAN);
-  } else if (k < E.C) {
+  if (k < E.C) {
     const int vi = E.cand[k];
     double x[3], p[3], H[3][3];
     load3(E.xn, vi, x);
@@ -2269,7 +2298,9 @@ __global__ void k_env_dir(const EnvDesc* envs, int n) {
     dm = fmax(dm, E.part_dir[2 * k]);
     gd += E.part_dir[2 * k + 1];
   }
-  for (int k = threadIdx.x; k < E.n_ct + E.n_pt; k += blockDim.x) am = fmin(am, E.part_filt[k]);
+  // the pairs' partial minima follow when the pad has pairs this step
+  const int nf = E.n_ct + (pair_active(E, E.pose) ? E.n_pt : 0);
+  for (int k = threadIdx.x; k < nf; k += blockDim.x) am = fmin(am, E.part_filt[k]);
   dm = block_reduce(dm, OpMax(), sh);
   gd = block_reduce(gd, OpSum(), sh);
   am = block_reduce(am, OpMin(), sh);
@@ -2361,16 +2392,8 @@ __global__ void k_energy(const Tile* tiles, int ntiles, const EnvDesc* envs, int
       }
       acc = 0.5 * E.mass[i] * s;
     }
-  } else if ((tt -= E.n_vt) >= E.n_ct) {
-    // pair tiles (mesh_contact 2)
-    const int j = (tt - E.n_ct) * blockDim.x + threadIdx.x;
-    if (j < E.S + E.Se && pair_active(E, P)) {
-      int vid[3];
-      double xw[3][3];
-      prim_load<R>(E, j, E.xn, mode ? d : nullptr, al, vid, xw);
-      acc = prim_pair_energy(E, P, j, xw);
-    }
   } else {
+    tt -= E.n_vt;
     const int k = tt * blockDim.x + threadIdx.x;
     if (k < E.C) {
       const int vi = E.cand[k];
@@ -2410,7 +2433,8 @@ __global__ void k_env_ls(const EnvDesc* envs, int n, int mode) {
   double el = 0, in = 0, ba = 0;
   for (int k = threadIdx.x; k < E.n_te; k += blockDim.x) el += E.part_e[k];
   for (int k = threadIdx.x; k < E.n_vt; k += blockDim.x) in += E.part_e[E.n_te + k];
-  for (int k = threadIdx.x; k < E.n_ct + E.n_pt; k += blockDim.x) ba += E.part_e[E.n_te + E.n_vt + k];
+  const int nb = E.n_ct + (pair_active(E, E.pose) ? E.n_pt : 0);   // the pairs' partial sums follow
+  for (int k = threadIdx.x; k < nb; k += blockDim.x) ba += E.part_e[E.n_te + E.n_vt + k];
   el = block_reduce(el, OpSum(), sh);
   in = block_reduce(in, OpSum(), sh);
   ba = block_reduce(ba, OpSum(), sh);
@@ -2800,7 +2824,7 @@ hipError_t launch_typed(KernelId id, const LaunchArgs& a) {
       if (a.n_env > 0) TC_GO(k_env_extract, a.n_env, 256, a.stream, a.envs, a.n_env);
       break;
     case KernelId::commit: TC_LAUNCH(k_commit, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs); break;
-    case KernelId::pairs: TC_LAUNCH(k_pairs, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs, a.mode); break;
+    case KernelId::pairs: TC_LAUNCH(k_pairs<R>, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs, a.mode); break;
     case KernelId::pair_push:
       TC_LAUNCH(k_pair_push, a.ntiles, a.block, a.stream, a.tiles, a.ntiles, a.envs, a.mode);
       break;

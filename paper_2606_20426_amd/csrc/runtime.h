@@ -196,9 +196,8 @@ struct BatchPlan {
   EnvState* h_state = nullptr;      // pinned
   Tile* d_tiles = nullptr;
   size_t dev_bytes = 0;
-  // PAIR: surface triangles and edges (mesh_contact 2); FILT: contact
-  // vertices, then PAIR
-  enum Cls { VERT, TET, CAND, SURF, ASM, ENERGY, SPMV, PAIR, FILT, NCLS };
+  // PAIR: surface triangles and edges (mesh_contact 2)
+  enum Cls { VERT, TET, CAND, SURF, ASM, ENERGY, SPMV, PAIR, NCLS };
   int lpr = 0;                       // SpMV lanes per row
   int off[NCLS] = {0}, cnt[NCLS] = {0};
   std::vector<EnvDesc> h_desc;

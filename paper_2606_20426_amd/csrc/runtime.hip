@@ -564,10 +564,9 @@ tc_status build_plan(tc_context* ctx, int n, tc_pad* const* pads, const int* slo
   add_cls(BatchPlan::CAND, [](const EnvDesc& E) { return E.n_ct; });
   add_cls(BatchPlan::SURF, [](const EnvDesc& E) { return E.n_st; });
   add_cls(BatchPlan::ASM, [](const EnvDesc& E) { return E.n_at; });
-  add_cls(BatchPlan::ENERGY, [](const EnvDesc& E) { return E.n_te + E.n_vt + E.n_ct + E.n_pt; });
+  add_cls(BatchPlan::ENERGY, [](const EnvDesc& E) { return E.n_te + E.n_vt + E.n_ct; });
   add_cls(BatchPlan::SPMV, [](const EnvDesc& E) { return E.n_spt; });
   add_cls(BatchPlan::PAIR, [](const EnvDesc& E) { return E.n_pt; });
-  add_cls(BatchPlan::FILT, [](const EnvDesc& E) { return E.n_ct + E.n_pt; });
   TC_HIP(hipMalloc(&P->d_desc, sizeof(EnvDesc) * n));
   TC_HIP(hipMalloc(&P->d_tiles, sizeof(Tile) * std::max<size_t>(tiles.size(), 1)));
   P->ctiles_cap = 4 * (int)tiles.size() + 64;
@@ -647,8 +646,8 @@ Runner::View Runner::view(bool (*pred)(const EnvState&)) {
       const EnvDesc& E = P->h_desc[i];
       const int cnt = c == BatchPlan::VERT ? E.n_vt : c == BatchPlan::TET ? E.n_tt : c == BatchPlan::CAND ? E.n_ct
                     : c == BatchPlan::SURF ? E.n_st : c == BatchPlan::ASM ? E.n_at
-                    : c == BatchPlan::ENERGY ? E.n_te + E.n_vt + E.n_ct + E.n_pt
-                    : c == BatchPlan::PAIR ? E.n_pt : c == BatchPlan::FILT ? E.n_ct + E.n_pt : E.n_spt;
+                    : c == BatchPlan::ENERGY ? E.n_te + E.n_vt + E.n_ct
+                    : c == BatchPlan::PAIR ? E.n_pt : E.n_spt;
       if (k + cnt > P->ctiles_cap) break;   // ring full: cannot happen (4x capacity)
       for (int t = 0; t < cnt; ++t) P->h_ctiles[k++] = Tile{i, t};
     }
@@ -736,6 +735,7 @@ tc_status Runner::tick(bool init) {
       launch_v(KernelId::pair_push, vi, BatchPlan::PAIR, 0, 1);
     }
     launch_v(KernelId::energy, vi, BatchPlan::ENERGY, 0, 0);
+    if (any_pairs(is_init)) launch_v(KernelId::pairs, vi, BatchPlan::PAIR, 0, 4);
     launch(KernelId::env_ls, BatchPlan::NCLS, 0, 0);
   }
   if (any(init ? init_or_run : is_run)) {
@@ -769,7 +769,8 @@ tc_status Runner::tick(bool init) {
     // the views are rebuilt after the sync: pads may have failed meanwhile
     const View vr = view(is_run);
     launch_v(KernelId::newton_dir, vr, BatchPlan::VERT);
-    launch_v(KernelId::filter, vr, BatchPlan::FILT);
+    launch_v(KernelId::filter, vr, BatchPlan::CAND);
+    if (any_pairs(is_run)) launch_v(KernelId::pairs, vr, BatchPlan::PAIR, 0, 3);
     launch(KernelId::env_dir, BatchPlan::NCLS);
     if (debug) {
       if ((st = readback())) return st;
@@ -785,8 +786,10 @@ tc_status Runner::tick(bool init) {
     // first line-search round without waiting for the direction's flags
     // (pads that converged skip it on the device)
     View vl = debug ? view(ls_pending) : vr;
+    const bool ls_pairs = any_pairs(is_run);
     for (int r = 0; r <= max_h + 1; ++r) {
       launch_v(KernelId::energy, vl, BatchPlan::ENERGY, 0, 1);
+      if (ls_pairs) launch_v(KernelId::pairs, vl, BatchPlan::PAIR, 0, 2);
       launch(KernelId::env_ls, BatchPlan::NCLS, 0, 1);
       if ((st = readback())) return st;
       if (debug)
@@ -1050,6 +1053,7 @@ tc_status newton_direction(tc_pad* pad, int n_ind, const tc_indenter* ind, doubl
   const Runner::View v = run.view(Runner::not_done);
   run.launch_v(KernelId::predict, v, BatchPlan::VERT);
   run.launch_v(KernelId::energy, v, BatchPlan::ENERGY, 0, 0);
+  if (run.any_pairs(Runner::not_done)) run.launch_v(KernelId::pairs, v, BatchPlan::PAIR, 0, 4);
   run.launch(KernelId::env_ls, BatchPlan::NCLS, 0, 0);
   run.launch(KernelId::newton_begin, BatchPlan::NCLS);
   run.launch_v(KernelId::element, v, BatchPlan::TET);
