@@ -253,25 +253,49 @@ def pair_terms(ind, x, tris, pedges, pedge_len0, dhat, kappa):
     return E, g, (np.zeros(0, np.int64), np.zeros(0, np.int64), np.zeros((0, 3, 3)))
 
 
-def _pair_bound(d, pm, sep, pu):
-    """Per pair, the larger of two safe step fractions (reading; both keep
-    the pair apart): 0.9 d / pm, since the distance shrinks at most by alpha
-    times the largest vertex displacement pm; and, with u the unit vector
-    between the closest points, sep = min over the mesh feature of w.u -
-    max over the pad feature's vertices of x_a.u (the features' separation
-    along u, a lower bound on their distance for any positions) and pu =
-    max_a p_a.u, 0.9 sep / pu (no bound when pu <= 0), so that motion
-    across u does not count."""
+def _advance(dist_at, d0, pm, span=1.0):
+    """Conservative advancement per pair (reading): every point of the
+    moving pad feature moves at most alpha pm, so the pair's distance
+    d(alpha) is Lipschitz with constant pm, and from a reached alpha the step
+    (d(alpha) - 0.1 d0) / pm keeps it above 0.1 d0.  Advances until within
+    0.1 % of that floor, 32 advances, or span; dist_at(alpha, mask) gives the
+    distances of the masked pairs at their alphas."""
+    al = np.zeros_like(d0)
+    dc = d0.copy()
+    floor = 0.1 * d0
+    live = (pm > 0) & (d0 > 0)
+    for _ in range(32):
+        if not live.any():
+            break
+        al = np.where(live, al + (dc - floor) / np.where(pm > 0, pm, 1.0), al)
+        hit = live & (al >= span)
+        al = np.where(hit, span, al)
+        live &= ~hit
+        if not live.any():
+            break
+        dc = np.where(live, dist_at(al, live), dc)
+        live &= dc - floor > 1e-3 * floor
+    al = np.where(pm > 0, al, np.inf)
+    return np.where(d0 > 0, al, 0.0)
+
+
+def _separation_bound(d, pm, sep, pu):
+    """With u the unit vector between a pair's closest points, sep = min
+    over the mesh feature of w.u - max over the pad feature's vertices of
+    x_a.u is the features' separation along u, a lower bound on their
+    distance for any positions, and it shrinks at most by alpha pu with pu =
+    max_a p_a.u: alpha <= 0.9 sep / pu keeps the pair apart (no bound when
+    pu <= 0), whatever the motion across u."""
     with np.errstate(divide="ignore", invalid="ignore"):
-        a = np.where(pm > 0, 0.9 * d / pm, np.inf)
-        b = np.where(sep > 0, np.where(pu > 0, 0.9 * sep / pu, np.inf), 0.0)
-    return np.maximum(a, b)
+        return np.where(sep > 0, np.where(pu > 0, 0.9 * sep / pu, np.inf), 0.0)
 
 
 def step_bound(ind, x, p, tris, pedges):
-    """Largest safe step fraction for the pad's surface triangles and edges
-    moving by alpha p against the rigid mesh (_pair_bound per pair, the
-    minimum over all pairs, at most 1)."""
+    """Largest safe step fraction (at most 1) for the pad's surface
+    triangles and edges moving by alpha p against the rigid mesh: per pair
+    the larger of two safe bounds (reading), conservative advancement
+    (_advance) and the separation along the pair direction
+    (_separation_bound); the minimum over all pairs."""
     V0, F = ind.mesh
     _, medges = mesh_tables(V0, F)
     Yw, _ = _world(ind)
@@ -280,16 +304,22 @@ def step_bound(ind, x, p, tris, pedges):
     big = np.inf
     iv, it, d, _, u = vf_pairs(Yw, x, tris, big)
     if iv.size:
-        xu = np.einsum("pki,pi->pk", x[tris[it]], u)
+        def vf_at(al, m):
+            xa = x[tris[it]] + al[:, None, None] * p[tris[it]]
+            return closest_on_triangles(Yw[iv], xa[:, 0], xa[:, 1], xa[:, 2])[0]
+        sep = np.einsum("pi,pi->p", Yw[iv], u) - np.einsum("pki,pi->pk", x[tris[it]], u).max(axis=1)
         pu = np.einsum("pki,pi->pk", p[tris[it]], u).max(axis=1)
-        sep = np.einsum("pi,pi->p", Yw[iv], u) - xu.max(axis=1)
-        a = min(a, float(np.min(_pair_bound(d, pn[tris].max(axis=1)[it], sep, pu))))
+        ca = _advance(vf_at, d, pn[tris].max(axis=1)[it])
+        a = min(a, float(np.min(np.maximum(ca, _separation_bound(d, None, sep, pu)))))
     ie, jf, d, _, _, u = ee_pairs(Yw, medges, x, pedges, big)
     if ie.size:
-        wu = np.einsum("pki,pi->pk", Yw[medges[ie]], u).min(axis=1)
-        xu = np.einsum("pki,pi->pk", x[pedges[jf]], u).max(axis=1)
+        def ee_at(al, m):
+            xa = x[pedges[jf]] + al[:, None, None] * p[pedges[jf]]
+            return closest_on_segments(Yw[medges[ie, 0]], Yw[medges[ie, 1]], xa[:, 0], xa[:, 1])[0]
+        sep = np.einsum("pki,pi->pk", Yw[medges[ie]], u).min(axis=1) - np.einsum("pki,pi->pk", x[pedges[jf]], u).max(axis=1)
         pu = np.einsum("pki,pi->pk", p[pedges[jf]], u).max(axis=1)
-        a = min(a, float(np.min(_pair_bound(d, pn[pedges].max(axis=1)[jf], wu - xu, pu))))
+        ca = _advance(ee_at, d, pn[pedges].max(axis=1)[jf])
+        a = min(a, float(np.min(np.maximum(ca, _separation_bound(d, None, sep, pu)))))
     return a
 
 

@@ -616,6 +616,8 @@ struct PairTerm {
   double dc1[3];    // dc/dx_1 of the pad edge (edge-edge)
   double sep;       // separation along u: min over the mesh feature of w.u - max over the pad
                     // feature's vertices of x_a.u (a lower bound on the distance; 0 when d = 0)
+  const double* w0; // the mesh feature in the mesh's frame: the vertex, or the edge's ends
+  const double* w1; //   (null for a vertex)
   bool interior;    // both closest points interior to their features
 };
 
@@ -780,6 +782,8 @@ __device__ void visit_pairs(const EnvDesc& E, const EnvPose* P, int j, const dou
           pt.dm = 0.0;
           pt.dc1[0] = pt.dc1[1] = pt.dc1[2] = 0.0;
           pt.interior = pt.lam[0] > 0 && pt.lam[1] > 0 && pt.lam[2] > 0;
+          pt.w0 = y;
+          pt.w1 = nullptr;
           pt.sep = 0.0;
           if (pt.d > 0.0) {
             const double iu = 1.0 / pt.d;
@@ -817,6 +821,8 @@ __device__ void visit_pairs(const EnvDesc& E, const EnvPose* P, int j, const dou
           for (int i = 0; i < 3; ++i) dcl[i] = 2.0 * (ee * fv[i] - ef * ev[i]);
           world(dcl, pt.dc1);
           pt.interior = sp > 0.0 && sp < 1.0 && tp > 0.0 && tp < 1.0;
+          pt.w0 = p0;
+          pt.w1 = p1;
           pt.sep = 0.0;
           if (pt.d > 0.0) {
             const double iu = 1.0 / pt.d;
@@ -1553,12 +1559,16 @@ __device__ __forceinline__ bool pair_edge_block(const EnvDesc& E, int k, double 
 }
 
 // Collision-free step bound of pad primitive j moving by alpha p (p the
-// direction at its vertices).  Per pair the larger of two safe bounds: the
-// distance shrinks at most by alpha max_a |p_a|, so alpha <= 0.9 d /
-// max |p_a|; and the separation along the pair's unit vector u (a lower
-// bound on the distance) shrinks at most by alpha max_a p_a.u, so alpha <=
-// 0.9 sep / max_a p_a.u (none when that is <= 0): motion across u does not
-// count.  Pairs farther than FILTER_SPAN max |p_a| / 0.9 cannot bind.
+// direction at its vertices).  Per pair the larger of two safe bounds:
+// conservative advancement (every point of the moving primitive moves at
+// most alpha max_a |p_a|, so the pair's distance d(alpha) is Lipschitz with
+// that constant, and from a reached alpha the step (d(alpha) - 0.1 d(0)) /
+// max_a |p_a| keeps it above 0.1 d(0); advances stop within 0.1 % of that
+// floor, after 32 advances, or at FILTER_SPAN), and the separation along
+// the pair's unit vector u, which shrinks at most by alpha max_a p_a.u
+// (alpha <= 0.9 sep / max_a p_a.u, none when that is <= 0: motion across u
+// does not count).  Pairs farther than FILTER_SPAN max |p_a| / 0.9 cannot
+// bind.
 template <typename R>
 __device__ double prim_pair_bound(const EnvDesc& E, const EnvPose* P, int j, const R* d, double span) {
   int vid[3];
@@ -1577,11 +1587,39 @@ __device__ double prim_pair_bound(const EnvDesc& E, const EnvPose* P, int j, con
   double r[MAX_IND];
   for (int m = 0; m < MAX_IND; ++m) r[m] = span * pm / 0.9;
   double a = INFINITY;
-  visit_pairs(E, P, j, xw, r, [&](int, const PairTerm& pt) {
+  visit_pairs(E, P, j, xw, r, [&](int m, const PairTerm& pt) {
+    const double floor_ = 0.1 * pt.d;
+    if (!(pt.d > 0.0)) {
+      a = 0.0;
+      return;
+    }
+    // the primitive in the mesh's frame: vertices and directions
+    const DevIndenter& I = P->ind[m];
+    double xl[3][3], pl[3][3];
+    for (int k = 0; k < nv; ++k)
+      for (int i = 0; i < 3; ++i) {
+        xl[k][i] = I.R[0 * 3 + i] * (xw[k][0] - I.c[0]) + I.R[1 * 3 + i] * (xw[k][1] - I.c[1]) +
+                   I.R[2 * 3 + i] * (xw[k][2] - I.c[2]);
+        pl[k][i] = I.R[0 * 3 + i] * pv[k][0] + I.R[1 * 3 + i] * pv[k][1] + I.R[2 * 3 + i] * pv[k][2];
+      }
+    double al = 0.0, dc = pt.d;
+    for (int it = 0; it < 32; ++it) {
+      al += (dc - floor_) / pm;
+      if (al >= span) {
+        al = span;
+        break;
+      }
+      double y[3][3], lam[3], df[3], sp, tp;
+      for (int k = 0; k < nv; ++k)
+        for (int i = 0; i < 3; ++i) y[k][i] = xl[k][i] + al * pl[k][i];
+      const double d2 = pt.w1 ? seg_seg(pt.w0, pt.w1, y[0], y[1], sp, tp, df) : pt_tri_lam(pt.w0, y[0], y[1], y[2], lam, df);
+      dc = sqrt(d2);
+      if (dc - floor_ <= 1e-3 * floor_) break;
+    }
     double pu = -INFINITY;
     for (int k = 0; k < nv; ++k) pu = fmax(pu, pv[k][0] * pt.u[0] + pv[k][1] * pt.u[1] + pv[k][2] * pt.u[2]);
     const double b = pt.sep > 0.0 ? (pu > 0.0 ? 0.9 * pt.sep / pu : INFINITY) : 0.0;
-    a = fmin(a, fmax(0.9 * pt.d / pm, b));
+    a = fmin(a, fmax(al, b));
   });
   return a;
 }

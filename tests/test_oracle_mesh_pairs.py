@@ -264,3 +264,34 @@ def test_step_bound_lets_tangential_motion_through():
         d0 = mp.vf_pairs(Yw, Xa, tris, np.inf)[2].min()
         d1 = mp.ee_pairs(Yw, medges, Xa, edges, np.inf)[2].min()
         assert min(d0, d1) > 0
+
+
+def test_step_bound_advances_past_a_tilt():
+    """A pad triangle tilting about the point under a mesh vertex: its
+    vertices rise and sink by far more than the gap, so both the
+    displacement and the separation bounds stop the step at a small
+    fraction, while conservative advancement along the actual distance goes
+    on until the tilted triangle nears the vertex; every pair stays apart
+    along the step."""
+    X, tris, edges, elen = _flat_pad(2, 2 * MM)
+    t = 3
+    c = X[tris[t]].mean(axis=0)
+    V = np.array([[0, 0, 0], [1, 0, 3], [-1, 1, 3], [-1, -1, 3.]]) * MM
+    F = np.array([[0, 2, 1], [0, 3, 2], [0, 1, 3], [1, 2, 3]])
+    h = 0.01 * MM
+    ind = _Mesh(V, F, c + [0, 0, h])
+    p = np.zeros_like(X)
+    w = np.array([0.0, 20 * h / MM, 0.0])                 # rotation about y through the centroid
+    p = np.cross(w[None], X - c[None])
+    a = mp.step_bound(ind, X, p, tris, edges)
+    Yw, _ = mp._world(ind)
+    iv, it, d, lam, u = mp.vf_pairs(Yw, X, tris, np.inf)
+    k = np.nonzero(it == t)[0][0]
+    pu = (p[tris[t]] @ u[k]).max()
+    sep_only = 0.9 * d[k] / pu
+    assert a > 2 * sep_only, (a, sep_only)
+    _, medges = mp.mesh_tables(*ind.mesh)
+    for f in np.linspace(0, 1, 41):
+        Xa = X + f * a * p
+        assert mp.vf_pairs(Yw, Xa, tris, np.inf)[2].min() > 0
+        assert mp.ee_pairs(Yw, medges, Xa, edges, np.inf)[2].min() > 0
