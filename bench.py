@@ -281,6 +281,7 @@ def run_steps(args):
     ctx.set_launch(cg_block=args.cg_block, elem_block=args.elem_block, spmv_block=args.spmv_block,
                    cg_per_replay=args.cg_per_replay, use_graphs=args.graphs)
     ctx.set_streams(args.streams)
+    ctx.set_schedule(args.schedule == "staged", args.ls_evals)
     tuned = None
     if args.autotune:
         # tuned on the first warm-up step's poses from the rest state
@@ -353,7 +354,7 @@ def run_steps(args):
                    "tets": int(sum(e.pad.tets.shape[0] for e in envs)), "mode": mode,
                    "newton_max_mean": float(np.mean(newton)), "cg_iters_mean": float(np.mean(cg)),
                    "precision": args.precision, "graphs": bool(args.graphs and args.no_timing),
-                   "streams": streams, "autotuned": tuned,
+                   "streams": streams, "schedule": args.schedule, "autotuned": tuned,
                    "timed_one_stream_steps_per_s": round(n_env * args.steps / single[0], 2) if single else None},
         "roofline": roof,
     }
@@ -598,6 +599,9 @@ def main():
     ap.add_argument("--cg-eta-max", type=float, default=0.2)
     ap.add_argument("--cg-forcing", type=int, default=2)
     ap.add_argument("--streams", type=int, default=2, help="streams a batch step is split over (1..4)")
+    ap.add_argument("--schedule", default="staged", choices=("staged", "lockstep"),
+                    help="pads through their Newton iterations at their own pace, or in lockstep")
+    ap.add_argument("--ls-evals", type=int, default=0, help="trial energies per staged round (0: default)")
     ap.add_argument("--cg-conv-tol", type=float, default=0.0,
                     help="CG tolerance of a direction that decides convergence (0 = the solve tolerance)")
     ap.add_argument("--hess-proj", type=int, default=4)

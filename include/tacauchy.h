@@ -377,6 +377,27 @@ tc_status tc_set_launch(tc_context* ctx, int32_t cg_block, int32_t elem_block, i
 #define TC_MAX_STREAMS 4
 tc_status tc_set_streams(tc_context* ctx, int32_t n_streams);
 
+/* How a batch step orders its pads' Newton iterations (Sec. III-B: each pad
+ * runs its own Newton solve of the incremental potential, with CG for the
+ * linear systems and a backtracking line search).
+ *   staged = 1 (default): every pad moves through the stages of its Newton
+ *     iterations (Hessians and assembly, CG, direction and step bound, line
+ *     search, update) at its own pace.  The step runs in rounds: pads whose
+ *     CG has ended are taken through direction, step bound, line_search_evals
+ *     trial energies and, when the search ends, the update and the next
+ *     iteration's assembly, while every pad in CG runs a chunk of CG
+ *     iterations (cg_per_replay of tc_set_launch); one host readback per
+ *     round.  Pads that converge in few iterations no longer wait for the
+ *     slowest pad at every iteration, and the launches of the slowest pads'
+ *     iterations carry the other pads' work.
+ *   staged = 0: lockstep; one Newton iteration of every running pad at a
+ *     time, each stage waiting for its slowest pad.
+ * line_search_evals: 1..8 (0 keeps the current value; default 2).  Every
+ * pad's result is bitwise the same under both schedules: each runs the same
+ * kernels on its own data in the same order.  Takes effect from the next
+ * batch; the serving loop and single-pad inspection calls keep lockstep. */
+tc_status tc_set_schedule(tc_context* ctx, int32_t staged, int32_t line_search_evals);
+
 /* ------------------------------------------------------------------- pads */
 /* Copies the mesh and materials into HBM and runs the setup kernels: Eq. 1
  * Lame parameters, Dm^-1 and V_e, lumped mass, rest contact areas; builds the

@@ -244,6 +244,12 @@ class Context:
         """Split batch steps over n streams (1..4), one host thread each."""
         check(self.lib.tc_set_streams(self.h, int(n)))
 
+    def set_schedule(self, staged: bool = True, line_search_evals: int = 0):
+        """Batch schedule: staged (each pad through its Newton iterations at
+        its own pace, in rounds of launches) or lockstep; trial energies per
+        round (0 keeps the current value)."""
+        check(self.lib.tc_set_schedule(self.h, int(bool(staged)), int(line_search_evals)))
+
     def autotune(self, pads: Sequence["Pad"], indenters: Sequence[Sequence]):
         n = len(pads)
         ph = (C.c_void_p * n)(*[p.h for p in pads])

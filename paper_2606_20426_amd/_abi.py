@@ -112,6 +112,7 @@ PROTOS = {
     "tc_autotune": (S, [P, S, C.POINTER(P), C.POINTER(S), C.POINTER(TcIndenter), C.POINTER(S)]),
     "tc_set_launch": (S, [P, S, S, S, S, S]),
     "tc_set_streams": (S, [P, S]),
+    "tc_set_schedule": (S, [P, S, S]),
     "tc_rigid_mesh_create": (S, [P, S, C.POINTER(C.c_double), S, C.POINTER(S), C.POINTER(S)]),
     "tc_rigid_mesh_destroy": (S, [P, S]),
     "tc_validate_rigid_mesh": (S, [S, C.POINTER(C.c_double), S, C.POINTER(S)]),

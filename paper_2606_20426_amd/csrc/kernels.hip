@@ -42,6 +42,21 @@ __device__ __forceinline__ bool initialising(const EnvState* S) {
   return S->phase == PH_INIT && S->status == TC_OK;
 }
 
+__device__ __forceinline__ bool at_stage(const EnvState* S, int stage) {
+  return running(S) && S->stage == stage;
+}
+
+// the CG of this Newton iteration has ended: direction, filter and step
+// bound pending
+__device__ __forceinline__ bool dir_ready(const EnvState* S) {
+  return running(S) && S->stage == ST_CG && S->cg_done;
+}
+
+// CG iterations pending (the first product moves the pad from ST_ASM to ST_CG)
+__device__ __forceinline__ bool cg_running(const EnvState* S) {
+  return running(S) && (S->stage == ST_ASM || S->stage == ST_CG) && !S->cg_done;
+}
+
 struct OpSum { __device__ double operator()(double a, double b) const { return a + b; } };
 struct OpMax { __device__ double operator()(double a, double b) const { return fmax(a, b); } };
 struct OpMin { __device__ double operator()(double a, double b) const { return fmin(a, b); } };
@@ -1166,7 +1181,7 @@ __global__ void __launch_bounds__(256) k_element(const Tile* tiles, int ntiles, 
   const int t = xcd_tile(ntiles);
   if (t < 0) return;
   const EnvDesc& E = envs[tiles[t].env];
-  if (!running(E.st)) return;
+  if (!at_stage(E.st, ST_ASM)) return;
   const int e = tiles[t].tile * blockDim.x + threadIdx.x;
   if (e >= E.T) return;
   const int4 tv = reinterpret_cast<const int4*>(E.tets)[e];
@@ -1357,7 +1372,7 @@ __global__ void k_pairs(const Tile* tiles, int ntiles, const EnvDesc* envs, int 
   const int j = tl.tile * blockDim.x + threadIdx.x;
   if (mode >= 2) {
     // block reductions: every thread of the block takes part
-    if (mode == 2 ? (!running(S) || S->ls_done) : mode == 4 ? !initialising(S) : !running(S)) return;
+    if (mode == 2 ? (!at_stage(S, ST_LS) || S->ls_done) : mode == 4 ? !initialising(S) : !dir_ready(S)) return;
     const bool in = j < E.S + E.Se;
     if (mode == 3) {
       double a = INFINITY;
@@ -1377,7 +1392,7 @@ __global__ void k_pairs(const Tile* tiles, int ntiles, const EnvDesc* envs, int 
     if (threadIdx.x == 0) E.part_e[E.n_te + E.n_vt + E.n_ct + tl.tile] = e;
     return;
   }
-  if (mode == 0 ? !running(S) : !extract_ok(S)) return;
+  if (mode == 0 ? !at_stage(S, ST_ASM) : !extract_ok(S)) return;
   if (j >= E.S + E.Se) return;
   const double* x = (mode == 1 && S->mode == 1) ? E.x : E.xn;
   int vid[3];
@@ -1647,7 +1662,7 @@ __global__ void k_barrier(const Tile* tiles, int ntiles, const EnvDesc* envs) {
   if (t < 0) return;
   const EnvDesc& E = envs[tiles[t].env];
   const EnvPose* P = E.pose;
-  if (!running(E.st)) return;
+  if (!at_stage(E.st, ST_ASM)) return;
   const int k = tiles[t].tile * blockDim.x + threadIdx.x;
   if (k >= E.C) return;
   const int vi = E.cand[k];
@@ -1822,7 +1837,7 @@ __global__ void k_asm_diag(const Tile* tiles, int ntiles, const EnvDesc* envs) {
   if (t < 0) return;
   const Tile tl = tiles[t];
   const EnvDesc& E = envs[tl.env];
-  if (!running(E.st)) return;
+  if (!at_stage(E.st, ST_ASM)) return;
   const int lane = threadIdx.x & (ASM_LPR - 1);
   const int groups = blockDim.x / ASM_LPR;
   const int row0 = tl.tile * blockDim.x + threadIdx.x / ASM_LPR;
@@ -1863,7 +1878,7 @@ __global__ void k_asm_off(const Tile* tiles, int ntiles, const EnvDesc* envs) {
   const int t = xcd_tile(ntiles);
   if (t < 0) return;
   const EnvDesc& E = envs[tiles[t].env];
-  if (!running(E.st)) return;
+  if (!at_stage(E.st, ST_ASM)) return;
   const int k = tiles[t].tile * blockDim.x + threadIdx.x;
   if (k >= E.V_E) return;
   const R* Ko = (const R*)E.Ke + (size_t)KC * 4 * E.T;
@@ -1905,7 +1920,7 @@ __global__ void k_asm_off(const Tile* tiles, int ntiles, const EnvDesc* envs) {
 __global__ void k_env_newton_begin(const EnvDesc* envs, int n) {
   if (blockIdx.x >= n || threadIdx.x != 0) return;
   EnvState* S = envs[blockIdx.x].st;
-  if (!running(S)) return;
+  if (!at_stage(S, ST_START)) return;
   if (S->newton_iters == 0) {
     S->rz0_prev = -1.0;
     S->eta_prev = 0.0;
@@ -1926,6 +1941,7 @@ __global__ void k_env_newton_begin(const EnvDesc* envs, int n) {
   S->ls_halv = 0;
   S->ls_expanding = 0;
   S->ls_expand_n = 0;
+  S->stage = ST_ASM;
 }
 
 // Common head of the CG product for one tile: reduce this pad's r.z
@@ -1938,7 +1954,7 @@ __device__ __forceinline__ bool cg_go(const EnvDesc& E) {
   // tile 0 of the pad may set cg_done while this block reads it: one thread
   // reads, the block follows, so that all its waves take the same path
   __shared__ int s_go;
-  if (threadIdx.x == 0) s_go = running(S) && !S->cg_done;
+  if (threadIdx.x == 0) s_go = cg_running(S);
   __syncthreads();
   const bool go = s_go != 0;
   __syncthreads();
@@ -1987,6 +2003,9 @@ __device__ __forceinline__ bool cg_decide(const Tile tl, const EnvDesc& E, int p
   }
   const bool done = it >= E.max_cg || !(rz > tol2 * rz0) || S->breakdown;
   if (tl.tile == 0 && threadIdx.x == 0) {
+    // the other blocks of this launch read the stage: ST_ASM and ST_CG
+    // both let them run
+    S->stage = ST_CG;
     if (it == 0) S->cg_tol2 = tol2;
     if (done) {
       S->cg_done = 1;
@@ -2165,7 +2184,7 @@ template <typename R>
 __device__ __forceinline__ void cg_update_tile(const Tile tl, const EnvDesc* envs, int parity, double* sh) {
   const EnvDesc& E = envs[tl.env];
   EnvState* S = E.st;
-  if (!running(S) || S->cg_done) return;
+  if (!cg_running(S)) return;
   cg_update_body<R>(tl, E, parity, cg_alpha(tl, E, parity, sh), sh);
 }
 
@@ -2214,7 +2233,7 @@ __global__ void k_newton_dir(const Tile* tiles, int ntiles, const EnvDesc* envs)
   if (t < 0) return;
   const Tile tl = tiles[t];
   const EnvDesc& E = envs[tl.env];
-  if (!running(E.st)) return;
+  if (!dir_ready(E.st)) return;
   const int i = tl.tile * blockDim.x + threadIdx.x;
   double dm = 0.0, gd = 0.0;
   if (i < E.V) {
@@ -2254,7 +2273,7 @@ __global__ void k_filter(const Tile* tiles, int ntiles, const EnvDesc* envs) {
   const Tile tl = tiles[t];
   const EnvDesc& E = envs[tl.env];
   const EnvPose* P = E.pose;
-  if (!running(E.st)) return;
+  if (!dir_ready(E.st)) return;
   const int k = tl.tile * blockDim.x + threadIdx.x;
   double amax = INFINITY;
   if (k < E.C) {
@@ -2330,7 +2349,7 @@ __global__ void k_env_dir(const EnvDesc* envs, int n) {
   if (blockIdx.x >= n) return;
   const EnvDesc& E = envs[blockIdx.x];
   EnvState* S = E.st;
-  if (!running(S)) return;
+  if (!dir_ready(S)) return;
   double dm = -INFINITY, gd = 0.0, am = INFINITY;
   for (int k = threadIdx.x; k < E.n_vt; k += blockDim.x) {
     dm = fmax(dm, E.part_dir[2 * k]);
@@ -2371,6 +2390,7 @@ __global__ void k_env_dir(const EnvDesc* envs, int n) {
     S->ls_done = S->dir_conv;
     S->apply = S->dir_conv;
     S->cg_total += S->cg_iters;
+    S->stage = S->ls_done ? ST_UPD : ST_LS;
   }
 }
 
@@ -2389,7 +2409,7 @@ __global__ void k_energy(const Tile* tiles, int ntiles, const EnvDesc* envs, int
   const EnvDesc& E = envs[tl.env];
   const EnvState* S = E.st;
   const EnvPose* P = E.pose;
-  if (mode == 0 ? !initialising(S) : (!running(S) || S->ls_done)) return;
+  if (mode == 0 ? !initialising(S) : (!at_stage(S, ST_LS) || S->ls_done)) return;
   const double al = mode == 0 ? 0.0 : S->ls_alpha;
   const R* d = (const R*)E.d;
   double acc = 0.0;
@@ -2467,7 +2487,7 @@ __global__ void k_env_ls(const EnvDesc* envs, int n, int mode) {
   if (blockIdx.x >= n) return;
   const EnvDesc& E = envs[blockIdx.x];
   EnvState* S = E.st;
-  if (mode == 0 ? !initialising(S) : (!running(S) || S->ls_done)) return;
+  if (mode == 0 ? !initialising(S) : (!at_stage(S, ST_LS) || S->ls_done)) return;
   double el = 0, in = 0, ba = 0;
   for (int k = threadIdx.x; k < E.n_te; k += blockDim.x) el += E.part_e[k];
   for (int k = threadIdx.x; k < E.n_vt; k += blockDim.x) in += E.part_e[E.n_te + k];
@@ -2506,6 +2526,7 @@ __global__ void k_env_ls(const EnvDesc* envs, int n, int mode) {
     S->E_next = S->ls_best_E;
     S->ls_done = 1;
     S->apply = 1;
+    S->stage = ST_UPD;
     return;
   }
   if (armijo) {
@@ -2519,6 +2540,7 @@ __global__ void k_env_ls(const EnvDesc* envs, int n, int mode) {
     S->ls_done = 1;
     S->apply = 1;
     S->E_next = Etot;
+    S->stage = ST_UPD;
   } else {
     S->ls_alpha = 0.5 * a;
     S->ls_halv += 1;
@@ -2537,7 +2559,7 @@ __global__ void k_update(const Tile* tiles, int ntiles, const EnvDesc* envs) {
   const Tile tl = tiles[t];
   const EnvDesc& E = envs[tl.env];
   EnvState* S = E.st;
-  if (!running(S)) return;
+  if (!at_stage(S, ST_UPD)) return;
   const int i = tl.tile * blockDim.x + threadIdx.x;
   if (S->apply && i < E.V) {
     const R* d = (const R*)E.d;
@@ -2546,13 +2568,13 @@ __global__ void k_update(const Tile* tiles, int ntiles, const EnvDesc* envs) {
   }
 }
 
-// One block per pad, after k_update (which must see the pad still running in
-// every block): Newton counters and the end-of-solve transition.
+// One block per pad, after k_update (which must see the pad at its update
+// stage in every block): Newton counters and the end-of-solve transition.
 __global__ void k_env_update(const EnvDesc* envs, int n) {
   if (blockIdx.x >= n || threadIdx.x != 0) return;
   const EnvDesc& E = envs[blockIdx.x];
   EnvState* S = E.st;
-  if (!running(S)) return;
+  if (!at_stage(S, ST_UPD)) return;
   S->newton_iters += 1;
   S->ls_total += S->ls_halv;
   const bool adaptive = (E.hess_proj & 3) == 2 || ((E.hess_proj >> 2) & 3) == 3;
@@ -2564,6 +2586,8 @@ __global__ void k_env_update(const EnvDesc* envs, int n) {
   } else if (S->newton_iters >= E.max_newton) {
     S->status = TC_E_NOT_CONVERGED;
     S->phase = PH_FINISH;
+  } else {
+    S->stage = ST_START;
   }
 }
 

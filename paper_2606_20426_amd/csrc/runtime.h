@@ -110,6 +110,8 @@ struct tc_context {
   int el_block = 128;
   int cg_per_replay = 16;
   bool use_graphs = false;
+  bool staged = true;                // batch schedule: staged (else lockstep)
+  int ls_per_round = 2;              // trial energies per round of the staged schedule
   // timing
   bool timing = false;
   int timing_stride = 1;             // time every k-th launch of each kernel
@@ -280,11 +282,24 @@ struct Runner {
     int c[BatchPlan::NCLS];
     bool full;
   };
-  View view(bool (*pred)(const EnvState&));
+  // mask: bit c set for each kernel class c to list (the others stay
+  // empty); copy false: the lists are copied to the device by the next
+  // flush_views, which must come before the first launch that reads them
+  View view(bool (*pred)(const EnvState&), unsigned mask = ~0u, bool copy = true);
+  void flush_views();
+  int unflushed = -1;               // ring start of lists built but not yet copied
   void launch_v(KernelId k, const View& v, int cls, int parity = 0, int mode = 0);
   tc_status cg_chunk(int M, const View& v);
   void launch_tiles(KernelId k, const Tile* tiles, int ntiles, int block, int parity, int mode = 0);
+  // lockstep schedule: one Newton iteration of every running pad (pads
+  // being initialised first)
   tc_status tick(bool init);
+  // staged schedule: the whole step, each pad through the stages of its
+  // Newton iterations at its own pace, in rounds of launches
+  tc_status staged(int M, int K);
+  tc_status round(int M, int K);
+  void init_launches();
+  tc_status finish();
 
   static bool is_run(const EnvState& s) { return s.phase == PH_RUN && s.status == TC_OK; }
   static bool cg_pending(const EnvState& s) { return is_run(s) && !s.cg_done; }
@@ -293,6 +308,13 @@ struct Runner {
   static bool not_done(const EnvState& s) { return s.phase != PH_DONE && s.phase != PH_IDLE; }
   static bool is_init(const EnvState& s) { return s.phase == PH_INIT && s.status == TC_OK; }
   static bool init_or_run(const EnvState& s) { return is_init(s) || is_run(s); }
+  // stages of running pads as the last readback saw them
+  static bool in_cg(const EnvState& s) {
+    return is_run(s) && (s.stage == ST_ASM || s.stage == ST_CG) && !s.cg_done;
+  }
+  static bool dir_pending(const EnvState& s) { return is_run(s) && s.stage == ST_CG && s.cg_done; }
+  static bool turning(const EnvState& s) { return dir_pending(s) || (is_run(s) && s.stage == ST_LS); }
+  static bool may_start(const EnvState& s) { return is_run(s) && (s.stage == ST_START || turning(s)); }
 };
 
 }  // namespace tc

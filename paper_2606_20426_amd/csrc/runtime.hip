@@ -624,7 +624,7 @@ void Runner::launch_tiles(KernelId k, const Tile* tiles, int ntiles, int block, 
   (void)timed_launch(ctx, slice(), k, P->fp64, a);
 }
 
-Runner::View Runner::view(bool (*pred)(const EnvState&)) {
+Runner::View Runner::view(bool (*pred)(const EnvState&), unsigned mask, bool copy) {
   View v{};
   int nm = 0;
   for (int i = 0; i < n; ++i) nm += pred(state(i));
@@ -638,8 +638,12 @@ Runner::View Runner::view(bool (*pred)(const EnvState&)) {
   }
   // compacted lists go to the next free part of the ring; the ring is only
   // rewritten after a host sync, when every earlier copy and launch is done
+  const int base = P->ctiles_off;
   for (int c = 0; c < BatchPlan::NCLS; ++c) {
     const int start = P->ctiles_off;
+    v.t[c] = P->d_ctiles + start;
+    v.c[c] = 0;
+    if (!(mask >> c & 1u)) continue;
     int k = start;
     for (int i = 0; i < n; ++i) {
       if (!pred(state(i))) continue;
@@ -651,16 +655,21 @@ Runner::View Runner::view(bool (*pred)(const EnvState&)) {
       if (k + cnt > P->ctiles_cap) break;   // ring full: cannot happen (4x capacity)
       for (int t = 0; t < cnt; ++t) P->h_ctiles[k++] = Tile{i, t};
     }
-    v.t[c] = P->d_ctiles + start;
     v.c[c] = k - start;
     P->ctiles_off = k;
   }
-  const int base = (int)(v.t[0] - P->d_ctiles);
-  const int len = P->ctiles_off - base;
-  if (len > 0)
-    (void)hipMemcpyAsync(P->d_ctiles + base, P->h_ctiles + base, sizeof(Tile) * len, hipMemcpyHostToDevice,
-                         strm());
+  if (unflushed < 0) unflushed = base;
+  if (copy) flush_views();
   return v;
+}
+
+void Runner::flush_views() {
+  if (unflushed < 0) return;
+  const int len = P->ctiles_off - unflushed;
+  if (len > 0)
+    (void)hipMemcpyAsync(P->d_ctiles + unflushed, P->h_ctiles + unflushed, sizeof(Tile) * len,
+                         hipMemcpyHostToDevice, strm());
+  unflushed = -1;
 }
 
 void Runner::launch_v(KernelId k, const View& v, int cls, int parity, int mode) {
@@ -673,6 +682,7 @@ tc_status Runner::readback() {
   TC_HIP(hipMemcpyAsync(pool->h_state, pool->d_state, sizeof(EnvState) * span, hipMemcpyDeviceToHost, strm()));
   TC_HIP(hipStreamSynchronize(strm()));
   P->ctiles_off = 0;
+  unflushed = -1;
   if (ctx->timing) resolve_timing(ctx, slice(), strm(), false);
   return TC_OK;
 }
@@ -713,31 +723,47 @@ tc_status Runner::cg_chunk(int M, const View& v) {
   return TC_OK;
 }
 
-// One Newton iteration for every pad in PH_RUN (pads in PH_INIT are
+// Predict, feasible start and E(x0) of the pads being initialised.
+void Runner::init_launches() {
+  const View vi = view(is_init);
+  launch_v(KernelId::predict, vi, BatchPlan::VERT);
+  launch_v(KernelId::project, vi, BatchPlan::CAND, 0, 0);
+  if (any_pairs(is_init)) {
+    // pads with vertex-face / edge-edge pairs: vertex rounds alternate
+    // with the surface primitives' pushes, then both checks
+    for (int r = 0; r < 8; ++r) {
+      launch_v(KernelId::project, vi, BatchPlan::CAND, 0, 1);
+      launch_v(KernelId::pair_push, vi, BatchPlan::PAIR, 0, 0);
+      launch_v(KernelId::pair_apply, vi, BatchPlan::CAND);
+    }
+    launch_v(KernelId::project, vi, BatchPlan::CAND, 0, 2);
+    launch_v(KernelId::pair_push, vi, BatchPlan::PAIR, 0, 1);
+  }
+  launch_v(KernelId::energy, vi, BatchPlan::ENERGY, 0, 0);
+  if (any_pairs(is_init)) launch_v(KernelId::pairs, vi, BatchPlan::PAIR, 0, 4);
+  launch(KernelId::env_ls, BatchPlan::NCLS, 0, 0);
+}
+
+// Extraction and commit of the pads whose Newton solve has ended.
+tc_status Runner::finish() {
+  if (!any(is_finish)) return TC_OK;
+  const View vf = view(is_finish);
+  launch_v(KernelId::sigma, vf, BatchPlan::TET);
+  launch_v(KernelId::traction, vf, BatchPlan::SURF);
+  if (any_pairs(is_finish)) launch_v(KernelId::pairs, vf, BatchPlan::PAIR, 0, 1);
+  launch_v(KernelId::contact, vf, BatchPlan::CAND);
+  launch_v(KernelId::commit, vf, BatchPlan::VERT);
+  launch(KernelId::env_extract, BatchPlan::NCLS);
+  return readback();
+}
+
+// Lockstep schedule: one Newton iteration for every pad in PH_RUN (pads in PH_INIT are
 // initialised first and join it; pads that end up in PH_FINISH get their
 // extraction).  Launches cover only the tiles of the pads concerned.
 tc_status Runner::tick(bool init) {
   tc_status st;
   static const bool debug = std::getenv("TC_DEBUG") != nullptr;
-  if (init) {
-    const View vi = view(is_init);
-    launch_v(KernelId::predict, vi, BatchPlan::VERT);
-    launch_v(KernelId::project, vi, BatchPlan::CAND, 0, 0);
-    if (any_pairs(is_init)) {
-      // pads with vertex-face / edge-edge pairs: vertex rounds alternate
-      // with the surface primitives' pushes, then both checks
-      for (int r = 0; r < 8; ++r) {
-        launch_v(KernelId::project, vi, BatchPlan::CAND, 0, 1);
-        launch_v(KernelId::pair_push, vi, BatchPlan::PAIR, 0, 0);
-        launch_v(KernelId::pair_apply, vi, BatchPlan::CAND);
-      }
-      launch_v(KernelId::project, vi, BatchPlan::CAND, 0, 2);
-      launch_v(KernelId::pair_push, vi, BatchPlan::PAIR, 0, 1);
-    }
-    launch_v(KernelId::energy, vi, BatchPlan::ENERGY, 0, 0);
-    if (any_pairs(is_init)) launch_v(KernelId::pairs, vi, BatchPlan::PAIR, 0, 4);
-    launch(KernelId::env_ls, BatchPlan::NCLS, 0, 0);
-  }
+  if (init) init_launches();
   if (any(init ? init_or_run : is_run)) {
     const View v = view(init ? init_or_run : is_run);
     launch(KernelId::newton_begin, BatchPlan::NCLS);
@@ -808,17 +834,89 @@ tc_status Runner::tick(bool init) {
   } else if (init) {
     if ((st = readback())) return st;
   }
-  if (any(is_finish)) {
-    const View vf = view(is_finish);
-    launch_v(KernelId::sigma, vf, BatchPlan::TET);
-    launch_v(KernelId::traction, vf, BatchPlan::SURF);
-    if (any_pairs(is_finish)) launch_v(KernelId::pairs, vf, BatchPlan::PAIR, 0, 1);
-    launch_v(KernelId::contact, vf, BatchPlan::CAND);
-    launch_v(KernelId::commit, vf, BatchPlan::VERT);
-    launch(KernelId::env_extract, BatchPlan::NCLS);
-    if ((st = readback())) return st;
+  return finish();
+}
+
+// One round of the staged schedule, from the stages the last readback saw.
+// Pads whose CG ended get their direction, step bound and K trial energies
+// of the line search; pads whose search ends within the round are updated,
+// and those that go on start their next Newton iteration (Hessians,
+// assembly); then every pad in CG, those just assembled included, runs M CG
+// iterations (M even: every pad enters its CG at parity 0).  A launch also
+// covers pads that may reach the kernel's stage only within the round; the
+// kernels pass over pads at another stage.  One readback ends the round.
+tc_status Runner::round(int M, int K) {
+  static const bool debug = std::getenv("TC_DEBUG") != nullptr;
+  using B = BatchPlan;
+  const unsigned mD = 1u << B::VERT | 1u << B::CAND | 1u << B::PAIR;
+  const unsigned mL = 1u << B::ENERGY | 1u << B::PAIR | 1u << B::VERT;
+  const unsigned mA = 1u << B::TET | 1u << B::PAIR | 1u << B::CAND | 1u << B::VERT | 1u << B::ASM;
+  const unsigned mC = 1u << B::SPMV | 1u << B::VERT;
+  const bool anyD = any(dir_pending), anyL = any(turning), anyA = any(may_start);
+  std::vector<char> was_dir;
+  if (debug)
+    for (int i = 0; i < n; ++i) was_dir.push_back(dir_pending(state(i)));
+  View vD{}, vL{}, vA{};
+  if (anyD) vD = view(dir_pending, mD, false);
+  if (anyL) vL = view(turning, mL, false);
+  if (anyA) vA = view(may_start, mA, false);
+  const View vC = view(is_run, mC, false);
+  flush_views();
+  if (anyD) {
+    launch_v(KernelId::newton_dir, vD, B::VERT);
+    launch_v(KernelId::filter, vD, B::CAND);
+    if (any_pairs(dir_pending)) launch_v(KernelId::pairs, vD, B::PAIR, 0, 3);
+    launch(KernelId::env_dir, B::NCLS);
   }
+  if (anyL) {
+    const bool pairs = any_pairs(turning);
+    for (int k = 0; k < K; ++k) {
+      launch_v(KernelId::energy, vL, B::ENERGY, 0, 1);
+      if (pairs) launch_v(KernelId::pairs, vL, B::PAIR, 0, 2);
+      launch(KernelId::env_ls, B::NCLS, 0, 1);
+    }
+    launch_v(KernelId::update, vL, B::VERT);
+    launch(KernelId::env_update, B::NCLS);
+  }
+  if (anyA) {
+    launch(KernelId::newton_begin, B::NCLS);
+    launch_v(KernelId::element, vA, B::TET);
+    if (any_pairs(may_start)) launch_v(KernelId::pairs, vA, B::PAIR, 0, 0);
+    launch_v(KernelId::barrier, vA, B::CAND);
+    launch_v(KernelId::asm_diag, vA, B::VERT);
+    launch_v(KernelId::asm_off, vA, B::ASM);
+  }
+  tc_status st;
+  // no CG chunk when no pad can be in CG (all others still searching)
+  if ((anyA || any(in_cg)) && (st = cg_chunk(M, vC))) return st;
+  if ((st = readback())) return st;
+  if (debug)
+    for (int i = 0; i < n; ++i) {
+      if (!was_dir[i]) continue;
+      const EnvState& S = state(i);
+      std::fprintf(stderr, "[tc] pad %d newton %d cg %d rz0 %.3e |d| %.3e g.d %.3e amax %.3e E %.12e conv %d\n", i,
+                   S.newton_iters, S.cg_iters, S.rz0, S.final_step_inf, S.gTd, S.alpha_max, S.E_cur, S.dir_conv);
+    }
   return TC_OK;
+}
+
+tc_status Runner::staged(int M, int K) {
+  tc_status st;
+  init_launches();
+  if ((st = readback())) return st;
+  // a Newton iteration takes at most this many rounds: its CG chunks, its
+  // line search's trial energies K per round, one round to start
+  int limit = 2;
+  for (int i = 0; i < n; ++i) {
+    const tc_params& q = P->pads[i]->params;
+    const int per_it = (q.max_cg + M) / M + (q.max_halvings + q.ls_expand + 1 + K - 1) / K + 1;
+    limit = std::max(limit, (q.max_newton + 1) * per_it + 2);
+  }
+  for (int r = 0; any(is_run); ++r) {
+    if (r >= limit) return set_error(TC_E_HIP, "staged Newton driver did not terminate");
+    if ((st = round(M, K))) return st;
+  }
+  return finish();
 }
 
 // Algorithmic HBM bytes of one launch's work on one pad (each array element
@@ -961,6 +1059,8 @@ tc_status run_batch(tc_context* ctx, int n, tc_pad* const* pads, const int32_t* 
     tc_status st = TC_OK;
     if (mode == 1) {
       st = run.tick(false);
+    } else if (ctx->staged) {
+      st = run.staged(std::max(2, ctx->cg_per_replay & ~1), ctx->ls_per_round);
     } else {
       bool init = true;
       for (int guard = 0;; ++guard) {
@@ -1403,6 +1503,17 @@ tc_status tc_set_streams(tc_context* ctx, int32_t n_streams) {
   if (n_streams < 1 || n_streams > TC_MAX_STREAMS) return set_error(TC_E_INVALID_ARG, "n_streams must be 1..4");
   std::lock_guard<std::recursive_mutex> lk(ctx->mu);
   ctx->n_lanes = n_streams;
+  return TC_OK;
+}
+
+tc_status tc_set_schedule(tc_context* ctx, int32_t staged, int32_t line_search_evals) {
+  if (!ctx) return set_error(TC_E_INVALID_ARG, "ctx is null");
+  if (staged < 0 || staged > 1) return set_error(TC_E_INVALID_ARG, "staged must be 0 or 1");
+  if (line_search_evals < 0 || line_search_evals > 8)
+    return set_error(TC_E_INVALID_ARG, "line_search_evals must be 0..8");
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  ctx->staged = staged != 0;
+  if (line_search_evals) ctx->ls_per_round = line_search_evals;
   return TC_OK;
 }
 

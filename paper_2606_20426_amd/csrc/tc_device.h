@@ -112,10 +112,22 @@ enum Phase : int32_t {
   PH_IDLE = 4     // slot not in use
 };
 
+// Stage of a running pad inside its Newton iteration.  Every kernel of an
+// iteration acts only on pads at its own stage, so one launch may carry
+// pads at different stages (pads of a batch need not iterate in step).
+enum Stage : int32_t {
+  ST_START = 0,   // next: reset of the iteration's counters
+  ST_ASM = 1,     // element and barrier Hessians, assembly
+  ST_CG = 2,      // CG running; with cg_done the direction is ready
+  ST_LS = 3,      // line search
+  ST_UPD = 4      // step accepted (or converged): update pending
+};
+
 // Mutable per-pad state of one step, in device memory (one slot of a pool).
 // The runtime initialises it at step start; kernels own it afterwards.
 struct EnvState {
   int32_t phase;
+  int32_t stage;           // Stage, while phase == PH_RUN
   int32_t mode;            // 0 = full step, 1 = extraction only
   int32_t status;          // TC_OK or TC_E_*
   int32_t infeasible;
