@@ -359,7 +359,7 @@ tc_status tc_autotune(tc_context* ctx, int32_t n, tc_pad* const* pads,
                       const int32_t* n_ind, const tc_indenter* ind, int32_t* chosen);
 /* Force a launch shape: block sizes of the vertex-row kernels (64..1024),
  * the element kernels (64..256) and the SpMV (64..1024), all multiples of 64;
- * CG iterations between host checks of convergence (even, >= 2; default 16);
+ * CG iterations between host checks of convergence (even, >= 2; default 12);
  * use_graphs 1 replays those iterations of a whole batch as one captured HIP
  * graph, 0 (default) launches them directly, -1 leaves it unchanged.
  * 0 leaves a value unchanged. */
@@ -367,10 +367,13 @@ tc_status tc_set_launch(tc_context* ctx, int32_t cg_block, int32_t elem_block, i
                         int32_t cg_per_replay, int32_t use_graphs);
 
 /* Streams a batch step is split over (default 1).  With n > 1, tc_step_batch
- * divides its pads into n groups of about equal tet counts; each group is
- * stepped on a stream of its own, driven by a host thread of its own, so
- * one group's last CG iterations and host round trips overlap with the
- * other groups' launches.  Every pad's result is bitwise the same for any n
+ * divides its pads into n groups: the pads with the most Newton iterations
+ * in their last step (up to a quarter of the batch's tets) form the first,
+ * the others are split into groups of about equal cost (tets x Newton
+ * iterations).  Each group is stepped on a stream of its own, driven by a
+ * host thread of its own, so the slow pads' long chains of small launches
+ * and every group's host round trips overlap with the other groups' large
+ * launches.  Every pad's result is bitwise the same for any n
  * (pads never share arithmetic).  Streams keep the default priority.  The
  * setting takes effect from the next batch; extraction-only calls and
  * single pads use the context stream. */
@@ -392,7 +395,7 @@ tc_status tc_set_streams(tc_context* ctx, int32_t n_streams);
  *     iterations carry the other pads' work.
  *   staged = 0: lockstep; one Newton iteration of every running pad at a
  *     time, each stage waiting for its slowest pad.
- * line_search_evals: 1..8 (0 keeps the current value; default 2).  Every
+ * line_search_evals: 1..8 (0 keeps the current value; default 3).  Every
  * pad's result is bitwise the same under both schedules: each runs the same
  * kernels on its own data in the same order.  Takes effect from the next
  * batch; the serving loop and single-pad inspection calls keep lockstep. */

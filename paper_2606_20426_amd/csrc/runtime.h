@@ -108,10 +108,10 @@ struct tc_context {
   int cg_block = 256;
   int spmv_block = 256;
   int el_block = 128;
-  int cg_per_replay = 16;
+  int cg_per_replay = 12;
   bool use_graphs = false;
   bool staged = true;                // batch schedule: staged (else lockstep)
-  int ls_per_round = 2;              // trial energies per round of the staged schedule
+  int ls_per_round = 3;              // trial energies per round of the staged schedule
   // timing
   bool timing = false;
   int timing_stride = 1;             // time every k-th launch of each kernel

@@ -986,17 +986,35 @@ tc_status run_batch(tc_context* ctx, int n, tc_pad* const* pads, const int32_t* 
   if (G == 1) {
     for (int i = 0; i < n; ++i) groups[0].push_back(i);
   } else {
-    // a pad's cost is taken as its tets times the Newton iterations of its
-    // last step (a step's length is set by the pads that iterate longest:
-    // they go to different groups); largest cost first to the group with
-    // the least, each group keeping the batch order
-    auto cost = [&](int i) { return (int64_t)pads[i]->T * std::max(1, pads[i]->last_newton); };
+    // the pads that iterated longest in their last step, up to a quarter of
+    // the batch's tets, get the first stream: their long chains of small
+    // launches run beside the other groups' large launches instead of
+    // lengthening steps that also carry bulk work.  The rest are split into
+    // groups of about equal cost, a pad's cost being its tets times its
+    // Newton iterations, largest first to the group with the least; each
+    // group keeps the batch order
     std::vector<int> order(n);
     for (int i = 0; i < n; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost(x) > cost(y); });
-    std::vector<int64_t> load(G, 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return pads[x]->last_newton > pads[y]->last_newton; });
+    int64_t total = 0, slow = 0;
+    for (int i = 0; i < n; ++i) total += pads[i]->T;
+    auto cost = [&](int i) { return (int64_t)pads[i]->T * std::max(1, pads[i]->last_newton); };
+    std::vector<int> rest;
     for (int i : order) {
-      const int g = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      // (at least one pad left for each of the other groups)
+      const int left = n - (int)groups[0].size() - (int)rest.size();
+      if (slow < total / 4 && left > G - 1) {
+        groups[0].push_back(i);
+        slow += pads[i]->T;
+      } else {
+        rest.push_back(i);
+      }
+    }
+    std::stable_sort(rest.begin(), rest.end(), [&](int x, int y) { return cost(x) > cost(y); });
+    std::vector<int64_t> load(G, 0);
+    for (int i : rest) {
+      const int g = 1 + (int)(std::min_element(load.begin() + 1, load.end()) - load.begin() - 1);
       groups[g].push_back(i);
       load[g] += cost(i);
     }
@@ -2104,7 +2122,7 @@ tc_status tc_autotune(tc_context* ctx, int32_t n, tc_pad* const* pads, const int
     ctx->n_lanes = best_lanes;
     int best_chunk = ctx->cg_per_replay;
     best_ms = 1e30;
-    for (int ch : {8, 16, 32}) {
+    for (int ch : {8, 12, 16, 24}) {
       ctx->cg_per_replay = ch;
       double ms;
       tc_status s = wall(&ms);
