@@ -194,7 +194,13 @@ typedef struct {
                            energy keeps falling (within the collision-free
                            bound); 0 = off.  Same minimiser, fewer
                            iterations where the filtered Hessian is stiffer
-                           than the energy along the direction. */
+                           than the energy along the direction.  In the
+                           other case (a full step that passes with much
+                           less decrease than the model predicts, the
+                           energy curving up at least 1.4 times as fast
+                           along the direction) the minimum of the
+                           quadratic through E(0), g.d and E(1) is tried
+                           instead, whatever ls_expand. */
   int32_t mesh_contact; /* rigid meshes (TC_MESH): 0 = barrier of the
                            distance to the whole surface, b(phi / d_hat);
                            1 = barrier summed over the mesh's triangles

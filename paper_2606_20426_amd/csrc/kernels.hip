@@ -1941,6 +1941,7 @@ __global__ void k_env_newton_begin(const EnvDesc* envs, int n) {
   S->ls_halv = 0;
   S->ls_expanding = 0;
   S->ls_expand_n = 0;
+  S->ls_contracting = 0;
   S->stage = ST_ASM;
 }
 
@@ -2482,6 +2483,27 @@ __global__ void k_energy(const Tile* tiles, int ntiles, const EnvDesc* envs, int
 // One block per pad: E = inertia + h^2 (elastic + barrier + friction).  mode 0 stores
 // E(x).  mode 1: Armijo test E(x + a d) <= E(x) + 1e-4 a g.d + noise |E(x)|,
 // accept or halve a.
+// After a full step passes Armijo with much less decrease than the model
+// predicts: the quadratic through E(0), E'(0) = g.d and E(1) has its
+// minimum at alpha* = -g.d / (2 (E(1) - E(0) - g.d)).  With the CG
+// direction's own curvature (d.Hd = -g.d) the model's minimum is at 1; a
+// minimum below 0.7 means the energy curves up along d at least 1.4 times
+// as fast as the model (the full step overshoots, and Newton stalls on
+// the component it keeps overshooting).  Then alpha* (at least 0.1) is
+// tried next, and kept if it lowers the energy below E(1).
+__device__ __forceinline__ bool ls_try_contract(EnvState* S, double E1) {
+  const double gd = S->gTd;
+  const double c = E1 - S->E_cur - gd;
+  if (!(gd < 0.0) || !(c > 0.0)) return false;
+  const double as = -gd / (2.0 * c);
+  if (!(as < 0.7)) return false;
+  S->ls_contracting = 1;
+  S->ls_best_alpha = 1.0;
+  S->ls_best_E = E1;
+  S->ls_alpha = fmax(as, 0.1);
+  return true;
+}
+
 __global__ void k_env_ls(const EnvDesc* envs, int n, int mode) {
   __shared__ double sh[16];
   if (blockIdx.x >= n) return;
@@ -2510,6 +2532,18 @@ __global__ void k_env_ls(const EnvDesc* envs, int n, int mode) {
   }
   const double a = S->ls_alpha;
   const bool armijo = Etot <= S->E_cur + 1e-4 * a * S->gTd + E.noise * fabs(S->E_cur);
+  if (S->ls_contracting) {
+    if (Etot < S->ls_best_E) {
+      S->ls_best_alpha = a;
+      S->ls_best_E = Etot;
+    }
+    S->ls_alpha = S->ls_best_alpha;
+    S->E_next = S->ls_best_E;
+    S->ls_done = 1;
+    S->apply = 1;
+    S->stage = ST_UPD;
+    return;
+  }
   if (S->ls_expanding) {
     // doubling an accepted full step: keep the larger step while it lowers
     // the energy further (and still passes Armijo)
@@ -2530,6 +2564,7 @@ __global__ void k_env_ls(const EnvDesc* envs, int n, int mode) {
     return;
   }
   if (armijo) {
+    if (S->ls_halv == 0 && a == 1.0 && ls_try_contract(S, Etot)) return;
     if (E.ls_expand > 0 && S->ls_halv == 0 && a == 1.0 && 2.0 <= S->alpha_max) {
       S->ls_expanding = 1;
       S->ls_best_alpha = a;

@@ -145,6 +145,7 @@ struct EnvState {
   double ls_alpha;
   int32_t ls_expanding;    // the line search is doubling an accepted full step
   int32_t ls_expand_n;     // doublings taken
+  int32_t ls_contracting;  // trying the shorter step of the quadratic fit after a full step
   double ls_best_alpha;    // best accepted step and its energy while doubling
   double ls_best_E;
   double alpha_max;
