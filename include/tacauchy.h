@@ -404,7 +404,9 @@ tc_status tc_set_streams(tc_context* ctx, int32_t n_streams);
  * line_search_evals: 1..8 (0 keeps the current value; default 3).  Every
  * pad's result is bitwise the same under both schedules: each runs the same
  * kernels on its own data in the same order.  Takes effect from the next
- * batch; the serving loop and single-pad inspection calls keep lockstep. */
+ * batch; the serving loop and single-pad inspection calls keep lockstep
+ * (staged serving ticks measured slower: more host round trips per unit of
+ * work, and admissions split into more initialisations). */
 tc_status tc_set_schedule(tc_context* ctx, int32_t staged, int32_t line_search_evals);
 
 /* ------------------------------------------------------------------- pads */
