@@ -196,7 +196,8 @@ def cpu_baseline(envs, budget_s=15.0, workers=None):
 
 def make_pads(tc, ctx, envs, args, precision=None):
     extra = dict(cg_rel_tol=args.cg_rel_tol, cg_eta_max=args.cg_eta_max, cg_forcing=args.cg_forcing,
-                 hess_proj=args.hess_proj, ls_expand=args.ls_expand, cg_conv_tol=args.cg_conv_tol)
+                 hess_proj=args.hess_proj, ls_expand=args.ls_expand, cg_conv_tol=args.cg_conv_tol,
+                 cg_warm=args.cg_warm)
     if args.init_guess is not None:
         extra["init_guess"] = args.init_guess
     pads = []
@@ -614,6 +615,7 @@ def main():
     ap.add_argument("--cg-conv-tol", type=float, default=0.0,
                     help="CG tolerance of a direction that decides convergence (0 = the solve tolerance)")
     ap.add_argument("--hess-proj", type=int, default=4)
+    ap.add_argument("--cg-warm", type=int, default=0, help="CG from the best multiple of the previous direction")
     ap.add_argument("--ls-expand", type=int, default=4,
                     help="doublings of an accepted full Newton step while the energy keeps falling")
     ap.add_argument("--init-guess", type=int, default=1,

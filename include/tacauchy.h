@@ -252,6 +252,16 @@ typedef struct {
                            indenters, else the step's own (w = 0). */
   double eps_v;         /* friction velocity threshold [m/s] > 0 (Sec.
                            III-B: 0.01) */
+  int32_t cg_warm;      /* 1: from the second Newton iteration of a step on,
+                           CG starts from the best multiple of the previous
+                           Newton direction, gamma d_prev with gamma =
+                           -g.d_prev / d_prev.H d_prev (one extra product,
+                           skipped when d_prev.H d_prev <= 0), instead of
+                           0; its stopping test stays relative to the cold
+                           start's r0.z0.  Where Newton converges linearly
+                           along a slowly turning direction, that start
+                           already meets the CG tolerance.  0 = cold start. */
+  int32_t reserved0;    /* 0 */
 } tc_params;
 
 /* Rigid indenter pose at the end of the step: world x = R y + c. */

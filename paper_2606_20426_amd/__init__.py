@@ -45,7 +45,7 @@ def make_params(**kw) -> _abi.TcParams:
     (dt, dhat, kappa, newton_tol, cg_rel_tol, max_newton, max_cg,
     quasi_static, precision, gravity, literal_alpha, precond, max_halvings,
     cg_forcing, hess_proj, init_guess, cg_conv_tol, cg_eta_max, ls_expand,
-    mesh_contact, friction, eps_v)."""
+    mesh_contact, friction, eps_v, cg_warm)."""
     p = _abi.TcParams()
     check(load().tc_params_default(C.byref(p)))
     for k, v in kw.items():

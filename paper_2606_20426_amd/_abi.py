@@ -48,7 +48,8 @@ class TcParams(C.Structure):
                 ("hess_proj", C.c_int32), ("init_guess", C.c_int32),
                 ("cg_conv_tol", C.c_double), ("cg_eta_max", C.c_double),
                 ("ls_expand", C.c_int32), ("mesh_contact", C.c_int32),
-                ("friction", C.c_double), ("eps_v", C.c_double)]
+                ("friction", C.c_double), ("eps_v", C.c_double),
+                ("cg_warm", C.c_int32), ("reserved0", C.c_int32)]
 
 
 class TcSizing(C.Structure):

@@ -1754,7 +1754,7 @@ constexpr int ASM_LPR = 8;
 
 template <typename R>
 __device__ __forceinline__ void asm_diag_row(const EnvDesc& E, int i, double D[3][3], double gs[3], double& rz,
-                                             double& gg) {
+                                             double& gg, double& gd, bool warm) {
   D[1][0] = D[0][1]; D[2][0] = D[0][2]; D[2][1] = D[1][2];
   const size_t it0 = (size_t)i * E.W;
   const double h2 = E.h * E.h;
@@ -1819,13 +1819,17 @@ __device__ __forceinline__ void asm_diag_row(const EnvDesc& E, int i, double D[3
     E.g[3 * i + r] = gs[r];
     rr[r] = -gs[r];
     E.r[3 * i + r] = rr[r];
+    // warm start: the previous Newton direction becomes the search
+    // direction of iteration -1 (p_old of parity 0, with z = 0 and beta 1)
+    const R dp = warm ? d[3 * i + r] : R(0);
+    gd += rr[r] * (double)dp;
     d[3 * i + r] = R(0);
-    p1[3 * i + r] = R(0);
+    p1[3 * i + r] = dp;
     gg += gs[r] * gs[r];
   }
   for (int r = 0; r < 3; ++r) {
     const R zr = Pr[r][0] * (R)rr[0] + Pr[r][1] * (R)rr[1] + Pr[r][2] * (R)rr[2];
-    z[3 * i + r] = zr;
+    z[3 * i + r] = warm ? R(0) : zr;
     rz += rr[r] * (double)zr;
   }
 }
@@ -1842,7 +1846,8 @@ __global__ void k_asm_diag(const Tile* tiles, int ntiles, const EnvDesc* envs) {
   const int groups = blockDim.x / ASM_LPR;
   const int row0 = tl.tile * blockDim.x + threadIdx.x / ASM_LPR;
   const R* Kd = (const R*)E.Ke;
-  double rz = 0.0, gg = 0.0;
+  const bool warm = E.st->warm != 0;
+  double rz = 0.0, gg = 0.0, gd = 0.0;
   for (int k = 0; k < ASM_LPR; ++k) {
     const int i = row0 + k * groups;
     double v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};   // xx xy xz yy yz zz, gradient
@@ -1859,14 +1864,17 @@ __global__ void k_asm_diag(const Tile* tiles, int ntiles, const EnvDesc* envs) {
     if (lane == 0 && i < E.V) {
       double D[3][3] = {{v[0], v[1], v[2]}, {0, v[3], v[4]}, {0, 0, v[5]}};
       double gs[3] = {v[6], v[7], v[8]};
-      asm_diag_row<R>(E, i, D, gs, rz, gg);
+      asm_diag_row<R>(E, i, D, gs, rz, gg, gd, warm);
     }
   }
   rz = block_reduce(rz, OpSum(), sh);
   gg = block_reduce(gg, OpSum(), sh);
+  if (warm) gd = block_reduce(gd, OpSum(), sh);
   if (threadIdx.x == 0) {
     E.part_rz[tl.tile] = rz;
     E.part_g2[tl.tile] = gg;
+    // r0.d_prev partials (the direction partials are free until k_newton_dir)
+    if (warm) E.part_dir[tl.tile] = gd;
   }
 }
 
@@ -1928,12 +1936,14 @@ __global__ void k_env_newton_begin(const EnvDesc* envs, int n) {
     S->rz0_prev = S->rz0;
     S->eta_prev = sqrt(S->cg_tol2);
   }
+  // warm start from the previous Newton direction of this step (still in d)
+  S->warm = envs[blockIdx.x].cg_warm && S->newton_iters > 0 && S->apply;
   S->cg_done = 0;
   S->cg_iters = 0;
   S->breakdown = 0;
   S->true_hess = S->true_hess && !S->no_true_hess;
   S->it[0] = -1;
-  S->it[1] = -1;
+  S->it[1] = S->warm ? -2 : -1;
   S->rzp[0] = S->rzp[1] = 0.0;
   S->dir_conv = 0;
   S->apply = 0;
@@ -1975,50 +1985,64 @@ __device__ __forceinline__ bool cg_head(const Tile tl, const EnvDesc& E, int par
   return cg_decide(tl, E, parity, rz, beta, &it);
 }
 
+// Forcing term of a Newton iteration's solve, from its cold-start r0.z0:
+// the relative tolerance squared.
+__device__ __forceinline__ double cg_tol2_of(const EnvDesc& E, const EnvState* S, double rz) {
+  double eta = S->force_tight ? fmin(E.cg_conv_tol, E.cg_rel_tol) : E.cg_rel_tol;
+  if (E.cg_forcing && !S->force_tight) {
+    if (S->rz0_prev > 0.0) {
+      const double r2 = rz / S->rz0_prev;      // (|g_k| / |g_k-1|)^2, preconditioned norms
+      if (r2 < 0.25 || E.cg_forcing == 2) {
+        eta = 0.9 * r2;                        // Eisenstat-Walker choice 2
+        const double safe = 0.9 * S->eta_prev * S->eta_prev;
+        if (safe > 0.1) eta = fmax(eta, safe);
+      } else {
+        eta = 0.25 * S->eta_prev;              // slow progress: solve more accurately
+      }
+    } else {
+      eta = E.cg_eta_max;
+    }
+    eta = fmin(E.cg_eta_max, fmax(eta, E.cg_rel_tol));
+  }
+  return eta * eta;
+}
+
 __device__ __forceinline__ bool cg_decide(const Tile tl, const EnvDesc& E, int parity, double rz, double* beta,
                                           int* it_out) {
   EnvState* S = E.st;
   const int it = S->it[parity ^ 1] + 1;
   *it_out = it;
-  const double rz0 = it == 0 ? rz : S->rz0;
-  double tol2 = S->cg_tol2;
-  if (it == 0) {
-    // forcing term of this Newton iteration
-    double eta = S->force_tight ? fmin(E.cg_conv_tol, E.cg_rel_tol) : E.cg_rel_tol;
-    if (E.cg_forcing && !S->force_tight) {
-      if (S->rz0_prev > 0.0) {
-        const double r2 = rz / S->rz0_prev;      // (|g_k| / |g_k-1|)^2, preconditioned norms
-        if (r2 < 0.25 || E.cg_forcing == 2) {
-          eta = 0.9 * r2;                        // Eisenstat-Walker choice 2
-          const double safe = 0.9 * S->eta_prev * S->eta_prev;
-          if (safe > 0.1) eta = fmax(eta, safe);
-        } else {
-          eta = 0.25 * S->eta_prev;              // slow progress: solve more accurately
-        }
-      } else {
-        eta = E.cg_eta_max;
-      }
-      eta = fmin(E.cg_eta_max, fmax(eta, E.cg_rel_tol));
-    }
-    tol2 = eta * eta;
+  // iteration -1 of a warm start is the product with p = d_prev (z = 0,
+  // beta 1); the solve's tolerance is set there, or at iteration 0 of a cold
+  // start, from the cold start's r0.z0 (the partials of the assembly)
+  const bool first = it < 0 || (it == 0 && !S->warm);
+  const double rz0 = first ? rz : S->rz0;
+  const double tol2 = first ? cg_tol2_of(E, S, rz) : S->cg_tol2;
+  const bool done = it >= 0 && (it >= E.max_cg || !(rz > tol2 * rz0) || S->breakdown);
+  double gd = 0.0;
+  if (it < 0 && tl.tile == 0) {
+    // r0.d_prev from the assembly's partials (block-uniform branch)
+    __shared__ double shd[16];
+    gd = reduce_partials(E.part_dir, E.n_vt, OpSum(), 0.0, shd);
   }
-  const bool done = it >= E.max_cg || !(rz > tol2 * rz0) || S->breakdown;
   if (tl.tile == 0 && threadIdx.x == 0) {
     // the other blocks of this launch read the stage: ST_ASM and ST_CG
     // both let them run
     S->stage = ST_CG;
-    if (it == 0) S->cg_tol2 = tol2;
+    if (first) {
+      S->cg_tol2 = tol2;
+      S->rz0 = rz;
+    }
     if (done) {
       S->cg_done = 1;
       S->cg_iters = it;
     } else {
       S->it[parity] = it;
-      S->rzp[parity] = rz;
-      if (it == 0) S->rz0 = rz;
+      S->rzp[parity] = it < 0 ? gd : rz;   // the update's alpha = rzp / p.Ap
     }
   }
   if (done) return false;
-  *beta = it == 0 ? 0.0 : rz / S->rzp[parity ^ 1];
+  *beta = it < 0 ? 1.0 : it == 0 ? 0.0 : rz / S->rzp[parity ^ 1];
   return true;
 }
 
@@ -2147,7 +2171,9 @@ __device__ __forceinline__ double cg_alpha(const Tile tl, const EnvDesc& E, int 
   double alpha = rz / pq;
   if (!(pq > 0.0) || !isfinite(alpha)) {
     alpha = 0.0;
-    if (tl.tile == 0 && threadIdx.x == 0) S->breakdown = 1;
+    // (a warm start along a direction of non-positive curvature is only
+    // skipped: the cold start follows)
+    if (tl.tile == 0 && threadIdx.x == 0 && S->it[parity] >= 0) S->breakdown = 1;
   }
   return alpha;
 }
@@ -2390,7 +2416,7 @@ __global__ void k_env_dir(const EnvDesc* envs, int n) {
     }
     S->ls_done = S->dir_conv;
     S->apply = S->dir_conv;
-    S->cg_total += S->cg_iters;
+    S->cg_total += S->cg_iters + S->warm;   // (a warm start's product counts as an iteration)
     S->stage = S->ls_done ? ST_UPD : ST_LS;
   }
 }

@@ -1864,6 +1864,7 @@ tc_status tc_pad_set_params(tc_pad* pad, const tc_params* params) {
   E.cg_eta_max = params->cg_eta_max;
   E.init_guess = params->init_guess;
   E.ls_expand = params->ls_expand;
+  E.cg_warm = params->cg_warm;
   E.fr_mu = params->friction;
   E.fr_eps = params->eps_v * params->dt;
   E.mesh_pairs = params->mesh_contact;

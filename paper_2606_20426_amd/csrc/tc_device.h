@@ -157,6 +157,7 @@ struct EnvState {
   double rz0;
   int32_t it[2];
   int32_t cg_done;
+  int32_t warm;            // this iteration's CG starts from gamma d_prev (iteration -1)
   int32_t cg_iters;
   int32_t breakdown;
   int32_t force_tight;     // next CG must reach the floor tolerance
@@ -261,6 +262,7 @@ struct EnvDesc {
   double gravity[3];
   int32_t quasi_static, max_cg, max_newton, max_halvings, precond, cg_forcing, hess_proj, init_guess;
   int32_t ls_expand;
+  int32_t cg_warm;           // CG starts from the best multiple of the previous direction
   int32_t mesh_pairs;        // rigid meshes: 0 distance; 1 barrier summed over triangles within
                              // d_hat; 2 that plus vertex-face and edge-edge pairs
   double fr_mu, fr_eps;      // friction ratio (0 = off) and slip threshold eps_v h [m]

@@ -91,6 +91,7 @@ tc_status validate_params(const tc_params* p, std::string& err) {
   if (!finite(p->friction) || p->friction < 0) { err = "friction must be finite and >= 0"; return TC_E_INVALID_ARG; }
   if (p->friction > 0 && (!finite(p->eps_v) || !(p->eps_v > 0))) { err = "eps_v must be finite and > 0 with friction on"; return TC_E_INVALID_ARG; }
   if (p->mesh_contact < 0 || p->mesh_contact > 2) { err = "mesh_contact must be 0, 1 or 2"; return TC_E_INVALID_ARG; }
+  if (p->cg_warm < 0 || p->cg_warm > 1) { err = "cg_warm must be 0 or 1"; return TC_E_INVALID_ARG; }
   for (int c = 0; c < 3; ++c)
     if (!finite(p->gravity[c])) { err = "gravity must be finite"; return TC_E_INVALID_ARG; }
   return TC_OK;

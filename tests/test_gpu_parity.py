@@ -76,10 +76,10 @@ def test_extraction_on_prescribed_positions(prec, tol):
             assert np.allclose(gp.read("reaction"), cf["reaction"], rtol=1e-9, atol=1e-15)
 
 
-def _episode(prec, steps, newton_tol, cg_rel_tol):
+def _episode(prec, steps, newton_tol, cg_rel_tol, **kw):
     ep = scenes.config1()
     ctx = context()
-    gp = gpu_pad(ctx, ep.pad, prec, newton_tol=newton_tol, cg_rel_tol=cg_rel_tol)
+    gp = gpu_pad(ctx, ep.pad, prec, newton_tol=newton_tol, cg_rel_tol=cg_rel_tol, **kw)
     op, refs = oracle_episode(ep, steps, tol=1e-10)
     X = ep.pad.X
     top = op.is_top.astype(bool)
@@ -111,6 +111,14 @@ def test_config1_episode_fp64():
 
 def test_config1_episode_mixed():
     worst = _episode("mixed", 10, 1e-6, 1e-4)
+    assert (worst < 1e-4).all(), worst
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_config1_episode_warm_start(prec):
+    """CG started from the best multiple of the previous Newton direction
+    (cg_warm): the same minimiser as the oracle's exact Newton."""
+    worst = _episode(prec, 10, 1e-9 if prec == "fp64" else 1e-6, 1e-9 if prec == "fp64" else 1e-4, cg_warm=1)
     assert (worst < 1e-4).all(), worst
 
 

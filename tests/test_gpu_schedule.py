@@ -20,7 +20,7 @@ pytestmark = pytest.mark.gpu
 FIELDS = ("positions", "velocities", "sigma", "pressure", "contact_force", "reaction")
 
 
-def _run(envs, steps, staged, ls_evals=0, cg_chunk=0, streams=1):
+def _run(envs, steps, staged, ls_evals=0, cg_chunk=0, streams=1, cg_warm=0):
     ctx = tc.Context(0)
     ctx.set_schedule(staged, ls_evals)
     if cg_chunk:
@@ -41,7 +41,7 @@ def _run(envs, steps, staged, ls_evals=0, cg_chunk=0, streams=1):
                                               kappa=e.params.kappa, newton_tol=e.params.newton_tol,
                                               friction=e.friction, mesh_contact=e.mesh_contact,
                                               cg_rel_tol=0.2, cg_eta_max=0.2, cg_forcing=2, hess_proj=4,
-                                              ls_expand=4, init_guess=1),
+                                              ls_expand=4, init_guess=1, cg_warm=cg_warm),
                                tet_material=idx))
 
         def poses(e, s):
@@ -101,6 +101,20 @@ def test_staged_small_rounds_and_streams():
     lock = _run(envs, steps, staged=False)
     _same(lock, _run(envs, steps, staged=True, ls_evals=1, cg_chunk=2), "chunk 2, one trial energy")
     _same(lock, _run(envs, steps, staged=True, streams=2), "two streams")
+
+
+def test_staged_warm_start_bitwise_equal_to_lockstep():
+    """The warm-started CG (iteration -1 along the previous direction) under
+    both schedules, including chunks of 2 (the warm product and the first
+    iteration in different rounds)."""
+    envs = [scenes.config3()[k] for k in PICK]
+    steps = 5
+    lock = _run(envs, steps, staged=False, cg_warm=1)
+    _same(lock, _run(envs, steps, staged=True, cg_warm=1), "warm start")
+    _same(lock, _run(envs, steps, staged=True, cg_chunk=2, cg_warm=1), "warm start, chunk 2")
+    cold = _run(envs, steps, staged=False)
+    log(f"CG iterations per pad at step {steps}: cold {[x[2] for x in cold[0][-1]]}, "
+        f"warm {[x[2] for x in lock[0][-1]]}")
 
 
 def test_set_schedule_rejects_bad_values():
