@@ -145,7 +145,7 @@ def test_autotune_keeps_state_and_stepping_valid():
     chosen = ctxs[1].autotune(pads[1], [[e.pose(3)] for e in eps])
     log(f"autotune chose {chosen}")
     assert chosen[0] in (128, 256, 512, 1024) and chosen[1] in (64, 128, 256)
-    assert chosen[2] % 64 == 0 and 64 <= chosen[2] <= 1024 and chosen[3] in (8, 16, 32)
+    assert chosen[2] % 64 == 0 and 64 <= chosen[2] <= 1024 and chosen[3] in (8, 12, 16, 24)
     assert 1 <= chosen[4] <= 2                      # 4 pads: at most 2 streams of 2 pads
     for p, x in zip(pads[1], before):
         assert np.array_equal(p.read("positions"), x)
