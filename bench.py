@@ -474,6 +474,7 @@ def run_serve(args):
     envs, desc = build_workload(args.workload)
     n_pads = len(envs)
     ctx = tc.Context(0, hbm_budget=int(args.hbm_budget_gib * 2**30) if args.hbm_budget_gib else 0)
+    ctx.set_schedule(args.schedule == "staged", args.ls_evals)
     t0 = time.perf_counter()
     pads = make_pads(tc, ctx, envs, args)
     resident = sum(p.info["resident_bytes"] for p in pads)
@@ -503,6 +504,7 @@ def run_serve(args):
         "config": {"workload": args.workload, "description": desc, "pads": n_pads,
                    "arrival_rate_hz": head["arrival_rate_hz"], "duration_s": args.duration,
                    "max_slots": args.max_slots, "hbm_budget_gib": args.hbm_budget_gib,
+                   "schedule": args.schedule,
                    "resident_gib": round(resident / 2**30, 3), "hbm_used_gib": round(ctx.memory()[0] / 2**30, 3),
                    "requests": head["requests"], "completed": head["completed"],
                    "failed_by_status": head["failed_by_status"], "saturated": head["saturated"]},
@@ -609,8 +611,9 @@ def main():
     ap.add_argument("--cg-forcing", type=int, default=2)
     ap.add_argument("--streams", type=int, default=0,
                     help="streams a batch step is split over (1..4; default 2, 1 for paper60)")
-    ap.add_argument("--schedule", default="staged", choices=("staged", "lockstep"),
-                    help="pads through their Newton iterations at their own pace, or in lockstep")
+    ap.add_argument("--schedule", default="", choices=("", "staged", "lockstep"),
+                    help="pads through their Newton iterations at their own pace, or in lockstep "
+                         "(default: staged; lockstep for serving)")
     ap.add_argument("--ls-evals", type=int, default=0, help="trial energies per staged round (0: default)")
     ap.add_argument("--cg-conv-tol", type=float, default=0.0,
                     help="CG tolerance of a direction that decides convergence (0 = the solve tolerance)")
@@ -627,6 +630,10 @@ def main():
     ap.add_argument("--max-slots", type=int, default=64)
     ap.add_argument("--hbm-budget-gib", type=float, default=0.0)
     args = ap.parse_args()
+    if not args.schedule:
+        # serving: one lockstep Newton iteration per tick sustained the higher
+        # load (2,130 against 2,000 completed steps/s at saturation)
+        args.schedule = "lockstep" if args.workload == "serve256" else "staged"
     if not args.streams:
         # the 60 small pads of paper60 are launch-latency bound: a second
         # host thread costs more than its overlap brings (measured 28.1k

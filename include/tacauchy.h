@@ -414,9 +414,11 @@ tc_status tc_set_streams(tc_context* ctx, int32_t n_streams);
  * line_search_evals: 1..8 (0 keeps the current value; default 3).  Every
  * pad's result is bitwise the same under both schedules: each runs the same
  * kernels on its own data in the same order.  Takes effect from the next
- * batch; the serving loop and single-pad inspection calls keep lockstep
- * (staged serving ticks measured slower: more host round trips per unit of
- * work, and admissions split into more initialisations). */
+ * batch.  The serving loop follows the same setting: one Newton iteration
+ * (lockstep) or one round (staged) of its running pads per tick; a staged
+ * round also initialises the requests admitted since the last tick and
+ * extracts the ones that had ended, so its readback is the tick's only host
+ * round trip. */
 tc_status tc_set_schedule(tc_context* ctx, int32_t staged, int32_t line_search_evals);
 
 /* ------------------------------------------------------------------- pads */
@@ -590,7 +592,8 @@ typedef struct {
   int64_t submitted, admitted, completed, rejected;
   int32_t queued, running;
   int32_t max_running_seen;
-  int64_t ticks;           /* batched Newton iterations executed */
+  int64_t ticks;           /* batched ticks executed (Newton iterations in
+                              lockstep, rounds in the staged schedule) */
   uint64_t scratch_in_use; /* bytes of step scratch held by running requests */
   int64_t evictions;       /* step scratch released to make room (context total) */
 } tc_server_stats;
@@ -598,7 +601,7 @@ typedef struct {
 /* Continuous-batching request loop on its own host thread.  Pads stay
  * resident; a request (pad, poses) is admitted when a slot is free and its
  * step scratch fits the context budget, joins the running batch at the next
- * Newton-iteration boundary and leaves it when its step completes.  When the
+ * tick (see tc_set_schedule) and leaves it when its step completes.  When the
  * budget is short, the step scratch of pads with no step on the device is
  * released (their committed state stays resident); a request that cannot fit
  * even then, with nothing running, completes with TC_E_NO_MEMORY.

@@ -2665,8 +2665,12 @@ __global__ void k_sigma(const Tile* tiles, int ntiles, const EnvDesc* envs) {
   const int t = xcd_tile(ntiles);
   if (t < 0) return;
   const EnvDesc& E = envs[tiles[t].env];
-  const EnvState* S = E.st;
+  EnvState* S = E.st;
   if (!extract_ok(S)) return;
+  // the pad's extraction is under way: k_env_extract may finish it (a pad
+  // that ended its Newton solve while other pads' extraction was launched
+  // waits for its own)
+  if (tiles[t].tile == 0 && threadIdx.x == 0) S->extracting = 1;
   const int e = tiles[t].tile * blockDim.x + threadIdx.x;
   if (e >= E.T) return;
   const double* x = S->mode == 1 ? E.x : E.xn;
@@ -2845,6 +2849,7 @@ __global__ void k_env_extract(const EnvDesc* envs, int n) {
     if (threadIdx.x == 0) S->phase = PH_DONE;
     return;
   }
+  if (!S->extracting) return;
   for (int c = 0; c < 3; ++c) {
     double f = 0, s = 0;
     for (int k = threadIdx.x; k < E.n_ct; k += blockDim.x) f += E.part_c3[3 * k + c];

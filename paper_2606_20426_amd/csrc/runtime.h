@@ -203,6 +203,7 @@ struct BatchPlan {
   int lpr = 0;                       // SpMV lanes per row
   int off[NCLS] = {0}, cnt[NCLS] = {0};
   std::vector<EnvDesc> h_desc;
+  int desc_cap = 0, tiles_cap = 0;   // allocated lengths of d_desc and d_tiles
   Tile* d_ctiles = nullptr;          // ring of compacted tile lists
   Tile* h_ctiles = nullptr;          // pinned staging of the ring
   int ctiles_cap = 0;
@@ -230,6 +231,10 @@ tc_status ensure_scratch_evicting(tc_pad* pad, const std::vector<tc_pad*>& keep)
 void release_scratch(tc_pad* pad);
 tc_status pool_reserve(tc_context* ctx, SlotPool& p, int cap);
 void pool_free(SlotPool& p);
+// Builds the plan into `out`.  A plan already there is replaced; its device
+// and pinned buffers are taken over when large enough (its stream must be
+// idle), so that rebuilding a plan for a changed set of pads (the serving
+// loop, between ticks) allocates nothing in the common case.
 tc_status build_plan(tc_context* ctx, int n, tc_pad* const* pads, const int* slots, const SlotPool& pool,
                      std::unique_ptr<BatchPlan>& out, hipStream_t stream = nullptr);
 // Lane g of split batches (created on first use, default-priority stream).
@@ -297,8 +302,12 @@ struct Runner {
   // staged schedule: the whole step, each pad through the stages of its
   // Newton iterations at its own pace, in rounds of launches
   tc_status staged(int M, int K);
-  tc_status round(int M, int K);
+  // serve: pads admitted since the last readback are initialised within the
+  // round, and pads that had ended at its start are extracted within it, so
+  // the round's readback is its only host round trip
+  tc_status round(int M, int K, bool serve = false);
   void init_launches();
+  void finish_launches();
   tc_status finish();
 
   static bool is_run(const EnvState& s) { return s.phase == PH_RUN && s.status == TC_OK; }
@@ -315,6 +324,9 @@ struct Runner {
   static bool dir_pending(const EnvState& s) { return is_run(s) && s.stage == ST_CG && s.cg_done; }
   static bool turning(const EnvState& s) { return dir_pending(s) || (is_run(s) && s.stage == ST_LS); }
   static bool may_start(const EnvState& s) { return is_run(s) && (s.stage == ST_START || turning(s)); }
+  // the same with the pads admitted since the last readback (serving)
+  static bool may_start_or_init(const EnvState& s) { return may_start(s) || is_init(s); }
+  static bool run_or_init(const EnvState& s) { return is_run(s) || is_init(s); }
 };
 
 }  // namespace tc

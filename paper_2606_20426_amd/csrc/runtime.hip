@@ -511,6 +511,7 @@ void free_lanes(tc_context* ctx) {
 tc_status build_plan(tc_context* ctx, int n, tc_pad* const* pads, const int* slots, const SlotPool& pool,
                      std::unique_ptr<BatchPlan>& out, hipStream_t stream) {
   if (!stream) stream = ctx->stream;
+  std::unique_ptr<BatchPlan> old = std::move(out);
   auto P = std::make_unique<BatchPlan>();
   P->slots.assign(slots, slots + n);
   P->BV = ctx->cg_block;
@@ -567,11 +568,35 @@ tc_status build_plan(tc_context* ctx, int n, tc_pad* const* pads, const int* slo
   add_cls(BatchPlan::ENERGY, [](const EnvDesc& E) { return E.n_te + E.n_vt + E.n_ct; });
   add_cls(BatchPlan::SPMV, [](const EnvDesc& E) { return E.n_spt; });
   add_cls(BatchPlan::PAIR, [](const EnvDesc& E) { return E.n_pt; });
-  TC_HIP(hipMalloc(&P->d_desc, sizeof(EnvDesc) * n));
-  TC_HIP(hipMalloc(&P->d_tiles, sizeof(Tile) * std::max<size_t>(tiles.size(), 1)));
-  P->ctiles_cap = 4 * (int)tiles.size() + 64;
-  TC_HIP(hipMalloc(&P->d_ctiles, sizeof(Tile) * std::max(P->ctiles_cap, 1)));
-  TC_HIP(hipHostMalloc(&P->h_ctiles, sizeof(Tile) * std::max(P->ctiles_cap, 1), hipHostMallocDefault));
+  // buffers of the replaced plan are taken over when large enough (its graph
+  // executable, which holds their addresses, is destroyed with it below);
+  // new ones get 25 % headroom
+  const int nt = std::max<int>((int)tiles.size(), 1);
+  const int ring = 4 * (int)tiles.size() + 64;
+  if (old && old->desc_cap >= n) {
+    std::swap(P->d_desc, old->d_desc);
+    P->desc_cap = old->desc_cap;
+  } else {
+    P->desc_cap = n + n / 4 + 1;
+    TC_HIP(hipMalloc(&P->d_desc, sizeof(EnvDesc) * P->desc_cap));
+  }
+  if (old && old->tiles_cap >= nt) {
+    std::swap(P->d_tiles, old->d_tiles);
+    P->tiles_cap = old->tiles_cap;
+  } else {
+    P->tiles_cap = nt + nt / 4;
+    TC_HIP(hipMalloc(&P->d_tiles, sizeof(Tile) * P->tiles_cap));
+  }
+  if (old && old->ctiles_cap >= ring) {
+    std::swap(P->d_ctiles, old->d_ctiles);
+    std::swap(P->h_ctiles, old->h_ctiles);
+    P->ctiles_cap = old->ctiles_cap;
+  } else {
+    P->ctiles_cap = ring + ring / 4;
+    TC_HIP(hipMalloc(&P->d_ctiles, sizeof(Tile) * P->ctiles_cap));
+    TC_HIP(hipHostMalloc(&P->h_ctiles, sizeof(Tile) * P->ctiles_cap, hipHostMallocDefault));
+  }
+  old.reset();
   TC_HIP(hipMemcpyAsync(P->d_desc, P->h_desc.data(), sizeof(EnvDesc) * n, hipMemcpyHostToDevice, stream));
   TC_HIP(hipMemcpyAsync(P->d_tiles, tiles.data(), sizeof(Tile) * tiles.size(), hipMemcpyHostToDevice, stream));
   TC_HIP(hipStreamSynchronize(stream));
@@ -745,8 +770,7 @@ void Runner::init_launches() {
 }
 
 // Extraction and commit of the pads whose Newton solve has ended.
-tc_status Runner::finish() {
-  if (!any(is_finish)) return TC_OK;
+void Runner::finish_launches() {
   const View vf = view(is_finish);
   launch_v(KernelId::sigma, vf, BatchPlan::TET);
   launch_v(KernelId::traction, vf, BatchPlan::SURF);
@@ -754,6 +778,11 @@ tc_status Runner::finish() {
   launch_v(KernelId::contact, vf, BatchPlan::CAND);
   launch_v(KernelId::commit, vf, BatchPlan::VERT);
   launch(KernelId::env_extract, BatchPlan::NCLS);
+}
+
+tc_status Runner::finish() {
+  if (!any(is_finish)) return TC_OK;
+  finish_launches();
   return readback();
 }
 
@@ -845,22 +874,29 @@ tc_status Runner::tick(bool init) {
 // iterations (M even: every pad enters its CG at parity 0).  A launch also
 // covers pads that may reach the kernel's stage only within the round; the
 // kernels pass over pads at another stage.  One readback ends the round.
-tc_status Runner::round(int M, int K) {
+tc_status Runner::round(int M, int K, bool serve) {
   static const bool debug = std::getenv("TC_DEBUG") != nullptr;
   using B = BatchPlan;
+  const bool init = serve && any(is_init);
+  const bool fin = serve && any(is_finish);
+  // pads being initialised join the first Newton iteration's launches; the
+  // kernels pass over any that the feasible start fails
+  auto starting = init ? may_start_or_init : may_start;
+  auto cg_pads = init ? run_or_init : is_run;
+  if (init) init_launches();
   const unsigned mD = 1u << B::VERT | 1u << B::CAND | 1u << B::PAIR;
   const unsigned mL = 1u << B::ENERGY | 1u << B::PAIR | 1u << B::VERT;
   const unsigned mA = 1u << B::TET | 1u << B::PAIR | 1u << B::CAND | 1u << B::VERT | 1u << B::ASM;
   const unsigned mC = 1u << B::SPMV | 1u << B::VERT;
-  const bool anyD = any(dir_pending), anyL = any(turning), anyA = any(may_start);
+  const bool anyD = any(dir_pending), anyL = any(turning), anyA = any(starting);
   std::vector<char> was_dir;
   if (debug)
     for (int i = 0; i < n; ++i) was_dir.push_back(dir_pending(state(i)));
   View vD{}, vL{}, vA{};
   if (anyD) vD = view(dir_pending, mD, false);
   if (anyL) vL = view(turning, mL, false);
-  if (anyA) vA = view(may_start, mA, false);
-  const View vC = view(is_run, mC, false);
+  if (anyA) vA = view(starting, mA, false);
+  const View vC = view(cg_pads, mC, false);
   flush_views();
   if (anyD) {
     launch_v(KernelId::newton_dir, vD, B::VERT);
@@ -881,7 +917,7 @@ tc_status Runner::round(int M, int K) {
   if (anyA) {
     launch(KernelId::newton_begin, B::NCLS);
     launch_v(KernelId::element, vA, B::TET);
-    if (any_pairs(may_start)) launch_v(KernelId::pairs, vA, B::PAIR, 0, 0);
+    if (any_pairs(starting)) launch_v(KernelId::pairs, vA, B::PAIR, 0, 0);
     launch_v(KernelId::barrier, vA, B::CAND);
     launch_v(KernelId::asm_diag, vA, B::VERT);
     launch_v(KernelId::asm_off, vA, B::ASM);
@@ -889,6 +925,7 @@ tc_status Runner::round(int M, int K) {
   tc_status st;
   // no CG chunk when no pad can be in CG (all others still searching)
   if ((anyA || any(in_cg)) && (st = cg_chunk(M, vC))) return st;
+  if (fin) finish_launches();    // (the pads that had ended before this round)
   if ((st = readback())) return st;
   if (debug)
     for (int i = 0; i < n; ++i) {
@@ -1052,7 +1089,6 @@ tc_status run_batch(tc_context* ctx, int n, tc_pad* const* pads, const int32_t* 
     std::vector<int> slots(m);
     for (int i = 0; i < m; ++i) slots[i] = i;
     if (!plan_matches(L.plan->get(), ctx, m, J.pads.data(), slots.data(), *L.pool)) {
-      L.plan->reset();
       if ((s = build_plan(ctx, m, J.pads.data(), slots.data(), *L.pool, *L.plan, L.stream))) return s;
     }
     for (int k = 0; k < m; ++k) {
@@ -1159,7 +1195,6 @@ tc_status newton_direction(tc_pad* pad, int n_ind, const tc_indenter* ind, doubl
   int slot = 0;
   tc_pad* pads[1] = {pad};
   if (!plan_matches(ctx->plan.get(), ctx, 1, pads, &slot, pool)) {
-    ctx->plan.reset();
     if ((s = build_plan(ctx, 1, pads, &slot, pool, ctx->plan))) return s;
   }
   BatchPlan* P = ctx->plan.get();

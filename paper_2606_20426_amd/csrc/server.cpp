@@ -144,12 +144,14 @@ void tc_server::loop() {
     }
     tc_status st = TC_OK;
     if (!plan_matches(plan.get(), ctx, n, pads.data(), slots.data(), pool)) {
-      plan.reset();
       st = build_plan(ctx, n, pads.data(), slots.data(), pool, plan);
     }
     if (st == TC_OK) {
       Runner run{ctx, plan.get(), n, &pool, max_slots};
-      st = run.tick(!fresh.empty());
+      // one tick: a lockstep Newton iteration, or a staged round that also
+      // initialises the admitted requests and extracts the ended ones
+      st = ctx->staged ? run.round(std::max(2, ctx->cg_per_replay & ~1), ctx->ls_per_round, true)
+                       : run.tick(!fresh.empty());
     }
     std::lock_guard<std::mutex> lk(m);
     stats.ticks++;

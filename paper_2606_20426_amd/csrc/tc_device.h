@@ -128,6 +128,7 @@ enum Stage : int32_t {
 struct EnvState {
   int32_t phase;
   int32_t stage;           // Stage, while phase == PH_RUN
+  int32_t extracting;      // the extraction kernels were launched for this pad (set by k_sigma)
   int32_t mode;            // 0 = full step, 1 = extraction only
   int32_t status;          // TC_OK or TC_E_*
   int32_t infeasible;

@@ -1,6 +1,7 @@
 """Continuous-batching server (tc_server_*): requests from pads of different
-sizes arrive while others run, join the running batch at Newton-iteration
-boundaries, and give the same result as the same step run alone (bitwise:
+sizes arrive while others run, join the running batch between its ticks
+(a Newton iteration in lockstep, a round of the staged schedule), and give
+the same result as the same step run alone (bitwise:
 the per-pad arithmetic does not depend on the batch).  Admission by HBM
 footprint: with a budget that holds only a few pads' step scratch, every
 request still completes, with the same results."""
@@ -45,8 +46,9 @@ def _alone(eps):
     return out
 
 
-def _served(eps, budget=0, max_slots=4):
+def _served(eps, budget=0, max_slots=4, staged=True):
     ctx = tc.Context(0, hbm_budget=budget)
+    ctx.set_schedule(staged)
     pads = [gpu_pad(ctx, e.pad, "mixed") for e in eps]
     srv = tc.Server(ctx, max_slots)
     order = [(k, s) for s in range(1, N_STEPS + 1) for k in range(len(eps))]
@@ -87,11 +89,12 @@ def _check(eps, alone, results, final, stats, label):
         f"{stats['ticks']}, latency p50 {np.percentile(lat, 50):.1f} ms p99 {np.percentile(lat, 99):.1f} ms")
 
 
-def test_server_results_equal_alone_bitwise():
+@pytest.mark.parametrize("staged", [True, False])
+def test_server_results_equal_alone_bitwise(staged):
     eps = _episodes()
     alone = _alone(eps)
-    results, final, stats = _served(eps)
-    _check(eps, alone, results, final, stats, "server")
+    results, final, stats = _served(eps, staged=staged)
+    _check(eps, alone, results, final, stats, "server, " + ("staged" if staged else "lockstep"))
     assert stats["max_running_seen"] > 1      # requests did overlap on the device
 
 
