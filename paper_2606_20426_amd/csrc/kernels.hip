@@ -1754,7 +1754,7 @@ constexpr int ASM_LPR = 8;
 
 template <typename R>
 __device__ __forceinline__ void asm_diag_row(const EnvDesc& E, int i, double D[3][3], double gs[3], double& rz,
-                                             double& gg, double& gd, bool warm) {
+                                             double& gg, bool warm) {
   D[1][0] = D[0][1]; D[2][0] = D[0][2]; D[2][1] = D[1][2];
   const size_t it0 = (size_t)i * E.W;
   const double h2 = E.h * E.h;
@@ -1822,7 +1822,6 @@ __device__ __forceinline__ void asm_diag_row(const EnvDesc& E, int i, double D[3
     // warm start: the previous Newton direction becomes the search
     // direction of iteration -1 (p_old of parity 0, with z = 0 and beta 1)
     const R dp = warm ? d[3 * i + r] : R(0);
-    gd += rr[r] * (double)dp;
     d[3 * i + r] = R(0);
     p1[3 * i + r] = dp;
     gg += gs[r] * gs[r];
@@ -1846,8 +1845,8 @@ __global__ void k_asm_diag(const Tile* tiles, int ntiles, const EnvDesc* envs) {
   const int groups = blockDim.x / ASM_LPR;
   const int row0 = tl.tile * blockDim.x + threadIdx.x / ASM_LPR;
   const R* Kd = (const R*)E.Ke;
-  const bool warm = E.st->warm != 0;
-  double rz = 0.0, gg = 0.0, gd = 0.0;
+  const bool warm = E.cg_warm && E.st->warm != 0;
+  double rz = 0.0, gg = 0.0;
   for (int k = 0; k < ASM_LPR; ++k) {
     const int i = row0 + k * groups;
     double v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};   // xx xy xz yy yz zz, gradient
@@ -1864,17 +1863,27 @@ __global__ void k_asm_diag(const Tile* tiles, int ntiles, const EnvDesc* envs) {
     if (lane == 0 && i < E.V) {
       double D[3][3] = {{v[0], v[1], v[2]}, {0, v[3], v[4]}, {0, 0, v[5]}};
       double gs[3] = {v[6], v[7], v[8]};
-      asm_diag_row<R>(E, i, D, gs, rz, gg, gd, warm);
+      asm_diag_row<R>(E, i, D, gs, rz, gg, warm);
     }
   }
   rz = block_reduce(rz, OpSum(), sh);
   gg = block_reduce(gg, OpSum(), sh);
-  if (warm) gd = block_reduce(gd, OpSum(), sh);
   if (threadIdx.x == 0) {
     E.part_rz[tl.tile] = rz;
     E.part_g2[tl.tile] = gg;
-    // r0.d_prev partials (the direction partials are free until k_newton_dir)
-    if (warm) E.part_dir[tl.tile] = gd;
+  }
+  if (warm) {
+    // r0.d_prev partials over the tile's rows, from r0 and the copy of d_prev
+    // just written (the block reductions above ordered those writes); the
+    // direction partials are free until k_newton_dir
+    const int i = tl.tile * blockDim.x + threadIdx.x;
+    double gd = 0.0;
+    if (i < E.V) {
+      const R* p1 = (const R*)E.p1;
+      for (int c = 0; c < 3; ++c) gd += E.r[3 * i + c] * (double)p1[3 * i + c];
+    }
+    gd = block_reduce(gd, OpSum(), sh);
+    if (threadIdx.x == 0) E.part_dir[tl.tile] = gd;
   }
 }
 
