@@ -786,9 +786,10 @@ tc_status Runner::finish() {
   return readback();
 }
 
-// Lockstep schedule: one Newton iteration for every pad in PH_RUN (pads in PH_INIT are
-// initialised first and join it; pads that end up in PH_FINISH get their
-// extraction).  Launches cover only the tiles of the pads concerned.
+// Lockstep schedule: one Newton iteration for every pad in PH_RUN (pads in
+// PH_INIT are initialised first and join it; pads that end up in PH_FINISH
+// get their extraction).  Launches cover only the tiles of the pads
+// concerned.
 tc_status Runner::tick(bool init) {
   tc_status st;
   static const bool debug = std::getenv("TC_DEBUG") != nullptr;
