@@ -125,3 +125,43 @@ def test_set_schedule_rejects_bad_values():
                 tc.check(ctx.lib.tc_set_schedule(ctx.h, staged, evals))
     finally:
         ctx.close()
+
+
+def test_failing_pads_leave_the_others_untouched():
+    """One batch, staged: a pad capped at one Newton iteration (not
+    converged) and a pad whose feasible start fails, beside two pads that
+    step normally.  The failing pads keep their state (the step is
+    transactional); the others' results are bitwise those of stepping them
+    alone."""
+    from gpu_util import gpu_pad
+    MM = scenes.MM
+    ep = scenes.config1()
+    ctx = tc.Context(0)
+    pads, alone = [], []
+    try:
+        cube = scenes.one_cube_pad(1 * MM)
+        fixed = np.where(cube.X[:, 2] == 0, 7, 3).astype(np.uint8)
+        cyl = dict(shape=tc.CYLINDER, prm=(0.8 * MM, 5 * MM), R=np.eye(3), c=(0.5e-3, 0.5e-3, 0.5e-3))
+        pads = [gpu_pad(ctx, ep.pad, "fp64"),
+                gpu_pad(ctx, ep.pad, "fp64", max_newton=1, newton_tol=1e-12),
+                gpu_pad(ctx, cube, "fp64", fixed=fixed),
+                gpu_pad(ctx, ep.pad, "fp64", newton_tol=1e-8)]
+        alone = [gpu_pad(ctx, ep.pad, "fp64"), gpu_pad(ctx, ep.pad, "fp64", newton_tol=1e-8)]
+        poses = [[ep.pose(2)], [ep.pose(1)], [cyl], [ep.pose(2)]]
+        for p in (pads[0], pads[3], alone[0], alone[1]):
+            p.step([ep.pose(1)])
+        before = [(p.read("positions"), p.read("velocities")) for p in pads]
+        st = tc.step_batch(ctx, pads, poses, raise_on_error=False)
+        assert [x.status for x in st] == [0, tc._abi.E_NOT_CONVERGED, tc._abi.E_INFEASIBLE, 0], st
+        for k in (1, 2):
+            assert np.array_equal(pads[k].read("positions"), before[k][0])
+            assert np.array_equal(pads[k].read("velocities"), before[k][1])
+        for p, a in ((pads[0], alone[0]), (pads[3], alone[1])):
+            a.step([ep.pose(2)])
+            for f in FIELDS:
+                assert np.array_equal(p.read(f), a.read(f)), f
+        log(f"batch with failures: {[(x.status, x.newton_iters) for x in st]}")
+    finally:
+        for p in pads + alone:
+            p.close()
+        ctx.close()
