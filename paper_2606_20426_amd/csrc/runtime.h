@@ -204,6 +204,8 @@ struct BatchPlan {
   int off[NCLS] = {0}, cnt[NCLS] = {0};
   std::vector<EnvDesc> h_desc;
   int desc_cap = 0, tiles_cap = 0;   // allocated lengths of d_desc and d_tiles
+  char* h_stage = nullptr;           // pinned staging of the descriptor and tile uploads
+  size_t stage_cap = 0;
   Tile* d_ctiles = nullptr;          // ring of compacted tile lists
   Tile* h_ctiles = nullptr;          // pinned staging of the ring
   int ctiles_cap = 0;

@@ -111,6 +111,7 @@ BatchPlan::~BatchPlan() {
   if (h_ctiles) (void)hipHostFree(h_ctiles);
   if (d_desc) (void)hipFree(d_desc);
   if (d_tiles) (void)hipFree(d_tiles);
+  if (h_stage) (void)hipHostFree(h_stage);
 }
 
 // Descriptor versions are unique across all pads of the process: a plan
@@ -596,10 +597,25 @@ tc_status build_plan(tc_context* ctx, int n, tc_pad* const* pads, const int* slo
     TC_HIP(hipMalloc(&P->d_ctiles, sizeof(Tile) * P->ctiles_cap));
     TC_HIP(hipHostMalloc(&P->h_ctiles, sizeof(Tile) * P->ctiles_cap, hipHostMallocDefault));
   }
+  // the uploads go through pinned staging, asynchronously; a staging buffer
+  // taken over may still feed the last rebuild's copies only if that call
+  // ended early (every step, tick and probe ends with a readback), so the
+  // stream, normally idle here, is waited for first
+  const size_t stage_need = sizeof(EnvDesc) * n + sizeof(Tile) * tiles.size();
+  if (old && old->stage_cap >= stage_need) {
+    TC_HIP(hipStreamSynchronize(stream));
+    std::swap(P->h_stage, old->h_stage);
+    P->stage_cap = old->stage_cap;
+  } else {
+    P->stage_cap = stage_need + stage_need / 4 + 64;
+    TC_HIP(hipHostMalloc(&P->h_stage, P->stage_cap, hipHostMallocDefault));
+  }
   old.reset();
-  TC_HIP(hipMemcpyAsync(P->d_desc, P->h_desc.data(), sizeof(EnvDesc) * n, hipMemcpyHostToDevice, stream));
-  TC_HIP(hipMemcpyAsync(P->d_tiles, tiles.data(), sizeof(Tile) * tiles.size(), hipMemcpyHostToDevice, stream));
-  TC_HIP(hipStreamSynchronize(stream));
+  std::memcpy(P->h_stage, P->h_desc.data(), sizeof(EnvDesc) * n);
+  std::memcpy(P->h_stage + sizeof(EnvDesc) * n, tiles.data(), sizeof(Tile) * tiles.size());
+  TC_HIP(hipMemcpyAsync(P->d_desc, P->h_stage, sizeof(EnvDesc) * n, hipMemcpyHostToDevice, stream));
+  TC_HIP(hipMemcpyAsync(P->d_tiles, P->h_stage + sizeof(EnvDesc) * n, sizeof(Tile) * tiles.size(),
+                        hipMemcpyHostToDevice, stream));
   P->d_state = pool.d_state;
   out = std::move(P);
   return TC_OK;
