@@ -295,6 +295,7 @@ struct Runner {
   View view(bool (*pred)(const EnvState&), unsigned mask = ~0u, bool copy = true);
   void flush_views();
   int unflushed = -1;               // ring start of lists built but not yet copied
+  bool ring_overflow = false;       // a view did not fit the ring (reported at the next readback)
   void launch_v(KernelId k, const View& v, int cls, int parity = 0, int mode = 0);
   tc_status cg_chunk(int M, const View& v);
   void launch_tiles(KernelId k, const Tile* tiles, int ntiles, int block, int parity, int mode = 0);

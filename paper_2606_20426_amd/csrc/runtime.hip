@@ -693,7 +693,10 @@ Runner::View Runner::view(bool (*pred)(const EnvState&), unsigned mask, bool cop
                     : c == BatchPlan::SURF ? E.n_st : c == BatchPlan::ASM ? E.n_at
                     : c == BatchPlan::ENERGY ? E.n_te + E.n_vt + E.n_ct
                     : c == BatchPlan::PAIR ? E.n_pt : E.n_spt;
-      if (k + cnt > P->ctiles_cap) break;   // ring full: cannot happen (4x capacity)
+      if (k + cnt > P->ctiles_cap) {   // cannot happen (4x capacity); never launch a truncated list
+        ring_overflow = true;
+        break;
+      }
       for (int t = 0; t < cnt; ++t) P->h_ctiles[k++] = Tile{i, t};
     }
     v.c[c] = k - start;
@@ -720,6 +723,7 @@ void Runner::launch_v(KernelId k, const View& v, int cls, int parity, int mode) 
 
 tc_status Runner::readback() {
   TC_HIP(hipGetLastError());
+  if (ring_overflow) return set_error(TC_E_HIP, "compacted tile lists overflowed their ring");
   TC_HIP(hipMemcpyAsync(pool->h_state, pool->d_state, sizeof(EnvState) * span, hipMemcpyDeviceToHost, strm()));
   TC_HIP(hipStreamSynchronize(strm()));
   P->ctiles_off = 0;
